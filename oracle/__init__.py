@@ -1,0 +1,272 @@
+"""FP64 CPU oracle for the auxiliary Kalman MCMC hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no code
+with the HIP library in ``paper_2303_00301_amd`` and never imports it.
+
+The arithmetic lives in ``akf_oracle.c`` (sequential textbook loops, double
+precision); this module only builds/loads it and marshals numpy arrays.
+``scan_ops`` holds the associative-scan operators (parallel filter and sampler
+elements) written out in numpy, used to pin the scan orderings.
+
+Parity status of each function: see the header of ``akf_oracle.c``; the pins
+are in ``tests/test_oracle_*.py``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "akf_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T = 0, 1, 2
+ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
+
+
+def build(force: bool = False) -> str:
+    """Compile akf_oracle.c into liboracle.so with gcc (plain -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        _declare(_lib)
+    return _lib
+
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("N", C.c_int), ("dx", C.c_int), ("dy", C.c_int),
+        ("m0", _dp), ("P0", _dp), ("F", _dp), ("b", _dp), ("Q", _dp),
+        ("emit", C.c_int),
+        ("H", _dp), ("R", _dp),
+        ("site", _ip),
+        ("nu", C.c_double), ("scale", C.c_double),
+    ]
+
+
+def _declare(L):
+    L.or_kf.restype = C.c_int
+    L.or_kf.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_long, _dp,
+                        C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_rts_sample.restype = C.c_int
+    L.or_rts_sample.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_rts_smooth.restype = C.c_int
+    L.or_rts_smooth.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_emission.restype = C.c_double
+    L.or_emission.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, _dp]
+    L.or_linearise.restype = C.c_int
+    L.or_linearise.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp, _dp]
+    L.or_mh_step.restype = C.c_int
+    L.or_mh_step.argtypes = [C.POINTER(_Model), _dp, _dp, C.c_double, C.c_int, _dp, _dp, C.c_double,
+                             _dp, _dp, _ip, _dp, _dp, _dp, _dp]
+    L.or_mh_chain.restype = C.c_int
+    L.or_mh_chain.argtypes = [C.POINTER(_Model), _dp, _dp, C.c_double, C.c_int, C.c_int, _dp, _dp,
+                              _dp, _ip, _ip, _dp]
+    L.or_lgssm_loglik.restype = C.c_double
+    L.or_lgssm_loglik.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_fisher_score.restype = C.c_double
+    L.or_fisher_score.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp,
+                                  _dp, _dp, _dp]
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a: Optional[np.ndarray]):
+    if a is None:
+        return C.cast(None, _dp)
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+@dataclass
+class Model:
+    """State-space model: p0 = N(m0,P0), p_t = N(F x + b, Q), emission h_t.
+
+    emit: EMIT_GAUSSIAN (H [dy,dx], R [dy,dy]); EMIT_POISSON_LOG or
+    EMIT_STUDENT_T (site [dy]: y_k observes x[site[k]]; nu, scale for Student-t).
+    """
+    m0: np.ndarray
+    P0: np.ndarray
+    F: np.ndarray
+    Q: np.ndarray
+    emit: int
+    b: Optional[np.ndarray] = None
+    H: Optional[np.ndarray] = None
+    R: Optional[np.ndarray] = None
+    site: Optional[np.ndarray] = None
+    nu: float = 0.0
+    scale: float = 0.0
+
+    @property
+    def dx(self) -> int:
+        return int(np.asarray(self.m0).shape[0])
+
+    @property
+    def dy(self) -> int:
+        if self.emit == EMIT_GAUSSIAN:
+            return int(np.asarray(self.H).shape[0])
+        return int(np.asarray(self.site).shape[0])
+
+
+class _Bound:
+    """Keeps the numpy buffers referenced by a ctypes _Model alive."""
+
+    def __init__(self, M: Model, N: int):
+        self.keep = {}
+        s = _Model()
+        s.N, s.dx, s.dy = N, M.dx, M.dy
+        for k in ("m0", "P0", "F", "b", "Q", "H", "R"):
+            v = getattr(M, k)
+            if v is None:
+                setattr(s, k, C.cast(None, _dp))
+            else:
+                a = _f64(v)
+                self.keep[k] = a
+                setattr(s, k, _p(a))
+        s.emit = int(M.emit)
+        if M.site is not None:
+            si = np.ascontiguousarray(M.site, dtype=np.int32)
+            self.keep["site"] = si
+            s.site = si.ctypes.data_as(_ip)
+        else:
+            s.site = C.cast(None, _ip)
+        s.nu, s.scale = float(M.nu), float(M.scale)
+        self.s = s
+
+    def ref(self):
+        return C.byref(self.s)
+
+
+def kf(m0, P0, F, Q, H, R, y, b=None, H_per_t=False, R_per_t=False):
+    """Kalman filter.  Returns dict with mf, Pf, mp, Pp, ell, logZ, rc."""
+    y = _f64(y)
+    N, dy = y.shape
+    dx = len(m0)
+    H, R = _f64(H), _f64(R)
+    out = {k: np.zeros(s) for k, s in (("mf", (N, dx)), ("Pf", (N, dx, dx)), ("mp", (N, dx)),
+                                       ("Pp", (N, dx, dx)), ("ell", (N,)))}
+    bb = None if b is None else _f64(b)
+    rc = lib().or_kf(N, dx, dy, _p(_f64(m0)), _p(_f64(P0)), _p(_f64(F)), _p(bb), _p(_f64(Q)), _p(H),
+                     dy * dx if H_per_t else 0, _p(R), dy * dy if R_per_t else 0, _p(y),
+                     _p(out["mf"]), _p(out["Pf"]), _p(out["mp"]), _p(out["Pp"]), _p(out["ell"]))
+    out["rc"] = rc
+    out["logZ"] = float(out["ell"].sum())
+    return out
+
+
+def rts_sample(F, mf, Pf, mp, Pp, xi):
+    mf, Pf, mp, Pp, xi = map(_f64, (mf, Pf, mp, Pp, xi))
+    N, dx = mf.shape
+    x = np.zeros((N, dx))
+    rc = lib().or_rts_sample(N, dx, _p(_f64(F)), _p(mf), _p(Pf), _p(mp), _p(Pp), _p(xi), _p(x))
+    return x, rc
+
+
+def rts_smooth(F, mf, Pf, mp, Pp):
+    mf, Pf, mp, Pp = map(_f64, (mf, Pf, mp, Pp))
+    N, dx = mf.shape
+    ms = np.zeros((N, dx))
+    Ps = np.zeros((N, dx, dx))
+    G = np.zeros((N, dx, dx))
+    rc = lib().or_rts_smooth(N, dx, _p(_f64(F)), _p(mf), _p(Pf), _p(mp), _p(Pp), _p(ms), _p(Ps), _p(G))
+    return ms, Ps, G, rc
+
+
+def emission(M: Model, yt, xt):
+    """Returns (log h, v, Lambda) at one time step."""
+    B = _Bound(M, 1)
+    yt, xt = _f64(yt), _f64(xt)
+    v = np.zeros(M.dx)
+    Lam = np.zeros((M.dx, M.dx))
+    lh = lib().or_emission(B.ref(), _p(yt), _p(xt), _p(v), _p(Lam))
+    return lh, v, Lam
+
+
+def linearise(M: Model, y, x, u, delta, order):
+    y, x, u = _f64(y), _f64(x), _f64(u)
+    N = x.shape[0]
+    B = _Bound(M, N)
+    om = np.zeros((N, M.dx))
+    Om = np.zeros((N, M.dx, M.dx))
+    lh = C.c_double(0.0)
+    rc = lib().or_linearise(B.ref(), _p(y), _p(x), _p(u), float(delta), int(order), _p(om), _p(Om),
+                            C.byref(lh))
+    return om, Om, lh.value, rc
+
+
+def mh_step(M: Model, y, x, delta, order, xi_u, xi_x, unif):
+    """One auxiliary-Kalman MH step.  Returns a dict of every output."""
+    y, x, xi_u, xi_x = map(_f64, (y, x, xi_u, xi_x))
+    N = x.shape[0]
+    B = _Bound(M, N)
+    x_out = np.zeros_like(x)
+    xs = np.zeros_like(x)
+    ell = np.zeros(N)
+    lr, lzf, lzr = C.c_double(), C.c_double(), C.c_double()
+    acc = C.c_int()
+    st = lib().or_mh_step(B.ref(), _p(y), _p(x), float(delta), int(order), _p(xi_u), _p(xi_x),
+                          float(unif), _p(x_out), C.byref(lr), C.byref(acc), C.byref(lzf),
+                          C.byref(lzr), _p(xs), _p(ell))
+    return dict(x_out=x_out, log_ratio=lr.value, accepted=int(acc.value), logZ_fwd=lzf.value,
+                logZ_rev=lzr.value, status=int(st), xstar=xs, ell_fwd=ell)
+
+
+def mh_chain(M: Model, y, x0, delta, order, xi, unif, keep_samples=True):
+    """n_steps MH steps; xi [n_steps,2,N,dx], unif [n_steps]."""
+    y, xi, unif = _f64(y), _f64(xi), _f64(unif)
+    x = _f64(x0).copy()
+    n_steps = xi.shape[0]
+    N = x.shape[0]
+    B = _Bound(M, N)
+    lr = np.zeros(n_steps)
+    acc = np.zeros(n_steps, dtype=np.int32)
+    st = np.zeros(n_steps, dtype=np.int32)
+    samples = np.zeros((n_steps,) + x.shape) if keep_samples else None
+    lib().or_mh_chain(B.ref(), _p(y), _p(x), float(delta), int(order), n_steps, _p(xi), _p(unif),
+                      _p(lr), acc.ctypes.data_as(_ip), st.ctypes.data_as(_ip), _p(samples))
+    return dict(x=x, log_ratio=lr, accepted=acc, status=st, samples=samples)
+
+
+def lgssm_loglik(m0, P0, F, logq, H, logr, y):
+    y = _f64(y)
+    N, dy = y.shape
+    dx = len(m0)
+    return lib().or_lgssm_loglik(N, dx, dy, _p(_f64(m0)), _p(_f64(P0)), _p(_f64(F)), _p(_f64(logq)),
+                                 _p(_f64(H)), _p(_f64(logr)), _p(y))
+
+
+def fisher_score(m0, P0, F, logq, H, logr, y):
+    """Returns (loglik, dF, dlogq, dH, dlogr) by Fisher's identity."""
+    y = _f64(y)
+    N, dy = y.shape
+    dx = len(m0)
+    dF = np.zeros((dx, dx))
+    dq = np.zeros(dx)
+    dH = np.zeros((dy, dx))
+    dr = np.zeros(dy)
+    ll = lib().or_fisher_score(N, dx, dy, _p(_f64(m0)), _p(_f64(P0)), _p(_f64(F)), _p(_f64(logq)),
+                               _p(_f64(H)), _p(_f64(logr)), _p(y), _p(dF), _p(dq), _p(dH), _p(dr))
+    return ll, dF, dq, dH, dr

@@ -1,0 +1,732 @@
+/*
+ * akf_oracle.c -- sequential FP64 CPU oracle for the auxiliary Kalman MCMC step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU path is checked against.  It shares no code, header, table or helper with
+ * the HIP library (paper_2303_00301_amd/csrc); only tests/, the smoke check and
+ * the CPU-baseline leg of bench.py may load it.
+ *
+ * Everything is double precision, row-major, one chain, textbook loops.
+ * Paper: Corenflos & Sarkka, "Auxiliary MCMC samplers for parallelisable
+ * inference in high-dimensional latent dynamical systems" (arXiv 2303.00301).
+ *
+ *   or_kf            Kalman filter with predictive-form marginal likelihood
+ *                    (App. A.1, Alg. "Kalman filter"; eq. marginal-likelihood).
+ *   or_rts_sample    Rauch-Tung-Striebel *sampler* with a fixed noise map
+ *                    (App. A.1, Alg. "Rauch-Tung-Striebel sampler", eq. backward).
+ *   or_rts_smooth    RTS smoother marginals and the backward gains, used for the
+ *                    Fisher-identity score and moment checks.
+ *   or_emission      log h_t, its gradient v_t and Hessian Lambda_t for the
+ *                    Gaussian / Poisson-log / Student-t families (Sec. 2.2,
+ *                    eq. linearised-log-potential-second).
+ *   or_linearise     pseudo-observations (omega_t, Omega_t) of the auxiliary
+ *                    LGSSM: first order (eq. gaussian-FK-proposal) or second
+ *                    order (eq. second-order), with Sigma_t = I.
+ *   or_mh_step       one step of the general auxiliary Kalman sampler
+ *                    (Alg. "General Auxiliary Kalman sampler"), Hastings-within-
+ *                    Gibbs on x | u.
+ *   or_fisher_score  gradient of log p(y | theta) by Fisher's identity for an
+ *                    LGSSM with theta = (F, log diag Q, H, log diag R).
+ *
+ * Parity status: every function here is pinned by tests/test_oracle_*.py against
+ * dense joint-Gaussian brute force, closed forms, quadrature and finite
+ * differences (see the test files for which pin covers which function).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define LOG2PI 1.8378770664093454835606594728112
+
+/* ------------------------------------------------------------------ */
+/* small dense helpers (row-major)                                      */
+/* ------------------------------------------------------------------ */
+
+/* C[m,n] = A[m,k] * B[k,n] */
+static void mm(int m, int n, int k, const double* A, const double* B, double* C) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += A[i * k + l] * B[l * n + j];
+      C[i * n + j] = s;
+    }
+}
+
+/* C[m,n] = A[m,k] * B[n,k]^T */
+static void mm_nt(int m, int n, int k, const double* A, const double* B, double* C) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += A[i * k + l] * B[j * k + l];
+      C[i * n + j] = s;
+    }
+}
+
+/* C[m,n] = A[k,m]^T * B[k,n] */
+static void mm_tn(int m, int n, int k, const double* A, const double* B, double* C) {
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) {
+      double s = 0.0;
+      for (int l = 0; l < k; ++l) s += A[l * m + i] * B[l * n + j];
+      C[i * n + j] = s;
+    }
+}
+
+static void mv(int m, int n, const double* A, const double* x, double* y) {
+  for (int i = 0; i < m; ++i) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += A[i * n + j] * x[j];
+    y[i] = s;
+  }
+}
+
+static void symmetrise(int n, double* A) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      double s = 0.5 * (A[i * n + j] + A[j * n + i]);
+      A[i * n + j] = s;
+      A[j * n + i] = s;
+    }
+}
+
+/* Lower Cholesky factor L (positive diagonal) of a symmetric matrix A.
+ * Returns 0 on success, 1 when A is not numerically positive definite. */
+static int chol(int n, const double* A, double* L) {
+  memset(L, 0, sizeof(double) * (size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+    if (!(s > 0.0) || !isfinite(s)) return 1;
+    double d = sqrt(s);
+    L[j * n + j] = d;
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i * n + j];
+      for (int k = 0; k < j; ++k) t -= L[i * n + k] * L[j * n + k];
+      L[i * n + j] = t / d;
+    }
+  }
+  return 0;
+}
+
+/* Solve L z = b in place (forward substitution). */
+static void fwd_sub(int n, const double* L, double* b) {
+  for (int i = 0; i < n; ++i) {
+    double s = b[i];
+    for (int k = 0; k < i; ++k) s -= L[i * n + k] * b[k];
+    b[i] = s / L[i * n + i];
+  }
+}
+
+/* Solve L^T z = b in place (backward substitution). */
+static void bwd_sub(int n, const double* L, double* b) {
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * b[k];
+    b[i] = s / L[i * n + i];
+  }
+}
+
+/* X = A^{-1} B for SPD A given its Cholesky factor L; B is [n, nrhs], in place. */
+static void chol_solve(int n, int nrhs, const double* L, double* B, double* col) {
+  for (int j = 0; j < nrhs; ++j) {
+    for (int i = 0; i < n; ++i) col[i] = B[i * nrhs + j];
+    fwd_sub(n, L, col);
+    bwd_sub(n, L, col);
+    for (int i = 0; i < n; ++i) B[i * nrhs + j] = col[i];
+  }
+}
+
+static double chol_logdet(int n, const double* L) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += log(L[i * n + i]);
+  return 2.0 * s;
+}
+
+/* log N(x; mu, S) with S given by its Cholesky factor L. */
+static double gauss_logpdf_chol(int n, const double* x, const double* mu, const double* L, double* tmp) {
+  for (int i = 0; i < n; ++i) tmp[i] = x[i] - mu[i];
+  fwd_sub(n, L, tmp);
+  double q = 0.0;
+  for (int i = 0; i < n; ++i) q += tmp[i] * tmp[i];
+  return -0.5 * (n * LOG2PI + chol_logdet(n, L) + q);
+}
+
+/* ------------------------------------------------------------------ */
+/* Kalman filter                                                        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Kalman filter for  x_0 ~ N(m0,P0),  x_t = F x_{t-1} + b + N(0,Q),
+ * y_t = H_t x_t + N(0, R_t),  t = 0..N-1.
+ * H_t = H + t*H_stride, R_t = R + t*R_stride (stride 0: time-invariant).
+ * The likelihood uses the predictive moments, log p(y_t | y_{0:t-1}) =
+ * log N(y_t; H m^p_t, H P^p_t H^T + R_t) (the printed filtered-moment form is a
+ * typo; the algorithm's update line uses the predictive one).
+ * Outputs mf/Pf/mp/Pp may be NULL.  ell[t] receives the per-step term.
+ * Returns 0, or 1 + t when S_t was not positive definite at step t.
+ */
+int or_kf(int N, int dx, int dy, const double* m0, const double* P0, const double* F,
+          const double* b, const double* Q, const double* H, long H_stride, const double* R,
+          long R_stride, const double* y, double* mf, double* Pf, double* mp, double* Pp,
+          double* ell) {
+  const int n = dx, p = dy;
+  double* m_p = malloc(sizeof(double) * n);
+  double* P_p = malloc(sizeof(double) * n * n);
+  double* m_f = malloc(sizeof(double) * n);
+  double* P_f = malloc(sizeof(double) * n * n);
+  double* T = malloc(sizeof(double) * n * n);
+  double* HP = malloc(sizeof(double) * p * n);
+  double* S = malloc(sizeof(double) * p * p);
+  double* L = malloc(sizeof(double) * p * p);
+  double* v = malloc(sizeof(double) * p);
+  double* Kt = malloc(sizeof(double) * p * n); /* K^T = S^{-1} H P */
+  double* col = malloc(sizeof(double) * (p > n ? p : n));
+  double* tmp = malloc(sizeof(double) * (p > n ? p : n));
+  int rc = 0;
+  for (int t = 0; t < N && rc == 0; ++t) {
+    const double* Ht = H + (long)t * H_stride;
+    const double* Rt = R + (long)t * R_stride;
+    if (t == 0) {
+      memcpy(m_p, m0, sizeof(double) * n);
+      memcpy(P_p, P0, sizeof(double) * n * n);
+    } else {
+      mv(n, n, F, m_f, m_p);
+      if (b)
+        for (int i = 0; i < n; ++i) m_p[i] += b[i];
+      mm(n, n, n, F, P_f, T);
+      mm_nt(n, n, n, T, F, P_p);
+      for (int i = 0; i < n * n; ++i) P_p[i] += Q[i];
+      symmetrise(n, P_p);
+    }
+    if (mp) memcpy(mp + (long)t * n, m_p, sizeof(double) * n);
+    if (Pp) memcpy(Pp + (long)t * n * n, P_p, sizeof(double) * n * n);
+    /* innovation */
+    mm(p, n, n, Ht, P_p, HP);
+    mm_nt(p, p, n, HP, Ht, S);
+    for (int i = 0; i < p * p; ++i) S[i] += Rt[i];
+    symmetrise(p, S);
+    if (chol(p, S, L)) {
+      rc = 1 + t;
+      break;
+    }
+    mv(p, n, Ht, m_p, v);
+    for (int i = 0; i < p; ++i) v[i] = y[(long)t * p + i] - v[i];
+    for (int i = 0; i < p; ++i) tmp[i] = v[i];
+    fwd_sub(p, L, tmp);
+    double q = 0.0;
+    for (int i = 0; i < p; ++i) q += tmp[i] * tmp[i];
+    ell[t] = -0.5 * (p * LOG2PI + chol_logdet(p, L) + q);
+    /* gain: K^T = S^{-1} (H P) */
+    memcpy(Kt, HP, sizeof(double) * p * n);
+    chol_solve(p, n, L, Kt, col);
+    /* m_f = m_p + K v */
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int k = 0; k < p; ++k) s += Kt[k * n + i] * v[k];
+      m_f[i] = m_p[i] + s;
+    }
+    /* P_f = P_p - K H P_p = P_p - (HP)^T S^{-1} (HP) */
+    mm_tn(n, n, p, HP, Kt, T);
+    for (int i = 0; i < n * n; ++i) P_f[i] = P_p[i] - T[i];
+    symmetrise(n, P_f);
+    if (mf) memcpy(mf + (long)t * n, m_f, sizeof(double) * n);
+    if (Pf) memcpy(Pf + (long)t * n * n, P_f, sizeof(double) * n * n);
+  }
+  free(m_p); free(P_p); free(m_f); free(P_f); free(T); free(HP); free(S); free(L);
+  free(v); free(Kt); free(col); free(tmp);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Backward gains shared by the sampler and smoother                    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * G_t = P^f_t F^T (P^p_{t+1})^{-1} and Sigma_t = P^f_t - G_t P^p_{t+1} G_t^T,
+ * the moments of p(x_t | x_{t+1}, y_{0:t}) (eq. backward).  Returns 0 or 1.
+ */
+static int backward_gain(int n, const double* F, const double* Pf, const double* Pp1, double* G,
+                         double* Sig, double* work) {
+  double* Lp = work;             /* n*n */
+  double* FP = work + n * n;     /* n*n : F P^f  (so G^T = Pp1^{-1} F P^f) */
+  double* col = work + 2 * n * n;
+  double* T = work + 2 * n * n + n;
+  if (chol(n, Pp1, Lp)) return 1;
+  mm(n, n, n, F, Pf, FP);
+  memcpy(T, FP, sizeof(double) * n * n);
+  chol_solve(n, n, Lp, T, col); /* T = Pp1^{-1} F Pf = G^T */
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) G[i * n + j] = T[j * n + i];
+  /* Sigma = Pf - G Pp1 G^T = Pf - G (F Pf) */
+  mm(n, n, n, G, FP, T);
+  for (int i = 0; i < n * n; ++i) Sig[i] = Pf[i] - T[i];
+  symmetrise(n, Sig);
+  return 0;
+}
+
+/*
+ * RTS sampler with a fixed noise map (eq. backward): x_{N-1} = m^f + chol(P^f) xi,
+ * x_t = m^f_t + G_t (x_{t+1} - m^p_{t+1}) + chol(Sigma_t) xi_t, chol = lower
+ * Cholesky factor with positive diagonal.  Returns 0, or 1 + t on a non-PD
+ * covariance at step t.
+ */
+int or_rts_sample(int N, int dx, const double* F, const double* mf, const double* Pf,
+                  const double* mp, const double* Pp, const double* xi, double* x) {
+  const int n = dx;
+  double* G = malloc(sizeof(double) * n * n);
+  double* Sig = malloc(sizeof(double) * n * n);
+  double* L = malloc(sizeof(double) * n * n);
+  double* d = malloc(sizeof(double) * n);
+  double* work = malloc(sizeof(double) * (3 * n * n + n));
+  int rc = 0;
+  const long t1 = N - 1;
+  if (chol(n, Pf + t1 * n * n, L)) rc = N;
+  else {
+    mv(n, n, L, xi + t1 * n, d);
+    for (int i = 0; i < n; ++i) x[t1 * n + i] = mf[t1 * n + i] + d[i];
+  }
+  for (long t = N - 2; t >= 0 && rc == 0; --t) {
+    if (backward_gain(n, F, Pf + t * n * n, Pp + (t + 1) * n * n, G, Sig, work) ||
+        chol(n, Sig, L)) {
+      rc = 1 + (int)t;
+      break;
+    }
+    for (int i = 0; i < n; ++i) d[i] = x[(t + 1) * n + i] - mp[(t + 1) * n + i];
+    double* e = work;
+    mv(n, n, G, d, e);
+    double* z = work + n;
+    mv(n, n, L, xi + t * n, z);
+    for (int i = 0; i < n; ++i) x[t * n + i] = mf[t * n + i] + e[i] + z[i];
+  }
+  free(G); free(Sig); free(L); free(d); free(work);
+  return rc;
+}
+
+/*
+ * RTS smoother: smoothed means/covariances and the gains G_t (t < N-1;
+ * G_{N-1} is set to zero).  Cov(x_{t+1}, x_t | y) = P^s_{t+1} G_t^T.
+ */
+int or_rts_smooth(int N, int dx, const double* F, const double* mf, const double* Pf,
+                  const double* mp, const double* Pp, double* ms, double* Ps, double* Gout) {
+  const int n = dx;
+  double* G = malloc(sizeof(double) * n * n);
+  double* Sig = malloc(sizeof(double) * n * n);
+  double* D = malloc(sizeof(double) * n * n);
+  double* T = malloc(sizeof(double) * n * n);
+  double* d = malloc(sizeof(double) * n);
+  double* work = malloc(sizeof(double) * (3 * n * n + n));
+  int rc = 0;
+  const long t1 = N - 1;
+  memcpy(ms + t1 * n, mf + t1 * n, sizeof(double) * n);
+  memcpy(Ps + t1 * n * n, Pf + t1 * n * n, sizeof(double) * n * n);
+  if (Gout) memset(Gout + t1 * n * n, 0, sizeof(double) * n * n);
+  for (long t = N - 2; t >= 0; --t) {
+    if (backward_gain(n, F, Pf + t * n * n, Pp + (t + 1) * n * n, G, Sig, work)) {
+      rc = 1 + (int)t;
+      break;
+    }
+    for (int i = 0; i < n; ++i) d[i] = ms[(t + 1) * n + i] - mp[(t + 1) * n + i];
+    mv(n, n, G, d, ms + t * n);
+    for (int i = 0; i < n; ++i) ms[t * n + i] += mf[t * n + i];
+    /* Ps_t = Sigma_t + G Ps_{t+1} G^T */
+    mm(n, n, n, G, Ps + (t + 1) * n * n, T);
+    mm_nt(n, n, n, T, G, D);
+    for (int i = 0; i < n * n; ++i) Ps[t * n * n + i] = Sig[i] + D[i];
+    symmetrise(n, Ps + t * n * n);
+    if (Gout) memcpy(Gout + t * n * n, G, sizeof(double) * n * n);
+  }
+  free(G); free(Sig); free(D); free(T); free(d); free(work);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Emission families                                                    */
+/* ------------------------------------------------------------------ */
+
+enum { OR_EMIT_GAUSSIAN = 0, OR_EMIT_POISSON_LOG = 1, OR_EMIT_STUDENT_T = 2 };
+
+typedef struct {
+  int N, dx, dy;
+  const double *m0, *P0, *F, *b, *Q;
+  int emit;
+  const double *H, *R;  /* Gaussian: [dy,dx], [dy,dy] */
+  const int* site;      /* Poisson / Student-t: y_k observes x[site[k]] */
+  double nu, scale;     /* Student-t */
+} or_model;
+
+/*
+ * log h(y_t | x_t) up to an additive constant that does not depend on x,
+ * together with v = grad_x log h and Lambda = Hessian (dense [dx,dx]).
+ * Constants dropped: Gaussian -(dy log 2pi + logdet R)/2, Poisson -log y!,
+ * Student-t log Gamma terms and -log s.  They cancel in the MH ratio.
+ * v and Lam may be NULL.  Returns log h (may be +-inf / nan on overflow).
+ */
+double or_emission(const or_model* M, const double* yt, const double* xt, double* v, double* Lam) {
+  const int n = M->dx, p = M->dy;
+  double lh = 0.0;
+  if (v) memset(v, 0, sizeof(double) * n);
+  if (Lam) memset(Lam, 0, sizeof(double) * n * n);
+  if (M->emit == OR_EMIT_GAUSSIAN) {
+    double* r = malloc(sizeof(double) * p);
+    double* w = malloc(sizeof(double) * p);
+    double* L = malloc(sizeof(double) * p * p);
+    double* RiH = malloc(sizeof(double) * p * n);
+    double* col = malloc(sizeof(double) * p);
+    chol(p, M->R, L);
+    mv(p, n, M->H, xt, r);
+    for (int k = 0; k < p; ++k) r[k] = yt[k] - r[k];
+    memcpy(w, r, sizeof(double) * p);
+    fwd_sub(p, L, w);
+    double q = 0.0;
+    for (int k = 0; k < p; ++k) q += w[k] * w[k];
+    lh = -0.5 * q;
+    /* w = R^{-1} r */
+    memcpy(w, r, sizeof(double) * p);
+    fwd_sub(p, L, w);
+    bwd_sub(p, L, w);
+    if (v)
+      for (int i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < p; ++k) s += M->H[k * n + i] * w[k];
+        v[i] = s;
+      }
+    if (Lam) {
+      memcpy(RiH, M->H, sizeof(double) * p * n);
+      chol_solve(p, n, L, RiH, col);
+      mm_tn(n, n, p, M->H, RiH, Lam);
+      for (int i = 0; i < n * n; ++i) Lam[i] = -Lam[i];
+      symmetrise(n, Lam);
+    }
+    free(r); free(w); free(L); free(RiH); free(col);
+  } else if (M->emit == OR_EMIT_POISSON_LOG) {
+    for (int k = 0; k < p; ++k) {
+      int i = M->site[k];
+      double e = exp(xt[i]);
+      lh += yt[k] * xt[i] - e;
+      if (v) v[i] += yt[k] - e;
+      if (Lam) Lam[i * n + i] -= e;
+    }
+  } else {
+    const double a = M->nu * M->scale * M->scale;
+    for (int k = 0; k < p; ++k) {
+      int i = M->site[k];
+      double r = yt[k] - xt[i];
+      double den = a + r * r;
+      lh += -0.5 * (M->nu + 1.0) * log1p(r * r / a);
+      if (v) v[i] += (M->nu + 1.0) * r / den;
+      if (Lam) Lam[i * n + i] += (M->nu + 1.0) * (r * r - a) / (den * den);
+    }
+  }
+  return lh;
+}
+
+/*
+ * Pseudo-observations of the auxiliary LGSSM at linearisation point x:
+ *   order 2 (eq. second-order): Omega_t = (2/delta I - Lambda_t)^{-1},
+ *                                omega_t = Omega_t (2/delta u_t + v_t - Lambda_t x_t);
+ *   order 1 (eq. gaussian-FK-proposal): Lambda_t = 0, so Omega_t = delta/2 I and
+ *                                omega_t = u_t + delta/2 v_t.
+ * Omega: [N,dx,dx] dense.  loghsum receives sum_t log h_t(y_t|x_t).
+ * Returns 0, or 1 + t when 2/delta I - Lambda_t is not positive definite.
+ */
+int or_linearise(const or_model* M, const double* y, const double* x, const double* u, double delta,
+                 int order, double* omega, double* Omega, double* loghsum) {
+  const int n = M->dx, p = M->dy;
+  double* v = malloc(sizeof(double) * n);
+  double* Lam = malloc(sizeof(double) * n * n);
+  double* Prec = malloc(sizeof(double) * n * n);
+  double* L = malloc(sizeof(double) * n * n);
+  double* rhs = malloc(sizeof(double) * n);
+  double* col = malloc(sizeof(double) * n);
+  double* I = malloc(sizeof(double) * n * n);
+  double lhs = 0.0;
+  int rc = 0;
+  for (long t = 0; t < M->N; ++t) {
+    const double* xt = x + t * n;
+    lhs += or_emission(M, y + t * p, xt, v, Lam);
+    if (order == 1) memset(Lam, 0, sizeof(double) * n * n);
+    for (int i = 0; i < n * n; ++i) Prec[i] = -Lam[i];
+    for (int i = 0; i < n; ++i) Prec[i * n + i] += 2.0 / delta;
+    if (chol(n, Prec, L)) {
+      if (rc == 0) rc = 1 + (int)t;
+      memset(omega + t * n, 0, sizeof(double) * n);
+      memset(Omega + t * n * n, 0, sizeof(double) * n * n);
+      continue;
+    }
+    /* Omega = Prec^{-1} */
+    memset(I, 0, sizeof(double) * n * n);
+    for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+    chol_solve(n, n, L, I, col);
+    symmetrise(n, I);
+    memcpy(Omega + t * n * n, I, sizeof(double) * n * n);
+    /* rhs = 2/delta u + v - Lam x */
+    mv(n, n, Lam, xt, rhs);
+    for (int i = 0; i < n; ++i) rhs[i] = 2.0 / delta * u[t * n + i] + v[i] - rhs[i];
+    mv(n, n, I, rhs, omega + t * n);
+  }
+  if (loghsum) *loghsum = lhs;
+  free(v); free(Lam); free(Prec); free(L); free(rhs); free(col); free(I);
+  return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* One auxiliary Kalman MH step                                         */
+/* ------------------------------------------------------------------ */
+
+enum { OR_ST_FWD_NOT_PD = 1, OR_ST_REV_NOT_PD = 2, OR_ST_NONFINITE = 4 };
+
+/* sum_t log N(omega_t; z_t, Omega_t) */
+static double pseudo_obs_loglik(int N, int n, const double* omega, const double* Omega,
+                                const double* z, double* L, double* tmp) {
+  double s = 0.0;
+  for (long t = 0; t < N; ++t) {
+    if (chol(n, Omega + t * n * n, L)) return NAN;
+    s += gauss_logpdf_chol(n, omega + t * n, z + t * n, L, tmp);
+  }
+  return s;
+}
+
+/*
+ * One step of the auxiliary Kalman sampler with Sigma_t = I (Alg. "General
+ * Auxiliary Kalman sampler", Gaussian dynamics so the dynamics linearisation
+ * is the identity).  Inputs: current path x [N,dx], xi_u, xi_x [N,dx] standard
+ * normals, unif in (0,1).  u_t = x_t + sqrt(delta/2) xi_u_t.
+ *
+ * log r = sum_t [log h(y_t|x*_t) - log h(y_t|x_t)]
+ *       + sum_t [|u_t - x_t|^2 - |u_t - x*_t|^2] / delta
+ *       + sum_t [log N(omega*_t; x_t, Omega*_t) - log N(omega_t; x*_t, Omega_t)]
+ *       + log Z(x) - log Z(x*),
+ * the prior p0 prod p_t cancelling between target and both proposals; Z(.) is
+ * the auxiliary LGSSM marginal likelihood (eq. marginal-likelihood).  Accept iff
+ * log(unif) < log r.  x_out may alias x.  Diagnostics (may be NULL):
+ * xstar [N,dx], ell_f [N] per-step log-likelihood terms of the forward filter.
+ * Returns the status bitmask (0 = all well-defined).
+ */
+int or_mh_step(const or_model* M, const double* y, const double* x, double delta, int order,
+               const double* xi_u, const double* xi_x, double unif, double* x_out,
+               double* log_ratio, int* accepted, double* logZ_fwd, double* logZ_rev,
+               double* xstar_out, double* ell_f_out) {
+  const int N = M->N, n = M->dx;
+  const size_t vn = (size_t)N * n, mn = (size_t)N * n * n;
+  double* u = malloc(sizeof(double) * vn);
+  double* om = malloc(sizeof(double) * vn);
+  double* Om = malloc(sizeof(double) * mn);
+  double* om2 = malloc(sizeof(double) * vn);
+  double* Om2 = malloc(sizeof(double) * mn);
+  double* mf = malloc(sizeof(double) * vn);
+  double* Pf = malloc(sizeof(double) * mn);
+  double* mp = malloc(sizeof(double) * vn);
+  double* Pp = malloc(sizeof(double) * mn);
+  double* ell = malloc(sizeof(double) * N);
+  double* xs = malloc(sizeof(double) * vn);
+  double* I = malloc(sizeof(double) * n * n);
+  double* L = malloc(sizeof(double) * n * n);
+  double* tmp = malloc(sizeof(double) * n);
+  int status = 0;
+  double lr = -INFINITY, lzf = NAN, lzr = NAN;
+  memset(I, 0, sizeof(double) * n * n);
+  for (int i = 0; i < n; ++i) I[i * n + i] = 1.0;
+  const double su = sqrt(0.5 * delta);
+  for (size_t i = 0; i < vn; ++i) u[i] = x[i] + su * xi_u[i];
+
+  double lh_x = 0.0, lh_s = 0.0;
+  /* forward proposal at x */
+  if (or_linearise(M, y, x, u, delta, order, om, Om, &lh_x)) status |= OR_ST_FWD_NOT_PD;
+  if (!status) {
+    if (or_kf(N, n, n, M->m0, M->P0, M->F, M->b, M->Q, I, 0, Om, (long)n * n, om, mf, Pf, mp, Pp,
+              ell))
+      status |= OR_ST_FWD_NOT_PD;
+  }
+  if (!status) {
+    lzf = 0.0;
+    for (int t = 0; t < N; ++t) lzf += ell[t];
+    if (ell_f_out) memcpy(ell_f_out, ell, sizeof(double) * N);
+    if (or_rts_sample(N, n, M->F, mf, Pf, mp, Pp, xi_x, xs)) status |= OR_ST_FWD_NOT_PD;
+  }
+  if (!status) {
+    if (xstar_out) memcpy(xstar_out, xs, sizeof(double) * vn);
+    /* reverse proposal at x*, same u */
+    if (or_linearise(M, y, xs, u, delta, order, om2, Om2, &lh_s)) status |= OR_ST_REV_NOT_PD;
+  }
+  if (!status) {
+    if (or_kf(N, n, n, M->m0, M->P0, M->F, M->b, M->Q, I, 0, Om2, (long)n * n, om2, NULL, NULL,
+              NULL, NULL, ell))
+      status |= OR_ST_REV_NOT_PD;
+  }
+  if (!status) {
+    lzr = 0.0;
+    for (int t = 0; t < N; ++t) lzr += ell[t];
+    double aux = 0.0;
+    for (size_t i = 0; i < vn; ++i) {
+      double a = u[i] - x[i], c = u[i] - xs[i];
+      aux += a * a - c * c;
+    }
+    aux /= delta;
+    double q_rev = pseudo_obs_loglik(N, n, om2, Om2, x, L, tmp);
+    double q_fwd = pseudo_obs_loglik(N, n, om, Om, xs, L, tmp);
+    lr = (lh_s - lh_x) + aux + (q_rev - q_fwd) + (lzf - lzr);
+    if (!isfinite(lr)) {
+      status |= OR_ST_NONFINITE;
+      lr = -INFINITY;
+    }
+  }
+  int acc = (status == 0) && (log(unif) < lr);
+  if (status) lr = -INFINITY;
+  if (x_out != x) memcpy(x_out, x, sizeof(double) * vn);
+  if (acc) memcpy(x_out, xs, sizeof(double) * vn);
+  if (log_ratio) *log_ratio = lr;
+  if (accepted) *accepted = acc;
+  if (logZ_fwd) *logZ_fwd = lzf;
+  if (logZ_rev) *logZ_rev = lzr;
+  free(u); free(om); free(Om); free(om2); free(Om2); free(mf); free(Pf); free(mp); free(Pp);
+  free(ell); free(xs); free(I); free(L); free(tmp);
+  return status;
+}
+
+/*
+ * A chain of n_steps MH steps.  xi: [n_steps, 2, N, dx] (u-noise then path
+ * noise), unif: [n_steps].  x is updated in place; per-step log r, acceptance
+ * and status are written when the arrays are non-NULL; samples (if non-NULL)
+ * receives the path after every step, [n_steps, N, dx].
+ */
+int or_mh_chain(const or_model* M, const double* y, double* x, double delta, int order, int n_steps,
+                const double* xi, const double* unif, double* log_ratio, int* accepted,
+                int* status, double* samples) {
+  const size_t vn = (size_t)M->N * M->dx;
+  for (int s = 0; s < n_steps; ++s) {
+    double lr;
+    int acc;
+    int st = or_mh_step(M, y, x, delta, order, xi + (size_t)s * 2 * vn, xi + ((size_t)s * 2 + 1) * vn,
+                        unif[s], x, &lr, &acc, NULL, NULL, NULL, NULL);
+    if (log_ratio) log_ratio[s] = lr;
+    if (accepted) accepted[s] = acc;
+    if (status) status[s] = st;
+    if (samples) memcpy(samples + (size_t)s * vn, x, sizeof(double) * vn);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* LGSSM log-likelihood and its Fisher-identity score                   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * log p(y | theta) for  x_0 ~ N(m0,P0), x_t = F x_{t-1} + N(0, diag exp(logq)),
+ * y_t = H x_t + N(0, diag exp(logr)).  Returns the log-likelihood (NaN on failure).
+ */
+double or_lgssm_loglik(int N, int dx, int dy, const double* m0, const double* P0, const double* F,
+                       const double* logq, const double* H, const double* logr, const double* y) {
+  double* Q = calloc((size_t)dx * dx, sizeof(double));
+  double* R = calloc((size_t)dy * dy, sizeof(double));
+  double* ell = malloc(sizeof(double) * N);
+  for (int i = 0; i < dx; ++i) Q[i * dx + i] = exp(logq[i]);
+  for (int i = 0; i < dy; ++i) R[i * dy + i] = exp(logr[i]);
+  int rc = or_kf(N, dx, dy, m0, P0, F, NULL, Q, H, 0, R, 0, y, NULL, NULL, NULL, NULL, ell);
+  double s = 0.0;
+  for (int t = 0; t < N; ++t) s += ell[t];
+  free(Q); free(R); free(ell);
+  return rc ? NAN : s;
+}
+
+/*
+ * Fisher's identity: grad log p(y|theta) = E[grad log p(x, y | theta) | y], with
+ * the expectation taken from the RTS smoother (marginals m^s, P^s and lag-one
+ * covariances Cov(x_t, x_{t-1} | y) = P^s_t G_{t-1}^T).  Complete-data
+ * statistics (sums over t = 1..N-1):
+ *   S00 = sum E[x_{t-1} x_{t-1}^T], S10 = sum E[x_t x_{t-1}^T], S11 = sum E[x_t x_t^T]
+ *   dF        = Q^{-1} (S10 - F S00)
+ *   dlogq_i   = -(N-1)/2 + exp(-logq_i) Psi_ii / 2,
+ *               Psi = S11 - F S10^T - S10 F^T + F S00 F^T
+ *   dH        = R^{-1} (sum_t y_t m_t^T - H sum_t E[x_t x_t^T])        (t = 0..N-1)
+ *   dlogr_j   = -N/2 + exp(-logr_j) Phi_jj / 2,
+ *               Phi = sum_t E[(y_t - H x_t)(y_t - H x_t)^T]
+ * Returns the log-likelihood (NaN on failure).
+ */
+double or_fisher_score(int N, int dx, int dy, const double* m0, const double* P0, const double* F,
+                       const double* logq, const double* H, const double* logr, const double* y,
+                       double* dF, double* dlogq, double* dH, double* dlogr) {
+  const int n = dx, p = dy;
+  const size_t vn = (size_t)N * n, mn = (size_t)N * n * n;
+  double* Q = calloc((size_t)n * n, sizeof(double));
+  double* R = calloc((size_t)p * p, sizeof(double));
+  for (int i = 0; i < n; ++i) Q[i * n + i] = exp(logq[i]);
+  for (int i = 0; i < p; ++i) R[i * p + i] = exp(logr[i]);
+  double* mf = malloc(sizeof(double) * vn);
+  double* Pf = malloc(sizeof(double) * mn);
+  double* mp = malloc(sizeof(double) * vn);
+  double* Pp = malloc(sizeof(double) * mn);
+  double* ms = malloc(sizeof(double) * vn);
+  double* Ps = malloc(sizeof(double) * mn);
+  double* G = malloc(sizeof(double) * mn);
+  double* ell = malloc(sizeof(double) * N);
+  double* S00 = calloc((size_t)n * n, sizeof(double));
+  double* S10 = calloc((size_t)n * n, sizeof(double));
+  double* S11 = calloc((size_t)n * n, sizeof(double));
+  double* Sxx = calloc((size_t)n * n, sizeof(double));
+  double* Syx = calloc((size_t)p * n, sizeof(double));
+  double* Phi = calloc((size_t)p * p, sizeof(double));
+  double* T = malloc(sizeof(double) * n * n);
+  double* T2 = malloc(sizeof(double) * n * n);
+  double* Psi = malloc(sizeof(double) * n * n);
+  double* HM = malloc(sizeof(double) * p * n);
+  double* HP = malloc(sizeof(double) * p * n);
+  double* r = malloc(sizeof(double) * p);
+  double ll = NAN;
+  int rc = or_kf(N, n, p, m0, P0, F, NULL, Q, H, 0, R, 0, y, mf, Pf, mp, Pp, ell);
+  if (!rc) rc = or_rts_smooth(N, n, F, mf, Pf, mp, Pp, ms, Ps, G);
+  if (!rc) {
+    ll = 0.0;
+    for (int t = 0; t < N; ++t) ll += ell[t];
+    for (long t = 0; t < N; ++t) {
+      const double* m = ms + t * n;
+      const double* P = Ps + t * n * n;
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Sxx[i * n + j] += P[i * n + j] + m[i] * m[j];
+      for (int k = 0; k < p; ++k)
+        for (int j = 0; j < n; ++j) Syx[k * n + j] += y[t * p + k] * m[j];
+      /* E[(y - Hx)(y - Hx)^T] = (y - H m)(y - H m)^T + H P H^T */
+      mv(p, n, H, m, r);
+      for (int k = 0; k < p; ++k) r[k] = y[t * p + k] - r[k];
+      mm(p, n, n, H, P, HP);
+      for (int k = 0; k < p; ++k)
+        for (int l = 0; l < p; ++l) {
+          double s = 0.0;
+          for (int j = 0; j < n; ++j) s += HP[k * n + j] * H[l * n + j];
+          Phi[k * p + l] += r[k] * r[l] + s;
+        }
+      if (t >= 1) {
+        const double* m0t = ms + (t - 1) * n;
+        const double* P0t = Ps + (t - 1) * n * n;
+        /* Cov(x_t, x_{t-1}) = P^s_t G_{t-1}^T */
+        mm_nt(n, n, n, P, G + (t - 1) * n * n, T);
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) {
+            S00[i * n + j] += P0t[i * n + j] + m0t[i] * m0t[j];
+            S10[i * n + j] += T[i * n + j] + m[i] * m0t[j];
+            S11[i * n + j] += P[i * n + j] + m[i] * m[j];
+          }
+      }
+    }
+    /* dF = Q^{-1}(S10 - F S00) */
+    mm(n, n, n, F, S00, T);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) dF[i * n + j] = (S10[i * n + j] - T[i * n + j]) / Q[i * n + i];
+    /* Psi = S11 - F S10^T - S10 F^T + F S00 F^T */
+    mm_nt(n, n, n, F, S10, T2); /* F S10^T */
+    mm_nt(n, n, n, T, F, Psi);  /* F S00 F^T */
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j)
+        Psi[i * n + j] += S11[i * n + j] - T2[i * n + j] - T2[j * n + i];
+    for (int i = 0; i < n; ++i)
+      dlogq[i] = -0.5 * (N - 1) + 0.5 * exp(-logq[i]) * Psi[i * n + i];
+    /* dH = R^{-1}(Syx - H Sxx) */
+    mm(p, n, n, H, Sxx, HM);
+    for (int k = 0; k < p; ++k)
+      for (int j = 0; j < n; ++j) dH[k * n + j] = (Syx[k * n + j] - HM[k * n + j]) / R[k * p + k];
+    for (int k = 0; k < p; ++k) dlogr[k] = -0.5 * N + 0.5 * exp(-logr[k]) * Phi[k * p + k];
+  }
+  free(Q); free(R); free(mf); free(Pf); free(mp); free(Pp); free(ms); free(Ps); free(G); free(ell);
+  free(S00); free(S10); free(S11); free(Sxx); free(Syx); free(Phi); free(T); free(T2); free(Psi);
+  free(HM); free(HP); free(r);
+  return ll;
+}

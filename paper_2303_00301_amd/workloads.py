@@ -1,0 +1,216 @@
+"""Seeded synthetic workloads shaped like the paper's experiments.
+
+This module holds no part of the sampler's arithmetic: it only builds model
+parameters, simulates observations from the model and draws the standard
+normals / uniforms that the MCMC step consumes.  Both the GPU path and the CPU
+oracle are fed from here.  Pure numpy; importing it does not load the HIP
+library.
+
+Seeds: model/data from ``default_rng(data_seed)``, step normals from
+``default_rng(100 + cfg)``, uniforms from ``default_rng(200 + cfg)``.
+
+Emission codes match the C-ABI: 0 Gaussian (H, R), 1 Poisson with log link,
+2 Student-t at observation sites.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T = 0, 1, 2
+
+
+@dataclass
+class Workload:
+    """A state-space model with Gaussian dynamics and a chosen emission family,
+    its observations y [N, dy], an initial path x0 [N, dx] and step settings."""
+    name: str
+    N: int
+    m0: np.ndarray
+    P0: np.ndarray
+    F: np.ndarray
+    Q: np.ndarray
+    emit: int
+    y: np.ndarray
+    b: Optional[np.ndarray] = None
+    H: Optional[np.ndarray] = None
+    R: Optional[np.ndarray] = None
+    site: Optional[np.ndarray] = None
+    nu: float = 0.0
+    scale: float = 0.0
+    delta: float = 0.5
+    order: int = 2
+    seed: int = 0
+    x_true: Optional[np.ndarray] = None
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def dx(self) -> int:
+        return int(self.m0.shape[0])
+
+    @property
+    def dy(self) -> int:
+        return int(self.y.shape[1])
+
+    def x_init(self) -> np.ndarray:
+        """Initial chain state: the zero path (warm-up steps are not scored)."""
+        return np.zeros((self.N, self.dx))
+
+    def normals(self, n_steps: int, seed: Optional[int] = None) -> np.ndarray:
+        """Standard normals [n_steps, 2, N, dx]: [:,0] for u, [:,1] for the path."""
+        rng = np.random.default_rng(100 + self.seed if seed is None else seed)
+        return rng.standard_normal((n_steps, 2, self.N, self.dx))
+
+    def uniforms(self, n_steps: int, seed: Optional[int] = None) -> np.ndarray:
+        """MH uniforms in (0, 1), [n_steps]."""
+        rng = np.random.default_rng(200 + self.seed if seed is None else seed)
+        u = rng.random(n_steps)
+        return np.where(u <= 0.0, np.nextafter(0.0, 1.0), u)
+
+    def oracle_kwargs(self) -> dict:
+        return dict(m0=self.m0, P0=self.P0, F=self.F, Q=self.Q, emit=self.emit, b=self.b,
+                    H=self.H, R=self.R, site=self.site, nu=self.nu, scale=self.scale)
+
+
+def _simulate(rng, N, m0, P0, F, Q, b=None):
+    d = len(m0)
+    Lq = np.linalg.cholesky(Q)
+    x = np.zeros((N, d))
+    x[0] = m0 + np.linalg.cholesky(P0) @ rng.standard_normal(d)
+    for t in range(1, N):
+        x[t] = F @ x[t - 1] + (0 if b is None else b) + Lq @ rng.standard_normal(d)
+    return x
+
+
+def rotation(theta: float) -> np.ndarray:
+    c, s = np.cos(theta), np.sin(theta)
+    return np.array([[c, -s], [s, c]])
+
+
+def random_stable_F(rng, d: int, rho: float) -> np.ndarray:
+    """F = rho * G / spectral_radius(G), G with i.i.d. N(0,1) entries."""
+    G = rng.standard_normal((d, d))
+    return rho * G / np.max(np.abs(np.linalg.eigvals(G)))
+
+
+def linear_gaussian_tiny(N: int = 64, seed: int = 0) -> Workload:
+    """d_x = d_y = 2 linear-Gaussian SSM: F = 0.9 R(pi/8), Q = 0.1 I, H = I,
+    R = 0.5 I, x0 ~ N(0, I); delta = 0.5, second-order proposal (exact)."""
+    rng = np.random.default_rng(seed)
+    d = 2
+    m0, P0 = np.zeros(d), np.eye(d)
+    F, Q = 0.9 * rotation(np.pi / 8), 0.1 * np.eye(d)
+    H, R = np.eye(d), 0.5 * np.eye(d)
+    x = _simulate(rng, N, m0, P0, F, Q)
+    y = x @ H.T + rng.standard_normal((N, d)) @ np.linalg.cholesky(R).T
+    return Workload("linear_gaussian_d2_N64", N, m0, P0, F, Q, EMIT_GAUSSIAN, y, H=H, R=R,
+                    delta=0.5, order=2, seed=seed, x_true=x)
+
+
+def poisson_ar1(N: int = 1024, d: int = 8, seed: int = 2) -> Workload:
+    """d_x = d_y = 8 AR(1) latent (F = 0.95 I, Q = 0.2 I, x0 ~ N(0, I)) with
+    y_{t,i} ~ Poisson(exp(x_{t,i})); delta = 0.2."""
+    rng = np.random.default_rng(seed)
+    m0, P0 = np.zeros(d), np.eye(d)
+    F, Q = 0.95 * np.eye(d), 0.2 * np.eye(d)
+    x = _simulate(rng, N, m0, P0, F, Q)
+    y = rng.poisson(np.exp(x)).astype(np.float64)
+    return Workload(f"poisson_ar1_d{d}_N{N}", N, m0, P0, F, Q, EMIT_POISSON_LOG, y,
+                    site=np.arange(d, dtype=np.int32), delta=0.2, order=2, seed=seed, x_true=x)
+
+
+def periodic_grid_F_Q(d: int = 64):
+    """F = 0.9 I + 0.04 (P + P^T), P the cyclic shift; Q the squared-exponential
+    kernel on the periodic grid, lengthscale 4, variance 0.1, plus 1e-6 I."""
+    P = np.roll(np.eye(d), 1, axis=1)
+    F = 0.9 * np.eye(d) + 0.04 * (P + P.T)
+    i = np.arange(d)
+    dist = np.abs(i[:, None] - i[None, :])
+    dist = np.minimum(dist, d - dist)
+    Q = 0.1 * np.exp(-dist.astype(float) ** 2 / (2 * 4.0 ** 2)) + 1e-6 * np.eye(d)
+    return F, Q
+
+
+# Step size for the latent-field workload, frozen after a Robbins-Monro warm-up
+# toward 30% acceptance (see paper_2303_00301_amd.mcmc.tune_delta).
+LATENT_FIELD_DELTA = 0.03
+
+
+def latent_field(N: int = 4096, d: int = 64, n_sites: int = 32, nu: float = 3.0,
+                 scale: float = 0.5, seed: int = 3, delta: Optional[float] = None) -> Workload:
+    """d_x = 64 latent field on a 1-D periodic grid (periodic_grid_F_Q), observed
+    at n_sites evenly spaced sites through Student-t(nu, scale) noise."""
+    rng = np.random.default_rng(seed)
+    m0, P0 = np.zeros(d), np.eye(d)
+    F, Q = periodic_grid_F_Q(d)
+    x = _simulate(rng, N, m0, P0, F, Q)
+    site = (np.arange(n_sites) * (d // n_sites)).astype(np.int32)
+    y = x[:, site] + scale * rng.standard_t(nu, size=(N, n_sites))
+    return Workload(f"latent_field_d{d}_N{N}", N, m0, P0, F, Q, EMIT_STUDENT_T, y, site=site,
+                    nu=nu, scale=scale, delta=LATENT_FIELD_DELTA if delta is None else delta,
+                    order=2, seed=seed, x_true=x)
+
+
+def ragged_poisson_batch(n_chains: int = 512, n_min: int = 128, n_max: int = 8192,
+                         dims=(4, 16, 32), seed: int = 4, delta: float = 0.1) -> List[Workload]:
+    """Independent chains with N_i ~ U{n_min..n_max}, d_i ~ U(dims), random stable
+    F_i (spectral radius ~ U(0.5, 0.95)), Q = 0.1 I, P0 = I, Poisson log-link
+    emissions with d_y = d_x."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(n_chains):
+        N = int(rng.integers(n_min, n_max + 1))
+        d = int(rng.choice(dims))
+        rho = float(rng.uniform(0.5, 0.95))
+        F = random_stable_F(rng, d, rho)
+        Q = 0.1 * np.eye(d)
+        m0, P0 = np.zeros(d), np.eye(d)
+        x = _simulate(rng, N, m0, P0, F, Q)
+        y = rng.poisson(np.exp(np.clip(x, -30, 10))).astype(np.float64)
+        out.append(Workload(f"chain{c}_d{d}_N{N}", N, m0, P0, F, Q, EMIT_POISSON_LOG, y,
+                            site=np.arange(d, dtype=np.int32), delta=delta, order=2,
+                            seed=1000 * seed + c, x_true=x))
+    return out
+
+
+@dataclass
+class LGSSMTheta:
+    F: np.ndarray
+    logq: np.ndarray
+    H: np.ndarray
+    logr: np.ndarray
+
+    def flat(self) -> np.ndarray:
+        return np.concatenate([self.F.ravel(), self.logq, self.H.ravel(), self.logr])
+
+
+@dataclass
+class ParamWorkload:
+    name: str
+    N: int
+    m0: np.ndarray
+    P0: np.ndarray
+    y: np.ndarray
+    theta_true: LGSSMTheta
+    theta0: LGSSMTheta
+
+
+def lgssm_params(N: int = 16384, dx: int = 32, dy: int = 16, seed: int = 5) -> ParamWorkload:
+    """Linear-Gaussian SSM for parameter gradients: theta = (F, log diag Q, H,
+    log diag R).  True: F (spectral radius 0.9), Q = 0.1 I, H ~ N(0, 1/32),
+    R = 0.5 I; y simulated from seed.  Evaluation point theta0 drawn fresh."""
+    rng = np.random.default_rng(seed)
+    m0, P0 = np.zeros(dx), np.eye(dx)
+    Ft = random_stable_F(rng, dx, 0.9)
+    Ht = rng.normal(0.0, np.sqrt(1.0 / 32), size=(dy, dx))
+    tt = LGSSMTheta(Ft, np.full(dx, np.log(0.1)), Ht, np.full(dy, np.log(0.5)))
+    x = _simulate(rng, N, m0, P0, Ft, 0.1 * np.eye(dx))
+    y = x @ Ht.T + np.sqrt(0.5) * rng.standard_normal((N, dy))
+    rng0 = np.random.default_rng(seed + 1000)
+    t0 = LGSSMTheta(random_stable_F(rng0, dx, 0.9),
+                    np.log(0.1) + 0.1 * rng0.standard_normal(dx),
+                    rng0.normal(0.0, np.sqrt(1.0 / 32), size=(dy, dx)),
+                    np.log(0.5) + 0.1 * rng0.standard_normal(dy))
+    return ParamWorkload(f"lgssm_params_dx{dx}_dy{dy}_N{N}", N, m0, P0, y, tt, t0)
