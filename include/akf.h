@@ -1,0 +1,167 @@
+/*
+ * akf.h -- C ABI of the MI355X auxiliary Kalman MCMC library (libauxkf.so).
+ *
+ * Method: Corenflos & Sarkka, "Auxiliary MCMC samplers for parallelisable
+ * inference in high-dimensional latent dynamical systems" (arXiv 2303.00301).
+ * A state-space model has Gaussian dynamics p_0 = N(m0, P0),
+ * p_t(x_t | x_{t-1}) = N(F x_{t-1} + b, Q) and emission densities h_t(y_t | x_t)
+ * (Sec. 2.2, eq. gaussian-FK).  One MCMC step (Alg. "General Auxiliary Kalman
+ * sampler" with Sigma_t = I) draws u_t = x_t + sqrt(delta/2) xi^u_t, linearises
+ * log h_t at the current path (first order, eq. gaussian-FK-proposal, or second
+ * order, eq. second-order), samples a proposal x* from the resulting auxiliary
+ * linear-Gaussian model with a parallel-in-time Kalman filter and pathwise
+ * backward sampler (App. A, "Prefix-sums and the parallel Kalman filter",
+ * "Parallel Rauch--Tung--Striebel sampler"), and accepts it with the Hastings
+ * ratio of the augmented target pi(x, u).
+ *
+ * Conventions for every entry point:
+ *   - Arrays are DEVICE pointers to row-major float64 data, owned by the caller;
+ *     the library never allocates, frees or retains them.  Every call is
+ *     enqueued on `stream` (a hipStream_t; NULL = the default stream) and is
+ *     asynchronous with respect to the host.
+ *   - Scratch memory is the caller's `ws` buffer of `ws_bytes` bytes (device,
+ *     256-byte aligned); query its size with the matching *_workspace_bytes
+ *     call.  A workspace must not be shared by calls that may overlap.
+ *   - Synchronous errors (bad arguments, unsupported sizes, launch failures)
+ *     are returned as akf_status; akf_last_error() describes the last one on
+ *     the calling thread.  Numerical failures are asynchronous and reported
+ *     in the per-step device status word (AKF_ST_* bits); a step with a
+ *     non-zero status rejects (x_out = x_in).
+ *   - Sizes: 1 <= dx <= 64, 1 <= dy <= 64, N >= 1.
+ */
+#ifndef AKF_H
+#define AKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AKF_OK = 0,
+  AKF_ERR_INVALID = 1,     /* null pointer, bad enum, delta <= 0, ... */
+  AKF_ERR_SHAPE = 2,       /* sizes outside the supported range */
+  AKF_ERR_WORKSPACE = 3,   /* ws_bytes smaller than required, or misaligned */
+  AKF_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+  AKF_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
+} akf_status;
+
+typedef enum {
+  AKF_EMIT_GAUSSIAN = 0,    /* y_t = H x_t + N(0, R): H [dy,dx], R [dy,dy] SPD */
+  AKF_EMIT_POISSON_LOG = 1, /* y_{t,k} ~ Poisson(exp(x_{t,site[k]})) */
+  AKF_EMIT_STUDENT_T = 2    /* y_{t,k} = x_{t,site[k]} + scale * t_nu */
+} akf_emit;
+
+/* Per-step device status bits. */
+enum {
+  AKF_ST_FWD_NOT_PD = 1, /* forward proposal undefined: 2/delta - Lambda_t not PD,
+                            or a Cholesky pivot <= 0 in the forward filter/sampler */
+  AKF_ST_REV_NOT_PD = 2, /* same for the reverse proposal at x* */
+  AKF_ST_NONFINITE = 4   /* the log ratio is not finite */
+};
+/* When the forward proposal fails only AKF_ST_FWD_NOT_PD is reported, since x*
+ * and everything derived from it are then undefined. */
+
+/*
+ * Model description (eq. ssm with Gaussian dynamics).  m0 [dx], P0 [dx,dx],
+ * F [dx,dx], b [dx] or NULL (zero), Q [dx,dx].  Emission per `emit`:
+ * GAUSSIAN uses H, R; POISSON_LOG and STUDENT_T use site [dy] (int32, each in
+ * [0, dx); several sites may observe the same coordinate) and, for STUDENT_T,
+ * nu > 0 and scale > 0.  All pointers are device pointers.
+ */
+typedef struct akf_model {
+  int32_t N, dx, dy;
+  const double *m0, *P0, *F, *b, *Q;
+  int32_t emit;
+  const double *H, *R;
+  const int32_t* site;
+  double nu, scale;
+} akf_model;
+
+/* Description of the last synchronous error on this thread (static storage). */
+const char* akf_last_error(void);
+
+/*
+ * Workspace bytes for akf_mh_step / akf_mh_run on this model.  `block` is the
+ * number of time steps per scan block (0 = automatic); pass the same value to
+ * the step call.  Returns 0 when the model sizes are unsupported.
+ */
+size_t akf_mh_workspace_bytes(const akf_model* model, int32_t order, int32_t block);
+
+/*
+ * One auxiliary Kalman MH step (Alg. "General Auxiliary Kalman sampler").
+ *   y      [N,dy]     observations
+ *   x_in   [N,dx]     current path
+ *   delta  > 0        auxiliary step size (u_t ~ N(x_t, delta/2 I))
+ *   order  1 or 2     linearisation order of log h_t
+ *   xi     [2,N,dx]   standard normals: xi[0] for u, xi[1] for the path sample
+ *   unif   [1]        uniform in (0,1) for the accept test (accept iff log unif < log r)
+ *   x_out  [N,dx]     new path (x* if accepted, else x_in); may alias x_in
+ *   log_ratio, logZ_fwd, logZ_rev [1] double, accepted, status [1] int32: optional
+ *                     (NULL = not written).  logZ_* are the log marginal
+ *                     likelihoods of the pseudo-observations under the forward
+ *                     (at x) and reverse (at x*) auxiliary models; log_ratio is
+ *                     -inf when status != 0.
+ */
+akf_status akf_mh_step(const akf_model* model, const double* y, const double* x_in, double delta,
+                       int32_t order, const double* xi, const double* unif, double* x_out,
+                       double* log_ratio, int32_t* accepted, double* logZ_fwd, double* logZ_rev,
+                       int32_t* status, void* ws, size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * n_steps MH steps on one chain, x updated in place.  xi [n_steps,2,N,dx],
+ * unif [n_steps]; per-step outputs are arrays of n_steps (each may be NULL).
+ * Same workspace as akf_mh_step.
+ */
+akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double delta,
+                      int32_t order, int32_t n_steps, const double* xi, const double* unif,
+                      double* log_ratio, int32_t* accepted, double* logZ_fwd, double* logZ_rev,
+                      int32_t* status, void* ws, size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * Parallel-in-time Kalman filter of the auxiliary linear-Gaussian model
+ * x_t = F x_{t-1} + b + N(0,Q), omega_t = x_t + N(0, diag(Omega_t))
+ * (App. A, "Prefix-sums and the parallel Kalman filter"; likelihood in the
+ * predictive form of eq. marginal-likelihood).  The model's emission fields
+ * are ignored.  omega, Omega [N,dx]; outputs mf [N,dx], Pf [N,dx,dx] (each may
+ * be NULL), ell [N] per-step log-likelihood terms.  *status (device int32, may
+ * be NULL) receives AKF_ST_FWD_NOT_PD on a Cholesky failure, else 0.
+ */
+size_t akf_filter_workspace_bytes(const akf_model* model, int32_t block);
+akf_status akf_aux_filter(const akf_model* model, const double* omega, const double* Omega,
+                          double* mf, double* Pf, double* ell, int32_t* status, void* ws,
+                          size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * Pathwise sampler (App. A, "Parallel Rauch--Tung--Striebel sampler"): from the
+ * filtering moments mf [N,dx], Pf [N,dx,dx] of the model's dynamics, returns
+ * x [N,dx] with x_{N-1} = mf + chol(Pf) xi_{N-1} and
+ * x_t = mf_t + G_t (x_{t+1} - F mf_t - b) + chol(Sigma_t) xi_t (chol = lower
+ * Cholesky factor with positive diagonal), xi [N,dx] standard normals.
+ */
+size_t akf_sampler_workspace_bytes(const akf_model* model, int32_t block);
+akf_status akf_rts_sample(const akf_model* model, const double* mf, const double* Pf,
+                          const double* xi, double* x, int32_t* status, void* ws,
+                          size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * Kernel timing, for diagnostics and benchmarks.  While enabled for `family`
+ * (0 filter fold, 1 filter up-sweep, 2 filter down-sweep, 3 filter final,
+ * 4 sampler element build, 5 sampler fold, 6 sampler up-sweep, 7 sampler
+ * down-sweep, 8 sampler final), every launch of that kernel on any stream is
+ * bracketed by a pair of hipEvents recorded on the launch stream; at most
+ * `capacity` launches are kept.  akf_timing_collect waits for the recorded
+ * events and returns the number of launches and their summed duration in
+ * milliseconds, then clears the record.  family < 0 disables timing.  The
+ * events are created by akf_timing_enable (not under graph capture).
+ */
+akf_status akf_timing_enable(int32_t family, int32_t capacity);
+akf_status akf_timing_collect(int32_t* n_launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AKF_H */

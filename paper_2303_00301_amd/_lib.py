@@ -1,0 +1,82 @@
+"""ctypes binding of libauxkf.so (include/akf.h).  Argument marshalling only:
+every step of the sampler runs in the library's HIP kernels.  The library must
+have been built (``python -m paper_2303_00301_amd.build`` or
+``__graft_entry__.build()``); there is no fallback."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libauxkf.so")
+
+AKF_OK = 0
+ERR_NAMES = {1: "AKF_ERR_INVALID", 2: "AKF_ERR_SHAPE", 3: "AKF_ERR_WORKSPACE", 4: "AKF_ERR_HIP",
+             5: "AKF_ERR_UNSUPPORTED"}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+
+
+class AkfModel(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32), ("dx", C.c_int32), ("dy", C.c_int32),
+        ("m0", C.c_void_p), ("P0", C.c_void_p), ("F", C.c_void_p), ("b", C.c_void_p),
+        ("Q", C.c_void_p),
+        ("emit", C.c_int32),
+        ("H", C.c_void_p), ("R", C.c_void_p),
+        ("site", C.c_void_p),
+        ("nu", C.c_double), ("scale", C.c_double),
+    ]
+
+
+# name -> (restype, argtypes); the exported symbols of include/akf.h
+_vp, _sz, _i32, _d = C.c_void_p, C.c_size_t, C.c_int32, C.c_double
+_MP = C.POINTER(AkfModel)
+SIGNATURES = {
+    "akf_last_error": (C.c_char_p, []),
+    "akf_mh_workspace_bytes": (_sz, [_MP, _i32, _i32]),
+    "akf_mh_step": (C.c_int, [_MP, _vp, _vp, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                              _vp, _sz, _i32, _vp]),
+    "akf_mh_run": (C.c_int, [_MP, _vp, _vp, _d, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                             _vp, _sz, _i32, _vp]),
+    "akf_filter_workspace_bytes": (_sz, [_MP, _i32]),
+    "akf_aux_filter": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "akf_sampler_workspace_bytes": (_sz, [_MP, _i32]),
+    "akf_rts_sample": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "akf_timing_enable": (C.c_int, [_i32, _i32]),
+    "akf_timing_collect": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+}
+
+# kernel families of akf_timing_enable
+FAMILIES = {"filter_fold": 0, "filter_up": 1, "filter_down": 2, "filter_final": 3,
+            "samp_build": 4, "samp_fold": 5, "samp_up": 6, "samp_down": 7, "samp_final": 8}
+
+_lib = None
+
+
+class AkfError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Load the library and declare every exported entry point."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise AkfError(f"HIP library not built: {path} is missing "
+                           "(run `python -m paper_2303_00301_amd.build`)")
+        lib = C.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def check(rc: int, what: str):
+    if rc != AKF_OK:
+        msg = load().akf_last_error()
+        raise AkfError(f"{what} failed with {ERR_NAMES.get(rc, rc)}: "
+                       f"{msg.decode() if msg else ''}")

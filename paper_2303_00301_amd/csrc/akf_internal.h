@@ -1,0 +1,121 @@
+// akf_internal.h -- structures shared by the kernels and the host launcher.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace akf {
+
+enum { EMIT_GAUSSIAN = 0, EMIT_POISSON_LOG = 1, EMIT_STUDENT_T = 2 };
+enum { ST_FWD_NOT_PD = 1, ST_REV_NOT_PD = 2, ST_NONFINITE = 4 };
+
+// Model as the kernels see it (all arrays are device pointers, d-sized).
+struct KModel {
+  int N, d, dy, emit;
+  const double *m0, *P0, *F, *b, *Q;
+  const double *H, *R;
+  const int* site;
+  double nu, scale;
+};
+
+// Filter element (A, b, C, eta, J), padded to D.
+template <int D>
+struct ElemLayout {
+  static constexpr int A = 0, C = D * D, J = 2 * D * D, b = 3 * D * D, eta = 3 * D * D + D;
+  static constexpr int SIZE = 3 * D * D + 2 * D;
+};
+
+// Filtering moments entering a tree node; flag != 0 marks the identity prefix.
+template <int D>
+struct PrefLayout {
+  static constexpr int P = 0, m = D * D, flag = D * D + D;
+  static constexpr int SIZE = D * D + D + 2;
+};
+
+// Sampling path element (E, U).
+template <int D>
+struct SampLayout {
+  static constexpr int E = 0, U = D * D;
+  static constexpr int SIZE = D * D + D;
+};
+
+struct StepArgs {
+  const double* y;
+  const double* x;
+  const double* xi_u;
+  double delta;
+  int order;
+  double *u, *om, *Om, *om2, *Om2;  // [N*d]
+  double* xs;                       // [N*d]
+  double *ell, *ell2;               // [N]
+  double *part_lh_x, *part_lh_xs, *part_terms;
+  double *g_G, *g_Rinv, *g_Omd, *g_Omd_inv, *g_scal;
+  int* status;
+  int* accept_flag;
+};
+
+struct FilterArgs {
+  int B;
+  const double* om;
+  const double* Om;   // diagonal Omega [N*d]
+  const double* Omd;  // dense constant Omega [d*d] or nullptr
+  double* elem;       // block elements, level 0 of the tree
+  const double* pre;  // prefixes entering each block
+  double *mf, *Pf;    // [N*ldm], [N*ldm*ldm] or nullptr
+  int ldm;            // leading dimension of mf/Pf (D inside the step, d for callers)
+  double* ell;        // [N]
+  int* status;
+  int fail_bit;
+};
+
+struct TreeArgs {
+  const double* src;
+  double* dst;
+  int n_src, n_dst;
+  const double* pre_src;
+  double* pre_dst;
+  int* status;
+  int fail_bit;
+};
+
+struct SampArgs {
+  int B;
+  const double *mf, *Pf, *xi_x;
+  int ldm;           // leading dimension of mf/Pf
+  double *E, *U;     // [N*D*D], [N*D]
+  double* agg;       // block aggregates, level 0
+  const double* xin; // x* entering each block from the right, level 0
+  double* xs;        // [N*d]
+  int* status;
+};
+
+struct FinalArgs {
+  const double* unif;
+  double* log_ratio;
+  int* accepted;
+  double* logZ_fwd;
+  double* logZ_rev;
+  int* status_out;
+  int n_part_fwd, n_part_rev;
+};
+
+// Kernel families for the timing hook (include/akf.h, akf_timing_enable).
+enum {
+  FAM_FILTER_FOLD = 0, FAM_FILTER_UP = 1, FAM_FILTER_DOWN = 2, FAM_FILTER_FINAL = 3,
+  FAM_SAMP_BUILD = 4, FAM_SAMP_FOLD = 5, FAM_SAMP_UP = 6, FAM_SAMP_DOWN = 7, FAM_SAMP_FINAL = 8,
+  FAM_LIN = 9, FAM_FINALIZE = 10, FAM_COUNT = 11
+};
+// Called by the launchers before (begin = 1) and after (begin = 0) each launch.
+void timing_mark(int family, int begin, hipStream_t st);
+
+hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, TreeArgs* down,
+                             int n_levels, hipStream_t st);
+hipError_t launch_sampler_any(int D, const KModel& M, SampArgs S, TreeArgs* up, TreeArgs* down,
+                              int n_levels, hipStream_t st);
+hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStream_t st);
+hipError_t launch_step_init(int* status, double* root_flag, double* root_xin, int D,
+                            hipStream_t st);
+hipError_t launch_finalize(const KModel& M, StepArgs A, FinalArgs F, const double* x,
+                           double* x_out, hipStream_t st);
+hipError_t set_lds_limits_all();
+
+}  // namespace akf

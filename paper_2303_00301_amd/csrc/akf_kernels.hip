@@ -1,0 +1,1205 @@
+// akf_kernels.hip -- gfx950 kernels for one auxiliary-Kalman MH step.
+//
+// Method: Corenflos & Sarkka, auxiliary Kalman sampler (Alg. "General
+// Auxiliary Kalman sampler", eq. second-order / gaussian-FK-proposal) with the
+// parallel-in-time filter (App. A, "Prefix-sums and the parallel Kalman
+// filter") and the parallel pathwise RTS sampler (App. A, "Parallel
+// Rauch--Tung--Striebel sampler", eq. backward, eq. EgL_comb).
+//
+// The auxiliary LGSSM of one step has the model's Gaussian dynamics and the
+// pseudo-observation omega_t = x_t + N(0, Omega_t) (H = I).  Both scans are
+// blocked, reduce-then-scan, with one team (workgroup) per block of B time
+// steps:
+//   filter  : fold   -- each block folds its elements sequentially into the
+//                       block element (A, b, C, eta, J);
+//             tree   -- work-efficient up-sweep (full element combine) and
+//                       down-sweep (prefix applied to an element) over the
+//                       block elements -> filtering moments entering each block;
+//             final  -- each block re-runs its steps from that prefix, giving
+//                       m^f_t, P^f_t and the predictive log-likelihood terms.
+//   sampler : build  -- one team per t: E_t, U_t = g_t + chol(L_t) xi_t;
+//             fold   -- suffix aggregate of (E, U) per block;
+//             tree   -- up-sweep (E_i E_j, E_i U_j + U_i), down-sweep of the
+//                       boundary states;
+//             final  -- x*_t = E_t x*_{t+1} + U_t inside each block.
+// Every matrix product is an f64 MFMA; Cholesky factors are FP64.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "akf_team.hpp"
+#include "akf_internal.h"
+
+namespace akf {
+
+static constexpr double LOG2PI = 1.8378770664093454835606594728112;
+
+__device__ __forceinline__ void flag_status(int* st, int bit) { atomicOr(st, bit); }
+
+// ---------------------------------------------------------------------------
+// status word / scalar reset (graph-safe replacement for a memset)
+// ---------------------------------------------------------------------------
+// Also marks the root of the filter prefix tree as the identity and sets the
+// state entering the sampler's last block from the right to zero (it is
+// multiplied by E = 0 of the terminal step, but must be finite).
+__global__ void k_step_init(int* status, double* root_flag, double* root_xin, int D) {
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    *status = 0;
+    if (root_flag) *root_flag = 1.0;
+  }
+  if (root_xin && tid < D) root_xin[tid] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Emission linearisation, diagonal families (Poisson log-link, Student-t).
+// One thread per (t, i).  Site k observes latent site[k]; a latent observed by
+// several sites sums their contributions.
+//   v_i = d log h / d x_i,  Lambda_ii = d^2 log h / d x_i^2 (0 under order 1)
+//   Omega_i = 1 / (2/delta - Lambda_ii),  omega_i = Omega_i (2/delta u_i + v_i - Lambda_ii x_i)
+// (eq. second-order with Sigma_t = I; order 1: eq. gaussian-FK-proposal).
+// ---------------------------------------------------------------------------
+struct EmitOut {
+  double lh, v, lam;
+};
+
+__device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __restrict__ yt,
+                                             double xi, int i) {
+  EmitOut o{0.0, 0.0, 0.0};
+  for (int k = 0; k < M.dy; ++k) {
+    if (M.site[k] != i) continue;
+    if (M.emit == EMIT_POISSON_LOG) {
+      const double e = exp(xi);
+      o.lh += yt[k] * xi - e;
+      o.v += yt[k] - e;
+      o.lam -= e;
+    } else {
+      const double a = M.nu * M.scale * M.scale;
+      const double r = yt[k] - xi, den = a + r * r;
+      o.lh += -0.5 * (M.nu + 1.0) * log1p(r * r / a);
+      o.v += (M.nu + 1.0) * r / den;
+      o.lam += (M.nu + 1.0) * (r * r - a) / (den * den);
+    }
+  }
+  return o;
+}
+
+// Forward linearisation at x: draws u, writes omega/Omega (diagonal), log h
+// partial sums per workgroup.  blockDim.x = 256.
+__global__ void __launch_bounds__(256) k_lin_fwd_diag(KModel M, StepArgs A) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)M.N * M.d;
+  double lh = 0.0;
+  if (gid < n) {
+    const int t = (int)(gid / M.d), i = (int)(gid % M.d);
+    const double x = A.x[gid];
+    const double u = x + sqrt(0.5 * A.delta) * A.xi_u[gid];
+    A.u[gid] = u;
+    const EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, x, i);
+    const double lam = (A.order == 1) ? 0.0 : e.lam;
+    const double prec = 2.0 / A.delta - lam;
+    if (!(prec > 0.0) || !isfinite(e.v) || !isfinite(prec)) {
+      flag_status(A.status, ST_FWD_NOT_PD);
+      A.om[gid] = 0.0;
+      A.Om[gid] = 1.0;
+    } else {
+      const double Om = 1.0 / prec;
+      A.Om[gid] = Om;
+      A.om[gid] = Om * (2.0 / A.delta * u + e.v - lam * x);
+    }
+    lh = e.lh;
+  }
+  // block partial of log h(x)
+  __shared__ double red[4];
+  for (int o = 32; o > 0; o >>= 1) lh += __shfl_xor(lh, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lh;
+  __syncthreads();
+  if (threadIdx.x == 0) A.part_lh_x[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// Reverse linearisation at x* with the same u, and the per-(t,i) MH terms:
+//   [log h(y|x*) - log h(y|x)] + [(u-x)^2 - (u-x*)^2]/delta
+//   + log N(omega*_i; x_i, Omega*_i) - log N(omega_i; x*_i, Omega_i)
+__global__ void __launch_bounds__(256) k_lin_rev_diag(KModel M, StepArgs A) {
+  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = (int64_t)M.N * M.d;
+  double term = 0.0, lhs = 0.0;
+  if (gid < n) {
+    const int t = (int)(gid / M.d), i = (int)(gid % M.d);
+    const double x = A.x[gid], xs = A.xs[gid], u = A.u[gid];
+    const EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, xs, i);
+    const double lam = (A.order == 1) ? 0.0 : e.lam;
+    const double prec = 2.0 / A.delta - lam;
+    double om2 = 0.0, Om2 = 1.0;
+    if (!(prec > 0.0) || !isfinite(e.v) || !isfinite(prec)) {
+      flag_status(A.status, ST_REV_NOT_PD);
+    } else {
+      Om2 = 1.0 / prec;
+      om2 = Om2 * (2.0 / A.delta * u + e.v - lam * xs);
+    }
+    A.om2[gid] = om2;
+    A.Om2[gid] = Om2;
+    const double om = A.om[gid], Om = A.Om[gid];
+    const double a = u - x, c = u - xs;
+    const double rq = om2 - x, fq = om - xs;
+    term = (a * a - c * c) / A.delta +
+           (-0.5 * (LOG2PI + log(Om2) + rq * rq / Om2)) - (-0.5 * (LOG2PI + log(Om) + fq * fq / Om));
+    lhs = e.lh;
+  }
+  __shared__ double red[8];
+  for (int o = 32; o > 0; o >>= 1) {
+    term += __shfl_xor(term, o);
+    lhs += __shfl_xor(lhs, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = term;
+    red[4 + (threadIdx.x >> 6)] = lhs;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    A.part_terms[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    A.part_lh_xs[blockIdx.x] = red[4] + red[5] + red[6] + red[7];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Gaussian emissions y = H x + N(0, R): v = G (y - H x), Lambda = -G H with
+// G = H^T R^{-1}; constant dense Omega under order 2.  One thread per t.
+// gprep: G [d, dy], Rinv [dy, dy], Omd [d, d] (order 2), Omd_inv [d, d],
+// logdet(Omd) in gscal[0].
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_gauss_prep(KModel M, StepArgs A) {
+  // single team of 64 threads; dims <= 64.  Gauss-Jordan on SPD matrices
+  // (no pivoting needed) in LDS.
+  __shared__ double sM[64 * 65];
+  __shared__ double sI[64 * 65];
+  const int tid = threadIdx.x, d = M.d, p = M.dy;
+  const int LDm = 65;
+  // R^{-1}
+  for (int e = tid; e < p * p; e += 64) {
+    const int i = e / p, j = e % p;
+    sM[i * LDm + j] = M.R[e];
+    sI[i * LDm + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < p; ++k) {
+    const double piv = sM[k * LDm + k];
+    __syncthreads();
+    if (tid < p) {
+      sM[k * LDm + tid] /= piv;
+      sI[k * LDm + tid] /= piv;
+    }
+    __syncthreads();
+    for (int e = tid; e < p * p; e += 64) {
+      const int i = e / p, j = e % p;
+      if (i != k) {
+        const double f = sM[i * LDm + k];
+        sI[i * LDm + j] -= f * sI[k * LDm + j];
+        if (j != k) sM[i * LDm + j] -= f * sM[k * LDm + j];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < p; i += 64)
+      if (i != k) sM[i * LDm + k] = 0.0;
+    __syncthreads();
+  }
+  for (int e = tid; e < p * p; e += 64) A.g_Rinv[e] = sI[(e / p) * LDm + e % p];
+  // G = H^T R^{-1}  [d, p]
+  for (int e = tid; e < d * p; e += 64) {
+    const int i = e / p, j = e % p;
+    double s = 0.0;
+    for (int k = 0; k < p; ++k) s += M.H[k * d + i] * sI[k * LDm + j];
+    A.g_G[e] = s;
+  }
+  __syncthreads();
+  // precision 2/delta I - Lambda = 2/delta I + G H  -> Omd_inv ; Omd = inverse
+  for (int e = tid; e < d * d; e += 64) {
+    const int i = e / d, j = e % d;
+    double s = 0.0;
+    if (A.order != 1)
+      for (int k = 0; k < p; ++k) s += A.g_G[i * p + k] * M.H[k * d + j];
+    s += (i == j) ? 2.0 / A.delta : 0.0;
+    A.g_Omd_inv[e] = s;
+    sM[i * LDm + j] = s;
+    sI[i * LDm + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double logdet_prec = 0.0;
+  for (int k = 0; k < d; ++k) {
+    const double piv = sM[k * LDm + k];
+    logdet_prec += log(piv);
+    __syncthreads();
+    if (tid < d) {
+      sM[k * LDm + tid] /= piv;
+      sI[k * LDm + tid] /= piv;
+    }
+    __syncthreads();
+    for (int e = tid; e < d * d; e += 64) {
+      const int i = e / d, j = e % d;
+      if (i != k) {
+        const double f = sM[i * LDm + k];
+        sI[i * LDm + j] -= f * sI[k * LDm + j];
+        if (j != k) sM[i * LDm + j] -= f * sM[k * LDm + j];
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < d; i += 64)
+      if (i != k) sM[i * LDm + k] = 0.0;
+    __syncthreads();
+  }
+  for (int e = tid; e < d * d; e += 64) {
+    const int i = e / d, j = e % d;
+    A.g_Omd[e] = 0.5 * (sI[i * LDm + j] + sI[j * LDm + i]);
+  }
+  if (tid == 0) A.g_scal[0] = -logdet_prec;  // log det Omega
+}
+
+// log h(y_t | x) = -1/2 (y - H x)^T R^{-1} (y - H x) (constants dropped)
+__device__ double gauss_loglik_t(const KModel& M, const StepArgs& A, const double* yt,
+                                 const double* xt, double* res /*[dy] scratch*/) {
+  for (int k = 0; k < M.dy; ++k) {
+    double s = yt[k];
+    for (int j = 0; j < M.d; ++j) s -= M.H[k * M.d + j] * xt[j];
+    res[k] = s;
+  }
+  double q = 0.0;
+  for (int k = 0; k < M.dy; ++k) {
+    double s = 0.0;
+    for (int l = 0; l < M.dy; ++l) s += A.g_Rinv[k * M.dy + l] * res[l];
+    q += res[k] * s;
+  }
+  return -0.5 * q;
+}
+
+// One thread per t.  rev = 0: forward (draw u, linearise at x); rev = 1:
+// reverse (linearise at x*, same u) plus the MH terms.  Order 2 gives a
+// constant dense Omega (omega = Omega (2/delta u + G y)); order 1 gives the
+// diagonal Omega = delta/2 with omega = u + delta/2 v.
+__global__ void __launch_bounds__(64) k_lin_gauss(KModel M, StepArgs A, int rev) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double lh = 0.0, term = 0.0;
+  if (t < M.N) {
+    const int d = M.d, p = M.dy;
+    const double* yt = A.y + (int64_t)t * p;
+    const double* xt = A.x + (int64_t)t * d;
+    const double* xst = A.xs + (int64_t)t * d;
+    double* ut = A.u + (int64_t)t * d;
+    double res[64], rhs[64], v[64];
+    if (!rev)
+      for (int i = 0; i < d; ++i) ut[i] = xt[i] + sqrt(0.5 * A.delta) * A.xi_u[(int64_t)t * d + i];
+    const double* lin = rev ? xst : xt;
+    lh = gauss_loglik_t(M, A, yt, lin, res);
+    double* om = (rev ? A.om2 : A.om) + (int64_t)t * d;
+    double* Om = (rev ? A.Om2 : A.Om) + (int64_t)t * d;
+    if (A.order == 1) {
+      // v = G (y - H x)
+      for (int i = 0; i < d; ++i) {
+        double s = 0.0;
+        for (int k = 0; k < p; ++k) s += A.g_G[i * p + k] * res[k];
+        v[i] = s;
+      }
+      for (int i = 0; i < d; ++i) {
+        Om[i] = 0.5 * A.delta;
+        om[i] = ut[i] + 0.5 * A.delta * v[i];
+      }
+    } else {
+      for (int i = 0; i < d; ++i) {
+        double s = 2.0 / A.delta * ut[i];
+        for (int k = 0; k < p; ++k) s += A.g_G[i * p + k] * yt[k];
+        rhs[i] = s;
+      }
+      for (int i = 0; i < d; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < d; ++j) s += A.g_Omd[i * d + j] * rhs[j];
+        om[i] = s;
+        Om[i] = A.g_Omd[i * d + i];
+      }
+    }
+    if (rev) {
+      // MH terms (log h difference is added from the partial sums)
+      double aux = 0.0;
+      for (int i = 0; i < d; ++i) {
+        const double a = ut[i] - xt[i], c = ut[i] - xst[i];
+        aux += a * a - c * c;
+      }
+      term = aux / A.delta;
+      const double* omf = A.om + (int64_t)t * d;
+      if (A.order == 1) {
+        const double s2 = 0.5 * A.delta;
+        double q = 0.0;
+        for (int i = 0; i < d; ++i) {
+          const double rq = om[i] - xt[i], fq = omf[i] - xst[i];
+          q += -0.5 * rq * rq / s2 + 0.5 * fq * fq / s2;
+        }
+        term += q;
+      } else {
+        // same dense Omega both ways: log-determinants cancel
+        double q = 0.0;
+        for (int i = 0; i < d; ++i) {
+          double sr = 0.0, sf = 0.0;
+          for (int j = 0; j < d; ++j) {
+            sr += A.g_Omd_inv[i * d + j] * (om[j] - xt[j]);
+            sf += A.g_Omd_inv[i * d + j] * (omf[j] - xst[j]);
+          }
+          q += -0.5 * (om[i] - xt[i]) * sr + 0.5 * (omf[i] - xst[i]) * sf;
+        }
+        term += q;
+      }
+    }
+  }
+  __shared__ double red[2];
+  for (int o = 32; o > 0; o >>= 1) {
+    lh += __shfl_xor(lh, o);
+    term += __shfl_xor(term, o);
+  }
+  if (threadIdx.x == 0) {
+    if (rev) {
+      A.part_terms[blockIdx.x] = term;
+      A.part_lh_xs[blockIdx.x] = lh;
+    } else {
+      A.part_lh_x[blockIdx.x] = lh;
+    }
+  }
+  (void)red;
+}
+
+// ---------------------------------------------------------------------------
+// Shared pieces of the filter kernels
+// ---------------------------------------------------------------------------
+
+// S = P + Omega_t into LDS buffer s (diagonal Omega from om_diag, or the dense
+// constant Omega when dense != nullptr).  Team-wide; ends synchronised.
+template <int D>
+__device__ __forceinline__ void build_S(double* s, const RM<D>& P, const double* __restrict__ Om_t,
+                                        const double* __restrict__ dense, int d) {
+  rm_stage<D>(P, s);
+  team_sync();
+  const int tid = threadIdx.x;
+  if (dense) {
+    for (int e = tid; e < d * d; e += Cfg<D>::NT) s[(e / d) * Cfg<D>::LD + (e % d)] += dense[e];
+  } else if (tid < d) {
+    s[tid * Cfg<D>::LD + tid] += Om_t[tid];
+  }
+  team_sync();
+}
+
+// Load a d x d user matrix into an LDS buffer, zero padded.
+template <int D>
+__device__ __forceinline__ void lds_load_mat(double* s, const double* __restrict__ g, int d) {
+  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
+    const int i = e / D, j = e % D;
+    s[i * Cfg<D>::LD + j] = (i < d && j < d) ? g[i * d + j] : 0.0;
+  }
+}
+
+// Load a padded D x D workspace matrix into an LDS buffer.
+template <int D>
+__device__ __forceinline__ void lds_load_pad(double* s, const double* __restrict__ g) {
+  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) s[(e / D) * Cfg<D>::LD + (e % D)] = g[e];
+}
+
+template <int D>
+__device__ __forceinline__ void vec_load(double* s, const double* __restrict__ g, int d) {
+  const int tid = threadIdx.x;
+  if (tid < D) s[tid] = (tid < d && g) ? g[tid] : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Filter, phase 1: fold the elements of one block.
+// State (A, b, C, eta, J) represents p(x_t | omega_{s:t}, x_{s-1}) =
+// N(A x_{s-1} + b, C) and p(omega_{s:t} | x_{s-1}) ~ exp(-x'Jx/2 + eta'x).
+// Appending step t (predict through the dynamics, condition on omega_t):
+//   Pp = F C F' + Q, T = F A, mu = F b + bias,  S = Pp + Omega_t = L L'
+//   X = L^{-1} Pp, Y = L^{-1} T, r = L^{-1}(omega_t - mu)
+//   C <- Pp - X'X,  A <- T - X'Y,  J <- J + Y'Y,  b <- mu + X'r,  eta <- eta + Y'r
+// which is the element combine of App. A with the raw element of step t
+// written in terms of F, Q and Omega_t.  The block containing t = 0 starts
+// from the prior (A = 0 throughout).  Output element layout: ElemLayout.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs P) {
+  using C = Cfg<D>;
+  extern __shared__ double lds[];
+  double* sF = lds;
+  double* B1 = sF + C::MAT;
+  double* B2 = B1 + C::MAT;
+  double* B3 = B2 + C::MAT;
+  double* vb = B3 + C::MAT;   // b
+  double* veta = vb + D;      // eta
+  double* vmu = veta + D;     // mu
+  double* vw = vmu + D;       // omega - mu
+  double* vr = vw + D;        // r
+  double* scal = vr + D;      // 8 doubles
+  const int blk = blockIdx.x, tid = threadIdx.x, d = M.d;
+  const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
+  const bool first = (s0 == 0);
+  lds_load_mat<D>(sF, M.F, d);
+  if (tid < D) {
+    vb[tid] = 0.0;
+    veta[tid] = 0.0;
+  }
+  RM<D> A, Cc, J, T, X, Y;
+  rm_eye<D>(A, d);
+  rm_zero<D>(Cc);
+  rm_zero<D>(J);
+  team_sync();
+  bool ok = true;
+  for (int t = s0; t < s1; ++t) {
+    RM<D> Pp;
+    if (t == 0) {
+      rm_load<D>(Pp, M.P0, d, d);
+      if (tid < D) vmu[tid] = (tid < d) ? M.m0[tid] : 0.0;
+    } else {
+      rm_stage<D>(Cc, B1);
+      team_sync();
+      gemm<D, false, false, false>(T, sF, B1);  // F C
+      team_sync();
+      rm_stage<D>(T, B1);
+      team_sync();
+      gemm<D, false, true, false>(Pp, B1, sF);  // (F C) F'
+      rm_add_load<D>(Pp, M.Q, d, d);
+      matvec<D, false>(vmu, sF, vb);
+      team_sync();
+      if (tid < d && M.b) vmu[tid] += M.b[tid];
+      if (!first) {
+        rm_stage<D>(A, B1);
+        team_sync();
+        gemm<D, false, false, false>(T, sF, B1);  // F A
+        team_sync();
+      }
+    }
+    build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
+    double logdet;
+    ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;  // B3 = L^{-1}
+    rm_stage<D>(Pp, B1);
+    if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
+    team_sync();
+    gemm<D, false, false, false>(X, B3, B1);  // X = L^{-1} Pp
+    matvec<D, false>(vr, B3, vw);             // r = L^{-1} (omega - mu)
+    team_sync();
+    rm_stage<D>(X, B2);
+    team_sync();
+    gemm<D, true, false, false>(Cc, B2, B2);  // X'X
+    rm_axpy<D>(Cc, -1.0, Pp);
+    rm_axpy<D>(Cc, -2.0, Cc);  // Cc = Pp - X'X  (Cc <- -(X'X - Pp))
+    if (tid < D) {
+      double s = 0.0;
+      for (int j = 0; j < D; ++j) s = fma(B2[j * C::LD + tid], vr[j], s);
+      vb[tid] = vmu[tid] + s;  // b = mu + X' r
+    }
+    if (!first && t > 0) {
+      rm_stage<D>(T, B1);
+      team_sync();
+      gemm<D, false, false, false>(Y, B3, B1);  // Y = L^{-1} T
+      team_sync();
+      rm_stage<D>(Y, B1);
+      team_sync();
+      gemm<D, true, false, true>(J, B1, B1);   // J += Y'Y
+      gemm<D, true, false, false>(A, B2, B1);  // X'Y
+      rm_axpy<D>(A, -1.0, T);
+      rm_axpy<D>(A, -2.0, A);  // A = T - X'Y
+      if (tid < D) {
+        double s = 0.0;
+        for (int j = 0; j < D; ++j) s = fma(B1[j * C::LD + tid], vr[j], s);
+        veta[tid] += s;  // eta += Y' r
+      }
+    } else if (first) {
+      rm_zero<D>(A);
+    }
+    team_sync();
+    rm_symmetrise<D>(Cc, B1);
+  }
+  if (!ok && tid == 0) flag_status(P.status, P.fail_bit);
+  if (first) {
+    rm_zero<D>(A);
+    rm_zero<D>(J);
+  }
+  rm_symmetrise<D>(J, B1);
+  double* out = P.elem + (int64_t)blk * ElemLayout<D>::SIZE;
+  rm_store<D>(A, out + ElemLayout<D>::A, D, D);
+  rm_store<D>(Cc, out + ElemLayout<D>::C, D, D);
+  rm_store<D>(J, out + ElemLayout<D>::J, D, D);
+  if (tid < D) {
+    out[ElemLayout<D>::b + tid] = vb[tid];
+    out[ElemLayout<D>::eta + tid] = veta[tid];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Filter, phase 2 up-sweep: node k of a level = left (earlier) (x) right.
+// With C_i = L L' (FP64 Cholesky), W = I + L' J_j L = R R', V = L R^{-T}, so
+// that (I + C_i J_j)^{-1} C_i = V V' and (I + C_i J_j)^{-1} = I - V V' J_j:
+//   A  = A_j (A_i - V V' J_j A_i)
+//   b  = A_j (b_i + V V' c) + b_j,            c = eta_j - J_j b_i
+//   C  = (A_j V)(A_j V)' + C_j
+//   eta = A_i' (c - J_j V V' c) + eta_i
+//   J  = A_i' J_j A_i - (V' J_j A_i)'(V' J_j A_i) + J_i
+// (the element combine of App. A in Cholesky form; covariances stay PSD).
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) {
+  using C = Cfg<D>;
+  using EL = ElemLayout<D>;
+  extern __shared__ double lds[];
+  double* S0 = lds;
+  double* S1 = S0 + C::MAT;
+  double* S2 = S1 + C::MAT;
+  double* S3 = S2 + C::MAT;
+  double* vbi = S3 + C::MAT;
+  double* vc = vbi + D;
+  double* vz = vc + D;
+  double* vw = vz + D;
+  double* vk = vw + D;
+  double* scal = vk + D;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
+  double* out = T.dst + (int64_t)k * EL::SIZE;
+  if (2 * k + 1 >= T.n_src) {
+    for (int e = tid; e < EL::SIZE; e += C::NT) out[e] = ei[e];
+    return;
+  }
+  const double* ej = ei + EL::SIZE;
+  bool ok = true;
+  double ld;
+  lds_load_pad<D>(S0, ei + EL::C);
+  lds_load_pad<D>(S1, ej + EL::J);
+  if (tid < D) vbi[tid] = ei[EL::b + tid];
+  team_sync();
+  ok = chol_inv<D, false>(S0, S3, M.d, &ld, scal) && ok;  // S0 = L
+  RM<D> R1, R2, R3;
+  gemm<D, false, false, false>(R1, S1, S0);  // T = J_j L
+  rm_stage<D>(R1, S2);
+  team_sync();
+  gemm<D, true, false, false>(R2, S0, S2);  // L' T
+  {
+    RM<D> I;
+    rm_eye<D>(I, D);
+    rm_axpy<D>(R2, 1.0, I);  // W = I + L' J_j L
+  }
+  team_sync();
+  rm_stage<D>(R2, S2);
+  team_sync();
+  ok = chol_inv<D, true>(S2, S3, D, &ld, scal) && ok;  // S3 = R^{-1}
+  gemm<D, false, true, false>(R1, S0, S3);            // V = L R^{-T}
+  team_sync();
+  rm_stage<D>(R1, S2);  // S2 = V
+  // c = eta_j - J_j b_i
+  matvec<D, false>(vc, S1, vbi);
+  team_sync();
+  if (tid < D) vc[tid] = ej[EL::eta + tid] - vc[tid];
+  team_sync();
+  matvec<D, true>(vz, S2, vc);  // V' c
+  team_sync();
+  matvec<D, false>(vw, S2, vz);  // w = V V' c
+  team_sync();
+  matvec<D, false>(vk, S1, vw);  // J_j w
+  team_sync();
+  if (tid < D) vk[tid] = vc[tid] - vk[tid];  // k2 = c - J_j V V' c
+  lds_load_pad<D>(S0, ei + EL::A);           // S0 = A_i
+  team_sync();
+  gemm<D, false, false, false>(R1, S1, S0);  // P = J_j A_i
+  team_sync();
+  rm_stage<D>(R1, S3);  // S3 = P
+  team_sync();
+  gemm<D, true, false, false>(R2, S2, S3);  // Q' = V' P
+  gemm<D, true, false, false>(R3, S0, S3);  // A_i' P
+  rm_add_load<D>(R3, ei + EL::J, D, D);     // + J_i
+  // eta = A_i' k2 + eta_i
+  if (tid < D) {
+    double s = 0.0;
+    for (int j = 0; j < D; ++j) s = fma(S0[j * C::LD + tid], vk[j], s);
+    out[EL::eta + tid] = s + ei[EL::eta + tid];
+  }
+  team_sync();
+  rm_stage<D>(R2, S1);  // S1 = Q'
+  team_sync();
+  {
+    RM<D> QQ;
+    gemm<D, true, false, false>(QQ, S1, S1);  // Q'' Q'
+    rm_axpy<D>(R3, -1.0, QQ);                 // J
+  }
+  gemm<D, false, false, false>(R1, S2, S1);  // V Q'
+  {
+    RM<D> Ai;
+    rm_load<D>(Ai, ei + EL::A, D, D);
+    rm_axpy<D>(R1, -1.0, Ai);
+    rm_axpy<D>(R1, -2.0, R1);  // Z1 = A_i - V Q'
+  }
+  rm_symmetrise<D>(R3, S3);  // (ends synchronised; S3 free afterwards)
+  rm_store<D>(R3, out + EL::J, D, D);
+  lds_load_pad<D>(S3, ej + EL::A);  // S3 = A_j
+  team_sync();
+  gemm<D, false, false, false>(R2, S3, S2);  // A_j V
+  team_sync();
+  rm_stage<D>(R1, S1);  // S1 = Z1
+  team_sync();
+  gemm<D, false, false, false>(R3, S3, S1);  // A = A_j Z1
+  rm_store<D>(R3, out + EL::A, D, D);
+  rm_stage<D>(R2, S0);  // S0 = A_j V
+  // b = A_j (b_i + w) + b_j
+  if (tid < D) vw[tid] += vbi[tid];
+  team_sync();
+  matvec<D, false>(vz, S3, vw);
+  gemm<D, false, true, false>(R3, S0, S0);  // (A_j V)(A_j V)'
+  rm_add_load<D>(R3, ej + EL::C, D, D);
+  team_sync();
+  if (tid < D) out[EL::b + tid] = vz[tid] + ej[EL::b + tid];
+  rm_symmetrise<D>(R3, S1);
+  rm_store<D>(R3, out + EL::C, D, D);
+  if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
+}
+
+// ---------------------------------------------------------------------------
+// Filter, phase 2 down-sweep: the prefix entering node k of level l is known
+// (pre_src, as a filtering moment pair (m, P), or the identity for the left
+// spine).  Its children: left gets the same prefix, right gets
+// prefix (x) element(left child).  For a moment pair (m, P) with P = L L',
+// W = I + L' J L = R R', V = L R^{-T}:
+//   m' = A (m + V V'(eta - J m)) + b,   P' = (A V)(A V)' + C.
+// With the identity prefix the result is the left child's (b, C) (its A = 0).
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T) {
+  using C = Cfg<D>;
+  using EL = ElemLayout<D>;
+  using PL = PrefLayout<D>;
+  extern __shared__ double lds[];
+  double* S0 = lds;
+  double* S1 = S0 + C::MAT;
+  double* S2 = S1 + C::MAT;
+  double* S3 = S2 + C::MAT;
+  double* vm = S3 + C::MAT;
+  double* vc = vm + D;
+  double* vz = vc + D;
+  double* vw = vz + D;
+  double* scal = vw + D;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const double* pin = T.pre_src + (int64_t)k * PL::SIZE;
+  const bool ident = pin[PL::flag] != 0.0;
+  // left child: same prefix
+  double* pl = T.pre_dst + (int64_t)(2 * k) * PL::SIZE;
+  for (int e = tid; e < PL::SIZE; e += C::NT) pl[e] = pin[e];
+  if (2 * k + 1 >= T.n_dst) return;
+  double* pr = T.pre_dst + (int64_t)(2 * k + 1) * PL::SIZE;
+  const double* el = T.src + (int64_t)(2 * k) * EL::SIZE;  // left child's element
+  if (ident) {
+    for (int e = tid; e < D * D; e += C::NT) pr[PL::P + e] = el[EL::C + e];
+    if (tid < D) pr[PL::m + tid] = el[EL::b + tid];
+    if (tid == 0) pr[PL::flag] = 0.0;
+    return;
+  }
+  bool ok = true;
+  double ld;
+  lds_load_pad<D>(S0, pin + PL::P);
+  lds_load_pad<D>(S1, el + EL::J);
+  if (tid < D) vm[tid] = pin[PL::m + tid];
+  team_sync();
+  ok = chol_inv<D, false>(S0, S3, M.d, &ld, scal) && ok;
+  RM<D> R1, R2;
+  gemm<D, false, false, false>(R1, S1, S0);  // J L
+  rm_stage<D>(R1, S2);
+  team_sync();
+  gemm<D, true, false, false>(R2, S0, S2);  // L' J L
+  {
+    RM<D> I;
+    rm_eye<D>(I, D);
+    rm_axpy<D>(R2, 1.0, I);
+  }
+  team_sync();
+  rm_stage<D>(R2, S2);
+  team_sync();
+  ok = chol_inv<D, true>(S2, S3, D, &ld, scal) && ok;  // S3 = R^{-1}
+  gemm<D, false, true, false>(R1, S0, S3);            // V
+  team_sync();
+  rm_stage<D>(R1, S2);  // S2 = V
+  matvec<D, false>(vc, S1, vm);
+  team_sync();
+  if (tid < D) vc[tid] = el[EL::eta + tid] - vc[tid];  // eta - J m
+  team_sync();
+  matvec<D, true>(vz, S2, vc);
+  team_sync();
+  matvec<D, false>(vw, S2, vz);  // V V' (eta - J m)
+  lds_load_pad<D>(S3, el + EL::A);
+  team_sync();
+  if (tid < D) vw[tid] += vm[tid];
+  gemm<D, false, false, false>(R1, S3, S2);  // A V
+  team_sync();
+  matvec<D, false>(vz, S3, vw);
+  rm_stage<D>(R1, S0);
+  team_sync();
+  gemm<D, false, true, false>(R2, S0, S0);
+  rm_add_load<D>(R2, el + EL::C, D, D);
+  if (tid < D) pr[PL::m + tid] = vz[tid] + el[EL::b + tid];
+  if (tid == 0) pr[PL::flag] = 0.0;
+  rm_symmetrise<D>(R2, S1);
+  rm_store<D>(R2, pr + PL::P, D, D);
+  if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
+}
+
+// ---------------------------------------------------------------------------
+// Filter, phase 3: each block re-runs its steps from the prefix entering it
+// (sequential Kalman filter, App. A "Kalman filter"), with the predictive-
+// form likelihood term ell_t = log N(omega_t; m^p_t, P^p_t + Omega_t).
+// Writes m^f_t, P^f_t (when requested) and ell_t.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArgs P) {
+  using C = Cfg<D>;
+  using PL = PrefLayout<D>;
+  extern __shared__ double lds[];
+  double* sF = lds;
+  double* B1 = sF + C::MAT;
+  double* B2 = B1 + C::MAT;
+  double* B3 = B2 + C::MAT;
+  double* vm = B3 + C::MAT;
+  double* vmp = vm + D;
+  double* vw = vmp + D;
+  double* vr = vw + D;
+  double* red = vr + D;
+  double* scal = red + 8;
+  const int blk = blockIdx.x, tid = threadIdx.x, d = M.d;
+  const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
+  lds_load_mat<D>(sF, M.F, d);
+  RM<D> Pm, Pp, T, X;
+  if (s0 > 0) {
+    const double* pin = P.pre + (int64_t)blk * PL::SIZE;
+    rm_load<D>(Pm, pin + PL::P, D, D);
+    if (tid < D) vm[tid] = pin[PL::m + tid];
+  }
+  team_sync();
+  bool ok = true;
+  for (int t = s0; t < s1; ++t) {
+    if (t == 0) {
+      rm_load<D>(Pp, M.P0, d, d);
+      if (tid < D) vmp[tid] = (tid < d) ? M.m0[tid] : 0.0;
+    } else {
+      rm_stage<D>(Pm, B1);
+      team_sync();
+      gemm<D, false, false, false>(T, sF, B1);
+      team_sync();
+      rm_stage<D>(T, B1);
+      team_sync();
+      gemm<D, false, true, false>(Pp, B1, sF);
+      rm_add_load<D>(Pp, M.Q, d, d);
+      matvec<D, false>(vmp, sF, vm);
+      team_sync();
+      if (tid < d && M.b) vmp[tid] += M.b[tid];
+    }
+    build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
+    double logdet;
+    ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;
+    rm_stage<D>(Pp, B1);
+    if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
+    team_sync();
+    gemm<D, false, false, false>(X, B3, B1);
+    matvec<D, false>(vr, B3, vw);
+    team_sync();
+    rm_stage<D>(X, B2);
+    const double rr = team_sum<D>(tid < D ? vr[tid] * vr[tid] : 0.0, red);
+    gemm<D, true, false, false>(Pm, B2, B2);
+    rm_axpy<D>(Pm, -1.0, Pp);
+    rm_axpy<D>(Pm, -2.0, Pm);  // P^f = Pp - X'X
+    if (tid < D) {
+      double s = 0.0;
+      for (int j = 0; j < D; ++j) s = fma(B2[j * C::LD + tid], vr[j], s);
+      vm[tid] = vmp[tid] + s;  // m^f = m^p + X' r
+    }
+    if (tid == 0) P.ell[t] = -0.5 * (d * LOG2PI + logdet + rr);
+    team_sync();
+    rm_symmetrise<D>(Pm, B1);
+    if (P.mf) {
+      if (tid < d) P.mf[(int64_t)t * P.ldm + tid] = vm[tid];
+      rm_store<D>(Pm, P.Pf + (int64_t)t * P.ldm * P.ldm, P.ldm, d);
+    }
+  }
+  if (!ok && tid == 0) flag_status(P.status, P.fail_bit);
+}
+
+// ---------------------------------------------------------------------------
+// Sampler, element build (eq. backward, Alg. "Parallel RTS sampler"), one team
+// per t:  P^p = F P^f F' + Q = L_p L_p',  W = L_p^{-1} F P^f,
+//   E_t = W' L_p^{-1} = P^f F' (P^p)^{-1},   L_t = P^f - W'W,
+//   g_t = m^f - E_t (F m^f + bias),          U_t = g_t + chol(L_t) xi_t.
+// Terminal step: E = 0, U = m^f + chol(P^f) xi.
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_build(KModel M, SampArgs S) {
+  using C = Cfg<D>;
+  extern __shared__ double lds[];
+  double* sF = lds;
+  double* B1 = sF + C::MAT;
+  double* B2 = B1 + C::MAT;
+  double* B3 = B2 + C::MAT;
+  double* vm = B3 + C::MAT;
+  double* vmp = vm + D;
+  double* vg = vmp + D;
+  double* vxi = vg + D;
+  double* scal = vxi + D;
+  const int t = blockIdx.x, tid = threadIdx.x, d = M.d;
+  RM<D> Pf, R1, R2;
+  rm_load<D>(Pf, S.Pf + (int64_t)t * S.ldm * S.ldm, S.ldm, d);
+  if (tid < D) {
+    vm[tid] = (tid < d) ? S.mf[(int64_t)t * S.ldm + tid] : 0.0;
+    vxi[tid] = (tid < d) ? S.xi_x[(int64_t)t * d + tid] : 0.0;
+  }
+  bool ok = true;
+  double ld;
+  if (t == M.N - 1) {
+    rm_stage<D>(Pf, B2);
+    team_sync();
+    ok = chol_inv<D, false>(B2, B3, d, &ld, scal);
+    if (tid < D) {
+      double s = vm[tid];
+      for (int j = 0; j <= tid; ++j) s = fma(B2[tid * C::LD + j], vxi[j], s);
+      S.U[(int64_t)t * D + tid] = s;
+    }
+    RM<D> Z;
+    rm_zero<D>(Z);
+    rm_store<D>(Z, S.E + (int64_t)t * D * D, D, D);
+  } else {
+    lds_load_mat<D>(sF, M.F, d);
+    rm_stage<D>(Pf, B1);
+    team_sync();
+    gemm<D, false, false, false>(R1, sF, B1);  // F P^f
+    team_sync();
+    rm_stage<D>(R1, B1);  // B1 = F P^f
+    team_sync();
+    gemm<D, false, true, false>(R2, B1, sF);  // F P^f F'
+    rm_add_load<D>(R2, M.Q, d, d);
+    matvec<D, false>(vmp, sF, vm);
+    rm_stage<D>(R2, B2);
+    team_sync();
+    if (tid < d && M.b) vmp[tid] += M.b[tid];
+    ok = chol_inv<D, true>(B2, B3, d, &ld, scal) && ok;  // B3 = L_p^{-1}
+    gemm<D, false, false, false>(R1, B3, B1);           // W = L_p^{-1} F P^f
+    team_sync();
+    rm_stage<D>(R1, B2);  // B2 = W
+    team_sync();
+    gemm<D, true, false, false>(R2, B2, B3);  // E = W' L_p^{-1}
+    rm_store<D>(R2, S.E + (int64_t)t * D * D, D, D);
+    gemm<D, true, false, false>(R1, B2, B2);  // W'W
+    rm_axpy<D>(R1, -1.0, Pf);
+    rm_axpy<D>(R1, -2.0, R1);  // L_t = P^f - W'W
+    team_sync();
+    rm_stage<D>(R2, B1);  // B1 = E
+    team_sync();
+    matvec<D, false>(vg, B1, vmp);
+    team_sync();
+    if (tid < D) vg[tid] = vm[tid] - vg[tid];  // g = m^f - E m^p
+    rm_symmetrise<D>(R1, B3);
+    rm_stage<D>(R1, B2);
+    team_sync();
+    ok = chol_inv<D, false>(B2, B3, d, &ld, scal) && ok;
+    if (tid < D) {
+      double s = vg[tid];
+      for (int j = 0; j <= tid; ++j) s = fma(B2[tid * C::LD + j], vxi[j], s);
+      S.U[(int64_t)t * D + tid] = s;
+    }
+  }
+  if (!ok && tid == 0) flag_status(S.status, ST_FWD_NOT_PD);
+}
+
+// Sampler, block fold: suffix aggregate (E~, U~) of a block, folding from its
+// last step backwards: (E~, U~) <- (E_t E~, E_t U~ + U_t).
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_fold(KModel M, SampArgs S) {
+  using C = Cfg<D>;
+  extern __shared__ double lds[];
+  double* B1 = lds;
+  double* B2 = B1 + C::MAT;
+  double* vu = B2 + C::MAT;
+  double* vn = vu + D;
+  const int blk = blockIdx.x, tid = threadIdx.x;
+  const int s0 = blk * S.B, s1 = min(M.N, s0 + S.B);
+  RM<D> Et;
+  rm_load<D>(Et, S.E + (int64_t)(s1 - 1) * D * D, D, D);
+  if (tid < D) vu[tid] = S.U[(int64_t)(s1 - 1) * D + tid];
+  for (int t = s1 - 2; t >= s0; --t) {
+    lds_load_pad<D>(B1, S.E + (int64_t)t * D * D);
+    rm_stage<D>(Et, B2);
+    team_sync();
+    gemm<D, false, false, false>(Et, B1, B2);
+    matvec<D, false>(vn, B1, vu);
+    team_sync();
+    if (tid < D) vu[tid] = vn[tid] + S.U[(int64_t)t * D + tid];
+    team_sync();
+  }
+  double* out = S.agg + (int64_t)blk * SampLayout<D>::SIZE;
+  rm_store<D>(Et, out + SampLayout<D>::E, D, D);
+  if (tid < D) out[SampLayout<D>::U + tid] = vu[tid];
+}
+
+// Sampler tree up-sweep: node k = left (earlier) o right = (E_l E_r, E_l U_r + U_l).
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_up(KModel M, TreeArgs T) {
+  using C = Cfg<D>;
+  using SL = SampLayout<D>;
+  extern __shared__ double lds[];
+  double* B1 = lds;
+  double* B2 = B1 + C::MAT;
+  double* vu = B2 + C::MAT;
+  double* vn = vu + D;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const double* el = T.src + (int64_t)(2 * k) * SL::SIZE;
+  double* out = T.dst + (int64_t)k * SL::SIZE;
+  if (2 * k + 1 >= T.n_src) {
+    for (int e = tid; e < SL::SIZE; e += C::NT) out[e] = el[e];
+    return;
+  }
+  const double* er = el + SL::SIZE;
+  lds_load_pad<D>(B1, el + SL::E);
+  lds_load_pad<D>(B2, er + SL::E);
+  if (tid < D) vu[tid] = er[SL::U + tid];
+  team_sync();
+  RM<D> R;
+  gemm<D, false, false, false>(R, B1, B2);
+  matvec<D, false>(vn, B1, vu);
+  rm_store<D>(R, out + SL::E, D, D);
+  team_sync();
+  if (tid < D) out[SL::U + tid] = vn[tid] + el[SL::U + tid];
+}
+
+// Sampler tree down-sweep: xin[node] is x* at the step just after the node's
+// range.  Right child inherits it; left child gets E_r xin + U_r.
+template <int D>
+__global__ void __launch_bounds__(64) k_samp_down(KModel M, TreeArgs T) {
+  using SL = SampLayout<D>;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const double* xin = T.pre_src + (int64_t)k * D;
+  double* xl = T.pre_dst + (int64_t)(2 * k) * D;
+  const bool has_right = (2 * k + 1 < T.n_dst);
+  if (!has_right) {
+    if (tid < D) xl[tid] = xin[tid];
+    return;
+  }
+  double* xr = T.pre_dst + (int64_t)(2 * k + 1) * D;
+  const double* er = T.src + (int64_t)(2 * k + 1) * SL::SIZE;
+  if (tid < D) {
+    double s = er[SL::U + tid];
+    for (int j = 0; j < D; ++j) s = fma(er[SL::E + tid * D + j], xin[j], s);
+    xr[tid] = xin[tid];
+    xl[tid] = s;
+  }
+}
+
+// Sampler, block final: x*_t = E_t x*_{t+1} + U_t inside each block.
+template <int D>
+__global__ void __launch_bounds__(64) k_samp_final(KModel M, SampArgs S) {
+  __shared__ double vx[64];
+  __shared__ double vn[64];
+  const int blk = blockIdx.x, tid = threadIdx.x, d = M.d;
+  const int s0 = blk * S.B, s1 = min(M.N, s0 + S.B);
+  if (tid < D) vx[tid] = S.xin[(int64_t)blk * D + tid];
+  __syncthreads();
+  for (int t = s1 - 1; t >= s0; --t) {
+    const double* Et = S.E + (int64_t)t * D * D;
+    if (tid < D) {
+      double s = S.U[(int64_t)t * D + tid];
+      for (int j = 0; j < D; ++j) s = fma(Et[tid * D + j], vx[j], s);
+      vn[tid] = s;
+    }
+    __syncthreads();
+    if (tid < D) vx[tid] = vn[tid];
+    if (tid < d) S.xs[(int64_t)t * d + tid] = vn[tid];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// MH decision: log r = terms + [log h(x*) - log h(x)] + log Z(x) - log Z(x*);
+// accept iff log U < log r and no status bit is set.  One team of 256.
+// ---------------------------------------------------------------------------
+__device__ double block_sum(const double* a, int n, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) s += a[i];
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  double tot = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += red[i];
+  __syncthreads();
+  return tot;
+}
+
+__global__ void __launch_bounds__(256) k_mh_finalize(KModel M, StepArgs A, FinalArgs F) {
+  __shared__ double red[4];
+  const double lzf = block_sum(A.ell, M.N, red);
+  const double lzr = block_sum(A.ell2, M.N, red);
+  const double terms = block_sum(A.part_terms, F.n_part_rev, red);
+  const double lhx = block_sum(A.part_lh_x, F.n_part_fwd, red);
+  const double lhs = block_sum(A.part_lh_xs, F.n_part_rev, red);
+  if (threadIdx.x == 0) {
+    int st = *A.status;
+    // a failed forward proposal makes x* (and everything computed from it)
+    // meaningless: report only the forward failure
+    if (st & ST_FWD_NOT_PD) st = ST_FWD_NOT_PD;
+    double lr = terms + (lhs - lhx) + (lzf - lzr);
+    if (st == 0 && !isfinite(lr)) st |= ST_NONFINITE;
+    if (st != 0) lr = -INFINITY;
+    const int acc = (st == 0) && (log(F.unif[0]) < lr);
+    *A.accept_flag = acc;
+    *A.status = st;
+    if (F.log_ratio) *F.log_ratio = lr;
+    if (F.accepted) *F.accepted = acc;
+    if (F.logZ_fwd) *F.logZ_fwd = lzf;
+    if (F.logZ_rev) *F.logZ_rev = lzr;
+    if (F.status_out) *F.status_out = st;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mh_select(int64_t n, const double* __restrict__ x,
+                                                   const double* __restrict__ xs,
+                                                   double* __restrict__ x_out,
+                                                   const int* __restrict__ accept_flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x_out[i] = (*accept_flag) ? xs[i] : x[i];
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers (templated on D), used by akf_capi.cpp
+// ---------------------------------------------------------------------------
+template <int D>
+size_t lds_bytes_filter() {
+  return (size_t)(4 * Cfg<D>::MAT + 6 * D + 16) * sizeof(double);
+}
+template <int D>
+size_t lds_bytes_samp2() {
+  return (size_t)(2 * Cfg<D>::MAT + 2 * D) * sizeof(double);
+}
+
+template <int D>
+hipError_t launch_filter(const KModel& M, FilterArgs P, TreeArgs* lv_up, TreeArgs* lv_down,
+                         int n_levels, hipStream_t st) {
+  const size_t lds = lds_bytes_filter<D>();
+  const int nb = (M.N + P.B - 1) / P.B;
+  timing_mark(FAM_FILTER_FOLD, 1, st);
+  hipLaunchKernelGGL(k_filter_fold<D>, dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  timing_mark(FAM_FILTER_FOLD, 0, st);
+  for (int l = 0; l < n_levels; ++l) {
+    timing_mark(FAM_FILTER_UP, 1, st);
+    hipLaunchKernelGGL(k_filter_up<D>, dim3(lv_up[l].n_dst), dim3(Cfg<D>::NT), lds, st, M,
+                       lv_up[l]);
+    timing_mark(FAM_FILTER_UP, 0, st);
+  }
+  for (int l = n_levels - 1; l >= 0; --l) {
+    timing_mark(FAM_FILTER_DOWN, 1, st);
+    hipLaunchKernelGGL(k_filter_down<D>, dim3(lv_down[l].n_src), dim3(Cfg<D>::NT), lds, st, M,
+                       lv_down[l]);
+    timing_mark(FAM_FILTER_DOWN, 0, st);
+  }
+  timing_mark(FAM_FILTER_FINAL, 1, st);
+  hipLaunchKernelGGL(k_filter_final<D>, dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  timing_mark(FAM_FILTER_FINAL, 0, st);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_sampler(const KModel& M, SampArgs S, TreeArgs* lv_up, TreeArgs* lv_down,
+                          int n_levels, hipStream_t st) {
+  const int nb = (M.N + S.B - 1) / S.B;
+  timing_mark(FAM_SAMP_BUILD, 1, st);
+  hipLaunchKernelGGL(k_samp_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_filter<D>(), st, M, S);
+  timing_mark(FAM_SAMP_BUILD, 0, st);
+  timing_mark(FAM_SAMP_FOLD, 1, st);
+  hipLaunchKernelGGL(k_samp_fold<D>, dim3(nb), dim3(Cfg<D>::NT), lds_bytes_samp2<D>(), st, M, S);
+  timing_mark(FAM_SAMP_FOLD, 0, st);
+  for (int l = 0; l < n_levels; ++l) {
+    timing_mark(FAM_SAMP_UP, 1, st);
+    hipLaunchKernelGGL(k_samp_up<D>, dim3(lv_up[l].n_dst), dim3(Cfg<D>::NT), lds_bytes_samp2<D>(),
+                       st, M, lv_up[l]);
+    timing_mark(FAM_SAMP_UP, 0, st);
+  }
+  for (int l = n_levels - 1; l >= 0; --l) {
+    timing_mark(FAM_SAMP_DOWN, 1, st);
+    hipLaunchKernelGGL(k_samp_down<D>, dim3(lv_down[l].n_src), dim3(64), 0, st, M, lv_down[l]);
+    timing_mark(FAM_SAMP_DOWN, 0, st);
+  }
+  timing_mark(FAM_SAMP_FINAL, 1, st);
+  hipLaunchKernelGGL(k_samp_final<D>, dim3(nb), dim3(64), 0, st, M, S);
+  timing_mark(FAM_SAMP_FINAL, 0, st);
+  return hipGetLastError();
+}
+
+template <int D>
+hipError_t set_lds_limits() {
+  hipError_t e;
+  const int lf = (int)lds_bytes_filter<D>();
+  if ((e = hipFuncSetAttribute((const void*)k_filter_fold<D>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_filter_up<D>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_filter_down<D>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_filter_final<D>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_samp_build<D>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
+hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, TreeArgs* down,
+                             int nl, hipStream_t st) {
+  switch (D) {
+    case 16: return launch_filter<16>(M, P, up, down, nl, st);
+    case 32: return launch_filter<32>(M, P, up, down, nl, st);
+    case 64: return launch_filter<64>(M, P, up, down, nl, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sampler_any(int D, const KModel& M, SampArgs S, TreeArgs* up, TreeArgs* down,
+                              int nl, hipStream_t st) {
+  switch (D) {
+    case 16: return launch_sampler<16>(M, S, up, down, nl, st);
+    case 32: return launch_sampler<32>(M, S, up, down, nl, st);
+    case 64: return launch_sampler<64>(M, S, up, down, nl, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t set_lds_limits_all() {
+  hipError_t e;
+  if ((e = set_lds_limits<16>()) != hipSuccess) return e;
+  if ((e = set_lds_limits<32>()) != hipSuccess) return e;
+  return set_lds_limits<64>();
+}
+
+hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStream_t st) {
+  if (M.emit == EMIT_GAUSSIAN) {
+    const int nblk = (M.N + 63) / 64;
+    *n_part = nblk;
+    if (!rev) hipLaunchKernelGGL(k_gauss_prep, dim3(1), dim3(64), 0, st, M, A);
+    hipLaunchKernelGGL(k_lin_gauss, dim3(nblk), dim3(64), 0, st, M, A, rev);
+  } else {
+    const int64_t n = (int64_t)M.N * M.d;
+    const int nblk = (int)((n + 255) / 256);
+    *n_part = nblk;
+    if (!rev)
+      hipLaunchKernelGGL(k_lin_fwd_diag, dim3(nblk), dim3(256), 0, st, M, A);
+    else
+      hipLaunchKernelGGL(k_lin_rev_diag, dim3(nblk), dim3(256), 0, st, M, A);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_step_init(int* status, double* root_flag, double* root_xin, int D,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_step_init, dim3(1), dim3(64), 0, st, status, root_flag, root_xin, D);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const KModel& M, StepArgs A, FinalArgs F, const double* x,
+                           double* x_out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mh_finalize, dim3(1), dim3(256), 0, st, M, A, F);
+  const int64_t n = (int64_t)M.N * M.d;
+  hipLaunchKernelGGL(k_mh_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, A.xs,
+                     x_out, A.accept_flag);
+  return hipGetLastError();
+}
+
+}  // namespace akf

@@ -1,0 +1,237 @@
+"""Python front end of the auxiliary Kalman MCMC library.
+
+Torch supplies device memory and the stream; the arithmetic happens in the HIP
+kernels behind include/akf.h.  All tensors are float64 on a ROCm device.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T = 0, 1, 2
+ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
+
+
+def _dev(device=None) -> torch.device:
+    if device is None:
+        device = torch.device("cuda", torch.cuda.current_device())
+    device = torch.device(device)
+    if device.type != "cuda":
+        raise _lib.AkfError("the auxiliary Kalman kernels need a ROCm device tensor")
+    return device
+
+
+def _t(a, device, dtype=torch.float64) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=device)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_f64(name, t: torch.Tensor, shape):
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.device.type != "cuda":
+        raise _lib.AkfError(f"{name} must be a contiguous float64 ROCm tensor")
+    if tuple(t.shape) != tuple(shape):
+        raise _lib.AkfError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+@dataclass
+class DeviceModel:
+    """Gaussian-dynamics state-space model resident on the device."""
+    N: int
+    m0: torch.Tensor
+    P0: torch.Tensor
+    F: torch.Tensor
+    Q: torch.Tensor
+    emit: int
+    b: Optional[torch.Tensor] = None
+    H: Optional[torch.Tensor] = None
+    R: Optional[torch.Tensor] = None
+    site: Optional[torch.Tensor] = None
+    nu: float = 0.0
+    scale: float = 0.0
+
+    @classmethod
+    def from_arrays(cls, N, m0, P0, F, Q, emit, b=None, H=None, R=None, site=None, nu=0.0,
+                    scale=0.0, device=None):
+        dev = _dev(device)
+        return cls(N=int(N), m0=_t(m0, dev), P0=_t(P0, dev), F=_t(F, dev), Q=_t(Q, dev),
+                   emit=int(emit), b=_t(b, dev), H=_t(H, dev), R=_t(R, dev),
+                   site=_t(site, dev, torch.int32), nu=float(nu), scale=float(scale))
+
+    @classmethod
+    def from_workload(cls, w, device=None):
+        return cls.from_arrays(w.N, w.m0, w.P0, w.F, w.Q, w.emit, b=w.b, H=w.H, R=w.R,
+                               site=w.site, nu=w.nu, scale=w.scale, device=device)
+
+    @property
+    def dx(self) -> int:
+        return int(self.m0.shape[0])
+
+    @property
+    def dy(self) -> int:
+        if self.emit == EMIT_GAUSSIAN:
+            return int(self.H.shape[0]) if self.H is not None else 0
+        return int(self.site.shape[0]) if self.site is not None else 0
+
+    @property
+    def device(self) -> torch.device:
+        return self.m0.device
+
+    def cstruct(self) -> _lib.AkfModel:
+        s = _lib.AkfModel()
+        s.N, s.dx, s.dy = self.N, self.dx, self.dy
+        s.m0, s.P0, s.F, s.Q = (self.m0.data_ptr(), self.P0.data_ptr(), self.F.data_ptr(),
+                                self.Q.data_ptr())
+        s.b = self.b.data_ptr() if self.b is not None else None
+        s.emit = self.emit
+        s.H = self.H.data_ptr() if self.H is not None else None
+        s.R = self.R.data_ptr() if self.R is not None else None
+        s.site = self.site.data_ptr() if self.site is not None else None
+        s.nu, s.scale = self.nu, self.scale
+        return s
+
+
+class Workspace:
+    """Caller-owned scratch buffer reused across calls (grown on demand)."""
+
+    def __init__(self, device=None):
+        self.device = _dev(device)
+        self.buf: Optional[torch.Tensor] = None
+
+    def get(self, nbytes: int) -> torch.Tensor:
+        if nbytes <= 0:
+            raise _lib.AkfError("unsupported problem size (workspace query returned 0)")
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+    def ptr_bytes(self, nbytes: int):
+        b = self.get(nbytes)
+        p = b.data_ptr()
+        off = (-p) % 256
+        return C.c_void_p(p + off), C.c_size_t(b.numel() - off)
+
+
+_default_ws = {}
+
+
+def _ws_for(device) -> Workspace:
+    key = (device.type, device.index)
+    if key not in _default_ws:
+        _default_ws[key] = Workspace(device)
+    return _default_ws[key]
+
+
+def mh_step(model: DeviceModel, y, x, delta: float, order: int, xi, unif, x_out=None,
+            block: int = 0, ws: Optional[Workspace] = None) -> dict:
+    """One auxiliary Kalman MH step.  xi [2,N,dx], unif [1] (device tensors).
+    Returns device tensors: x_out, log_ratio, accepted, logZ_fwd, logZ_rev, status."""
+    lib = _lib.load()
+    dev = model.device
+    N, dx = model.N, model.dx
+    _check_f64("y", y, (N, model.dy))
+    _check_f64("x", x, (N, dx))
+    _check_f64("xi", xi, (2, N, dx))
+    _check_f64("unif", unif, (1,))
+    if x_out is None:
+        x_out = torch.empty_like(x)
+    lr = torch.empty(1, dtype=torch.float64, device=dev)
+    lzf = torch.empty(1, dtype=torch.float64, device=dev)
+    lzr = torch.empty(1, dtype=torch.float64, device=dev)
+    acc = torch.empty(1, dtype=torch.int32, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    ms = model.cstruct()
+    need = lib.akf_mh_workspace_bytes(C.byref(ms), order, block)
+    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+    rc = lib.akf_mh_step(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), _ptr(xi),
+                         _ptr(unif), _ptr(x_out), _ptr(lr), _ptr(acc), _ptr(lzf), _ptr(lzr),
+                         _ptr(st), wsp, wsb, int(block), _stream(dev))
+    _lib.check(rc, "akf_mh_step")
+    return dict(x_out=x_out, log_ratio=lr, accepted=acc, logZ_fwd=lzf, logZ_rev=lzr, status=st)
+
+
+def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: int = 0,
+           ws: Optional[Workspace] = None, outputs: bool = True) -> dict:
+    """n_steps MH steps, x updated in place.  xi [n_steps,2,N,dx], unif [n_steps]."""
+    lib = _lib.load()
+    dev = model.device
+    N, dx = model.N, model.dx
+    n = int(xi.shape[0])
+    _check_f64("y", y, (N, model.dy))
+    _check_f64("x", x, (N, dx))
+    _check_f64("xi", xi, (n, 2, N, dx))
+    _check_f64("unif", unif, (n,))
+    out = {}
+    if outputs:
+        out = dict(log_ratio=torch.empty(n, dtype=torch.float64, device=dev),
+                   accepted=torch.empty(n, dtype=torch.int32, device=dev),
+                   logZ_fwd=torch.empty(n, dtype=torch.float64, device=dev),
+                   logZ_rev=torch.empty(n, dtype=torch.float64, device=dev),
+                   status=torch.empty(n, dtype=torch.int32, device=dev))
+    ms = model.cstruct()
+    need = lib.akf_mh_workspace_bytes(C.byref(ms), order, block)
+    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+    rc = lib.akf_mh_run(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), n, _ptr(xi),
+                        _ptr(unif), _ptr(out.get("log_ratio")), _ptr(out.get("accepted")),
+                        _ptr(out.get("logZ_fwd")), _ptr(out.get("logZ_rev")),
+                        _ptr(out.get("status")), wsp, wsb, int(block), _stream(dev))
+    _lib.check(rc, "akf_mh_run")
+    out["x"] = x
+    return out
+
+
+def aux_filter(model: DeviceModel, omega, Omega, block: int = 0, moments: bool = True,
+               ws: Optional[Workspace] = None):
+    """Parallel-in-time filter of x_t = F x_{t-1} + b + N(0,Q), omega_t = x_t + N(0, diag Omega_t).
+    Returns (mf [N,dx] | None, Pf [N,dx,dx] | None, ell [N], status [1])."""
+    lib = _lib.load()
+    dev = model.device
+    N, dx = model.N, model.dx
+    _check_f64("omega", omega, (N, dx))
+    _check_f64("Omega", Omega, (N, dx))
+    mf = torch.empty((N, dx), dtype=torch.float64, device=dev) if moments else None
+    Pf = torch.empty((N, dx, dx), dtype=torch.float64, device=dev) if moments else None
+    ell = torch.empty(N, dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    ms = model.cstruct()
+    need = lib.akf_filter_workspace_bytes(C.byref(ms), block)
+    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+    rc = lib.akf_aux_filter(C.byref(ms), _ptr(omega), _ptr(Omega), _ptr(mf), _ptr(Pf), _ptr(ell),
+                            _ptr(st), wsp, wsb, int(block), _stream(dev))
+    _lib.check(rc, "akf_aux_filter")
+    return mf, Pf, ell, st
+
+
+def rts_sample(model: DeviceModel, mf, Pf, xi, block: int = 0, ws: Optional[Workspace] = None):
+    """Pathwise RTS sample from filtering moments.  Returns (x [N,dx], status [1])."""
+    lib = _lib.load()
+    dev = model.device
+    N, dx = model.N, model.dx
+    _check_f64("mf", mf, (N, dx))
+    _check_f64("Pf", Pf, (N, dx, dx))
+    _check_f64("xi", xi, (N, dx))
+    x = torch.empty((N, dx), dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    ms = model.cstruct()
+    need = lib.akf_sampler_workspace_bytes(C.byref(ms), block)
+    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+    rc = lib.akf_rts_sample(C.byref(ms), _ptr(mf), _ptr(Pf), _ptr(xi), _ptr(x), _ptr(st), wsp,
+                            wsb, int(block), _stream(dev))
+    _lib.check(rc, "akf_rts_sample")
+    return x, st

@@ -1,0 +1,94 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/akf.h declares, sizes workspaces, and rejects bad
+arguments before touching device memory."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2303_00301_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "akf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(akf_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared_functions()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), (set(names) ^ set(_lib.SIGNATURES))
+
+
+def _fake_model(N=16, dx=4, dy=4, emit=1):
+    m = _lib.AkfModel()
+    m.N, m.dx, m.dy = N, dx, dy
+    fake = 0x1000
+    m.m0 = m.P0 = m.F = m.Q = fake
+    m.b = None
+    m.emit = emit
+    m.H = m.R = fake
+    m.site = fake
+    m.nu, m.scale = 3.0, 0.5
+    return m
+
+
+def test_workspace_sizes_grow_with_problem():
+    lib = _lib.load()
+    small = lib.akf_mh_workspace_bytes(C.byref(_fake_model(N=64, dx=8)), 2, 0)
+    big = lib.akf_mh_workspace_bytes(C.byref(_fake_model(N=4096, dx=64)), 2, 0)
+    assert 0 < small < big
+    assert lib.akf_mh_workspace_bytes(C.byref(_fake_model(dx=65)), 2, 0) == 0
+    assert lib.akf_mh_workspace_bytes(C.byref(_fake_model()), 3, 0) == 0
+    assert lib.akf_filter_workspace_bytes(C.byref(_fake_model(N=100, dx=3)), 0) > 0
+    assert lib.akf_sampler_workspace_bytes(C.byref(_fake_model(N=100, dx=3)), 7) > 0
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("N", 0, 2), ("dx", 0, 2), ("dx", 65, 2), ("dy", 0, 2), ("emit", 9, 1),
+])
+def test_mh_step_rejects_bad_model(field, value, code):
+    lib = _lib.load()
+    m = _fake_model()
+    setattr(m, field, value)
+    p = C.c_void_p(0x2000)
+    rc = lib.akf_mh_step(C.byref(m), p, p, 0.5, 2, p, p, p, None, None, None, None, None,
+                         C.c_void_p(0x10000), 1 << 30, 0, None)
+    assert rc == code
+    assert lib.akf_last_error()
+
+
+def test_mh_step_rejects_bad_arguments():
+    lib = _lib.load()
+    m = _fake_model()
+    p = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x10000)
+    call = lambda **kw: lib.akf_mh_step(
+        C.byref(m), kw.get("y", p), p, kw.get("delta", 0.5), kw.get("order", 2), p, p, p, None,
+        None, None, None, None, kw.get("ws", ws), kw.get("ws_bytes", 1 << 30), kw.get("block", 0),
+        None)
+    assert call(delta=0.0) == 1
+    assert call(delta=float("nan")) == 1
+    assert call(order=3) == 1
+    assert call(y=None) == 1
+    assert call(block=-1) == 1
+    assert call(ws=C.c_void_p(0x10001)) == 3   # misaligned
+    assert call(ws_bytes=100) == 3            # too small
+    assert b"workspace" in lib.akf_last_error()
+
+
+def test_student_t_needs_positive_parameters():
+    lib = _lib.load()
+    m = _fake_model(emit=2)
+    m.nu = 0.0
+    p = C.c_void_p(0x2000)
+    rc = lib.akf_mh_step(C.byref(m), p, p, 0.5, 2, p, p, p, None, None, None, None, None,
+                         C.c_void_p(0x10000), 1 << 30, 0, None)
+    assert rc == 1
