@@ -133,9 +133,10 @@ def periodic_grid_F_Q(d: int = 64):
     return F, Q
 
 
-# Step size for the latent-field workload, frozen after a Robbins-Monro warm-up
-# toward 30% acceptance (see paper_2303_00301_amd.mcmc.tune_delta).
-LATENT_FIELD_DELTA = 0.03
+# Step size for the latent-field workload, frozen after a 400-step Robbins-Monro warm-up
+# toward 30% acceptance (paper_2303_00301_amd.mcmc.tune_delta, seed 7); 300 frozen steps
+# then accepted 30.0%.
+LATENT_FIELD_DELTA = 0.057
 
 
 def latent_field(N: int = 4096, d: int = 64, n_sites: int = 32, nu: float = 3.0,
