@@ -147,6 +147,109 @@ akf_status akf_rts_sample(const akf_model* model, const double* mf, const double
                           size_t ws_bytes, int32_t block, void* stream);
 
 /*
+ * RTS smoother (eq. init-dnc, eq. EgL_comb): from the filtering moments
+ * mf [N,dx], Pf [N,dx,dx] of the model's dynamics, the smoothing moments
+ * ms [N,dx], Ps [N,dx,dx] by a parallel suffix scan of (E, g, L) elements.
+ */
+size_t akf_smoother_workspace_bytes(const akf_model* model, int32_t block);
+akf_status akf_smoother(const akf_model* model, const double* mf, const double* Pf, double* ms,
+                        double* Ps, int32_t* status, void* ws, size_t ws_bytes, int32_t block,
+                        void* stream);
+
+/*
+ * Linear-Gaussian state-space model with parameters theta = (F, log diag Q,
+ * H, log diag R) (App. A, eq. lgssm-app with b = c = 0):
+ *   x_0 ~ N(m0, P0), x_t = F x_{t-1} + N(0, diag exp(logq)),
+ *   y_t = H x_t + N(0, diag exp(logr)).
+ * m0 [dx], P0 [dx,dx], F [dx,dx], logq [dx], H [dy,dx], logr [dy], y [N,dy];
+ * 1 <= dx, dy <= 32.
+ */
+typedef struct akf_lgssm {
+  int32_t N, dx, dy;
+  const double *m0, *P0;
+  const double *F, *logq;
+  const double *H, *logr;
+  const double* y;
+} akf_lgssm;
+
+/*
+ * log p(y_{0:T} | theta) by the parallel filter (predictive form of eq.
+ * marginal-likelihood): ll [1] device double, ell [N] per-step terms (may be
+ * NULL).  The filtering moments stay in `ws` as the checkpoint of the
+ * adjoint; akf_lgssm_loglik_grad must be called with the same model, block
+ * and workspace, after this call and before any other use of the workspace.
+ */
+size_t akf_lgssm_workspace_bytes(const akf_lgssm* m, int32_t block);
+akf_status akf_lgssm_loglik(const akf_lgssm* m, double* ll, double* ell, int32_t* status, void* ws,
+                            size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * Reverse-mode adjoint of akf_lgssm_loglik: ll_bar [1] (device, NULL = 1)
+ * times d log p / d theta, written to dF [dx,dx], dlogq [dx], dH [dy,dx],
+ * dlogr [dy].  Two suffix scans over time (mean and covariance adjoints) from
+ * the checkpointed filtering moments, then per-step gradient terms.
+ */
+akf_status akf_lgssm_loglik_grad(const akf_lgssm* m, const double* ll_bar, double* dF,
+                                 double* dlogq, double* dH, double* dlogr, int32_t* status,
+                                 void* ws, size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * Batched chains: many independent chains (each its own model, length N and
+ * dimension dx) advanced together.  All chains are grouped by team size
+ * (dx <= 16, <= 32, <= 64); every phase of a step is one persistent launch per
+ * group that walks a table of (chain, block / tree node / time step) work
+ * items, so the whole batch needs a few dozen launches per step instead of a
+ * few dozen per chain.  One step is captured in a hipGraph and replayed; a
+ * device step counter selects each step's normals and outputs.  Emissions:
+ * Poisson log-link and Student-t.
+ *
+ * Per chain (device pointers): model, y [N,dy], x [N,dx] (updated in place),
+ * xi [n_steps,2,N,dx], unif [n_steps], delta, order, and optional per-step
+ * outputs [n_steps] (NULL = not written).
+ */
+typedef struct akf_chain {
+  akf_model model;
+  const double* y;
+  double* x;
+  const double* xi;
+  const double* unif;
+  double delta;
+  int32_t order;
+  double* log_ratio;
+  int32_t* accepted;
+  double* logZ_fwd;
+  double* logZ_rev;
+  int32_t* status;
+} akf_chain;
+
+typedef struct akf_batch_plan akf_batch_plan;
+
+/*
+ * Builds a plan (library-owned; the only object this library allocates):
+ * validates the chains (host array, copied), allocates the device descriptors,
+ * work tables and per-chain workspaces, and picks the scan block per group.
+ * block = 0 autotunes: each candidate block size is timed on one step of the
+ * real batch (on scratch copies of x; no state changes), and the choice is
+ * appended to the text cache `tune_cache` (one JSON object per line; NULL =
+ * no cache) and reused when the same group shape is seen again.
+ */
+akf_status akf_batch_plan_create(akf_batch_plan** plan, int32_t n_chains, const akf_chain* chains,
+                                 int32_t n_steps, int32_t block, const char* tune_cache,
+                                 void* stream);
+
+/* Runs n_steps steps on every chain; use_graph = 1 captures one step in a
+ * hipGraph on `stream` (which must not be the legacy default stream) at the
+ * first call and replays it, use_graph = 0 launches eagerly. */
+akf_status akf_batch_mh_run(akf_batch_plan* plan, int32_t use_graph, void* stream);
+
+/* Plan diagnostics: number of groups and, per group (up to max_classes), its
+ * team size D, scan block and chain count; total device bytes. */
+akf_status akf_batch_plan_info(const akf_batch_plan* plan, int32_t max_classes,
+                               int32_t* n_classes, int32_t* D, int32_t* block,
+                               int32_t* n_chains_in_class, size_t* device_bytes);
+void akf_batch_plan_destroy(akf_batch_plan* plan);
+
+/*
  * Kernel timing, for diagnostics and benchmarks.  While enabled for `family`
  * (0 filter fold, 1 filter up-sweep, 2 filter down-sweep, 3 filter final,
  * 4 sampler element build, 5 sampler fold, 6 sampler up-sweep, 7 sampler

@@ -30,6 +30,26 @@ class AkfModel(C.Structure):
     ]
 
 
+class AkfLgssm(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32), ("dx", C.c_int32), ("dy", C.c_int32),
+        ("m0", C.c_void_p), ("P0", C.c_void_p),
+        ("F", C.c_void_p), ("logq", C.c_void_p),
+        ("H", C.c_void_p), ("logr", C.c_void_p),
+        ("y", C.c_void_p),
+    ]
+
+
+class AkfChain(C.Structure):
+    _fields_ = [
+        ("model", AkfModel),
+        ("y", C.c_void_p), ("x", C.c_void_p), ("xi", C.c_void_p), ("unif", C.c_void_p),
+        ("delta", C.c_double), ("order", C.c_int32),
+        ("log_ratio", C.c_void_p), ("accepted", C.c_void_p), ("logZ_fwd", C.c_void_p),
+        ("logZ_rev", C.c_void_p), ("status", C.c_void_p),
+    ]
+
+
 # name -> (restype, argtypes); the exported symbols of include/akf.h
 _vp, _sz, _i32, _d = C.c_void_p, C.c_size_t, C.c_int32, C.c_double
 _MP = C.POINTER(AkfModel)
@@ -44,6 +64,19 @@ SIGNATURES = {
     "akf_aux_filter": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
     "akf_sampler_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_rts_sample": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "akf_smoother_workspace_bytes": (_sz, [_MP, _i32]),
+    "akf_smoother": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "akf_lgssm_workspace_bytes": (_sz, [C.c_void_p, _i32]),
+    "akf_lgssm_loglik": (C.c_int, [C.c_void_p, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "akf_lgssm_loglik_grad": (C.c_int, [C.c_void_p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
+                                        _vp]),
+    "akf_batch_plan_create": (C.c_int, [C.POINTER(C.c_void_p), _i32, C.POINTER(AkfChain), _i32,
+                                        _i32, C.c_char_p, _vp]),
+    "akf_batch_mh_run": (C.c_int, [_vp, _i32, _vp]),
+    "akf_batch_plan_info": (C.c_int, [_vp, _i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_size_t)]),
+    "akf_batch_plan_destroy": (None, [_vp]),
     "akf_timing_enable": (C.c_int, [_i32, _i32]),
     "akf_timing_collect": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
 }

@@ -9,258 +9,11 @@
 
 #include "../../include/akf.h"
 #include "akf_internal.h"
+#include "akf_layout.h"
 
 using namespace akf;
 
 namespace {
-
-thread_local char g_err[512] = "";
-
-akf_status fail(akf_status s, const char* fmt, ...) {
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(g_err, sizeof g_err, fmt, ap);
-  va_end(ap);
-  return s;
-}
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-int pick_D(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : (d <= 64 ? 64 : 0)); }
-
-// Default scan block: enough blocks to give every CU (256) its resident teams
-// (LDS-limited: 1 team of 4 waves at D = 64, several single-wave teams below),
-// and at least 4 steps per block so that small problems do not pay for a deep
-// tree of tiny launches.
-int auto_block(int N, int D) {
-  const int teams_per_cu = D == 64 ? 1 : (D == 32 ? 4 : 8);
-  const int target = 256 * teams_per_cu;
-  int B = (N + target - 1) / target;
-  if (B < 4) B = 4;
-  if (B > N) B = N;
-  return B;
-}
-
-constexpr int kMaxLevels = 32;
-
-struct Layout {
-  int N = 0, d = 0, dy = 0, D = 0, B = 0, nb = 0, L = 0;
-  int n_lvl[kMaxLevels + 1] = {0};
-  int n_part = 0;
-  // byte offsets
-  size_t u = 0, om = 0, Om = 0, om2 = 0, Om2 = 0, xs = 0, ell = 0, ell2 = 0;
-  size_t plhx = 0, plhxs = 0, pterms = 0;
-  size_t gG = 0, gRinv = 0, gOmd = 0, gOmdinv = 0, gscal = 0;
-  size_t elem[kMaxLevels + 1] = {0};
-  size_t pre[kMaxLevels + 1] = {0};
-  size_t mf = 0, Pf = 0, E = 0, U = 0;
-  size_t sagg[kMaxLevels + 1] = {0};
-  size_t xin[kMaxLevels + 1] = {0};
-  size_t status = 0, accept = 0;
-  size_t total = 0;
-};
-
-enum LayoutKind { LAYOUT_STEP = 0, LAYOUT_FILTER = 1, LAYOUT_SAMPLER = 2 };
-
-void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
-  Lo.N = N;
-  Lo.d = d;
-  Lo.dy = dy;
-  Lo.D = pick_D(d);
-  const int D = Lo.D;
-  Lo.B = block > 0 ? (block > N ? N : block) : auto_block(N, D);
-  Lo.nb = (N + Lo.B - 1) / Lo.B;
-  Lo.n_lvl[0] = Lo.nb;
-  Lo.L = 0;
-  while (Lo.n_lvl[Lo.L] > 1 && Lo.L < kMaxLevels) {
-    Lo.n_lvl[Lo.L + 1] = (Lo.n_lvl[Lo.L] + 1) / 2;
-    ++Lo.L;
-  }
-  const size_t dbl = sizeof(double);
-  const size_t vn = (size_t)N * d * dbl;
-  const size_t ES = (size_t)(3 * D * D + 2 * D) * dbl;
-  const size_t PS = (size_t)(D * D + D + 2) * dbl;
-  const size_t SS = (size_t)(D * D + D) * dbl;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t o = off;
-    off += align_up(bytes == 0 ? 1 : bytes);
-    return o;
-  };
-  const int nparts_diag = (int)(((int64_t)N * d + 255) / 256);
-  const int nparts_gauss = (N + 63) / 64;
-  Lo.n_part = nparts_diag > nparts_gauss ? nparts_diag : nparts_gauss;
-  if (kind == LAYOUT_STEP) {
-    Lo.u = take(vn);
-    Lo.om = take(vn);
-    Lo.Om = take(vn);
-    Lo.om2 = take(vn);
-    Lo.Om2 = take(vn);
-    Lo.xs = take(vn);
-    Lo.ell2 = take((size_t)N * dbl);
-    Lo.plhx = take((size_t)Lo.n_part * dbl);
-    Lo.plhxs = take((size_t)Lo.n_part * dbl);
-    Lo.pterms = take((size_t)Lo.n_part * dbl);
-    Lo.gG = take((size_t)d * (dy > 0 ? dy : 1) * dbl);
-    Lo.gRinv = take((size_t)(dy > 0 ? dy * dy : 1) * dbl);
-    Lo.gOmd = take((size_t)d * d * dbl);
-    Lo.gOmdinv = take((size_t)d * d * dbl);
-    Lo.gscal = take(8 * dbl);
-    Lo.accept = take(sizeof(int));
-  }
-  if (kind == LAYOUT_STEP || kind == LAYOUT_FILTER) {
-    Lo.ell = take((size_t)N * dbl);
-    for (int l = 0; l <= Lo.L; ++l) Lo.elem[l] = take((size_t)Lo.n_lvl[l] * ES);
-    for (int l = 0; l <= Lo.L; ++l) Lo.pre[l] = take((size_t)Lo.n_lvl[l] * PS);
-  }
-  if (kind == LAYOUT_STEP) {
-    Lo.mf = take((size_t)N * D * dbl);
-    Lo.Pf = take((size_t)N * D * D * dbl);
-  }
-  if (kind == LAYOUT_STEP || kind == LAYOUT_SAMPLER) {
-    Lo.E = take((size_t)N * D * D * dbl);
-    Lo.U = take((size_t)N * D * dbl);
-    for (int l = 0; l <= Lo.L; ++l) Lo.sagg[l] = take((size_t)Lo.n_lvl[l] * SS);
-    for (int l = 0; l <= Lo.L; ++l) Lo.xin[l] = take((size_t)Lo.n_lvl[l] * D * dbl);
-  }
-  Lo.status = take(sizeof(int));
-  Lo.total = off;
-}
-
-template <class T>
-T* at(void* ws, size_t off) {
-  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
-}
-
-akf_status check_model(const akf_model* m, bool need_emission) {
-  if (!m) return fail(AKF_ERR_INVALID, "model is NULL");
-  if (m->N < 1) return fail(AKF_ERR_SHAPE, "N must be >= 1 (got %d)", m->N);
-  if (m->dx < 1 || m->dx > 64) return fail(AKF_ERR_SHAPE, "dx must be in [1, 64] (got %d)", m->dx);
-  if (!m->m0 || !m->P0 || !m->F || !m->Q)
-    return fail(AKF_ERR_INVALID, "m0, P0, F and Q must be non-NULL");
-  if (!need_emission) return AKF_OK;
-  if (m->dy < 1 || m->dy > 64) return fail(AKF_ERR_SHAPE, "dy must be in [1, 64] (got %d)", m->dy);
-  switch (m->emit) {
-    case AKF_EMIT_GAUSSIAN:
-      if (!m->H || !m->R) return fail(AKF_ERR_INVALID, "Gaussian emission needs H and R");
-      break;
-    case AKF_EMIT_POISSON_LOG:
-      if (!m->site) return fail(AKF_ERR_INVALID, "Poisson emission needs site");
-      break;
-    case AKF_EMIT_STUDENT_T:
-      if (!m->site) return fail(AKF_ERR_INVALID, "Student-t emission needs site");
-      if (!(m->nu > 0.0) || !(m->scale > 0.0))
-        return fail(AKF_ERR_INVALID, "Student-t emission needs nu > 0 and scale > 0");
-      break;
-    default:
-      return fail(AKF_ERR_INVALID, "unknown emission family %d", m->emit);
-  }
-  return AKF_OK;
-}
-
-KModel to_kmodel(const akf_model* m) {
-  KModel M;
-  M.N = m->N;
-  M.d = m->dx;
-  M.dy = m->dy;
-  M.emit = m->emit;
-  M.m0 = m->m0;
-  M.P0 = m->P0;
-  M.F = m->F;
-  M.b = m->b;
-  M.Q = m->Q;
-  M.H = m->H;
-  M.R = m->R;
-  M.site = m->site;
-  M.nu = m->nu;
-  M.scale = m->scale;
-  return M;
-}
-
-akf_status prepare_device() {
-  static std::once_flag once;
-  static hipError_t err = hipSuccess;
-  std::call_once(once, [] { err = set_lds_limits_all(); });
-  if (err != hipSuccess)
-    return fail(AKF_ERR_HIP, "setting LDS limits failed: %s", hipGetErrorString(err));
-  return AKF_OK;
-}
-
-akf_status hip_check(hipError_t e, const char* what) {
-  if (e != hipSuccess) return fail(AKF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
-  return AKF_OK;
-}
-
-void fill_tree(const Layout& Lo, void* ws, size_t elem_size, const size_t* lvl_elem,
-               const size_t* lvl_pre, int* status, int fail_bit, TreeArgs* up, TreeArgs* down) {
-  for (int l = 1; l <= Lo.L; ++l) {
-    TreeArgs u{};
-    u.src = at<double>(ws, lvl_elem[l - 1]);
-    u.dst = at<double>(ws, lvl_elem[l]);
-    u.n_src = Lo.n_lvl[l - 1];
-    u.n_dst = Lo.n_lvl[l];
-    u.status = status;
-    u.fail_bit = fail_bit;
-    up[l - 1] = u;
-    TreeArgs d{};
-    d.src = at<double>(ws, lvl_elem[l - 1]);
-    d.pre_src = at<double>(ws, lvl_pre[l]);
-    d.pre_dst = at<double>(ws, lvl_pre[l - 1]);
-    d.n_src = Lo.n_lvl[l];
-    d.n_dst = Lo.n_lvl[l - 1];
-    d.status = status;
-    d.fail_bit = fail_bit;
-    down[l - 1] = d;
-  }
-  (void)elem_size;
-}
-
-// root prefix flag (identity) of the filter tree
-double* root_flag(const Layout& Lo, void* ws) {
-  return at<double>(ws, Lo.pre[Lo.L]) + (Lo.D * Lo.D + Lo.D);
-}
-
-akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double* om,
-                      const double* Om, const double* Omd, double* mf, double* Pf, int ldm,
-                      double* ell, int* status, int fail_bit, hipStream_t st) {
-  FilterArgs P{};
-  P.B = Lo.B;
-  P.om = om;
-  P.Om = Om;
-  P.Omd = Omd;
-  P.elem = at<double>(ws, Lo.elem[0]);
-  P.pre = at<double>(ws, Lo.pre[0]);
-  P.mf = mf;
-  P.Pf = Pf;
-  P.ldm = ldm;
-  P.ell = ell;
-  P.status = status;
-  P.fail_bit = fail_bit;
-  TreeArgs up[kMaxLevels], down[kMaxLevels];
-  fill_tree(Lo, ws, 0, Lo.elem, Lo.pre, status, fail_bit, up, down);
-  return hip_check(launch_filter_any(Lo.D, M, P, up, down, Lo.L, st), "filter launch");
-}
-
-akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
-                       const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
-                       hipStream_t st) {
-  SampArgs S{};
-  S.B = Lo.B;
-  S.mf = mf;
-  S.Pf = Pf;
-  S.ldm = ldm;
-  S.xi_x = xi_x;
-  S.E = at<double>(ws, Lo.E);
-  S.U = at<double>(ws, Lo.U);
-  S.agg = at<double>(ws, Lo.sagg[0]);
-  S.xin = at<double>(ws, Lo.xin[0]);
-  S.xs = xs;
-  S.status = status;
-  TreeArgs up[kMaxLevels], down[kMaxLevels];
-  fill_tree(Lo, ws, 0, Lo.sagg, Lo.xin, status, ST_FWD_NOT_PD, up, down);
-  return hip_check(launch_sampler_any(Lo.D, M, S, up, down, Lo.L, st), "sampler launch");
-}
 
 akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
                         double delta, int order, const double* xi, const double* unif,
@@ -371,6 +124,199 @@ void timing_mark(int family, int begin, hipStream_t st) {
 
 extern "C" {
 
+size_t akf_smoother_workspace_bytes(const akf_model* model, int32_t block) {
+  if (check_model(model, false) != AKF_OK) return 0;
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, 0, block, LAYOUT_SMOOTH);
+  return Lo.total;
+}
+
+akf_status akf_smoother(const akf_model* model, const double* mf, const double* Pf, double* ms,
+                        double* Ps, int32_t* status, void* ws, size_t ws_bytes, int32_t block,
+                        void* stream) {
+  akf_status s;
+  if ((s = check_model(model, false)) != AKF_OK) return s;
+  if (!mf || !Pf || !ms || !Ps) return fail(AKF_ERR_INVALID, "mf, Pf, ms and Ps must be non-NULL");
+  if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, 0, block, LAYOUT_SMOOTH);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  if ((s = prepare_device()) != AKF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  int* dstat = at<int>(ws, Lo.status);
+  if ((s = hip_check(launch_step_init(dstat, nullptr, nullptr, 0, st), "init launch")) != AKF_OK)
+    return s;
+  SmoothArgs S{};
+  S.mf = mf;
+  S.Pf = Pf;
+  S.ldm = model->dx;
+  S.E = at<double>(ws, Lo.E);
+  S.g = at<double>(ws, Lo.g);
+  S.L = at<double>(ws, Lo.Lm);
+  S.status = dstat;
+  if ((s = hip_check(launch_smooth_build_any(Lo.D, to_kmodel(model), S, st), "smoother build")) !=
+      AKF_OK)
+    return s;
+  if ((s = run_egl(Lo, ws, S.g, Ps, ms, model->dx, model->dx, st)) != AKF_OK) return s;
+  if (status)
+    return hip_check(hipMemcpyAsync(status, dstat, sizeof(int), hipMemcpyDeviceToDevice, st),
+                     "status copy");
+  return AKF_OK;
+}
+
+namespace {
+akf_status check_lgssm(const akf_lgssm* m) {
+  if (!m) return fail(AKF_ERR_INVALID, "lgssm is NULL");
+  if (m->N < 1) return fail(AKF_ERR_SHAPE, "N must be >= 1 (got %d)", m->N);
+  if (m->dx < 1 || m->dx > 32)
+    return fail(AKF_ERR_SHAPE, "dx must be in [1, 32] for the LGSSM likelihood (got %d)", m->dx);
+  if (m->dy < 1 || m->dy > 32)
+    return fail(AKF_ERR_SHAPE, "dy must be in [1, 32] for the LGSSM likelihood (got %d)", m->dy);
+  if (!m->m0 || !m->P0 || !m->F || !m->logq || !m->H || !m->logr || !m->y)
+    return fail(AKF_ERR_INVALID, "every LGSSM array must be non-NULL");
+  return AKF_OK;
+}
+
+int lgssm_D(const akf_lgssm* m) {
+  const int d = m->dx > m->dy ? m->dx : m->dy;
+  return d <= 16 ? 16 : 32;
+}
+
+void lgssm_layout(Layout& Lo, const akf_lgssm* m, int block) {
+  // team size follows max(dx, dy): the observation block is padded to the same D
+  make_layout(Lo, m->N, m->dx > m->dy ? m->dx : m->dy, m->dy, block, LAYOUT_LGSSM);
+  Lo.d = m->dx;
+}
+
+KModel lgssm_kmodel(const akf_lgssm* m, void* ws, const Layout& Lo) {
+  KModel M{};
+  M.N = m->N;
+  M.d = m->dx;
+  M.dy = m->dy;
+  M.emit = EMIT_GAUSSIAN;
+  M.m0 = m->m0;
+  M.P0 = m->P0;
+  M.F = m->F;
+  M.b = nullptr;
+  M.Q = at<double>(ws, Lo.Qd);
+  M.H = m->H;
+  M.R = at<double>(ws, Lo.Rd);
+  return M;
+}
+
+LgArgs lgssm_args(const akf_lgssm* m, void* ws, const Layout& Lo) {
+  LgArgs G{};
+  G.dx = m->dx;
+  G.dy = m->dy;
+  G.B = Lo.B;
+  G.logq = m->logq;
+  G.logr = m->logr;
+  G.H = m->H;
+  G.y = m->y;
+  G.Q = at<double>(ws, Lo.Qd);
+  G.R = at<double>(ws, Lo.Rd);
+  G.mf = at<double>(ws, Lo.mf);
+  G.Pf = at<double>(ws, Lo.Pf);
+  G.E = at<double>(ws, Lo.E);
+  G.U = at<double>(ws, Lo.U);
+  G.Cm = at<double>(ws, Lo.Lm);
+  G.mbar = at<double>(ws, Lo.mbar);
+  G.Pbar = at<double>(ws, Lo.Pbar);
+  G.part = at<double>(ws, Lo.part);
+  G.status = at<int>(ws, Lo.status);
+  return G;
+}
+}  // namespace
+
+size_t akf_lgssm_workspace_bytes(const akf_lgssm* m, int32_t block) {
+  if (check_lgssm(m) != AKF_OK || block < 0) return 0;
+  Layout Lo;
+  lgssm_layout(Lo, m, block);
+  return Lo.total;
+}
+
+akf_status akf_lgssm_loglik(const akf_lgssm* m, double* ll, double* ell, int32_t* status, void* ws,
+                            size_t ws_bytes, int32_t block, void* stream) {
+  akf_status s;
+  if ((s = check_lgssm(m)) != AKF_OK) return s;
+  if (!ll) return fail(AKF_ERR_INVALID, "ll must be non-NULL");
+  if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
+  Layout Lo;
+  lgssm_layout(Lo, m, block);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  if ((s = prepare_device()) != AKF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  int* dstat = at<int>(ws, Lo.status);
+  if ((s = hip_check(launch_step_init(dstat, root_flag(Lo, ws), nullptr, 0, st), "init launch")) !=
+      AKF_OK)
+    return s;
+  LgArgs G = lgssm_args(m, ws, Lo);
+  if ((s = hip_check(launch_lgssm_prep(G, st), "parameter launch")) != AKF_OK) return s;
+  const KModel M = lgssm_kmodel(m, ws, Lo);
+  double* ellw = ell ? ell : at<double>(ws, Lo.ell);
+  if ((s = run_filter(Lo, M, ws, nullptr, nullptr, nullptr, at<double>(ws, Lo.mf),
+                      at<double>(ws, Lo.Pf), Lo.D, ellw, dstat, ST_FWD_NOT_PD, st, m->y, m->H,
+                      G.R, m->dy)) != AKF_OK)
+    return s;
+  if ((s = hip_check(launch_sum(ellw, m->N, ll, st), "sum launch")) != AKF_OK) return s;
+  if (status)
+    return hip_check(hipMemcpyAsync(status, dstat, sizeof(int), hipMemcpyDeviceToDevice, st),
+                     "status copy");
+  return AKF_OK;
+}
+
+akf_status akf_lgssm_loglik_grad(const akf_lgssm* m, const double* ll_bar, double* dF,
+                                 double* dlogq, double* dH, double* dlogr, int32_t* status,
+                                 void* ws, size_t ws_bytes, int32_t block, void* stream) {
+  akf_status s;
+  if ((s = check_lgssm(m)) != AKF_OK) return s;
+  if (!dF || !dlogq || !dH || !dlogr)
+    return fail(AKF_ERR_INVALID, "dF, dlogq, dH and dlogr must be non-NULL");
+  if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
+  Layout Lo;
+  lgssm_layout(Lo, m, block);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  if ((s = prepare_device()) != AKF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  const int D = Lo.D;
+  LgArgs G = lgssm_args(m, ws, Lo);
+  G.dF = dF;
+  G.dlogq = dlogq;
+  G.dH = dH;
+  G.dlogr = dlogr;
+  KModel M = lgssm_kmodel(m, ws, Lo);
+  // adjoint elements: E = Phi', U = H'w, Cm = -1/2 H' Sig H
+  if ((s = hip_check(launch_step_init(G.status, nullptr, at<double>(ws, Lo.xin[Lo.L]), D, st),
+                     "init launch")) != AKF_OK)
+    return s;
+  if ((s = hip_check(launch_adj_build_any(D, M, G, st), "adjoint build")) != AKF_OK) return s;
+  // mbar: path scan with (E, U) (output stride D)
+  SampArgs S{};
+  S.B = Lo.B;
+  S.E = G.E;
+  S.U = G.U;
+  S.agg = at<double>(ws, Lo.sagg[0]);
+  S.xin = at<double>(ws, Lo.xin[0]);
+  S.xs = G.mbar;
+  S.status = G.status;
+  TreeArgs up[kMaxLevels], down[kMaxLevels];
+  fill_tree(Lo, ws, 0, Lo.sagg, Lo.xin, G.status, ST_FWD_NOT_PD, up, down);
+  KModel Mv = M;
+  Mv.d = D;
+  if ((s = hip_check(launch_samp_scan_any(D, Mv, S, up, down, Lo.L, st), "mbar scan")) != AKF_OK)
+    return s;
+  // G_t in place of Cm, then Pbar: (E, L) scan
+  if ((s = hip_check(launch_adj_G_any(D, G, m->N, st), "adjoint G")) != AKF_OK) return s;
+  if ((s = run_egl(Lo, ws, nullptr, G.Pbar, nullptr, D, D, st)) != AKF_OK) return s;
+  if ((s = hip_check(launch_adj_finish_any(D, M, G, Lo.nb, ll_bar, st), "adjoint gradient")) !=
+      AKF_OK)
+    return s;
+  if (status)
+    return hip_check(hipMemcpyAsync(status, G.status, sizeof(int), hipMemcpyDeviceToDevice, st),
+                     "status copy");
+  return AKF_OK;
+}
+
 akf_status akf_timing_enable(int32_t family, int32_t capacity) {
   std::lock_guard<std::mutex> lk(g_timing.mu);
   timing_release_locked();
@@ -414,7 +360,7 @@ akf_status akf_timing_collect(int32_t* n_launches, double* total_ms) {
   return AKF_OK;
 }
 
-const char* akf_last_error(void) { return g_err; }
+const char* akf_last_error(void) { return akf::last_error(); }
 
 size_t akf_mh_workspace_bytes(const akf_model* model, int32_t order, int32_t block) {
   if (check_model(model, true) != AKF_OK || (order != 1 && order != 2)) return 0;

@@ -65,6 +65,11 @@ struct FilterArgs {
   double* ell;        // [N]
   int* status;
   int fail_bit;
+  // general observation model y_t = H x_t + N(0, R) (Ho != nullptr; D <= 32)
+  const double* yo;   // [N*dyo]
+  const double* Ho;   // [dyo*d]
+  const double* Ro;   // [dyo*dyo]
+  int dyo;
 };
 
 struct TreeArgs {
@@ -98,6 +103,81 @@ struct FinalArgs {
   int n_part_fwd, n_part_rev;
 };
 
+// (E, g, L) suffix scan (App. A eq. EgL_comb): elements E [N*D*D], g [N*D]
+// (nullable), L [N*D*D]; block aggregates `agg` (level 0); suffix states
+// entering each block `state` (level 0); outputs L~ (and g~) per step.
+struct EglArgs {
+  int N, B;
+  const double *E, *g, *L;
+  double* agg;
+  const double* state;
+  double* outL;  // [N*ldo*ldo]
+  double* outg;  // [N*ldo] or nullptr
+  int ldo, dout;
+};
+
+struct EglTree {
+  const double* src;
+  double* dst;
+  int n_src, n_dst;
+  const double* pre_src;
+  double* pre_dst;
+};
+
+struct SmoothArgs {
+  const double *mf, *Pf;
+  int ldm;
+  double *E, *g, *L;  // [N*D*D], [N*D], [N*D*D]
+  int* status;
+};
+
+// Linear-Gaussian model with theta = (F, log diag Q, H, log diag R).
+struct LgArgs {
+  int dx, dy, B;
+  const double *logq, *logr, *H, *y;
+  double *Q, *R;          // dense diagonal matrices built from theta (user dims)
+  const double *mf, *Pf;  // forward filtering moments (checkpoint, stride D)
+  double *E, *U, *Cm, *mbar, *Pbar, *part;
+  double *dF, *dlogq, *dH, *dlogr;
+  int* status;
+};
+
+// ---------------------------------------------------------------------------
+// Batched chains: per-chain descriptors resident in device memory and work
+// tables of (chain, item) pairs walked by persistent kernels.
+// ---------------------------------------------------------------------------
+constexpr int kMaxLv = 24;
+
+struct ChainDev {
+  KModel M;
+  StepArgs A;          // xi_u is set per step from xi_base
+  FilterArgs Ff, Fr;   // forward (at x) and reverse (at x*) filters
+  SampArgs S;          // xi_x is set per step
+  FinalArgs Fin;       // unif and outputs are set per step
+  int L;               // tree levels of this chain
+  int n_part;          // partial-sum blocks of the linearisation
+  TreeArgs fup[kMaxLv], fdown[kMaxLv], sup[kMaxLv], sdown[kMaxLv];
+  double* root_flag;
+  double* root_xin;
+  const double* xi_base;  // [n_steps, 2, N, d]
+  int64_t xi_stride;      // 2 N d
+  const double* unif_base;
+  double *lr_base, *lzf_base, *lzr_base;
+  int *acc_base, *st_base;
+  double* x;              // chain state, updated in place
+};
+
+struct Item {
+  int c, i;
+};
+
+struct BatchLaunch {
+  const ChainDev* cd;
+  const Item* items;
+  int n_items;
+  int grid;
+};
+
 // Kernel families for the timing hook (include/akf.h, akf_timing_enable).
 enum {
   FAM_FILTER_FOLD = 0, FAM_FILTER_UP = 1, FAM_FILTER_DOWN = 2, FAM_FILTER_FINAL = 3,
@@ -117,5 +197,27 @@ hipError_t launch_step_init(int* status, double* root_flag, double* root_xin, in
 hipError_t launch_finalize(const KModel& M, StepArgs A, FinalArgs F, const double* x,
                            double* x_out, hipStream_t st);
 hipError_t set_lds_limits_all();
+hipError_t launch_samp_scan_any(int D, const KModel& M, SampArgs S, TreeArgs* up, TreeArgs* down,
+                                int n_levels, hipStream_t st);
+hipError_t launch_egl_scan_any(int D, EglArgs A, EglTree* up, EglTree* down, int n_levels,
+                               hipStream_t st);
+hipError_t launch_smooth_build_any(int D, const KModel& M, SmoothArgs S, hipStream_t st);
+hipError_t launch_lgssm_prep(LgArgs G, hipStream_t st);
+hipError_t launch_sum(const double* a, int n, double* out, hipStream_t st);
+hipError_t launch_adj_build_any(int D, const KModel& M, LgArgs G, hipStream_t st);
+hipError_t launch_adj_G_any(int D, LgArgs G, int N, hipStream_t st);
+hipError_t launch_adj_finish_any(int D, const KModel& M, LgArgs G, int nblk, const double* ll_bar,
+                                 hipStream_t st);
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
+
+// Batched launches for one D class.  `step` is the device step counter.
+enum BatchPhase {
+  BP_INIT = 0, BP_LIN_FWD, BP_LIN_REV, BP_FOLD, BP_UP, BP_DOWN, BP_FINAL, BP_SBUILD, BP_SFOLD,
+  BP_SUP, BP_SDOWN, BP_SFINAL, BP_FINALIZE, BP_SELECT
+};
+hipError_t launch_batch_phase(int D, int phase, BatchLaunch L, int level, int rev,
+                              const int* step, hipStream_t st);
+hipError_t launch_step_advance(int* step, int reset, hipStream_t st);
+size_t batch_lds_bytes(int D, int phase);
 
 }  // namespace akf

@@ -86,8 +86,8 @@ __device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __re
 
 // Forward linearisation at x: draws u, writes omega/Omega (diagonal), log h
 // partial sums per workgroup.  blockDim.x = 256.
-__global__ void __launch_bounds__(256) k_lin_fwd_diag(KModel M, StepArgs A) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lin_fwd_diag_body(const KModel& M, const StepArgs& A, int item) {
+  const int64_t gid = (int64_t)item * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)M.N * M.d;
   double lh = 0.0;
   if (gid < n) {
@@ -114,14 +114,18 @@ __global__ void __launch_bounds__(256) k_lin_fwd_diag(KModel M, StepArgs A) {
   for (int o = 32; o > 0; o >>= 1) lh += __shfl_xor(lh, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = lh;
   __syncthreads();
-  if (threadIdx.x == 0) A.part_lh_x[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) A.part_lh_x[item] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) k_lin_fwd_diag(KModel M, StepArgs A) {
+  lin_fwd_diag_body(M, A, blockIdx.x);
 }
 
 // Reverse linearisation at x* with the same u, and the per-(t,i) MH terms:
 //   [log h(y|x*) - log h(y|x)] + [(u-x)^2 - (u-x*)^2]/delta
 //   + log N(omega*_i; x_i, Omega*_i) - log N(omega_i; x*_i, Omega_i)
-__global__ void __launch_bounds__(256) k_lin_rev_diag(KModel M, StepArgs A) {
-  const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void lin_rev_diag_body(const KModel& M, const StepArgs& A, int item) {
+  const int64_t gid = (int64_t)item * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)M.N * M.d;
   double term = 0.0, lhs = 0.0;
   if (gid < n) {
@@ -157,9 +161,13 @@ __global__ void __launch_bounds__(256) k_lin_rev_diag(KModel M, StepArgs A) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    A.part_terms[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-    A.part_lh_xs[blockIdx.x] = red[4] + red[5] + red[6] + red[7];
+    A.part_terms[item] = red[0] + red[1] + red[2] + red[3];
+    A.part_lh_xs[item] = red[4] + red[5] + red[6] + red[7];
   }
+}
+
+__global__ void __launch_bounds__(256) k_lin_rev_diag(KModel M, StepArgs A) {
+  lin_rev_diag_body(M, A, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -404,6 +412,40 @@ __device__ __forceinline__ void vec_load(double* s, const double* __restrict__ g
   if (tid < D) s[tid] = (tid < d && g) ? g[tid] : 0.0;
 }
 
+// Load a rows x cols user matrix (row-major) into an LDS buffer, zero padded.
+template <int D>
+__device__ __forceinline__ void lds_load_rect(double* s, const double* __restrict__ g, int rows,
+                                              int cols) {
+  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
+    const int i = e / D, j = e % D;
+    s[i * Cfg<D>::LD + j] = (i < rows && j < cols) ? g[i * cols + j] : 0.0;
+  }
+}
+
+// General observation model at step t: B1 <- H Pp, S = H Pp H' + R -> B2 (then
+// L), B3 <- L^{-1}, vw <- y_t - H mu.  Team-wide; ends synchronised.
+template <int D>
+__device__ __forceinline__ void obs_general(double* B1, double* B2, double* B3, const double* sH,
+                                            const RM<D>& Pp, const double* vmu, double* vw,
+                                            const FilterArgs& P, int t, double* scal,
+                                            double* logdet, bool& ok) {
+  const int tid = threadIdx.x;
+  RM<D> R1;
+  rm_stage<D>(Pp, B1);
+  team_sync();
+  gemm<D, false, false, false>(R1, sH, B1);  // H Pp
+  team_sync();
+  rm_stage<D>(R1, B1);
+  team_sync();
+  gemm<D, false, true, false>(R1, B1, sH);  // H Pp H'
+  rm_add_load<D>(R1, P.Ro, P.dyo, P.dyo);
+  rm_stage<D>(R1, B2);
+  matvec<D, false>(vw, sH, vmu);
+  team_sync();
+  if (tid < D) vw[tid] = (tid < P.dyo) ? P.yo[(int64_t)t * P.dyo + tid] - vw[tid] : 0.0;
+  ok = chol_inv<D, true>(B2, B3, P.dyo, logdet, scal) && ok;
+}
+
 // ---------------------------------------------------------------------------
 // Filter, phase 1: fold the elements of one block.
 // State (A, b, C, eta, J) represents p(x_t | omega_{s:t}, x_{s-1}) =
@@ -415,25 +457,30 @@ __device__ __forceinline__ void vec_load(double* s, const double* __restrict__ g
 // which is the element combine of App. A with the raw element of step t
 // written in terms of F, Q and Omega_t.  The block containing t = 0 starts
 // from the prior (A = 0 throughout).  Output element layout: ElemLayout.
+// GH (general observation y_t = H x_t + N(0, R), D <= 32): S = H Pp H' + R,
+// X = L^{-1} H Pp, Y = L^{-1} H T, r = L^{-1}(y_t - H mu).
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs P) {
+template <int D, bool GH>
+__device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterArgs& P, int item) {
   using C = Cfg<D>;
+  static_assert(!GH || D <= 32, "general observation matrices need D <= 32");
   extern __shared__ double lds[];
   double* sF = lds;
   double* B1 = sF + C::MAT;
   double* B2 = B1 + C::MAT;
   double* B3 = B2 + C::MAT;
-  double* vb = B3 + C::MAT;   // b
+  double* sH = B3 + C::MAT;   // GH only
+  double* vb = sH + (GH ? C::MAT : 0);   // b
   double* veta = vb + D;      // eta
   double* vmu = veta + D;     // mu
   double* vw = vmu + D;       // omega - mu
   double* vr = vw + D;        // r
   double* scal = vr + D;      // 8 doubles
-  const int blk = blockIdx.x, tid = threadIdx.x, d = M.d;
+  const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   const bool first = (s0 == 0);
   lds_load_mat<D>(sF, M.F, d);
+  if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
   if (tid < D) {
     vb[tid] = 0.0;
     veta[tid] = 0.0;
@@ -468,13 +515,17 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
         team_sync();
       }
     }
-    build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
     double logdet;
-    ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;  // B3 = L^{-1}
-    rm_stage<D>(Pp, B1);
-    if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
-    team_sync();
-    gemm<D, false, false, false>(X, B3, B1);  // X = L^{-1} Pp
+    if constexpr (GH) {
+      obs_general<D>(B1, B2, B3, sH, Pp, vmu, vw, P, t, scal, &logdet, ok);  // B1 = H Pp
+    } else {
+      build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
+      ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;  // B3 = L^{-1}
+      rm_stage<D>(Pp, B1);
+      if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
+      team_sync();
+    }
+    gemm<D, false, false, false>(X, B3, B1);  // X = L^{-1} Pp   (GH: L^{-1} H Pp)
     matvec<D, false>(vr, B3, vw);             // r = L^{-1} (omega - mu)
     team_sync();
     rm_stage<D>(X, B2);
@@ -490,7 +541,13 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
     if (!first && t > 0) {
       rm_stage<D>(T, B1);
       team_sync();
-      gemm<D, false, false, false>(Y, B3, B1);  // Y = L^{-1} T
+      if constexpr (GH) {
+        gemm<D, false, false, false>(Y, sH, B1);  // H T
+        team_sync();
+        rm_stage<D>(Y, B1);
+        team_sync();
+      }
+      gemm<D, false, false, false>(Y, B3, B1);  // Y = L^{-1} T   (GH: L^{-1} H T)
       team_sync();
       rm_stage<D>(Y, B1);
       team_sync();
@@ -525,6 +582,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
   }
 }
 
+template <int D, bool GH>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs P) {
+  filter_fold_body<D, GH>(M, P, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Filter, phase 2 up-sweep: node k of a level = left (earlier) (x) right.
 // With C_i = L L' (FP64 Cholesky), W = I + L' J_j L = R R', V = L R^{-T}, so
@@ -537,7 +599,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 // (the element combine of App. A in Cholesky form; covariances stay PSD).
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) {
+__device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& T, int item) {
   using C = Cfg<D>;
   using EL = ElemLayout<D>;
   extern __shared__ double lds[];
@@ -551,7 +613,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) 
   double* vw = vz + D;
   double* vk = vw + D;
   double* scal = vk + D;
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = item, tid = threadIdx.x;
   const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
   double* out = T.dst + (int64_t)k * EL::SIZE;
   if (2 * k + 1 >= T.n_src) {
@@ -649,6 +711,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) 
   if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
 }
 
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) {
+  filter_up_body<D>(M, T, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Filter, phase 2 down-sweep: the prefix entering node k of level l is known
 // (pre_src, as a filtering moment pair (m, P), or the identity for the left
@@ -659,7 +726,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) 
 // With the identity prefix the result is the left child's (b, C) (its A = 0).
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T) {
+__device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs& T, int item) {
   using C = Cfg<D>;
   using EL = ElemLayout<D>;
   using PL = PrefLayout<D>;
@@ -673,7 +740,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T
   double* vz = vc + D;
   double* vw = vz + D;
   double* scal = vw + D;
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = item, tid = threadIdx.x;
   const double* pin = T.pre_src + (int64_t)k * PL::SIZE;
   const bool ident = pin[PL::flag] != 0.0;
   // left child: same prefix
@@ -736,30 +803,39 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T
   if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
 }
 
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T) {
+  filter_down_body<D>(M, T, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Filter, phase 3: each block re-runs its steps from the prefix entering it
 // (sequential Kalman filter, App. A "Kalman filter"), with the predictive-
 // form likelihood term ell_t = log N(omega_t; m^p_t, P^p_t + Omega_t).
 // Writes m^f_t, P^f_t (when requested) and ell_t.
 // ---------------------------------------------------------------------------
-template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArgs P) {
+template <int D, bool GH>
+__device__ __forceinline__ void filter_final_body(const KModel& M, const FilterArgs& P, int item) {
   using C = Cfg<D>;
+  static_assert(!GH || D <= 32, "general observation matrices need D <= 32");
   using PL = PrefLayout<D>;
   extern __shared__ double lds[];
   double* sF = lds;
   double* B1 = sF + C::MAT;
   double* B2 = B1 + C::MAT;
   double* B3 = B2 + C::MAT;
-  double* vm = B3 + C::MAT;
+  double* sH = B3 + C::MAT;  // GH only
+  double* vm = sH + (GH ? C::MAT : 0);
   double* vmp = vm + D;
   double* vw = vmp + D;
   double* vr = vw + D;
   double* red = vr + D;
   double* scal = red + 8;
-  const int blk = blockIdx.x, tid = threadIdx.x, d = M.d;
+  const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   lds_load_mat<D>(sF, M.F, d);
+  if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
+  const int dobs = GH ? P.dyo : d;
   RM<D> Pm, Pp, T, X;
   if (s0 > 0) {
     const double* pin = P.pre + (int64_t)blk * PL::SIZE;
@@ -785,12 +861,16 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArg
       team_sync();
       if (tid < d && M.b) vmp[tid] += M.b[tid];
     }
-    build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
     double logdet;
-    ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;
-    rm_stage<D>(Pp, B1);
-    if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
-    team_sync();
+    if constexpr (GH) {
+      obs_general<D>(B1, B2, B3, sH, Pp, vmp, vw, P, t, scal, &logdet, ok);  // B1 = H Pp
+    } else {
+      build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
+      ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;
+      rm_stage<D>(Pp, B1);
+      if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
+      team_sync();
+    }
     gemm<D, false, false, false>(X, B3, B1);
     matvec<D, false>(vr, B3, vw);
     team_sync();
@@ -804,7 +884,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArg
       for (int j = 0; j < D; ++j) s = fma(B2[j * C::LD + tid], vr[j], s);
       vm[tid] = vmp[tid] + s;  // m^f = m^p + X' r
     }
-    if (tid == 0) P.ell[t] = -0.5 * (d * LOG2PI + logdet + rr);
+    if (tid == 0) P.ell[t] = -0.5 * (dobs * LOG2PI + logdet + rr);
     team_sync();
     rm_symmetrise<D>(Pm, B1);
     if (P.mf) {
@@ -815,6 +895,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArg
   if (!ok && tid == 0) flag_status(P.status, P.fail_bit);
 }
 
+template <int D, bool GH>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArgs P) {
+  filter_final_body<D, GH>(M, P, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------
 // Sampler, element build (eq. backward, Alg. "Parallel RTS sampler"), one team
 // per t:  P^p = F P^f F' + Q = L_p L_p',  W = L_p^{-1} F P^f,
@@ -823,7 +908,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArg
 // Terminal step: E = 0, U = m^f + chol(P^f) xi.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_build(KModel M, SampArgs S) {
+__device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs& S, int item) {
   using C = Cfg<D>;
   extern __shared__ double lds[];
   double* sF = lds;
@@ -835,7 +920,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_build(KModel M, SampArgs S)
   double* vg = vmp + D;
   double* vxi = vg + D;
   double* scal = vxi + D;
-  const int t = blockIdx.x, tid = threadIdx.x, d = M.d;
+  const int t = item, tid = threadIdx.x, d = M.d;
   RM<D> Pf, R1, R2;
   rm_load<D>(Pf, S.Pf + (int64_t)t * S.ldm * S.ldm, S.ldm, d);
   if (tid < D) {
@@ -899,17 +984,22 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_build(KModel M, SampArgs S)
   if (!ok && tid == 0) flag_status(S.status, ST_FWD_NOT_PD);
 }
 
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_build(KModel M, SampArgs S) {
+  samp_build_body<D>(M, S, blockIdx.x);
+}
+
 // Sampler, block fold: suffix aggregate (E~, U~) of a block, folding from its
 // last step backwards: (E~, U~) <- (E_t E~, E_t U~ + U_t).
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_fold(KModel M, SampArgs S) {
+__device__ __forceinline__ void samp_fold_body(const KModel& M, const SampArgs& S, int item) {
   using C = Cfg<D>;
   extern __shared__ double lds[];
   double* B1 = lds;
   double* B2 = B1 + C::MAT;
   double* vu = B2 + C::MAT;
   double* vn = vu + D;
-  const int blk = blockIdx.x, tid = threadIdx.x;
+  const int blk = item, tid = threadIdx.x;
   const int s0 = blk * S.B, s1 = min(M.N, s0 + S.B);
   RM<D> Et;
   rm_load<D>(Et, S.E + (int64_t)(s1 - 1) * D * D, D, D);
@@ -929,9 +1019,14 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_fold(KModel M, SampArgs S) 
   if (tid < D) out[SampLayout<D>::U + tid] = vu[tid];
 }
 
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_fold(KModel M, SampArgs S) {
+  samp_fold_body<D>(M, S, blockIdx.x);
+}
+
 // Sampler tree up-sweep: node k = left (earlier) o right = (E_l E_r, E_l U_r + U_l).
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_up(KModel M, TreeArgs T) {
+__device__ __forceinline__ void samp_up_body(const KModel& M, const TreeArgs& T, int item) {
   using C = Cfg<D>;
   using SL = SampLayout<D>;
   extern __shared__ double lds[];
@@ -939,7 +1034,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_up(KModel M, TreeArgs T) {
   double* B2 = B1 + C::MAT;
   double* vu = B2 + C::MAT;
   double* vn = vu + D;
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = item, tid = threadIdx.x;
   const double* el = T.src + (int64_t)(2 * k) * SL::SIZE;
   double* out = T.dst + (int64_t)k * SL::SIZE;
   if (2 * k + 1 >= T.n_src) {
@@ -959,12 +1054,17 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_up(KModel M, TreeArgs T) {
   if (tid < D) out[SL::U + tid] = vn[tid] + el[SL::U + tid];
 }
 
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_up(KModel M, TreeArgs T) {
+  samp_up_body<D>(M, T, blockIdx.x);
+}
+
 // Sampler tree down-sweep: xin[node] is x* at the step just after the node's
 // range.  Right child inherits it; left child gets E_r xin + U_r.
 template <int D>
-__global__ void __launch_bounds__(64) k_samp_down(KModel M, TreeArgs T) {
+__device__ __forceinline__ void samp_down_body(const KModel& M, const TreeArgs& T, int item) {
   using SL = SampLayout<D>;
-  const int k = blockIdx.x, tid = threadIdx.x;
+  const int k = item, tid = threadIdx.x;
   const double* xin = T.pre_src + (int64_t)k * D;
   double* xl = T.pre_dst + (int64_t)(2 * k) * D;
   const bool has_right = (2 * k + 1 < T.n_dst);
@@ -982,12 +1082,17 @@ __global__ void __launch_bounds__(64) k_samp_down(KModel M, TreeArgs T) {
   }
 }
 
+template <int D>
+__global__ void __launch_bounds__(64) k_samp_down(KModel M, TreeArgs T) {
+  samp_down_body<D>(M, T, blockIdx.x);
+}
+
 // Sampler, block final: x*_t = E_t x*_{t+1} + U_t inside each block.
 template <int D>
-__global__ void __launch_bounds__(64) k_samp_final(KModel M, SampArgs S) {
+__device__ __forceinline__ void samp_final_body(const KModel& M, const SampArgs& S, int item) {
   __shared__ double vx[64];
   __shared__ double vn[64];
-  const int blk = blockIdx.x, tid = threadIdx.x, d = M.d;
+  const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * S.B, s1 = min(M.N, s0 + S.B);
   if (tid < D) vx[tid] = S.xin[(int64_t)blk * D + tid];
   __syncthreads();
@@ -1003,6 +1108,11 @@ __global__ void __launch_bounds__(64) k_samp_final(KModel M, SampArgs S) {
     if (tid < d) S.xs[(int64_t)t * d + tid] = vn[tid];
     __syncthreads();
   }
+}
+
+template <int D>
+__global__ void __launch_bounds__(64) k_samp_final(KModel M, SampArgs S) {
+  samp_final_body<D>(M, S, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1021,7 +1131,8 @@ __device__ double block_sum(const double* a, int n, double* red) {
   return tot;
 }
 
-__global__ void __launch_bounds__(256) k_mh_finalize(KModel M, StepArgs A, FinalArgs F) {
+__device__ __forceinline__ void mh_finalize_body(const KModel& M, const StepArgs& A,
+                                                 const FinalArgs& F) {
   __shared__ double red[4];
   const double lzf = block_sum(A.ell, M.N, red);
   const double lzr = block_sum(A.ell2, M.N, red);
@@ -1047,33 +1158,44 @@ __global__ void __launch_bounds__(256) k_mh_finalize(KModel M, StepArgs A, Final
   }
 }
 
+__global__ void __launch_bounds__(256) k_mh_finalize(KModel M, StepArgs A, FinalArgs F) {
+  mh_finalize_body(M, A, F);
+}
+
+__device__ __forceinline__ void mh_select_body(int64_t n, const double* __restrict__ x,
+                                               const double* __restrict__ xs,
+                                               double* __restrict__ x_out,
+                                               const int* __restrict__ accept_flag, int item) {
+  const int64_t i = (int64_t)item * blockDim.x + threadIdx.x;
+  if (i < n) x_out[i] = (*accept_flag) ? xs[i] : x[i];
+}
+
 __global__ void __launch_bounds__(256) k_mh_select(int64_t n, const double* __restrict__ x,
                                                    const double* __restrict__ xs,
                                                    double* __restrict__ x_out,
                                                    const int* __restrict__ accept_flag) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) x_out[i] = (*accept_flag) ? xs[i] : x[i];
+  mh_select_body(n, x, xs, x_out, accept_flag, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launch helpers (templated on D), used by akf_capi.cpp
 // ---------------------------------------------------------------------------
 template <int D>
-size_t lds_bytes_filter() {
-  return (size_t)(4 * Cfg<D>::MAT + 6 * D + 16) * sizeof(double);
+size_t lds_bytes_filter(bool gh = false) {
+  return (size_t)((gh ? 5 : 4) * Cfg<D>::MAT + 6 * D + 16) * sizeof(double);
 }
 template <int D>
 size_t lds_bytes_samp2() {
   return (size_t)(2 * Cfg<D>::MAT + 2 * D) * sizeof(double);
 }
 
-template <int D>
+template <int D, bool GH>
 hipError_t launch_filter(const KModel& M, FilterArgs P, TreeArgs* lv_up, TreeArgs* lv_down,
                          int n_levels, hipStream_t st) {
-  const size_t lds = lds_bytes_filter<D>();
+  const size_t lds = lds_bytes_filter<D>(GH);
   const int nb = (M.N + P.B - 1) / P.B;
   timing_mark(FAM_FILTER_FOLD, 1, st);
-  hipLaunchKernelGGL(k_filter_fold<D>, dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  hipLaunchKernelGGL((k_filter_fold<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FOLD, 0, st);
   for (int l = 0; l < n_levels; ++l) {
     timing_mark(FAM_FILTER_UP, 1, st);
@@ -1088,18 +1210,15 @@ hipError_t launch_filter(const KModel& M, FilterArgs P, TreeArgs* lv_up, TreeArg
     timing_mark(FAM_FILTER_DOWN, 0, st);
   }
   timing_mark(FAM_FILTER_FINAL, 1, st);
-  hipLaunchKernelGGL(k_filter_final<D>, dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  hipLaunchKernelGGL((k_filter_final<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FINAL, 0, st);
   return hipGetLastError();
 }
 
 template <int D>
-hipError_t launch_sampler(const KModel& M, SampArgs S, TreeArgs* lv_up, TreeArgs* lv_down,
-                          int n_levels, hipStream_t st) {
+hipError_t launch_samp_scan(const KModel& M, SampArgs S, TreeArgs* lv_up, TreeArgs* lv_down,
+                            int n_levels, hipStream_t st) {
   const int nb = (M.N + S.B - 1) / S.B;
-  timing_mark(FAM_SAMP_BUILD, 1, st);
-  hipLaunchKernelGGL(k_samp_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_filter<D>(), st, M, S);
-  timing_mark(FAM_SAMP_BUILD, 0, st);
   timing_mark(FAM_SAMP_FOLD, 1, st);
   hipLaunchKernelGGL(k_samp_fold<D>, dim3(nb), dim3(Cfg<D>::NT), lds_bytes_samp2<D>(), st, M, S);
   timing_mark(FAM_SAMP_FOLD, 0, st);
@@ -1121,10 +1240,40 @@ hipError_t launch_sampler(const KModel& M, SampArgs S, TreeArgs* lv_up, TreeArgs
 }
 
 template <int D>
+hipError_t launch_sampler(const KModel& M, SampArgs S, TreeArgs* lv_up, TreeArgs* lv_down,
+                          int n_levels, hipStream_t st) {
+  timing_mark(FAM_SAMP_BUILD, 1, st);
+  hipLaunchKernelGGL(k_samp_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_filter<D>(), st, M, S);
+  timing_mark(FAM_SAMP_BUILD, 0, st);
+  return launch_samp_scan<D>(M, S, lv_up, lv_down, n_levels, st);
+}
+
+hipError_t launch_samp_scan_any(int D, const KModel& M, SampArgs S, TreeArgs* up, TreeArgs* down,
+                                int nl, hipStream_t st) {
+  switch (D) {
+    case 16: return launch_samp_scan<16>(M, S, up, down, nl, st);
+    case 32: return launch_samp_scan<32>(M, S, up, down, nl, st);
+    case 64: return launch_samp_scan<64>(M, S, up, down, nl, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+__global__ void k_zero(double* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+hipError_t launch_zero(double* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+template <int D>
 hipError_t set_lds_limits() {
   hipError_t e;
   const int lf = (int)lds_bytes_filter<D>();
-  if ((e = hipFuncSetAttribute((const void*)k_filter_fold<D>,
+  if ((e = hipFuncSetAttribute((const void*)k_filter_fold<D, false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
     return e;
   if ((e = hipFuncSetAttribute((const void*)k_filter_up<D>,
@@ -1133,7 +1282,7 @@ hipError_t set_lds_limits() {
   if ((e = hipFuncSetAttribute((const void*)k_filter_down<D>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
     return e;
-  if ((e = hipFuncSetAttribute((const void*)k_filter_final<D>,
+  if ((e = hipFuncSetAttribute((const void*)k_filter_final<D, false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
     return e;
   if ((e = hipFuncSetAttribute((const void*)k_samp_build<D>,
@@ -1144,10 +1293,17 @@ hipError_t set_lds_limits() {
 
 hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, TreeArgs* down,
                              int nl, hipStream_t st) {
+  if (P.Ho) {
+    switch (D) {
+      case 16: return launch_filter<16, true>(M, P, up, down, nl, st);
+      case 32: return launch_filter<32, true>(M, P, up, down, nl, st);
+    }
+    return hipErrorInvalidValue;
+  }
   switch (D) {
-    case 16: return launch_filter<16>(M, P, up, down, nl, st);
-    case 32: return launch_filter<32>(M, P, up, down, nl, st);
-    case 64: return launch_filter<64>(M, P, up, down, nl, st);
+    case 16: return launch_filter<16, false>(M, P, up, down, nl, st);
+    case 32: return launch_filter<32, false>(M, P, up, down, nl, st);
+    case 64: return launch_filter<64, false>(M, P, up, down, nl, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1200,6 +1356,221 @@ hipError_t launch_finalize(const KModel& M, StepArgs A, FinalArgs F, const doubl
   hipLaunchKernelGGL(k_mh_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, A.xs,
                      x_out, A.accept_flag);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Batched chains.  Each persistent kernel walks a table of (chain, item) pairs
+// (grid-stride); every pair runs the same body as the single-chain kernel with
+// that chain's descriptor.  Per-step inputs (normals, uniform) and outputs are
+// offset by the device step counter, so one captured step is replayed.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ StepArgs step_args(const ChainDev& c, int step) {
+  StepArgs A = c.A;
+  A.xi_u = c.xi_base + (int64_t)step * c.xi_stride;
+  return A;
+}
+
+__global__ void __launch_bounds__(64) kb_init(BatchLaunch L, int D) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const ChainDev& c = L.cd[L.items[w].c];
+    if (threadIdx.x == 0) {
+      *c.A.status = 0;
+      *c.root_flag = 1.0;
+    }
+    if ((int)threadIdx.x < D) c.root_xin[threadIdx.x] = 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) kb_lin(BatchLaunch L, int rev, const int* step) {
+  const int s = *step;
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    const StepArgs A = step_args(c, s);
+    if (rev)
+      lin_rev_diag_body(c.M, A, I.i);
+    else
+      lin_fwd_diag_body(c.M, A, I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) kb_fold(BatchLaunch L, int rev) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    filter_fold_body<D, false>(c.M, rev ? c.Fr : c.Ff, I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) kb_final(BatchLaunch L, int rev) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    filter_final_body<D, false>(c.M, rev ? c.Fr : c.Ff, I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) kb_up(BatchLaunch L, int level, int rev) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    TreeArgs T = c.fup[level - 1];
+    T.fail_bit = rev ? ST_REV_NOT_PD : ST_FWD_NOT_PD;
+    filter_up_body<D>(c.M, T, I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) kb_down(BatchLaunch L, int level, int rev) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    TreeArgs T = c.fdown[level - 1];
+    T.fail_bit = rev ? ST_REV_NOT_PD : ST_FWD_NOT_PD;
+    filter_down_body<D>(c.M, T, I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) kb_sbuild(BatchLaunch L, const int* step) {
+  const int s = *step;
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    SampArgs S = c.S;
+    S.xi_x = c.xi_base + (int64_t)s * c.xi_stride + (int64_t)c.M.N * c.M.d;
+    samp_build_body<D>(c.M, S, I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) kb_sfold(BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    samp_fold_body<D>(c.M, c.S, I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) kb_sup(BatchLaunch L, int level) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    samp_up_body<D>(c.M, c.sup[level - 1], I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(64) kb_sdown(BatchLaunch L, int level) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    samp_down_body<D>(c.M, c.sdown[level - 1], I.i);
+    __syncthreads();
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(64) kb_sfinal(BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    samp_final_body<D>(c.M, c.S, I.i);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) kb_finalize(BatchLaunch L, const int* step) {
+  const int s = *step;
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const ChainDev& c = L.cd[L.items[w].c];
+    FinalArgs F = c.Fin;
+    F.unif = c.unif_base + s;
+    F.log_ratio = c.lr_base ? c.lr_base + s : nullptr;
+    F.accepted = c.acc_base ? c.acc_base + s : nullptr;
+    F.logZ_fwd = c.lzf_base ? c.lzf_base + s : nullptr;
+    F.logZ_rev = c.lzr_base ? c.lzr_base + s : nullptr;
+    F.status_out = c.st_base ? c.st_base + s : nullptr;
+    mh_finalize_body(c.M, c.A, F);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) kb_select(BatchLaunch L) {
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    mh_select_body((int64_t)c.M.N * c.M.d, c.x, c.A.xs, c.x, c.A.accept_flag, I.i);
+  }
+}
+
+__global__ void k_step_advance(int* step, int reset) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *step = reset ? 0 : *step + 1;
+}
+
+hipError_t launch_step_advance(int* step, int reset, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(64), 0, st, step, reset);
+  return hipGetLastError();
+}
+
+size_t batch_lds_bytes(int D, int phase) {
+  const bool team = phase == BP_FOLD || phase == BP_UP || phase == BP_DOWN || phase == BP_FINAL ||
+                    phase == BP_SBUILD;
+  const bool two = phase == BP_SFOLD || phase == BP_SUP;
+  switch (D) {
+    case 16: return team ? lds_bytes_filter<16>() : (two ? lds_bytes_samp2<16>() : 0);
+    case 32: return team ? lds_bytes_filter<32>() : (two ? lds_bytes_samp2<32>() : 0);
+    case 64: return team ? lds_bytes_filter<64>() : (two ? lds_bytes_samp2<64>() : 0);
+  }
+  return 0;
+}
+
+template <int D>
+hipError_t launch_batch_phase_t(int phase, BatchLaunch L, int level, int rev, const int* step,
+                                hipStream_t st) {
+  if (L.n_items <= 0) return hipSuccess;
+  const dim3 g(L.grid), bt(Cfg<D>::NT), b64(64), b256(256);
+  const size_t lds = batch_lds_bytes(D, phase);
+  switch (phase) {
+    case BP_INIT: hipLaunchKernelGGL(kb_init, g, b64, 0, st, L, D); break;
+    case BP_LIN_FWD: hipLaunchKernelGGL(kb_lin, g, b256, 0, st, L, 0, step); break;
+    case BP_LIN_REV: hipLaunchKernelGGL(kb_lin, g, b256, 0, st, L, 1, step); break;
+    case BP_FOLD: hipLaunchKernelGGL(kb_fold<D>, g, bt, lds, st, L, rev); break;
+    case BP_UP: hipLaunchKernelGGL(kb_up<D>, g, bt, lds, st, L, level, rev); break;
+    case BP_DOWN: hipLaunchKernelGGL(kb_down<D>, g, bt, lds, st, L, level, rev); break;
+    case BP_FINAL: hipLaunchKernelGGL(kb_final<D>, g, bt, lds, st, L, rev); break;
+    case BP_SBUILD: hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step); break;
+    case BP_SFOLD: hipLaunchKernelGGL(kb_sfold<D>, g, bt, lds, st, L); break;
+    case BP_SUP: hipLaunchKernelGGL(kb_sup<D>, g, bt, lds, st, L, level); break;
+    case BP_SDOWN: hipLaunchKernelGGL(kb_sdown<D>, g, b64, 0, st, L, level); break;
+    case BP_SFINAL: hipLaunchKernelGGL(kb_sfinal<D>, g, b64, 0, st, L); break;
+    case BP_FINALIZE: hipLaunchKernelGGL(kb_finalize, g, b256, 0, st, L, step); break;
+    case BP_SELECT: hipLaunchKernelGGL(kb_select, g, b256, 0, st, L); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_phase(int D, int phase, BatchLaunch L, int level, int rev,
+                              const int* step, hipStream_t st) {
+  switch (D) {
+    case 16: return launch_batch_phase_t<16>(phase, L, level, rev, step, st);
+    case 32: return launch_batch_phase_t<32>(phase, L, level, rev, step, st);
+    case 64: return launch_batch_phase_t<64>(phase, L, level, rev, step, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace akf

@@ -1,0 +1,310 @@
+// akf_layout.cpp -- host-side helpers shared by the C ABI translation units
+// (see akf_layout.h).
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+
+#include "akf_layout.h"
+
+namespace akf {
+
+
+thread_local char g_err[512] = "";
+
+akf_status fail(akf_status s, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return s;
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int pick_D(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : (d <= 64 ? 64 : 0)); }
+
+// Default scan block: enough blocks to give every CU (256) its resident teams
+// (LDS-limited: 1 team of 4 waves at D = 64, several single-wave teams below),
+// and at least 4 steps per block so that small problems do not pay for a deep
+// tree of tiny launches.
+int auto_block(int N, int D) {
+  const int teams_per_cu = D == 64 ? 1 : (D == 32 ? 4 : 8);
+  const int target = 256 * teams_per_cu;
+  int B = (N + target - 1) / target;
+  if (B < 4) B = 4;
+  if (B > N) B = N;
+  return B;
+}
+
+void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
+  Lo.N = N;
+  Lo.d = d;
+  Lo.dy = dy;
+  Lo.D = pick_D(d);
+  const int D = Lo.D;
+  Lo.B = block > 0 ? (block > N ? N : block) : auto_block(N, D);
+  Lo.nb = (N + Lo.B - 1) / Lo.B;
+  Lo.n_lvl[0] = Lo.nb;
+  Lo.L = 0;
+  while (Lo.n_lvl[Lo.L] > 1 && Lo.L < kMaxLevels) {
+    Lo.n_lvl[Lo.L + 1] = (Lo.n_lvl[Lo.L] + 1) / 2;
+    ++Lo.L;
+  }
+  const size_t dbl = sizeof(double);
+  const size_t vn = (size_t)N * d * dbl;
+  const size_t ES = (size_t)(3 * D * D + 2 * D) * dbl;
+  const size_t PS = (size_t)(D * D + D + 2) * dbl;
+  const size_t SS = (size_t)(D * D + D) * dbl;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes == 0 ? 1 : bytes);
+    return o;
+  };
+  const int nparts_diag = (int)(((int64_t)N * d + 255) / 256);
+  const int nparts_gauss = (N + 63) / 64;
+  Lo.n_part = nparts_diag > nparts_gauss ? nparts_diag : nparts_gauss;
+  if (kind == LAYOUT_STEP) {
+    Lo.u = take(vn);
+    Lo.om = take(vn);
+    Lo.Om = take(vn);
+    Lo.om2 = take(vn);
+    Lo.Om2 = take(vn);
+    Lo.xs = take(vn);
+    Lo.ell2 = take((size_t)N * dbl);
+    Lo.plhx = take((size_t)Lo.n_part * dbl);
+    Lo.plhxs = take((size_t)Lo.n_part * dbl);
+    Lo.pterms = take((size_t)Lo.n_part * dbl);
+    Lo.gG = take((size_t)d * (dy > 0 ? dy : 1) * dbl);
+    Lo.gRinv = take((size_t)(dy > 0 ? dy * dy : 1) * dbl);
+    Lo.gOmd = take((size_t)d * d * dbl);
+    Lo.gOmdinv = take((size_t)d * d * dbl);
+    Lo.gscal = take(8 * dbl);
+    Lo.accept = take(sizeof(int));
+  }
+  if (kind == LAYOUT_LGSSM) {
+    Lo.Qd = take((size_t)d * d * dbl);
+    Lo.Rd = take((size_t)dy * dy * dbl);
+    Lo.llv = take(8 * dbl);
+  }
+  if (kind == LAYOUT_STEP || kind == LAYOUT_FILTER || kind == LAYOUT_LGSSM) {
+    Lo.ell = take((size_t)N * dbl);
+    for (int l = 0; l <= Lo.L; ++l) Lo.elem[l] = take((size_t)Lo.n_lvl[l] * ES);
+    for (int l = 0; l <= Lo.L; ++l) Lo.pre[l] = take((size_t)Lo.n_lvl[l] * PS);
+  }
+  if (kind == LAYOUT_STEP || kind == LAYOUT_LGSSM) {
+    Lo.mf = take((size_t)N * D * dbl);
+    Lo.Pf = take((size_t)N * D * D * dbl);
+  }
+  if (kind == LAYOUT_STEP || kind == LAYOUT_SAMPLER || kind == LAYOUT_LGSSM ||
+      kind == LAYOUT_SMOOTH) {
+    Lo.E = take((size_t)N * D * D * dbl);
+  }
+  if (kind == LAYOUT_STEP || kind == LAYOUT_SAMPLER || kind == LAYOUT_LGSSM) {
+    Lo.U = take((size_t)N * D * dbl);
+    for (int l = 0; l <= Lo.L; ++l) Lo.sagg[l] = take((size_t)Lo.n_lvl[l] * SS);
+    for (int l = 0; l <= Lo.L; ++l) Lo.xin[l] = take((size_t)Lo.n_lvl[l] * D * dbl);
+  }
+  if (kind == LAYOUT_SMOOTH || kind == LAYOUT_LGSSM) {
+    const size_t EG = (size_t)(2 * D * D + D) * dbl;
+    const size_t ESt = (size_t)(D * D + D) * dbl;
+    Lo.Lm = take((size_t)N * D * D * dbl);
+    for (int l = 0; l <= Lo.L; ++l) Lo.eagg[l] = take((size_t)Lo.n_lvl[l] * EG);
+    for (int l = 0; l <= Lo.L; ++l) Lo.estate[l] = take((size_t)Lo.n_lvl[l] * ESt);
+  }
+  if (kind == LAYOUT_SMOOTH) Lo.g = take((size_t)N * D * dbl);
+  if (kind == LAYOUT_LGSSM) {
+    Lo.mbar = take((size_t)N * D * dbl);
+    Lo.Pbar = take((size_t)N * D * D * dbl);
+    Lo.part = take((size_t)Lo.nb * (2 * D * D + 2 * D) * dbl);
+  }
+  Lo.status = take(sizeof(int));
+  Lo.total = off;
+}
+
+
+akf_status check_model(const akf_model* m, bool need_emission) {
+  if (!m) return fail(AKF_ERR_INVALID, "model is NULL");
+  if (m->N < 1) return fail(AKF_ERR_SHAPE, "N must be >= 1 (got %d)", m->N);
+  if (m->dx < 1 || m->dx > 64) return fail(AKF_ERR_SHAPE, "dx must be in [1, 64] (got %d)", m->dx);
+  if (!m->m0 || !m->P0 || !m->F || !m->Q)
+    return fail(AKF_ERR_INVALID, "m0, P0, F and Q must be non-NULL");
+  if (!need_emission) return AKF_OK;
+  if (m->dy < 1 || m->dy > 64) return fail(AKF_ERR_SHAPE, "dy must be in [1, 64] (got %d)", m->dy);
+  switch (m->emit) {
+    case AKF_EMIT_GAUSSIAN:
+      if (!m->H || !m->R) return fail(AKF_ERR_INVALID, "Gaussian emission needs H and R");
+      break;
+    case AKF_EMIT_POISSON_LOG:
+      if (!m->site) return fail(AKF_ERR_INVALID, "Poisson emission needs site");
+      break;
+    case AKF_EMIT_STUDENT_T:
+      if (!m->site) return fail(AKF_ERR_INVALID, "Student-t emission needs site");
+      if (!(m->nu > 0.0) || !(m->scale > 0.0))
+        return fail(AKF_ERR_INVALID, "Student-t emission needs nu > 0 and scale > 0");
+      break;
+    default:
+      return fail(AKF_ERR_INVALID, "unknown emission family %d", m->emit);
+  }
+  return AKF_OK;
+}
+
+KModel to_kmodel(const akf_model* m) {
+  KModel M;
+  M.N = m->N;
+  M.d = m->dx;
+  M.dy = m->dy;
+  M.emit = m->emit;
+  M.m0 = m->m0;
+  M.P0 = m->P0;
+  M.F = m->F;
+  M.b = m->b;
+  M.Q = m->Q;
+  M.H = m->H;
+  M.R = m->R;
+  M.site = m->site;
+  M.nu = m->nu;
+  M.scale = m->scale;
+  return M;
+}
+
+akf_status prepare_device() {
+  static std::once_flag once;
+  static hipError_t err = hipSuccess;
+  std::call_once(once, [] { err = set_lds_limits_all(); });
+  if (err != hipSuccess)
+    return fail(AKF_ERR_HIP, "setting LDS limits failed: %s", hipGetErrorString(err));
+  return AKF_OK;
+}
+
+akf_status hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(AKF_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return AKF_OK;
+}
+
+void fill_tree(const Layout& Lo, void* ws, size_t elem_size, const size_t* lvl_elem,
+               const size_t* lvl_pre, int* status, int fail_bit, TreeArgs* up, TreeArgs* down) {
+  for (int l = 1; l <= Lo.L; ++l) {
+    TreeArgs u{};
+    u.src = at<double>(ws, lvl_elem[l - 1]);
+    u.dst = at<double>(ws, lvl_elem[l]);
+    u.n_src = Lo.n_lvl[l - 1];
+    u.n_dst = Lo.n_lvl[l];
+    u.status = status;
+    u.fail_bit = fail_bit;
+    up[l - 1] = u;
+    TreeArgs d{};
+    d.src = at<double>(ws, lvl_elem[l - 1]);
+    d.pre_src = at<double>(ws, lvl_pre[l]);
+    d.pre_dst = at<double>(ws, lvl_pre[l - 1]);
+    d.n_src = Lo.n_lvl[l];
+    d.n_dst = Lo.n_lvl[l - 1];
+    d.status = status;
+    d.fail_bit = fail_bit;
+    down[l - 1] = d;
+  }
+  (void)elem_size;
+}
+
+// root prefix flag (identity) of the filter tree
+double* root_flag(const Layout& Lo, void* ws) {
+  return at<double>(ws, Lo.pre[Lo.L]) + (Lo.D * Lo.D + Lo.D);
+}
+
+akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double* om,
+                      const double* Om, const double* Omd, double* mf, double* Pf, int ldm,
+                      double* ell, int* status, int fail_bit, hipStream_t st,
+                      const double* yo, const double* Ho, const double* Ro, int dyo) {
+  FilterArgs P{};
+  P.yo = yo;
+  P.Ho = Ho;
+  P.Ro = Ro;
+  P.dyo = dyo;
+  P.B = Lo.B;
+  P.om = om;
+  P.Om = Om;
+  P.Omd = Omd;
+  P.elem = at<double>(ws, Lo.elem[0]);
+  P.pre = at<double>(ws, Lo.pre[0]);
+  P.mf = mf;
+  P.Pf = Pf;
+  P.ldm = ldm;
+  P.ell = ell;
+  P.status = status;
+  P.fail_bit = fail_bit;
+  TreeArgs up[kMaxLevels], down[kMaxLevels];
+  fill_tree(Lo, ws, 0, Lo.elem, Lo.pre, status, fail_bit, up, down);
+  return hip_check(launch_filter_any(Lo.D, M, P, up, down, Lo.L, st), "filter launch");
+}
+
+akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
+                       const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
+                       hipStream_t st) {
+  SampArgs S{};
+  S.B = Lo.B;
+  S.mf = mf;
+  S.Pf = Pf;
+  S.ldm = ldm;
+  S.xi_x = xi_x;
+  S.E = at<double>(ws, Lo.E);
+  S.U = at<double>(ws, Lo.U);
+  S.agg = at<double>(ws, Lo.sagg[0]);
+  S.xin = at<double>(ws, Lo.xin[0]);
+  S.xs = xs;
+  S.status = status;
+  TreeArgs up[kMaxLevels], down[kMaxLevels];
+  fill_tree(Lo, ws, 0, Lo.sagg, Lo.xin, status, ST_FWD_NOT_PD, up, down);
+  return hip_check(launch_sampler_any(Lo.D, M, S, up, down, Lo.L, st), "sampler launch");
+}
+
+void fill_egl_tree(const Layout& Lo, void* ws, EglTree* up, EglTree* down) {
+  for (int l = 1; l <= Lo.L; ++l) {
+    EglTree u{};
+    u.src = at<double>(ws, Lo.eagg[l - 1]);
+    u.dst = at<double>(ws, Lo.eagg[l]);
+    u.n_src = Lo.n_lvl[l - 1];
+    u.n_dst = Lo.n_lvl[l];
+    up[l - 1] = u;
+    EglTree d{};
+    d.src = at<double>(ws, Lo.eagg[l - 1]);
+    d.pre_src = at<double>(ws, Lo.estate[l]);
+    d.pre_dst = at<double>(ws, Lo.estate[l - 1]);
+    d.n_src = Lo.n_lvl[l];
+    d.n_dst = Lo.n_lvl[l - 1];
+    down[l - 1] = d;
+  }
+}
+
+// Suffix (E, g, L) scan over E = ws.E, L = ws.Lm, g (nullable); writes outL/outg.
+akf_status run_egl(const Layout& Lo, void* ws, const double* g, double* outL, double* outg,
+                   int ldo, int dout, hipStream_t st) {
+  const int D = Lo.D;
+  akf_status s;
+  // the suffix state entering the last block is zero (it meets E = 0)
+  if ((s = hip_check(launch_zero(at<double>(ws, Lo.estate[Lo.L]), (int64_t)D * D + D, st),
+                     "zero launch")) != AKF_OK)
+    return s;
+  EglArgs A{};
+  A.N = Lo.N;
+  A.B = Lo.B;
+  A.E = at<double>(ws, Lo.E);
+  A.g = g;
+  A.L = at<double>(ws, Lo.Lm);
+  A.agg = at<double>(ws, Lo.eagg[0]);
+  A.state = at<double>(ws, Lo.estate[0]);
+  A.outL = outL;
+  A.outg = outg;
+  A.ldo = ldo;
+  A.dout = dout;
+  EglTree up[kMaxLevels], down[kMaxLevels];
+  fill_egl_tree(Lo, ws, up, down);
+  return hip_check(launch_egl_scan_any(D, A, up, down, Lo.L, st), "(E,g,L) scan launch");
+}
+
+
+const char* last_error() { return g_err; }
+
+}  // namespace akf

@@ -129,9 +129,11 @@ __device__ __forceinline__ void rm_axpy(RM<D>& y, double alpha, const RM<D>& x) 
   for (int q = 0; q < Cfg<D>::TPW; ++q) y.t[q] += alpha * x.t[q];
 }
 
-// 0.5 (a + a^T) through an LDS scratch matrix (team-wide; ends synchronised)
+// 0.5 (a + a^T) through an LDS scratch matrix (team-wide; starts and ends
+// with a barrier, so s may still be in use by a preceding product)
 template <int D>
 __device__ __forceinline__ void rm_symmetrise(RM<D>& a, double* s) {
+  team_sync();
   rm_stage_t<D>(a, s);
   team_sync();
   AKF_RM_FOR(D, q, r, i, j) a.t[q][r] = 0.5 * (a.t[q][r] + s[i * Cfg<D>::LD + j]);

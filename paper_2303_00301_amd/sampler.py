@@ -235,3 +235,184 @@ def rts_sample(model: DeviceModel, mf, Pf, xi, block: int = 0, ws: Optional[Work
                             wsb, int(block), _stream(dev))
     _lib.check(rc, "akf_rts_sample")
     return x, st
+
+
+def smoother(model: DeviceModel, mf, Pf, block: int = 0, ws: Optional[Workspace] = None):
+    """RTS smoothing moments from filtering moments (parallel (E, g, L) suffix scan).
+    Returns (ms [N,dx], Ps [N,dx,dx], status [1])."""
+    lib = _lib.load()
+    dev = model.device
+    N, dx = model.N, model.dx
+    _check_f64("mf", mf, (N, dx))
+    _check_f64("Pf", Pf, (N, dx, dx))
+    ms = torch.empty((N, dx), dtype=torch.float64, device=dev)
+    Ps = torch.empty((N, dx, dx), dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    ms_ = model.cstruct()
+    need = lib.akf_smoother_workspace_bytes(C.byref(ms_), block)
+    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+    rc = lib.akf_smoother(C.byref(ms_), _ptr(mf), _ptr(Pf), _ptr(ms), _ptr(Ps), _ptr(st), wsp, wsb,
+                          int(block), _stream(dev))
+    _lib.check(rc, "akf_smoother")
+    return ms, Ps, st
+
+
+class LGSSM:
+    """Linear-Gaussian model with theta = (F, log diag Q, H, log diag R) on the device."""
+
+    def __init__(self, m0, P0, y, device=None):
+        dev = _dev(device)
+        self.m0 = _t(m0, dev)
+        self.P0 = _t(P0, dev)
+        self.y = _t(y, dev)
+        self.N, self.dy = self.y.shape
+        self.dx = self.m0.shape[0]
+        self.device = dev
+
+    def cstruct(self, F, logq, H, logr) -> _lib.AkfLgssm:
+        for name, t, shp in (("F", F, (self.dx, self.dx)), ("logq", logq, (self.dx,)),
+                             ("H", H, (self.dy, self.dx)), ("logr", logr, (self.dy,))):
+            _check_f64(name, t, shp)
+        s = _lib.AkfLgssm()
+        s.N, s.dx, s.dy = self.N, self.dx, self.dy
+        s.m0, s.P0 = self.m0.data_ptr(), self.P0.data_ptr()
+        s.F, s.logq, s.H, s.logr = F.data_ptr(), logq.data_ptr(), H.data_ptr(), logr.data_ptr()
+        s.y = self.y.data_ptr()
+        return s
+
+
+def lgssm_loglik(model: LGSSM, F, logq, H, logr, block: int = 0,
+                 ws: Optional[Workspace] = None, ell: bool = False):
+    """log p(y | theta).  Returns (ll [1], ell [N] | None, status [1], ws).  The
+    returned workspace holds the checkpoint used by lgssm_loglik_grad."""
+    lib = _lib.load()
+    dev = model.device
+    s = model.cstruct(F, logq, H, logr)
+    need = lib.akf_lgssm_workspace_bytes(C.byref(s), block)
+    ws = ws or Workspace(dev)
+    wsp, wsb = ws.ptr_bytes(need)
+    ll = torch.empty(1, dtype=torch.float64, device=dev)
+    el = torch.empty(model.N, dtype=torch.float64, device=dev) if ell else None
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    rc = lib.akf_lgssm_loglik(C.byref(s), _ptr(ll), _ptr(el), _ptr(st), wsp, wsb, int(block),
+                              _stream(dev))
+    _lib.check(rc, "akf_lgssm_loglik")
+    return ll, el, st, ws
+
+
+def lgssm_loglik_grad(model: LGSSM, F, logq, H, logr, ws: Workspace, ll_bar=None,
+                      block: int = 0):
+    """Adjoint of lgssm_loglik (same workspace, called after it).  Returns
+    (dF, dlogq, dH, dlogr, status)."""
+    lib = _lib.load()
+    dev = model.device
+    s = model.cstruct(F, logq, H, logr)
+    need = lib.akf_lgssm_workspace_bytes(C.byref(s), block)
+    wsp, wsb = ws.ptr_bytes(need)
+    dF = torch.empty_like(F)
+    dq = torch.empty_like(logq)
+    dH = torch.empty_like(H)
+    dr = torch.empty_like(logr)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    if ll_bar is not None:
+        _check_f64("ll_bar", ll_bar, (1,))
+    rc = lib.akf_lgssm_loglik_grad(C.byref(s), _ptr(ll_bar), _ptr(dF), _ptr(dq), _ptr(dH),
+                                   _ptr(dr), _ptr(st), wsp, wsb, int(block), _stream(dev))
+    _lib.check(rc, "akf_lgssm_loglik_grad")
+    return dF, dq, dH, dr, st
+
+
+class KalmanLogLik(torch.autograd.Function):
+    """log p(y | F, log diag Q, H, log diag R) with a hand-written reverse-mode
+    adjoint.  forward keeps the workspace (the filtering-moment checkpoint) on
+    ctx; backward runs the adjoint scans on it."""
+
+    @staticmethod
+    def forward(ctx, F, logq, H, logr, model: LGSSM, block: int = 0):
+        F, logq, H, logr = (a.detach().contiguous() for a in (F, logq, H, logr))
+        ll, _, st, ws = lgssm_loglik(model, F, logq, H, logr, block=block)
+        ctx.model, ctx.ws, ctx.block = model, ws, block
+        ctx.save_for_backward(F, logq, H, logr)
+        return ll.reshape(())
+
+    @staticmethod
+    def backward(ctx, g):
+        F, logq, H, logr = ctx.saved_tensors
+        gb = g.reshape(1).to(torch.float64).contiguous()
+        dF, dq, dH, dr, _ = lgssm_loglik_grad(ctx.model, F, logq, H, logr, ctx.ws, ll_bar=gb,
+                                              block=ctx.block)
+        return dF, dq, dH, dr, None, None
+
+
+class BatchPlan:
+    """Many independent chains advanced together by batched persistent kernels
+    (include/akf.h, akf_batch_*).  `chains` is a list of dicts with keys model
+    (DeviceModel), y, x (updated in place), xi [n_steps,2,N,dx], unif [n_steps],
+    delta, order and optional per-step outputs log_ratio, accepted, logZ_fwd,
+    logZ_rev, status (device tensors).  The plan keeps references to every
+    tensor it points at."""
+
+    def __init__(self, chains, n_steps: int, block: int = 0, tune_cache: Optional[str] = None,
+                 device=None):
+        lib = _lib.load()
+        self.device = _dev(device)
+        self.stream = torch.cuda.Stream(device=self.device)  # default priority
+        self.chains = chains
+        self.n_steps = int(n_steps)
+        arr = (_lib.AkfChain * len(chains))()
+        for k, c in enumerate(chains):
+            m = c["model"]
+            N, dx = m.N, m.dx
+            _check_f64("y", c["y"], (N, m.dy))
+            _check_f64("x", c["x"], (N, dx))
+            _check_f64("xi", c["xi"], (n_steps, 2, N, dx))
+            _check_f64("unif", c["unif"], (n_steps,))
+            a = arr[k]
+            a.model = m.cstruct()
+            a.y, a.x, a.xi, a.unif = (c["y"].data_ptr(), c["x"].data_ptr(), c["xi"].data_ptr(),
+                                      c["unif"].data_ptr())
+            a.delta, a.order = float(c["delta"]), int(c["order"])
+            for f in ("log_ratio", "accepted", "logZ_fwd", "logZ_rev", "status"):
+                t = c.get(f)
+                setattr(a, f, t.data_ptr() if t is not None else None)
+        self._arr = arr
+        self.handle = C.c_void_p()
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        rc = lib.akf_batch_plan_create(C.byref(self.handle), len(chains), arr, self.n_steps,
+                                       int(block), tune_cache.encode() if tune_cache else None,
+                                       C.c_void_p(self.stream.cuda_stream))
+        _lib.check(rc, "akf_batch_plan_create")
+        cur.wait_stream(self.stream)
+
+    def run(self, use_graph: bool = True):
+        lib = _lib.load()
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        rc = lib.akf_batch_mh_run(self.handle, 1 if use_graph else 0,
+                                  C.c_void_p(self.stream.cuda_stream))
+        _lib.check(rc, "akf_batch_mh_run")
+        cur.wait_stream(self.stream)
+
+    def info(self) -> dict:
+        lib = _lib.load()
+        n = C.c_int32()
+        D = (C.c_int32 * 4)()
+        B = (C.c_int32 * 4)()
+        nc = (C.c_int32 * 4)()
+        nbytes = C.c_size_t()
+        _lib.check(lib.akf_batch_plan_info(self.handle, 4, C.byref(n), D, B, nc, C.byref(nbytes)),
+                   "akf_batch_plan_info")
+        return dict(classes=[dict(D=D[i], block=B[i], chains=nc[i]) for i in range(n.value)],
+                    device_bytes=nbytes.value)
+
+    def close(self):
+        if self.handle:
+            _lib.load().akf_batch_plan_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,147 @@
+"""GPU parity of the RTS smoother, the LGSSM log-likelihood and its reverse-mode
+adjoint (MI355X only).
+
+The gradient reference is the oracle's Fisher-identity score (RTS smoother +
+complete-data statistics; shares nothing with the adjoint scans) and central
+finite differences of the oracle's FP64 log-likelihood.  The stated bar is a
+norm-wise relative error <= 1e-5 per parameter block; the FP64 adjoint is held
+to 1e-7 against the Fisher score.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2303_00301_amd import workloads as W  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 1e-7      # FP64 adjoint vs FP64 Fisher score (stated bar: 1e-5)
+FD_TOL = 1e-5        # vs central differences with h = 1e-4 (truncation ~ h^2)
+
+
+@pytest.fixture(scope="module")
+def S():
+    if not torch.cuda.is_available():
+        pytest.skip("no ROCm device")
+    from paper_2303_00301_amd import sampler
+    return sampler
+
+
+def dev():
+    return torch.device("cuda", 0)
+
+
+def T(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev())
+
+
+def N_(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("N,d,block", [(1, 2, 0), (10, 3, 3), (200, 8, 0), (77, 20, 6),
+                                       (130, 33, 0), (256, 64, 0), (100, 64, 7)])
+def test_smoother_matches_oracle(S, N, d, block):
+    rng = np.random.default_rng(3000 + N + d)
+    G = rng.standard_normal((d, d))
+    F = 0.9 * G / np.max(np.abs(np.linalg.eigvals(G)))
+    A = rng.standard_normal((d, d))
+    Q = A @ A.T / d + 0.1 * np.eye(d)
+    m0, P0 = rng.standard_normal(d) * 0.2, np.eye(d)
+    b = 0.1 * rng.standard_normal(d)
+    om = rng.standard_normal((N, d))
+    Om = rng.uniform(0.1, 1.0, size=(N, d))
+    ref = oracle.kf(m0, P0, F, Q, np.eye(d), np.stack([np.diag(o) for o in Om]), om, b=b,
+                    R_per_t=True)
+    ms, Ps, _, _ = oracle.rts_smooth(F, ref["mf"], ref["Pf"], ref["mp"], ref["Pp"])
+    M = S.DeviceModel.from_arrays(N, m0, P0, F, Q, 1, b=b, device=dev())
+    gms, gPs, st = S.smoother(M, T(ref["mf"]), T(ref["Pf"]), block=block)
+    torch.cuda.synchronize()
+    assert int(N_(st)[0]) == 0
+    scale = np.sqrt(np.einsum("tii->ti", Ps))
+    assert (np.abs(N_(gms) - ms) / scale).max() < 1e-8
+    assert (np.linalg.norm(N_(gPs) - Ps, axis=(1, 2)) / np.linalg.norm(Ps, axis=(1, 2))).max() < 1e-8
+
+
+def _theta_dev(t0):
+    return T(t0.F), T(t0.logq), T(t0.H), T(t0.logr)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+@pytest.mark.parametrize("N,dx,dy,block", [(1, 3, 2, 0), (5, 2, 1, 2), (64, 4, 3, 0),
+                                           (300, 6, 2, 7), (257, 16, 8, 0), (500, 20, 32, 0),
+                                           (1024, 32, 16, 0)])
+def test_lgssm_loglik_and_adjoint_match_oracle(S, N, dx, dy, block):
+    pw = W.lgssm_params(N=N, dx=dx, dy=dy, seed=10 + N)
+    t0 = pw.theta0
+    ll_ref, dF, dq, dH, dr = oracle.fisher_score(pw.m0, pw.P0, t0.F, t0.logq, t0.H, t0.logr, pw.y)
+    model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev())
+    th = _theta_dev(t0)
+    ll, _, st, ws = S.lgssm_loglik(model, *th, block=block)
+    g = S.lgssm_loglik_grad(model, *th, ws, block=block)
+    torch.cuda.synchronize()
+    assert int(N_(st)[0]) == 0 and int(N_(g[4])[0]) == 0
+    assert abs(float(N_(ll)[0]) - ll_ref) <= 1e-9 * max(1.0, abs(ll_ref))
+    for got, ref in zip(g[:4], (dF, dq, dH, dr)):
+        assert _rel(N_(got), ref) < GRAD_TOL, _rel(N_(got), ref)
+
+
+def test_adjoint_matches_central_differences(S):
+    """16 random directions, FD of the oracle's FP64 log-likelihood, h = 1e-4."""
+    pw = W.lgssm_params(N=400, dx=8, dy=5, seed=77)
+    t0 = pw.theta0
+    model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev())
+    th = _theta_dev(t0)
+    ll, _, _, ws = S.lgssm_loglik(model, *th)
+    g = S.lgssm_loglik_grad(model, *th, ws)
+    gv = np.concatenate([N_(a).ravel() for a in g[:4]])
+    v0 = t0.flat()
+    dx, dy = 8, 5
+
+    def f(v):
+        i = 0
+        F = v[i:i + dx * dx].reshape(dx, dx); i += dx * dx
+        lq = v[i:i + dx]; i += dx
+        H = v[i:i + dy * dx].reshape(dy, dx); i += dy * dx
+        lr = v[i:i + dy]
+        return oracle.lgssm_loglik(pw.m0, pw.P0, F, lq, H, lr, pw.y)
+
+    rng = np.random.default_rng(0)
+    for _ in range(16):
+        u = rng.standard_normal(v0.size)
+        u /= np.linalg.norm(u)
+        fd = (f(v0 + 1e-4 * u) - f(v0 - 1e-4 * u)) / 2e-4
+        assert abs(fd - gv @ u) <= FD_TOL * max(1.0, np.linalg.norm(gv))
+
+
+def test_adjoint_full_size_gradient_workload(S):
+    """d_x = 32, d_y = 16, T = 16384: GPU adjoint vs the oracle's Fisher score."""
+    pw = W.lgssm_params()
+    t0 = pw.theta0
+    ll_ref, dF, dq, dH, dr = oracle.fisher_score(pw.m0, pw.P0, t0.F, t0.logq, t0.H, t0.logr, pw.y)
+    model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev())
+    th = _theta_dev(t0)
+    ll, _, st, ws = S.lgssm_loglik(model, *th)
+    g = S.lgssm_loglik_grad(model, *th, ws)
+    torch.cuda.synchronize()
+    assert abs(float(N_(ll)[0]) - ll_ref) <= 1e-9 * abs(ll_ref)
+    for got, ref in zip(g[:4], (dF, dq, dH, dr)):
+        assert _rel(N_(got), ref) < GRAD_TOL
+
+
+def test_autograd_function(S):
+    pw = W.lgssm_params(N=128, dx=6, dy=3, seed=5)
+    t0 = pw.theta0
+    model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev())
+    params = [T(a).requires_grad_() for a in (t0.F, t0.logq, t0.H, t0.logr)]
+    ll = S.KalmanLogLik.apply(*params, model, 0)
+    (2.5 * ll).backward()
+    ll_ref, dF, dq, dH, dr = oracle.fisher_score(pw.m0, pw.P0, t0.F, t0.logq, t0.H, t0.logr, pw.y)
+    assert abs(ll.item() - ll_ref) < 1e-9 * abs(ll_ref)
+    for p, ref in zip(params, (dF, dq, dH, dr)):
+        assert _rel(N_(p.grad), 2.5 * ref) < GRAD_TOL
