@@ -75,6 +75,105 @@ def cpu_baseline(w, n_steps: int) -> dict:
             "seconds": dt}
 
 
+def bench_batched(torch, S, W, K: int, dev) -> dict:
+    """512 ragged chains (N ~ U{128..8192}, d ~ U{4,16,32}, Poisson log link):
+    K steps as one batched plan (hipGraph replay) vs 512 sequential plain runs
+    of the same K steps, same normals, same scan blocks."""
+    import os
+    t0 = time.perf_counter()
+    ws = W.ragged_poisson_batch()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(104)
+    chains = []
+    for w in ws:
+        y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+        x0 = torch.log(y + 0.5).contiguous()
+        chains.append(dict(model=S.DeviceModel.from_workload(w, device=dev), y=y, x=x0.clone(),
+                           x0=x0, delta=w.delta, order=2,
+                           xi=torch.randn((K, 2, w.N, w.dx), dtype=torch.float64, device=dev,
+                                          generator=gen),
+                           unif=torch.rand((K,), dtype=torch.float64, device=dev,
+                                           generator=gen).clamp_(min=1e-300),
+                           accepted=torch.empty(K, dtype=torch.int32, device=dev)))
+    t_setup = time.perf_counter() - t0
+    cache = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gpurun_out",
+                         "batch_tune.jsonl")
+    os.makedirs(os.path.dirname(cache), exist_ok=True)
+    t0 = time.perf_counter()
+    plan = S.BatchPlan(chains, K, block=0, tune_cache=cache, device=dev)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    info = plan.info()
+    plan.run(use_graph=True)  # warm-up: captures the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(plan.stream)
+    plan.run(use_graph=True)
+    e1.record(plan.stream)
+    torch.cuda.synchronize()
+    ms_batched = e0.elapsed_time(e1)
+    acc = float(torch.stack([c["accepted"].float().mean() for c in chains]).mean().item())
+    # plain per-chain launches, same inputs and blocks
+    blk = {c["D"]: c["block"] for c in info["classes"]}
+    wsp = S.Workspace(dev)
+    xs = [c["x0"].clone() for c in chains]
+    for c, x in zip(chains, xs):  # warm-up (workspace growth, code load)
+        S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"][:1], c["unif"][:1],
+                 block=blk[16 if c["model"].dx <= 16 else 32], ws=wsp, outputs=False)
+    xs = [c["x0"].clone() for c in chains]
+    torch.cuda.synchronize()
+    e0.record()
+    for c, x in zip(chains, xs):
+        S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"],
+                 block=blk[16 if c["model"].dx <= 16 else 32], ws=wsp, outputs=False)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1)
+    n_ch = len(chains)
+    plan.close()
+    return {"workload": "512 chains, N ~ U{128..8192}, d_x ~ U{4,16,32}, random stable F, "
+                        "Q = 0.1 I, Poisson log link, order 2",
+            "steps": K, "chains": n_ch, "time_steps": int(sum(w.N for w in ws)),
+            "batched_ms_per_step": ms_batched / K, "plain_ms_per_step": ms_plain / K,
+            "batched_chain_steps_per_s": n_ch * K / (ms_batched * 1e-3),
+            "plain_chain_steps_per_s": n_ch * K / (ms_plain * 1e-3),
+            "speedup_vs_plain": ms_plain / ms_batched,
+            "batched_time_steps_per_s": sum(w.N for w in ws) * K / (ms_batched * 1e-3),
+            "acceptance": acc, "classes": info["classes"], "plan_s": t_plan,
+            "setup_s": t_setup}
+
+
+def bench_adjoint(torch, S, W, reps: int, dev) -> dict:
+    """log p(y | theta) and its reverse-mode adjoint, d_x = 32, d_y = 16, T = 16384."""
+    pw = W.lgssm_params()
+    model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev)
+    th = [torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+          for a in (pw.theta0.F, pw.theta0.logq, pw.theta0.H, pw.theta0.logr)]
+    ws = S.Workspace(dev)
+    S.lgssm_loglik(model, *th, ws=ws)
+    S.lgssm_loglik_grad(model, *th, ws)
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tf, tb = [], []
+    for _ in range(reps):
+        e[0].record()
+        S.lgssm_loglik(model, *th, ws=ws)
+        e[1].record()
+        S.lgssm_loglik_grad(model, *th, ws)
+        e[2].record()
+        torch.cuda.synchronize()
+        tf.append(e[0].elapsed_time(e[1]))
+        tb.append(e[1].elapsed_time(e[2]))
+    tf.sort()
+    tb.sort()
+    mf, mb = tf[len(tf) // 2], tb[len(tb) // 2]
+    return {"workload": "LGSSM d_x=32, d_y=16, T=16384, theta = (F, log diag Q, H, log diag R), "
+                        "1584 parameters",
+            "forward_ms": mf, "adjoint_ms": mb,
+            "adjoint_time_steps_per_s": pw.N / ((mf + mb) * 1e-3),
+            "adjoint_over_forward": mb / mf}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +183,9 @@ def main() -> int:
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default="filter_fold")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -176,6 +278,10 @@ def main() -> int:
         "rejected_by_status": status_bad,
         "roofline": roof,
     }
+    if not args.no_batched:
+        res["batched"] = bench_batched(torch, S, W, args.batched_steps, dev)
+    if not args.no_adjoint:
+        res["adjoint"] = bench_adjoint(torch, S, W, 5, dev)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(res), flush=True)

@@ -75,12 +75,16 @@ class Workload:
 
 
 def _simulate(rng, N, m0, P0, F, Q, b=None):
+    """x_0 ~ N(m0, P0), x_t = F x_{t-1} + b + N(0, Q): all noise drawn at once."""
     d = len(m0)
-    Lq = np.linalg.cholesky(Q)
-    x = np.zeros((N, d))
-    x[0] = m0 + np.linalg.cholesky(P0) @ rng.standard_normal(d)
+    z = rng.standard_normal((N, d))
+    e = z @ np.linalg.cholesky(Q).T
+    if b is not None:
+        e = e + b
+    x = np.empty((N, d))
+    x[0] = m0 + np.linalg.cholesky(P0) @ z[0]
     for t in range(1, N):
-        x[t] = F @ x[t - 1] + (0 if b is None else b) + Lq @ rng.standard_normal(d)
+        x[t] = F @ x[t - 1] + e[t]
     return x
 
 
