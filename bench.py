@@ -47,6 +47,40 @@ def fold_flops_per_launch(N: int, d: int, B: int) -> float:
     return tot
 
 
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "filter_fold_latent_field_traffic.txt")
+KERNEL_SOURCES = ("paper_2303_00301_amd/csrc/akf_team.hpp",
+                  "paper_2303_00301_amd/csrc/akf_internal.h",
+                  "paper_2303_00301_amd/csrc/akf_kernels.hip")
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    root = os.path.dirname(os.path.abspath(__file__))
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(root, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(block: int):
+    """HBM bytes per fold launch from the committed FETCH_SIZE / WRITE_SIZE
+    counter summary, or None when there is none, it was taken at another scan
+    block size, or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256") != kernel_source_digest():
+        return None
+    if int(kv.get("scan_block", "-1")) != block:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def auto_block(N: int, d: int) -> int:
     D = 16 if d <= 16 else (32 if d <= 32 else 64)
     teams = 1 if D == 64 else (4 if D == 32 else 8)
@@ -186,6 +220,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
+                         "reference for the HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -251,7 +288,8 @@ def main() -> int:
             flops = float("nan")
         achieved = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": measured_traffic(B) if args.roofline_kernel == "filter_fold" else None,
                 "kernel": f"k_filter_fold<64> ({args.roofline_kernel})",
                 "avg_launch_ms": avg_ms, "launches": n_l.value,
                 "flops_per_launch": flops}
@@ -284,6 +322,15 @@ def main() -> int:
         res["adjoint"] = bench_adjoint(torch, S, W, 5, dev)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        res["copy_calibration_bytes"] = n * 8
     print(json.dumps(res), flush=True)
     return 0
 

@@ -236,7 +236,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   double* vm = B3 + C::MAT;
   double* vmp = vm + D;
   double* vg = vmp + D;
-  double* scal = vg + D;
+  double* sbuf = vg + D;  // 4 D
   const int t = blockIdx.x, tid = threadIdx.x, d = M.d;
   RM<D> Pf, R1, R2;
   rm_load<D>(Pf, S.Pf + (int64_t)t * S.ldm * S.ldm, S.ldm, d);
@@ -253,34 +253,27 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   lds_load_user<D>(sF, M.F, d, d);
   rm_stage<D>(Pf, B1);
   team_sync();
-  gemm<D, false, false, false>(R1, sF, B1);  // F P^f
+  gemm<D, false, false, false>(R1, sF, B1);  // G = F P^f
   team_sync();
   rm_stage<D>(R1, B1);
   team_sync();
-  gemm<D, false, true, false>(R2, B1, sF);  // F P^f F'
+  gemm<D, false, true, false>(R2, B1, sF);  // G F'
   rm_add_load<D>(R2, M.Q, d, d);
   matvec<D, false>(vmp, sF, vm);
+  if (tid < d && M.b) vmp[tid] += M.b[tid];
+  ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // (P^p)^{-1}
   rm_stage<D>(R2, B2);
   team_sync();
-  if (tid < d && M.b) vmp[tid] += M.b[tid];
-  ok = chol_inv<D, true>(B2, B3, d, &ld, scal) && ok;
-  gemm<D, false, false, false>(R1, B3, B1);  // W = L_p^{-1} F P^f
+  gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
+  rm_store<D>(R1, S.E + (int64_t)t * D * D, D, D);
+  rm_stage<D>(R1, B3);
   team_sync();
-  rm_stage<D>(R1, B2);
-  team_sync();
-  gemm<D, true, false, false>(R2, B2, B3);  // E
-  rm_store<D>(R2, S.E + (int64_t)t * D * D, D, D);
-  gemm<D, true, false, false>(R1, B2, B2);  // W'W
-  rm_axpy<D>(R1, -1.0, Pf);
-  rm_axpy<D>(R1, -2.0, R1);  // L = P^f - W'W
-  team_sync();
-  rm_stage<D>(R2, B1);
-  team_sync();
-  matvec<D, false>(vg, B1, vmp);
-  team_sync();
+  gemm<D, false, false, false>(R2, B3, B1);  // E G
+  rm_rsub<D>(R2, Pf);                        // L = P^f - E G
+  matvec<D, false>(vg, B3, vmp);
   if (tid < D) S.g[(int64_t)t * D + tid] = vm[tid] - vg[tid];
-  rm_symmetrise<D>(R1, B3);
-  rm_store<D>(R1, S.L + (int64_t)t * D * D, D, D);
+  rm_symmetrise<D>(R2, B2);
+  rm_store<D>(R2, S.L + (int64_t)t * D * D, D, D);
   if (!ok && tid == 0) flag_status2(S.status, ST_FWD_NOT_PD);
 }
 
@@ -312,13 +305,14 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ a, int n
 }
 
 // Recompute the filter quantities of step t from the checkpoint:
-// Pp, mp (registers / LDS), B_HP <- H Pp, B_Li <- L_S^{-1}, B_Si <- S^{-1},
-// vw <- w = S^{-1} v, vv <- v.  Team-wide; ends synchronised.
+// Pp, mp (registers / LDS), B_HP <- H Pp, B_Si <- S^{-1} (Gauss-Jordan in
+// registers), vw <- w = S^{-1} v, vv <- v.  sbuf: 4 D doubles.  Team-wide;
+// ends synchronised.
 template <int D>
 __device__ void adj_step_quantities(const KModel& M, const LgArgs& G, int t, const double* sF,
-                                    const double* sH, double* B_HP, double* B_Li, double* B_Si,
-                                    double* Btmp, RM<D>& Pp, double* vmp, double* vv, double* vw,
-                                    double* scal, bool& ok) {
+                                    const double* sH, double* B_HP, double* B_Si, double* Btmp,
+                                    RM<D>& Pp, double* vmp, double* vv, double* vw, double* sbuf,
+                                    bool& ok) {
   const int tid = threadIdx.x, d = G.dx, p = G.dy;
   RM<D> R1;
   if (t == 0) {
@@ -344,17 +338,12 @@ __device__ void adj_step_quantities(const KModel& M, const LgArgs& G, int t, con
   team_sync();
   rm_stage<D>(R1, B_HP);
   team_sync();
-  gemm<D, false, true, false>(R1, B_HP, sH);  // H Pp H'
+  gemm<D, false, true, false>(R1, B_HP, sH);  // S = H Pp H' + R
   rm_add_load<D>(R1, G.R, p, p);
-  rm_stage<D>(R1, Btmp);
   matvec<D, false>(vv, sH, vmp);
-  team_sync();
   if (tid < D) vv[tid] = (tid < p) ? G.y[(int64_t)t * p + tid] - vv[tid] : 0.0;
   double ld;
-  ok = chol_inv<D, true>(Btmp, B_Li, p, &ld, scal) && ok;  // B_Li = L^{-1}
-  gemm<D, true, false, false>(R1, B_Li, B_Li);            // S^{-1} = L^{-T} L^{-1}
-  // zero the padded block of S^{-1} (L^{-1} carries the identity there)
-  AKF_RM_FOR(D, q, r, i, j) if (i >= p || j >= p) R1.t[q][r] = 0.0;
+  ok = spd_inv<D>(R1, p, sbuf, &ld) && ok;  // S^{-1} (zero outside p x p)
   rm_stage<D>(R1, B_Si);
   team_sync();
   matvec<D, false>(vw, B_Si, vv);  // w = S^{-1} v
@@ -376,14 +365,14 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
   double* vmp = Bt + C::MAT;
   double* vv = vmp + D;
   double* vw = vv + D;
-  double* scal = vw + D;
+  double* sbuf = vw + D;  // 4 D
   const int t = blockIdx.x, tid = threadIdx.x, d = G.dx, p = G.dy;
   lds_load_user<D>(sF, M.F, d, d);
   lds_load_user<D>(sH, G.H, p, d);
   team_sync();
   bool ok = true;
   RM<D> Pp, R1, R2;
-  adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Li, B_Si, Bt, Pp, vmp, vv, vw, scal, ok);
+  adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, sbuf, ok);
   // h = H' w
   if (tid < D) {
     double s = 0.0;
@@ -419,8 +408,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
     gemm<D, false, false, false>(R1, Bt, sH);  // F K H
     RM<D> Fm;
     rm_load<D>(Fm, M.F, d, d);
-    rm_axpy<D>(R1, -1.0, Fm);
-    rm_axpy<D>(R1, -2.0, R1);  // Phi = F - F K H
+    rm_rsub<D>(R1, Fm);  // Phi = F - F K H
     rm_store_t<D>(R1, G.E + (int64_t)t * D * D, D, D);
   }
   if (!ok && tid == 0) flag_status2(G.status, ST_FWD_NOT_PD);
@@ -462,7 +450,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
   double* vmb = vpf + D;   // mbar_{t+1}
   double* vq = vmb + D;    // accumulated dL/dQ_ii
   double* vr = vq + D;     // accumulated dL/dR_jj
-  double* scal = vr + D;
+  double* sbuf = vr + D;   // 4 D
   const int blk = blockIdx.x, tid = threadIdx.x, d = G.dx, p = G.dy, N = M.N;
   const int s0 = blk * G.B, s1 = min(N, s0 + G.B);
   lds_load_user<D>(sF, M.F, d, d);
@@ -477,7 +465,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
   rm_zero<D>(gH);
   bool ok = true;
   for (int t = s0; t < s1; ++t) {
-    adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Li, B_Si, Bt, Pp, vmp, vv, vw, scal, ok);
+    adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, sbuf, ok);
     const bool last = (t == N - 1);
     rm_load<D>(Pf, G.Pf + (int64_t)t * D * D, D, D);
     if (tid < D) {
@@ -633,13 +621,13 @@ hipError_t launch_egl_scan_any(int D, EglArgs A, EglTree* up, EglTree* down, int
 hipError_t launch_smooth_build_any(int D, const KModel& M, SmoothArgs S, hipStream_t st) {
   switch (D) {
     case 16:
-      hipLaunchKernelGGL(k_smooth_build<16>, dim3(M.N), dim3(64), lds_bytes_mats<16>(4, 3), st, M, S);
+      hipLaunchKernelGGL(k_smooth_build<16>, dim3(M.N), dim3(64), lds_bytes_mats<16>(4, 7), st, M, S);
       break;
     case 32:
-      hipLaunchKernelGGL(k_smooth_build<32>, dim3(M.N), dim3(64), lds_bytes_mats<32>(4, 3), st, M, S);
+      hipLaunchKernelGGL(k_smooth_build<32>, dim3(M.N), dim3(64), lds_bytes_mats<32>(4, 7), st, M, S);
       break;
     case 64:
-      hipLaunchKernelGGL(k_smooth_build<64>, dim3(M.N), dim3(256), lds_bytes_mats<64>(4, 3), st, M,
+      hipLaunchKernelGGL(k_smooth_build<64>, dim3(M.N), dim3(256), lds_bytes_mats<64>(4, 7), st, M,
                          S);
       break;
     default:
@@ -661,14 +649,14 @@ hipError_t launch_sum(const double* a, int n, double* out, hipStream_t st) {
 
 template <int D>
 hipError_t launch_adj_build_t(const KModel& M, LgArgs G, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_mats<D>(6, 4), st, M, G);
+  hipLaunchKernelGGL(k_adj_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_mats<D>(6, 7), st, M, G);
   return hipGetLastError();
 }
 template <int D>
 hipError_t launch_adj_finish_t(const KModel& M, LgArgs G, int nblk, const double* ll_bar,
                                hipStream_t st) {
   const int64_t n = (int64_t)M.N * D * D;
-  hipLaunchKernelGGL(k_adj_grad<D>, dim3(nblk), dim3(Cfg<D>::NT), lds_bytes_mats<D>(7, 12), st, M,
+  hipLaunchKernelGGL(k_adj_grad<D>, dim3(nblk), dim3(Cfg<D>::NT), lds_bytes_mats<D>(7, 15), st, M,
                      G);
   const int tot = G.dx * G.dx + G.dx + G.dy * G.dx + G.dy;
   hipLaunchKernelGGL(k_adj_reduce<D>, dim3((tot + 255) / 256), dim3(256), 0, st, G, nblk, ll_bar);

@@ -422,43 +422,21 @@ __device__ __forceinline__ void lds_load_rect(double* s, const double* __restric
   }
 }
 
-// General observation model at step t: B1 <- H Pp, S = H Pp H' + R -> B2 (then
-// L), B3 <- L^{-1}, vw <- y_t - H mu.  Team-wide; ends synchronised.
-template <int D>
-__device__ __forceinline__ void obs_general(double* B1, double* B2, double* B3, const double* sH,
-                                            const RM<D>& Pp, const double* vmu, double* vw,
-                                            const FilterArgs& P, int t, double* scal,
-                                            double* logdet, bool& ok) {
-  const int tid = threadIdx.x;
-  RM<D> R1;
-  rm_stage<D>(Pp, B1);
-  team_sync();
-  gemm<D, false, false, false>(R1, sH, B1);  // H Pp
-  team_sync();
-  rm_stage<D>(R1, B1);
-  team_sync();
-  gemm<D, false, true, false>(R1, B1, sH);  // H Pp H'
-  rm_add_load<D>(R1, P.Ro, P.dyo, P.dyo);
-  rm_stage<D>(R1, B2);
-  matvec<D, false>(vw, sH, vmu);
-  team_sync();
-  if (tid < D) vw[tid] = (tid < P.dyo) ? P.yo[(int64_t)t * P.dyo + tid] - vw[tid] : 0.0;
-  ok = chol_inv<D, true>(B2, B3, P.dyo, logdet, scal) && ok;
-}
-
 // ---------------------------------------------------------------------------
 // Filter, phase 1: fold the elements of one block.
 // State (A, b, C, eta, J) represents p(x_t | omega_{s:t}, x_{s-1}) =
 // N(A x_{s-1} + b, C) and p(omega_{s:t} | x_{s-1}) ~ exp(-x'Jx/2 + eta'x).
 // Appending step t (predict through the dynamics, condition on omega_t):
-//   Pp = F C F' + Q, T = F A, mu = F b + bias,  S = Pp + Omega_t = L L'
-//   X = L^{-1} Pp, Y = L^{-1} T, r = L^{-1}(omega_t - mu)
-//   C <- Pp - X'X,  A <- T - X'Y,  J <- J + Y'Y,  b <- mu + X'r,  eta <- eta + Y'r
+//   Pp = F C F' + Q, T = F A, mu = F b + bias,  S = Pp + Omega_t (inverted in
+//   registers by Gauss-Jordan), w = omega_t - mu
+//   C <- Pp - Pp S^{-1} Pp,  A <- T - Pp S^{-1} T,  J <- J + T' S^{-1} T,
+//   b <- mu + Pp S^{-1} w,   eta <- eta + T' S^{-1} w
 // which is the element combine of App. A with the raw element of step t
 // written in terms of F, Q and Omega_t.  The block containing t = 0 starts
 // from the prior (A = 0 throughout).  Output element layout: ElemLayout.
 // GH (general observation y_t = H x_t + N(0, R), D <= 32): S = H Pp H' + R,
-// X = L^{-1} H Pp, Y = L^{-1} H T, r = L^{-1}(y_t - H mu).
+// Pp S^{-1} Pp -> (H Pp)' S^{-1} (H Pp), T' S^{-1} T -> (H T)' S^{-1} (H T),
+// w = y_t - H mu.
 // ---------------------------------------------------------------------------
 template <int D, bool GH>
 __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterArgs& P, int item) {
@@ -469,23 +447,24 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
   double* B1 = sF + C::MAT;
   double* B2 = B1 + C::MAT;
   double* B3 = B2 + C::MAT;
-  double* sH = B3 + C::MAT;   // GH only
-  double* vb = sH + (GH ? C::MAT : 0);   // b
-  double* veta = vb + D;      // eta
-  double* vmu = veta + D;     // mu
-  double* vw = vmu + D;       // omega - mu
-  double* vr = vw + D;        // r
-  double* scal = vr + D;      // 8 doubles
+  double* sH = B3 + C::MAT;                // GH only
+  double* vb = sH + (GH ? C::MAT : 0);     // b
+  double* veta = vb + D;                   // eta
+  double* vmu = veta + D;                  // mu
+  double* vw = vmu + D;                    // omega - mu  (GH: y - H mu)
+  double* vs = vw + D;                     // S^{-1} w
+  double* sbuf = vs + D;                   // 4 D: pivot broadcast
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   const bool first = (s0 == 0);
+  const int dobs = GH ? P.dyo : d;
   lds_load_mat<D>(sF, M.F, d);
   if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
   if (tid < D) {
     vb[tid] = 0.0;
     veta[tid] = 0.0;
   }
-  RM<D> A, Cc, J, T, X, Y;
+  RM<D> A, Cc, J, T, R1, R2;
   rm_eye<D>(A, d);
   rm_zero<D>(Cc);
   rm_zero<D>(J);
@@ -511,60 +490,75 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
       if (!first) {
         rm_stage<D>(A, B1);
         team_sync();
-        gemm<D, false, false, false>(T, sF, B1);  // F A
-        team_sync();
+        gemm<D, false, false, false>(T, sF, B1);  // T = F A
       }
+      team_sync();
+    }
+    // B1 <- Mo (Pp, or H Pp); R2 <- S; vw <- innovation
+    rm_stage<D>(Pp, B1);
+    if constexpr (GH) {
+      team_sync();
+      gemm<D, false, false, false>(R1, sH, B1);  // H Pp
+      team_sync();
+      rm_stage<D>(R1, B1);
+      team_sync();
+      gemm<D, false, true, false>(R2, B1, sH);  // H Pp H'
+      rm_add_load<D>(R2, P.Ro, P.dyo, P.dyo);
+      matvec<D, false>(vw, sH, vmu);
+      team_sync();
+      if (tid < D) vw[tid] = (tid < P.dyo) ? P.yo[(int64_t)t * P.dyo + tid] - vw[tid] : 0.0;
+    } else {
+      R2 = Pp;
+      if (P.Omd) {
+        rm_add_load<D>(R2, P.Omd, d, d);
+      } else {
+        const double* Om = P.Om + (int64_t)t * d;
+        AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += Om[i];
+      }
+      if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
     }
     double logdet;
-    if constexpr (GH) {
-      obs_general<D>(B1, B2, B3, sH, Pp, vmu, vw, P, t, scal, &logdet, ok);  // B1 = H Pp
-    } else {
-      build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
-      ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;  // B3 = L^{-1}
-      rm_stage<D>(Pp, B1);
-      if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
-      team_sync();
-    }
-    gemm<D, false, false, false>(X, B3, B1);  // X = L^{-1} Pp   (GH: L^{-1} H Pp)
-    matvec<D, false>(vr, B3, vw);             // r = L^{-1} (omega - mu)
+    ok = spd_inv<D>(R2, dobs, sbuf, &logdet) && ok;  // R2 = S^{-1}
+    rm_stage<D>(R2, B3);
     team_sync();
-    rm_stage<D>(X, B2);
+    gemm<D, false, false, false>(R1, B3, B1);  // S^{-1} Mo
+    matvec<D, false>(vs, B3, vw);              // S^{-1} w
     team_sync();
-    gemm<D, true, false, false>(Cc, B2, B2);  // X'X
-    rm_axpy<D>(Cc, -1.0, Pp);
-    rm_axpy<D>(Cc, -2.0, Cc);  // Cc = Pp - X'X  (Cc <- -(X'X - Pp))
+    rm_stage<D>(R1, B2);
+    team_sync();
+    gemm<D, true, false, false>(Cc, B1, B2);  // Mo' S^{-1} Mo
+    rm_rsub<D>(Cc, Pp);  // C = Pp - Mo' S^{-1} Mo
     if (tid < D) {
-      double s = 0.0;
-      for (int j = 0; j < D; ++j) s = fma(B2[j * C::LD + tid], vr[j], s);
-      vb[tid] = vmu[tid] + s;  // b = mu + X' r
+      double sacc = 0.0;
+      for (int j = 0; j < D; ++j) sacc = fma(B1[j * C::LD + tid], vs[j], sacc);
+      vb[tid] = vmu[tid] + sacc;  // b = mu + Mo' S^{-1} w
     }
     if (!first && t > 0) {
-      rm_stage<D>(T, B1);
       team_sync();
+      rm_stage<D>(T, B2);  // B2 <- Mt (T, or H T)
       if constexpr (GH) {
-        gemm<D, false, false, false>(Y, sH, B1);  // H T
         team_sync();
-        rm_stage<D>(Y, B1);
+        gemm<D, false, false, false>(R1, sH, B2);  // H T
         team_sync();
+        rm_stage<D>(R1, B2);
       }
-      gemm<D, false, false, false>(Y, B3, B1);  // Y = L^{-1} T   (GH: L^{-1} H T)
       team_sync();
-      rm_stage<D>(Y, B1);
+      gemm<D, false, false, false>(R1, B3, B2);  // S^{-1} Mt
       team_sync();
-      gemm<D, true, false, true>(J, B1, B1);   // J += Y'Y
-      gemm<D, true, false, false>(A, B2, B1);  // X'Y
-      rm_axpy<D>(A, -1.0, T);
-      rm_axpy<D>(A, -2.0, A);  // A = T - X'Y
+      rm_stage<D>(R1, B3);
+      team_sync();
+      gemm<D, true, false, true>(J, B2, B3);   // J += Mt' S^{-1} Mt
+      gemm<D, true, false, false>(A, B1, B3);  // Mo' S^{-1} Mt
+      rm_rsub<D>(A, T);  // A = T - Mo' S^{-1} Mt
       if (tid < D) {
-        double s = 0.0;
-        for (int j = 0; j < D; ++j) s = fma(B1[j * C::LD + tid], vr[j], s);
-        veta[tid] += s;  // eta += Y' r
+        double sacc = 0.0;
+        for (int j = 0; j < D; ++j) sacc = fma(B2[j * C::LD + tid], vs[j], sacc);
+        veta[tid] += sacc;  // eta += Mt' S^{-1} w
       }
     } else if (first) {
       rm_zero<D>(A);
     }
-    team_sync();
-    rm_symmetrise<D>(Cc, B1);
+    rm_symmetrise<D>(Cc, B2);
   }
   if (!ok && tid == 0) flag_status(P.status, P.fail_bit);
   if (first) {
@@ -589,14 +583,15 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 
 // ---------------------------------------------------------------------------
 // Filter, phase 2 up-sweep: node k of a level = left (earlier) (x) right.
-// With C_i = L L' (FP64 Cholesky), W = I + L' J_j L = R R', V = L R^{-T}, so
-// that (I + C_i J_j)^{-1} C_i = V V' and (I + C_i J_j)^{-1} = I - V V' J_j:
-//   A  = A_j (A_i - V V' J_j A_i)
-//   b  = A_j (b_i + V V' c) + b_j,            c = eta_j - J_j b_i
-//   C  = (A_j V)(A_j V)' + C_j
-//   eta = A_i' (c - J_j V V' c) + eta_i
-//   J  = A_i' J_j A_i - (V' J_j A_i)'(V' J_j A_i) + J_i
-// (the element combine of App. A in Cholesky form; covariances stay PSD).
+// With C_i = L L' (register Cholesky), W = I + L' J_j L (SPD, eigenvalues
+// >= 1, inverted by Gauss-Jordan) and M = L W^{-1} L' = (I + C_i J_j)^{-1} C_i:
+//   A   = A_j (A_i - M J_j A_i)
+//   b   = A_j (b_i + M c) + b_j,             c = eta_j - J_j b_i
+//   C   = A_j M A_j' + C_j
+//   eta = A_i' (c - J_j M c) + eta_i
+//   J   = A_i' J_j A_i - (J_j A_i)' M (J_j A_i) + J_i
+// (the filtering-element combine of App. A, "Prefix-sums and the parallel
+// Kalman filter").
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& T, int item) {
@@ -609,11 +604,10 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   double* S3 = S2 + C::MAT;
   double* vbi = S3 + C::MAT;
   double* vc = vbi + D;
-  double* vz = vc + D;
-  double* vw = vz + D;
+  double* vw = vc + D;
   double* vk = vw + D;
-  double* scal = vk + D;
-  const int k = item, tid = threadIdx.x;
+  double* sbuf = vk + D;  // 4 D
+  const int k = item, tid = threadIdx.x, d = M.d;
   const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
   double* out = T.dst + (int64_t)k * EL::SIZE;
   if (2 * k + 1 >= T.n_src) {
@@ -623,90 +617,72 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   const double* ej = ei + EL::SIZE;
   bool ok = true;
   double ld;
-  lds_load_pad<D>(S0, ei + EL::C);
+  RM<D> R1, R2, R3;
+  rm_load<D>(R1, ei + EL::C, D, d);
   lds_load_pad<D>(S1, ej + EL::J);
   if (tid < D) vbi[tid] = ei[EL::b + tid];
+  ok = chol_reg<D>(R1, d, sbuf, &ld) && ok;  // R1 = L
+  rm_stage<D>(R1, S0);                        // S0 = L
   team_sync();
-  ok = chol_inv<D, false>(S0, S3, M.d, &ld, scal) && ok;  // S0 = L
-  RM<D> R1, R2, R3;
-  gemm<D, false, false, false>(R1, S1, S0);  // T = J_j L
-  rm_stage<D>(R1, S2);
-  team_sync();
-  gemm<D, true, false, false>(R2, S0, S2);  // L' T
-  {
-    RM<D> I;
-    rm_eye<D>(I, D);
-    rm_axpy<D>(R2, 1.0, I);  // W = I + L' J_j L
-  }
-  team_sync();
+  gemm<D, false, false, false>(R2, S1, S0);  // J_j L
   rm_stage<D>(R2, S2);
   team_sync();
-  ok = chol_inv<D, true>(S2, S3, D, &ld, scal) && ok;  // S3 = R^{-1}
-  gemm<D, false, true, false>(R1, S0, S3);            // V = L R^{-T}
+  gemm<D, true, false, false>(R2, S0, S2);  // L' J_j L
+  AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
+  ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // W^{-1}
+  rm_stage<D>(R2, S2);
   team_sync();
-  rm_stage<D>(R1, S2);  // S2 = V
-  // c = eta_j - J_j b_i
-  matvec<D, false>(vc, S1, vbi);
+  gemm<D, false, false, false>(R3, S0, S2);  // L W^{-1}
+  rm_stage<D>(R3, S3);
   team_sync();
+  gemm<D, false, true, false>(R2, S3, S0);  // M = L W^{-1} L'
+  matvec<D, false>(vc, S1, vbi);            // J_j b_i
+  team_sync();
+  rm_stage<D>(R2, S2);  // S2 = M
   if (tid < D) vc[tid] = ej[EL::eta + tid] - vc[tid];
   team_sync();
-  matvec<D, true>(vz, S2, vc);  // V' c
+  matvec<D, false>(vw, S2, vc);  // w = M c
+  lds_load_pad<D>(S0, ei + EL::A);  // S0 = A_i
   team_sync();
-  matvec<D, false>(vw, S2, vz);  // w = V V' c
-  team_sync();
-  matvec<D, false>(vk, S1, vw);  // J_j w
-  team_sync();
-  if (tid < D) vk[tid] = vc[tid] - vk[tid];  // k2 = c - J_j V V' c
-  lds_load_pad<D>(S0, ei + EL::A);           // S0 = A_i
-  team_sync();
+  matvec<D, false>(vk, S1, vw);              // J_j w
   gemm<D, false, false, false>(R1, S1, S0);  // P = J_j A_i
+  rm_stage<D>(R1, S3);                       // S3 = P
   team_sync();
-  rm_stage<D>(R1, S3);  // S3 = P
+  if (tid < D) vk[tid] = vc[tid] - vk[tid];  // c - J_j M c
+  gemm<D, true, false, false>(R3, S0, S3);   // A_i' P
+  gemm<D, false, false, false>(R2, S2, S3);  // M P
   team_sync();
-  gemm<D, true, false, false>(R2, S2, S3);  // Q' = V' P
-  gemm<D, true, false, false>(R3, S0, S3);  // A_i' P
-  rm_add_load<D>(R3, ei + EL::J, D, D);     // + J_i
-  // eta = A_i' k2 + eta_i
-  if (tid < D) {
-    double s = 0.0;
-    for (int j = 0; j < D; ++j) s = fma(S0[j * C::LD + tid], vk[j], s);
-    out[EL::eta + tid] = s + ei[EL::eta + tid];
+  if (tid < D) {  // eta = A_i' (c - J_j M c) + eta_i
+    double sacc = 0.0;
+    for (int j = 0; j < D; ++j) sacc = fma(S0[j * C::LD + tid], vk[j], sacc);
+    out[EL::eta + tid] = sacc + ei[EL::eta + tid];
   }
-  team_sync();
-  rm_stage<D>(R2, S1);  // S1 = Q'
+  rm_stage<D>(R2, S1);  // S1 = M P
+  rm_unstage<D>(R1, S0);
+  rm_axpy<D>(R1, -1.0, R2);  // Z1 = A_i - M P
   team_sync();
   {
     RM<D> QQ;
-    gemm<D, true, false, false>(QQ, S1, S1);  // Q'' Q'
-    rm_axpy<D>(R3, -1.0, QQ);                 // J
+    gemm<D, true, false, false>(QQ, S3, S1);  // P' M P
+    rm_axpy<D>(R3, -1.0, QQ);
   }
-  gemm<D, false, false, false>(R1, S2, S1);  // V Q'
-  {
-    RM<D> Ai;
-    rm_load<D>(Ai, ei + EL::A, D, D);
-    rm_axpy<D>(R1, -1.0, Ai);
-    rm_axpy<D>(R1, -2.0, R1);  // Z1 = A_i - V Q'
-  }
-  rm_symmetrise<D>(R3, S3);  // (ends synchronised; S3 free afterwards)
+  rm_add_load<D>(R3, ei + EL::J, D, D);
+  rm_symmetrise<D>(R3, S3);  // ends synchronised
   rm_store<D>(R3, out + EL::J, D, D);
   lds_load_pad<D>(S3, ej + EL::A);  // S3 = A_j
-  team_sync();
-  gemm<D, false, false, false>(R2, S3, S2);  // A_j V
-  team_sync();
-  rm_stage<D>(R1, S1);  // S1 = Z1
-  team_sync();
-  gemm<D, false, false, false>(R3, S3, S1);  // A = A_j Z1
-  rm_store<D>(R3, out + EL::A, D, D);
-  rm_stage<D>(R2, S0);  // S0 = A_j V
-  // b = A_j (b_i + w) + b_j
+  rm_stage<D>(R1, S0);              // S0 = Z1
   if (tid < D) vw[tid] += vbi[tid];
   team_sync();
-  matvec<D, false>(vz, S3, vw);
-  gemm<D, false, true, false>(R3, S0, S0);  // (A_j V)(A_j V)'
-  rm_add_load<D>(R3, ej + EL::C, D, D);
+  gemm<D, false, false, false>(R3, S3, S0);  // A = A_j Z1
+  rm_store<D>(R3, out + EL::A, D, D);
+  gemm<D, false, false, false>(R2, S3, S2);  // A_j M
+  matvec<D, false>(vc, S3, vw);              // A_j (b_i + M c)
+  rm_stage<D>(R2, S1);                       // S1 = A_j M
   team_sync();
-  if (tid < D) out[EL::b + tid] = vz[tid] + ej[EL::b + tid];
-  rm_symmetrise<D>(R3, S1);
+  gemm<D, false, true, false>(R3, S1, S3);  // A_j M A_j'
+  rm_add_load<D>(R3, ej + EL::C, D, D);
+  if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
+  rm_symmetrise<D>(R3, S0);
   rm_store<D>(R3, out + EL::C, D, D);
   if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
 }
@@ -717,12 +693,12 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) 
 }
 
 // ---------------------------------------------------------------------------
-// Filter, phase 2 down-sweep: the prefix entering node k of level l is known
+// Filter, phase 2 down-sweep: the prefix entering node k of a level is known
 // (pre_src, as a filtering moment pair (m, P), or the identity for the left
 // spine).  Its children: left gets the same prefix, right gets
 // prefix (x) element(left child).  For a moment pair (m, P) with P = L L',
-// W = I + L' J L = R R', V = L R^{-T}:
-//   m' = A (m + V V'(eta - J m)) + b,   P' = (A V)(A V)' + C.
+// W = I + L' J L and M = L W^{-1} L' = (P^{-1} + J)^{-1}:
+//   m' = A (m + M (eta - J m)) + b,   P' = A M A' + C.
 // With the identity prefix the result is the left child's (b, C) (its A = 0).
 // ---------------------------------------------------------------------------
 template <int D>
@@ -739,8 +715,8 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   double* vc = vm + D;
   double* vz = vc + D;
   double* vw = vz + D;
-  double* scal = vw + D;
-  const int k = item, tid = threadIdx.x;
+  double* sbuf = vw + D;  // 4 D
+  const int k = item, tid = threadIdx.x, d = M.d;
   const double* pin = T.pre_src + (int64_t)k * PL::SIZE;
   const bool ident = pin[PL::flag] != 0.0;
   // left child: same prefix
@@ -757,45 +733,40 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   }
   bool ok = true;
   double ld;
-  lds_load_pad<D>(S0, pin + PL::P);
+  RM<D> R1, R2;
+  rm_load<D>(R1, pin + PL::P, D, d);
   lds_load_pad<D>(S1, el + EL::J);
   if (tid < D) vm[tid] = pin[PL::m + tid];
-  team_sync();
-  ok = chol_inv<D, false>(S0, S3, M.d, &ld, scal) && ok;
-  RM<D> R1, R2;
-  gemm<D, false, false, false>(R1, S1, S0);  // J L
-  rm_stage<D>(R1, S2);
-  team_sync();
-  gemm<D, true, false, false>(R2, S0, S2);  // L' J L
-  {
-    RM<D> I;
-    rm_eye<D>(I, D);
-    rm_axpy<D>(R2, 1.0, I);
-  }
-  team_sync();
-  rm_stage<D>(R2, S2);
-  team_sync();
-  ok = chol_inv<D, true>(S2, S3, D, &ld, scal) && ok;  // S3 = R^{-1}
-  gemm<D, false, true, false>(R1, S0, S3);            // V
-  team_sync();
-  rm_stage<D>(R1, S2);  // S2 = V
-  matvec<D, false>(vc, S1, vm);
-  team_sync();
-  if (tid < D) vc[tid] = el[EL::eta + tid] - vc[tid];  // eta - J m
-  team_sync();
-  matvec<D, true>(vz, S2, vc);
-  team_sync();
-  matvec<D, false>(vw, S2, vz);  // V V' (eta - J m)
-  lds_load_pad<D>(S3, el + EL::A);
-  team_sync();
-  if (tid < D) vw[tid] += vm[tid];
-  gemm<D, false, false, false>(R1, S3, S2);  // A V
-  team_sync();
-  matvec<D, false>(vz, S3, vw);
+  ok = chol_reg<D>(R1, d, sbuf, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);
   team_sync();
-  gemm<D, false, true, false>(R2, S0, S0);
+  gemm<D, false, false, false>(R2, S1, S0);  // J L
+  rm_stage<D>(R2, S2);
+  team_sync();
+  gemm<D, true, false, false>(R2, S0, S2);  // L' J L
+  AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
+  ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // W^{-1}
+  rm_stage<D>(R2, S2);
+  team_sync();
+  gemm<D, false, false, false>(R1, S0, S2);  // L W^{-1}
+  rm_stage<D>(R1, S3);
+  team_sync();
+  gemm<D, false, true, false>(R2, S3, S0);  // M
+  matvec<D, false>(vc, S1, vm);             // J m
+  team_sync();
+  rm_stage<D>(R2, S2);  // S2 = M
+  if (tid < D) vc[tid] = el[EL::eta + tid] - vc[tid];
+  lds_load_pad<D>(S3, el + EL::A);  // S3 = A
+  team_sync();
+  matvec<D, false>(vw, S2, vc);              // M (eta - J m)
+  gemm<D, false, false, false>(R1, S3, S2);  // A M
+  rm_stage<D>(R1, S0);
+  team_sync();
+  if (tid < D) vw[tid] += vm[tid];
+  gemm<D, false, true, false>(R2, S0, S3);  // A M A'
   rm_add_load<D>(R2, el + EL::C, D, D);
+  team_sync();
+  matvec<D, false>(vz, S3, vw);
   if (tid < D) pr[PL::m + tid] = vz[tid] + el[EL::b + tid];
   if (tid == 0) pr[PL::flag] = 0.0;
   rm_symmetrise<D>(R2, S1);
@@ -817,8 +788,8 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T
 template <int D, bool GH>
 __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterArgs& P, int item) {
   using C = Cfg<D>;
-  static_assert(!GH || D <= 32, "general observation matrices need D <= 32");
   using PL = PrefLayout<D>;
+  static_assert(!GH || D <= 32, "general observation matrices need D <= 32");
   extern __shared__ double lds[];
   double* sF = lds;
   double* B1 = sF + C::MAT;
@@ -828,15 +799,15 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
   double* vm = sH + (GH ? C::MAT : 0);
   double* vmp = vm + D;
   double* vw = vmp + D;
-  double* vr = vw + D;
-  double* red = vr + D;
-  double* scal = red + 8;
+  double* vs = vw + D;
+  double* red = vs + D;
+  double* sbuf = red + 8;  // 4 D
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   lds_load_mat<D>(sF, M.F, d);
   if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
   const int dobs = GH ? P.dyo : d;
-  RM<D> Pm, Pp, T, X;
+  RM<D> Pm, Pp, T, R2;
   if (s0 > 0) {
     const double* pin = P.pre + (int64_t)blk * PL::SIZE;
     rm_load<D>(Pm, pin + PL::P, D, D);
@@ -860,33 +831,48 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       matvec<D, false>(vmp, sF, vm);
       team_sync();
       if (tid < d && M.b) vmp[tid] += M.b[tid];
-    }
-    double logdet;
-    if constexpr (GH) {
-      obs_general<D>(B1, B2, B3, sH, Pp, vmp, vw, P, t, scal, &logdet, ok);  // B1 = H Pp
-    } else {
-      build_S<D>(B2, Pp, P.Om + (int64_t)t * d, P.Omd, d);
-      ok = chol_inv<D, true>(B2, B3, d, &logdet, scal) && ok;
-      rm_stage<D>(Pp, B1);
-      if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
       team_sync();
     }
-    gemm<D, false, false, false>(X, B3, B1);
-    matvec<D, false>(vr, B3, vw);
+    rm_stage<D>(Pp, B1);
+    if constexpr (GH) {
+      team_sync();
+      gemm<D, false, false, false>(T, sH, B1);  // H Pp
+      team_sync();
+      rm_stage<D>(T, B1);
+      team_sync();
+      gemm<D, false, true, false>(R2, B1, sH);
+      rm_add_load<D>(R2, P.Ro, P.dyo, P.dyo);
+      matvec<D, false>(vw, sH, vmp);
+      team_sync();
+      if (tid < D) vw[tid] = (tid < P.dyo) ? P.yo[(int64_t)t * P.dyo + tid] - vw[tid] : 0.0;
+    } else {
+      R2 = Pp;
+      if (P.Omd) {
+        rm_add_load<D>(R2, P.Omd, d, d);
+      } else {
+        const double* Om = P.Om + (int64_t)t * d;
+        AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += Om[i];
+      }
+      if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
+    }
+    double logdet;
+    ok = spd_inv<D>(R2, dobs, sbuf, &logdet) && ok;
+    rm_stage<D>(R2, B3);
     team_sync();
-    rm_stage<D>(X, B2);
-    const double rr = team_sum<D>(tid < D ? vr[tid] * vr[tid] : 0.0, red);
-    gemm<D, true, false, false>(Pm, B2, B2);
-    rm_axpy<D>(Pm, -1.0, Pp);
-    rm_axpy<D>(Pm, -2.0, Pm);  // P^f = Pp - X'X
+    gemm<D, false, false, false>(T, B3, B1);  // S^{-1} Mo
+    matvec<D, false>(vs, B3, vw);
+    team_sync();
+    rm_stage<D>(T, B2);
+    const double rr = team_sum<D>(tid < D ? vw[tid] * vs[tid] : 0.0, red);
+    gemm<D, true, false, false>(Pm, B1, B2);  // Mo' S^{-1} Mo
+    rm_rsub<D>(Pm, Pp);  // P^f = Pp - Mo' S^{-1} Mo
     if (tid < D) {
-      double s = 0.0;
-      for (int j = 0; j < D; ++j) s = fma(B2[j * C::LD + tid], vr[j], s);
-      vm[tid] = vmp[tid] + s;  // m^f = m^p + X' r
+      double sacc = 0.0;
+      for (int j = 0; j < D; ++j) sacc = fma(B1[j * C::LD + tid], vs[j], sacc);
+      vm[tid] = vmp[tid] + sacc;  // m^f = m^p + Mo' S^{-1} w
     }
     if (tid == 0) P.ell[t] = -0.5 * (dobs * LOG2PI + logdet + rr);
-    team_sync();
-    rm_symmetrise<D>(Pm, B1);
+    rm_symmetrise<D>(Pm, B2);
     if (P.mf) {
       if (tid < d) P.mf[(int64_t)t * P.ldm + tid] = vm[tid];
       rm_store<D>(Pm, P.Pf + (int64_t)t * P.ldm * P.ldm, P.ldm, d);
@@ -902,9 +888,9 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArg
 
 // ---------------------------------------------------------------------------
 // Sampler, element build (eq. backward, Alg. "Parallel RTS sampler"), one team
-// per t:  P^p = F P^f F' + Q = L_p L_p',  W = L_p^{-1} F P^f,
-//   E_t = W' L_p^{-1} = P^f F' (P^p)^{-1},   L_t = P^f - W'W,
-//   g_t = m^f - E_t (F m^f + bias),          U_t = g_t + chol(L_t) xi_t.
+// per t:  G = F P^f,  P^p = G F' + Q (inverted by Gauss-Jordan),
+//   E_t = G' (P^p)^{-1} = P^f F' (P^p)^{-1},   L_t = P^f - E_t G,
+//   g_t = m^f - E_t (F m^f + bias),            U_t = g_t + chol(L_t) xi_t.
 // Terminal step: E = 0, U = m^f + chol(P^f) xi.
 // ---------------------------------------------------------------------------
 template <int D>
@@ -919,7 +905,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   double* vmp = vm + D;
   double* vg = vmp + D;
   double* vxi = vg + D;
-  double* scal = vxi + D;
+  double* sbuf = vxi + D;  // 4 D
   const int t = item, tid = threadIdx.x, d = M.d;
   RM<D> Pf, R1, R2;
   rm_load<D>(Pf, S.Pf + (int64_t)t * S.ldm * S.ldm, S.ldm, d);
@@ -930,9 +916,9 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   bool ok = true;
   double ld;
   if (t == M.N - 1) {
+    ok = chol_reg<D>(Pf, d, sbuf, &ld);
     rm_stage<D>(Pf, B2);
     team_sync();
-    ok = chol_inv<D, false>(B2, B3, d, &ld, scal);
     if (tid < D) {
       double s = vm[tid];
       for (int j = 0; j <= tid; ++j) s = fma(B2[tid * C::LD + j], vxi[j], s);
@@ -945,36 +931,29 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     lds_load_mat<D>(sF, M.F, d);
     rm_stage<D>(Pf, B1);
     team_sync();
-    gemm<D, false, false, false>(R1, sF, B1);  // F P^f
+    gemm<D, false, false, false>(R1, sF, B1);  // G = F P^f
     team_sync();
-    rm_stage<D>(R1, B1);  // B1 = F P^f
+    rm_stage<D>(R1, B1);  // B1 = G
     team_sync();
-    gemm<D, false, true, false>(R2, B1, sF);  // F P^f F'
+    gemm<D, false, true, false>(R2, B1, sF);  // G F'
     rm_add_load<D>(R2, M.Q, d, d);
     matvec<D, false>(vmp, sF, vm);
+    if (tid < d && M.b) vmp[tid] += M.b[tid];
+    ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // (P^p)^{-1}
     rm_stage<D>(R2, B2);
     team_sync();
-    if (tid < d && M.b) vmp[tid] += M.b[tid];
-    ok = chol_inv<D, true>(B2, B3, d, &ld, scal) && ok;  // B3 = L_p^{-1}
-    gemm<D, false, false, false>(R1, B3, B1);           // W = L_p^{-1} F P^f
+    gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
+    rm_store<D>(R1, S.E + (int64_t)t * D * D, D, D);
+    rm_stage<D>(R1, B3);  // B3 = E
     team_sync();
-    rm_stage<D>(R1, B2);  // B2 = W
-    team_sync();
-    gemm<D, true, false, false>(R2, B2, B3);  // E = W' L_p^{-1}
-    rm_store<D>(R2, S.E + (int64_t)t * D * D, D, D);
-    gemm<D, true, false, false>(R1, B2, B2);  // W'W
-    rm_axpy<D>(R1, -1.0, Pf);
-    rm_axpy<D>(R1, -2.0, R1);  // L_t = P^f - W'W
-    team_sync();
-    rm_stage<D>(R2, B1);  // B1 = E
-    team_sync();
-    matvec<D, false>(vg, B1, vmp);
-    team_sync();
+    gemm<D, false, false, false>(R2, B3, B1);  // E G
+    rm_rsub<D>(R2, Pf);                        // L_t = P^f - E G
+    matvec<D, false>(vg, B3, vmp);
     if (tid < D) vg[tid] = vm[tid] - vg[tid];  // g = m^f - E m^p
-    rm_symmetrise<D>(R1, B3);
-    rm_stage<D>(R1, B2);
+    rm_symmetrise<D>(R2, B2);
+    ok = chol_reg<D>(R2, d, sbuf, &ld) && ok;
+    rm_stage<D>(R2, B2);
     team_sync();
-    ok = chol_inv<D, false>(B2, B3, d, &ld, scal) && ok;
     if (tid < D) {
       double s = vg[tid];
       for (int j = 0; j <= tid; ++j) s = fma(B2[tid * C::LD + j], vxi[j], s);
@@ -1182,7 +1161,7 @@ __global__ void __launch_bounds__(256) k_mh_select(int64_t n, const double* __re
 // ---------------------------------------------------------------------------
 template <int D>
 size_t lds_bytes_filter(bool gh = false) {
-  return (size_t)((gh ? 5 : 4) * Cfg<D>::MAT + 6 * D + 16) * sizeof(double);
+  return (size_t)((gh ? 5 : 4) * Cfg<D>::MAT + 12 * D + 16) * sizeof(double);
 }
 template <int D>
 size_t lds_bytes_samp2() {

@@ -10,14 +10,13 @@
 //    ownership map, so element-wise arithmetic needs no data movement.
 //  * LDS matrices are row-major with leading dimension LD = D + 1 doubles (the
 //    odd stride spreads column accesses over the banks).
-//  * Runtime size d <= D: padded rows/columns are zero in every matrix, except
-//    that a matrix about to be Cholesky-factored gets ones on its padded
-//    diagonal, so every factor and inverse is block-diagonal [L 0; 0 I].
+//  * Runtime size d <= D: padded rows/columns are zero in every matrix
+//    (factors and inverses included).
 //
-// GEMMs run on the f64 matrix cores; the Cholesky factorisation and the
-// triangular inverse are blocked by 16: each 16 x 16 diagonal block is
-// factored by one wave in registers (row per lane, cross-lane reads), and the
-// panel solve and trailing update are MFMA products.
+// GEMMs run on the f64 matrix cores.  Inverses of SPD matrices (Gauss-Jordan)
+// and Cholesky factors are computed in registers, one pivot per sweep, with
+// the pivot row/column broadcast through a small double-buffered LDS vector
+// (one barrier per sweep).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -129,6 +128,13 @@ __device__ __forceinline__ void rm_axpy(RM<D>& y, double alpha, const RM<D>& x) 
   for (int q = 0; q < Cfg<D>::TPW; ++q) y.t[q] += alpha * x.t[q];
 }
 
+// y = x - y
+template <int D>
+__device__ __forceinline__ void rm_rsub(RM<D>& y, const RM<D>& x) {
+#pragma unroll
+  for (int q = 0; q < Cfg<D>::TPW; ++q) y.t[q] = x.t[q] - y.t[q];
+}
+
 // 0.5 (a + a^T) through an LDS scratch matrix (team-wide; starts and ends
 // with a barrier, so s may still be in use by a preceding product)
 template <int D>
@@ -171,197 +177,143 @@ __device__ __forceinline__ void gemm(RM<D>& c, const double* sA, const double* s
   }
 }
 
-// One 16 x 16 tile product on one wave: acc (+)= op(A_blk) op(B_blk), where the
-// blocks start at the given LDS addresses (leading dimension LD).  Returns the
-// accumulator tile in the MFMA layout (lane l, reg r -> (4*r + l/16, l%16)).
-template <int D, bool TA, bool TB>
-__device__ __forceinline__ dbl4 tile_mma(dbl4 acc, const double* sA, const double* sB) {
-  using C = Cfg<D>;
-  const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
-#pragma unroll
-  for (int kb = 0; kb < 4; ++kb) {
-    const int k = 4 * kb + lk;
-    const double a = TA ? sA[k * C::LD + li] : sA[li * C::LD + k];
-    const double b = TB ? sB[li * C::LD + k] : sB[k * C::LD + li];
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-  }
-  return acc;
-}
-
+// Rows and columns owned by this lane in the register layout: tile row ti,
+// register r -> row rows[ti][r]; tile column tj -> column cols[tj].
 template <int D>
-__device__ __forceinline__ void tile_store(const dbl4& t, double* s) {
-  const int l = threadIdx.x & 63;
+struct Own {
+  int rows[Cfg<D>::TS][4];
+  int cols[Cfg<D>::TS];
+  __device__ __forceinline__ Own() {
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int r0 = (D == 64) ? 32 * (w >> 1) : 0, c0 = (D == 64) ? 32 * (w & 1) : 0;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) s[(4 * r + (l >> 4)) * Cfg<D>::LD + (l & 15)] = t[r];
-}
+    for (int ti = 0; ti < Cfg<D>::TS; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rows[ti][r] = r0 + 16 * ti + 4 * r + (l >> 4);
+#pragma unroll
+    for (int tj = 0; tj < Cfg<D>::TS; ++tj) cols[tj] = c0 + 16 * tj + (l & 15);
+  }
+};
 
+// In-place inverse of a symmetric positive definite matrix held in registers
+// (zero outside the leading d x d block) by d Gauss-Jordan sweeps:
+//   p = A_kk;  A_kk <- 1/p;  A_kj <- A_kj/p;  A_ik <- -A_ik/p;
+//   A_ij <- A_ij - A_ik A_kj / p            (i, j != k)
+// The pivots p are those of the LDL' factorisation, so the matrix is PD iff
+// all are > 0 and log det = sum log p.  Pivot row/column are broadcast through
+// sbuf (4*D doubles of LDS, double-buffered: one barrier per sweep).  Returns
+// false on a non-positive pivot (the result is then unspecified).  On entry no
+// thread of the team may still be reading sbuf (a barrier separates any
+// earlier use); the leading barrier also publishes earlier LDS writes.
 template <int D>
-__device__ __forceinline__ dbl4 tile_load(const double* s) {
-  const int l = threadIdx.x & 63;
-  dbl4 t;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) t[r] = s[(4 * r + (l >> 4)) * Cfg<D>::LD + (l & 15)];
-  return t;
-}
-
-// Wave-local factorisation of the 16 x 16 diagonal block at sS + off: lower
-// Cholesky factor written back in place (upper part zeroed) and, when sG is
-// its inverse written to sG + off.  Lane r (< 16) holds row r.
-// Adds log det of the block to *logdet; clears *ok on a non-positive pivot.
-template <int D>
-__device__ __forceinline__ void diag16_chol_inv(double* sS, double* sG, int off, bool& ok,
-                                                double& logdet) {
+__device__ bool spd_inv(RM<D>& A, int d, double* sbuf, double* logdet) {
   using C = Cfg<D>;
-  const int l = threadIdx.x & 63, r = l & 15;
-  double a[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) a[j] = sS[off + r * C::LD + j];
-  double ld = 0.0;
-  bool good = true;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) {
-    const double piv = lane_bcast(a[k], k);
-    good = good && (piv > 0.0);
-    const double p = piv > 0.0 ? piv : 1.0;
-    const double s = sqrt(p), inv = 1.0 / s;
-    ld += log(p);
-    a[k] = (r == k) ? s : (r > k ? a[k] * inv : 0.0);
-#pragma unroll
-    for (int j = k + 1; j < 16; ++j) a[j] = fma(-a[k], lane_bcast(a[k], j), a[j]);
-  }
-#pragma unroll
-  for (int j = 0; j < 16; ++j)
-    if (j > r) a[j] = 0.0;
-  {
-    // column r of L^{-1} by forward substitution, L_ik read from lane i
-    double x[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      double s = (i == r) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) s = fma(-lane_bcast(a[k], i), x[k], s);
-      x[i] = s / lane_bcast(a[i], i);
-    }
-    if (l < 16) {
-#pragma unroll
-      for (int i = 0; i < 16; ++i) sG[off + i * C::LD + r] = x[i];
-    }
-  }
-  if (l < 16) {
-#pragma unroll
-    for (int j = 0; j < 16; ++j) sS[off + r * C::LD + j] = a[j];
-  }
-  ok = ok && good;
-  logdet += ld;
-}
-
-// Team-wide blocked Cholesky of the symmetric matrix in sS (lower triangle
-// used; indices >= d replaced by the identity).  On return sS holds L (lower,
-// upper zeroed).  sG is a D x D LDS buffer: with FULL it receives L^{-1}
-// (lower, upper zeroed); otherwise only its diagonal 16 x 16 blocks hold the
-// inverses of L's diagonal blocks.  Returns false if a pivot was not strictly
-// positive; *logdet_out gets log det of the leading d x d block.  sScal is a
-// 2-double LDS scratch.  Ends synchronised.
-template <int D, bool FULL>
-__device__ bool chol_inv(double* sS, double* sG, int d, double* logdet_out, double* sScal) {
-  using C = Cfg<D>;
-  const int tid = threadIdx.x, w = tid >> 6;
-  // pad to the identity beyond d; zero the upper triangle
-  for (int e = tid; e < D * D; e += C::NT) {
-    const int i = e / D, j = e % D;
-    if (i >= d || j >= d) sS[i * C::LD + j] = (i == j) ? 1.0 : 0.0;
-    else if (j > i) sS[i * C::LD + j] = 0.0;
-  }
-  if (FULL)
-    for (int e = tid; e < D * D; e += C::NT) sG[(e / D) * C::LD + (e % D)] = 0.0;
-  team_sync();
+  const Own<D> o;
   bool ok = true;
-  double ld = 0.0;
+  double ld = 0.0, prod = 1.0;
+  for (int k = 0; k < d; ++k) {
+    double* sr = sbuf + (k & 1) * D;
+    double* sc = sbuf + 2 * D + (k & 1) * D;
 #pragma unroll
-  for (int K = 0; K < C::NB; ++K) {
-    const int offKK = (16 * K) * C::LD + 16 * K;
-    if (w == 0) diag16_chol_inv<D>(sS, sG, offKK, ok, ld);
-    team_sync();
-    if (K + 1 < C::NB) {
-      // panel: L_IK = S_IK L_KK^{-T}, with L_KK^{-1} in the diagonal block of sG
-      const int npanel = C::NB - 1 - K;
-      for (int p = w; p < npanel; p += C::NW) {
-        const int I = K + 1 + p;
-        const int offIK = (16 * I) * C::LD + 16 * K;
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        acc = tile_mma<D, false, true>(acc, sS + offIK, sG + offKK);
-        wave_lds_fence();
-        tile_store<D>(acc, sS + offIK);
-      }
-      team_sync();
-      // trailing update: S_IJ -= L_IK L_JK^T for K < J <= I
-      const int m = C::NB - 1 - K;
-      const int ntr = m * (m + 1) / 2;
-      for (int p = w; p < ntr; p += C::NW) {
-        int I = 0, J = 0, c = 0;
-        for (int ii = 0; ii < m; ++ii)
-          for (int jj = 0; jj <= ii; ++jj) {
-            if (c == p) { I = K + 1 + ii; J = K + 1 + jj; }
-            ++c;
-          }
-        const int offIJ = (16 * I) * C::LD + 16 * J;
-        dbl4 acc = tile_load<D>(sS + offIJ);
-        dbl4 prod = {0.0, 0.0, 0.0, 0.0};
-        prod = tile_mma<D, false, true>(prod, sS + (16 * I) * C::LD + 16 * K,
-                                        sS + (16 * J) * C::LD + 16 * K);
-        acc -= prod;
-        if (I == J) {
-          // keep the diagonal tile's upper part zero (only lower is read)
-          const int l = tid & 63;
+    for (int ti = 0; ti < C::TS; ++ti)
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if ((l & 15) > 4 * r + (l >> 4)) acc[r] = 0.0;
+      for (int tj = 0; tj < C::TS; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = o.rows[ti][r], j = o.cols[tj];
+          if (i == k) sr[j] = A.t[ti * C::TS + tj][r];
+          if (j == k) sc[i] = A.t[ti * C::TS + tj][r];
         }
-        wave_lds_fence();
-        tile_store<D>(acc, sS + offIJ);
-      }
-      team_sync();
-    }
-  }
-  if (FULL && C::NB > 1) {
-    // off-diagonal blocks of L^{-1}: G_IJ = -G_II sum_{K=J}^{I-1} L_IK G_KJ, by distance
-    for (int dist = 1; dist < C::NB; ++dist) {
-      const int npair = C::NB - dist;
-      for (int p = w; p < npair; p += C::NW) {
-        const int I = dist + p, J = p;
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int K = J; K < I; ++K)
-          acc = tile_mma<D, false, false>(acc, sS + (16 * I) * C::LD + 16 * K,
-                                          sG + (16 * K) * C::LD + 16 * J);
-        // stage into the (unused) upper block (J, I) of sG, then multiply by -G_II
-        double* scr = sG + (16 * J) * C::LD + 16 * I;
-        tile_store<D>(acc, scr);
-        wave_lds_fence();
-        dbl4 res = {0.0, 0.0, 0.0, 0.0};
-        res = tile_mma<D, false, false>(res, sG + (16 * I) * C::LD + 16 * I, scr);
-        res = -res;
-        wave_lds_fence();
-        tile_store<D>(res, sG + (16 * I) * C::LD + 16 * J);
-      }
-      team_sync();
-    }
-    // clear the upper scratch blocks
-    for (int e = tid; e < D * D; e += C::NT) {
-      const int i = e / D, j = e % D;
-      if (j / 16 > i / 16) sG[i * C::LD + j] = 0.0;
-    }
     team_sync();
+    const double p = sr[k];
+    ok = ok && (p > 0.0);
+    const double ip = (p > 0.0) ? 1.0 / p : 0.0;
+    prod *= (p > 0.0) ? p : 1.0;
+    if ((k & 15) == 15 || k == d - 1) {
+      ld += log(prod);
+      prod = 1.0;
+    }
+    double rk[C::TS];
+#pragma unroll
+    for (int tj = 0; tj < C::TS; ++tj) rk[tj] = sr[o.cols[tj]];
+#pragma unroll
+    for (int ti = 0; ti < C::TS; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = o.rows[ti][r];
+        const double cik = sc[i];
+        const double f = -cik * ip;
+#pragma unroll
+        for (int tj = 0; tj < C::TS; ++tj) {
+          const int j = o.cols[tj];
+          const double v = A.t[ti * C::TS + tj][r];
+          A.t[ti * C::TS + tj][r] = (i == k) ? ((j == k) ? ip : rk[tj] * ip)
+                                             : ((j == k) ? f : fma(f, rk[tj], v));
+        }
+      }
   }
-  // combine per-wave results (only wave 0 factored diagonal blocks)
-  if (tid == 0) {
-    sScal[0] = ld;
-    sScal[1] = ok ? 1.0 : 0.0;
+  *logdet = ld;
+  return ok;
+}
+
+// Lower Cholesky factor (positive diagonal) of a symmetric positive definite
+// matrix held in registers (zero outside the leading d x d block), in place,
+// right-looking: column k is scaled by 1/sqrt(A_kk) and broadcast through
+// sbuf (2*D doubles, double-buffered), then the trailing lower triangle is
+// updated.  The strict upper triangle is zeroed.  Returns false on a
+// non-positive pivot; *logdet gets log det of the matrix.  Same sbuf entry
+// condition as spd_inv.
+template <int D>
+__device__ bool chol_reg(RM<D>& A, int d, double* sbuf, double* logdet) {
+  using C = Cfg<D>;
+  const Own<D> o;
+  bool ok = true;
+  double ld = 0.0, prod = 1.0;
+  for (int k = 0; k < d; ++k) {
+    double* sc = sbuf + (k & 1) * D;
+#pragma unroll
+    for (int ti = 0; ti < C::TS; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < C::TS; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = o.rows[ti][r], j = o.cols[tj];
+          if (j == k && i >= k) sc[i] = A.t[ti * C::TS + tj][r];
+        }
+    team_sync();
+    const double p = sc[k];
+    ok = ok && (p > 0.0);
+    const double pp = (p > 0.0) ? p : 1.0;
+    const double sq = sqrt(pp), is = 1.0 / sq;
+    prod *= pp;
+    if ((k & 15) == 15 || k == d - 1) {
+      ld += log(prod);
+      prod = 1.0;
+    }
+    double ljk[C::TS];
+#pragma unroll
+    for (int tj = 0; tj < C::TS; ++tj) {
+      const int j = o.cols[tj];
+      ljk[tj] = (j > k && j < d) ? sc[j] * is : 0.0;
+    }
+#pragma unroll
+    for (int ti = 0; ti < C::TS; ++ti)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = o.rows[ti][r];
+        const double lik = (i > k && i < d) ? sc[i] * is : 0.0;
+#pragma unroll
+        for (int tj = 0; tj < C::TS; ++tj) {
+          const int j = o.cols[tj];
+          const double v = A.t[ti * C::TS + tj][r];
+          A.t[ti * C::TS + tj][r] = (j == k) ? ((i == k) ? sq : lik)
+                                             : ((j > k && i >= j) ? fma(-lik, ljk[tj], v) : v);
+        }
+      }
   }
-  team_sync();
-  if (logdet_out) *logdet_out = sScal[0];
-  const bool res = sScal[1] != 0.0;
-  team_sync();
-  return res;
+  AKF_RM_FOR(D, q, r, i, j) if (j > i) A.t[q][r] = 0.0;
+  *logdet = ld;  // log det A = sum_k log p_k (p_k = L_kk^2)
+  return ok;
 }
 
 // y[i] = sum_j op(A)[i][j] x[j] for i < D (LDS matrix, LDS vectors). Caller syncs.
