@@ -453,7 +453,8 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
   double* vmu = veta + D;                  // mu
   double* vw = vmu + D;                    // omega - mu  (GH: y - H mu)
   double* vs = vw + D;                     // S^{-1} w
-  double* sbuf = vs + D;                   // 4 D: pivot broadcast
+  double* vom = vs + D;                    // diagonal Omega_t
+  double* sbuf = vom + D;                  // 4 D: pivot broadcast
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   const bool first = (s0 == 0);
@@ -493,6 +494,42 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
         gemm<D, false, false, false>(T, sF, B1);  // T = F A
       }
       team_sync();
+    }
+    if (!GH && !P.Omd) {
+      // diagonal Omega_t: with S = Pp + Omega, I - Pp S^{-1} = Omega S^{-1}, so
+      // C = Omega S^{-1} Pp, A = Omega S^{-1} T, b = omega - Omega S^{-1} w.
+      const double* Om = P.Om + (int64_t)t * d;
+      R2 = Pp;
+      AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += Om[i];
+      if (tid < D) {
+        vom[tid] = (tid < d) ? Om[tid] : 0.0;
+        vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
+      }
+      double logdet;
+      ok = spd_inv<D>(R2, d, sbuf, &logdet) && ok;  // R2 = S^{-1}
+      rm_stage<D>(R2, B3);
+      rm_stage<D>(Pp, B1);
+      team_sync();
+      gemm<D, false, false, false>(Cc, B3, B1);  // S^{-1} Pp
+      AKF_RM_FOR(D, q, r, i, j) Cc.t[q][r] *= vom[i];
+      matvec<D, false>(vs, B3, vw);  // S^{-1} w
+      if (!first && t > 0) {
+        rm_stage<D>(T, B2);
+        team_sync();
+        gemm<D, false, false, false>(R1, B3, B2);  // S^{-1} T
+        rm_stage<D>(R1, B1);
+        team_sync();
+        gemm<D, true, false, true>(J, B2, B1);  // J += T' S^{-1} T
+        AKF_RM_FOR(D, q, r, i, j) A.t[q][r] = vom[i] * R1.t[q][r];
+        if (tid < D) {
+          double sacc = 0.0;
+          for (int j = 0; j < D; ++j) sacc = fma(B2[j * C::LD + tid], vs[j], sacc);
+          veta[tid] += sacc;  // eta += T' S^{-1} w
+        }
+      }
+      if (tid < D) vb[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vom[tid] * vs[tid] : 0.0;
+      rm_symmetrise<D>(Cc, B2);
+      continue;
     }
     // B1 <- Mo (Pp, or H Pp); R2 <- S; vw <- innovation
     rm_stage<D>(Pp, B1);
@@ -589,7 +626,8 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 //   b   = A_j (b_i + M c) + b_j,             c = eta_j - J_j b_i
 //   C   = A_j M A_j' + C_j
 //   eta = A_i' (c - J_j M c) + eta_i
-//   J   = A_i' J_j A_i - (J_j A_i)' M (J_j A_i) + J_i
+//   J   = A_i' J_j A_i - (J_j A_i)' M (J_j A_i) + J_i = Z' J_j A_i + J_i,
+//         Z = A_i - M J_j A_i
 // (the filtering-element combine of App. A, "Prefix-sums and the parallel
 // Kalman filter").
 // ---------------------------------------------------------------------------
@@ -641,7 +679,7 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   rm_stage<D>(R2, S2);  // S2 = M
   if (tid < D) vc[tid] = ej[EL::eta + tid] - vc[tid];
   team_sync();
-  matvec<D, false>(vw, S2, vc);  // w = M c
+  matvec<D, false>(vw, S2, vc);     // w = M c
   lds_load_pad<D>(S0, ei + EL::A);  // S0 = A_i
   team_sync();
   matvec<D, false>(vk, S1, vw);              // J_j w
@@ -649,40 +687,34 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   rm_stage<D>(R1, S3);                       // S3 = P
   team_sync();
   if (tid < D) vk[tid] = vc[tid] - vk[tid];  // c - J_j M c
-  gemm<D, true, false, false>(R3, S0, S3);   // A_i' P
   gemm<D, false, false, false>(R2, S2, S3);  // M P
+  rm_unstage<D>(R3, S0);
+  rm_axpy<D>(R3, -1.0, R2);  // Z1 = A_i - M P
   team_sync();
   if (tid < D) {  // eta = A_i' (c - J_j M c) + eta_i
     double sacc = 0.0;
     for (int j = 0; j < D; ++j) sacc = fma(S0[j * C::LD + tid], vk[j], sacc);
     out[EL::eta + tid] = sacc + ei[EL::eta + tid];
   }
-  rm_stage<D>(R2, S1);  // S1 = M P
-  rm_unstage<D>(R1, S0);
-  rm_axpy<D>(R1, -1.0, R2);  // Z1 = A_i - M P
+  rm_stage<D>(R3, S1);  // S1 = Z1
   team_sync();
-  {
-    RM<D> QQ;
-    gemm<D, true, false, false>(QQ, S3, S1);  // P' M P
-    rm_axpy<D>(R3, -1.0, QQ);
-  }
-  rm_add_load<D>(R3, ei + EL::J, D, D);
-  rm_symmetrise<D>(R3, S3);  // ends synchronised
-  rm_store<D>(R3, out + EL::J, D, D);
-  lds_load_pad<D>(S3, ej + EL::A);  // S3 = A_j
-  rm_stage<D>(R1, S0);              // S0 = Z1
+  gemm<D, true, false, false>(R1, S1, S3);  // J = Z1' P + J_i = A_i'P - P'MP + J_i
+  rm_add_load<D>(R1, ei + EL::J, D, D);
+  rm_symmetrise<D>(R1, S3);  // ends synchronised
+  rm_store<D>(R1, out + EL::J, D, D);
+  lds_load_pad<D>(S0, ej + EL::A);  // S0 = A_j
   if (tid < D) vw[tid] += vbi[tid];
   team_sync();
-  gemm<D, false, false, false>(R3, S3, S0);  // A = A_j Z1
+  gemm<D, false, false, false>(R3, S0, S1);  // A = A_j Z1
   rm_store<D>(R3, out + EL::A, D, D);
-  gemm<D, false, false, false>(R2, S3, S2);  // A_j M
-  matvec<D, false>(vc, S3, vw);              // A_j (b_i + M c)
-  rm_stage<D>(R2, S1);                       // S1 = A_j M
+  gemm<D, false, false, false>(R2, S0, S2);  // A_j M
+  matvec<D, false>(vc, S0, vw);              // A_j (b_i + M c)
+  rm_stage<D>(R2, S3);
   team_sync();
-  gemm<D, false, true, false>(R3, S1, S3);  // A_j M A_j'
+  gemm<D, false, true, false>(R3, S3, S0);  // A_j M A_j'
   rm_add_load<D>(R3, ej + EL::C, D, D);
   if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
-  rm_symmetrise<D>(R3, S0);
+  rm_symmetrise<D>(R3, S1);
   rm_store<D>(R3, out + EL::C, D, D);
   if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
 }
@@ -800,7 +832,8 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
   double* vmp = vm + D;
   double* vw = vmp + D;
   double* vs = vw + D;
-  double* red = vs + D;
+  double* vom = vs + D;  // diagonal Omega_t
+  double* red = vom + D;
   double* sbuf = red + 8;  // 4 D
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
@@ -832,6 +865,33 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       team_sync();
       if (tid < d && M.b) vmp[tid] += M.b[tid];
       team_sync();
+    }
+    if (!GH && !P.Omd) {
+      // diagonal Omega_t: P^f = Omega S^{-1} Pp, m^f = omega - Omega S^{-1} w
+      const double* Om = P.Om + (int64_t)t * d;
+      R2 = Pp;
+      AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += Om[i];
+      if (tid < D) {
+        vom[tid] = (tid < d) ? Om[tid] : 0.0;
+        vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
+      }
+      double logdet;
+      ok = spd_inv<D>(R2, d, sbuf, &logdet) && ok;
+      rm_stage<D>(R2, B3);
+      rm_stage<D>(Pp, B1);
+      team_sync();
+      gemm<D, false, false, false>(Pm, B3, B1);  // S^{-1} Pp
+      matvec<D, false>(vs, B3, vw);
+      AKF_RM_FOR(D, q, r, i, j) Pm.t[q][r] *= vom[i];
+      const double rr = team_sum<D>(tid < D ? vw[tid] * vs[tid] : 0.0, red);
+      if (tid < D) vm[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vom[tid] * vs[tid] : 0.0;
+      if (tid == 0) P.ell[t] = -0.5 * (d * LOG2PI + logdet + rr);
+      rm_symmetrise<D>(Pm, B2);
+      if (P.mf) {
+        if (tid < d) P.mf[(int64_t)t * P.ldm + tid] = vm[tid];
+        rm_store<D>(Pm, P.Pf + (int64_t)t * P.ldm * P.ldm, P.ldm, d);
+      }
+      continue;
     }
     rm_stage<D>(Pp, B1);
     if constexpr (GH) {

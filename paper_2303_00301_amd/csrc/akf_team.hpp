@@ -177,23 +177,50 @@ __device__ __forceinline__ void gemm(RM<D>& c, const double* sA, const double* s
   }
 }
 
-// Rows and columns owned by this lane in the register layout: tile row ti,
-// register r -> row rows[ti][r]; tile column tj -> column cols[tj].
+// Pivot sweeps on a register matrix.  Sweeps run in groups of 16 (the pivot
+// index k = 16 kb + kk with kk unrolled), so the register that holds row k or
+// column k of a lane's tiles is known at compile time up to the tile index:
+//   row k    -> tile row kb - r0/16, register kk/4, lanes with l/16 == kk%4;
+//   column k -> tile column kb - c0/16, lanes with l%16 == kk.
 template <int D>
-struct Own {
-  int rows[Cfg<D>::TS][4];
-  int cols[Cfg<D>::TS];
-  __device__ __forceinline__ Own() {
+struct Sweep {
+  using C = Cfg<D>;
+  int r0, c0, lg, lc;
+  __device__ __forceinline__ Sweep() {
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    const int r0 = (D == 64) ? 32 * (w >> 1) : 0, c0 = (D == 64) ? 32 * (w & 1) : 0;
-#pragma unroll
-    for (int ti = 0; ti < Cfg<D>::TS; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) rows[ti][r] = r0 + 16 * ti + 4 * r + (l >> 4);
-#pragma unroll
-    for (int tj = 0; tj < Cfg<D>::TS; ++tj) cols[tj] = c0 + 16 * tj + (l & 15);
+    r0 = (D == 64) ? 32 * (w >> 1) : 0;
+    c0 = (D == 64) ? 32 * (w & 1) : 0;
+    lg = l >> 4;
+    lc = l & 15;
   }
+  __device__ __forceinline__ int row(int ti, int r) const { return r0 + 16 * ti + 4 * r + lg; }
+  __device__ __forceinline__ int col(int tj) const { return c0 + 16 * tj + lc; }
 };
+
+// element (ti, tj, r) of a register matrix with a runtime tile index ti or tj
+// (TS <= 2).  Both candidates are read as values before the select: a select
+// between two element lvalues would index the register array at run time and
+// push it to scratch memory.
+template <int D>
+__device__ __forceinline__ double rm_pick_row(const RM<D>& A, int ti, int tj, int r) {
+  if constexpr (Cfg<D>::TS == 1) {
+    return A.t[0][r];
+  } else {
+    const double a = static_cast<double>(A.t[tj][r]);
+    const double b = static_cast<double>(A.t[Cfg<D>::TS + tj][r]);
+    return ti ? b : a;
+  }
+}
+template <int D>
+__device__ __forceinline__ double rm_pick_col(const RM<D>& A, int ti, int tj, int r) {
+  if constexpr (Cfg<D>::TS == 1) {
+    return A.t[0][r];
+  } else {
+    const double a = static_cast<double>(A.t[ti * Cfg<D>::TS][r]);
+    const double b = static_cast<double>(A.t[ti * Cfg<D>::TS + 1][r]);
+    return tj ? b : a;
+  }
+}
 
 // In-place inverse of a symmetric positive definite matrix held in registers
 // (zero outside the leading d x d block) by d Gauss-Jordan sweeps:
@@ -208,49 +235,57 @@ struct Own {
 template <int D>
 __device__ bool spd_inv(RM<D>& A, int d, double* sbuf, double* logdet) {
   using C = Cfg<D>;
-  const Own<D> o;
+  const Sweep<D> o;
   bool ok = true;
-  double ld = 0.0, prod = 1.0;
-  for (int k = 0; k < d; ++k) {
-    double* sr = sbuf + (k & 1) * D;
-    double* sc = sbuf + 2 * D + (k & 1) * D;
+  double ld = 0.0;
+  for (int kb = 0; 16 * kb < d; ++kb) {
+    const int ti_k = kb - o.r0 / 16, tj_k = kb - o.c0 / 16;
+    const bool in_r = ti_k >= 0 && ti_k < C::TS, in_c = tj_k >= 0 && tj_k < C::TS;
+    double prod = 1.0;
 #pragma unroll
-    for (int ti = 0; ti < C::TS; ++ti)
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * kb + kk;
+      if (k >= d) continue;  // uniform; keeps the trip count constant for unrolling
+      double* sr = sbuf + (kk & 1) * D;
+      double* sc = sbuf + 2 * D + (kk & 1) * D;
+      const bool row_owner = in_r && o.lg == (kk & 3);
+      const bool col_owner = in_c && o.lc == kk;
+      if (row_owner) {
 #pragma unroll
-      for (int tj = 0; tj < C::TS; ++tj)
+        for (int tj = 0; tj < C::TS; ++tj) sr[o.col(tj)] = rm_pick_row<D>(A, ti_k, tj, kk >> 2);
+      }
+      if (col_owner) {
+#pragma unroll
+        for (int ti = 0; ti < C::TS; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sc[o.row(ti, r)] = rm_pick_col<D>(A, ti, tj_k, r);
+      }
+      team_sync();
+      const double p = sr[k];
+      ok = ok && (p > 0.0);
+      const double ip = (p > 0.0) ? 1.0 / p : 0.0;
+      prod *= (p > 0.0) ? p : 1.0;
+      double rk[C::TS];
+#pragma unroll
+      for (int tj = 0; tj < C::TS; ++tj) rk[tj] = sr[o.col(tj)];
+#pragma unroll
+      for (int ti = 0; ti < C::TS; ++ti) {
+        const bool rowk = row_owner && ti == ti_k;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = o.rows[ti][r], j = o.cols[tj];
-          if (i == k) sr[j] = A.t[ti * C::TS + tj][r];
-          if (j == k) sc[i] = A.t[ti * C::TS + tj][r];
-        }
-    team_sync();
-    const double p = sr[k];
-    ok = ok && (p > 0.0);
-    const double ip = (p > 0.0) ? 1.0 / p : 0.0;
-    prod *= (p > 0.0) ? p : 1.0;
-    if ((k & 15) == 15 || k == d - 1) {
-      ld += log(prod);
-      prod = 1.0;
-    }
-    double rk[C::TS];
+          const double f = -sc[o.row(ti, r)] * ip;
 #pragma unroll
-    for (int tj = 0; tj < C::TS; ++tj) rk[tj] = sr[o.cols[tj]];
-#pragma unroll
-    for (int ti = 0; ti < C::TS; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = o.rows[ti][r];
-        const double cik = sc[i];
-        const double f = -cik * ip;
-#pragma unroll
-        for (int tj = 0; tj < C::TS; ++tj) {
-          const int j = o.cols[tj];
-          const double v = A.t[ti * C::TS + tj][r];
-          A.t[ti * C::TS + tj][r] = (i == k) ? ((j == k) ? ip : rk[tj] * ip)
-                                             : ((j == k) ? f : fma(f, rk[tj], v));
+          for (int tj = 0; tj < C::TS; ++tj) {
+            const bool colk = col_owner && tj == tj_k;
+            double v = A.t[ti * C::TS + tj][r];
+            v = colk ? f : fma(f, rk[tj], v);
+            if (r == (kk >> 2)) v = rowk ? (colk ? ip : rk[tj] * ip) : v;
+            A.t[ti * C::TS + tj][r] = v;
+          }
         }
       }
+    }
+    ld += log(prod);
   }
   *logdet = ld;
   return ok;
@@ -266,50 +301,56 @@ __device__ bool spd_inv(RM<D>& A, int d, double* sbuf, double* logdet) {
 template <int D>
 __device__ bool chol_reg(RM<D>& A, int d, double* sbuf, double* logdet) {
   using C = Cfg<D>;
-  const Own<D> o;
+  const Sweep<D> o;
   bool ok = true;
-  double ld = 0.0, prod = 1.0;
-  for (int k = 0; k < d; ++k) {
-    double* sc = sbuf + (k & 1) * D;
+  double ld = 0.0;
+  for (int kb = 0; 16 * kb < d; ++kb) {
+    const int tj_k = kb - o.c0 / 16;
+    const bool in_c = tj_k >= 0 && tj_k < C::TS;
+    double prod = 1.0;
 #pragma unroll
-    for (int ti = 0; ti < C::TS; ++ti)
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 16 * kb + kk;
+      if (k >= d) continue;  // uniform; keeps the trip count constant for unrolling
+      double* sc = sbuf + (kk & 1) * D;
+      const bool col_owner = in_c && o.lc == kk;
+      if (col_owner) {
 #pragma unroll
-      for (int tj = 0; tj < C::TS; ++tj)
+        for (int ti = 0; ti < C::TS; ++ti)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) sc[o.row(ti, r)] = rm_pick_col<D>(A, ti, tj_k, r);
+      }
+      team_sync();
+      const double p = sc[k];
+      ok = ok && (p > 0.0);
+      const double pp = (p > 0.0) ? p : 1.0;
+      const double sq = sqrt(pp), is = 1.0 / sq;
+      prod *= pp;
+      double ljk[C::TS];
+#pragma unroll
+      for (int tj = 0; tj < C::TS; ++tj) {
+        const int j = o.col(tj);
+        const double scj = sc[j];  // loaded unconditionally: no branch per element
+        ljk[tj] = (j > k && j < d) ? scj * is : 0.0;
+      }
+#pragma unroll
+      for (int ti = 0; ti < C::TS; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = o.rows[ti][r], j = o.cols[tj];
-          if (j == k && i >= k) sc[i] = A.t[ti * C::TS + tj][r];
+          const int i = o.row(ti, r);
+          const double sci = sc[i];
+          const double lik = (i > k && i < d) ? sci * is : 0.0;
+#pragma unroll
+          for (int tj = 0; tj < C::TS; ++tj) {
+            const int j = o.col(tj);
+            const bool colk = col_owner && tj == tj_k;
+            const double v = A.t[ti * C::TS + tj][r];
+            A.t[ti * C::TS + tj][r] =
+                colk ? ((i == k) ? sq : lik) : ((j > k && i >= j) ? fma(-lik, ljk[tj], v) : v);
+          }
         }
-    team_sync();
-    const double p = sc[k];
-    ok = ok && (p > 0.0);
-    const double pp = (p > 0.0) ? p : 1.0;
-    const double sq = sqrt(pp), is = 1.0 / sq;
-    prod *= pp;
-    if ((k & 15) == 15 || k == d - 1) {
-      ld += log(prod);
-      prod = 1.0;
     }
-    double ljk[C::TS];
-#pragma unroll
-    for (int tj = 0; tj < C::TS; ++tj) {
-      const int j = o.cols[tj];
-      ljk[tj] = (j > k && j < d) ? sc[j] * is : 0.0;
-    }
-#pragma unroll
-    for (int ti = 0; ti < C::TS; ++ti)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = o.rows[ti][r];
-        const double lik = (i > k && i < d) ? sc[i] * is : 0.0;
-#pragma unroll
-        for (int tj = 0; tj < C::TS; ++tj) {
-          const int j = o.cols[tj];
-          const double v = A.t[ti * C::TS + tj][r];
-          A.t[ti * C::TS + tj][r] = (j == k) ? ((i == k) ? sq : lik)
-                                             : ((j > k && i >= j) ? fma(-lik, ljk[tj], v) : v);
-        }
-      }
+    ld += log(prod);
   }
   AKF_RM_FOR(D, q, r, i, j) if (j > i) A.t[q][r] = 0.0;
   *logdet = ld;  // log det A = sum_k log p_k (p_k = L_kk^2)

@@ -54,3 +54,17 @@ def test_fisher_score_directional_fd_larger():
         d /= np.linalg.norm(d)
         fd = (f(v0 + h * d) - f(v0 - h * d)) / (2 * h)
         assert abs(fd - g @ d) < 1e-5 * max(1.0, np.linalg.norm(g)), (fd, g @ d)
+
+
+@pytest.mark.parametrize("N,dx,dy,seed", [(1, 2, 1, 7), (6, 3, 2, 8), (8, 4, 3, 9)])
+def test_lgssm_loglik_vs_dense_joint_gaussian(N, dx, dy, seed):
+    """The theta-parameterised log-likelihood equals log N(y; E y, Cov y) of the
+    joint Gaussian with Q = diag(exp(logq)), R = diag(exp(logr))."""
+    from tests.oracle_util import dense_lgssm
+    pw = W.lgssm_params(N=N, dx=dx, dy=dy, seed=seed)
+    t0 = pw.theta0
+    Q = np.diag(np.exp(t0.logq))
+    R = np.diag(np.exp(t0.logr))
+    ll_dense = dense_lgssm(N, pw.m0, pw.P0, t0.F, Q, [t0.H] * N, [R] * N, pw.y)[0]
+    ll = oracle.lgssm_loglik(pw.m0, pw.P0, t0.F, t0.logq, t0.H, t0.logr, pw.y)
+    assert abs(ll - ll_dense) < 1e-9 * max(1.0, abs(ll_dense))
