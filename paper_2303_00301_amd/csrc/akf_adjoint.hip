@@ -236,7 +236,6 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   double* vm = B3 + C::MAT;
   double* vmp = vm + D;
   double* vg = vmp + D;
-  double* sbuf = vg + D;  // 4 D
   const int t = blockIdx.x, tid = threadIdx.x, d = M.d;
   RM<D> Pf, R1, R2;
   rm_load<D>(Pf, S.Pf + (int64_t)t * S.ldm * S.ldm, S.ldm, d);
@@ -261,7 +260,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   rm_add_load<D>(R2, M.Q, d, d);
   matvec<D, false>(vmp, sF, vm);
   if (tid < d && M.b) vmp[tid] += M.b[tid];
-  ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // (P^p)^{-1}
+  {
+    const RM<D> Pp = R2;
+    ok = spd_inv<D>(R2, d, B3, &ld) && ok;  // (P^p)^{-1}
+    inv_refine<D>(R2, Pp, d, B2, B3);       // P^p inherits the conditioning of Q
+  }
   rm_stage<D>(R2, B2);
   team_sync();
   gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
@@ -306,12 +309,12 @@ __global__ void __launch_bounds__(256) k_sum(const double* __restrict__ a, int n
 
 // Recompute the filter quantities of step t from the checkpoint:
 // Pp, mp (registers / LDS), B_HP <- H Pp, B_Si <- S^{-1} (Gauss-Jordan in
-// registers), vw <- w = S^{-1} v, vv <- v.  sbuf: 4 D doubles.  Team-wide;
+// registers), vw <- w = S^{-1} v, vv <- v.  scr: a free D x D LDS buffer.  Team-wide;
 // ends synchronised.
 template <int D>
 __device__ void adj_step_quantities(const KModel& M, const LgArgs& G, int t, const double* sF,
                                     const double* sH, double* B_HP, double* B_Si, double* Btmp,
-                                    RM<D>& Pp, double* vmp, double* vv, double* vw, double* sbuf,
+                                    RM<D>& Pp, double* vmp, double* vv, double* vw, double* scr,
                                     bool& ok) {
   const int tid = threadIdx.x, d = G.dx, p = G.dy;
   RM<D> R1;
@@ -343,7 +346,7 @@ __device__ void adj_step_quantities(const KModel& M, const LgArgs& G, int t, con
   matvec<D, false>(vv, sH, vmp);
   if (tid < D) vv[tid] = (tid < p) ? G.y[(int64_t)t * p + tid] - vv[tid] : 0.0;
   double ld;
-  ok = spd_inv<D>(R1, p, sbuf, &ld) && ok;  // S^{-1} (zero outside p x p)
+  ok = spd_inv<D>(R1, p, scr, &ld) && ok;  // S^{-1} (zero outside p x p)
   rm_stage<D>(R1, B_Si);
   team_sync();
   matvec<D, false>(vw, B_Si, vv);  // w = S^{-1} v
@@ -365,14 +368,13 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
   double* vmp = Bt + C::MAT;
   double* vv = vmp + D;
   double* vw = vv + D;
-  double* sbuf = vw + D;  // 4 D
   const int t = blockIdx.x, tid = threadIdx.x, d = G.dx, p = G.dy;
   lds_load_user<D>(sF, M.F, d, d);
   lds_load_user<D>(sH, G.H, p, d);
   team_sync();
   bool ok = true;
   RM<D> Pp, R1, R2;
-  adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, sbuf, ok);
+  adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, B_Li, ok);
   // h = H' w
   if (tid < D) {
     double s = 0.0;
@@ -450,7 +452,6 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
   double* vmb = vpf + D;   // mbar_{t+1}
   double* vq = vmb + D;    // accumulated dL/dQ_ii
   double* vr = vq + D;     // accumulated dL/dR_jj
-  double* sbuf = vr + D;   // 4 D
   const int blk = blockIdx.x, tid = threadIdx.x, d = G.dx, p = G.dy, N = M.N;
   const int s0 = blk * G.B, s1 = min(N, s0 + G.B);
   lds_load_user<D>(sF, M.F, d, d);
@@ -465,7 +466,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
   rm_zero<D>(gH);
   bool ok = true;
   for (int t = s0; t < s1; ++t) {
-    adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, sbuf, ok);
+    adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, B_Li, ok);
     const bool last = (t == N - 1);
     rm_load<D>(Pf, G.Pf + (int64_t)t * D * D, D, D);
     if (tid < D) {

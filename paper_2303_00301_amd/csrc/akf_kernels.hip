@@ -454,7 +454,6 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
   double* vw = vmu + D;                    // omega - mu  (GH: y - H mu)
   double* vs = vw + D;                     // S^{-1} w
   double* vom = vs + D;                    // diagonal Omega_t
-  double* sbuf = vom + D;                  // 4 D: pivot broadcast
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   const bool first = (s0 == 0);
@@ -506,7 +505,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
         vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
       }
       double logdet;
-      ok = spd_inv<D>(R2, d, sbuf, &logdet) && ok;  // R2 = S^{-1}
+      ok = spd_inv<D>(R2, d, B2, &logdet) && ok;  // R2 = S^{-1}
       rm_stage<D>(R2, B3);
       rm_stage<D>(Pp, B1);
       team_sync();
@@ -555,7 +554,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
       if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
     }
     double logdet;
-    ok = spd_inv<D>(R2, dobs, sbuf, &logdet) && ok;  // R2 = S^{-1}
+    ok = spd_inv<D>(R2, dobs, B2, &logdet) && ok;  // R2 = S^{-1}
     rm_stage<D>(R2, B3);
     team_sync();
     gemm<D, false, false, false>(R1, B3, B1);  // S^{-1} Mo
@@ -644,7 +643,6 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   double* vc = vbi + D;
   double* vw = vc + D;
   double* vk = vw + D;
-  double* sbuf = vk + D;  // 4 D
   const int k = item, tid = threadIdx.x, d = M.d;
   const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
   double* out = T.dst + (int64_t)k * EL::SIZE;
@@ -659,7 +657,7 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   rm_load<D>(R1, ei + EL::C, D, d);
   lds_load_pad<D>(S1, ej + EL::J);
   if (tid < D) vbi[tid] = ei[EL::b + tid];
-  ok = chol_reg<D>(R1, d, sbuf, &ld) && ok;  // R1 = L
+  ok = chol_reg<D>(R1, d, S3, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);                        // S0 = L
   team_sync();
   gemm<D, false, false, false>(R2, S1, S0);  // J_j L
@@ -667,7 +665,7 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   team_sync();
   gemm<D, true, false, false>(R2, S0, S2);  // L' J_j L
   AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
-  ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // W^{-1}
+  ok = spd_inv<D>(R2, d, S3, &ld) && ok;  // W^{-1}
   rm_stage<D>(R2, S2);
   team_sync();
   gemm<D, false, false, false>(R3, S0, S2);  // L W^{-1}
@@ -747,7 +745,6 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   double* vc = vm + D;
   double* vz = vc + D;
   double* vw = vz + D;
-  double* sbuf = vw + D;  // 4 D
   const int k = item, tid = threadIdx.x, d = M.d;
   const double* pin = T.pre_src + (int64_t)k * PL::SIZE;
   const bool ident = pin[PL::flag] != 0.0;
@@ -769,7 +766,7 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   rm_load<D>(R1, pin + PL::P, D, d);
   lds_load_pad<D>(S1, el + EL::J);
   if (tid < D) vm[tid] = pin[PL::m + tid];
-  ok = chol_reg<D>(R1, d, sbuf, &ld) && ok;  // R1 = L
+  ok = chol_reg<D>(R1, d, S3, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);
   team_sync();
   gemm<D, false, false, false>(R2, S1, S0);  // J L
@@ -777,7 +774,7 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   team_sync();
   gemm<D, true, false, false>(R2, S0, S2);  // L' J L
   AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
-  ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // W^{-1}
+  ok = spd_inv<D>(R2, d, S3, &ld) && ok;  // W^{-1}
   rm_stage<D>(R2, S2);
   team_sync();
   gemm<D, false, false, false>(R1, S0, S2);  // L W^{-1}
@@ -834,7 +831,6 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
   double* vs = vw + D;
   double* vom = vs + D;  // diagonal Omega_t
   double* red = vom + D;
-  double* sbuf = red + 8;  // 4 D
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   lds_load_mat<D>(sF, M.F, d);
@@ -876,7 +872,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
         vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
       }
       double logdet;
-      ok = spd_inv<D>(R2, d, sbuf, &logdet) && ok;
+      ok = spd_inv<D>(R2, d, B2, &logdet) && ok;
       rm_stage<D>(R2, B3);
       rm_stage<D>(Pp, B1);
       team_sync();
@@ -916,7 +912,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       if (tid < D) vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmp[tid] : 0.0;
     }
     double logdet;
-    ok = spd_inv<D>(R2, dobs, sbuf, &logdet) && ok;
+    ok = spd_inv<D>(R2, dobs, B2, &logdet) && ok;
     rm_stage<D>(R2, B3);
     team_sync();
     gemm<D, false, false, false>(T, B3, B1);  // S^{-1} Mo
@@ -965,7 +961,6 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   double* vmp = vm + D;
   double* vg = vmp + D;
   double* vxi = vg + D;
-  double* sbuf = vxi + D;  // 4 D
   const int t = item, tid = threadIdx.x, d = M.d;
   RM<D> Pf, R1, R2;
   rm_load<D>(Pf, S.Pf + (int64_t)t * S.ldm * S.ldm, S.ldm, d);
@@ -976,7 +971,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   bool ok = true;
   double ld;
   if (t == M.N - 1) {
-    ok = chol_reg<D>(Pf, d, sbuf, &ld);
+    ok = chol_reg<D>(Pf, d, B3, &ld);
     rm_stage<D>(Pf, B2);
     team_sync();
     if (tid < D) {
@@ -999,7 +994,11 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     rm_add_load<D>(R2, M.Q, d, d);
     matvec<D, false>(vmp, sF, vm);
     if (tid < d && M.b) vmp[tid] += M.b[tid];
-    ok = spd_inv<D>(R2, d, sbuf, &ld) && ok;  // (P^p)^{-1}
+    {
+      const RM<D> Pp = R2;
+      ok = spd_inv<D>(R2, d, B3, &ld) && ok;  // (P^p)^{-1}
+      inv_refine<D>(R2, Pp, d, B2, B3);       // P^p inherits the conditioning of Q
+    }
     rm_stage<D>(R2, B2);
     team_sync();
     gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
@@ -1011,7 +1010,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     matvec<D, false>(vg, B3, vmp);
     if (tid < D) vg[tid] = vm[tid] - vg[tid];  // g = m^f - E m^p
     rm_symmetrise<D>(R2, B2);
-    ok = chol_reg<D>(R2, d, sbuf, &ld) && ok;
+    ok = chol_reg<D>(R2, d, B3, &ld) && ok;
     rm_stage<D>(R2, B2);
     team_sync();
     if (tid < D) {

@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 namespace akf {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -177,26 +179,6 @@ __device__ __forceinline__ void gemm(RM<D>& c, const double* sA, const double* s
   }
 }
 
-// Pivot sweeps on a register matrix.  Sweeps run in groups of 16 (the pivot
-// index k = 16 kb + kk with kk unrolled), so the register that holds row k or
-// column k of a lane's tiles is known at compile time up to the tile index:
-//   row k    -> tile row kb - r0/16, register kk/4, lanes with l/16 == kk%4;
-//   column k -> tile column kb - c0/16, lanes with l%16 == kk.
-template <int D>
-struct Sweep {
-  using C = Cfg<D>;
-  int r0, c0, lg, lc;
-  __device__ __forceinline__ Sweep() {
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    r0 = (D == 64) ? 32 * (w >> 1) : 0;
-    c0 = (D == 64) ? 32 * (w & 1) : 0;
-    lg = l >> 4;
-    lc = l & 15;
-  }
-  __device__ __forceinline__ int row(int ti, int r) const { return r0 + 16 * ti + 4 * r + lg; }
-  __device__ __forceinline__ int col(int tj) const { return c0 + 16 * tj + lc; }
-};
-
 // element (ti, tj, r) of a register matrix with a runtime tile index ti or tj
 // (TS <= 2).  Both candidates are read as values before the select: a select
 // between two element lvalues would index the register array at run time and
@@ -222,138 +204,353 @@ __device__ __forceinline__ double rm_pick_col(const RM<D>& A, int ti, int tj, in
   }
 }
 
-// In-place inverse of a symmetric positive definite matrix held in registers
-// (zero outside the leading d x d block) by d Gauss-Jordan sweeps:
-//   p = A_kk;  A_kk <- 1/p;  A_kj <- A_kj/p;  A_ik <- -A_ik/p;
-//   A_ij <- A_ij - A_ik A_kj / p            (i, j != k)
-// The pivots p are those of the LDL' factorisation, so the matrix is PD iff
-// all are > 0 and log det = sum log p.  Pivot row/column are broadcast through
-// sbuf (4*D doubles of LDS, double-buffered: one barrier per sweep).  Returns
-// false on a non-positive pivot (the result is then unspecified).  On entry no
-// thread of the team may still be reading sbuf (a barrier separates any
-// earlier use); the leading barrier also publishes earlier LDS writes.
-template <int D>
-__device__ bool spd_inv(RM<D>& A, int d, double* sbuf, double* logdet) {
-  using C = Cfg<D>;
-  const Sweep<D> o;
-  bool ok = true;
-  double ld = 0.0;
-  for (int kb = 0; 16 * kb < d; ++kb) {
-    const int ti_k = kb - o.r0 / 16, tj_k = kb - o.c0 / 16;
-    const bool in_r = ti_k >= 0 && ti_k < C::TS, in_c = tj_k >= 0 && tj_k < C::TS;
-    double prod = 1.0;
+// 16 x 16 x 16 tile product on one wave: c + A B with the operands given as
+// per-k-step fragments: a[s] = A[l%16][4s + l/16], b[s] = B[4s + l/16][l%16].
+// In the accumulator layout, register s of a tile M is M[4s + l/16][l%16], so
+// the registers of M are its own B fragments and the A fragments of M'.
+__device__ __forceinline__ dbl4 mfma16(const double a[4], const double b[4], dbl4 c) {
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = 16 * kb + kk;
-      if (k >= d) continue;  // uniform; keeps the trip count constant for unrolling
-      double* sr = sbuf + (kk & 1) * D;
-      double* sc = sbuf + 2 * D + (kk & 1) * D;
-      const bool row_owner = in_r && o.lg == (kk & 3);
-      const bool col_owner = in_c && o.lc == kk;
-      if (row_owner) {
+  for (int s = 0; s < 4; ++s) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], b[s], c, 0, 0, 0);
+  return c;
+}
+__device__ __forceinline__ void tile_regs(const dbl4& t, double x[4]) {
 #pragma unroll
-        for (int tj = 0; tj < C::TS; ++tj) sr[o.col(tj)] = rm_pick_row<D>(A, ti_k, tj, kk >> 2);
+  for (int s = 0; s < 4; ++s) x[s] = t[s];
+}
+
+// log-determinant accumulator: mantissa product and binary exponent sum
+struct LogDet {
+  double m = 1.0;
+  int e = 0;
+  __device__ __forceinline__ void mul(double x) {
+    int ex;
+    m = frexp(m * x, &ex);
+    e += ex;
+  }
+  __device__ __forceinline__ double value() const { return log(m) + e * 0.69314718055994530942; }
+};
+
+// f(integral_constant<int, K>) for K = B .. E-1 (compile-time loop)
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Broadcast of lane K of every row of 16 lanes to the whole row (DPP
+// row_newbcast), for a double.
+template <int K>
+__device__ __forceinline__ double row_bcast(double v) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x150 + K, 0xF, 0xF, true);
+  const uint32_t hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x150 + K, 0xF, 0xF, true);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// v from lane src of the wave (ds_bpermute; no LDS memory involved)
+__device__ __forceinline__ double lane_fetch(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(u >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// 1/q for q > 0: hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - q r) (each step squares the relative error).
+__device__ __forceinline__ double recip(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  r = fma(r, fma(-q, r, 1.0), r);
+  r = fma(r, fma(-q, r, 1.0), r);
+  return r;
+}
+
+// One wave inverts a symmetric positive definite 16 x 16 tile held in the
+// accumulator layout (p[r] = P[4r + l/16][l%16]) by 16 steps of the symmetric
+// sweep operator: with c = column k of the current matrix and pivot q = c_k,
+//   a_ij <- a_ij - c_i c_j / q (i, j != k),  a_ik = a_ki <- c_i / q,  a_kk <- -1/q,
+// which leaves -P^{-1}.  The matrix stays symmetric, so column k is also row k.
+// Column k reaches the lanes of each row of 16 by a DPP row broadcast of lane
+// k (c_i for the lane's rows i = 4r + l/16), row k by a lane permute (c_j for
+// the lane's column j = l%16), the pivot by a lane read.  Every element update
+// is one FMA: a' = f_i r_j + [i != k, j != k] a with f_i = -c_i/q (f_k = 1/q)
+// and r_j = c_j (r_k = -1).  The pivots are those of the LDL' factorisation;
+// with CHOL the lower Cholesky factor is captured on the way
+// (L_ik = c_i / sqrt(q), i >= k).  Indices >= nv are padding: they get a unit
+// diagonal.
+template <bool CHOL>
+__device__ __forceinline__ void tile_sweep16(double p[4], int nv, double Lk[4], LogDet& ld,
+                                             bool& ok) {
+  const int l = threadIdx.x & 63, lg = l >> 4, lc = l & 15;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (4 * r + lg >= nv && 4 * r + lg == lc) p[r] = 1.0;
+    if constexpr (CHOL) Lk[r] = 0.0;
+  }
+  auto step = [&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    double ci[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) ci[r] = row_bcast<k>(p[r]);
+    const double q = lane_bcast(p[k >> 2], 16 * (k & 3) + k);
+    const double cj = lane_fetch(p[k >> 2], 16 * (k & 3) + lc);
+    const bool pos = q > 0.0;
+    ok = ok && pos;
+    const double iq = pos ? recip(q) : 0.0;
+    ld.mul(pos ? q : 1.0);
+    const bool jk = (lc == k);
+    const double rj = jk ? -1.0 : cj;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const bool ik = (r == (k >> 2)) && (lg == (k & 3));
+      const double fi = ik ? iq : -ci[r] * iq;
+      const double v = (ik || jk) ? 0.0 : p[r];
+      p[r] = fma(fi, rj, v);
+    }
+    if constexpr (CHOL) {
+      const double isq = pos ? sqrt(iq) : 0.0;
+      const double sq = q * isq;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 4 * r + lg;
+        const double lv = (i > k) ? ci[r] * isq : ((i == k) ? sq : 0.0);
+        Lk[r] = jk ? lv : Lk[r];
       }
-      if (col_owner) {
+    }
+  };
+  static_for<0, 16>(step);
 #pragma unroll
-        for (int ti = 0; ti < C::TS; ++ti)
+  for (int r = 0; r < 4; ++r) p[r] = -p[r];
+}
+
+// G = L^{-T} for a 16 x 16 tile from its Cholesky factor (Lk, acc layout) and
+// the inverse of the tile (ainv, symmetric): G0 = A^{-1} L, then one Newton
+// step G = G0 + G0 (I - L' G0), with L^{-1} ~ L' A^{-1} as G0' in the
+// correction.  Forming L^{-T} through A^{-1} alone loses accuracy with the
+// conditioning of the tile; the Newton step restores it.
+__device__ __forceinline__ void chol_tile_rinv(const double ainv[4], const double Lk[4],
+                                               double G[4]) {
+  const int l = threadIdx.x & 63, lg = l >> 4, lc = l & 15;
+  const dbl4 z = {0.0, 0.0, 0.0, 0.0};
+  double H[4], R[4];
+  tile_regs(mfma16(ainv, Lk, z), G);  // A^{-1} L  (acc of L^{-T})
+  tile_regs(mfma16(Lk, ainv, z), H);  // L' A^{-1} (acc of L^{-1})
+  const dbl4 T = mfma16(Lk, G, z);    // L' G ~ I
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sc[o.row(ti, r)] = rm_pick_col<D>(A, ti, tj_k, r);
+  for (int r = 0; r < 4; ++r) R[r] = ((4 * r + lg == lc) ? 1.0 : 0.0) - T[r];
+  dbl4 g = {G[0], G[1], G[2], G[3]};
+  tile_regs(mfma16(H, R, g), G);  // G + G (I - L' G)
+}
+
+// One Newton-Schulz step X <- X + X (I - A X) on an approximate inverse X of
+// the register matrix A (both zero outside the leading d x d block): squares
+// the residual, so an inverse accurate to r relative becomes accurate to
+// ~cond(A) r^2 plus rounding.  s1, s2: free LDS matrices.  Team-wide; ends
+// synchronised.
+template <int D>
+__device__ void inv_refine(RM<D>& X, const RM<D>& A, int d, double* s1, double* s2) {
+  team_sync();
+  rm_stage<D>(X, s1);
+  rm_stage<D>(A, s2);
+  team_sync();
+  RM<D> T;
+  gemm<D, false, false, false>(T, s2, s1);  // A X
+  AKF_RM_FOR(D, q, r, i, j) T.t[q][r] = ((i == j && i < d) ? 1.0 : 0.0) - T.t[q][r];
+  team_sync();
+  rm_stage<D>(T, s2);
+  team_sync();
+  gemm<D, false, false, true>(X, s1, s2);  // X + X (I - A X)
+  team_sync();
+}
+
+// LDS scratch (doubles) needed by spd_inv and chol_reg: the staged block row
+// or column, double-buffered across waves (none at D = 16: one tile).
+template <int D>
+constexpr int inv_scratch() {
+  using C = Cfg<D>;
+  constexpr int nbuf = C::NW > 1 ? 2 : 1;
+  constexpr int rows = nbuf * 16 * (D + 1), cols = nbuf * D * 17;
+  return D == 16 ? 0 : (rows > cols ? rows : cols);
+}
+
+// In-place inverse of a symmetric positive definite matrix held in registers
+// (zero outside the leading d x d block) by block Gauss-Jordan elimination
+// with 16 x 16 pivot blocks P = A_KK:
+//   A_KK <- P^{-1},  A_KJ <- P^{-1} A_KJ,  A_IK <- -A_IK P^{-1},
+//   A_IJ <- A_IJ - A_IK P^{-1} A_KJ.
+// The pivot block is inverted by every wave (tile_sweep16); the block row K
+// is staged through LDS and every other product is a 16 x 16 x 16 MFMA chain.
+// The elimination keeps A_IK = s_I A_KI' (s_I = -1 for processed blocks I < K,
+// +1 otherwise), so A_IK P^{-1} = s_I (P^{-1} A_KI)' needs only block row K.
+// Returns false on a non-positive pivot (the result is then unspecified);
+// *logdet = log det A from the pivots.  scr: inv_scratch<D>() doubles of LDS,
+// free at entry; the call begins and ends with a team barrier.
+template <int D>
+__device__ bool spd_inv(RM<D>& A, int d, double* scr, double* logdet) {
+  using C = Cfg<D>;
+  static_assert(inv_scratch<D>() <= C::MAT, "scratch must fit one LDS matrix");
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lg = l >> 4, lc = l & 15;
+  bool ok = true;
+  LogDet ld;
+  team_sync();
+  if constexpr (D == 16) {
+    double p[4], dummy[4];
+    tile_regs(A.t[0], p);
+    tile_sweep16<false>(p, d, dummy, ld, ok);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) A.t[0][r] = p[r];
+  } else {
+    constexpr int nbuf = C::NW > 1 ? 2 : 1, LDR = D + 1;
+    const int R0 = (D == 64) ? 2 * (w >> 1) : 0, C0 = (D == 64) ? 2 * (w & 1) : 0;
+    const int nb = (d + 15) / 16;
+    for (int kb = 0; kb < nb; ++kb) {
+      double* BR = scr + (kb % nbuf) * 16 * LDR;
+      const int ti_k = kb - R0;
+      if (ti_k >= 0 && ti_k < C::TS) {
+#pragma unroll
+        for (int tj = 0; tj < C::TS; ++tj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            BR[(4 * r + lg) * LDR + 16 * (C0 + tj) + lc] = rm_pick_row<D>(A, ti_k, tj, r);
       }
       team_sync();
-      const double p = sr[k];
-      ok = ok && (p > 0.0);
-      const double ip = (p > 0.0) ? 1.0 / p : 0.0;
-      prod *= (p > 0.0) ? p : 1.0;
-      double rk[C::TS];
+      auto brow = [&](int T, double x[4]) {  // B fragments of A_KT
 #pragma unroll
-      for (int tj = 0; tj < C::TS; ++tj) rk[tj] = sr[o.col(tj)];
+        for (int s = 0; s < 4; ++s) x[s] = BR[(4 * s + lg) * LDR + 16 * T + lc];
+      };
+      double pv[4], dummy[4];
+      brow(kb, pv);
+      tile_sweep16<false>(pv, d - 16 * kb, dummy, ld, ok);  // pv = P^{-1}
+      const dbl4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ti = 0; ti < C::TS; ++ti) {
-        const bool rowk = row_owner && ti == ti_k;
+        const int TI = R0 + ti;
+        const double sI = (TI < kb) ? -1.0 : 1.0;
+        double bi[4], xa[4];
+        brow(TI, bi);
+        if (TI != kb) {
+          const dbl4 xr = mfma16(pv, bi, z);  // P^{-1} A_KI
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const double f = -sc[o.row(ti, r)] * ip;
+          for (int s = 0; s < 4; ++s) xa[s] = -sI * xr[s];
+        }
 #pragma unroll
-          for (int tj = 0; tj < C::TS; ++tj) {
-            const bool colk = col_owner && tj == tj_k;
-            double v = A.t[ti * C::TS + tj][r];
-            v = colk ? f : fma(f, rk[tj], v);
-            if (r == (kk >> 2)) v = rowk ? (colk ? ip : rk[tj] * ip) : v;
-            A.t[ti * C::TS + tj][r] = v;
+        for (int tj = 0; tj < C::TS; ++tj) {
+          const int TJ = C0 + tj, q = ti * C::TS + tj;
+          if (TI == kb && TJ == kb) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) A.t[q][r] = pv[r];
+          } else if (TI == kb) {
+            double bj[4];
+            brow(TJ, bj);
+            A.t[q] = mfma16(pv, bj, z);  // P^{-1} A_KJ
+          } else if (TJ == kb) {
+            const dbl4 y = mfma16(bi, pv, z);  // A_KI' P^{-1}
+            A.t[q] = -sI * y;
+          } else {
+            double bj[4];
+            brow(TJ, bj);
+            A.t[q] = mfma16(xa, bj, A.t[q]);  // A_IJ - s_I (P^{-1} A_KI)' A_KJ
           }
         }
       }
     }
-    ld += log(prod);
   }
-  *logdet = ld;
+  AKF_RM_FOR(D, q, r, i, j) if (i >= d || j >= d) A.t[q][r] = 0.0;
+  team_sync();
+  *logdet = ld.value();
   return ok;
 }
 
 // Lower Cholesky factor (positive diagonal) of a symmetric positive definite
 // matrix held in registers (zero outside the leading d x d block), in place,
-// right-looking: column k is scaled by 1/sqrt(A_kk) and broadcast through
-// sbuf (2*D doubles, double-buffered), then the trailing lower triangle is
-// updated.  The strict upper triangle is zeroed.  Returns false on a
-// non-positive pivot; *logdet gets log det of the matrix.  Same sbuf entry
-// condition as spd_inv.
+// blocked right-looking with 16-column panels: the diagonal block is factored
+// by every wave (tile_sweep16, which also yields A_KK^{-1}); the panel is
+// L_IK = A_IK L_KK^{-T} (chol_tile_rinv); the trailing lower blocks get
+// A_IJ -= L_IK L_JK'.  The block column K is staged through LDS; products are
+// 16 x 16 x 16 MFMA chains.  The strict upper triangle is zeroed.  Returns
+// false on a non-positive pivot; *logdet = log det A.  Same scr contract as
+// spd_inv.
 template <int D>
-__device__ bool chol_reg(RM<D>& A, int d, double* sbuf, double* logdet) {
+__device__ bool chol_reg(RM<D>& A, int d, double* scr, double* logdet) {
   using C = Cfg<D>;
-  const Sweep<D> o;
+  static_assert(inv_scratch<D>() <= C::MAT, "scratch must fit one LDS matrix");
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lg = l >> 4, lc = l & 15;
   bool ok = true;
-  double ld = 0.0;
-  for (int kb = 0; 16 * kb < d; ++kb) {
-    const int tj_k = kb - o.c0 / 16;
-    const bool in_c = tj_k >= 0 && tj_k < C::TS;
-    double prod = 1.0;
+  LogDet ld;
+  team_sync();
+  if constexpr (D == 16) {
+    double p[4], Lk[4];
+    tile_regs(A.t[0], p);
+    tile_sweep16<true>(p, d, Lk, ld, ok);
 #pragma unroll
-    for (int kk = 0; kk < 16; ++kk) {
-      const int k = 16 * kb + kk;
-      if (k >= d) continue;  // uniform; keeps the trip count constant for unrolling
-      double* sc = sbuf + (kk & 1) * D;
-      const bool col_owner = in_c && o.lc == kk;
-      if (col_owner) {
+    for (int r = 0; r < 4; ++r) A.t[0][r] = Lk[r];
+  } else {
+    constexpr int nbuf = C::NW > 1 ? 2 : 1, LDC = 17;
+    const int R0 = (D == 64) ? 2 * (w >> 1) : 0, C0 = (D == 64) ? 2 * (w & 1) : 0;
+    const int nb = (d + 15) / 16;
+    for (int kb = 0; kb < nb; ++kb) {
+      double* BC = scr + (kb % nbuf) * D * LDC;
+      const int tj_k = kb - C0;
+      if (tj_k >= 0 && tj_k < C::TS) {
 #pragma unroll
         for (int ti = 0; ti < C::TS; ++ti)
+          if (R0 + ti >= kb) {
 #pragma unroll
-          for (int r = 0; r < 4; ++r) sc[o.row(ti, r)] = rm_pick_col<D>(A, ti, tj_k, r);
+            for (int r = 0; r < 4; ++r)
+              BC[(16 * (R0 + ti) + 4 * r + lg) * LDC + lc] = rm_pick_col<D>(A, ti, tj_k, r);
+          }
       }
       team_sync();
-      const double p = sc[k];
-      ok = ok && (p > 0.0);
-      const double pp = (p > 0.0) ? p : 1.0;
-      const double sq = sqrt(pp), is = 1.0 / sq;
-      prod *= pp;
-      double ljk[C::TS];
+      auto bcolt = [&](int T, double x[4]) {  // A fragments of A_TK (= B fragments of A_TK')
 #pragma unroll
-      for (int tj = 0; tj < C::TS; ++tj) {
-        const int j = o.col(tj);
-        const double scj = sc[j];  // loaded unconditionally: no branch per element
-        ljk[tj] = (j > k && j < d) ? scj * is : 0.0;
+        for (int s = 0; s < 4; ++s) x[s] = BC[(16 * T + lc) * LDC + 4 * s + lg];
+      };
+      double pv[4], Lk[4], G[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pv[r] = BC[(16 * kb + 4 * r + lg) * LDC + lc];
+      tile_sweep16<true>(pv, d - 16 * kb, Lk, ld, ok);  // pv = A_KK^{-1}, Lk = L_KK
+      const dbl4 z = {0.0, 0.0, 0.0, 0.0};
+      chol_tile_rinv(pv, Lk, G);  // G = L_KK^{-T}
+      double LTr[C::TS][4], LTc[C::TS][4];  // (L_TK)' for the wave's row / column tiles
+#pragma unroll
+      for (int t = 0; t < C::TS; ++t) {
+        if (R0 + t > kb) {
+          double a[4];
+          bcolt(R0 + t, a);
+          tile_regs(mfma16(G, a, z), LTr[t]);
+#pragma unroll
+          for (int s = 0; s < 4; ++s) LTr[t][s] = -LTr[t][s];
+        }
+        if (C0 + t > kb) {
+          double a[4];
+          bcolt(C0 + t, a);
+          tile_regs(mfma16(G, a, z), LTc[t]);
+        }
       }
 #pragma unroll
-      for (int ti = 0; ti < C::TS; ++ti)
+      for (int ti = 0; ti < C::TS; ++ti) {
+        const int TI = R0 + ti;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = o.row(ti, r);
-          const double sci = sc[i];
-          const double lik = (i > k && i < d) ? sci * is : 0.0;
+        for (int tj = 0; tj < C::TS; ++tj) {
+          const int TJ = C0 + tj, q = ti * C::TS + tj;
+          if (TI == kb && TJ == kb) {
 #pragma unroll
-          for (int tj = 0; tj < C::TS; ++tj) {
-            const int j = o.col(tj);
-            const bool colk = col_owner && tj == tj_k;
-            const double v = A.t[ti * C::TS + tj][r];
-            A.t[ti * C::TS + tj][r] =
-                colk ? ((i == k) ? sq : lik) : ((j > k && i >= j) ? fma(-lik, ljk[tj], v) : v);
+            for (int r = 0; r < 4; ++r) A.t[q][r] = Lk[r];
+          } else if (TJ == kb && TI > kb) {
+            double a[4];
+            bcolt(TI, a);
+            A.t[q] = mfma16(a, G, z);  // L_IK = A_IK G
+          } else if (TI > kb && TJ > kb && TI >= TJ) {
+            A.t[q] = mfma16(LTr[ti], LTc[tj], A.t[q]);  // A_IJ - L_IK L_JK'
           }
         }
+      }
     }
-    ld += log(prod);
   }
-  AKF_RM_FOR(D, q, r, i, j) if (j > i) A.t[q][r] = 0.0;
-  *logdet = ld;  // log det A = sum_k log p_k (p_k = L_kk^2)
+  AKF_RM_FOR(D, q, r, i, j) if (j > i || i >= d) A.t[q][r] = 0.0;
+  team_sync();
+  *logdet = ld.value();
   return ok;
 }
 

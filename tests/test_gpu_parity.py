@@ -20,6 +20,11 @@ pytestmark = pytest.mark.gpu
 MEAN_TOL = 1e-8      # FP64 path; the stated bar is 1e-4
 COV_TOL = 1e-8
 ELL_TOL = 1e-8       # per step, relative to max(1, |ell|); the stated bar is 1e-3 absolute
+# The log ratio is a difference of two N-step log-likelihoods plus sums of N*d
+# terms; in FP64 with condition numbers up to ~1e7 each (time step, coordinate)
+# contributes up to ~1e-9.  The stated bar (1e-3 per step on each
+# log-likelihood) would allow ~2e-3 N.
+LR_TOL_PER_TD = 1e-9
 TIE_BAND = 1e-6
 
 
@@ -120,12 +125,13 @@ def _compare_step(S, M_or, M_dev, y, x, delta, order, xi, un, block=0):
     lr = float(N_(out["log_ratio"])[0])
     if r["status"] == 0:
         lr_ref = r["log_ratio"]
-        assert abs(lr - lr_ref) <= 1e-7 * max(1.0, abs(lr_ref)), (lr, lr_ref)
-        N = y.shape[0]
+        N, d = x.shape
+        lr_tol = LR_TOL_PER_TD * N * d + 1e-9 * max(1.0, abs(lr_ref))
+        assert abs(lr - lr_ref) <= lr_tol, (lr, lr_ref, lr_tol)
         for k in ("logZ_fwd", "logZ_rev"):
             g = float(N_(out[k])[0])
             assert abs(g - r[k]) <= ELL_TOL * max(1.0, abs(r[k])) + 1e-9 * N, (k, g, r[k])
-        if abs(np.log(un) - lr_ref) > TIE_BAND:
+        if abs(np.log(un) - lr_ref) > max(TIE_BAND, lr_tol):
             assert acc == r["accepted"]
         x_exp = r["x_out"] if acc == r["accepted"] else (r["xstar"] if acc else x)
     else:
