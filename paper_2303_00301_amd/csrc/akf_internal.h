@@ -59,7 +59,9 @@ struct FilterArgs {
   const double* Om;   // diagonal Omega [N*d]
   const double* Omd;  // dense constant Omega [d*d] or nullptr
   double* elem;       // block elements, level 0 of the tree
-  const double* pre;  // prefixes entering each block
+  const double* pre;  // prefixes entering each block (PrefLayout), or
+  const double* pre_elem;  // inclusive scan elements: block k starts from
+                           // element k-1 read as a moment pair (b, C)
   double *mf, *Pf;    // [N*ldm], [N*ldm*ldm] or nullptr
   int ldm;            // leading dimension of mf/Pf (D inside the step, d for callers)
   double* ell;        // [N]
@@ -78,6 +80,16 @@ struct TreeArgs {
   int n_src, n_dst;
   const double* pre_src;
   double* pre_dst;
+  int* status;
+  int fail_bit;
+};
+
+// One level of the Hillis-Steele scan over block elements:
+// dst[k] = src[k - s] (x) src[k] for k >= s, dst[k] = src[k] otherwise.
+struct HsArgs {
+  const double* src;
+  double* dst;
+  int n, s;
   int* status;
   int fail_bit;
 };
@@ -187,6 +199,8 @@ enum {
 // Called by the launchers before (begin = 1) and after (begin = 0) each launch.
 void timing_mark(int family, int begin, hipStream_t st);
 
+hipError_t launch_filter_scan_any(int D, const KModel& M, FilterArgs P, const HsArgs* lv,
+                                  int n_levels, hipStream_t st);
 hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, TreeArgs* down,
                              int n_levels, hipStream_t st);
 hipError_t launch_sampler_any(int D, const KModel& M, SampArgs S, TreeArgs* up, TreeArgs* down,

@@ -631,7 +631,10 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 // Kalman filter").
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& T, int item) {
+__device__ __forceinline__ void filter_combine(const KModel& M, const double* __restrict__ ei,
+                                               const double* __restrict__ ej,
+                                               double* __restrict__ out, int* status,
+                                               int fail_bit) {
   using C = Cfg<D>;
   using EL = ElemLayout<D>;
   extern __shared__ double lds[];
@@ -643,14 +646,7 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   double* vc = vbi + D;
   double* vw = vc + D;
   double* vk = vw + D;
-  const int k = item, tid = threadIdx.x, d = M.d;
-  const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
-  double* out = T.dst + (int64_t)k * EL::SIZE;
-  if (2 * k + 1 >= T.n_src) {
-    for (int e = tid; e < EL::SIZE; e += C::NT) out[e] = ei[e];
-    return;
-  }
-  const double* ej = ei + EL::SIZE;
+  const int tid = threadIdx.x, d = M.d;
   bool ok = true;
   double ld;
   RM<D> R1, R2, R3;
@@ -714,7 +710,20 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
   if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
   rm_symmetrise<D>(R3, S1);
   rm_store<D>(R3, out + EL::C, D, D);
-  if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
+  if (!ok && tid == 0) flag_status(status, fail_bit);
+}
+
+template <int D>
+__device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& T, int item) {
+  using EL = ElemLayout<D>;
+  const int k = item, tid = threadIdx.x;
+  const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
+  double* out = T.dst + (int64_t)k * EL::SIZE;
+  if (2 * k + 1 >= T.n_src) {
+    for (int e = tid; e < EL::SIZE; e += Cfg<D>::NT) out[e] = ei[e];
+    return;
+  }
+  filter_combine<D>(M, ei, ei + EL::SIZE, out, T.status, T.fail_bit);
 }
 
 template <int D>
@@ -726,16 +735,19 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) 
 // Filter, phase 2 down-sweep: the prefix entering node k of a level is known
 // (pre_src, as a filtering moment pair (m, P), or the identity for the left
 // spine).  Its children: left gets the same prefix, right gets
-// prefix (x) element(left child).  For a moment pair (m, P) with P = L L',
-// W = I + L' J L and M = L W^{-1} L' = (P^{-1} + J)^{-1}:
-//   m' = A (m + M (eta - J m)) + b,   P' = A M A' + C.
-// With the identity prefix the result is the left child's (b, C) (its A = 0).
+// prefix (x) element(left child) (moment_combine).  With the identity prefix
+// the result is the left child's (b, C) (its A = 0).
 // ---------------------------------------------------------------------------
+// Moment pair (m, P) (x) element el -> (m', P'), written to mout / Pout:
+// with P = L L', W = I + L' J L and M = L W^{-1} L' = (P^{-1} + J)^{-1},
+//   m' = A (m + M (eta - J m)) + b,   P' = A M A' + C.
 template <int D>
-__device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs& T, int item) {
+__device__ __forceinline__ void moment_combine(const KModel& M, const double* Pin,
+                                               const double* min_, const double* el,
+                                               double* Pout, double* mout, int* status,
+                                               int fail_bit) {
   using C = Cfg<D>;
   using EL = ElemLayout<D>;
-  using PL = PrefLayout<D>;
   extern __shared__ double lds[];
   double* S0 = lds;
   double* S1 = S0 + C::MAT;
@@ -745,27 +757,13 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   double* vc = vm + D;
   double* vz = vc + D;
   double* vw = vz + D;
-  const int k = item, tid = threadIdx.x, d = M.d;
-  const double* pin = T.pre_src + (int64_t)k * PL::SIZE;
-  const bool ident = pin[PL::flag] != 0.0;
-  // left child: same prefix
-  double* pl = T.pre_dst + (int64_t)(2 * k) * PL::SIZE;
-  for (int e = tid; e < PL::SIZE; e += C::NT) pl[e] = pin[e];
-  if (2 * k + 1 >= T.n_dst) return;
-  double* pr = T.pre_dst + (int64_t)(2 * k + 1) * PL::SIZE;
-  const double* el = T.src + (int64_t)(2 * k) * EL::SIZE;  // left child's element
-  if (ident) {
-    for (int e = tid; e < D * D; e += C::NT) pr[PL::P + e] = el[EL::C + e];
-    if (tid < D) pr[PL::m + tid] = el[EL::b + tid];
-    if (tid == 0) pr[PL::flag] = 0.0;
-    return;
-  }
+  const int tid = threadIdx.x, d = M.d;
   bool ok = true;
   double ld;
   RM<D> R1, R2;
-  rm_load<D>(R1, pin + PL::P, D, d);
+  rm_load<D>(R1, Pin, D, d);
   lds_load_pad<D>(S1, el + EL::J);
-  if (tid < D) vm[tid] = pin[PL::m + tid];
+  if (tid < D) vm[tid] = min_[tid];
   ok = chol_reg<D>(R1, d, S3, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);
   team_sync();
@@ -796,11 +794,69 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   rm_add_load<D>(R2, el + EL::C, D, D);
   team_sync();
   matvec<D, false>(vz, S3, vw);
-  if (tid < D) pr[PL::m + tid] = vz[tid] + el[EL::b + tid];
-  if (tid == 0) pr[PL::flag] = 0.0;
+  if (tid < D) mout[tid] = vz[tid] + el[EL::b + tid];
   rm_symmetrise<D>(R2, S1);
-  rm_store<D>(R2, pr + PL::P, D, D);
-  if (!ok && tid == 0) flag_status(T.status, T.fail_bit);
+  rm_store<D>(R2, Pout, D, D);
+  if (!ok && tid == 0) flag_status(status, fail_bit);
+}
+
+
+template <int D>
+__device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs& T, int item) {
+  using C = Cfg<D>;
+  using EL = ElemLayout<D>;
+  using PL = PrefLayout<D>;
+  const int k = item, tid = threadIdx.x;
+  const double* pin = T.pre_src + (int64_t)k * PL::SIZE;
+  const bool ident = pin[PL::flag] != 0.0;
+  // left child: same prefix
+  double* pl = T.pre_dst + (int64_t)(2 * k) * PL::SIZE;
+  for (int e = tid; e < PL::SIZE; e += C::NT) pl[e] = pin[e];
+  if (2 * k + 1 >= T.n_dst) return;
+  double* pr = T.pre_dst + (int64_t)(2 * k + 1) * PL::SIZE;
+  const double* el = T.src + (int64_t)(2 * k) * EL::SIZE;  // left child's element
+  if (ident) {
+    for (int e = tid; e < D * D; e += C::NT) pr[PL::P + e] = el[EL::C + e];
+    if (tid < D) pr[PL::m + tid] = el[EL::b + tid];
+    if (tid == 0) pr[PL::flag] = 0.0;
+    return;
+  }
+  moment_combine<D>(M, pin + PL::P, pin + PL::m, el, pr + PL::P, pr + PL::m, T.status,
+                    T.fail_bit);
+  if (tid == 0) pr[PL::flag] = 0.0;
+}
+
+// Hillis-Steele scan level: element k >= s becomes src[k - s] (x) src[k].  When
+// k < 2s the left operand covers block 0, so it is a filtering moment pair
+// (A = 0, J = 0): the combine reduces to the moment update and the result is
+// again a moment pair.
+template <int D>
+__device__ __forceinline__ void filter_hs_body(const KModel& M, const HsArgs& H, int k) {
+  using EL = ElemLayout<D>;
+  const int tid = threadIdx.x;
+  const double* ej = H.src + (int64_t)k * EL::SIZE;
+  double* out = H.dst + (int64_t)k * EL::SIZE;
+  if (k < H.s) {
+    for (int e = tid; e < EL::SIZE; e += Cfg<D>::NT) out[e] = ej[e];
+    return;
+  }
+  const double* ei = H.src + (int64_t)(k - H.s) * EL::SIZE;
+  if (k < 2 * H.s) {
+    moment_combine<D>(M, ei + EL::C, ei + EL::b, ej, out + EL::C, out + EL::b, H.status,
+                      H.fail_bit);
+    for (int e = tid; e < D * D; e += Cfg<D>::NT) {
+      out[EL::A + e] = 0.0;
+      out[EL::J + e] = 0.0;
+    }
+    if (tid < D) out[EL::eta + tid] = 0.0;
+  } else {
+    filter_combine<D>(M, ei, ej, out, H.status, H.fail_bit);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_hs(KModel M, HsArgs H) {
+  filter_hs_body<D>(M, H, blockIdx.x);
 }
 
 template <int D>
@@ -838,9 +894,15 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
   const int dobs = GH ? P.dyo : d;
   RM<D> Pm, Pp, T, R2;
   if (s0 > 0) {
-    const double* pin = P.pre + (int64_t)blk * PL::SIZE;
-    rm_load<D>(Pm, pin + PL::P, D, D);
-    if (tid < D) vm[tid] = pin[PL::m + tid];
+    if (P.pre_elem) {
+      const double* pin = P.pre_elem + (int64_t)(blk - 1) * ElemLayout<D>::SIZE;
+      rm_load<D>(Pm, pin + ElemLayout<D>::C, D, D);
+      if (tid < D) vm[tid] = pin[ElemLayout<D>::b + tid];
+    } else {
+      const double* pin = P.pre + (int64_t)blk * PL::SIZE;
+      rm_load<D>(Pm, pin + PL::P, D, D);
+      if (tid < D) vm[tid] = pin[PL::m + tid];
+    }
   }
   team_sync();
   bool ok = true;
@@ -1253,6 +1315,25 @@ hipError_t launch_filter(const KModel& M, FilterArgs P, TreeArgs* lv_up, TreeArg
   return hipGetLastError();
 }
 
+template <int D, bool GH>
+hipError_t launch_filter_scan(const KModel& M, FilterArgs P, const HsArgs* lv, int n_levels,
+                              hipStream_t st) {
+  const size_t lds = lds_bytes_filter<D>(GH);
+  const int nb = (M.N + P.B - 1) / P.B;
+  timing_mark(FAM_FILTER_FOLD, 1, st);
+  hipLaunchKernelGGL((k_filter_fold<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  timing_mark(FAM_FILTER_FOLD, 0, st);
+  for (int l = 0; l < n_levels; ++l) {
+    timing_mark(FAM_FILTER_UP, 1, st);
+    hipLaunchKernelGGL(k_filter_hs<D>, dim3(nb), dim3(Cfg<D>::NT), lds, st, M, lv[l]);
+    timing_mark(FAM_FILTER_UP, 0, st);
+  }
+  timing_mark(FAM_FILTER_FINAL, 1, st);
+  hipLaunchKernelGGL((k_filter_final<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  timing_mark(FAM_FILTER_FINAL, 0, st);
+  return hipGetLastError();
+}
+
 template <int D>
 hipError_t launch_samp_scan(const KModel& M, SampArgs S, TreeArgs* lv_up, TreeArgs* lv_down,
                             int n_levels, hipStream_t st) {
@@ -1327,6 +1408,23 @@ hipError_t set_lds_limits() {
                                hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
     return e;
   return hipSuccess;
+}
+
+hipError_t launch_filter_scan_any(int D, const KModel& M, FilterArgs P, const HsArgs* lv,
+                                  int nl, hipStream_t st) {
+  if (P.Ho) {
+    switch (D) {
+      case 16: return launch_filter_scan<16, true>(M, P, lv, nl, st);
+      case 32: return launch_filter_scan<32, true>(M, P, lv, nl, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (D) {
+    case 16: return launch_filter_scan<16, false>(M, P, lv, nl, st);
+    case 32: return launch_filter_scan<32, false>(M, P, lv, nl, st);
+    case 64: return launch_filter_scan<64, false>(M, P, lv, nl, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, TreeArgs* down,

@@ -48,6 +48,8 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
   Lo.B = block > 0 ? (block > N ? N : block) : auto_block(N, D);
   Lo.nb = (N + Lo.B - 1) / Lo.B;
   Lo.n_lvl[0] = Lo.nb;
+  Lo.L_hs = 0;
+  while ((1 << Lo.L_hs) < Lo.nb) ++Lo.L_hs;
   Lo.L = 0;
   while (Lo.n_lvl[Lo.L] > 1 && Lo.L < kMaxLevels) {
     Lo.n_lvl[Lo.L + 1] = (Lo.n_lvl[Lo.L] + 1) / 2;
@@ -93,6 +95,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
   if (kind == LAYOUT_STEP || kind == LAYOUT_FILTER || kind == LAYOUT_LGSSM) {
     Lo.ell = take((size_t)N * dbl);
     for (int l = 0; l <= Lo.L; ++l) Lo.elem[l] = take((size_t)Lo.n_lvl[l] * ES);
+    Lo.hs = take((size_t)Lo.nb * ES);
     for (int l = 0; l <= Lo.L; ++l) Lo.pre[l] = take((size_t)Lo.n_lvl[l] * PS);
   }
   if (kind == LAYOUT_STEP || kind == LAYOUT_LGSSM) {
@@ -235,9 +238,20 @@ akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double*
   P.ell = ell;
   P.status = status;
   P.fail_bit = fail_bit;
-  TreeArgs up[kMaxLevels], down[kMaxLevels];
-  fill_tree(Lo, ws, 0, Lo.elem, Lo.pre, status, fail_bit, up, down);
-  return hip_check(launch_filter_any(Lo.D, M, P, up, down, Lo.L, st), "filter launch");
+  // one chain: Hillis-Steele scan over the block elements (every level keeps
+  // up to nb teams busy, and no down-sweep is needed)
+  HsArgs lv[32];
+  double* buf[2] = {at<double>(ws, Lo.elem[0]), at<double>(ws, Lo.hs)};
+  for (int l = 0; l < Lo.L_hs; ++l) {
+    lv[l].src = buf[l & 1];
+    lv[l].dst = buf[(l + 1) & 1];
+    lv[l].n = Lo.nb;
+    lv[l].s = 1 << l;
+    lv[l].status = status;
+    lv[l].fail_bit = fail_bit;
+  }
+  P.pre_elem = buf[Lo.L_hs & 1];
+  return hip_check(launch_filter_scan_any(Lo.D, M, P, lv, Lo.L_hs, st), "filter launch");
 }
 
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,

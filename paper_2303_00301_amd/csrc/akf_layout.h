@@ -23,6 +23,8 @@ struct Layout {
   size_t plhx = 0, plhxs = 0, pterms = 0;
   size_t gG = 0, gRinv = 0, gOmd = 0, gOmdinv = 0, gscal = 0;
   size_t elem[kMaxLevels + 1] = {0};
+  size_t hs = 0;  // second buffer of the scan over block elements
+  int L_hs = 0;   // levels of that scan: smallest L with 2^L >= nb
   size_t pre[kMaxLevels + 1] = {0};
   size_t mf = 0, Pf = 0, E = 0, U = 0;
   size_t sagg[kMaxLevels + 1] = {0};

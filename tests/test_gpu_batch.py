@@ -1,7 +1,12 @@
 """Batched chains on the GPU (MI355X only): the batched persistent launches
 (eager and hipGraph replay) give the same per-chain results as plain per-chain
 runs with the same block size, normals and uniforms; the autotuner writes and
-reuses its cache."""
+reuses its cache.
+
+Batched chains scan their block elements with the work-efficient up/down
+tree, a single chain with the Hillis-Steele scan; the two associate the
+combines differently, so they agree to FP64 rounding (not bit for bit), and
+the accept decisions agree away from ties."""
 import os
 
 import numpy as np
@@ -60,9 +65,11 @@ def test_batched_equals_plain_per_chain(S, use_graph):
         x = T(c["x0"])
         ref = S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"], block=8)
         torch.cuda.synchronize()
-        assert torch.equal(c["x"], x)
-        for k in ("log_ratio", "accepted", "logZ_fwd", "logZ_rev", "status"):
-            assert torch.equal(c[k], ref[k]), k
+        assert torch.equal(c["status"], ref["status"])
+        assert torch.equal(c["accepted"], ref["accepted"])
+        torch.testing.assert_close(c["x"], x, rtol=1e-9, atol=1e-11)
+        for k in ("log_ratio", "logZ_fwd", "logZ_rev"):
+            torch.testing.assert_close(c[k], ref[k], rtol=1e-9, atol=1e-9, msg=k)
     plan.close()
 
 
