@@ -376,11 +376,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
   RM<D> Pp, R1, R2;
   adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, B_Li, ok);
   // h = H' w
-  if (tid < D) {
-    double s = 0.0;
-    for (int k = 0; k < D; ++k) s = fma(sH[k * C::LD + tid], vw[k], s);
-    G.U[(int64_t)t * D + tid] = s;
-  }
+  matvec<D, true>(G.U + (int64_t)t * D, sH, vw);
   // Cm = -1/2 H' (S^{-1} - w w') H
   rm_unstage<D>(R1, B_Si);
   AKF_RM_FOR(D, q, r, i, j) R1.t[q][r] -= vw[i] * vw[j];
@@ -511,12 +507,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
     gemm<D, false, false, false>(R1, B_Si, B_HP);  // S^{-1} H Pp
     rm_axpy<D>(gH, -1.0, R1);
     // w' H Pp  (row vector) into vv
-    if (tid < D) {
-      double s = 0.0;
-      for (int k = 0; k < D; ++k) s = fma(vw[k], B_HP[k * C::LD + tid], s);
-      vv[tid] = s;
-    }
-    team_sync();
+    matvec<D, true>(vv, B_HP, vw);
     AKF_RM_FOR(D, q, r, i, j)
     gH.t[q][r] += vw[i] * vmp[j] + vw[i] * vv[j] + vw[i] * vpf[j] - vk[i] * vmf[j];
     // R-gradient diag: -1/2 Sig_jj - (K' fbar)_j w_j + (K' Fbar K)_jj

@@ -520,11 +520,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
         team_sync();
         gemm<D, true, false, true>(J, B2, B1);  // J += T' S^{-1} T
         AKF_RM_FOR(D, q, r, i, j) A.t[q][r] = vom[i] * R1.t[q][r];
-        if (tid < D) {
-          double sacc = 0.0;
-          for (int j = 0; j < D; ++j) sacc = fma(B2[j * C::LD + tid], vs[j], sacc);
-          veta[tid] += sacc;  // eta += T' S^{-1} w
-        }
+        matvec<D, true>(veta, B2, vs, veta);  // eta += T' S^{-1} w
       }
       if (tid < D) vb[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vom[tid] * vs[tid] : 0.0;
       rm_symmetrise<D>(Cc, B2);
@@ -564,11 +560,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
     team_sync();
     gemm<D, true, false, false>(Cc, B1, B2);  // Mo' S^{-1} Mo
     rm_rsub<D>(Cc, Pp);  // C = Pp - Mo' S^{-1} Mo
-    if (tid < D) {
-      double sacc = 0.0;
-      for (int j = 0; j < D; ++j) sacc = fma(B1[j * C::LD + tid], vs[j], sacc);
-      vb[tid] = vmu[tid] + sacc;  // b = mu + Mo' S^{-1} w
-    }
+    matvec<D, true>(vb, B1, vs, vmu);  // b = mu + Mo' S^{-1} w
     if (!first && t > 0) {
       team_sync();
       rm_stage<D>(T, B2);  // B2 <- Mt (T, or H T)
@@ -586,11 +578,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
       gemm<D, true, false, true>(J, B2, B3);   // J += Mt' S^{-1} Mt
       gemm<D, true, false, false>(A, B1, B3);  // Mo' S^{-1} Mt
       rm_rsub<D>(A, T);  // A = T - Mo' S^{-1} Mt
-      if (tid < D) {
-        double sacc = 0.0;
-        for (int j = 0; j < D; ++j) sacc = fma(B2[j * C::LD + tid], vs[j], sacc);
-        veta[tid] += sacc;  // eta += Mt' S^{-1} w
-      }
+      matvec<D, true>(veta, B2, vs, veta);  // eta += Mt' S^{-1} w
     } else if (first) {
       rm_zero<D>(A);
     }
@@ -685,11 +673,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   rm_unstage<D>(R3, S0);
   rm_axpy<D>(R3, -1.0, R2);  // Z1 = A_i - M P
   team_sync();
-  if (tid < D) {  // eta = A_i' (c - J_j M c) + eta_i
-    double sacc = 0.0;
-    for (int j = 0; j < D; ++j) sacc = fma(S0[j * C::LD + tid], vk[j], sacc);
-    out[EL::eta + tid] = sacc + ei[EL::eta + tid];
-  }
+  matvec<D, true>(out + EL::eta, S0, vk, ei + EL::eta);  // eta = A_i' (c - J_j M c) + eta_i
   rm_stage<D>(R3, S1);  // S1 = Z1
   team_sync();
   gemm<D, true, false, false>(R1, S1, S3);  // J = Z1' P + J_i = A_i'P - P'MP + J_i
@@ -984,11 +968,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
     const double rr = team_sum<D>(tid < D ? vw[tid] * vs[tid] : 0.0, red);
     gemm<D, true, false, false>(Pm, B1, B2);  // Mo' S^{-1} Mo
     rm_rsub<D>(Pm, Pp);  // P^f = Pp - Mo' S^{-1} Mo
-    if (tid < D) {
-      double sacc = 0.0;
-      for (int j = 0; j < D; ++j) sacc = fma(B1[j * C::LD + tid], vs[j], sacc);
-      vm[tid] = vmp[tid] + sacc;  // m^f = m^p + Mo' S^{-1} w
-    }
+    matvec<D, true>(vm, B1, vs, vmp);  // m^f = m^p + Mo' S^{-1} w
     if (tid == 0) P.ell[t] = -0.5 * (dobs * LOG2PI + logdet + rr);
     rm_symmetrise<D>(Pm, B2);
     if (P.mf) {

@@ -554,17 +554,30 @@ __device__ bool chol_reg(RM<D>& A, int d, double* scr, double* logdet) {
   return ok;
 }
 
-// y[i] = sum_j op(A)[i][j] x[j] for i < D (LDS matrix, LDS vectors). Caller syncs.
+// y[i] = add[i] + sum_j op(A)[i][j] x[j] for i < D (LDS matrix; add may be
+// null, may alias y, and may live in global memory; x must not alias y).
+// Every wave takes D / NW rows and splits each row over 64 / (D / NW) lanes,
+// reduced by lane shuffles, so the dependent chain is 16 (D >= 32) or 4 FMAs
+// long.  Team-wide; ends with a barrier, after which y is visible to all.
 template <int D, bool TA>
-__device__ __forceinline__ void matvec(double* y, const double* sA, const double* x) {
+__device__ __forceinline__ void matvec(double* y, const double* sA, const double* x,
+                                       const double* add = nullptr) {
   using C = Cfg<D>;
-  const int tid = threadIdx.x;
-  if (tid < D) {
-    double s = 0.0;
-#pragma unroll 8
-    for (int j = 0; j < D; ++j) s = fma(TA ? sA[j * C::LD + tid] : sA[tid * C::LD + j], x[j], s);
-    y[tid] = s;
+  constexpr int R = D / C::NW;  // rows per wave
+  constexpr int P = 64 / R;     // lanes per row
+  constexpr int JL = D / P;     // columns per lane
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int i = w * R + (l % R), j0 = (l / R) * JL;
+  double s = 0.0;
+#pragma unroll
+  for (int jj = 0; jj < JL; ++jj) {
+    const int j = j0 + jj;
+    s = fma(TA ? sA[j * C::LD + i] : sA[i * C::LD + j], x[j], s);
   }
+#pragma unroll
+  for (int m = R; m < 64; m <<= 1) s += __shfl_xor(s, m);
+  if (l < R) y[i] = (add ? add[i] : 0.0) + s;
+  team_sync();
 }
 
 // team-wide sum of one double per thread (result returned to every thread)
