@@ -239,14 +239,11 @@ __device__ __forceinline__ void static_for(F& f) {
   }
 }
 
-// Broadcast of lane K of every row of 16 lanes to the whole row (DPP
-// row_newbcast), for a double.
+// Broadcast of lane K of every row of 16 lanes to the whole row (64-bit DPP
+// row_newbcast).
 template <int K>
 __device__ __forceinline__ double row_bcast(double v) {
-  const uint64_t u = __builtin_bit_cast(uint64_t, v);
-  const uint32_t lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)u, 0x150 + K, 0xF, 0xF, true);
-  const uint32_t hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(u >> 32), 0x150 + K, 0xF, 0xF, true);
-  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xF, 0xF, true);
 }
 
 // v from lane src of the wave (ds_bpermute; no LDS memory involved)
@@ -266,6 +263,16 @@ __device__ __forceinline__ double recip(double q) {
   return r;
 }
 
+// 1/sqrt(q) for q > 0: hardware estimate refined by two Newton-Raphson steps
+// r <- r (3 - q r^2) / 2.
+__device__ __forceinline__ double rsqrt_nr(double q) {
+  double r = __builtin_amdgcn_rsq(q);
+  const double h = 0.5 * q;
+  r = r * fma(-h * r, r, 1.5);
+  r = r * fma(-h * r, r, 1.5);
+  return r;
+}
+
 // One wave inverts a symmetric positive definite 16 x 16 tile held in the
 // accumulator layout (p[r] = P[4r + l/16][l%16]) by 16 steps of the symmetric
 // sweep operator: with c = column k of the current matrix and pivot q = c_k,
@@ -274,11 +281,12 @@ __device__ __forceinline__ double recip(double q) {
 // Column k reaches the lanes of each row of 16 by a DPP row broadcast of lane
 // k (c_i for the lane's rows i = 4r + l/16), row k by a lane permute (c_j for
 // the lane's column j = l%16), the pivot by a lane read.  Every element update
-// is one FMA: a' = f_i r_j + [i != k, j != k] a with f_i = -c_i/q (f_k = 1/q)
-// and r_j = c_j (r_k = -1).  The pivots are those of the LDL' factorisation;
-// with CHOL the lower Cholesky factor is captured on the way
-// (L_ik = c_i / sqrt(q), i >= k).  Indices >= nv are padding: they get a unit
-// diagonal.
+// is one FMA, a' = f_i r_j + m a, with f_i = -c_i/q (f_k = 1/q), r_j = c_j
+// (r_k = -1) and m = 0 on row and column k, 1 elsewhere.  The pivots are those
+// of the LDL' factorisation; with CHOL the lower Cholesky factor is captured
+// on the way (L_ik = c_i / sqrt(q), i >= k).  Indices >= nv are padding: they
+// get a unit diagonal.  A non-positive pivot clears ok (the results are then
+// unspecified).
 template <bool CHOL>
 __device__ __forceinline__ void tile_sweep16(double p[4], int nv, double Lk[4], LogDet& ld,
                                              bool& ok) {
@@ -288,33 +296,40 @@ __device__ __forceinline__ void tile_sweep16(double p[4], int nv, double Lk[4], 
     if (4 * r + lg >= nv && 4 * r + lg == lc) p[r] = 1.0;
     if constexpr (CHOL) Lk[r] = 0.0;
   }
+  double prod = 1.0;
   auto step = [&](auto kc) {
     constexpr int k = decltype(kc)::value;
+    constexpr int rk = k >> 2;
     double ci[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) ci[r] = row_bcast<k>(p[r]);
-    const double q = lane_bcast(p[k >> 2], 16 * (k & 3) + k);
-    const double cj = lane_fetch(p[k >> 2], 16 * (k & 3) + lc);
-    const bool pos = q > 0.0;
-    ok = ok && pos;
-    const double iq = pos ? recip(q) : 0.0;
-    ld.mul(pos ? q : 1.0);
-    const bool jk = (lc == k);
+    const double q = lane_bcast(p[rk], 16 * (k & 3) + k);
+    const double cj = lane_fetch(p[rk], 16 * (k & 3) + lc);
+    ok = ok && (q > 0.0);
+    const double iq = recip(q);
+    prod *= q;
+    if constexpr ((k & 3) == 3) {
+      ld.mul(prod);
+      prod = 1.0;
+    }
+    const bool jk = (lc == k), ik = (lg == (k & 3));
     const double rj = jk ? -1.0 : cj;
+    const double mc = jk ? 0.0 : 1.0;         // rows other than k
+    const double mk = (jk || ik) ? 0.0 : 1.0;  // register rk (holds row k when ik)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const bool ik = (r == (k >> 2)) && (lg == (k & 3));
-      const double fi = ik ? iq : -ci[r] * iq;
-      const double v = (ik || jk) ? 0.0 : p[r];
-      p[r] = fma(fi, rj, v);
+      double fi = -ci[r] * iq;
+      if (r == rk) fi = ik ? iq : fi;
+      p[r] = fma(fi, rj, p[r] * (r == rk ? mk : mc));
     }
     if constexpr (CHOL) {
-      const double isq = pos ? sqrt(iq) : 0.0;
-      const double sq = q * isq;
+      const double isq = rsqrt_nr(q);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int i = 4 * r + lg;
-        const double lv = (i > k) ? ci[r] * isq : ((i == k) ? sq : 0.0);
+        double lv;
+        if (r > rk) lv = ci[r] * isq;
+        else if (r < rk) lv = 0.0;
+        else lv = (lg > (k & 3)) ? ci[r] * isq : (ik ? q * isq : 0.0);
         Lk[r] = jk ? lv : Lk[r];
       }
     }
