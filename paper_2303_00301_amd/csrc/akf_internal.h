@@ -53,6 +53,10 @@ struct StepArgs {
   int* accept_flag;
 };
 
+// pseudo-observation model of a filter: diagonal Omega_t, dense constant
+// Omega, or a general y_t = H x_t + N(0, R)
+enum { OBS_DIAG = 0, OBS_DENSE = 1, OBS_GH = 2 };
+
 struct FilterArgs {
   int B;
   const double* om;

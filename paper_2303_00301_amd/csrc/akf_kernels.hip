@@ -438,9 +438,13 @@ __device__ __forceinline__ void lds_load_rect(double* s, const double* __restric
 // Pp S^{-1} Pp -> (H Pp)' S^{-1} (H Pp), T' S^{-1} T -> (H T)' S^{-1} (H T),
 // w = y_t - H mu.
 // ---------------------------------------------------------------------------
-template <int D, bool GH>
-__device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterArgs& P, int item) {
+// FIRST: the block contains t = 0 (its element has A = 0 and J = 0).  The
+// two cases are compiled separately so that A and T hold no registers across
+// the inverse.
+template <int D, int OBS, bool FIRST>
+__device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterArgs& P, int item) {
   using C = Cfg<D>;
+  constexpr bool GH = (OBS == OBS_GH);
   static_assert(!GH || D <= 32, "general observation matrices need D <= 32");
   extern __shared__ double lds[];
   double* sF = lds;
@@ -456,7 +460,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
   double* vom = vs + D;                    // diagonal Omega_t
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
-  const bool first = (s0 == 0);
+  constexpr bool first = FIRST;
   const int dobs = GH ? P.dyo : d;
   lds_load_mat<D>(sF, M.F, d);
   if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
@@ -494,7 +498,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
       }
       team_sync();
     }
-    if (!GH && !P.Omd) {
+    if constexpr (OBS == OBS_DIAG) {
       // diagonal Omega_t: with S = Pp + Omega, I - Pp S^{-1} = Omega S^{-1}, so
       // C = Omega S^{-1} Pp, A = Omega S^{-1} T, b = omega - Omega S^{-1} w.
       const double* Om = P.Om + (int64_t)t * d;
@@ -504,23 +508,24 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
         vom[tid] = (tid < d) ? Om[tid] : 0.0;
         vw[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vmu[tid] : 0.0;
       }
+      // Pp and T go to LDS before the inverse, so they hold no registers
+      // across it (B1 = Pp, B3 = T, B2 = the inverse's scratch, then S^{-1})
+      rm_stage<D>(Pp, B1);
+      if (!first) rm_stage<D>(T, B3);
       double logdet;
       ok = spd_inv<D>(R2, d, B2, &logdet) && ok;  // R2 = S^{-1}
-      rm_stage<D>(R2, B3);
-      rm_stage<D>(Pp, B1);
+      rm_stage<D>(R2, B2);
       team_sync();
-      gemm<D, false, false, false>(Cc, B3, B1);  // S^{-1} Pp
+      gemm<D, false, false, false>(Cc, B2, B1);  // S^{-1} Pp
       AKF_RM_FOR(D, q, r, i, j) Cc.t[q][r] *= vom[i];
-      matvec<D, false>(vs, B3, vw);  // S^{-1} w
-      if (!first && t > 0) {
-        rm_stage<D>(T, B2);
-        team_sync();
-        gemm<D, false, false, false>(R1, B3, B2);  // S^{-1} T
+      matvec<D, false>(vs, B2, vw);  // S^{-1} w
+      if (!first) {
+        gemm<D, false, false, false>(R1, B2, B3);  // S^{-1} T
         rm_stage<D>(R1, B1);
         team_sync();
-        gemm<D, true, false, true>(J, B2, B1);  // J += T' S^{-1} T
+        gemm<D, true, false, true>(J, B3, B1);  // J += T' S^{-1} T
         AKF_RM_FOR(D, q, r, i, j) A.t[q][r] = vom[i] * R1.t[q][r];
-        matvec<D, true>(veta, B2, vs, veta);  // eta += T' S^{-1} w
+        matvec<D, true>(veta, B3, vs, veta);  // eta += T' S^{-1} w
       }
       if (tid < D) vb[tid] = (tid < d) ? P.om[(int64_t)t * d + tid] - vom[tid] * vs[tid] : 0.0;
       rm_symmetrise<D>(Cc, B2);
@@ -561,7 +566,7 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
     gemm<D, true, false, false>(Cc, B1, B2);  // Mo' S^{-1} Mo
     rm_rsub<D>(Cc, Pp);  // C = Pp - Mo' S^{-1} Mo
     matvec<D, true>(vb, B1, vs, vmu);  // b = mu + Mo' S^{-1} w
-    if (!first && t > 0) {
+    if (!first) {
       team_sync();
       rm_stage<D>(T, B2);  // B2 <- Mt (T, or H T)
       if constexpr (GH) {
@@ -600,9 +605,17 @@ __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterAr
   }
 }
 
-template <int D, bool GH>
+template <int D, int OBS>
+__device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterArgs& P, int item) {
+  if (item == 0)
+    filter_fold_impl<D, OBS, true>(M, P, item);
+  else
+    filter_fold_impl<D, OBS, false>(M, P, item);
+}
+
+template <int D, int OBS>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs P) {
-  filter_fold_body<D, GH>(M, P, blockIdx.x);
+  filter_fold_body<D, OBS>(M, P, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -854,10 +867,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T
 // form likelihood term ell_t = log N(omega_t; m^p_t, P^p_t + Omega_t).
 // Writes m^f_t, P^f_t (when requested) and ell_t.
 // ---------------------------------------------------------------------------
-template <int D, bool GH>
+template <int D, int OBS>
 __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterArgs& P, int item) {
   using C = Cfg<D>;
   using PL = PrefLayout<D>;
+  constexpr bool GH = (OBS == OBS_GH);
   static_assert(!GH || D <= 32, "general observation matrices need D <= 32");
   extern __shared__ double lds[];
   double* sF = lds;
@@ -908,7 +922,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       if (tid < d && M.b) vmp[tid] += M.b[tid];
       team_sync();
     }
-    if (!GH && !P.Omd) {
+    if constexpr (OBS == OBS_DIAG) {
       // diagonal Omega_t: P^f = Omega S^{-1} Pp, m^f = omega - Omega S^{-1} w
       const double* Om = P.Om + (int64_t)t * d;
       R2 = Pp;
@@ -979,9 +993,9 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
   if (!ok && tid == 0) flag_status(P.status, P.fail_bit);
 }
 
-template <int D, bool GH>
+template <int D, int OBS>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArgs P) {
-  filter_final_body<D, GH>(M, P, blockIdx.x);
+  filter_final_body<D, OBS>(M, P, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1269,13 +1283,13 @@ size_t lds_bytes_samp2() {
   return (size_t)(2 * Cfg<D>::MAT + 2 * D) * sizeof(double);
 }
 
-template <int D, bool GH>
+template <int D, int OBS>
 hipError_t launch_filter(const KModel& M, FilterArgs P, TreeArgs* lv_up, TreeArgs* lv_down,
                          int n_levels, hipStream_t st) {
-  const size_t lds = lds_bytes_filter<D>(GH);
+  const size_t lds = lds_bytes_filter<D>(OBS == OBS_GH);
   const int nb = (M.N + P.B - 1) / P.B;
   timing_mark(FAM_FILTER_FOLD, 1, st);
-  hipLaunchKernelGGL((k_filter_fold<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  hipLaunchKernelGGL((k_filter_fold<D, OBS>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FOLD, 0, st);
   for (int l = 0; l < n_levels; ++l) {
     timing_mark(FAM_FILTER_UP, 1, st);
@@ -1290,18 +1304,18 @@ hipError_t launch_filter(const KModel& M, FilterArgs P, TreeArgs* lv_up, TreeArg
     timing_mark(FAM_FILTER_DOWN, 0, st);
   }
   timing_mark(FAM_FILTER_FINAL, 1, st);
-  hipLaunchKernelGGL((k_filter_final<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  hipLaunchKernelGGL((k_filter_final<D, OBS>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FINAL, 0, st);
   return hipGetLastError();
 }
 
-template <int D, bool GH>
+template <int D, int OBS>
 hipError_t launch_filter_scan(const KModel& M, FilterArgs P, const HsArgs* lv, int n_levels,
                               hipStream_t st) {
-  const size_t lds = lds_bytes_filter<D>(GH);
+  const size_t lds = lds_bytes_filter<D>(OBS == OBS_GH);
   const int nb = (M.N + P.B - 1) / P.B;
   timing_mark(FAM_FILTER_FOLD, 1, st);
-  hipLaunchKernelGGL((k_filter_fold<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  hipLaunchKernelGGL((k_filter_fold<D, OBS>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FOLD, 0, st);
   for (int l = 0; l < n_levels; ++l) {
     timing_mark(FAM_FILTER_UP, 1, st);
@@ -1309,7 +1323,7 @@ hipError_t launch_filter_scan(const KModel& M, FilterArgs P, const HsArgs* lv, i
     timing_mark(FAM_FILTER_UP, 0, st);
   }
   timing_mark(FAM_FILTER_FINAL, 1, st);
-  hipLaunchKernelGGL((k_filter_final<D, GH>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  hipLaunchKernelGGL((k_filter_final<D, OBS>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FINAL, 0, st);
   return hipGetLastError();
 }
@@ -1372,16 +1386,18 @@ template <int D>
 hipError_t set_lds_limits() {
   hipError_t e;
   const int lf = (int)lds_bytes_filter<D>();
-  if ((e = hipFuncSetAttribute((const void*)k_filter_fold<D, false>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
-    return e;
+  const void* fns[] = {(const void*)k_filter_fold<D, OBS_DIAG>,
+                       (const void*)k_filter_fold<D, OBS_DENSE>,
+                       (const void*)k_filter_final<D, OBS_DIAG>,
+                       (const void*)k_filter_final<D, OBS_DENSE>,
+                       (const void*)k_filter_hs<D>};
+  for (const void* f : fns)
+    if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
+      return e;
   if ((e = hipFuncSetAttribute((const void*)k_filter_up<D>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
     return e;
   if ((e = hipFuncSetAttribute((const void*)k_filter_down<D>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute((const void*)k_filter_final<D, false>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
     return e;
   if ((e = hipFuncSetAttribute((const void*)k_samp_build<D>,
@@ -1394,15 +1410,23 @@ hipError_t launch_filter_scan_any(int D, const KModel& M, FilterArgs P, const Hs
                                   int nl, hipStream_t st) {
   if (P.Ho) {
     switch (D) {
-      case 16: return launch_filter_scan<16, true>(M, P, lv, nl, st);
-      case 32: return launch_filter_scan<32, true>(M, P, lv, nl, st);
+      case 16: return launch_filter_scan<16, OBS_GH>(M, P, lv, nl, st);
+      case 32: return launch_filter_scan<32, OBS_GH>(M, P, lv, nl, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (P.Omd) {
+    switch (D) {
+      case 16: return launch_filter_scan<16, OBS_DENSE>(M, P, lv, nl, st);
+      case 32: return launch_filter_scan<32, OBS_DENSE>(M, P, lv, nl, st);
+      case 64: return launch_filter_scan<64, OBS_DENSE>(M, P, lv, nl, st);
     }
     return hipErrorInvalidValue;
   }
   switch (D) {
-    case 16: return launch_filter_scan<16, false>(M, P, lv, nl, st);
-    case 32: return launch_filter_scan<32, false>(M, P, lv, nl, st);
-    case 64: return launch_filter_scan<64, false>(M, P, lv, nl, st);
+    case 16: return launch_filter_scan<16, OBS_DIAG>(M, P, lv, nl, st);
+    case 32: return launch_filter_scan<32, OBS_DIAG>(M, P, lv, nl, st);
+    case 64: return launch_filter_scan<64, OBS_DIAG>(M, P, lv, nl, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1411,15 +1435,23 @@ hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up,
                              int nl, hipStream_t st) {
   if (P.Ho) {
     switch (D) {
-      case 16: return launch_filter<16, true>(M, P, up, down, nl, st);
-      case 32: return launch_filter<32, true>(M, P, up, down, nl, st);
+      case 16: return launch_filter<16, OBS_GH>(M, P, up, down, nl, st);
+      case 32: return launch_filter<32, OBS_GH>(M, P, up, down, nl, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (P.Omd) {
+    switch (D) {
+      case 16: return launch_filter<16, OBS_DENSE>(M, P, up, down, nl, st);
+      case 32: return launch_filter<32, OBS_DENSE>(M, P, up, down, nl, st);
+      case 64: return launch_filter<64, OBS_DENSE>(M, P, up, down, nl, st);
     }
     return hipErrorInvalidValue;
   }
   switch (D) {
-    case 16: return launch_filter<16, false>(M, P, up, down, nl, st);
-    case 32: return launch_filter<32, false>(M, P, up, down, nl, st);
-    case 64: return launch_filter<64, false>(M, P, up, down, nl, st);
+    case 16: return launch_filter<16, OBS_DIAG>(M, P, up, down, nl, st);
+    case 32: return launch_filter<32, OBS_DIAG>(M, P, up, down, nl, st);
+    case 64: return launch_filter<64, OBS_DIAG>(M, P, up, down, nl, st);
   }
   return hipErrorInvalidValue;
 }
@@ -1516,7 +1548,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_fold(BatchLaunch L, int rev) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
-    filter_fold_body<D, false>(c.M, rev ? c.Fr : c.Ff, I.i);
+    filter_fold_body<D, OBS_DIAG>(c.M, rev ? c.Fr : c.Ff, I.i);
     __syncthreads();
   }
 }
@@ -1526,7 +1558,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_final(BatchLaunch L, int rev) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
-    filter_final_body<D, false>(c.M, rev ? c.Fr : c.Ff, I.i);
+    filter_final_body<D, OBS_DIAG>(c.M, rev ? c.Fr : c.Ff, I.i);
     __syncthreads();
   }
 }
