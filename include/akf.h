@@ -127,7 +127,8 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
  * predictive form of eq. marginal-likelihood).  The model's emission fields
  * are ignored.  omega, Omega [N,dx]; outputs mf [N,dx], Pf [N,dx,dx] (each may
  * be NULL), ell [N] per-step log-likelihood terms.  *status (device int32, may
- * be NULL) receives AKF_ST_FWD_NOT_PD on a Cholesky failure, else 0.
+ * be NULL) receives AKF_ST_FWD_NOT_PD when a matrix that must be positive
+ * definite is not (a non-positive pivot), else 0.
  */
 size_t akf_filter_workspace_bytes(const akf_model* model, int32_t block);
 akf_status akf_aux_filter(const akf_model* model, const double* omega, const double* Omega,
@@ -251,7 +252,8 @@ void akf_batch_plan_destroy(akf_batch_plan* plan);
 
 /*
  * Kernel timing, for diagnostics and benchmarks.  While enabled for `family`
- * (0 filter fold, 1 filter up-sweep, 2 filter down-sweep, 3 filter final,
+ * (0 filter fold, 1 filter scan levels (Hillis-Steele levels for one chain,
+ * up-sweep levels for batched chains), 2 filter down-sweep, 3 filter final,
  * 4 sampler element build, 5 sampler fold, 6 sampler up-sweep, 7 sampler
  * down-sweep, 8 sampler final), every launch of that kernel on any stream is
  * bracketed by a pair of hipEvents recorded on the launch stream; at most
