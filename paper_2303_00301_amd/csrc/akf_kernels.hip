@@ -654,6 +654,13 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   rm_load<D>(R1, ei + EL::C, D, d);
   lds_load_pad<D>(S1, ej + EL::J);
   if (tid < D) vbi[tid] = ei[EL::b + tid];
+  // the operands needed later are fetched now, so their HBM latency overlaps
+  // the factorisations (no global stores precede the barriers until then)
+  RM<D> Ai, Ji, Aj, Cj;
+  rm_load<D>(Ai, ei + EL::A, D, D);
+  rm_load<D>(Ji, ei + EL::J, D, D);
+  rm_load<D>(Aj, ej + EL::A, D, D);
+  rm_load<D>(Cj, ej + EL::C, D, D);
   ok = chol_reg<D>(R1, d, S3, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);                        // S0 = L
   team_sync();
@@ -675,7 +682,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   if (tid < D) vc[tid] = ej[EL::eta + tid] - vc[tid];
   team_sync();
   matvec<D, false>(vw, S2, vc);     // w = M c
-  lds_load_pad<D>(S0, ei + EL::A);  // S0 = A_i
+  rm_stage<D>(Ai, S0);  // S0 = A_i
   team_sync();
   matvec<D, false>(vk, S1, vw);              // J_j w
   gemm<D, false, false, false>(R1, S1, S0);  // P = J_j A_i
@@ -683,17 +690,17 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   team_sync();
   if (tid < D) vk[tid] = vc[tid] - vk[tid];  // c - J_j M c
   gemm<D, false, false, false>(R2, S2, S3);  // M P
-  rm_unstage<D>(R3, S0);
+  R3 = Ai;
   rm_axpy<D>(R3, -1.0, R2);  // Z1 = A_i - M P
   team_sync();
   matvec<D, true>(out + EL::eta, S0, vk, ei + EL::eta);  // eta = A_i' (c - J_j M c) + eta_i
   rm_stage<D>(R3, S1);  // S1 = Z1
   team_sync();
   gemm<D, true, false, false>(R1, S1, S3);  // J = Z1' P + J_i = A_i'P - P'MP + J_i
-  rm_add_load<D>(R1, ei + EL::J, D, D);
+  rm_axpy<D>(R1, 1.0, Ji);
   rm_symmetrise<D>(R1, S3);  // ends synchronised
   rm_store<D>(R1, out + EL::J, D, D);
-  lds_load_pad<D>(S0, ej + EL::A);  // S0 = A_j
+  rm_stage<D>(Aj, S0);  // S0 = A_j
   if (tid < D) vw[tid] += vbi[tid];
   team_sync();
   gemm<D, false, false, false>(R3, S0, S1);  // A = A_j Z1
@@ -703,7 +710,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   rm_stage<D>(R2, S3);
   team_sync();
   gemm<D, false, true, false>(R3, S3, S0);  // A_j M A_j'
-  rm_add_load<D>(R3, ej + EL::C, D, D);
+  rm_axpy<D>(R3, 1.0, Cj);
   if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
   rm_symmetrise<D>(R3, S1);
   rm_store<D>(R3, out + EL::C, D, D);
@@ -757,10 +764,12 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
   const int tid = threadIdx.x, d = M.d;
   bool ok = true;
   double ld;
-  RM<D> R1, R2;
+  RM<D> R1, R2, Ae, Ce;
   rm_load<D>(R1, Pin, D, d);
   lds_load_pad<D>(S1, el + EL::J);
   if (tid < D) vm[tid] = min_[tid];
+  rm_load<D>(Ae, el + EL::A, D, D);  // needed after the factorisations
+  rm_load<D>(Ce, el + EL::C, D, D);
   ok = chol_reg<D>(R1, d, S3, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);
   team_sync();
@@ -780,7 +789,7 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
   team_sync();
   rm_stage<D>(R2, S2);  // S2 = M
   if (tid < D) vc[tid] = el[EL::eta + tid] - vc[tid];
-  lds_load_pad<D>(S3, el + EL::A);  // S3 = A
+  rm_stage<D>(Ae, S3);  // S3 = A
   team_sync();
   matvec<D, false>(vw, S2, vc);              // M (eta - J m)
   gemm<D, false, false, false>(R1, S3, S2);  // A M
@@ -788,7 +797,7 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
   team_sync();
   if (tid < D) vw[tid] += vm[tid];
   gemm<D, false, true, false>(R2, S0, S3);  // A M A'
-  rm_add_load<D>(R2, el + EL::C, D, D);
+  rm_axpy<D>(R2, 1.0, Ce);
   team_sync();
   matvec<D, false>(vz, S3, vw);
   if (tid < D) mout[tid] = vz[tid] + el[EL::b + tid];
