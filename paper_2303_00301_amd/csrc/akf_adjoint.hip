@@ -249,6 +249,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   }
   bool ok = true;
   double ld;
+  rm_load<D>(R2, M.Q, d, d);  // issued early: its latency overlaps G = F P^f
   lds_load_user<D>(sF, M.F, d, d);
   rm_stage<D>(Pf, B1);
   team_sync();
@@ -256,8 +257,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   team_sync();
   rm_stage<D>(R1, B1);
   team_sync();
-  gemm<D, false, true, false>(R2, B1, sF);  // G F'
-  rm_add_load<D>(R2, M.Q, d, d);
+  gemm<D, false, true, true>(R2, B1, sF);  // Q + G F'
   matvec<D, false>(vmp, sF, vm);
   if (tid < d && M.b) vmp[tid] += M.b[tid];
   {

@@ -480,14 +480,14 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       rm_load<D>(Pp, M.P0, d, d);
       if (tid < D) vmu[tid] = (tid < d) ? M.m0[tid] : 0.0;
     } else {
+      rm_load<D>(Pp, M.Q, d, d);  // issued early: its latency overlaps F C
       rm_stage<D>(Cc, B1);
       team_sync();
       gemm<D, false, false, false>(T, sF, B1);  // F C
       team_sync();
       rm_stage<D>(T, B1);
       team_sync();
-      gemm<D, false, true, false>(Pp, B1, sF);  // (F C) F'
-      rm_add_load<D>(Pp, M.Q, d, d);
+      gemm<D, false, true, true>(Pp, B1, sF);  // Q + (F C) F'
       matvec<D, false>(vmu, sF, vb);
       team_sync();
       if (tid < d && M.b) vmu[tid] += M.b[tid];
@@ -918,14 +918,14 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       rm_load<D>(Pp, M.P0, d, d);
       if (tid < D) vmp[tid] = (tid < d) ? M.m0[tid] : 0.0;
     } else {
+      rm_load<D>(Pp, M.Q, d, d);  // issued early: its latency overlaps F P
       rm_stage<D>(Pm, B1);
       team_sync();
       gemm<D, false, false, false>(T, sF, B1);
       team_sync();
       rm_stage<D>(T, B1);
       team_sync();
-      gemm<D, false, true, false>(Pp, B1, sF);
-      rm_add_load<D>(Pp, M.Q, d, d);
+      gemm<D, false, true, true>(Pp, B1, sF);  // Q + (F P) F'
       matvec<D, false>(vmp, sF, vm);
       team_sync();
       if (tid < d && M.b) vmp[tid] += M.b[tid];
@@ -1048,6 +1048,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     rm_zero<D>(Z);
     rm_store<D>(Z, S.E + (int64_t)t * D * D, D, D);
   } else {
+    rm_load<D>(R2, M.Q, d, d);  // issued early: its latency overlaps G = F P^f
     lds_load_mat<D>(sF, M.F, d);
     rm_stage<D>(Pf, B1);
     team_sync();
@@ -1055,8 +1056,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     team_sync();
     rm_stage<D>(R1, B1);  // B1 = G
     team_sync();
-    gemm<D, false, true, false>(R2, B1, sF);  // G F'
-    rm_add_load<D>(R2, M.Q, d, d);
+    gemm<D, false, true, true>(R2, B1, sF);  // Q + G F'
     matvec<D, false>(vmp, sF, vm);
     if (tid < d && M.b) vmp[tid] += M.b[tid];
     {
