@@ -54,7 +54,15 @@ __device__ __forceinline__ void wave_lds_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-__device__ __forceinline__ void team_sync() { __syncthreads(); }
+// Team barrier that orders LDS only: threads of a team exchange data through
+// LDS, never through global memory within one launch, so the barrier waits
+// for the team's LDS operations but not for its outstanding global loads and
+// stores (a per-step store of a result need not finish before the next step).
+__device__ __forceinline__ void team_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 template <int D>
 struct RM {
