@@ -208,6 +208,34 @@ def bench_adjoint(torch, S, W, reps: int, dev) -> dict:
             "adjoint_over_forward": mb / mf}
 
 
+def bench_stoch_vol(torch, S, W, K: int, dev) -> dict:
+    """Second paper workload on the same path: multivariate stochastic volatility
+    (d_x = 30, T = 250), one chain, both linearisation orders."""
+    out = {"workload": "stoch_vol_d30_T250: F = 0.9 I, equicorrelated Q (tau 2, rho 0.25), "
+                       "y ~ N(0, exp(x)) per coordinate, one chain"}
+    for order in (1, 2):
+        w = W.stoch_vol(order=order)
+        M = S.DeviceModel.from_workload(w, device=dev)
+        y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+        x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(60 + order)
+        xi = torch.randn((K + 2, 2, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
+        un = torch.rand((K + 2,), dtype=torch.float64, device=dev, generator=gen).clamp_(min=1e-300)
+        ws = S.Workspace(dev)
+        S.mh_run(M, y, x, w.delta, order, xi[:2], un[:2], ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = S.mh_run(M, y, x, w.delta, order, xi[2:], un[2:], ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        out[f"order{order}"] = {"delta": w.delta, "ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+                                "acceptance": r["accepted"].float().mean().item()}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +248,7 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-stoch-vol", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
                          "reference for the HBM byte counters)")
@@ -320,6 +349,8 @@ def main() -> int:
         res["batched"] = bench_batched(torch, S, W, args.batched_steps, dev)
     if not args.no_adjoint:
         res["adjoint"] = bench_adjoint(torch, S, W, 5, dev)
+    if not args.no_stoch_vol:
+        res["stoch_vol"] = bench_stoch_vol(torch, S, W, 20, dev)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     if args.copy_calibration > 0:

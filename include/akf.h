@@ -51,7 +51,8 @@ typedef enum {
 typedef enum {
   AKF_EMIT_GAUSSIAN = 0,    /* y_t = H x_t + N(0, R): H [dy,dx], R [dy,dy] SPD */
   AKF_EMIT_POISSON_LOG = 1, /* y_{t,k} ~ Poisson(exp(x_{t,site[k]})) */
-  AKF_EMIT_STUDENT_T = 2    /* y_{t,k} = x_{t,site[k]} + scale * t_nu */
+  AKF_EMIT_STUDENT_T = 2,   /* y_{t,k} = x_{t,site[k]} + scale * t_nu */
+  AKF_EMIT_STOCH_VOL = 3    /* y_{t,k} ~ N(0, exp(x_{t,site[k]})) (stochastic volatility) */
 } akf_emit;
 
 /* Per-step device status bits. */
@@ -67,7 +68,7 @@ enum {
 /*
  * Model description (eq. ssm with Gaussian dynamics).  m0 [dx], P0 [dx,dx],
  * F [dx,dx], b [dx] or NULL (zero), Q [dx,dx].  Emission per `emit`:
- * GAUSSIAN uses H, R; POISSON_LOG and STUDENT_T use site [dy] (int32, each in
+ * GAUSSIAN uses H, R; POISSON_LOG, STUDENT_T and STOCH_VOL use site [dy] (int32, each in
  * [0, dx); several sites may observe the same coordinate) and, for STUDENT_T,
  * nu > 0 and scale > 0.  All pointers are device pointers.
  */

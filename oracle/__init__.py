@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "akf_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T = 0, 1, 2
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL = 0, 1, 2, 3
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
 
@@ -105,8 +105,9 @@ def _p(a: Optional[np.ndarray]):
 class Model:
     """State-space model: p0 = N(m0,P0), p_t = N(F x + b, Q), emission h_t.
 
-    emit: EMIT_GAUSSIAN (H [dy,dx], R [dy,dy]); EMIT_POISSON_LOG or
-    EMIT_STUDENT_T (site [dy]: y_k observes x[site[k]]; nu, scale for Student-t).
+    emit: EMIT_GAUSSIAN (H [dy,dx], R [dy,dy]); EMIT_POISSON_LOG,
+    EMIT_STUDENT_T or EMIT_STOCH_VOL (site [dy]: y_k observes x[site[k]]; nu,
+    scale for Student-t).
     """
     m0: np.ndarray
     P0: np.ndarray

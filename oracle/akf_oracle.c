@@ -17,8 +17,8 @@
  *   or_rts_smooth    RTS smoother marginals and the backward gains, used for the
  *                    Fisher-identity score and moment checks.
  *   or_emission      log h_t, its gradient v_t and Hessian Lambda_t for the
- *                    Gaussian / Poisson-log / Student-t families (Sec. 2.2,
- *                    eq. linearised-log-potential-second).
+ *                    Gaussian / Poisson-log / Student-t / stochastic-volatility
+ *                    families (Sec. 2.2, eq. linearised-log-potential-second).
  *   or_linearise     pseudo-observations (omega_t, Omega_t) of the auxiliary
  *                    LGSSM: first order (eq. gaussian-FK-proposal) or second
  *                    order (eq. second-order), with Sigma_t = I.
@@ -343,7 +343,7 @@ int or_rts_smooth(int N, int dx, const double* F, const double* mf, const double
 /* Emission families                                                    */
 /* ------------------------------------------------------------------ */
 
-enum { OR_EMIT_GAUSSIAN = 0, OR_EMIT_POISSON_LOG = 1, OR_EMIT_STUDENT_T = 2 };
+enum { OR_EMIT_GAUSSIAN = 0, OR_EMIT_POISSON_LOG = 1, OR_EMIT_STUDENT_T = 2, OR_EMIT_STOCH_VOL = 3 };
 
 typedef struct {
   int N, dx, dy;
@@ -405,6 +405,16 @@ double or_emission(const or_model* M, const double* yt, const double* xt, double
       lh += yt[k] * xt[i] - e;
       if (v) v[i] += yt[k] - e;
       if (Lam) Lam[i * n + i] -= e;
+    }
+  } else if (M->emit == OR_EMIT_STOCH_VOL) {
+    /* y_k ~ N(0, exp(x_i)) (Sec. "Multivariate stochastic volatility model"):
+       log h = -x_i/2 - y_k^2 exp(-x_i)/2 (the -log(2 pi)/2 constant dropped) */
+    for (int k = 0; k < p; ++k) {
+      int i = M->site[k];
+      double q = yt[k] * yt[k] * exp(-xt[i]);
+      lh += -0.5 * xt[i] - 0.5 * q;
+      if (v) v[i] += -0.5 + 0.5 * q;
+      if (Lam) Lam[i * n + i] -= 0.5 * q;
     }
   } else {
     const double a = M->nu * M->scale * M->scale;

@@ -4,7 +4,8 @@ The sampler itself lives in the HIP library libauxkf.so (include/akf.h); this
 package is its Python binding.  Importing the package does not load the
 library; the first call does, and fails loudly if it has not been built.
 """
-from .workloads import (EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T)  # noqa: F401
+from .workloads import (EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T,  # noqa: F401
+                        EMIT_STOCH_VOL)
 
 
 def __getattr__(name):

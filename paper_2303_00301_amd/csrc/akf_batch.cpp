@@ -49,8 +49,8 @@ akf_status check_chain(const akf_chain& c, int k) {
   akf_status s = check_model(&c.model, true);
   if (s != AKF_OK) return s;
   if (c.model.emit == AKF_EMIT_GAUSSIAN)
-    return fail(AKF_ERR_UNSUPPORTED, "chain %d: batched chains support the Poisson and "
-                    "Student-t emission families", k);
+    return fail(AKF_ERR_UNSUPPORTED, "chain %d: batched chains support the Poisson, "
+                    "Student-t and stochastic-volatility emission families", k);
   if (!c.y || !c.x || !c.xi || !c.unif)
     return fail(AKF_ERR_INVALID, "chain %d: y, x, xi and unif must be non-NULL", k);
   if (!(c.delta > 0.0)) return fail(AKF_ERR_INVALID, "chain %d: delta must be > 0", k);

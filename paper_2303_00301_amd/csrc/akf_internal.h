@@ -5,7 +5,7 @@
 
 namespace akf {
 
-enum { EMIT_GAUSSIAN = 0, EMIT_POISSON_LOG = 1, EMIT_STUDENT_T = 2 };
+enum { EMIT_GAUSSIAN = 0, EMIT_POISSON_LOG = 1, EMIT_STUDENT_T = 2, EMIT_STOCH_VOL = 3 };
 enum { ST_FWD_NOT_PD = 1, ST_REV_NOT_PD = 2, ST_NONFINITE = 4 };
 
 // Model as the kernels see it (all arrays are device pointers, d-sized).

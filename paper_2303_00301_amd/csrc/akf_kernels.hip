@@ -52,7 +52,8 @@ __global__ void k_step_init(int* status, double* root_flag, double* root_xin, in
 }
 
 // ---------------------------------------------------------------------------
-// Emission linearisation, diagonal families (Poisson log-link, Student-t).
+// Emission linearisation, diagonal families (Poisson log-link, Student-t,
+// stochastic volatility).
 // One thread per (t, i).  Site k observes latent site[k]; a latent observed by
 // several sites sums their contributions.
 //   v_i = d log h / d x_i,  Lambda_ii = d^2 log h / d x_i^2 (0 under order 1)
@@ -73,6 +74,11 @@ __device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __re
       o.lh += yt[k] * xi - e;
       o.v += yt[k] - e;
       o.lam -= e;
+    } else if (M.emit == EMIT_STOCH_VOL) {
+      const double q = yt[k] * yt[k] * exp(-xi);  // y ~ N(0, exp(x))
+      o.lh += -0.5 * xi - 0.5 * q;
+      o.v += -0.5 + 0.5 * q;
+      o.lam -= 0.5 * q;
     } else {
       const double a = M.nu * M.scale * M.scale;
       const double r = yt[k] - xi, den = a + r * r;

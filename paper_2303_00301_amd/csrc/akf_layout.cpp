@@ -144,6 +144,9 @@ akf_status check_model(const akf_model* m, bool need_emission) {
     case AKF_EMIT_POISSON_LOG:
       if (!m->site) return fail(AKF_ERR_INVALID, "Poisson emission needs site");
       break;
+    case AKF_EMIT_STOCH_VOL:
+      if (!m->site) return fail(AKF_ERR_INVALID, "stochastic-volatility emission needs site");
+      break;
     case AKF_EMIT_STUDENT_T:
       if (!m->site) return fail(AKF_ERR_INVALID, "Student-t emission needs site");
       if (!(m->nu > 0.0) || !(m->scale > 0.0))

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 
-EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T = 0, 1, 2
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL = 0, 1, 2, 3
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
 

@@ -10,7 +10,7 @@ Seeds: model/data from ``default_rng(data_seed)``, step normals from
 ``default_rng(100 + cfg)``, uniforms from ``default_rng(200 + cfg)``.
 
 Emission codes match the C-ABI: 0 Gaussian (H, R), 1 Poisson with log link,
-2 Student-t at observation sites.
+2 Student-t at observation sites, 3 stochastic volatility (y ~ N(0, exp(x))).
 """
 from __future__ import annotations
 
@@ -19,7 +19,7 @@ from typing import List, Optional
 
 import numpy as np
 
-EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T = 0, 1, 2
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL = 0, 1, 2, 3
 
 
 @dataclass
@@ -156,6 +156,33 @@ def latent_field(N: int = 4096, d: int = 64, n_sites: int = 32, nu: float = 3.0,
     return Workload(f"latent_field_d{d}_N{N}", N, m0, P0, F, Q, EMIT_STUDENT_T, y, site=site,
                     nu=nu, scale=scale, delta=LATENT_FIELD_DELTA if delta is None else delta,
                     order=2, seed=seed, x_true=x)
+
+
+# Step sizes of the stochastic-volatility workload (d = 30, T = 250, seed 6) toward
+# the paper's 50% acceptance: a 600-step Robbins-Monro warm-up on log delta (gain
+# k^-0.6, the recursion of paper_2303_00301_amd.mcmc.tune_delta) started at the
+# simulated path, then frozen; 400 frozen steps accepted 47% (order 1) and 49%
+# (order 2).
+STOCH_VOL_DELTA = {1: 0.039, 2: 0.091}
+
+
+def stoch_vol(N: int = 250, d: int = 30, order: int = 2, seed: int = 6,
+              delta: Optional[float] = None) -> Workload:
+    """Multivariate stochastic volatility (Sec. "Multivariate stochastic
+    volatility model"): F = phi I, Q_ij = tau (1 if i = j else rho) with
+    phi = 0.9, tau = 2, rho = 0.25, x_0 from the stationary law
+    N(0, Q / (1 - phi^2)), and y_t(k) ~ N(0, exp(x_t(k))) for every coordinate."""
+    rng = np.random.default_rng(seed)
+    phi, tau, rho = 0.9, 2.0, 0.25
+    F = phi * np.eye(d)
+    Q = tau * (rho * np.ones((d, d)) + (1.0 - rho) * np.eye(d))
+    m0, P0 = np.zeros(d), Q / (1.0 - phi * phi)
+    x = _simulate(rng, N, m0, P0, F, Q)
+    y = np.exp(0.5 * x) * rng.standard_normal((N, d))
+    return Workload(f"stoch_vol_d{d}_N{N}", N, m0, P0, F, Q, EMIT_STOCH_VOL, y,
+                    site=np.arange(d, dtype=np.int32),
+                    delta=STOCH_VOL_DELTA[order] if delta is None else delta, order=order,
+                    seed=seed, x_true=x)
 
 
 def ragged_poisson_batch(n_chains: int = 512, n_min: int = 128, n_max: int = 8192,

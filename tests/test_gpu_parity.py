@@ -203,6 +203,20 @@ def test_latent_field_steps(S, N, block):
         x = r["x_out"]
 
 
+@pytest.mark.parametrize("order,block", [(1, 0), (2, 0), (2, 7)])
+def test_stoch_vol_steps(S, order, block):
+    """Multivariate stochastic volatility (d = 30, T = 250), both orders."""
+    w = W.stoch_vol(order=order)
+    M_or = oracle.Model(**w.oracle_kwargs())
+    M_dev = S.DeviceModel.from_workload(w, device=dev())
+    xi = w.normals(3)
+    un = w.uniforms(3)
+    x = w.x_true.copy()
+    for k in range(3):
+        r = _compare_step(S, M_or, M_dev, w.y, x, w.delta, order, xi[k], un[k], block=block)
+        x = r["x_out"]
+
+
 def test_latent_field_full_size_one_step(S):
     """d = 64, N = 4096 (the benchmark workload), one step in the benchmark's
     launch configuration, against the oracle."""

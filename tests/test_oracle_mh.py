@@ -1,6 +1,7 @@
 """Pins for the oracle's emission linearisation and MH step (CPU only).
 
 * v_t, Lambda_t vs central finite differences of log h_t (every family);
+* the stochastic-volatility log h_t vs scipy's normal log-density;
 * the linearised potential plus the auxiliary Gaussian equals the pseudo-
   observation Gaussian up to a constant in z (eq. gaussian-FK-proposal,
   eq. second-order), and order 2 is exact for Gaussian emissions;
@@ -31,7 +32,7 @@ def _model(emit, dx, rng, dy=None):
         dy = dy or dx
         C = rng.standard_normal((dy, dy))
         kw.update(H=rng.standard_normal((dy, dx)), R=C @ C.T / dy + 0.3 * np.eye(dy))
-    elif emit == oracle.EMIT_POISSON_LOG:
+    elif emit in (oracle.EMIT_POISSON_LOG, oracle.EMIT_STOCH_VOL):
         dy = dy or dx
         kw.update(site=rng.integers(0, dx, size=dy).astype(np.int32))
     else:
@@ -46,7 +47,7 @@ def _y(M, dy, N, rng):
     return rng.standard_normal((N, dy))
 
 
-@pytest.mark.parametrize("emit", [0, 1, 2])
+@pytest.mark.parametrize("emit", [0, 1, 2, 3])
 def test_emission_gradient_hessian_fd(emit):
     rng = np.random.default_rng(10 + emit)
     for dx in (1, 3, 5):
@@ -62,7 +63,23 @@ def test_emission_gradient_hessian_fd(emit):
         np.testing.assert_allclose(Lam, Hs, rtol=1e-6, atol=1e-6)
 
 
-@pytest.mark.parametrize("emit,order", [(0, 1), (0, 2), (1, 1), (1, 2), (2, 1), (2, 2)])
+def test_stoch_vol_log_h_is_normal_log_density():
+    """Stochastic volatility: log h = sum_k log N(y_k; 0, exp(x_site[k])) up to the
+    constant -dy log(2 pi)/2 (scipy's normal log-density as the reference)."""
+    from scipy.stats import norm
+    rng = np.random.default_rng(77)
+    for dx, dy in ((1, 1), (4, 6), (30, 30)):
+        M, _ = _model(oracle.EMIT_STOCH_VOL, dx, rng, dy=dy)
+        for _ in range(3):
+            yt = 2.0 * rng.standard_normal(dy)
+            xt = 1.5 * rng.standard_normal(dx)
+            lh = oracle.emission(M, yt, xt)[0]
+            ref = norm.logpdf(yt, 0.0, np.exp(0.5 * xt[M.site])).sum() + 0.5 * dy * np.log(2 * np.pi)
+            assert abs(lh - ref) < 1e-10 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("emit,order", [(0, 1), (0, 2), (1, 1), (1, 2), (2, 1), (2, 2), (3, 1),
+                                        (3, 2)])
 def test_linearised_proposal_is_pseudo_observation_gaussian(emit, order):
     """vᵀ(z-x) + ½(z-x)ᵀΛ(z-x) + log N(u; z, δ/2 I) - log N(ω; z, Ω) is constant in z."""
     rng = np.random.default_rng(20 + emit)
@@ -129,7 +146,8 @@ def _brute_log_ratio(M, y, x, xs, u, delta, order):
 
 
 @pytest.mark.parametrize("emit,order,N,dx", [(0, 1, 4, 2), (0, 2, 3, 2), (1, 1, 5, 1), (1, 2, 4, 2),
-                                             (2, 1, 3, 3), (2, 2, 5, 2)])
+                                             (2, 1, 3, 3), (2, 2, 5, 2), (3, 1, 4, 2),
+                                             (3, 2, 3, 3)])
 def test_log_ratio_vs_dense_brute_force(emit, order, N, dx):
     rng = np.random.default_rng(40 + 3 * emit + order)
     M, dy = _model(emit, dx, rng)
@@ -196,6 +214,9 @@ def _quadrature_posterior(M, y, lim=8.0, n=801):
     for t, X in ((0, X0), (1, X1)):
         if M.emit == oracle.EMIT_POISSON_LOG:
             lp = lp + y[t, 0] * X - np.exp(X)
+        elif M.emit == oracle.EMIT_STOCH_VOL:
+            from scipy.stats import norm
+            lp = lp + norm.logpdf(y[t, 0], 0.0, np.exp(0.5 * X))
         else:
             a = M.nu * M.scale ** 2
             lp = lp - 0.5 * (M.nu + 1) * np.log1p((y[t, 0] - X) ** 2 / a)
@@ -204,7 +225,7 @@ def _quadrature_posterior(M, y, lim=8.0, n=801):
     return np.array([(w * X0).sum(), (w * X1).sum(), (w * X0 ** 2).sum(), (w * X1 ** 2).sum()])
 
 
-@pytest.mark.parametrize("emit,order,delta", [(1, 2, 1.5), (2, 2, 2.0), (2, 1, 1.0)])
+@pytest.mark.parametrize("emit,order,delta", [(1, 2, 1.5), (2, 2, 2.0), (2, 1, 1.0), (3, 2, 1.5)])
 def test_long_chain_matches_quadrature(emit, order, delta):
     """N = 2, d = 1: a 4e5-step chain must reproduce the posterior moments of
     (x_0, x_1) within 5 batch-means standard errors; a wrong Hastings ratio
@@ -214,6 +235,8 @@ def test_long_chain_matches_quadrature(emit, order, delta):
     if emit == oracle.EMIT_STUDENT_T:
         kw.update(nu=3.0, scale=0.5)
         y = np.array([[2.5], [-1.0]])
+    elif emit == oracle.EMIT_STOCH_VOL:
+        y = np.array([[2.0], [0.3]])
     else:
         y = np.array([[4.0], [0.0]])
     M = oracle.Model(**kw)
