@@ -236,6 +236,69 @@ def bench_stoch_vol(torch, S, W, K: int, dev) -> dict:
     return out
 
 
+def bench_spatio_temporal(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dict:
+    """Second paper workload: the spatio-temporal model (8 x 8 lattice, T = 1024,
+    multivariate-t observations with nu = 1), first order, one chain.  The
+    factorised step (64 scalar filters/samplers) is the product path; the dense
+    step on the same model is timed beside it."""
+    import ctypes as C
+    w = W.spatio_temporal()
+    Md = S.DeviceModel.from_workload(w, device=dev)
+    Mf = Md.diagonal()
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(80)
+    xi = torch.randn((K + 3, 2, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
+    un = torch.rand((K + 3,), dtype=torch.float64, device=dev, generator=gen).clamp_(min=1e-300)
+    out = {"workload": "spatio_temporal_8x8_T1024: random walks (sigma_x = 1) on an 8 x 8 "
+                       "lattice, multivariate-t observations (nu = 1, precision tau^D, tau = -1/4, "
+                       "D <= 1), first-order proposal, one chain",
+           "delta": w.delta}
+    lib = _lib.load()
+    for name, M, fact, k in (("factorised", Mf, True, K), ("dense", Md, False, max(2, K // 10))):
+        x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
+        ws = S.Workspace(dev)
+        S.mh_run(M, y, x, w.delta, 1, xi[:3], un[:3], ws=ws, factorised=fact)
+        torch.cuda.synchronize()
+        if fact:
+            _lib.check(lib.akf_timing_enable(_lib.FAMILIES["fact_scan"], 2 * k + 8),
+                       "akf_timing_enable")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = S.mh_run(M, y, x, w.delta, 1, xi[3:3 + k], un[3:3 + k], ws=ws, factorised=fact)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / k
+        res = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+               "acceptance": r["accepted"].float().mean().item(), "steps": k}
+        if fact:
+            n_l, k_ms = C.c_int32(), C.c_double()
+            _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
+            lib.akf_timing_enable(-1, 0)
+            if n_l.value:
+                res["k_fact_scan_avg_us"] = 1000.0 * k_ms.value / n_l.value
+        out[name] = res
+    out["paper_reference"] = ("0.52 ms per iteration for the parallel-in-time auxiliary Kalman "
+                              "sampler on an RTX 3090 (another machine: context only)")
+    if cpu_steps > 0:
+        import oracle
+        Mo = oracle.Model(**w.oracle_kwargs())
+        xin = w.normals(cpu_steps)
+        uin = w.uniforms(cpu_steps)
+        xc = w.x_true.copy()
+        t0 = time.perf_counter()
+        for k in range(cpu_steps):
+            rr = oracle.mh_step_factorised(Mo, w.y, xc, w.delta, 1, xin[k, 0], xin[k, 1], uin[k])
+            xc = rr["x_out"]
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": cpu_steps / dt, "unit": "steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{cpu_steps} factorised MH steps of the same workload by "
+                                         f"the sequential FP64 C oracle on one host thread, "
+                                         f"{dt:.1f} s"}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -249,6 +312,7 @@ def main() -> int:
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-stoch-vol", action="store_true")
+    ap.add_argument("--no-spatio-temporal", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
                          "reference for the HBM byte counters)")
@@ -351,6 +415,9 @@ def main() -> int:
         res["adjoint"] = bench_adjoint(torch, S, W, 5, dev)
     if not args.no_stoch_vol:
         res["stoch_vol"] = bench_stoch_vol(torch, S, W, 20, dev)
+    if not args.no_spatio_temporal:
+        res["spatio_temporal"] = bench_spatio_temporal(
+            torch, S, W, _lib, 100, dev, 0 if args.no_cpu_baseline else 100)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     if args.copy_calibration > 0:

@@ -52,7 +52,10 @@ typedef enum {
   AKF_EMIT_GAUSSIAN = 0,    /* y_t = H x_t + N(0, R): H [dy,dx], R [dy,dy] SPD */
   AKF_EMIT_POISSON_LOG = 1, /* y_{t,k} ~ Poisson(exp(x_{t,site[k]})) */
   AKF_EMIT_STUDENT_T = 2,   /* y_{t,k} = x_{t,site[k]} + scale * t_nu */
-  AKF_EMIT_STOCH_VOL = 3    /* y_{t,k} ~ N(0, exp(x_{t,site[k]})) (stochastic volatility) */
+  AKF_EMIT_STOCH_VOL = 3,   /* y_{t,k} ~ N(0, exp(x_{t,site[k]})) (stochastic volatility) */
+  AKF_EMIT_MVT = 4          /* y_t = x_t[site] + V_t, V_t multivariate t with nu degrees of
+                               freedom and precision R [dy,dy] (Sec. "Spatio-temporal model");
+                               first-order proposals only */
 } akf_emit;
 
 /* Per-step device status bits. */
@@ -68,9 +71,12 @@ enum {
 /*
  * Model description (eq. ssm with Gaussian dynamics).  m0 [dx], P0 [dx,dx],
  * F [dx,dx], b [dx] or NULL (zero), Q [dx,dx].  Emission per `emit`:
- * GAUSSIAN uses H, R; POISSON_LOG, STUDENT_T and STOCH_VOL use site [dy] (int32, each in
- * [0, dx); several sites may observe the same coordinate) and, for STUDENT_T,
- * nu > 0 and scale > 0.  All pointers are device pointers.
+ * GAUSSIAN uses H, R; POISSON_LOG, STUDENT_T, STOCH_VOL and MVT use site [dy]
+ * (int32, each in [0, dx); several sites may observe the same coordinate);
+ * STUDENT_T also nu > 0 and scale > 0; MVT also the precision R [dy,dy]
+ * (symmetric positive definite) and nu > 0.  All pointers are device pointers.
+ * MVT with order 2 is rejected with AKF_ERR_UNSUPPORTED (its Hessian would
+ * make Omega_t dense and time-varying).
  */
 typedef struct akf_model {
   int32_t N, dx, dy;
@@ -120,6 +126,34 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
                       int32_t order, int32_t n_steps, const double* xi, const double* unif,
                       double* log_ratio, int32_t* accepted, double* logZ_fwd, double* logZ_rev,
                       int32_t* status, void* ws, size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * Factorised step (Sec. "Spatio-temporal model").  When P0, F and Q are
+ * diagonal the prior is a product over coordinates; with a diagonal Omega_t
+ * (first order, or second order with the POISSON_LOG, STUDENT_T or STOCH_VOL
+ * families, whose Hessians are diagonal) the auxiliary linear-Gaussian model
+ * is then dx independent scalar models, while the target stays coupled
+ * through h_t.  These entry points run the same MH step as akf_mh_step /
+ * akf_mh_run (same arguments, outputs, status bits and normals) with dx scalar
+ * filters and samplers in place of the dense ones.
+ *   - model->P0, model->F and model->Q point to the DIAGONALS, [dx] each;
+ *     m0 [dx] and b [dx] (or NULL) as usual.
+ *   - emission: any family but GAUSSIAN (AKF_ERR_UNSUPPORTED); MVT needs
+ *     order 1.
+ *   - no scan-block argument: one workgroup per coordinate walks time in
+ *     chunks of at most 2048 steps.
+ */
+size_t akf_mh_factorised_workspace_bytes(const akf_model* model, int32_t order);
+akf_status akf_mh_step_factorised(const akf_model* model, const double* y, const double* x_in,
+                                  double delta, int32_t order, const double* xi,
+                                  const double* unif, double* x_out, double* log_ratio,
+                                  int32_t* accepted, double* logZ_fwd, double* logZ_rev,
+                                  int32_t* status, void* ws, size_t ws_bytes, void* stream);
+akf_status akf_mh_run_factorised(const akf_model* model, const double* y, double* x, double delta,
+                                 int32_t order, int32_t n_steps, const double* xi,
+                                 const double* unif, double* log_ratio, int32_t* accepted,
+                                 double* logZ_fwd, double* logZ_rev, int32_t* status, void* ws,
+                                 size_t ws_bytes, void* stream);
 
 /*
  * Parallel-in-time Kalman filter of the auxiliary linear-Gaussian model
@@ -203,7 +237,7 @@ akf_status akf_lgssm_loglik_grad(const akf_lgssm* m, const double* ll_bar, doubl
  * items, so the whole batch needs a few dozen launches per step instead of a
  * few dozen per chain.  One step is captured in a hipGraph and replayed; a
  * device step counter selects each step's normals and outputs.  Emissions:
- * Poisson log-link and Student-t.
+ * Poisson log-link, Student-t and stochastic volatility.
  *
  * Per chain (device pointers): model, y [N,dy], x [N,dx] (updated in place),
  * xi [n_steps,2,N,dx], unif [n_steps], delta, order, and optional per-step
@@ -256,7 +290,8 @@ void akf_batch_plan_destroy(akf_batch_plan* plan);
  * (0 filter fold, 1 filter scan levels (Hillis-Steele levels for one chain,
  * up-sweep levels for batched chains), 2 filter down-sweep, 3 filter final,
  * 4 sampler element build, 5 sampler fold, 6 sampler up-sweep, 7 sampler
- * down-sweep, 8 sampler final), every launch of that kernel on any stream is
+ * down-sweep, 8 sampler final, 9 factorised scalar filter/sampler,
+ * 10 emission linearisation), every launch of that kernel on any stream is
  * bracketed by a pair of hipEvents recorded on the launch stream; at most
  * `capacity` launches are kept.  akf_timing_collect waits for the recorded
  * events and returns the number of launches and their summed duration in

@@ -26,7 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "akf_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL = 0, 1, 2, 3
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
 
@@ -83,6 +83,12 @@ def _declare(L):
     L.or_mh_chain.restype = C.c_int
     L.or_mh_chain.argtypes = [C.POINTER(_Model), _dp, _dp, C.c_double, C.c_int, C.c_int, _dp, _dp,
                               _dp, _ip, _ip, _dp]
+    L.or_mh_step_factorised.restype = C.c_int
+    L.or_mh_step_factorised.argtypes = [C.POINTER(_Model), _dp, _dp, C.c_double, C.c_int, _dp, _dp,
+                                        C.c_double, _dp, _dp, _ip, _dp, _dp, _dp]
+    L.or_mh_chain_factorised.restype = C.c_int
+    L.or_mh_chain_factorised.argtypes = [C.POINTER(_Model), _dp, _dp, C.c_double, C.c_int, C.c_int,
+                                         _dp, _dp, _dp, _ip, _ip, _dp]
     L.or_lgssm_loglik.restype = C.c_double
     L.or_lgssm_loglik.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_fisher_score.restype = C.c_double
@@ -107,7 +113,7 @@ class Model:
 
     emit: EMIT_GAUSSIAN (H [dy,dx], R [dy,dy]); EMIT_POISSON_LOG,
     EMIT_STUDENT_T or EMIT_STOCH_VOL (site [dy]: y_k observes x[site[k]]; nu,
-    scale for Student-t).
+    scale for Student-t); EMIT_MVT (site [dy], precision R [dy,dy], nu).
     """
     m0: np.ndarray
     P0: np.ndarray
@@ -235,7 +241,24 @@ def mh_step(M: Model, y, x, delta, order, xi_u, xi_x, unif):
                 logZ_rev=lzr.value, status=int(st), xstar=xs, ell_fwd=ell)
 
 
-def mh_chain(M: Model, y, x0, delta, order, xi, unif, keep_samples=True):
+def mh_step_factorised(M: Model, y, x, delta, order, xi_u, xi_x, unif):
+    """mh_step for a prior and Omega_t that factorise over coordinates: dx
+    one-dimensional filters and samplers.  status -1 = the model does not factorise."""
+    y, x, xi_u, xi_x = map(_f64, (y, x, xi_u, xi_x))
+    N = x.shape[0]
+    B = _Bound(M, N)
+    x_out = np.zeros_like(x)
+    xs = np.zeros_like(x)
+    lr, lzf, lzr = C.c_double(), C.c_double(), C.c_double()
+    acc = C.c_int()
+    st = lib().or_mh_step_factorised(B.ref(), _p(y), _p(x), float(delta), int(order), _p(xi_u),
+                                     _p(xi_x), float(unif), _p(x_out), C.byref(lr), C.byref(acc),
+                                     C.byref(lzf), C.byref(lzr), _p(xs))
+    return dict(x_out=x_out, log_ratio=lr.value, accepted=int(acc.value), logZ_fwd=lzf.value,
+                logZ_rev=lzr.value, status=int(st), xstar=xs)
+
+
+def mh_chain(M: Model, y, x0, delta, order, xi, unif, keep_samples=True, factorised=False):
     """n_steps MH steps; xi [n_steps,2,N,dx], unif [n_steps]."""
     y, xi, unif = _f64(y), _f64(xi), _f64(unif)
     x = _f64(x0).copy()
@@ -246,8 +269,11 @@ def mh_chain(M: Model, y, x0, delta, order, xi, unif, keep_samples=True):
     acc = np.zeros(n_steps, dtype=np.int32)
     st = np.zeros(n_steps, dtype=np.int32)
     samples = np.zeros((n_steps,) + x.shape) if keep_samples else None
-    lib().or_mh_chain(B.ref(), _p(y), _p(x), float(delta), int(order), n_steps, _p(xi), _p(unif),
-                      _p(lr), acc.ctypes.data_as(_ip), st.ctypes.data_as(_ip), _p(samples))
+    fn = lib().or_mh_chain_factorised if factorised else lib().or_mh_chain
+    rc = fn(B.ref(), _p(y), _p(x), float(delta), int(order), n_steps, _p(xi), _p(unif), _p(lr),
+            acc.ctypes.data_as(_ip), st.ctypes.data_as(_ip), _p(samples))
+    if rc != 0:
+        raise ValueError("the model does not factorise over coordinates")
     return dict(x=x, log_ratio=lr, accepted=acc, status=st, samples=samples)
 
 

@@ -17,14 +17,18 @@
  *   or_rts_smooth    RTS smoother marginals and the backward gains, used for the
  *                    Fisher-identity score and moment checks.
  *   or_emission      log h_t, its gradient v_t and Hessian Lambda_t for the
- *                    Gaussian / Poisson-log / Student-t / stochastic-volatility
- *                    families (Sec. 2.2, eq. linearised-log-potential-second).
+ *                    Gaussian / Poisson-log / Student-t / stochastic-volatility /
+ *                    multivariate-t families (Sec. 2.2, eq.
+ *                    linearised-log-potential-second).
  *   or_linearise     pseudo-observations (omega_t, Omega_t) of the auxiliary
  *                    LGSSM: first order (eq. gaussian-FK-proposal) or second
  *                    order (eq. second-order), with Sigma_t = I.
  *   or_mh_step       one step of the general auxiliary Kalman sampler
  *                    (Alg. "General Auxiliary Kalman sampler"), Hastings-within-
  *                    Gibbs on x | u.
+ *   or_mh_step_factorised  the same step when the prior and Omega_t are
+ *                    diagonal, as dx one-dimensional filters and samplers
+ *                    (Sec. "Spatio-temporal model").
  *   or_fisher_score  gradient of log p(y | theta) by Fisher's identity for an
  *                    LGSSM with theta = (F, log diag Q, H, log diag R).
  *
@@ -343,22 +347,24 @@ int or_rts_smooth(int N, int dx, const double* F, const double* mf, const double
 /* Emission families                                                    */
 /* ------------------------------------------------------------------ */
 
-enum { OR_EMIT_GAUSSIAN = 0, OR_EMIT_POISSON_LOG = 1, OR_EMIT_STUDENT_T = 2, OR_EMIT_STOCH_VOL = 3 };
+enum { OR_EMIT_GAUSSIAN = 0, OR_EMIT_POISSON_LOG = 1, OR_EMIT_STUDENT_T = 2, OR_EMIT_STOCH_VOL = 3,
+       OR_EMIT_MVT = 4 };
 
 typedef struct {
   int N, dx, dy;
   const double *m0, *P0, *F, *b, *Q;
   int emit;
-  const double *H, *R;  /* Gaussian: [dy,dx], [dy,dy] */
-  const int* site;      /* Poisson / Student-t: y_k observes x[site[k]] */
-  double nu, scale;     /* Student-t */
+  const double *H, *R;  /* Gaussian: [dy,dx], [dy,dy]; multivariate t: R = precision [dy,dy] */
+  const int* site;      /* non-Gaussian families: y_k observes x[site[k]] */
+  double nu, scale;     /* Student-t (nu, scale); multivariate t (nu) */
 } or_model;
 
 /*
  * log h(y_t | x_t) up to an additive constant that does not depend on x,
  * together with v = grad_x log h and Lambda = Hessian (dense [dx,dx]).
  * Constants dropped: Gaussian -(dy log 2pi + logdet R)/2, Poisson -log y!,
- * Student-t log Gamma terms and -log s.  They cancel in the MH ratio.
+ * Student-t log Gamma terms and -log s, multivariate t log Gamma terms,
+ * -(dy/2) log(nu pi) and +(1/2) logdet R.  They cancel in the MH ratio.
  * v and Lam may be NULL.  Returns log h (may be +-inf / nan on overflow).
  */
 double or_emission(const or_model* M, const double* yt, const double* xt, double* v, double* Lam) {
@@ -406,6 +412,34 @@ double or_emission(const or_model* M, const double* yt, const double* xt, double
       if (v) v[i] += yt[k] - e;
       if (Lam) Lam[i * n + i] -= e;
     }
+  } else if (M->emit == OR_EMIT_MVT) {
+    /* y = x[site] + V, V multivariate t (nu degrees of freedom) with precision
+       matrix R [p, p] (Sec. "Spatio-temporal model"):
+       log h = -(nu + p)/2 log(1 + r'R r / nu), r = y - x[site] (constants dropped);
+       v_i = (nu + p)/(nu + q) s_i,  s_i = sum_{k: site[k] = i} (R r)_k,
+       Lambda_ij = (nu + p) [2 s_i s_j / (nu + q)^2 - Rt_ij / (nu + q)],
+       Rt_ij = sum_{k: site[k] = i, l: site[l] = j} R_kl. */
+    double* r = malloc(sizeof(double) * p);
+    double* Rr = malloc(sizeof(double) * p);
+    double* sv = calloc(n, sizeof(double));
+    for (int k = 0; k < p; ++k) r[k] = yt[k] - xt[M->site[k]];
+    mv(p, p, M->R, r, Rr);
+    double q = 0.0;
+    for (int k = 0; k < p; ++k) q += r[k] * Rr[k];
+    const double a = M->nu + p;
+    lh = -0.5 * a * log1p(q / M->nu);
+    for (int k = 0; k < p; ++k) sv[M->site[k]] += Rr[k];
+    if (v)
+      for (int i = 0; i < n; ++i) v[i] = a / (M->nu + q) * sv[i];
+    if (Lam) {
+      const double c1 = a / (M->nu + q), c2 = 2.0 * a / ((M->nu + q) * (M->nu + q));
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Lam[i * n + j] = c2 * sv[i] * sv[j];
+      for (int k = 0; k < p; ++k)
+        for (int l = 0; l < p; ++l) Lam[M->site[k] * n + M->site[l]] -= c1 * M->R[k * p + l];
+      symmetrise(n, Lam);
+    }
+    free(r); free(Rr); free(sv);
   } else if (M->emit == OR_EMIT_STOCH_VOL) {
     /* y_k ~ N(0, exp(x_i)) (Sec. "Multivariate stochastic volatility model"):
        log h = -x_i/2 - y_k^2 exp(-x_i)/2 (the -log(2 pi)/2 constant dropped) */
@@ -608,6 +642,192 @@ int or_mh_chain(const or_model* M, const double* y, double* x, double delta, int
     int acc;
     int st = or_mh_step(M, y, x, delta, order, xi + (size_t)s * 2 * vn, xi + ((size_t)s * 2 + 1) * vn,
                         unif[s], x, &lr, &acc, NULL, NULL, NULL, NULL);
+    if (log_ratio) log_ratio[s] = lr;
+    if (accepted) accepted[s] = acc;
+    if (status) status[s] = st;
+    if (samples) memcpy(samples + (size_t)s * vn, x, sizeof(double) * vn);
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* The same step when the auxiliary LGSSM factorises over coordinates   */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Diagonal linearisation: Omega_t = diag(1 / (2/delta - Lambda_t,ii)) and
+ * omega_t,i = Omega_t,i (2/delta u_t,i + v_t,i - Lambda_t,ii x_t,i) (eq.
+ * second-order with Sigma_t = I; Lambda = 0 under order 1).  Omega [N,dx]
+ * holds the diagonals.  Returns 0, 1 + t when a precision is not positive at
+ * step t, or -1 when order 2 meets an off-diagonal Hessian entry.
+ */
+static int linearise_diag(const or_model* M, const double* y, const double* x, const double* u,
+                          double delta, int order, double* omega, double* Omega, double* loghsum) {
+  const int n = M->dx, p = M->dy;
+  double* v = malloc(sizeof(double) * n);
+  double* Lam = malloc(sizeof(double) * n * n);
+  double lhs = 0.0;
+  int rc = 0;
+  for (long t = 0; t < M->N && rc >= 0; ++t) {
+    const double* xt = x + t * n;
+    lhs += or_emission(M, y + t * p, xt, v, Lam);
+    for (int i = 0; i < n; ++i) {
+      for (int j = 0; j < n; ++j)
+        if (order == 2 && i != j && Lam[i * n + j] != 0.0) rc = -1;
+      const double lam = (order == 1) ? 0.0 : Lam[i * n + i];
+      const double prec = 2.0 / delta - lam;
+      if (!(prec > 0.0) || !isfinite(v[i])) {
+        if (rc == 0) rc = 1 + (int)t;
+        omega[t * n + i] = 0.0;
+        Omega[t * n + i] = 1.0;
+        continue;
+      }
+      Omega[t * n + i] = 1.0 / prec;
+      omega[t * n + i] = Omega[t * n + i] * (2.0 / delta * u[t * n + i] + v[i] - lam * xt[i]);
+    }
+  }
+  if (loghsum) *loghsum = lhs;
+  free(v); free(Lam);
+  return rc;
+}
+
+/*
+ * Auxiliary LGSSM of a factorising prior (P0, F, Q diagonal) with diagonal
+ * Omega_t: dx independent one-dimensional LGSSMs (Sec. "Spatio-temporal
+ * model"), each filtered by or_kf and, when xi_x != NULL, sampled by
+ * or_rts_sample with dx = dy = 1.  Returns the sum of the per-coordinate log
+ * marginal likelihoods (NaN on a filter failure); xs [N,dx] receives the path.
+ */
+static double factorised_filter_sample(const or_model* M, const double* om, const double* Om,
+                                       const double* xi_x, double* xs, int* fail) {
+  const int N = M->N, n = M->dx;
+  double* yi = malloc(sizeof(double) * N);
+  double* Ri = malloc(sizeof(double) * N);
+  double* xii = malloc(sizeof(double) * N);
+  double* mf = malloc(sizeof(double) * N);
+  double* Pf = malloc(sizeof(double) * N);
+  double* mp = malloc(sizeof(double) * N);
+  double* Pp = malloc(sizeof(double) * N);
+  double* ell = malloc(sizeof(double) * N);
+  double* xo = malloc(sizeof(double) * N);
+  const double one = 1.0;
+  double lz = 0.0;
+  *fail = 0;
+  for (int i = 0; i < n && !*fail; ++i) {
+    for (int t = 0; t < N; ++t) {
+      yi[t] = om[(long)t * n + i];
+      Ri[t] = Om[(long)t * n + i];
+    }
+    const double F = M->F[i * n + i], Q = M->Q[i * n + i], P0 = M->P0[i * n + i];
+    if (or_kf(N, 1, 1, M->m0 + i, &P0, &F, M->b ? M->b + i : NULL, &Q, &one, 0, Ri, 1, yi, mf, Pf,
+              mp, Pp, ell)) {
+      *fail = 1;
+      break;
+    }
+    for (int t = 0; t < N; ++t) lz += ell[t];
+    if (xi_x) {
+      for (int t = 0; t < N; ++t) xii[t] = xi_x[(long)t * n + i];
+      if (or_rts_sample(N, 1, &F, mf, Pf, mp, Pp, xii, xo)) {
+        *fail = 1;
+        break;
+      }
+      for (int t = 0; t < N; ++t) xs[(long)t * n + i] = xo[t];
+    }
+  }
+  free(yi); free(Ri); free(xii); free(mf); free(Pf); free(mp); free(Pp); free(ell); free(xo);
+  return *fail ? NAN : lz;
+}
+
+/*
+ * or_mh_step for a prior that factorises over coordinates (P0, F and Q
+ * diagonal; b arbitrary) and a diagonal Omega_t (order 1, or order 2 with a
+ * diagonal emission Hessian).  The auxiliary proposal is then a product of dx
+ * one-dimensional LGSSMs while the target stays coupled through h_t (Sec.
+ * "Spatio-temporal model").  Same inputs, outputs and status bits as
+ * or_mh_step; returns -1 when the model does not factorise.
+ */
+int or_mh_step_factorised(const or_model* M, const double* y, const double* x, double delta,
+                          int order, const double* xi_u, const double* xi_x, double unif,
+                          double* x_out, double* log_ratio, int* accepted, double* logZ_fwd,
+                          double* logZ_rev, double* xstar_out) {
+  const int N = M->N, n = M->dx;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (i != j && (M->F[i * n + j] != 0.0 || M->Q[i * n + j] != 0.0 || M->P0[i * n + j] != 0.0))
+        return -1;
+  const size_t vn = (size_t)N * n;
+  double* u = malloc(sizeof(double) * vn);
+  double* om = malloc(sizeof(double) * vn);
+  double* Om = malloc(sizeof(double) * vn);
+  double* om2 = malloc(sizeof(double) * vn);
+  double* Om2 = malloc(sizeof(double) * vn);
+  double* xs = malloc(sizeof(double) * vn);
+  int status = 0, rc, fail;
+  double lr = -INFINITY, lzf = NAN, lzr = NAN, lh_x = 0.0, lh_s = 0.0;
+  const double su = sqrt(0.5 * delta);
+  for (size_t i = 0; i < vn; ++i) u[i] = x[i] + su * xi_u[i];
+
+  rc = linearise_diag(M, y, x, u, delta, order, om, Om, &lh_x);
+  if (rc < 0) goto unsupported;
+  if (rc) status |= OR_ST_FWD_NOT_PD;
+  if (!status) {
+    lzf = factorised_filter_sample(M, om, Om, xi_x, xs, &fail);
+    if (fail) status |= OR_ST_FWD_NOT_PD;
+  }
+  if (!status) {
+    if (xstar_out) memcpy(xstar_out, xs, sizeof(double) * vn);
+    rc = linearise_diag(M, y, xs, u, delta, order, om2, Om2, &lh_s);
+    if (rc < 0) goto unsupported;
+    if (rc) status |= OR_ST_REV_NOT_PD;
+  }
+  if (!status) {
+    lzr = factorised_filter_sample(M, om2, Om2, NULL, NULL, &fail);
+    if (fail) status |= OR_ST_REV_NOT_PD;
+  }
+  if (!status) {
+    double aux = 0.0, q_rev = 0.0, q_fwd = 0.0;
+    for (size_t i = 0; i < vn; ++i) {
+      const double a = u[i] - x[i], c = u[i] - xs[i];
+      aux += a * a - c * c;
+      const double r2 = om2[i] - x[i], f2 = om[i] - xs[i];
+      q_rev += -0.5 * (LOG2PI + log(Om2[i]) + r2 * r2 / Om2[i]);
+      q_fwd += -0.5 * (LOG2PI + log(Om[i]) + f2 * f2 / Om[i]);
+    }
+    lr = (lh_s - lh_x) + aux / delta + (q_rev - q_fwd) + (lzf - lzr);
+    if (!isfinite(lr)) {
+      status |= OR_ST_NONFINITE;
+      lr = -INFINITY;
+    }
+  }
+  {
+    const int acc = (status == 0) && (log(unif) < lr);
+    if (status) lr = -INFINITY;
+    if (x_out != x) memcpy(x_out, x, sizeof(double) * vn);
+    if (acc) memcpy(x_out, xs, sizeof(double) * vn);
+    if (log_ratio) *log_ratio = lr;
+    if (accepted) *accepted = acc;
+    if (logZ_fwd) *logZ_fwd = lzf;
+    if (logZ_rev) *logZ_rev = lzr;
+  }
+  free(u); free(om); free(Om); free(om2); free(Om2); free(xs);
+  return status;
+unsupported:
+  free(u); free(om); free(Om); free(om2); free(Om2); free(xs);
+  return -1;
+}
+
+/* A chain of or_mh_step_factorised steps; arguments as or_mh_chain. */
+int or_mh_chain_factorised(const or_model* M, const double* y, double* x, double delta, int order,
+                           int n_steps, const double* xi, const double* unif, double* log_ratio,
+                           int* accepted, int* status, double* samples) {
+  const size_t vn = (size_t)M->N * M->dx;
+  for (int s = 0; s < n_steps; ++s) {
+    double lr;
+    int acc;
+    int st = or_mh_step_factorised(M, y, x, delta, order, xi + (size_t)s * 2 * vn,
+                                   xi + ((size_t)s * 2 + 1) * vn, unif[s], x, &lr, &acc, NULL,
+                                   NULL, NULL);
+    if (st < 0) return -1;
     if (log_ratio) log_ratio[s] = lr;
     if (accepted) accepted[s] = acc;
     if (status) status[s] = st;

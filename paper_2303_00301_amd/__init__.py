@@ -5,7 +5,7 @@ package is its Python binding.  Importing the package does not load the
 library; the first call does, and fails loudly if it has not been built.
 """
 from .workloads import (EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T,  # noqa: F401
-                        EMIT_STOCH_VOL)
+                        EMIT_STOCH_VOL, EMIT_MVT)
 
 
 def __getattr__(name):

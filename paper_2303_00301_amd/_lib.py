@@ -60,6 +60,11 @@ SIGNATURES = {
                               _vp, _sz, _i32, _vp]),
     "akf_mh_run": (C.c_int, [_MP, _vp, _vp, _d, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                              _vp, _sz, _i32, _vp]),
+    "akf_mh_factorised_workspace_bytes": (_sz, [_MP, _i32]),
+    "akf_mh_step_factorised": (C.c_int, [_MP, _vp, _vp, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _vp, _vp, _vp, _sz, _vp]),
+    "akf_mh_run_factorised": (C.c_int, [_MP, _vp, _vp, _d, _i32, _i32, _vp, _vp, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, _sz, _vp]),
     "akf_filter_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_aux_filter": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
     "akf_sampler_workspace_bytes": (_sz, [_MP, _i32]),
@@ -83,7 +88,8 @@ SIGNATURES = {
 
 # kernel families of akf_timing_enable
 FAMILIES = {"filter_fold": 0, "filter_up": 1, "filter_down": 2, "filter_final": 3,
-            "samp_build": 4, "samp_fold": 5, "samp_up": 6, "samp_down": 7, "samp_final": 8}
+            "samp_build": 4, "samp_fold": 5, "samp_up": 6, "samp_down": 7, "samp_final": 8,
+            "fact_scan": 9, "lin": 10}
 
 _lib = None
 

@@ -15,12 +15,8 @@ using namespace akf;
 
 namespace {
 
-akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
-                        double delta, int order, const double* xi, const double* unif,
-                        double* x_out, double* log_ratio, int32_t* accepted, double* logZ_fwd,
-                        double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st) {
-  const size_t vn = (size_t)M.N * M.d;
-  int* status = at<int>(ws, Lo.status);
+StepArgs make_step_args(const Layout& Lo, void* ws, const double* y, const double* x_in,
+                        double delta, int order, const double* xi) {
   StepArgs A{};
   A.y = y;
   A.x = x_in;
@@ -43,8 +39,18 @@ akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, cons
   A.g_Omd = at<double>(ws, Lo.gOmd);
   A.g_Omd_inv = at<double>(ws, Lo.gOmdinv);
   A.g_scal = at<double>(ws, Lo.gscal);
-  A.status = status;
+  A.status = at<int>(ws, Lo.status);
   A.accept_flag = at<int>(ws, Lo.accept);
+  return A;
+}
+
+akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
+                        double delta, int order, const double* xi, const double* unif,
+                        double* x_out, double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                        double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st) {
+  const size_t vn = (size_t)M.N * M.d;
+  int* status = at<int>(ws, Lo.status);
+  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, order, xi);
   akf_status s;
   if ((s = hip_check(launch_step_init(status, root_flag(Lo, ws), at<double>(ws, Lo.xin[Lo.L]),
                                       Lo.D, st),
@@ -73,6 +79,63 @@ akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, cons
   F.n_part_fwd = n_part_fwd;
   F.n_part_rev = n_part_rev;
   return hip_check(launch_finalize(M, A, F, x_in, x_out, st), "finalize launch");
+}
+
+// One step with a factorising prior: the same linearisation and MH decision
+// as mh_step_impl, with the dense filter and sampler replaced by dx scalar
+// ones (one workgroup per coordinate).
+akf_status fact_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
+                          double delta, int order, const double* xi, const double* unif,
+                          double* x_out, double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                          double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st) {
+  const size_t vn = (size_t)M.N * M.d;
+  int* status = at<int>(ws, Lo.status);
+  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, order, xi);
+  akf_status s;
+  if ((s = hip_check(launch_step_init(status, nullptr, nullptr, 0, st), "init launch")) != AKF_OK)
+    return s;
+  int n_part_fwd = 0, n_part_rev = 0;
+  if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
+  FactArgs P{};
+  P.om = A.om;
+  P.Om = A.Om;
+  P.xi_x = xi + vn;
+  P.xs = A.xs;
+  P.mf = at<double>(ws, Lo.mf);
+  P.Pf = at<double>(ws, Lo.Pf);
+  P.lz = A.ell;
+  P.status = status;
+  P.fail_bit = ST_FWD_NOT_PD;
+  if ((s = hip_check(launch_fact_scan(M, P, st), "factorised scan launch")) != AKF_OK) return s;
+  if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
+  FactArgs R{};
+  R.om = A.om2;
+  R.Om = A.Om2;
+  R.lz = A.ell2;
+  R.status = status;
+  R.fail_bit = ST_REV_NOT_PD;
+  if ((s = hip_check(launch_fact_scan(M, R, st), "factorised scan launch")) != AKF_OK) return s;
+  FinalArgs F{};
+  F.n_ell = M.d;
+  F.unif = unif;
+  F.log_ratio = log_ratio;
+  F.accepted = accepted;
+  F.logZ_fwd = logZ_fwd;
+  F.logZ_rev = logZ_rev;
+  F.status_out = status_out;
+  F.n_part_fwd = n_part_fwd;
+  F.n_part_rev = n_part_rev;
+  return hip_check(launch_finalize(M, A, F, x_in, x_out, st), "finalize launch");
+}
+
+akf_status check_fact_model(const akf_model* model, int order) {
+  akf_status s;
+  if ((s = check_model(model, true)) != AKF_OK) return s;
+  if ((s = check_order(model, order)) != AKF_OK) return s;
+  if (model->emit == AKF_EMIT_GAUSSIAN)
+    return fail(AKF_ERR_UNSUPPORTED, "the factorised step needs a site-based emission family "
+                                     "(its Gaussian emission has a dense H)");
+  return AKF_OK;
 }
 
 // ---- kernel timing hook -------------------------------------------------
@@ -363,7 +426,7 @@ akf_status akf_timing_collect(int32_t* n_launches, double* total_ms) {
 const char* akf_last_error(void) { return akf::last_error(); }
 
 size_t akf_mh_workspace_bytes(const akf_model* model, int32_t order, int32_t block) {
-  if (check_model(model, true) != AKF_OK || (order != 1 && order != 2)) return 0;
+  if (check_model(model, true) != AKF_OK || check_order(model, order) != AKF_OK) return 0;
   Layout Lo;
   make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP);
   return Lo.total;
@@ -378,7 +441,7 @@ akf_status akf_mh_step(const akf_model* model, const double* y, const double* x_
   if (!y || !x_in || !xi || !unif || !x_out)
     return fail(AKF_ERR_INVALID, "y, x_in, xi, unif and x_out must be non-NULL");
   if (!(delta > 0.0)) return fail(AKF_ERR_INVALID, "delta must be > 0");
-  if (order != 1 && order != 2) return fail(AKF_ERR_INVALID, "order must be 1 or 2");
+  if ((s = check_order(model, order)) != AKF_OK) return s;
   if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
   Layout Lo;
   make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP);
@@ -397,7 +460,7 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
   if (!y || !x || !xi || !unif) return fail(AKF_ERR_INVALID, "y, x, xi and unif must be non-NULL");
   if (n_steps < 0) return fail(AKF_ERR_INVALID, "n_steps must be >= 0");
   if (!(delta > 0.0)) return fail(AKF_ERR_INVALID, "delta must be > 0");
-  if (order != 1 && order != 2) return fail(AKF_ERR_INVALID, "order must be 1 or 2");
+  if ((s = check_order(model, order)) != AKF_OK) return s;
   if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
   Layout Lo;
   make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP);
@@ -410,6 +473,55 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
                      log_ratio ? log_ratio + k : nullptr, accepted ? accepted + k : nullptr,
                      logZ_fwd ? logZ_fwd + k : nullptr, logZ_rev ? logZ_rev + k : nullptr,
                      status ? status + k : nullptr, ws, (hipStream_t)stream);
+    if (s != AKF_OK) return s;
+  }
+  return AKF_OK;
+}
+
+size_t akf_mh_factorised_workspace_bytes(const akf_model* model, int32_t order) {
+  if (check_fact_model(model, order) != AKF_OK) return 0;
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, model->dy, 0, LAYOUT_FACT);
+  return Lo.total;
+}
+
+akf_status akf_mh_step_factorised(const akf_model* model, const double* y, const double* x_in,
+                                  double delta, int32_t order, const double* xi,
+                                  const double* unif, double* x_out, double* log_ratio,
+                                  int32_t* accepted, double* logZ_fwd, double* logZ_rev,
+                                  int32_t* status, void* ws, size_t ws_bytes, void* stream) {
+  akf_status s;
+  if ((s = check_fact_model(model, order)) != AKF_OK) return s;
+  if (!y || !x_in || !xi || !unif || !x_out)
+    return fail(AKF_ERR_INVALID, "y, x_in, xi, unif and x_out must be non-NULL");
+  if (!(delta > 0.0)) return fail(AKF_ERR_INVALID, "delta must be > 0");
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, model->dy, 0, LAYOUT_FACT);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  return fact_step_impl(Lo, to_kmodel(model), y, x_in, delta, order, xi, unif, x_out, log_ratio,
+                        accepted, logZ_fwd, logZ_rev, status, ws, (hipStream_t)stream);
+}
+
+akf_status akf_mh_run_factorised(const akf_model* model, const double* y, double* x, double delta,
+                                 int32_t order, int32_t n_steps, const double* xi,
+                                 const double* unif, double* log_ratio, int32_t* accepted,
+                                 double* logZ_fwd, double* logZ_rev, int32_t* status, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  akf_status s;
+  if ((s = check_fact_model(model, order)) != AKF_OK) return s;
+  if (!y || !x || !xi || !unif) return fail(AKF_ERR_INVALID, "y, x, xi and unif must be non-NULL");
+  if (n_steps < 0) return fail(AKF_ERR_INVALID, "n_steps must be >= 0");
+  if (!(delta > 0.0)) return fail(AKF_ERR_INVALID, "delta must be > 0");
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, model->dy, 0, LAYOUT_FACT);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  const KModel M = to_kmodel(model);
+  const size_t vn = (size_t)M.N * M.d;
+  for (int k = 0; k < n_steps; ++k) {
+    s = fact_step_impl(Lo, M, y, x, delta, order, xi + (size_t)k * 2 * vn, unif + k, x,
+                       log_ratio ? log_ratio + k : nullptr, accepted ? accepted + k : nullptr,
+                       logZ_fwd ? logZ_fwd + k : nullptr, logZ_rev ? logZ_rev + k : nullptr,
+                       status ? status + k : nullptr, ws, (hipStream_t)stream);
     if (s != AKF_OK) return s;
   }
   return AKF_OK;

@@ -5,8 +5,12 @@
 
 namespace akf {
 
-enum { EMIT_GAUSSIAN = 0, EMIT_POISSON_LOG = 1, EMIT_STUDENT_T = 2, EMIT_STOCH_VOL = 3 };
+enum { EMIT_GAUSSIAN = 0, EMIT_POISSON_LOG = 1, EMIT_STUDENT_T = 2, EMIT_STOCH_VOL = 3,
+       EMIT_MVT = 4 };
 enum { ST_FWD_NOT_PD = 1, ST_REV_NOT_PD = 2, ST_NONFINITE = 4 };
+
+// time steps (one wave each) per workgroup of the multivariate-t linearisation
+constexpr int kMvtWaves = 4;
 
 // Model as the kernels see it (all arrays are device pointers, d-sized).
 struct KModel {
@@ -109,7 +113,20 @@ struct SampArgs {
   int* status;
 };
 
+// Auxiliary LGSSM of a factorising prior: dx scalar models, one per
+// coordinate.  The model's P0, F and Q hold diagonals [d].
+struct FactArgs {
+  const double *om, *Om;  // [N*d] pseudo-observations and their variances
+  const double* xi_x;     // [N*d] path normals; nullptr = filter only
+  double* xs;             // [N*d] sampled path
+  double *mf, *Pf;        // [d*N] filtering moments, coordinate-major (needed with xi_x)
+  double* lz;             // [d] log marginal likelihood per coordinate
+  int* status;
+  int fail_bit;
+};
+
 struct FinalArgs {
+  int n_ell;  // entries of ell/ell2 summed into log Z (0 = N)
   const double* unif;
   double* log_ratio;
   int* accepted;
@@ -198,7 +215,7 @@ struct BatchLaunch {
 enum {
   FAM_FILTER_FOLD = 0, FAM_FILTER_UP = 1, FAM_FILTER_DOWN = 2, FAM_FILTER_FINAL = 3,
   FAM_SAMP_BUILD = 4, FAM_SAMP_FOLD = 5, FAM_SAMP_UP = 6, FAM_SAMP_DOWN = 7, FAM_SAMP_FINAL = 8,
-  FAM_LIN = 9, FAM_FINALIZE = 10, FAM_COUNT = 11
+  FAM_FACT = 9, FAM_LIN = 10, FAM_COUNT = 11
 };
 // Called by the launchers before (begin = 1) and after (begin = 0) each launch.
 void timing_mark(int family, int begin, hipStream_t st);
@@ -227,6 +244,7 @@ hipError_t launch_adj_G_any(int D, LgArgs G, int N, hipStream_t st);
 hipError_t launch_adj_finish_any(int D, const KModel& M, LgArgs G, int nblk, const double* ll_bar,
                                  hipStream_t st);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
+hipError_t launch_fact_scan(const KModel& M, FactArgs P, hipStream_t st);
 
 // Batched launches for one D class.  `step` is the device step counter.
 enum BatchPhase {

@@ -90,6 +90,24 @@ __device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __re
   return o;
 }
 
+// Per-(t, i) tail of the forward linearisation: draws u and writes the
+// diagonal omega/Omega from v_i and Lambda_ii (0 under order 1).
+__device__ __forceinline__ void lin_fwd_point(const StepArgs& A, int64_t gid, double x, double v,
+                                              double lam) {
+  const double u = x + sqrt(0.5 * A.delta) * A.xi_u[gid];
+  A.u[gid] = u;
+  const double prec = 2.0 / A.delta - lam;
+  if (!(prec > 0.0) || !isfinite(v) || !isfinite(prec)) {
+    flag_status(A.status, ST_FWD_NOT_PD);
+    A.om[gid] = 0.0;
+    A.Om[gid] = 1.0;
+  } else {
+    const double Om = 1.0 / prec;
+    A.Om[gid] = Om;
+    A.om[gid] = Om * (2.0 / A.delta * u + v - lam * x);
+  }
+}
+
 // Forward linearisation at x: draws u, writes omega/Omega (diagonal), log h
 // partial sums per workgroup.  blockDim.x = 256.
 __device__ __forceinline__ void lin_fwd_diag_body(const KModel& M, const StepArgs& A, int item) {
@@ -99,20 +117,8 @@ __device__ __forceinline__ void lin_fwd_diag_body(const KModel& M, const StepArg
   if (gid < n) {
     const int t = (int)(gid / M.d), i = (int)(gid % M.d);
     const double x = A.x[gid];
-    const double u = x + sqrt(0.5 * A.delta) * A.xi_u[gid];
-    A.u[gid] = u;
     const EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, x, i);
-    const double lam = (A.order == 1) ? 0.0 : e.lam;
-    const double prec = 2.0 / A.delta - lam;
-    if (!(prec > 0.0) || !isfinite(e.v) || !isfinite(prec)) {
-      flag_status(A.status, ST_FWD_NOT_PD);
-      A.om[gid] = 0.0;
-      A.Om[gid] = 1.0;
-    } else {
-      const double Om = 1.0 / prec;
-      A.Om[gid] = Om;
-      A.om[gid] = Om * (2.0 / A.delta * u + e.v - lam * x);
-    }
+    lin_fwd_point(A, gid, x, e.v, (A.order == 1) ? 0.0 : e.lam);
     lh = e.lh;
   }
   // block partial of log h(x)
@@ -127,33 +133,41 @@ __global__ void __launch_bounds__(256) k_lin_fwd_diag(KModel M, StepArgs A) {
   lin_fwd_diag_body(M, A, blockIdx.x);
 }
 
-// Reverse linearisation at x* with the same u, and the per-(t,i) MH terms:
-//   [log h(y|x*) - log h(y|x)] + [(u-x)^2 - (u-x*)^2]/delta
+// Per-(t, i) tail of the reverse linearisation at x* with the same u: writes
+// omega*/Omega* and returns the MH terms
+//   [(u-x)^2 - (u-x*)^2]/delta
 //   + log N(omega*_i; x_i, Omega*_i) - log N(omega_i; x*_i, Omega_i)
+__device__ __forceinline__ double lin_rev_point(const StepArgs& A, int64_t gid, double xs,
+                                                double v, double lam) {
+  const double x = A.x[gid], u = A.u[gid];
+  const double prec = 2.0 / A.delta - lam;
+  double om2 = 0.0, Om2 = 1.0;
+  if (!(prec > 0.0) || !isfinite(v) || !isfinite(prec)) {
+    flag_status(A.status, ST_REV_NOT_PD);
+  } else {
+    Om2 = 1.0 / prec;
+    om2 = Om2 * (2.0 / A.delta * u + v - lam * xs);
+  }
+  A.om2[gid] = om2;
+  A.Om2[gid] = Om2;
+  const double om = A.om[gid], Om = A.Om[gid];
+  const double a = u - x, c = u - xs;
+  const double rq = om2 - x, fq = om - xs;
+  return (a * a - c * c) / A.delta +
+         (-0.5 * (LOG2PI + log(Om2) + rq * rq / Om2)) - (-0.5 * (LOG2PI + log(Om) + fq * fq / Om));
+}
+
+// Reverse linearisation at x*: per-(t,i) MH terms plus log h(y|x*), reduced
+// per workgroup.
 __device__ __forceinline__ void lin_rev_diag_body(const KModel& M, const StepArgs& A, int item) {
   const int64_t gid = (int64_t)item * blockDim.x + threadIdx.x;
   const int64_t n = (int64_t)M.N * M.d;
   double term = 0.0, lhs = 0.0;
   if (gid < n) {
     const int t = (int)(gid / M.d), i = (int)(gid % M.d);
-    const double x = A.x[gid], xs = A.xs[gid], u = A.u[gid];
+    const double xs = A.xs[gid];
     const EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, xs, i);
-    const double lam = (A.order == 1) ? 0.0 : e.lam;
-    const double prec = 2.0 / A.delta - lam;
-    double om2 = 0.0, Om2 = 1.0;
-    if (!(prec > 0.0) || !isfinite(e.v) || !isfinite(prec)) {
-      flag_status(A.status, ST_REV_NOT_PD);
-    } else {
-      Om2 = 1.0 / prec;
-      om2 = Om2 * (2.0 / A.delta * u + e.v - lam * xs);
-    }
-    A.om2[gid] = om2;
-    A.Om2[gid] = Om2;
-    const double om = A.om[gid], Om = A.Om[gid];
-    const double a = u - x, c = u - xs;
-    const double rq = om2 - x, fq = om - xs;
-    term = (a * a - c * c) / A.delta +
-           (-0.5 * (LOG2PI + log(Om2) + rq * rq / Om2)) - (-0.5 * (LOG2PI + log(Om) + fq * fq / Om));
+    term = lin_rev_point(A, gid, xs, e.v, (A.order == 1) ? 0.0 : e.lam);
     lhs = e.lh;
   }
   __shared__ double red[8];
@@ -174,6 +188,82 @@ __device__ __forceinline__ void lin_rev_diag_body(const KModel& M, const StepArg
 
 __global__ void __launch_bounds__(256) k_lin_rev_diag(KModel M, StepArgs A) {
   lin_rev_diag_body(M, A, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Multivariate-t emission with precision R (Sec. "Spatio-temporal model"):
+// r = y_t - x_t[site], q = r^T R r, log h = -(nu + p)/2 log(1 + q / nu) and
+// v_i = (nu + p)/(nu + q) sum_{k: site[k] = i} (R r)_k.  Its Hessian couples
+// every observed coordinate, so only first-order proposals (Lambda = 0) use it.
+// One wave per time step, MVT_WAVES waves per workgroup sharing R, which is
+// staged transposed in LDS so that lane k walks row k of R bank-conflict free.
+// ---------------------------------------------------------------------------
+constexpr int MVT_WAVES = kMvtWaves;
+
+__device__ __forceinline__ void lin_mvt_body(const KModel& M, const StepArgs& A, int rev,
+                                             int item) {
+  __shared__ double sRt[64 * 64];
+  __shared__ double sr[MVT_WAVES * 64];
+  __shared__ double sRr[MVT_WAVES * 64];
+  __shared__ int ssite[64];
+  __shared__ double red[2 * MVT_WAVES];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int p = M.dy, d = M.d;
+  for (int e = tid; e < p * p; e += blockDim.x) sRt[(e % p) * 64 + e / p] = M.R[e];
+  if (tid < p) ssite[tid] = M.site[tid];
+  const int t = item * MVT_WAVES + w;
+  const bool active = t < M.N;
+  const int64_t base = (int64_t)t * d;
+  const double* xt = (rev ? A.xs : A.x) + base;
+  double r = 0.0;
+  if (active && lane < p) r = A.y[(int64_t)t * p + lane] - xt[M.site[lane]];
+  sr[w * 64 + lane] = r;
+  __syncthreads();
+  double Rr = 0.0;
+  if (active && lane < p)
+    for (int l = 0; l < p; ++l) Rr += sRt[l * 64 + lane] * sr[w * 64 + l];
+  double q = r * Rr;
+  for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+  sRr[w * 64 + lane] = Rr;
+  __syncthreads();
+  const double a = M.nu + p;
+  double lh = 0.0, term = 0.0;
+  if (active) {
+    lh = -0.5 * a * log1p(q / M.nu);
+    if (lane < d) {
+      double sv = 0.0;
+      for (int k = 0; k < p; ++k)
+        if (ssite[k] == lane) sv += sRr[w * 64 + k];
+      const double v = a / (M.nu + q) * sv;
+      if (rev)
+        term = lin_rev_point(A, base + lane, xt[lane], v, 0.0);
+      else
+        lin_fwd_point(A, base + lane, xt[lane], v, 0.0);
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) term += __shfl_xor(term, o);
+  if (lane == 0) {
+    red[w] = lh;
+    red[MVT_WAVES + w] = term;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double sl = 0.0, st = 0.0;
+    for (int k = 0; k < MVT_WAVES; ++k) {
+      sl += red[k];
+      st += red[MVT_WAVES + k];
+    }
+    if (rev) {
+      A.part_lh_xs[item] = sl;
+      A.part_terms[item] = st;
+    } else {
+      A.part_lh_x[item] = sl;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(64 * MVT_WAVES) k_lin_mvt(KModel M, StepArgs A, int rev) {
+  lin_mvt_body(M, A, rev, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1243,8 +1333,9 @@ __device__ double block_sum(const double* a, int n, double* red) {
 __device__ __forceinline__ void mh_finalize_body(const KModel& M, const StepArgs& A,
                                                  const FinalArgs& F) {
   __shared__ double red[4];
-  const double lzf = block_sum(A.ell, M.N, red);
-  const double lzr = block_sum(A.ell2, M.N, red);
+  const int n_ell = F.n_ell > 0 ? F.n_ell : M.N;
+  const double lzf = block_sum(A.ell, n_ell, red);
+  const double lzr = block_sum(A.ell2, n_ell, red);
   const double terms = block_sum(A.part_terms, F.n_part_rev, red);
   const double lhx = block_sum(A.part_lh_x, F.n_part_fwd, red);
   const double lhs = block_sum(A.part_lh_xs, F.n_part_rev, red);
@@ -1489,11 +1580,16 @@ hipError_t set_lds_limits_all() {
 }
 
 hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStream_t st) {
+  timing_mark(FAM_LIN, 1, st);
   if (M.emit == EMIT_GAUSSIAN) {
     const int nblk = (M.N + 63) / 64;
     *n_part = nblk;
     if (!rev) hipLaunchKernelGGL(k_gauss_prep, dim3(1), dim3(64), 0, st, M, A);
     hipLaunchKernelGGL(k_lin_gauss, dim3(nblk), dim3(64), 0, st, M, A, rev);
+  } else if (M.emit == EMIT_MVT) {
+    const int nblk = (M.N + MVT_WAVES - 1) / MVT_WAVES;
+    *n_part = nblk;
+    hipLaunchKernelGGL(k_lin_mvt, dim3(nblk), dim3(64 * MVT_WAVES), 0, st, M, A, rev);
   } else {
     const int64_t n = (int64_t)M.N * M.d;
     const int nblk = (int)((n + 255) / 256);
@@ -1503,6 +1599,7 @@ hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStre
     else
       hipLaunchKernelGGL(k_lin_rev_diag, dim3(nblk), dim3(256), 0, st, M, A);
   }
+  timing_mark(FAM_LIN, 0, st);
   return hipGetLastError();
 }
 

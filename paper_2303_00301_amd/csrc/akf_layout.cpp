@@ -68,7 +68,9 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
   };
   const int nparts_diag = (int)(((int64_t)N * d + 255) / 256);
   const int nparts_gauss = (N + 63) / 64;
+  const int nparts_mvt = (N + kMvtWaves - 1) / kMvtWaves;
   Lo.n_part = nparts_diag > nparts_gauss ? nparts_diag : nparts_gauss;
+  if (nparts_mvt > Lo.n_part) Lo.n_part = nparts_mvt;
   if (kind == LAYOUT_STEP) {
     Lo.u = take(vn);
     Lo.om = take(vn);
@@ -86,6 +88,26 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
     Lo.gOmdinv = take((size_t)d * d * dbl);
     Lo.gscal = take(8 * dbl);
     Lo.accept = take(sizeof(int));
+  }
+  if (kind == LAYOUT_FACT) {
+    // the scan keeps no elements: only vectors [N*d] and per-coordinate sums
+    Lo.u = take(vn);
+    Lo.om = take(vn);
+    Lo.Om = take(vn);
+    Lo.om2 = take(vn);
+    Lo.Om2 = take(vn);
+    Lo.xs = take(vn);
+    Lo.mf = take(vn);
+    Lo.Pf = take(vn);
+    Lo.ell = take((size_t)d * dbl);
+    Lo.ell2 = take((size_t)d * dbl);
+    Lo.plhx = take((size_t)Lo.n_part * dbl);
+    Lo.plhxs = take((size_t)Lo.n_part * dbl);
+    Lo.pterms = take((size_t)Lo.n_part * dbl);
+    Lo.accept = take(sizeof(int));
+    Lo.status = take(sizeof(int));
+    Lo.total = off;
+    return;
   }
   if (kind == LAYOUT_LGSSM) {
     Lo.Qd = take((size_t)d * d * dbl);
@@ -152,9 +174,22 @@ akf_status check_model(const akf_model* m, bool need_emission) {
       if (!(m->nu > 0.0) || !(m->scale > 0.0))
         return fail(AKF_ERR_INVALID, "Student-t emission needs nu > 0 and scale > 0");
       break;
+    case AKF_EMIT_MVT:
+      if (!m->site || !m->R) return fail(AKF_ERR_INVALID, "multivariate-t emission needs site and R");
+      if (!(m->nu > 0.0)) return fail(AKF_ERR_INVALID, "multivariate-t emission needs nu > 0");
+      break;
     default:
       return fail(AKF_ERR_INVALID, "unknown emission family %d", m->emit);
   }
+  return AKF_OK;
+}
+
+akf_status check_order(const akf_model* m, int order) {
+  if (order != 1 && order != 2) return fail(AKF_ERR_INVALID, "order must be 1 or 2");
+  if (order == 2 && m->emit == AKF_EMIT_MVT)
+    return fail(AKF_ERR_UNSUPPORTED,
+                "the multivariate-t emission supports first-order proposals only (its Hessian "
+                "would make Omega_t dense and time-varying)");
   return AKF_OK;
 }
 

@@ -38,7 +38,7 @@ struct Layout {
 };
 
 enum LayoutKind { LAYOUT_STEP = 0, LAYOUT_FILTER = 1, LAYOUT_SAMPLER = 2, LAYOUT_SMOOTH = 3,
-                  LAYOUT_LGSSM = 4 };
+                  LAYOUT_LGSSM = 4, LAYOUT_FACT = 5 };
 
 
 template <class T>
@@ -51,6 +51,7 @@ int pick_D(int d);
 int auto_block(int N, int D);
 void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind);
 akf_status check_model(const akf_model* m, bool need_emission);
+akf_status check_order(const akf_model* m, int order);
 KModel to_kmodel(const akf_model* m);
 akf_status prepare_device();
 akf_status hip_check(hipError_t e, const char* what);

@@ -14,7 +14,7 @@ import torch
 
 from . import _lib
 
-EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL = 0, 1, 2, 3
+EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
 
@@ -93,6 +93,25 @@ class DeviceModel:
     def device(self) -> torch.device:
         return self.m0.device
 
+    @property
+    def is_diagonal_form(self) -> bool:
+        """True when P0, F and Q hold diagonals [dx] (the factorised entry points)."""
+        return self.F.dim() == 1
+
+    def diagonal(self) -> "DeviceModel":
+        """The model with P0, F and Q replaced by their diagonals, as the
+        factorised entry points take it.  Raises if any of them is not diagonal."""
+        out = {}
+        for k in ("P0", "F", "Q"):
+            a = getattr(self, k)
+            dg = torch.diagonal(a).contiguous()
+            if not torch.equal(a, torch.diag(dg)):
+                raise _lib.AkfError(f"{k} is not diagonal: the prior does not factorise")
+            out[k] = dg
+        return DeviceModel(N=self.N, m0=self.m0, P0=out["P0"], F=out["F"], Q=out["Q"],
+                           emit=self.emit, b=self.b, H=self.H, R=self.R, site=self.site,
+                           nu=self.nu, scale=self.scale)
+
     def cstruct(self) -> _lib.AkfModel:
         s = _lib.AkfModel()
         s.N, s.dx, s.dy = self.N, self.dx, self.dy
@@ -138,11 +157,29 @@ def _ws_for(device) -> Workspace:
     return _default_ws[key]
 
 
+def _need(nbytes: int, what: str) -> int:
+    """A workspace size from a *_workspace_bytes query; 0 means the request was
+    rejected, and the library's last error says why."""
+    if nbytes == 0:
+        msg = _lib.load().akf_last_error()
+        raise _lib.AkfError(f"{what} rejected the request: {msg.decode() if msg else ''}")
+    return nbytes
+
+
+def _check_form(model: DeviceModel, factorised: bool):
+    if factorised != model.is_diagonal_form:
+        raise _lib.AkfError("the factorised step takes P0, F and Q as diagonals "
+                            "(DeviceModel.diagonal()); the dense step takes matrices")
+
+
 def mh_step(model: DeviceModel, y, x, delta: float, order: int, xi, unif, x_out=None,
-            block: int = 0, ws: Optional[Workspace] = None) -> dict:
+            block: int = 0, ws: Optional[Workspace] = None, factorised: bool = False) -> dict:
     """One auxiliary Kalman MH step.  xi [2,N,dx], unif [1] (device tensors).
+    factorised=True runs the step for a prior that factorises over coordinates
+    (akf_mh_step_factorised; `model` from DeviceModel.diagonal(), block unused).
     Returns device tensors: x_out, log_ratio, accepted, logZ_fwd, logZ_rev, status."""
     lib = _lib.load()
+    _check_form(model, factorised)
     dev = model.device
     N, dx = model.N, model.dx
     _check_f64("y", y, (N, model.dy))
@@ -157,19 +194,31 @@ def mh_step(model: DeviceModel, y, x, delta: float, order: int, xi, unif, x_out=
     acc = torch.empty(1, dtype=torch.int32, device=dev)
     st = torch.empty(1, dtype=torch.int32, device=dev)
     ms = model.cstruct()
-    need = lib.akf_mh_workspace_bytes(C.byref(ms), order, block)
-    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
-    rc = lib.akf_mh_step(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), _ptr(xi),
-                         _ptr(unif), _ptr(x_out), _ptr(lr), _ptr(acc), _ptr(lzf), _ptr(lzr),
-                         _ptr(st), wsp, wsb, int(block), _stream(dev))
-    _lib.check(rc, "akf_mh_step")
+    if factorised:
+        need = _need(lib.akf_mh_factorised_workspace_bytes(C.byref(ms), order),
+                     "akf_mh_factorised_workspace_bytes")
+        wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+        rc = lib.akf_mh_step_factorised(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order),
+                                        _ptr(xi), _ptr(unif), _ptr(x_out), _ptr(lr), _ptr(acc),
+                                        _ptr(lzf), _ptr(lzr), _ptr(st), wsp, wsb, _stream(dev))
+        _lib.check(rc, "akf_mh_step_factorised")
+    else:
+        need = _need(lib.akf_mh_workspace_bytes(C.byref(ms), order, block),
+                     "akf_mh_workspace_bytes")
+        wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+        rc = lib.akf_mh_step(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), _ptr(xi),
+                             _ptr(unif), _ptr(x_out), _ptr(lr), _ptr(acc), _ptr(lzf), _ptr(lzr),
+                             _ptr(st), wsp, wsb, int(block), _stream(dev))
+        _lib.check(rc, "akf_mh_step")
     return dict(x_out=x_out, log_ratio=lr, accepted=acc, logZ_fwd=lzf, logZ_rev=lzr, status=st)
 
 
 def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: int = 0,
-           ws: Optional[Workspace] = None, outputs: bool = True) -> dict:
-    """n_steps MH steps, x updated in place.  xi [n_steps,2,N,dx], unif [n_steps]."""
+           ws: Optional[Workspace] = None, outputs: bool = True, factorised: bool = False) -> dict:
+    """n_steps MH steps, x updated in place.  xi [n_steps,2,N,dx], unif [n_steps].
+    factorised as in mh_step."""
     lib = _lib.load()
+    _check_form(model, factorised)
     dev = model.device
     N, dx = model.N, model.dx
     n = int(xi.shape[0])
@@ -185,13 +234,21 @@ def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: 
                    logZ_rev=torch.empty(n, dtype=torch.float64, device=dev),
                    status=torch.empty(n, dtype=torch.int32, device=dev))
     ms = model.cstruct()
-    need = lib.akf_mh_workspace_bytes(C.byref(ms), order, block)
-    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
-    rc = lib.akf_mh_run(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), n, _ptr(xi),
-                        _ptr(unif), _ptr(out.get("log_ratio")), _ptr(out.get("accepted")),
-                        _ptr(out.get("logZ_fwd")), _ptr(out.get("logZ_rev")),
-                        _ptr(out.get("status")), wsp, wsb, int(block), _stream(dev))
-    _lib.check(rc, "akf_mh_run")
+    outs = [_ptr(out.get(k)) for k in ("log_ratio", "accepted", "logZ_fwd", "logZ_rev", "status")]
+    if factorised:
+        need = _need(lib.akf_mh_factorised_workspace_bytes(C.byref(ms), order),
+                     "akf_mh_factorised_workspace_bytes")
+        wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+        rc = lib.akf_mh_run_factorised(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), n,
+                                       _ptr(xi), _ptr(unif), *outs, wsp, wsb, _stream(dev))
+        _lib.check(rc, "akf_mh_run_factorised")
+    else:
+        need = _need(lib.akf_mh_workspace_bytes(C.byref(ms), order, block),
+                     "akf_mh_workspace_bytes")
+        wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+        rc = lib.akf_mh_run(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), n, _ptr(xi),
+                            _ptr(unif), *outs, wsp, wsb, int(block), _stream(dev))
+        _lib.check(rc, "akf_mh_run")
     out["x"] = x
     return out
 

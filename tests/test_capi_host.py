@@ -92,3 +92,44 @@ def test_student_t_needs_positive_parameters():
     rc = lib.akf_mh_step(C.byref(m), p, p, 0.5, 2, p, p, p, None, None, None, None, None,
                          C.c_void_p(0x10000), 1 << 30, 0, None)
     assert rc == 1
+
+
+def test_multivariate_t_order_and_parameters():
+    lib = _lib.load()
+    p = C.c_void_p(0x2000)
+    m = _fake_model(emit=4)
+    # order 2 would need a dense time-varying Omega_t: rejected on both paths
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) == 0
+    assert b"first-order" in lib.akf_last_error()
+    assert lib.akf_mh_factorised_workspace_bytes(C.byref(m), 2) == 0
+    rc = lib.akf_mh_step(C.byref(m), p, p, 0.5, 2, p, p, p, None, None, None, None, None,
+                         C.c_void_p(0x10000), 1 << 30, 0, None)
+    assert rc == 5
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 1, 0) > 0
+    m.nu = 0.0
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 1, 0) == 0
+    m = _fake_model(emit=4)
+    m.R = None
+    assert lib.akf_mh_factorised_workspace_bytes(C.byref(m), 1) == 0
+
+
+def test_factorised_entry_points_reject_bad_requests():
+    lib = _lib.load()
+    p = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x10000)
+    g = _fake_model(emit=0)
+    assert lib.akf_mh_factorised_workspace_bytes(C.byref(g), 1) == 0
+    assert b"Gaussian" in lib.akf_last_error()
+    m = _fake_model(N=1024, dx=64, dy=64, emit=4)
+    need = lib.akf_mh_factorised_workspace_bytes(C.byref(m), 1)
+    # vectors only: far below the dense step's element storage
+    assert 0 < need < lib.akf_mh_workspace_bytes(C.byref(m), 1, 0) // 4
+    call = lambda **kw: lib.akf_mh_step_factorised(
+        C.byref(m), kw.get("y", p), p, kw.get("delta", 0.5), kw.get("order", 1), p, p, p, None,
+        None, None, None, None, kw.get("ws", ws), kw.get("ws_bytes", 1 << 30), None)
+    assert call(delta=-1.0) == 1
+    assert call(order=0) == 1
+    assert call(y=None) == 1
+    assert call(ws_bytes=need - 1) == 3
+    assert lib.akf_mh_run_factorised(C.byref(m), p, p, 0.5, 1, -1, p, p, None, None, None, None,
+                                     None, ws, 1 << 30, None) == 1

@@ -115,9 +115,11 @@ def test_rts_sample_matches_oracle(S, N, d, block):
     assert err.max() < MEAN_TOL
 
 
-def _compare_step(S, M_or, M_dev, y, x, delta, order, xi, un, block=0):
-    r = oracle.mh_step(M_or, y, x, delta, order, xi[0], xi[1], un)
-    out = S.mh_step(M_dev, T(y), T(x), delta, order, T(xi), T([un]), block=block)
+def _compare_step(S, M_or, M_dev, y, x, delta, order, xi, un, block=0, factorised=False):
+    step = oracle.mh_step_factorised if factorised else oracle.mh_step
+    r = step(M_or, y, x, delta, order, xi[0], xi[1], un)
+    out = S.mh_step(M_dev, T(y), T(x), delta, order, T(xi), T([un]), block=block,
+                    factorised=factorised)
     torch.cuda.synchronize()
     st = int(N_(out["status"])[0])
     assert st == r["status"], (st, r["status"])

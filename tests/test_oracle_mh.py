@@ -1,7 +1,8 @@
 """Pins for the oracle's emission linearisation and MH step (CPU only).
 
 * v_t, Lambda_t vs central finite differences of log h_t (every family);
-* the stochastic-volatility log h_t vs scipy's normal log-density;
+* the stochastic-volatility log h_t vs scipy's normal log-density, the
+  multivariate-t log h_t vs scipy's multivariate-t log-density;
 * the linearised potential plus the auxiliary Gaussian equals the pseudo-
   observation Gaussian up to a constant in z (eq. gaussian-FK-proposal,
   eq. second-order), and order 2 is exact for Gaussian emissions;
@@ -11,7 +12,10 @@
 * acceptance exactly 1 for linear-Gaussian emissions under order 2 (the
   linear-Gaussian tiny workload, 100 steps);
 * a long oracle chain on N = 2, d = 1 non-Gaussian models reproduces the
-  posterior mean and second moment computed by 2-D quadrature.
+  posterior mean and second moment computed by 2-D quadrature;
+* the factorised step (dx one-dimensional filters and samplers) equals the
+  dense step on models whose prior and Omega_t are diagonal, and refuses the
+  models that do not factorise.
 """
 import numpy as np
 import pytest
@@ -35,6 +39,11 @@ def _model(emit, dx, rng, dy=None):
     elif emit in (oracle.EMIT_POISSON_LOG, oracle.EMIT_STOCH_VOL):
         dy = dy or dx
         kw.update(site=rng.integers(0, dx, size=dy).astype(np.int32))
+    elif emit == oracle.EMIT_MVT:
+        dy = dy or dx
+        C = rng.standard_normal((dy, dy))
+        kw.update(site=rng.integers(0, dx, size=dy).astype(np.int32), nu=2.5,
+                  R=C @ C.T / dy + 0.5 * np.eye(dy))
     else:
         dy = dy or dx
         kw.update(site=rng.integers(0, dx, size=dy).astype(np.int32), nu=3.0, scale=0.5)
@@ -47,7 +56,7 @@ def _y(M, dy, N, rng):
     return rng.standard_normal((N, dy))
 
 
-@pytest.mark.parametrize("emit", [0, 1, 2, 3])
+@pytest.mark.parametrize("emit", [0, 1, 2, 3, 4])
 def test_emission_gradient_hessian_fd(emit):
     rng = np.random.default_rng(10 + emit)
     for dx in (1, 3, 5):
@@ -78,8 +87,41 @@ def test_stoch_vol_log_h_is_normal_log_density():
             assert abs(lh - ref) < 1e-10 * max(1.0, abs(ref))
 
 
+def test_mvt_log_h_is_multivariate_t_log_density():
+    """Multivariate t with precision R: log h(y | x) equals scipy's multivariate-t
+    log-density of y - x[site] (shape R^-1, nu degrees of freedom) plus the
+    dropped constant -log G((nu + p)/2) + log G(nu/2) + (p/2) log(nu pi) - (1/2) logdet R."""
+    from scipy.special import gammaln
+    from scipy.stats import multivariate_t
+    rng = np.random.default_rng(78)
+    for dx, dy in ((1, 1), (4, 6), (16, 16)):
+        M, _ = _model(oracle.EMIT_MVT, dx, rng, dy=dy)
+        const = (-gammaln(0.5 * (M.nu + dy)) + gammaln(0.5 * M.nu) + 0.5 * dy * np.log(M.nu * np.pi)
+                 - 0.5 * np.linalg.slogdet(M.R)[1])
+        for _ in range(3):
+            yt = 2.0 * rng.standard_normal(dy)
+            xt = 1.5 * rng.standard_normal(dx)
+            lh = oracle.emission(M, yt, xt)[0]
+            ref = multivariate_t(loc=xt[M.site], shape=np.linalg.inv(M.R), df=M.nu).logpdf(yt)
+            assert abs(lh - (ref + const)) < 1e-10 * max(1.0, abs(ref))
+
+
+def test_lattice_precision():
+    """tau^D for Manhattan distance D <= 1 on the 8 x 8 lattice: unit diagonal,
+    tau for the 2-4 lattice neighbours, zero elsewhere, symmetric positive definite."""
+    R = W.lattice_precision(8, -0.25, 1)
+    assert np.array_equal(np.diag(R), np.ones(64))
+    off = R - np.eye(64)
+    assert np.array_equal(R, R.T)
+    nnz = (off != 0).sum(1)
+    assert nnz.min() == 2 and nnz.max() == 4 and nnz.sum() == 2 * 2 * 8 * 7
+    assert set(np.unique(off)) == {0.0, -0.25}
+    assert R[0, 1] == -0.25 and R[0, 8] == -0.25 and R[0, 9] == 0.0 and R[7, 8] == 0.0
+    assert np.linalg.eigvalsh(R).min() > 0.0
+
+
 @pytest.mark.parametrize("emit,order", [(0, 1), (0, 2), (1, 1), (1, 2), (2, 1), (2, 2), (3, 1),
-                                        (3, 2)])
+                                        (3, 2), (4, 1), (4, 2)])
 def test_linearised_proposal_is_pseudo_observation_gaussian(emit, order):
     """vᵀ(z-x) + ½(z-x)ᵀΛ(z-x) + log N(u; z, δ/2 I) - log N(ω; z, Ω) is constant in z."""
     rng = np.random.default_rng(20 + emit)
@@ -147,7 +189,7 @@ def _brute_log_ratio(M, y, x, xs, u, delta, order):
 
 @pytest.mark.parametrize("emit,order,N,dx", [(0, 1, 4, 2), (0, 2, 3, 2), (1, 1, 5, 1), (1, 2, 4, 2),
                                              (2, 1, 3, 3), (2, 2, 5, 2), (3, 1, 4, 2),
-                                             (3, 2, 3, 3)])
+                                             (3, 2, 3, 3), (4, 1, 3, 3), (4, 2, 4, 2)])
 def test_log_ratio_vs_dense_brute_force(emit, order, N, dx):
     rng = np.random.default_rng(40 + 3 * emit + order)
     M, dy = _model(emit, dx, rng)
@@ -217,6 +259,8 @@ def _quadrature_posterior(M, y, lim=8.0, n=801):
         elif M.emit == oracle.EMIT_STOCH_VOL:
             from scipy.stats import norm
             lp = lp + norm.logpdf(y[t, 0], 0.0, np.exp(0.5 * X))
+        elif M.emit == oracle.EMIT_MVT:
+            lp = lp - 0.5 * (M.nu + 1) * np.log1p((y[t, 0] - X) ** 2 * M.R[0, 0] / M.nu)
         else:
             a = M.nu * M.scale ** 2
             lp = lp - 0.5 * (M.nu + 1) * np.log1p((y[t, 0] - X) ** 2 / a)
@@ -225,11 +269,14 @@ def _quadrature_posterior(M, y, lim=8.0, n=801):
     return np.array([(w * X0).sum(), (w * X1).sum(), (w * X0 ** 2).sum(), (w * X1 ** 2).sum()])
 
 
-@pytest.mark.parametrize("emit,order,delta", [(1, 2, 1.5), (2, 2, 2.0), (2, 1, 1.0), (3, 2, 1.5)])
-def test_long_chain_matches_quadrature(emit, order, delta):
+@pytest.mark.parametrize("emit,order,delta,factorised", [(1, 2, 1.5, False), (2, 2, 2.0, False),
+                                                       (2, 1, 1.0, False), (3, 2, 1.5, False),
+                                                       (4, 1, 1.0, True), (1, 2, 1.5, True)])
+def test_long_chain_matches_quadrature(emit, order, delta, factorised):
     """N = 2, d = 1: a 4e5-step chain must reproduce the posterior moments of
     (x_0, x_1) within 5 batch-means standard errors; a wrong Hastings ratio
-    biases the chain's stationary law."""
+    biases the chain's stationary law.  The factorised chains run the
+    one-dimensional filter/sampler step."""
     kw = dict(m0=np.array([0.2]), P0=np.array([[1.0]]), F=np.array([[0.6]]),
               Q=np.array([[0.5]]), emit=emit, b=np.array([0.1]), site=np.array([0], np.int32))
     if emit == oracle.EMIT_STUDENT_T:
@@ -237,6 +284,9 @@ def test_long_chain_matches_quadrature(emit, order, delta):
         y = np.array([[2.5], [-1.0]])
     elif emit == oracle.EMIT_STOCH_VOL:
         y = np.array([[2.0], [0.3]])
+    elif emit == oracle.EMIT_MVT:
+        kw.update(nu=1.0, R=np.array([[2.0]]))
+        y = np.array([[2.5], [-1.0]])
     else:
         y = np.array([[4.0], [0.0]])
     M = oracle.Model(**kw)
@@ -245,7 +295,7 @@ def test_long_chain_matches_quadrature(emit, order, delta):
     rng = np.random.default_rng(1234 + emit + order)
     xi = rng.standard_normal((n, 2, 2, 1))
     un = rng.random(n)
-    r = oracle.mh_chain(M, y, np.zeros((2, 1)), delta, order, xi, un)
+    r = oracle.mh_chain(M, y, np.zeros((2, 1)), delta, order, xi, un, factorised=factorised)
     s = r["samples"][:, :, 0]
     acc = r["accepted"].mean()
     assert 0.1 < acc < 0.99
@@ -255,3 +305,48 @@ def test_long_chain_matches_quadrature(emit, order, delta):
     se = bm.std(0, ddof=1) / np.sqrt(nb)
     z = (f.mean(0) - ref) / se
     assert np.abs(z).max() < 5.0, (z, f.mean(0), ref)
+
+
+def _diagonal_model(emit, dx, rng, dy=None):
+    M, dy = _model(emit, dx, rng, dy=dy)
+    M.F = np.diag(rng.uniform(0.5, 1.0, dx))
+    M.Q = np.diag(rng.uniform(0.2, 1.0, dx))
+    M.P0 = np.diag(rng.uniform(0.5, 1.5, dx))
+    return M, dy
+
+
+@pytest.mark.parametrize("emit,order", [(1, 1), (1, 2), (2, 1), (2, 2), (3, 1), (3, 2), (4, 1)])
+def test_factorised_step_equals_dense_step(emit, order):
+    """Diagonal P0, F, Q and diagonal Omega_t: dx one-dimensional filters and
+    samplers give the dense step's x*, log Z and log r (three chained steps)."""
+    rng = np.random.default_rng(60 + 2 * emit + order)
+    dx, N, delta = 5, 7, 0.3
+    M, dy = _diagonal_model(emit, dx, rng, dy=6)
+    y = _y(M, dy, N, rng)
+    x = 0.3 * rng.standard_normal((N, dx))
+    for k in range(3):
+        xi_u, xi_x = rng.standard_normal((2, N, dx))
+        un = rng.random()
+        a = oracle.mh_step(M, y, x, delta, order, xi_u, xi_x, un)
+        b = oracle.mh_step_factorised(M, y, x, delta, order, xi_u, xi_x, un)
+        assert a["status"] == 0 and b["status"] == 0
+        np.testing.assert_allclose(b["xstar"], a["xstar"], rtol=0, atol=1e-12)
+        for key in ("log_ratio", "logZ_fwd", "logZ_rev"):
+            assert abs(a[key] - b[key]) < 1e-10 * max(1.0, abs(a[key])), key
+        assert a["accepted"] == b["accepted"]
+        x = a["x_out"]
+
+
+def test_factorised_step_refuses_coupled_models():
+    rng = np.random.default_rng(66)
+    N, dx, delta = 4, 3, 0.3
+    M, dy = _diagonal_model(oracle.EMIT_MVT, dx, rng)
+    y = _y(M, dy, N, rng)
+    x = 0.3 * rng.standard_normal((N, dx))
+    xi_u, xi_x = rng.standard_normal((2, N, dx))
+    # order 2: the multivariate-t Hessian couples the coordinates
+    assert oracle.mh_step_factorised(M, y, x, delta, 2, xi_u, xi_x, 0.5)["status"] == -1
+    M2, _ = _diagonal_model(oracle.EMIT_POISSON_LOG, dx, rng)
+    M2.F[0, 1] = 0.1
+    assert oracle.mh_step_factorised(M2, _y(M2, dx, N, rng), x, delta, 1, xi_u, xi_x,
+                                     0.5)["status"] == -1
