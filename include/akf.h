@@ -53,10 +53,22 @@ typedef enum {
   AKF_EMIT_POISSON_LOG = 1, /* y_{t,k} ~ Poisson(exp(x_{t,site[k]})) */
   AKF_EMIT_STUDENT_T = 2,   /* y_{t,k} = x_{t,site[k]} + scale * t_nu */
   AKF_EMIT_STOCH_VOL = 3,   /* y_{t,k} ~ N(0, exp(x_{t,site[k]})) (stochastic volatility) */
-  AKF_EMIT_MVT = 4          /* y_t = x_t[site] + V_t, V_t multivariate t with nu degrees of
+  AKF_EMIT_MVT = 4,         /* y_t = x_t[site] + V_t, V_t multivariate t with nu degrees of
                                freedom and precision R [dy,dy] (Sec. "Spatio-temporal model");
                                first-order proposals only */
+  AKF_EMIT_GAUSS_SITE = 5   /* y_{t,k} = x_{t,site[k]} + N(0, scale^2) */
 } akf_emit;
+
+/* Dynamics families: x_t = F x_{t-1} + b + N(0, Q), or x_t = f(x_{t-1}) + N(0, Q)
+ * with f one Euler-Maruyama step of an SDE dx = beta(x) dt + noise. */
+typedef enum {
+  AKF_DYN_LINEAR = 0,    /* F, b */
+  AKF_DYN_LORENZ63 = 1,  /* dx = 3; beta = (p0 (x1 - x0), p1 x0 - x1 - x0 x2, x0 x1 - p2 x2),
+                            dt = p3 (Sec. "Parameter estimation in a continuous-discrete
+                            diffusion smoothing problem") */
+  AKF_DYN_LORENZ96 = 2   /* dx >= 4; beta_i = (x_{i+1} - x_{i-2}) x_{i-1} - x_i + p0 (cyclic),
+                            dt = p1 */
+} akf_dyn;
 
 /* Per-step device status bits. */
 enum {
@@ -71,12 +83,22 @@ enum {
 /*
  * Model description (eq. ssm with Gaussian dynamics).  m0 [dx], P0 [dx,dx],
  * F [dx,dx], b [dx] or NULL (zero), Q [dx,dx].  Emission per `emit`:
- * GAUSSIAN uses H, R; POISSON_LOG, STUDENT_T, STOCH_VOL and MVT use site [dy]
- * (int32, each in [0, dx); several sites may observe the same coordinate);
- * STUDENT_T also nu > 0 and scale > 0; MVT also the precision R [dy,dy]
- * (symmetric positive definite) and nu > 0.  All pointers are device pointers.
+ * GAUSSIAN uses H, R; POISSON_LOG, STUDENT_T, STOCH_VOL, MVT and GAUSS_SITE use
+ * site [dy] (int32, each in [0, dx); several sites may observe the same
+ * coordinate); STUDENT_T also nu > 0 and scale > 0; GAUSS_SITE scale > 0; MVT
+ * also the precision R [dy,dy] (symmetric positive definite) and nu > 0.  In
+ * the site-wise families (POISSON_LOG, STUDENT_T, STOCH_VOL, GAUSS_SITE) a NaN
+ * y_{t,k} marks an unobserved site.  All pointers are device pointers.
  * MVT with order 2 is rejected with AKF_ERR_UNSUPPORTED (its Hessian would
  * make Omega_t dense and time-varying).
+ *
+ * dyn selects the dynamics (akf_dyn; zero-initialise the struct for linear
+ * dynamics).  With a nonlinear family F and b are ignored (may be NULL), Q is
+ * the per-step noise covariance and dyn_par holds the family's parameters;
+ * each step linearises f around the current path (x for the forward proposal,
+ * x* for the reverse one; Example "gslr-example") and adds the mismatch
+ * between the true and the linearised transition densities to log r.
+ * Nonlinear dynamics are accepted by akf_mh_step / akf_mh_run only.
  */
 typedef struct akf_model {
   int32_t N, dx, dy;
@@ -85,6 +107,8 @@ typedef struct akf_model {
   const double *H, *R;
   const int32_t* site;
   double nu, scale;
+  int32_t dyn;
+  double dyn_par[4];
 } akf_model;
 
 /* Description of the last synchronous error on this thread (static storage). */

@@ -27,6 +27,8 @@ _SRC = os.path.join(_HERE, "akf_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
+EMIT_GAUSS_SITE = 5
+DYN_LINEAR, DYN_LORENZ63, DYN_LORENZ96 = 0, 1, 2
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
 
@@ -62,21 +64,26 @@ class _Model(C.Structure):
         ("H", _dp), ("R", _dp),
         ("site", _ip),
         ("nu", C.c_double), ("scale", C.c_double),
+        ("dyn", C.c_int), ("dyn_par", C.c_double * 4),
     ]
 
 
 def _declare(L):
     L.or_kf.restype = C.c_int
-    L.or_kf.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, C.c_long, _dp,
-                        C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_kf.argtypes = [C.c_int, C.c_int, C.c_int, _dp, _dp, _dp, C.c_long, _dp, C.c_long, _dp,
+                        _dp, C.c_long, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_rts_sample.restype = C.c_int
-    L.or_rts_sample.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_rts_sample.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_rts_smooth.restype = C.c_int
-    L.or_rts_smooth.argtypes = [C.c_int, C.c_int, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_rts_smooth.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_emission.restype = C.c_double
     L.or_emission.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, _dp]
     L.or_linearise.restype = C.c_int
     L.or_linearise.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp, _dp]
+    L.or_dyn.restype = None
+    L.or_dyn.argtypes = [C.POINTER(_Model), _dp, _dp, _dp]
+    L.or_dyn_linearise.restype = None
+    L.or_dyn_linearise.argtypes = [C.POINTER(_Model), _dp, _dp, _dp]
     L.or_mh_step.restype = C.c_int
     L.or_mh_step.argtypes = [C.POINTER(_Model), _dp, _dp, C.c_double, C.c_int, _dp, _dp, C.c_double,
                              _dp, _dp, _ip, _dp, _dp, _dp, _dp]
@@ -112,8 +119,10 @@ class Model:
     """State-space model: p0 = N(m0,P0), p_t = N(F x + b, Q), emission h_t.
 
     emit: EMIT_GAUSSIAN (H [dy,dx], R [dy,dy]); EMIT_POISSON_LOG,
-    EMIT_STUDENT_T or EMIT_STOCH_VOL (site [dy]: y_k observes x[site[k]]; nu,
-    scale for Student-t); EMIT_MVT (site [dy], precision R [dy,dy], nu).
+    EMIT_STUDENT_T, EMIT_STOCH_VOL or EMIT_GAUSS_SITE (site [dy]: y_k observes
+    x[site[k]]; nu, scale for Student-t; scale for Gaussian at sites; NaN = not
+    observed); EMIT_MVT (site [dy], precision R [dy,dy], nu).  dyn != DYN_LINEAR
+    replaces F, b by x_t = f(x_{t-1}) + N(0, Q) with parameters dyn_par.
     """
     m0: np.ndarray
     P0: np.ndarray
@@ -126,6 +135,8 @@ class Model:
     site: Optional[np.ndarray] = None
     nu: float = 0.0
     scale: float = 0.0
+    dyn: int = DYN_LINEAR
+    dyn_par: tuple = (0.0, 0.0, 0.0, 0.0)
 
     @property
     def dx(self) -> int:
@@ -161,6 +172,10 @@ class _Bound:
         else:
             s.site = C.cast(None, _ip)
         s.nu, s.scale = float(M.nu), float(M.scale)
+        s.dyn = int(M.dyn)
+        par = list(M.dyn_par) + [0.0] * (4 - len(M.dyn_par))
+        for i in range(4):
+            s.dyn_par[i] = float(par[i])
         self.s = s
 
     def ref(self):
@@ -168,15 +183,17 @@ class _Bound:
 
 
 def kf(m0, P0, F, Q, H, R, y, b=None, H_per_t=False, R_per_t=False):
-    """Kalman filter.  Returns dict with mf, Pf, mp, Pp, ell, logZ, rc."""
+    """Kalman filter.  Returns dict with mf, Pf, mp, Pp, ell, logZ, rc.
+    F [N,dx,dx] and b [N,dx] (entry t = transition into step t) are per-step."""
     y = _f64(y)
     N, dy = y.shape
     dx = len(m0)
-    H, R = _f64(H), _f64(R)
+    H, R, F = _f64(H), _f64(R), _f64(F)
     out = {k: np.zeros(s) for k, s in (("mf", (N, dx)), ("Pf", (N, dx, dx)), ("mp", (N, dx)),
                                        ("Pp", (N, dx, dx)), ("ell", (N,)))}
     bb = None if b is None else _f64(b)
-    rc = lib().or_kf(N, dx, dy, _p(_f64(m0)), _p(_f64(P0)), _p(_f64(F)), _p(bb), _p(_f64(Q)), _p(H),
+    rc = lib().or_kf(N, dx, dy, _p(_f64(m0)), _p(_f64(P0)), _p(F), dx * dx if F.ndim == 3 else 0,
+                     _p(bb), dx if (bb is not None and bb.ndim == 2) else 0, _p(_f64(Q)), _p(H),
                      dy * dx if H_per_t else 0, _p(R), dy * dy if R_per_t else 0, _p(y),
                      _p(out["mf"]), _p(out["Pf"]), _p(out["mp"]), _p(out["Pp"]), _p(out["ell"]))
     out["rc"] = rc
@@ -185,20 +202,24 @@ def kf(m0, P0, F, Q, H, R, y, b=None, H_per_t=False, R_per_t=False):
 
 
 def rts_sample(F, mf, Pf, mp, Pp, xi):
-    mf, Pf, mp, Pp, xi = map(_f64, (mf, Pf, mp, Pp, xi))
+    """RTS path sample; F [dx,dx] or per-step [N,dx,dx]."""
+    mf, Pf, mp, Pp, xi, F = map(_f64, (mf, Pf, mp, Pp, xi, F))
     N, dx = mf.shape
     x = np.zeros((N, dx))
-    rc = lib().or_rts_sample(N, dx, _p(_f64(F)), _p(mf), _p(Pf), _p(mp), _p(Pp), _p(xi), _p(x))
+    rc = lib().or_rts_sample(N, dx, _p(F), dx * dx if F.ndim == 3 else 0, _p(mf), _p(Pf), _p(mp),
+                             _p(Pp), _p(xi), _p(x))
     return x, rc
 
 
 def rts_smooth(F, mf, Pf, mp, Pp):
-    mf, Pf, mp, Pp = map(_f64, (mf, Pf, mp, Pp))
+    """RTS smoothing moments and gains; F [dx,dx] or per-step [N,dx,dx]."""
+    mf, Pf, mp, Pp, F = map(_f64, (mf, Pf, mp, Pp, F))
     N, dx = mf.shape
     ms = np.zeros((N, dx))
     Ps = np.zeros((N, dx, dx))
     G = np.zeros((N, dx, dx))
-    rc = lib().or_rts_smooth(N, dx, _p(_f64(F)), _p(mf), _p(Pf), _p(mp), _p(Pp), _p(ms), _p(Ps), _p(G))
+    rc = lib().or_rts_smooth(N, dx, _p(F), dx * dx if F.ndim == 3 else 0, _p(mf), _p(Pf), _p(mp),
+                             _p(Pp), _p(ms), _p(Ps), _p(G))
     return ms, Ps, G, rc
 
 
@@ -210,6 +231,27 @@ def emission(M: Model, yt, xt):
     Lam = np.zeros((M.dx, M.dx))
     lh = lib().or_emission(B.ref(), _p(yt), _p(xt), _p(v), _p(Lam))
     return lh, v, Lam
+
+
+def dyn(M: Model, x):
+    """f(x) and its Jacobian for the model's nonlinear dynamics family."""
+    x = _f64(x)
+    B = _Bound(M, 1)
+    f = np.zeros(M.dx)
+    J = np.zeros((M.dx, M.dx))
+    lib().or_dyn(B.ref(), _p(x), _p(f), _p(J))
+    return f, J
+
+
+def dyn_linearise(M: Model, a):
+    """Per-step (F_t, b_t) of the extended linearisation around the path a."""
+    a = _f64(a)
+    N = a.shape[0]
+    B = _Bound(M, N)
+    F = np.zeros((N, M.dx, M.dx))
+    b = np.zeros((N, M.dx))
+    lib().or_dyn_linearise(B.ref(), _p(a), _p(F), _p(b))
+    return F, b
 
 
 def linearise(M: Model, y, x, u, delta, order):

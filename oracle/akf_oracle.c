@@ -18,8 +18,10 @@
  *                    Fisher-identity score and moment checks.
  *   or_emission      log h_t, its gradient v_t and Hessian Lambda_t for the
  *                    Gaussian / Poisson-log / Student-t / stochastic-volatility /
- *                    multivariate-t families (Sec. 2.2, eq.
+ *                    multivariate-t / Gaussian-at-sites families (Sec. 2.2, eq.
  *                    linearised-log-potential-second).
+ *   or_dyn, or_dyn_linearise  Euler steps of the Lorenz-63 / Lorenz-96 SDEs and
+ *                    their extended linearisation (Example "gslr-example").
  *   or_linearise     pseudo-observations (omega_t, Omega_t) of the auxiliary
  *                    LGSSM: first order (eq. gaussian-FK-proposal) or second
  *                    order (eq. second-order), with Sigma_t = I.
@@ -160,9 +162,10 @@ static double gauss_logpdf_chol(int n, const double* x, const double* mu, const 
 /* ------------------------------------------------------------------ */
 
 /*
- * Kalman filter for  x_0 ~ N(m0,P0),  x_t = F x_{t-1} + b + N(0,Q),
+ * Kalman filter for  x_0 ~ N(m0,P0),  x_t = F_t x_{t-1} + b_t + N(0,Q),
  * y_t = H_t x_t + N(0, R_t),  t = 0..N-1.
- * H_t = H + t*H_stride, R_t = R + t*R_stride (stride 0: time-invariant).
+ * F_t = F + t*F_stride, b_t = b + t*b_stride, H_t = H + t*H_stride,
+ * R_t = R + t*R_stride (stride 0: time-invariant; F_0, b_0 are not used).
  * The likelihood uses the predictive moments, log p(y_t | y_{0:t-1}) =
  * log N(y_t; H m^p_t, H P^p_t H^T + R_t) (the printed filtered-moment form is a
  * typo; the algorithm's update line uses the predictive one).
@@ -170,9 +173,9 @@ static double gauss_logpdf_chol(int n, const double* x, const double* mu, const 
  * Returns 0, or 1 + t when S_t was not positive definite at step t.
  */
 int or_kf(int N, int dx, int dy, const double* m0, const double* P0, const double* F,
-          const double* b, const double* Q, const double* H, long H_stride, const double* R,
-          long R_stride, const double* y, double* mf, double* Pf, double* mp, double* Pp,
-          double* ell) {
+          long F_stride, const double* b, long b_stride, const double* Q, const double* H,
+          long H_stride, const double* R, long R_stride, const double* y, double* mf, double* Pf,
+          double* mp, double* Pp, double* ell) {
   const int n = dx, p = dy;
   double* m_p = malloc(sizeof(double) * n);
   double* P_p = malloc(sizeof(double) * n * n);
@@ -194,11 +197,12 @@ int or_kf(int N, int dx, int dy, const double* m0, const double* P0, const doubl
       memcpy(m_p, m0, sizeof(double) * n);
       memcpy(P_p, P0, sizeof(double) * n * n);
     } else {
-      mv(n, n, F, m_f, m_p);
+      const double* Ft = F + (long)t * F_stride;
+      mv(n, n, Ft, m_f, m_p);
       if (b)
-        for (int i = 0; i < n; ++i) m_p[i] += b[i];
-      mm(n, n, n, F, P_f, T);
-      mm_nt(n, n, n, T, F, P_p);
+        for (int i = 0; i < n; ++i) m_p[i] += b[(long)t * b_stride + i];
+      mm(n, n, n, Ft, P_f, T);
+      mm_nt(n, n, n, T, Ft, P_p);
       for (int i = 0; i < n * n; ++i) P_p[i] += Q[i];
       symmetrise(n, P_p);
     }
@@ -271,11 +275,13 @@ static int backward_gain(int n, const double* F, const double* Pf, const double*
 /*
  * RTS sampler with a fixed noise map (eq. backward): x_{N-1} = m^f + chol(P^f) xi,
  * x_t = m^f_t + G_t (x_{t+1} - m^p_{t+1}) + chol(Sigma_t) xi_t, chol = lower
- * Cholesky factor with positive diagonal.  Returns 0, or 1 + t on a non-PD
- * covariance at step t.
+ * Cholesky factor with positive diagonal; G_t uses F_{t+1} = F + (t+1)*F_stride,
+ * the transition into step t+1.  Returns 0, or 1 + t on a non-PD covariance at
+ * step t.
  */
-int or_rts_sample(int N, int dx, const double* F, const double* mf, const double* Pf,
-                  const double* mp, const double* Pp, const double* xi, double* x) {
+int or_rts_sample(int N, int dx, const double* F, long F_stride, const double* mf,
+                  const double* Pf, const double* mp, const double* Pp, const double* xi,
+                  double* x) {
   const int n = dx;
   double* G = malloc(sizeof(double) * n * n);
   double* Sig = malloc(sizeof(double) * n * n);
@@ -290,7 +296,8 @@ int or_rts_sample(int N, int dx, const double* F, const double* mf, const double
     for (int i = 0; i < n; ++i) x[t1 * n + i] = mf[t1 * n + i] + d[i];
   }
   for (long t = N - 2; t >= 0 && rc == 0; --t) {
-    if (backward_gain(n, F, Pf + t * n * n, Pp + (t + 1) * n * n, G, Sig, work) ||
+    if (backward_gain(n, F + (t + 1) * F_stride, Pf + t * n * n, Pp + (t + 1) * n * n, G, Sig,
+                      work) ||
         chol(n, Sig, L)) {
       rc = 1 + (int)t;
       break;
@@ -310,8 +317,9 @@ int or_rts_sample(int N, int dx, const double* F, const double* mf, const double
  * RTS smoother: smoothed means/covariances and the gains G_t (t < N-1;
  * G_{N-1} is set to zero).  Cov(x_{t+1}, x_t | y) = P^s_{t+1} G_t^T.
  */
-int or_rts_smooth(int N, int dx, const double* F, const double* mf, const double* Pf,
-                  const double* mp, const double* Pp, double* ms, double* Ps, double* Gout) {
+int or_rts_smooth(int N, int dx, const double* F, long F_stride, const double* mf,
+                  const double* Pf, const double* mp, const double* Pp, double* ms, double* Ps,
+                  double* Gout) {
   const int n = dx;
   double* G = malloc(sizeof(double) * n * n);
   double* Sig = malloc(sizeof(double) * n * n);
@@ -325,7 +333,8 @@ int or_rts_smooth(int N, int dx, const double* F, const double* mf, const double
   memcpy(Ps + t1 * n * n, Pf + t1 * n * n, sizeof(double) * n * n);
   if (Gout) memset(Gout + t1 * n * n, 0, sizeof(double) * n * n);
   for (long t = N - 2; t >= 0; --t) {
-    if (backward_gain(n, F, Pf + t * n * n, Pp + (t + 1) * n * n, G, Sig, work)) {
+    if (backward_gain(n, F + (t + 1) * F_stride, Pf + t * n * n, Pp + (t + 1) * n * n, G, Sig,
+                      work)) {
       rc = 1 + (int)t;
       break;
     }
@@ -348,7 +357,8 @@ int or_rts_smooth(int N, int dx, const double* F, const double* mf, const double
 /* ------------------------------------------------------------------ */
 
 enum { OR_EMIT_GAUSSIAN = 0, OR_EMIT_POISSON_LOG = 1, OR_EMIT_STUDENT_T = 2, OR_EMIT_STOCH_VOL = 3,
-       OR_EMIT_MVT = 4 };
+       OR_EMIT_MVT = 4, OR_EMIT_GAUSS_SITE = 5 };
+enum { OR_DYN_LINEAR = 0, OR_DYN_LORENZ63 = 1, OR_DYN_LORENZ96 = 2 };
 
 typedef struct {
   int N, dx, dy;
@@ -356,7 +366,9 @@ typedef struct {
   int emit;
   const double *H, *R;  /* Gaussian: [dy,dx], [dy,dy]; multivariate t: R = precision [dy,dy] */
   const int* site;      /* non-Gaussian families: y_k observes x[site[k]] */
-  double nu, scale;     /* Student-t (nu, scale); multivariate t (nu) */
+  double nu, scale;     /* Student-t (nu, scale); multivariate t (nu); Gaussian at sites (scale) */
+  int dyn;              /* OR_DYN_*: linear (F, b) or x_t = f(x_{t-1}) + N(0, Q) */
+  double dyn_par[4];    /* Lorenz-63: theta1, theta2, theta3, dt; Lorenz-96: forcing, dt */
 } or_model;
 
 /*
@@ -364,7 +376,10 @@ typedef struct {
  * together with v = grad_x log h and Lambda = Hessian (dense [dx,dx]).
  * Constants dropped: Gaussian -(dy log 2pi + logdet R)/2, Poisson -log y!,
  * Student-t log Gamma terms and -log s, multivariate t log Gamma terms,
- * -(dy/2) log(nu pi) and +(1/2) logdet R.  They cancel in the MH ratio.
+ * -(dy/2) log(nu pi) and +(1/2) logdet R, Gaussian at sites -(log 2pi)/2 - log s
+ * per site.  They cancel in the MH ratio.  In the site-wise families
+ * (Poisson, Student-t, stochastic volatility, Gaussian at sites) an entry
+ * y_{t,k} that is NaN is not observed and contributes nothing.
  * v and Lam may be NULL.  Returns log h (may be +-inf / nan on overflow).
  */
 double or_emission(const or_model* M, const double* yt, const double* xt, double* v, double* Lam) {
@@ -406,6 +421,7 @@ double or_emission(const or_model* M, const double* yt, const double* xt, double
     free(r); free(w); free(L); free(RiH); free(col);
   } else if (M->emit == OR_EMIT_POISSON_LOG) {
     for (int k = 0; k < p; ++k) {
+      if (isnan(yt[k])) continue;
       int i = M->site[k];
       double e = exp(xt[i]);
       lh += yt[k] * xt[i] - e;
@@ -444,15 +460,28 @@ double or_emission(const or_model* M, const double* yt, const double* xt, double
     /* y_k ~ N(0, exp(x_i)) (Sec. "Multivariate stochastic volatility model"):
        log h = -x_i/2 - y_k^2 exp(-x_i)/2 (the -log(2 pi)/2 constant dropped) */
     for (int k = 0; k < p; ++k) {
+      if (isnan(yt[k])) continue;
       int i = M->site[k];
       double q = yt[k] * yt[k] * exp(-xt[i]);
       lh += -0.5 * xt[i] - 0.5 * q;
       if (v) v[i] += -0.5 + 0.5 * q;
       if (Lam) Lam[i * n + i] -= 0.5 * q;
     }
+  } else if (M->emit == OR_EMIT_GAUSS_SITE) {
+    /* y_k = x_i + N(0, s^2): log h = -(y_k - x_i)^2 / (2 s^2) */
+    const double s2 = M->scale * M->scale;
+    for (int k = 0; k < p; ++k) {
+      if (isnan(yt[k])) continue;
+      int i = M->site[k];
+      double r = yt[k] - xt[i];
+      lh += -0.5 * r * r / s2;
+      if (v) v[i] += r / s2;
+      if (Lam) Lam[i * n + i] -= 1.0 / s2;
+    }
   } else {
     const double a = M->nu * M->scale * M->scale;
     for (int k = 0; k < p; ++k) {
+      if (isnan(yt[k])) continue;
       int i = M->site[k];
       double r = yt[k] - xt[i];
       double den = a + r * r;
@@ -462,6 +491,98 @@ double or_emission(const or_model* M, const double* yt, const double* xt, double
     }
   }
   return lh;
+}
+
+/* ------------------------------------------------------------------ */
+/* Nonlinear dynamics x_t = f(x_{t-1}) + N(0, Q)                        */
+/* ------------------------------------------------------------------ */
+
+/*
+ * One Euler-Maruyama step of an SDE dx = beta(x) dt + noise:
+ * f(x) = x + dt beta(x), J = df/dx = I + dt dbeta/dx (J may be NULL).
+ *   Lorenz-63 (Sec. "Parameter estimation in a continuous-discrete diffusion
+ *   smoothing problem"), d = 3: beta = (t1 (x1 - x0), t2 x0 - x1 - x0 x2,
+ *   x0 x1 - t3 x2);
+ *   Lorenz-96, d >= 4 (cyclic indices): beta_i = (x_{i+1} - x_{i-2}) x_{i-1} - x_i + forcing.
+ */
+void or_dyn(const or_model* M, const double* x, double* f, double* J) {
+  const int n = M->dx;
+  double* beta = malloc(sizeof(double) * n);
+  double* Jb = calloc((size_t)n * n, sizeof(double));
+  double dt;
+  if (M->dyn == OR_DYN_LORENZ63) {
+    const double t1 = M->dyn_par[0], t2 = M->dyn_par[1], t3 = M->dyn_par[2];
+    dt = M->dyn_par[3];
+    beta[0] = t1 * (x[1] - x[0]);
+    beta[1] = t2 * x[0] - x[1] - x[0] * x[2];
+    beta[2] = x[0] * x[1] - t3 * x[2];
+    Jb[0] = -t1; Jb[1] = t1; Jb[2] = 0.0;
+    Jb[3] = t2 - x[2]; Jb[4] = -1.0; Jb[5] = -x[0];
+    Jb[6] = x[1]; Jb[7] = x[0]; Jb[8] = -t3;
+  } else {
+    const double forcing = M->dyn_par[0];
+    dt = M->dyn_par[1];
+    for (int i = 0; i < n; ++i) {
+      const int ip = (i + 1) % n, im = (i + n - 1) % n, im2 = (i + n - 2) % n;
+      beta[i] = (x[ip] - x[im2]) * x[im] - x[i] + forcing;
+      Jb[i * n + ip] += x[im];
+      Jb[i * n + im2] -= x[im];
+      Jb[i * n + im] += x[ip] - x[im2];
+      Jb[i * n + i] -= 1.0;
+    }
+  }
+  for (int i = 0; i < n; ++i) f[i] = x[i] + dt * beta[i];
+  if (J)
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) J[i * n + j] = (i == j ? 1.0 : 0.0) + dt * Jb[i * n + j];
+  free(beta); free(Jb);
+}
+
+/*
+ * Extended linearisation of the dynamics around the path a (Example
+ * "gslr-example"): for t >= 1, F_t = J(a_{t-1}) and b_t = f(a_{t-1}) - F_t a_{t-1},
+ * so that N(z_t; F_t z_{t-1} + b_t, Q) approximates p_t(z_t | z_{t-1}).
+ * F [N,dx,dx], b [N,dx]; entries t = 0 are set to zero (unused).
+ */
+void or_dyn_linearise(const or_model* M, const double* a, double* F, double* b) {
+  const int n = M->dx;
+  double* f = malloc(sizeof(double) * n);
+  memset(F, 0, sizeof(double) * n * n);
+  memset(b, 0, sizeof(double) * n);
+  for (long t = 1; t < M->N; ++t) {
+    double* Ft = F + t * n * n;
+    or_dyn(M, a + (t - 1) * n, f, Ft);
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s += Ft[i * n + j] * a[(t - 1) * n + j];
+      b[t * n + i] = f[i] - s;
+    }
+  }
+  free(f);
+}
+
+/*
+ * sum_{t >= 1} [log N(z_t; f(z_{t-1}), Q) - log N(z_t; F_t z_{t-1} + b_t, Q)]:
+ * the true transition density of the path z against the linearised one in the
+ * proposal; the terms of p(z, u) / q(z | ...) that do not cancel once the
+ * dynamics are linearised.
+ */
+static double dyn_mismatch(const or_model* M, const double* z, const double* F, const double* b) {
+  const int n = M->dx;
+  double* L = malloc(sizeof(double) * n * n);
+  double* f = malloc(sizeof(double) * n);
+  double* g = malloc(sizeof(double) * n);
+  double* tmp = malloc(sizeof(double) * n);
+  double s = 0.0;
+  if (chol(n, M->Q, L)) s = NAN;
+  for (long t = 1; t < M->N && !isnan(s); ++t) {
+    or_dyn(M, z + (t - 1) * n, f, NULL);
+    mv(n, n, F + t * n * n, z + (t - 1) * n, g);
+    for (int i = 0; i < n; ++i) g[i] += b[t * n + i];
+    s += gauss_logpdf_chol(n, z + t * n, f, L, tmp) - gauss_logpdf_chol(n, z + t * n, g, L, tmp);
+  }
+  free(L); free(f); free(g); free(tmp);
+  return s;
 }
 
 /*
@@ -541,7 +662,10 @@ static double pseudo_obs_loglik(int N, int n, const double* omega, const double*
  *       + sum_t [log N(omega*_t; x_t, Omega*_t) - log N(omega_t; x*_t, Omega_t)]
  *       + log Z(x) - log Z(x*),
  * the prior p0 prod p_t cancelling between target and both proposals; Z(.) is
- * the auxiliary LGSSM marginal likelihood (eq. marginal-likelihood).  Accept iff
+ * the auxiliary LGSSM marginal likelihood (eq. marginal-likelihood).  With
+ * nonlinear dynamics the proposals use the extended linearisation of f around
+ * x and x* (Alg. "General Auxiliary Kalman sampler", eq. auxiliary-LGSSM) and
+ * log r gains dyn_mismatch(x*; at x) - dyn_mismatch(x; at x*).  Accept iff
  * log(unif) < log r.  x_out may alias x.  Diagnostics (may be NULL):
  * xstar [N,dx], ell_f [N] per-step log-likelihood terms of the forward filter.
  * Returns the status bitmask (0 = all well-defined).
@@ -574,27 +698,41 @@ int or_mh_step(const or_model* M, const double* y, const double* x, double delta
   for (size_t i = 0; i < vn; ++i) u[i] = x[i] + su * xi_u[i];
 
   double lh_x = 0.0, lh_s = 0.0;
+  /* dynamics of the auxiliary LGSSM: the model's (F, b), or the extended
+     linearisation of f around x (forward) and x* (reverse) */
+  const int nl = M->dyn != OR_DYN_LINEAR;
+  double* Fx = nl ? malloc(sizeof(double) * mn) : NULL;
+  double* bx = nl ? malloc(sizeof(double) * vn) : NULL;
+  double* Fs = nl ? malloc(sizeof(double) * mn) : NULL;
+  double* bs = nl ? malloc(sizeof(double) * vn) : NULL;
+  const long Fst = nl ? (long)n * n : 0, bst = nl ? n : 0;
+  if (nl) or_dyn_linearise(M, x, Fx, bx);
+  const double* Ff = nl ? Fx : M->F;
+  const double* bf = nl ? bx : M->b;
   /* forward proposal at x */
   if (or_linearise(M, y, x, u, delta, order, om, Om, &lh_x)) status |= OR_ST_FWD_NOT_PD;
   if (!status) {
-    if (or_kf(N, n, n, M->m0, M->P0, M->F, M->b, M->Q, I, 0, Om, (long)n * n, om, mf, Pf, mp, Pp,
-              ell))
+    if (or_kf(N, n, n, M->m0, M->P0, Ff, Fst, bf, bst, M->Q, I, 0, Om, (long)n * n, om, mf, Pf, mp,
+              Pp, ell))
       status |= OR_ST_FWD_NOT_PD;
   }
   if (!status) {
     lzf = 0.0;
     for (int t = 0; t < N; ++t) lzf += ell[t];
     if (ell_f_out) memcpy(ell_f_out, ell, sizeof(double) * N);
-    if (or_rts_sample(N, n, M->F, mf, Pf, mp, Pp, xi_x, xs)) status |= OR_ST_FWD_NOT_PD;
+    if (or_rts_sample(N, n, Ff, Fst, mf, Pf, mp, Pp, xi_x, xs)) status |= OR_ST_FWD_NOT_PD;
   }
   if (!status) {
     if (xstar_out) memcpy(xstar_out, xs, sizeof(double) * vn);
     /* reverse proposal at x*, same u */
     if (or_linearise(M, y, xs, u, delta, order, om2, Om2, &lh_s)) status |= OR_ST_REV_NOT_PD;
   }
+  if (nl && !status) or_dyn_linearise(M, xs, Fs, bs);
+  const double* Fr = nl ? Fs : M->F;
+  const double* br = nl ? bs : M->b;
   if (!status) {
-    if (or_kf(N, n, n, M->m0, M->P0, M->F, M->b, M->Q, I, 0, Om2, (long)n * n, om2, NULL, NULL,
-              NULL, NULL, ell))
+    if (or_kf(N, n, n, M->m0, M->P0, Fr, Fst, br, bst, M->Q, I, 0, Om2, (long)n * n, om2, NULL,
+              NULL, NULL, NULL, ell))
       status |= OR_ST_REV_NOT_PD;
   }
   if (!status) {
@@ -609,6 +747,7 @@ int or_mh_step(const or_model* M, const double* y, const double* x, double delta
     double q_rev = pseudo_obs_loglik(N, n, om2, Om2, x, L, tmp);
     double q_fwd = pseudo_obs_loglik(N, n, om, Om, xs, L, tmp);
     lr = (lh_s - lh_x) + aux + (q_rev - q_fwd) + (lzf - lzr);
+    if (nl) lr += dyn_mismatch(M, xs, Fx, bx) - dyn_mismatch(M, x, Fs, bs);
     if (!isfinite(lr)) {
       status |= OR_ST_NONFINITE;
       lr = -INFINITY;
@@ -624,6 +763,7 @@ int or_mh_step(const or_model* M, const double* y, const double* x, double delta
   if (logZ_rev) *logZ_rev = lzr;
   free(u); free(om); free(Om); free(om2); free(Om2); free(mf); free(Pf); free(mp); free(Pp);
   free(ell); free(xs); free(I); free(L); free(tmp);
+  free(Fx); free(bx); free(Fs); free(bs);
   return status;
 }
 
@@ -719,15 +859,15 @@ static double factorised_filter_sample(const or_model* M, const double* om, cons
       Ri[t] = Om[(long)t * n + i];
     }
     const double F = M->F[i * n + i], Q = M->Q[i * n + i], P0 = M->P0[i * n + i];
-    if (or_kf(N, 1, 1, M->m0 + i, &P0, &F, M->b ? M->b + i : NULL, &Q, &one, 0, Ri, 1, yi, mf, Pf,
-              mp, Pp, ell)) {
+    if (or_kf(N, 1, 1, M->m0 + i, &P0, &F, 0, M->b ? M->b + i : NULL, 0, &Q, &one, 0, Ri, 1, yi, mf,
+              Pf, mp, Pp, ell)) {
       *fail = 1;
       break;
     }
     for (int t = 0; t < N; ++t) lz += ell[t];
     if (xi_x) {
       for (int t = 0; t < N; ++t) xii[t] = xi_x[(long)t * n + i];
-      if (or_rts_sample(N, 1, &F, mf, Pf, mp, Pp, xii, xo)) {
+      if (or_rts_sample(N, 1, &F, 0, mf, Pf, mp, Pp, xii, xo)) {
         *fail = 1;
         break;
       }
@@ -751,6 +891,7 @@ int or_mh_step_factorised(const or_model* M, const double* y, const double* x, d
                           double* x_out, double* log_ratio, int* accepted, double* logZ_fwd,
                           double* logZ_rev, double* xstar_out) {
   const int N = M->N, n = M->dx;
+  if (M->dyn != OR_DYN_LINEAR) return -1;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j)
       if (i != j && (M->F[i * n + j] != 0.0 || M->Q[i * n + j] != 0.0 || M->P0[i * n + j] != 0.0))
@@ -851,7 +992,7 @@ double or_lgssm_loglik(int N, int dx, int dy, const double* m0, const double* P0
   double* ell = malloc(sizeof(double) * N);
   for (int i = 0; i < dx; ++i) Q[i * dx + i] = exp(logq[i]);
   for (int i = 0; i < dy; ++i) R[i * dy + i] = exp(logr[i]);
-  int rc = or_kf(N, dx, dy, m0, P0, F, NULL, Q, H, 0, R, 0, y, NULL, NULL, NULL, NULL, ell);
+  int rc = or_kf(N, dx, dy, m0, P0, F, 0, NULL, 0, Q, H, 0, R, 0, y, NULL, NULL, NULL, NULL, ell);
   double s = 0.0;
   for (int t = 0; t < N; ++t) s += ell[t];
   free(Q); free(R); free(ell);
@@ -902,8 +1043,8 @@ double or_fisher_score(int N, int dx, int dy, const double* m0, const double* P0
   double* HP = malloc(sizeof(double) * p * n);
   double* r = malloc(sizeof(double) * p);
   double ll = NAN;
-  int rc = or_kf(N, n, p, m0, P0, F, NULL, Q, H, 0, R, 0, y, mf, Pf, mp, Pp, ell);
-  if (!rc) rc = or_rts_smooth(N, n, F, mf, Pf, mp, Pp, ms, Ps, G);
+  int rc = or_kf(N, n, p, m0, P0, F, 0, NULL, 0, Q, H, 0, R, 0, y, mf, Pf, mp, Pp, ell);
+  if (!rc) rc = or_rts_smooth(N, n, F, 0, mf, Pf, mp, Pp, ms, Ps, G);
   if (!rc) {
     ll = 0.0;
     for (int t = 0; t < N; ++t) ll += ell[t];

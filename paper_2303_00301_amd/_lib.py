@@ -27,6 +27,7 @@ class AkfModel(C.Structure):
         ("H", C.c_void_p), ("R", C.c_void_p),
         ("site", C.c_void_p),
         ("nu", C.c_double), ("scale", C.c_double),
+        ("dyn", C.c_int32), ("dyn_par", C.c_double * 4),
     ]
 
 

@@ -48,6 +48,7 @@ int grid_for(int n, int cap) { return std::max(1, std::min(n, cap)); }
 akf_status check_chain(const akf_chain& c, int k) {
   akf_status s = check_model(&c.model, true);
   if (s != AKF_OK) return s;
+  if ((s = check_linear(&c.model, "batched chains")) != AKF_OK) return s;
   if (c.model.emit == AKF_EMIT_GAUSSIAN || c.model.emit == AKF_EMIT_MVT)
     return fail(AKF_ERR_UNSUPPORTED, "chain %d: batched chains support the Poisson, "
                     "Student-t and stochastic-volatility emission families", k);

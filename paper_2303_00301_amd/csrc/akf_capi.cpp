@@ -56,20 +56,43 @@ akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, cons
                                       Lo.D, st),
                      "init launch")) != AKF_OK)
     return s;
-  int n_part_fwd = 0, n_part_rev = 0;
+  int n_part_fwd = 0, n_part_rev = 0, n_part_dyn = 0;
   if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
+  // nonlinear dynamics: F_t, b_t of the extended linearisation, at x here and
+  // at x* (with the mismatch terms of log r) before the reverse filter
+  const bool nl = M.dyn != DYN_LINEAR;
+  double* Ft = nl ? at<double>(ws, Lo.Ft) : nullptr;
+  double* bt = nl ? at<double>(ws, Lo.bt) : nullptr;
+  DynArgs Dy{};
+  Dy.Ft = Ft;
+  Dy.bt = bt;
+  Dy.Qinv = nl ? at<double>(ws, Lo.Qinv) : nullptr;
+  if (nl) {
+    Dy.a = x_in;
+    if ((s = hip_check(launch_dyn_lin(M, Dy, nullptr, st), "dynamics launch")) != AKF_OK) return s;
+  }
   const double* Omd = (M.emit == EMIT_GAUSSIAN && order == 2) ? A.g_Omd : nullptr;
   double* mf = at<double>(ws, Lo.mf);
   double* Pf = at<double>(ws, Lo.Pf);
   if ((s = run_filter(Lo, M, ws, A.om, A.Om, Omd, mf, Pf, Lo.D, A.ell, status, ST_FWD_NOT_PD,
-                      st)) != AKF_OK)
+                      st, nullptr, nullptr, nullptr, 0, Ft, bt)) != AKF_OK)
     return s;
-  if ((s = run_sampler(Lo, M, ws, mf, Pf, Lo.D, xi + vn, A.xs, status, st)) != AKF_OK) return s;
+  if ((s = run_sampler(Lo, M, ws, mf, Pf, Lo.D, xi + vn, A.xs, status, st, Ft, bt)) != AKF_OK)
+    return s;
   if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
+  if (nl) {
+    Dy.a = A.xs;
+    Dy.z = x_in;
+    Dy.part = at<double>(ws, Lo.pdyn);
+    if ((s = hip_check(launch_dyn_lin(M, Dy, &n_part_dyn, st), "dynamics launch")) != AKF_OK)
+      return s;
+  }
   if ((s = run_filter(Lo, M, ws, A.om2, A.Om2, Omd, nullptr, nullptr, Lo.D, A.ell2, status,
-                      ST_REV_NOT_PD, st)) != AKF_OK)
+                      ST_REV_NOT_PD, st, nullptr, nullptr, nullptr, 0, Ft, bt)) != AKF_OK)
     return s;
   FinalArgs F{};
+  F.part_dyn = Dy.part;
+  F.n_part_dyn = n_part_dyn;
   F.unif = unif;
   F.log_ratio = log_ratio;
   F.accepted = accepted;
@@ -131,6 +154,7 @@ akf_status fact_step_impl(const Layout& Lo, const KModel& M, const double* y, co
 akf_status check_fact_model(const akf_model* model, int order) {
   akf_status s;
   if ((s = check_model(model, true)) != AKF_OK) return s;
+  if ((s = check_linear(model, "the factorised step")) != AKF_OK) return s;
   if ((s = check_order(model, order)) != AKF_OK) return s;
   if (model->emit == AKF_EMIT_GAUSSIAN)
     return fail(AKF_ERR_UNSUPPORTED, "the factorised step needs a site-based emission family "
@@ -188,7 +212,8 @@ void timing_mark(int family, int begin, hipStream_t st) {
 extern "C" {
 
 size_t akf_smoother_workspace_bytes(const akf_model* model, int32_t block) {
-  if (check_model(model, false) != AKF_OK) return 0;
+  if (check_model(model, false) != AKF_OK || check_linear(model, "akf_smoother") != AKF_OK)
+    return 0;
   Layout Lo;
   make_layout(Lo, model->N, model->dx, 0, block, LAYOUT_SMOOTH);
   return Lo.total;
@@ -199,6 +224,7 @@ akf_status akf_smoother(const akf_model* model, const double* mf, const double* 
                         void* stream) {
   akf_status s;
   if ((s = check_model(model, false)) != AKF_OK) return s;
+  if ((s = check_linear(model, "akf_smoother")) != AKF_OK) return s;
   if (!mf || !Pf || !ms || !Ps) return fail(AKF_ERR_INVALID, "mf, Pf, ms and Ps must be non-NULL");
   if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
   Layout Lo;
@@ -428,7 +454,7 @@ const char* akf_last_error(void) { return akf::last_error(); }
 size_t akf_mh_workspace_bytes(const akf_model* model, int32_t order, int32_t block) {
   if (check_model(model, true) != AKF_OK || check_order(model, order) != AKF_OK) return 0;
   Layout Lo;
-  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP);
+  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP, model->dyn != 0);
   return Lo.total;
 }
 
@@ -444,11 +470,16 @@ akf_status akf_mh_step(const akf_model* model, const double* y, const double* x_
   if ((s = check_order(model, order)) != AKF_OK) return s;
   if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
   Layout Lo;
-  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP);
+  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP, model->dyn != 0);
   if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
   if ((s = prepare_device()) != AKF_OK) return s;
-  return mh_step_impl(Lo, to_kmodel(model), y, x_in, delta, order, xi, unif, x_out, log_ratio,
-                      accepted, logZ_fwd, logZ_rev, status, ws, (hipStream_t)stream);
+  const KModel M = to_kmodel(model);
+  if (M.dyn != DYN_LINEAR &&
+      (s = hip_check(launch_qinv(M, at<double>(ws, Lo.Qinv), (hipStream_t)stream), "Q^-1 launch")) !=
+          AKF_OK)
+    return s;
+  return mh_step_impl(Lo, M, y, x_in, delta, order, xi, unif, x_out, log_ratio, accepted, logZ_fwd,
+                      logZ_rev, status, ws, (hipStream_t)stream);
 }
 
 akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double delta,
@@ -463,11 +494,15 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
   if ((s = check_order(model, order)) != AKF_OK) return s;
   if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
   Layout Lo;
-  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP);
+  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP, model->dyn != 0);
   if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
   if ((s = prepare_device()) != AKF_OK) return s;
   const KModel M = to_kmodel(model);
   const size_t vn = (size_t)M.N * M.d;
+  if (M.dyn != DYN_LINEAR && n_steps > 0 &&
+      (s = hip_check(launch_qinv(M, at<double>(ws, Lo.Qinv), (hipStream_t)stream), "Q^-1 launch")) !=
+          AKF_OK)
+    return s;
   for (int k = 0; k < n_steps; ++k) {
     s = mh_step_impl(Lo, M, y, x, delta, order, xi + (size_t)k * 2 * vn, unif + k, x,
                      log_ratio ? log_ratio + k : nullptr, accepted ? accepted + k : nullptr,
@@ -528,7 +563,8 @@ akf_status akf_mh_run_factorised(const akf_model* model, const double* y, double
 }
 
 size_t akf_filter_workspace_bytes(const akf_model* model, int32_t block) {
-  if (check_model(model, false) != AKF_OK) return 0;
+  if (check_model(model, false) != AKF_OK || check_linear(model, "akf_aux_filter") != AKF_OK)
+    return 0;
   Layout Lo;
   make_layout(Lo, model->N, model->dx, 0, block, LAYOUT_FILTER);
   return Lo.total;
@@ -539,6 +575,7 @@ akf_status akf_aux_filter(const akf_model* model, const double* omega, const dou
                           size_t ws_bytes, int32_t block, void* stream) {
   akf_status s;
   if ((s = check_model(model, false)) != AKF_OK) return s;
+  if ((s = check_linear(model, "akf_aux_filter")) != AKF_OK) return s;
   if (!omega || !Omega || !ell) return fail(AKF_ERR_INVALID, "omega, Omega and ell must be non-NULL");
   if ((mf == nullptr) != (Pf == nullptr))
     return fail(AKF_ERR_INVALID, "mf and Pf must both be given or both be NULL");
@@ -563,7 +600,8 @@ akf_status akf_aux_filter(const akf_model* model, const double* omega, const dou
 }
 
 size_t akf_sampler_workspace_bytes(const akf_model* model, int32_t block) {
-  if (check_model(model, false) != AKF_OK) return 0;
+  if (check_model(model, false) != AKF_OK || check_linear(model, "akf_rts_sample") != AKF_OK)
+    return 0;
   Layout Lo;
   make_layout(Lo, model->N, model->dx, 0, block, LAYOUT_SAMPLER);
   return Lo.total;
@@ -574,6 +612,7 @@ akf_status akf_rts_sample(const akf_model* model, const double* mf, const double
                           size_t ws_bytes, int32_t block, void* stream) {
   akf_status s;
   if ((s = check_model(model, false)) != AKF_OK) return s;
+  if ((s = check_linear(model, "akf_rts_sample")) != AKF_OK) return s;
   if (!mf || !Pf || !xi || !x) return fail(AKF_ERR_INVALID, "mf, Pf, xi and x must be non-NULL");
   if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
   Layout Lo;

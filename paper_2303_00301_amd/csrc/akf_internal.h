@@ -6,7 +6,8 @@
 namespace akf {
 
 enum { EMIT_GAUSSIAN = 0, EMIT_POISSON_LOG = 1, EMIT_STUDENT_T = 2, EMIT_STOCH_VOL = 3,
-       EMIT_MVT = 4 };
+       EMIT_MVT = 4, EMIT_GAUSS_SITE = 5 };
+enum { DYN_LINEAR = 0, DYN_LORENZ63 = 1, DYN_LORENZ96 = 2 };
 enum { ST_FWD_NOT_PD = 1, ST_REV_NOT_PD = 2, ST_NONFINITE = 4 };
 
 // time steps (one wave each) per workgroup of the multivariate-t linearisation
@@ -19,6 +20,8 @@ struct KModel {
   const double *H, *R;
   const int* site;
   double nu, scale;
+  int dyn;
+  double dyn_par[4];
 };
 
 // Filter element (A, b, C, eta, J), padded to D.
@@ -80,6 +83,9 @@ struct FilterArgs {
   const double* Ho;   // [dyo*d]
   const double* Ro;   // [dyo*dyo]
   int dyo;
+  // per-step dynamics F_t [N*d*d], b_t [N*d] (transition into step t), or
+  // nullptr for the model's F, b
+  const double *Ft, *bt;
 };
 
 struct TreeArgs {
@@ -111,6 +117,18 @@ struct SampArgs {
   const double* xin; // x* entering each block from the right, level 0
   double* xs;        // [N*d]
   int* status;
+  const double *Ft, *bt;  // per-step dynamics as in FilterArgs, or nullptr
+};
+
+// Extended linearisation of nonlinear dynamics (one wave per time step):
+// F_t = J(a_{t-1}), b_t = f(a_{t-1}) - F_t a_{t-1} around the path `a`; with
+// `z` (the other path) also the per-step MH terms of the dynamics mismatch.
+struct DynArgs {
+  const double* a;     // [N*d] linearisation point
+  const double* z;     // [N*d] the other path, or nullptr
+  double *Ft, *bt;     // [N*d*d], [N*d]
+  const double* Qinv;  // [d*d]
+  double* part;        // [n_part] partial sums of the mismatch terms
 };
 
 // Auxiliary LGSSM of a factorising prior: dx scalar models, one per
@@ -127,6 +145,8 @@ struct FactArgs {
 
 struct FinalArgs {
   int n_ell;  // entries of ell/ell2 summed into log Z (0 = N)
+  const double* part_dyn;  // dynamics mismatch partial sums (n_part_dyn), or nullptr
+  int n_part_dyn;
   const double* unif;
   double* log_ratio;
   int* accepted;
@@ -245,6 +265,8 @@ hipError_t launch_adj_finish_any(int D, const KModel& M, LgArgs G, int nblk, con
                                  hipStream_t st);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 hipError_t launch_fact_scan(const KModel& M, FactArgs P, hipStream_t st);
+hipError_t launch_qinv(const KModel& M, double* Qinv, hipStream_t st);
+hipError_t launch_dyn_lin(const KModel& M, DynArgs A, int* n_part, hipStream_t st);
 
 // Batched launches for one D class.  `step` is the device step counter.
 enum BatchPhase {

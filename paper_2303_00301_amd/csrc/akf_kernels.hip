@@ -53,7 +53,7 @@ __global__ void k_step_init(int* status, double* root_flag, double* root_xin, in
 
 // ---------------------------------------------------------------------------
 // Emission linearisation, diagonal families (Poisson log-link, Student-t,
-// stochastic volatility).
+// stochastic volatility, Gaussian at sites).
 // One thread per (t, i).  Site k observes latent site[k]; a latent observed by
 // several sites sums their contributions.
 //   v_i = d log h / d x_i,  Lambda_ii = d^2 log h / d x_i^2 (0 under order 1)
@@ -68,12 +68,17 @@ __device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __re
                                              double xi, int i) {
   EmitOut o{0.0, 0.0, 0.0};
   for (int k = 0; k < M.dy; ++k) {
-    if (M.site[k] != i) continue;
+    if (M.site[k] != i || isnan(yt[k])) continue;  // NaN: site not observed at t
     if (M.emit == EMIT_POISSON_LOG) {
       const double e = exp(xi);
       o.lh += yt[k] * xi - e;
       o.v += yt[k] - e;
       o.lam -= e;
+    } else if (M.emit == EMIT_GAUSS_SITE) {
+      const double s2 = M.scale * M.scale, r = yt[k] - xi;
+      o.lh += -0.5 * r * r / s2;
+      o.v += r / s2;
+      o.lam -= 1.0 / s2;
     } else if (M.emit == EMIT_STOCH_VOL) {
       const double q = yt[k] * yt[k] * exp(-xi);  // y ~ N(0, exp(x))
       o.lh += -0.5 * xi - 0.5 * q;
@@ -558,7 +563,7 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   constexpr bool first = FIRST;
   const int dobs = GH ? P.dyo : d;
-  lds_load_mat<D>(sF, M.F, d);
+  if (!P.Ft) lds_load_mat<D>(sF, M.F, d);
   if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
   if (tid < D) {
     vb[tid] = 0.0;
@@ -576,6 +581,12 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       rm_load<D>(Pp, M.P0, d, d);
       if (tid < D) vmu[tid] = (tid < d) ? M.m0[tid] : 0.0;
     } else {
+      const double* bt = M.b;
+      if (P.Ft) {  // per-step dynamics: F_t replaces F in LDS
+        team_sync();
+        lds_load_mat<D>(sF, P.Ft + (int64_t)t * d * d, d);
+        bt = P.bt + (int64_t)t * d;
+      }
       rm_load<D>(Pp, M.Q, d, d);  // issued early: its latency overlaps F C
       rm_stage<D>(Cc, B1);
       team_sync();
@@ -586,7 +597,7 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       gemm<D, false, true, true>(Pp, B1, sF);  // Q + (F C) F'
       matvec<D, false>(vmu, sF, vb);
       team_sync();
-      if (tid < d && M.b) vmu[tid] += M.b[tid];
+      if (tid < d && bt) vmu[tid] += bt[tid];
       if (!first) {
         rm_stage<D>(A, B1);
         team_sync();
@@ -992,7 +1003,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
   double* red = vom + D;
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
-  lds_load_mat<D>(sF, M.F, d);
+  if (!P.Ft) lds_load_mat<D>(sF, M.F, d);
   if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
   const int dobs = GH ? P.dyo : d;
   RM<D> Pm, Pp, T, R2;
@@ -1014,6 +1025,12 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       rm_load<D>(Pp, M.P0, d, d);
       if (tid < D) vmp[tid] = (tid < d) ? M.m0[tid] : 0.0;
     } else {
+      const double* bt = M.b;
+      if (P.Ft) {  // per-step dynamics: F_t replaces F in LDS
+        team_sync();
+        lds_load_mat<D>(sF, P.Ft + (int64_t)t * d * d, d);
+        bt = P.bt + (int64_t)t * d;
+      }
       rm_load<D>(Pp, M.Q, d, d);  // issued early: its latency overlaps F P
       rm_stage<D>(Pm, B1);
       team_sync();
@@ -1024,7 +1041,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       gemm<D, false, true, true>(Pp, B1, sF);  // Q + (F P) F'
       matvec<D, false>(vmp, sF, vm);
       team_sync();
-      if (tid < d && M.b) vmp[tid] += M.b[tid];
+      if (tid < d && bt) vmp[tid] += bt[tid];
       team_sync();
     }
     if constexpr (OBS == OBS_DIAG) {
@@ -1145,7 +1162,9 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     rm_store<D>(Z, S.E + (int64_t)t * D * D, D, D);
   } else {
     rm_load<D>(R2, M.Q, d, d);  // issued early: its latency overlaps G = F P^f
-    lds_load_mat<D>(sF, M.F, d);
+    // the transition into step t + 1
+    lds_load_mat<D>(sF, S.Ft ? S.Ft + (int64_t)(t + 1) * d * d : M.F, d);
+    const double* bt = S.Ft ? S.bt + (int64_t)(t + 1) * d : M.b;
     rm_stage<D>(Pf, B1);
     team_sync();
     gemm<D, false, false, false>(R1, sF, B1);  // G = F P^f
@@ -1154,7 +1173,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     team_sync();
     gemm<D, false, true, true>(R2, B1, sF);  // Q + G F'
     matvec<D, false>(vmp, sF, vm);
-    if (tid < d && M.b) vmp[tid] += M.b[tid];
+    if (tid < d && bt) vmp[tid] += bt[tid];
     {
       const RM<D> Pp = R2;
       ok = spd_inv<D>(R2, d, B3, &ld) && ok;  // (P^p)^{-1}
@@ -1339,12 +1358,13 @@ __device__ __forceinline__ void mh_finalize_body(const KModel& M, const StepArgs
   const double terms = block_sum(A.part_terms, F.n_part_rev, red);
   const double lhx = block_sum(A.part_lh_x, F.n_part_fwd, red);
   const double lhs = block_sum(A.part_lh_xs, F.n_part_rev, red);
+  const double dyn = F.part_dyn ? block_sum(F.part_dyn, F.n_part_dyn, red) : 0.0;
   if (threadIdx.x == 0) {
     int st = *A.status;
     // a failed forward proposal makes x* (and everything computed from it)
     // meaningless: report only the forward failure
     if (st & ST_FWD_NOT_PD) st = ST_FWD_NOT_PD;
-    double lr = terms + (lhs - lhx) + (lzf - lzr);
+    double lr = terms + (lhs - lhx) + (lzf - lzr) + dyn;
     if (st == 0 && !isfinite(lr)) st |= ST_NONFINITE;
     if (st != 0) lr = -INFINITY;
     const int acc = (st == 0) && (log(F.unif[0]) < lr);

@@ -39,7 +39,7 @@ int auto_block(int N, int D) {
   return B;
 }
 
-void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
+void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn) {
   Lo.N = N;
   Lo.d = d;
   Lo.dy = dy;
@@ -88,6 +88,13 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind) {
     Lo.gOmdinv = take((size_t)d * d * dbl);
     Lo.gscal = take(8 * dbl);
     Lo.accept = take(sizeof(int));
+    if (dyn) {
+      Lo.Ft = take((size_t)N * d * d * dbl);
+      Lo.bt = take(vn);
+      Lo.Qinv = take((size_t)d * d * dbl);
+      Lo.n_part_dyn = (N + 3) / 4;
+      Lo.pdyn = take((size_t)Lo.n_part_dyn * dbl);
+    }
   }
   if (kind == LAYOUT_FACT) {
     // the scan keeps no elements: only vectors [N*d] and per-coordinate sums
@@ -155,8 +162,22 @@ akf_status check_model(const akf_model* m, bool need_emission) {
   if (!m) return fail(AKF_ERR_INVALID, "model is NULL");
   if (m->N < 1) return fail(AKF_ERR_SHAPE, "N must be >= 1 (got %d)", m->N);
   if (m->dx < 1 || m->dx > 64) return fail(AKF_ERR_SHAPE, "dx must be in [1, 64] (got %d)", m->dx);
-  if (!m->m0 || !m->P0 || !m->F || !m->Q)
-    return fail(AKF_ERR_INVALID, "m0, P0, F and Q must be non-NULL");
+  switch (m->dyn) {
+    case AKF_DYN_LINEAR:
+      if (!m->F) return fail(AKF_ERR_INVALID, "linear dynamics need F");
+      break;
+    case AKF_DYN_LORENZ63:
+      if (m->dx != 3) return fail(AKF_ERR_SHAPE, "Lorenz-63 dynamics need dx = 3 (got %d)", m->dx);
+      if (!(m->dyn_par[3] > 0.0)) return fail(AKF_ERR_INVALID, "Lorenz-63 needs dt = dyn_par[3] > 0");
+      break;
+    case AKF_DYN_LORENZ96:
+      if (m->dx < 4) return fail(AKF_ERR_SHAPE, "Lorenz-96 dynamics need dx >= 4 (got %d)", m->dx);
+      if (!(m->dyn_par[1] > 0.0)) return fail(AKF_ERR_INVALID, "Lorenz-96 needs dt = dyn_par[1] > 0");
+      break;
+    default:
+      return fail(AKF_ERR_INVALID, "unknown dynamics family %d", m->dyn);
+  }
+  if (!m->m0 || !m->P0 || !m->Q) return fail(AKF_ERR_INVALID, "m0, P0 and Q must be non-NULL");
   if (!need_emission) return AKF_OK;
   if (m->dy < 1 || m->dy > 64) return fail(AKF_ERR_SHAPE, "dy must be in [1, 64] (got %d)", m->dy);
   switch (m->emit) {
@@ -173,6 +194,10 @@ akf_status check_model(const akf_model* m, bool need_emission) {
       if (!m->site) return fail(AKF_ERR_INVALID, "Student-t emission needs site");
       if (!(m->nu > 0.0) || !(m->scale > 0.0))
         return fail(AKF_ERR_INVALID, "Student-t emission needs nu > 0 and scale > 0");
+      break;
+    case AKF_EMIT_GAUSS_SITE:
+      if (!m->site) return fail(AKF_ERR_INVALID, "Gaussian-at-sites emission needs site");
+      if (!(m->scale > 0.0)) return fail(AKF_ERR_INVALID, "Gaussian-at-sites emission needs scale > 0");
       break;
     case AKF_EMIT_MVT:
       if (!m->site || !m->R) return fail(AKF_ERR_INVALID, "multivariate-t emission needs site and R");
@@ -193,6 +218,13 @@ akf_status check_order(const akf_model* m, int order) {
   return AKF_OK;
 }
 
+akf_status check_linear(const akf_model* m, const char* what) {
+  if (m->dyn != AKF_DYN_LINEAR)
+    return fail(AKF_ERR_UNSUPPORTED, "%s needs linear dynamics (nonlinear dynamics are "
+                                     "accepted by akf_mh_step and akf_mh_run only)", what);
+  return AKF_OK;
+}
+
 KModel to_kmodel(const akf_model* m) {
   KModel M;
   M.N = m->N;
@@ -209,6 +241,8 @@ KModel to_kmodel(const akf_model* m) {
   M.site = m->site;
   M.nu = m->nu;
   M.scale = m->scale;
+  M.dyn = m->dyn;
+  for (int i = 0; i < 4; ++i) M.dyn_par[i] = m->dyn_par[i];
   return M;
 }
 
@@ -258,8 +292,11 @@ double* root_flag(const Layout& Lo, void* ws) {
 akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double* om,
                       const double* Om, const double* Omd, double* mf, double* Pf, int ldm,
                       double* ell, int* status, int fail_bit, hipStream_t st,
-                      const double* yo, const double* Ho, const double* Ro, int dyo) {
+                      const double* yo, const double* Ho, const double* Ro, int dyo,
+                      const double* Ft, const double* bt) {
   FilterArgs P{};
+  P.Ft = Ft;
+  P.bt = bt;
   P.yo = yo;
   P.Ho = Ho;
   P.Ro = Ro;
@@ -294,8 +331,10 @@ akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double*
 
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
                        const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
-                       hipStream_t st) {
+                       hipStream_t st, const double* Ft, const double* bt) {
   SampArgs S{};
+  S.Ft = Ft;
+  S.bt = bt;
   S.B = Lo.B;
   S.mf = mf;
   S.Pf = Pf;

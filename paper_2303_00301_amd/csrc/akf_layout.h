@@ -30,6 +30,9 @@ struct Layout {
   size_t sagg[kMaxLevels + 1] = {0};
   size_t xin[kMaxLevels + 1] = {0};
   size_t status = 0, accept = 0;
+  // nonlinear dynamics: per-step F_t, b_t, Q^{-1}, mismatch partial sums
+  size_t Ft = 0, bt = 0, Qinv = 0, pdyn = 0;
+  int n_part_dyn = 0;
   // (E, g, L) scan, smoother and adjoint
   size_t g = 0, Lm = 0, Pbar = 0, mbar = 0, part = 0, Qd = 0, Rd = 0, llv = 0;
   size_t eagg[kMaxLevels + 1] = {0};
@@ -49,9 +52,10 @@ T* at(void* ws, size_t off) {
 akf_status fail(akf_status s, const char* fmt, ...);
 int pick_D(int d);
 int auto_block(int N, int D);
-void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind);
+void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn = false);
 akf_status check_model(const akf_model* m, bool need_emission);
 akf_status check_order(const akf_model* m, int order);
+akf_status check_linear(const akf_model* m, const char* what);
 KModel to_kmodel(const akf_model* m);
 akf_status prepare_device();
 akf_status hip_check(hipError_t e, const char* what);
@@ -62,10 +66,11 @@ akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double*
                       const double* Om, const double* Omd, double* mf, double* Pf, int ldm,
                       double* ell, int* status, int fail_bit, hipStream_t st,
                       const double* yo = nullptr, const double* Ho = nullptr,
-                      const double* Ro = nullptr, int dyo = 0);
+                      const double* Ro = nullptr, int dyo = 0, const double* Ft = nullptr,
+                      const double* bt = nullptr);
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
                        const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
-                       hipStream_t st);
+                       hipStream_t st, const double* Ft = nullptr, const double* bt = nullptr);
 void fill_egl_tree(const Layout& Lo, void* ws, EglTree* up, EglTree* down);
 akf_status run_egl(const Layout& Lo, void* ws, const double* g, double* outL, double* outg,
                    int ldo, int dout, hipStream_t st);

@@ -15,6 +15,8 @@ import torch
 from . import _lib
 
 EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
+EMIT_GAUSS_SITE = 5
+DYN_LINEAR, DYN_LORENZ63, DYN_LORENZ96 = 0, 1, 2
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
 
@@ -65,19 +67,23 @@ class DeviceModel:
     site: Optional[torch.Tensor] = None
     nu: float = 0.0
     scale: float = 0.0
+    dyn: int = DYN_LINEAR
+    dyn_par: tuple = (0.0, 0.0, 0.0, 0.0)
 
     @classmethod
     def from_arrays(cls, N, m0, P0, F, Q, emit, b=None, H=None, R=None, site=None, nu=0.0,
-                    scale=0.0, device=None):
+                    scale=0.0, dyn=DYN_LINEAR, dyn_par=(0.0, 0.0, 0.0, 0.0), device=None):
         dev = _dev(device)
         return cls(N=int(N), m0=_t(m0, dev), P0=_t(P0, dev), F=_t(F, dev), Q=_t(Q, dev),
                    emit=int(emit), b=_t(b, dev), H=_t(H, dev), R=_t(R, dev),
-                   site=_t(site, dev, torch.int32), nu=float(nu), scale=float(scale))
+                   site=_t(site, dev, torch.int32), nu=float(nu), scale=float(scale),
+                   dyn=int(dyn), dyn_par=tuple(float(v) for v in dyn_par))
 
     @classmethod
     def from_workload(cls, w, device=None):
         return cls.from_arrays(w.N, w.m0, w.P0, w.F, w.Q, w.emit, b=w.b, H=w.H, R=w.R,
-                               site=w.site, nu=w.nu, scale=w.scale, device=device)
+                               site=w.site, nu=w.nu, scale=w.scale, dyn=w.dyn,
+                               dyn_par=w.dyn_par, device=device)
 
     @property
     def dx(self) -> int:
@@ -96,7 +102,7 @@ class DeviceModel:
     @property
     def is_diagonal_form(self) -> bool:
         """True when P0, F and Q hold diagonals [dx] (the factorised entry points)."""
-        return self.F.dim() == 1
+        return self.Q.dim() == 1
 
     def diagonal(self) -> "DeviceModel":
         """The model with P0, F and Q replaced by their diagonals, as the
@@ -115,14 +121,18 @@ class DeviceModel:
     def cstruct(self) -> _lib.AkfModel:
         s = _lib.AkfModel()
         s.N, s.dx, s.dy = self.N, self.dx, self.dy
-        s.m0, s.P0, s.F, s.Q = (self.m0.data_ptr(), self.P0.data_ptr(), self.F.data_ptr(),
-                                self.Q.data_ptr())
+        s.m0, s.P0, s.Q = self.m0.data_ptr(), self.P0.data_ptr(), self.Q.data_ptr()
+        s.F = self.F.data_ptr() if self.F is not None else None
         s.b = self.b.data_ptr() if self.b is not None else None
         s.emit = self.emit
         s.H = self.H.data_ptr() if self.H is not None else None
         s.R = self.R.data_ptr() if self.R is not None else None
         s.site = self.site.data_ptr() if self.site is not None else None
         s.nu, s.scale = self.nu, self.scale
+        s.dyn = self.dyn
+        par = list(self.dyn_par) + [0.0] * (4 - len(self.dyn_par))
+        for i in range(4):
+            s.dyn_par[i] = par[i]
         return s
 
 
@@ -267,7 +277,7 @@ def aux_filter(model: DeviceModel, omega, Omega, block: int = 0, moments: bool =
     ell = torch.empty(N, dtype=torch.float64, device=dev)
     st = torch.empty(1, dtype=torch.int32, device=dev)
     ms = model.cstruct()
-    need = lib.akf_filter_workspace_bytes(C.byref(ms), block)
+    need = _need(lib.akf_filter_workspace_bytes(C.byref(ms), block), "akf_filter_workspace_bytes")
     wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
     rc = lib.akf_aux_filter(C.byref(ms), _ptr(omega), _ptr(Omega), _ptr(mf), _ptr(Pf), _ptr(ell),
                             _ptr(st), wsp, wsb, int(block), _stream(dev))
@@ -286,7 +296,7 @@ def rts_sample(model: DeviceModel, mf, Pf, xi, block: int = 0, ws: Optional[Work
     x = torch.empty((N, dx), dtype=torch.float64, device=dev)
     st = torch.empty(1, dtype=torch.int32, device=dev)
     ms = model.cstruct()
-    need = lib.akf_sampler_workspace_bytes(C.byref(ms), block)
+    need = _need(lib.akf_sampler_workspace_bytes(C.byref(ms), block), "akf_sampler_workspace_bytes")
     wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
     rc = lib.akf_rts_sample(C.byref(ms), _ptr(mf), _ptr(Pf), _ptr(xi), _ptr(x), _ptr(st), wsp,
                             wsb, int(block), _stream(dev))
@@ -306,7 +316,8 @@ def smoother(model: DeviceModel, mf, Pf, block: int = 0, ws: Optional[Workspace]
     Ps = torch.empty((N, dx, dx), dtype=torch.float64, device=dev)
     st = torch.empty(1, dtype=torch.int32, device=dev)
     ms_ = model.cstruct()
-    need = lib.akf_smoother_workspace_bytes(C.byref(ms_), block)
+    need = _need(lib.akf_smoother_workspace_bytes(C.byref(ms_), block),
+                 "akf_smoother_workspace_bytes")
     wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
     rc = lib.akf_smoother(C.byref(ms_), _ptr(mf), _ptr(Pf), _ptr(ms), _ptr(Ps), _ptr(st), wsp, wsb,
                           int(block), _stream(dev))
@@ -345,7 +356,7 @@ def lgssm_loglik(model: LGSSM, F, logq, H, logr, block: int = 0,
     lib = _lib.load()
     dev = model.device
     s = model.cstruct(F, logq, H, logr)
-    need = lib.akf_lgssm_workspace_bytes(C.byref(s), block)
+    need = _need(lib.akf_lgssm_workspace_bytes(C.byref(s), block), "akf_lgssm_workspace_bytes")
     ws = ws or Workspace(dev)
     wsp, wsb = ws.ptr_bytes(need)
     ll = torch.empty(1, dtype=torch.float64, device=dev)
@@ -364,7 +375,7 @@ def lgssm_loglik_grad(model: LGSSM, F, logq, H, logr, ws: Workspace, ll_bar=None
     lib = _lib.load()
     dev = model.device
     s = model.cstruct(F, logq, H, logr)
-    need = lib.akf_lgssm_workspace_bytes(C.byref(s), block)
+    need = _need(lib.akf_lgssm_workspace_bytes(C.byref(s), block), "akf_lgssm_workspace_bytes")
     wsp, wsb = ws.ptr_bytes(need)
     dF = torch.empty_like(F)
     dq = torch.empty_like(logq)

@@ -11,7 +11,9 @@ Seeds: model/data from ``default_rng(data_seed)``, step normals from
 
 Emission codes match the C-ABI: 0 Gaussian (H, R), 1 Poisson with log link,
 2 Student-t at observation sites, 3 stochastic volatility (y ~ N(0, exp(x))),
-4 multivariate t with a precision matrix.
+4 multivariate t with a precision matrix, 5 Gaussian at observation sites (NaN =
+not observed).  Dynamics: 0 linear (F, b), 1 Lorenz-63 and 2 Lorenz-96 Euler
+steps.
 """
 from __future__ import annotations
 
@@ -21,6 +23,8 @@ from typing import List, Optional
 import numpy as np
 
 EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
+EMIT_GAUSS_SITE = 5
+DYN_LINEAR, DYN_LORENZ63, DYN_LORENZ96 = 0, 1, 2
 
 
 @dataclass
@@ -46,6 +50,8 @@ class Workload:
     seed: int = 0
     x_true: Optional[np.ndarray] = None
     extra: dict = field(default_factory=dict)
+    dyn: int = DYN_LINEAR
+    dyn_par: tuple = (0.0, 0.0, 0.0, 0.0)
 
     @property
     def dx(self) -> int:
@@ -72,7 +78,8 @@ class Workload:
 
     def oracle_kwargs(self) -> dict:
         return dict(m0=self.m0, P0=self.P0, F=self.F, Q=self.Q, emit=self.emit, b=self.b,
-                    H=self.H, R=self.R, site=self.site, nu=self.nu, scale=self.scale)
+                    H=self.H, R=self.R, site=self.site, nu=self.nu, scale=self.scale,
+                    dyn=self.dyn, dyn_par=tuple(self.dyn_par))
 
 
 def _simulate(rng, N, m0, P0, F, Q, b=None):
@@ -224,6 +231,76 @@ def spatio_temporal(N: int = 1024, side: int = 8, nu: float = 1.0, tau: float = 
                     site=np.arange(d, dtype=np.int32), nu=nu,
                     delta=SPATIO_TEMPORAL_DELTA if delta is None else delta, order=1,
                     seed=seed, x_true=x)
+
+
+def euler_drift(dyn: int, par, x: np.ndarray) -> np.ndarray:
+    """beta(x) of the Lorenz-63 (dyn 1) or Lorenz-96 (dyn 2) SDE, for simulating
+    data; the samplers evaluate the dynamics themselves."""
+    if dyn == DYN_LORENZ63:
+        t1, t2, t3 = par[:3]
+        return np.array([t1 * (x[1] - x[0]), t2 * x[0] - x[1] - x[0] * x[2],
+                         x[0] * x[1] - t3 * x[2]])
+    return (np.roll(x, -1) - np.roll(x, 2)) * np.roll(x, 1) - x + par[0]
+
+
+def _simulate_sde(rng, N, m0, P0, dyn, par, dt, sigma):
+    d = len(m0)
+    x = np.zeros((N, d))
+    x[0] = m0 + np.linalg.cholesky(P0) @ rng.standard_normal(d)
+    for t in range(1, N):
+        x[t] = x[t - 1] + dt * euler_drift(dyn, par, x[t - 1]) + \
+            sigma * np.sqrt(dt) * rng.standard_normal(d)
+    return x
+
+
+# Step size of the Lorenz-63 workload (seed 9), second order.  On the oracle, 60
+# steps from the prior-simulated start accepted 95% at this delta and 2.5% at
+# delta = 100; from the simulated path, 77% at delta = 1e6, where the u_t carry
+# almost no information, matching the paper's report that its adaptation drove
+# delta to very large values at about 70% acceptance.
+LORENZ63_DELTA = 1.0
+
+
+def lorenz63(N: int = 10001, dt: float = 2e-4, obs_every: int = 50, sigma: float = 3.0,
+             seed: int = 9, delta: Optional[float] = None) -> Workload:
+    """Lorenz-63 SDE dx = beta_theta(x) dt + sigma dW with theta = (10, 28, 8/3)
+    (Sec. "Parameter estimation in a continuous-discrete diffusion smoothing
+    problem"), Euler-Maruyama on a fine grid of step dt over [0, (N-1) dt],
+    x_2 and x_3 observed every obs_every steps with N(0, 5) noise (NaN
+    elsewhere).  x_0 ~ N((1.5, -1.5, 25), I).  The chain starts from a path
+    simulated from the prior dynamics (another seed), as in that experiment."""
+    rng = np.random.default_rng(seed)
+    par = (10.0, 28.0, 8.0 / 3.0, dt)
+    m0, P0 = np.array([1.5, -1.5, 25.0]), np.eye(3)
+    Q = sigma ** 2 * dt * np.eye(3)
+    x = _simulate_sde(rng, N, m0, P0, DYN_LORENZ63, par, dt, sigma)
+    y = np.full((N, 2), np.nan)
+    obs = np.arange(0, N, obs_every)
+    y[obs] = x[obs][:, 1:] + np.sqrt(5.0) * rng.standard_normal((len(obs), 2))
+    x_start = _simulate_sde(np.random.default_rng(seed + 1000), N, m0, P0, DYN_LORENZ63, par, dt,
+                            sigma)
+    return Workload(f"lorenz63_dt{dt:g}_N{N}", N, m0, P0, None, Q, EMIT_GAUSS_SITE, y,
+                    site=np.array([1, 2], np.int32), scale=np.sqrt(5.0),
+                    delta=LORENZ63_DELTA if delta is None else delta, order=2, seed=seed,
+                    x_true=x, dyn=DYN_LORENZ63, dyn_par=par, extra={"x_start": x_start})
+
+
+def lorenz96(N: int = 2048, d: int = 40, dt: float = 0.005, forcing: float = 8.0,
+             sigma: float = 0.5, n_sites: int = 20, seed: int = 10,
+             delta: Optional[float] = None) -> Workload:
+    """Lorenz-96 SDE (d coordinates on a ring, forcing 8), Euler-Maruyama with
+    step dt and noise sigma dW, every other coordinate observed with Student-t
+    noise (nu = 3, scale 0.5) at every step; second order."""
+    rng = np.random.default_rng(seed)
+    par = (forcing, dt, 0.0, 0.0)
+    m0, P0 = forcing * np.ones(d), np.eye(d)
+    x = _simulate_sde(rng, N, m0, P0, DYN_LORENZ96, par, dt, sigma)
+    site = (np.arange(n_sites) * (d // n_sites)).astype(np.int32)
+    y = x[:, site] + 0.5 * rng.standard_t(3.0, size=(N, n_sites))
+    return Workload(f"lorenz96_d{d}_N{N}", N, m0, P0, None, sigma ** 2 * dt * np.eye(d),
+                    EMIT_STUDENT_T, y, site=site, nu=3.0, scale=0.5,
+                    delta=0.05 if delta is None else delta, order=2, seed=seed, x_true=x,
+                    dyn=DYN_LORENZ96, dyn_par=par)
 
 
 def ragged_poisson_batch(n_chains: int = 512, n_min: int = 128, n_max: int = 8192,

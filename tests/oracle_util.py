@@ -36,11 +36,37 @@ def prior_moments(N, m0, P0, F, Q, b=None):
     return mu.ravel(), S
 
 
+def prior_moments_tv(N, m0, P0, F, Q, b=None):
+    """Mean and covariance of x_{0:N-1} for per-step dynamics x_t = F[t] x_{t-1}
+    + b[t] + N(0, Q) (F [N,d,d], b [N,d]; entry 0 unused), from the linear
+    system (I - Fblk) X = c + e with Fblk holding F[t] at block (t, t-1),
+    c = (m0, b[1], ..., b[N-1]) and e ~ N(0, blkdiag(P0, Q, ..., Q))."""
+    d = len(m0)
+    n = N * d
+    M = np.eye(n)
+    c = np.zeros(n)
+    E = np.zeros((n, n))
+    c[:d] = m0
+    E[:d, :d] = P0
+    for t in range(1, N):
+        M[t * d:(t + 1) * d, (t - 1) * d:t * d] = -np.asarray(F[t], float)
+        if b is not None:
+            c[t * d:(t + 1) * d] = b[t]
+        E[t * d:(t + 1) * d, t * d:(t + 1) * d] = Q
+    Mi = np.linalg.inv(M)
+    S = Mi @ E @ Mi.T
+    return Mi @ c, 0.5 * (S + S.T)
+
+
 def dense_lgssm(N, m0, P0, F, Q, H_list, R_list, y, b=None):
     """log p(y), smoothing means [N,d] and covariances [N,d,d] by conditioning
-    the joint Gaussian of (x_{0:N-1}, y_{0:N-1})."""
+    the joint Gaussian of (x_{0:N-1}, y_{0:N-1}).  F (and b) may be per-step,
+    [N,d,d] ([N,d])."""
     d = len(m0)
-    mu, S = prior_moments(N, m0, P0, F, Q, b)
+    if np.ndim(F) == 3:
+        mu, S = prior_moments_tv(N, m0, P0, F, Q, b)
+    else:
+        mu, S = prior_moments(N, m0, P0, F, Q, b)
     dys = [H.shape[0] for H in H_list]
     Hb = np.zeros((sum(dys), N * d))
     Rb = np.zeros((sum(dys), sum(dys)))

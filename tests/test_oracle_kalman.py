@@ -59,6 +59,37 @@ def test_kf_and_smoother_vs_dense_joint_gaussian(seed, N, dx, dy, per_t):
     np.testing.assert_allclose(out["mf"][-1], ms_ref[-1], atol=1e-10)
 
 
+@pytest.mark.parametrize("seed,N,dx", [(21, 1, 2), (22, 6, 3), (23, 5, 1)])
+def test_kf_sampler_time_varying_dynamics_vs_dense(seed, N, dx):
+    """Per-step F_t, b_t (the linearised dynamics of nonlinear models): log p(y)
+    and smoothing marginals from the filter and smoother, and the pathwise
+    sampler's law: with zero noise it returns the smoothing mean, and the
+    columns of its noise map L (one sample per unit vector) give L L^T = the
+    posterior covariance of the whole path."""
+    rng = np.random.default_rng(seed)
+    m0, P0, _, _, Q, H, R, y = _random_lgssm(rng, N, dx, 2)
+    Fs = np.stack([0.9 * np.linalg.qr(rng.standard_normal((dx, dx)))[0] for _ in range(N)])
+    bs = 0.3 * rng.standard_normal((N, dx))
+    out = oracle.kf(m0, P0, Fs, Q, H, R, y, b=bs)
+    assert out["rc"] == 0
+    ll, ms_ref, Ps_ref, pm, pc = dense_lgssm(N, m0, P0, Fs, Q, [H] * N, [R] * N, y, b=bs)
+    assert abs(out["logZ"] - ll) < 1e-10 * max(1.0, abs(ll))
+    ms, Ps, _, rc = oracle.rts_smooth(Fs, out["mf"], out["Pf"], out["mp"], out["Pp"])
+    assert rc == 0
+    np.testing.assert_allclose(ms, ms_ref, atol=1e-10, rtol=1e-10)
+    np.testing.assert_allclose(Ps, Ps_ref, atol=1e-10, rtol=1e-10)
+    x0, rc = oracle.rts_sample(Fs, out["mf"], out["Pf"], out["mp"], out["Pp"], np.zeros((N, dx)))
+    assert rc == 0
+    np.testing.assert_allclose(x0.ravel(), pm, atol=1e-10)
+    Lmap = np.zeros((N * dx, N * dx))
+    for k in range(N * dx):
+        e = np.zeros(N * dx)
+        e[k] = 1.0
+        xk, _ = oracle.rts_sample(Fs, out["mf"], out["Pf"], out["mp"], out["Pp"], e.reshape(N, dx))
+        Lmap[:, k] = xk.ravel() - x0.ravel()
+    np.testing.assert_allclose(Lmap @ Lmap.T, pc, atol=1e-10)
+
+
 def test_kf_time_varying_H_vs_dense():
     rng = np.random.default_rng(11)
     N, dx, dy = 6, 3, 2
