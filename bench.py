@@ -347,6 +347,36 @@ def bench_lorenz(torch, S, W, K: int, dev, cpu_steps: int) -> dict:
     return out
 
 
+def bench_samplers(torch, S, W, _lib, K: int, dev) -> dict:
+    """The two pathwise samplers on the same filtering moments (latent field,
+    d = 64, T = 4096, pseudo-observations x + N(0, delta/2)): the prefix-sum
+    sampler of the MH step (element build + suffix scan) and the
+    divide-and-conquer sampler (bisection tree of bridges)."""
+    w = W.latent_field()
+    M = S.DeviceModel.from_workload(w, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(70)
+    x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev)
+    om = (x + (0.5 * w.delta) ** 0.5 * torch.randn(x.shape, dtype=torch.float64, device=dev,
+                                                   generator=gen)).contiguous()
+    Om = torch.full_like(om, 0.5 * w.delta)
+    mf, Pf, _, _ = S.aux_filter(M, om, Om)
+    xi = torch.randn((K + 1, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
+    out = {"workload": f"filtering moments of latent_field_d{w.dx}_T{w.N}"}
+    for name, fn in (("prefix_sum", S.rts_sample), ("divide_and_conquer", S.dnc_sample)):
+        ws = S.Workspace(dev)
+        fn(M, mf, Pf, xi[0], ws=ws)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for k in range(K):
+            fn(M, mf, Pf, xi[k + 1], ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms"] = e0.elapsed_time(e1) / K
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +392,7 @@ def main() -> int:
     ap.add_argument("--no-stoch-vol", action="store_true")
     ap.add_argument("--no-spatio-temporal", action="store_true")
     ap.add_argument("--no-lorenz", action="store_true")
+    ap.add_argument("--no-samplers", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
                          "reference for the HBM byte counters)")
@@ -467,6 +498,8 @@ def main() -> int:
     if not args.no_spatio_temporal:
         res["spatio_temporal"] = bench_spatio_temporal(
             torch, S, W, _lib, 100, dev, 0 if args.no_cpu_baseline else 100)
+    if not args.no_samplers:
+        res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev)
     if not args.no_lorenz:
         res["nonlinear"] = bench_lorenz(torch, S, W, 20, dev, 0 if args.no_cpu_baseline else 10)
     if not args.no_cpu_baseline and args.cpu_steps > 0:

@@ -207,6 +207,22 @@ akf_status akf_rts_sample(const akf_model* model, const double* mf, const double
                           size_t ws_bytes, int32_t block, void* stream);
 
 /*
+ * Divide-and-conquer pathwise sampler (App. A, "Divide-and-conquer
+ * strategies"): same inputs and law as akf_rts_sample, drawn top-down on the
+ * bisection tree of [0, T] (T = N-1; [k, m] with m - k >= 2 splits at
+ * l = (k + m) / 2) from the bridges p(x_l | x_k, x_m) (eq. recursive_params)
+ * built bottom-up from the elements of eq. init-dnc and eq. EgL_comb.  Noise
+ * map: x_T = mf_T + chol(Pf_T) xi_T, x_0 = E_{0:T} x_T + g_{0:T} +
+ * chol(L_{0:T}) xi_0, x_l = G x_k + Gamma x_m + w + chol(V) xi_l, so for the
+ * same xi the path differs from akf_rts_sample's (same distribution).
+ * mf [N,dx], Pf [N,dx,dx], xi [N,dx], x [N,dx]; linear dynamics only.
+ */
+size_t akf_dnc_workspace_bytes(const akf_model* model);
+akf_status akf_dnc_sample(const akf_model* model, const double* mf, const double* Pf,
+                          const double* xi, double* x, int32_t* status, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/*
  * RTS smoother (eq. init-dnc, eq. EgL_comb): from the filtering moments
  * mf [N,dx], Pf [N,dx,dx] of the model's dynamics, the smoothing moments
  * ms [N,dx], Ps [N,dx,dx] by a parallel suffix scan of (E, g, L) elements.
@@ -315,7 +331,8 @@ void akf_batch_plan_destroy(akf_batch_plan* plan);
  * up-sweep levels for batched chains), 2 filter down-sweep, 3 filter final,
  * 4 sampler element build, 5 sampler fold, 6 sampler up-sweep, 7 sampler
  * down-sweep, 8 sampler final, 9 factorised scalar filter/sampler,
- * 10 emission linearisation), every launch of that kernel on any stream is
+ * 10 emission and dynamics linearisation, 11 the whole divide-and-conquer
+ * sampler), every launch of that kernel on any stream is
  * bracketed by a pair of hipEvents recorded on the launch stream; at most
  * `capacity` launches are kept.  akf_timing_collect waits for the recorded
  * events and returns the number of launches and their summed duration in

@@ -74,6 +74,9 @@ def _declare(L):
                         _dp, C.c_long, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_rts_sample.restype = C.c_int
     L.or_rts_sample.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp]
+    L.or_dnc_sample.restype = C.c_int
+    L.or_dnc_sample.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, C.c_long, _dp, _dp, _dp, _dp,
+                                _dp]
     L.or_rts_smooth.restype = C.c_int
     L.or_rts_smooth.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_emission.restype = C.c_double
@@ -208,6 +211,19 @@ def rts_sample(F, mf, Pf, mp, Pp, xi):
     x = np.zeros((N, dx))
     rc = lib().or_rts_sample(N, dx, _p(F), dx * dx if F.ndim == 3 else 0, _p(mf), _p(Pf), _p(mp),
                              _p(Pp), _p(xi), _p(x))
+    return x, rc
+
+
+def dnc_sample(F, Q, mf, Pf, xi, b=None):
+    """Divide-and-conquer path sample (same law as rts_sample, its own noise
+    map); F [dx,dx] or per-step [N,dx,dx], b None, [dx] or per-step [N,dx]."""
+    mf, Pf, xi, F, Q = map(_f64, (mf, Pf, xi, F, Q))
+    N, dx = mf.shape
+    bb = None if b is None else _f64(b)
+    x = np.zeros((N, dx))
+    rc = lib().or_dnc_sample(N, dx, _p(F), dx * dx if F.ndim == 3 else 0, _p(bb),
+                             dx if (bb is not None and bb.ndim == 2) else 0, _p(Q), _p(mf), _p(Pf),
+                             _p(xi), _p(x))
     return x, rc
 
 

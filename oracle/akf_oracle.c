@@ -14,6 +14,8 @@
  *                    (App. A.1, Alg. "Kalman filter"; eq. marginal-likelihood).
  *   or_rts_sample    Rauch-Tung-Striebel *sampler* with a fixed noise map
  *                    (App. A.1, Alg. "Rauch-Tung-Striebel sampler", eq. backward).
+ *   or_dnc_sample    divide-and-conquer pathwise sampler on the bisection tree
+ *                    (App. A, "Divide-and-conquer strategies").
  *   or_rts_smooth    RTS smoother marginals and the backward gains, used for the
  *                    Fisher-identity score and moment checks.
  *   or_emission      log h_t, its gradient v_t and Hessian Lambda_t for the
@@ -310,6 +312,201 @@ int or_rts_sample(int N, int dx, const double* F, long F_stride, const double* m
     for (int i = 0; i < n; ++i) x[t * n + i] = mf[t * n + i] + e[i] + z[i];
   }
   free(G); free(Sig); free(L); free(d); free(work);
+  return rc;
+}
+
+/*
+ * Divide-and-conquer pathwise sampler (App. A, "Divide-and-conquer
+ * strategies"): the same law as or_rts_sample, drawn top-down on the bisection
+ * tree of [0, T] (T = N-1; an interval [k, m] with m - k >= 2 splits at
+ * l = (k + m) / 2).  Elements (E, g, L)_{k:m} of p(x_k | x_m) start from
+ * eq. init-dnc on [t, t+1] (F_{t+1}, b_{t+1} the transition into t+1) and
+ * compose by eq. EgL_comb; the bridge p(x_l | x_k, x_m) has the parameters of
+ * eq. recursive_params.  Noise map: x_T = m^f_T + chol(P^f_T) xi_T,
+ * x_0 = E_{0:T} x_T + g_{0:T} + chol(L_{0:T}) xi_0, and each midpoint
+ * x_l = G x_k + Gamma x_m + w + chol(V) xi_l (chol = lower factor, positive
+ * diagonal).  F [dx,dx] with F_stride = 0, or per step; b NULL, [dx] with
+ * b_stride = 0, or per step.  Returns 0, or 1 on a non-PD matrix.
+ */
+typedef struct {
+  int n;
+  const double *F, *b, *Q, *mf, *Pf;
+  long F_stride, b_stride;
+  const double* xi;
+  double* x;
+} dnc_ctx;
+
+/* (E, g, L) of [t, t+1] (eq. init-dnc) */
+static int dnc_leaf(const dnc_ctx* c, int t, double* E, double* g, double* L) {
+  const int n = c->n;
+  const double* F = c->F + (long)(t + 1) * c->F_stride;
+  const double* Pf = c->Pf + (long)t * n * n;
+  double* Pp = malloc(sizeof(double) * n * n);
+  double* FP = malloc(sizeof(double) * n * n);
+  double* Lp = malloc(sizeof(double) * n * n);
+  double* T = malloc(sizeof(double) * n * n);
+  double* col = malloc(sizeof(double) * n);
+  double* mp = malloc(sizeof(double) * n);
+  int rc = 0;
+  mm(n, n, n, F, Pf, FP);           /* F P^f */
+  mm_nt(n, n, n, FP, F, Pp);        /* F P^f F' */
+  for (int i = 0; i < n * n; ++i) Pp[i] += c->Q[i];
+  symmetrise(n, Pp);
+  if (chol(n, Pp, Lp)) rc = 1;
+  else {
+    memcpy(T, FP, sizeof(double) * n * n);
+    chol_solve(n, n, Lp, T, col);   /* T = Pp^{-1} F P^f = E' */
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) E[i * n + j] = T[j * n + i];
+    mv(n, n, F, c->mf + (long)t * n, mp);
+    if (c->b)
+      for (int i = 0; i < n; ++i) mp[i] += c->b[(long)(t + 1) * c->b_stride + i];
+    mv(n, n, E, mp, col);
+    for (int i = 0; i < n; ++i) g[i] = c->mf[(long)t * n + i] - col[i];
+    mm(n, n, n, E, FP, T);          /* E F P^f */
+    for (int i = 0; i < n * n; ++i) L[i] = Pf[i] - T[i];
+    symmetrise(n, L);
+  }
+  free(Pp); free(FP); free(Lp); free(T); free(col); free(mp);
+  return rc;
+}
+
+/*
+ * (E, g, L)_{k:m} of the interval; for m - k >= 2 also samples the subtree
+ * below it once x_k and x_m are known (bridges are formed on the way down,
+ * samples drawn after both endpoints are fixed by the caller).  Here: builds
+ * the element only; dnc_down draws.
+ */
+static int dnc_elem(const dnc_ctx* c, int k, int m, double* E, double* g, double* L) {
+  const int n = c->n;
+  if (m - k == 1) return dnc_leaf(c, k, E, g, L);
+  const int l = (k + m) / 2;
+  double* E1 = malloc(sizeof(double) * n * n);
+  double* g1 = malloc(sizeof(double) * n);
+  double* L1 = malloc(sizeof(double) * n * n);
+  double* E2 = malloc(sizeof(double) * n * n);
+  double* g2 = malloc(sizeof(double) * n);
+  double* L2 = malloc(sizeof(double) * n * n);
+  double* T = malloc(sizeof(double) * n * n);
+  int rc = dnc_elem(c, k, l, E1, g1, L1) || dnc_elem(c, l, m, E2, g2, L2);
+  if (!rc) {
+    /* eq. EgL_comb with [k,l] on the left and [l,m] on the right */
+    mm(n, n, n, E1, E2, E);
+    mv(n, n, E1, g2, g);
+    for (int i = 0; i < n; ++i) g[i] += g1[i];
+    mm(n, n, n, E1, L2, T);
+    mm_nt(n, n, n, T, E1, L);
+    for (int i = 0; i < n * n; ++i) L[i] += L1[i];
+    symmetrise(n, L);
+  }
+  free(E1); free(g1); free(L1); free(E2); free(g2); free(L2); free(T);
+  return rc;
+}
+
+/* draws x_l for the midpoint of [k, m] from p(x_l | x_k, x_m), then recurses */
+static int dnc_down(const dnc_ctx* c, int k, int m) {
+  const int n = c->n;
+  if (m - k < 2) return 0;
+  const int l = (k + m) / 2;
+  double* E1 = malloc(sizeof(double) * n * n);
+  double* g1 = malloc(sizeof(double) * n);
+  double* L1 = malloc(sizeof(double) * n * n);
+  double* E2 = malloc(sizeof(double) * n * n);
+  double* g2 = malloc(sizeof(double) * n);
+  double* L2 = malloc(sizeof(double) * n * n);
+  double* E = malloc(sizeof(double) * n * n);
+  double* g = malloc(sizeof(double) * n);
+  double* L = malloc(sizeof(double) * n * n);
+  double* G = malloc(sizeof(double) * n * n);
+  double* T = malloc(sizeof(double) * n * n);
+  double* V = malloc(sizeof(double) * n * n);
+  double* Lc = malloc(sizeof(double) * n * n);
+  double* col = malloc(sizeof(double) * n);
+  double* v = malloc(sizeof(double) * n);
+  int rc = dnc_elem(c, k, l, E1, g1, L1) || dnc_elem(c, l, m, E2, g2, L2);
+  if (!rc) {
+    mm(n, n, n, E1, E2, E);
+    mv(n, n, E1, g2, g);
+    for (int i = 0; i < n; ++i) g[i] += g1[i];
+    mm(n, n, n, E1, L2, T);
+    mm_nt(n, n, n, T, E1, L);
+    for (int i = 0; i < n * n; ++i) L[i] += L1[i];
+    symmetrise(n, L);
+    /* eq. recursive_params: G = L2 E1' L^{-1} (G' = L^{-1} E1 L2) */
+    if (chol(n, L, Lc)) rc = 1;
+  }
+  if (!rc) {
+    mm(n, n, n, E1, L2, T);       /* E1 L2 */
+    chol_solve(n, n, Lc, T, col); /* T = L^{-1} E1 L2 = G' */
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) G[i * n + j] = T[j * n + i];
+    /* mean: G x_k + (E2 - G E) x_m + (g2 - G g) */
+    const double* xk = c->x + (long)k * n;
+    const double* xm = c->x + (long)m * n;
+    double* xl = c->x + (long)l * n;
+    for (int i = 0; i < n; ++i) {
+      double s = g2[i];
+      for (int j = 0; j < n; ++j) s += E2[i * n + j] * xm[j];
+      v[i] = s;
+    }
+    for (int i = 0; i < n; ++i) col[i] = xk[i] - g[i];
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s += E[i * n + j] * xm[j];
+      col[i] -= s;                 /* x_k - E x_m - g */
+    }
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s += G[i * n + j] * col[j];
+      v[i] += s;
+    }
+    /* V = L2 - G L G' = L2 - G E1 L2 */
+    mm(n, n, n, E1, L2, T);
+    double* GT = malloc(sizeof(double) * n * n);
+    mm(n, n, n, G, T, GT);
+    for (int i = 0; i < n * n; ++i) V[i] = L2[i] - GT[i];
+    free(GT);
+    symmetrise(n, V);
+    if (chol(n, V, Lc)) rc = 1;
+    else {
+      mv(n, n, Lc, c->xi + (long)l * n, col);
+      for (int i = 0; i < n; ++i) xl[i] = v[i] + col[i];
+    }
+  }
+  free(E1); free(g1); free(L1); free(E2); free(g2); free(L2); free(E); free(g); free(L); free(G);
+  free(T); free(V); free(Lc); free(col); free(v);
+  if (rc) return rc;
+  return dnc_down(c, k, l) || dnc_down(c, l, m);
+}
+
+int or_dnc_sample(int N, int dx, const double* F, long F_stride, const double* b, long b_stride,
+                  const double* Q, const double* mf, const double* Pf, const double* xi,
+                  double* x) {
+  const int n = dx, T = N - 1;
+  dnc_ctx c = {n, F, b, Q, mf, Pf, F_stride, b_stride, xi, x};
+  double* L = malloc(sizeof(double) * n * n);
+  double* E = malloc(sizeof(double) * n * n);
+  double* g = malloc(sizeof(double) * n);
+  double* Lk = malloc(sizeof(double) * n * n);
+  double* d = malloc(sizeof(double) * n);
+  int rc = 0;
+  if (chol(n, Pf + (long)T * n * n, L)) rc = 1;
+  else {
+    mv(n, n, L, xi + (long)T * n, d);
+    for (int i = 0; i < n; ++i) x[(long)T * n + i] = mf[(long)T * n + i] + d[i];
+  }
+  if (!rc && T >= 1) {
+    rc = dnc_elem(&c, 0, T, E, g, Lk);
+    if (!rc && chol(n, Lk, L)) rc = 1;
+    if (!rc) {
+      mv(n, n, E, x + (long)T * n, d);
+      for (int i = 0; i < n; ++i) x[i] = d[i] + g[i];
+      mv(n, n, L, xi, d);
+      for (int i = 0; i < n; ++i) x[i] += d[i];
+      rc = dnc_down(&c, 0, T);
+    }
+  }
+  free(L); free(E); free(g); free(Lk); free(d);
   return rc;
 }
 

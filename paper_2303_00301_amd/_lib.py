@@ -70,6 +70,8 @@ SIGNATURES = {
     "akf_aux_filter": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
     "akf_sampler_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_rts_sample": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "akf_dnc_workspace_bytes": (_sz, [_MP]),
+    "akf_dnc_sample": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "akf_smoother_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_smoother": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
     "akf_lgssm_workspace_bytes": (_sz, [C.c_void_p, _i32]),
@@ -90,7 +92,7 @@ SIGNATURES = {
 # kernel families of akf_timing_enable
 FAMILIES = {"filter_fold": 0, "filter_up": 1, "filter_down": 2, "filter_final": 3,
             "samp_build": 4, "samp_fold": 5, "samp_up": 6, "samp_down": 7, "samp_final": 8,
-            "fact_scan": 9, "lin": 10}
+            "fact_scan": 9, "lin": 10, "dnc": 11}
 
 _lib = None
 

@@ -562,6 +562,55 @@ akf_status akf_mh_run_factorised(const akf_model* model, const double* y, double
   return AKF_OK;
 }
 
+size_t akf_dnc_workspace_bytes(const akf_model* model) {
+  if (check_model(model, false) != AKF_OK || check_linear(model, "akf_dnc_sample") != AKF_OK)
+    return 0;
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, 0, 0, LAYOUT_DNC);
+  return Lo.total;
+}
+
+akf_status akf_dnc_sample(const akf_model* model, const double* mf, const double* Pf,
+                          const double* xi, double* x, int32_t* status, void* ws,
+                          size_t ws_bytes, void* stream) {
+  akf_status s;
+  if ((s = check_model(model, false)) != AKF_OK) return s;
+  if ((s = check_linear(model, "akf_dnc_sample")) != AKF_OK) return s;
+  if (!mf || !Pf || !xi || !x) return fail(AKF_ERR_INVALID, "mf, Pf, xi and x must be non-NULL");
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, 0, 0, LAYOUT_DNC);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  int* dstat = at<int>(ws, Lo.status);
+  if ((s = hip_check(launch_step_init(dstat, nullptr, nullptr, 0, st), "init launch")) != AKF_OK)
+    return s;
+  DncArgs A{};
+  A.T = model->N - 1;
+  A.mf = mf;
+  A.Pf = Pf;
+  A.ldm = model->dx;
+  A.xi = xi;
+  A.x = x;
+  A.Elf = at<double>(ws, Lo.Elf);
+  A.glf = at<double>(ws, Lo.glf);
+  A.Llf = at<double>(ws, Lo.Llf);
+  A.Eno = at<double>(ws, Lo.Eno);
+  A.gno = at<double>(ws, Lo.gno);
+  A.Lno = at<double>(ws, Lo.Lno);
+  A.Gb = at<double>(ws, Lo.Gb);
+  A.Gam = at<double>(ws, Lo.Gam);
+  A.wb = at<double>(ws, Lo.wb);
+  A.Vc = at<double>(ws, Lo.Vc);
+  A.status = dstat;
+  if ((s = hip_check(launch_dnc_any(Lo.D, to_kmodel(model), A, st), "divide-and-conquer launch")) !=
+      AKF_OK)
+    return s;
+  if (status)
+    return hip_check(hipMemcpyAsync(status, dstat, sizeof(int), hipMemcpyDeviceToDevice, st),
+                     "status copy");
+  return AKF_OK;
+}
+
 size_t akf_filter_workspace_bytes(const akf_model* model, int32_t block) {
   if (check_model(model, false) != AKF_OK || check_linear(model, "akf_aux_filter") != AKF_OK)
     return 0;

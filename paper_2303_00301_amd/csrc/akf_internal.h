@@ -131,6 +131,21 @@ struct DynArgs {
   double* part;        // [n_part] partial sums of the mismatch terms
 };
 
+// Divide-and-conquer sampler: filtering moments in, path out; tree storage in
+// the workspace (D-padded), leaves by t, nodes and bridges by midpoint.
+struct DncArgs {
+  int T;                       // N - 1
+  const double *mf, *Pf;       // [N*ldm], [N*ldm*ldm]
+  int ldm;
+  const double* xi;            // [N*d]
+  double* x;                   // [N*d]
+  const double *Ft, *bt;       // per-step dynamics or nullptr
+  double *Elf, *glf, *Llf;     // leaves [t, t+1]
+  double *Eno, *gno, *Lno;     // node elements [k, m]
+  double *Gb, *Gam, *wb, *Vc;  // bridges G, Gamma, w, chol(V)
+  int* status;
+};
+
 // Auxiliary LGSSM of a factorising prior: dx scalar models, one per
 // coordinate.  The model's P0, F and Q hold diagonals [d].
 struct FactArgs {
@@ -235,7 +250,7 @@ struct BatchLaunch {
 enum {
   FAM_FILTER_FOLD = 0, FAM_FILTER_UP = 1, FAM_FILTER_DOWN = 2, FAM_FILTER_FINAL = 3,
   FAM_SAMP_BUILD = 4, FAM_SAMP_FOLD = 5, FAM_SAMP_UP = 6, FAM_SAMP_DOWN = 7, FAM_SAMP_FINAL = 8,
-  FAM_FACT = 9, FAM_LIN = 10, FAM_COUNT = 11
+  FAM_FACT = 9, FAM_LIN = 10, FAM_DNC = 11, FAM_COUNT = 12
 };
 // Called by the launchers before (begin = 1) and after (begin = 0) each launch.
 void timing_mark(int family, int begin, hipStream_t st);
@@ -266,6 +281,8 @@ hipError_t launch_adj_finish_any(int D, const KModel& M, LgArgs G, int nblk, con
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 hipError_t launch_fact_scan(const KModel& M, FactArgs P, hipStream_t st);
 hipError_t launch_qinv(const KModel& M, double* Qinv, hipStream_t st);
+hipError_t launch_dnc_any(int D, const KModel& M, DncArgs A, hipStream_t st);
+int dnc_depth(int T);
 hipError_t launch_dyn_lin(const KModel& M, DynArgs A, int* n_part, hipStream_t st);
 
 // Batched launches for one D class.  `step` is the device step counter.

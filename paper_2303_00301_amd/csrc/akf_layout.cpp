@@ -116,6 +116,22 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     Lo.total = off;
     return;
   }
+  if (kind == LAYOUT_DNC) {
+    const size_t mat = (size_t)N * D * D * dbl, vec = (size_t)N * D * dbl;
+    Lo.Elf = take(mat);
+    Lo.glf = take(vec);
+    Lo.Llf = take(mat);
+    Lo.Eno = take(mat);
+    Lo.gno = take(vec);
+    Lo.Lno = take(mat);
+    Lo.Gb = take(mat);
+    Lo.Gam = take(mat);
+    Lo.wb = take(vec);
+    Lo.Vc = take(mat);
+    Lo.status = take(sizeof(int));
+    Lo.total = off;
+    return;
+  }
   if (kind == LAYOUT_LGSSM) {
     Lo.Qd = take((size_t)d * d * dbl);
     Lo.Rd = take((size_t)dy * dy * dbl);

@@ -33,6 +33,8 @@ struct Layout {
   // nonlinear dynamics: per-step F_t, b_t, Q^{-1}, mismatch partial sums
   size_t Ft = 0, bt = 0, Qinv = 0, pdyn = 0;
   int n_part_dyn = 0;
+  // divide-and-conquer sampler tree
+  size_t Elf = 0, glf = 0, Llf = 0, Eno = 0, gno = 0, Lno = 0, Gb = 0, Gam = 0, wb = 0, Vc = 0;
   // (E, g, L) scan, smoother and adjoint
   size_t g = 0, Lm = 0, Pbar = 0, mbar = 0, part = 0, Qd = 0, Rd = 0, llv = 0;
   size_t eagg[kMaxLevels + 1] = {0};
@@ -41,7 +43,7 @@ struct Layout {
 };
 
 enum LayoutKind { LAYOUT_STEP = 0, LAYOUT_FILTER = 1, LAYOUT_SAMPLER = 2, LAYOUT_SMOOTH = 3,
-                  LAYOUT_LGSSM = 4, LAYOUT_FACT = 5 };
+                  LAYOUT_LGSSM = 4, LAYOUT_FACT = 5, LAYOUT_DNC = 6 };
 
 
 template <class T>

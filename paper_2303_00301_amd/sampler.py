@@ -304,6 +304,26 @@ def rts_sample(model: DeviceModel, mf, Pf, xi, block: int = 0, ws: Optional[Work
     return x, st
 
 
+def dnc_sample(model: DeviceModel, mf, Pf, xi, ws: Optional[Workspace] = None):
+    """Divide-and-conquer path sample from filtering moments (same law as
+    rts_sample, its own noise map).  Returns (x [N,dx], status [1])."""
+    lib = _lib.load()
+    dev = model.device
+    N, dx = model.N, model.dx
+    _check_f64("mf", mf, (N, dx))
+    _check_f64("Pf", Pf, (N, dx, dx))
+    _check_f64("xi", xi, (N, dx))
+    x = torch.empty((N, dx), dtype=torch.float64, device=dev)
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    ms = model.cstruct()
+    need = _need(lib.akf_dnc_workspace_bytes(C.byref(ms)), "akf_dnc_workspace_bytes")
+    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+    rc = lib.akf_dnc_sample(C.byref(ms), _ptr(mf), _ptr(Pf), _ptr(xi), _ptr(x), _ptr(st), wsp,
+                            wsb, _stream(dev))
+    _lib.check(rc, "akf_dnc_sample")
+    return x, st
+
+
 def smoother(model: DeviceModel, mf, Pf, block: int = 0, ws: Optional[Workspace] = None):
     """RTS smoothing moments from filtering moments (parallel (E, g, L) suffix scan).
     Returns (ms [N,dx], Ps [N,dx,dx], status [1])."""

@@ -90,6 +90,40 @@ def test_kf_sampler_time_varying_dynamics_vs_dense(seed, N, dx):
     np.testing.assert_allclose(Lmap @ Lmap.T, pc, atol=1e-10)
 
 
+@pytest.mark.parametrize("seed,N,dx,tv", [(31, 1, 2, False), (32, 2, 2, True), (33, 3, 1, False),
+                                          (34, 6, 3, True), (35, 9, 2, False), (36, 12, 2, True)])
+def test_dnc_sampler_law_vs_dense(seed, N, dx, tv):
+    """Divide-and-conquer sampler (App. A, divide-and-conquer strategies): with
+    zero noise it returns the posterior mean, and its noise map L satisfies
+    L L^T = the posterior covariance of the whole path (dense conditioning), so
+    it draws from the same law as the RTS sampler, on bisection trees of
+    several shapes (N = 1, 2, 3, 6, 9, 12)."""
+    rng = np.random.default_rng(seed)
+    m0, P0, F, b, Q, H, R, y = _random_lgssm(rng, N, dx, 2)
+    if tv:
+        F = np.stack([0.9 * np.linalg.qr(rng.standard_normal((dx, dx)))[0] for _ in range(N)])
+        b = 0.3 * rng.standard_normal((N, dx))
+    out = oracle.kf(m0, P0, F, Q, H, R, y, b=b)
+    assert out["rc"] == 0
+    _, _, _, pm, pc = dense_lgssm(N, m0, P0, F, Q, [H] * N, [R] * N, y, b=b)
+    x0, rc = oracle.dnc_sample(F, Q, out["mf"], out["Pf"], np.zeros((N, dx)), b=b)
+    assert rc == 0
+    np.testing.assert_allclose(x0.ravel(), pm, atol=1e-10)
+    Lmap = np.zeros((N * dx, N * dx))
+    for k in range(N * dx):
+        e = np.zeros(N * dx)
+        e[k] = 1.0
+        xk, _ = oracle.dnc_sample(F, Q, out["mf"], out["Pf"], e.reshape(N, dx), b=b)
+        Lmap[:, k] = xk.ravel() - x0.ravel()
+    np.testing.assert_allclose(Lmap @ Lmap.T, pc, atol=1e-10)
+    # a different noise map from the RTS sampler: the paths differ for the same normals
+    if N >= 3:
+        xi = rng.standard_normal((N, dx))
+        xa, _ = oracle.dnc_sample(F, Q, out["mf"], out["Pf"], xi, b=b)
+        xb, _ = oracle.rts_sample(F, out["mf"], out["Pf"], out["mp"], out["Pp"], xi)
+        assert np.abs(xa - xb).max() > 1e-6
+
+
 def test_kf_time_varying_H_vs_dense():
     rng = np.random.default_rng(11)
     N, dx, dy = 6, 3, 2
