@@ -22,7 +22,9 @@ The operator integrates out the shared intermediate state; with Z = I + C_i J_j:
     eta = A_i^T Z^{-T} (eta_j - J_j b_i) + eta_i
     J  = A_i^T Z^{-T} J_j A_i + J_i
 (i is the earlier element).  The prefix up to t has A = 0, J = 0, eta = 0,
-b = m^f_t, C = P^f_t.
+b = m^f_t, C = P^f_t.  Carrying the normaliser log c of p(y | x_prev) with each
+element (filter_log_norms, filter_combine_log_norm) makes the prefix's log c the
+log marginal likelihood log p(y_{0:t}), with no second pass.
 
 Sampling element (eq. backward, eq. EgL_comb):  E_t = P^f_t F^T (P^p_{t+1})^{-1},
 g_t = m^f_t - E_t m^p_{t+1}, L_t = P^f_t - E_t F P^f_t; terminal (0, m^f, P^f).
@@ -80,6 +82,41 @@ def filter_combine(ei, ej):
     eta = Ai.T @ np.linalg.solve(ZtT, ej_ - Jj @ bi) + ei_
     J = Ai.T @ np.linalg.solve(ZtT, Jj) @ Ai + Ji
     return (A, bb, 0.5 * (Cm + Cm.T), eta, 0.5 * (J + J.T))
+
+
+def filter_log_norms(m0, P0, F, b, Q, H, R, y):
+    """log c_t of each filtering element: p(y_t | x_{t-1}) = exp(log c_t + eta^T x
+    - 1/2 x^T J x), so log c_t = log N(y_t; H b, S_t) with S_t = H Q H^T + R_t
+    (t >= 1, the density at x_{t-1} = 0), and log c_0 = log N(y_0; H m0, H P0 H^T + R_0)."""
+    N = y.shape[0]
+    dx = len(m0)
+    b = np.zeros(dx) if b is None else np.asarray(b, float)
+    R = np.asarray(R, float)
+    out = []
+    for t in range(N):
+        Rt = R[t] if R.ndim == 3 else R
+        P, mu = (P0, m0) if t == 0 else (Q, b)
+        S = H @ P @ H.T + Rt
+        r = y[t] - H @ mu
+        _, logdet = np.linalg.slogdet(S)
+        out.append(-0.5 * (len(r) * np.log(2 * np.pi) + logdet + r @ np.linalg.solve(S, r)))
+    return out
+
+
+def filter_combine_log_norm(ei, lci, ej, lcj):
+    """log c of e_i (x) e_j: the x-independent part of
+    int N(x; A_i x_p + b_i, C_i) exp(log c_j + eta_j^T x - 1/2 x^T J_j x) dx,
+    a Gaussian integral: with Z = I + C_i J_j and v = eta_j - J_j b_i,
+    log c_i + log c_j - 1/2 log det Z + eta_j^T b_i - 1/2 b_i^T J_j b_i
+    + 1/2 v^T Z^{-1} C_i v."""
+    _, bi, Ci, _, _ = ei
+    _, _, _, ej_, Jj = ej
+    d = Ci.shape[0]
+    Z = np.eye(d) + Ci @ Jj
+    v = ej_ - Jj @ bi
+    _, logdet = np.linalg.slogdet(Z)
+    return (lci + lcj - 0.5 * logdet + ej_ @ bi - 0.5 * bi @ Jj @ bi
+            + 0.5 * v @ np.linalg.solve(Z, Ci @ v))
 
 
 def sampling_elements(F, mf, Pf, mp, Pp):

@@ -87,10 +87,14 @@ akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, cons
     if ((s = hip_check(launch_dyn_lin(M, Dy, &n_part_dyn, st), "dynamics launch")) != AKF_OK)
       return s;
   }
-  if ((s = run_filter(Lo, M, ws, A.om2, A.Om2, Omd, nullptr, nullptr, Lo.D, A.ell2, status,
-                      ST_REV_NOT_PD, st, nullptr, nullptr, nullptr, 0, Ft, bt)) != AKF_OK)
+  // the reverse proposal needs log Z(x*) only: element normalisers reduced up
+  // the block tree, no re-scan
+  const double* lz_rev = nullptr;
+  if ((s = run_filter_logz(Lo, M, ws, A.om2, A.Om2, Omd, status, ST_REV_NOT_PD, st, Ft, bt,
+                           &lz_rev)) != AKF_OK)
     return s;
   FinalArgs F{};
+  F.lz_rev = lz_rev;
   F.part_dyn = Dy.part;
   F.n_part_dyn = n_part_dyn;
   F.unif = unif;

@@ -24,11 +24,14 @@ struct KModel {
   double dyn_par[4];
 };
 
-// Filter element (A, b, C, eta, J), padded to D.
+// Filter element (A, b, C, eta, J), padded to D, and lc = log c, the
+// normaliser of p(omega | x_prev) = exp(lc + eta' x - x' J x / 2); the prefix
+// from t = 0 carries log p(omega_{0:t}).
 template <int D>
 struct ElemLayout {
   static constexpr int A = 0, C = D * D, J = 2 * D * D, b = 3 * D * D, eta = 3 * D * D + D;
-  static constexpr int SIZE = 3 * D * D + 2 * D;
+  static constexpr int lc = 3 * D * D + 2 * D;
+  static constexpr int SIZE = 3 * D * D + 2 * D + 2;
 };
 
 // Filtering moments entering a tree node; flag != 0 marks the identity prefix.
@@ -160,6 +163,7 @@ struct FactArgs {
 
 struct FinalArgs {
   int n_ell;  // entries of ell/ell2 summed into log Z (0 = N)
+  const double* lz_rev;  // log Z of the reverse proposal as one value, or nullptr (sum ell2)
   const double* part_dyn;  // dynamics mismatch partial sums (n_part_dyn), or nullptr
   int n_part_dyn;
   const double* unif;
@@ -259,6 +263,8 @@ hipError_t launch_filter_scan_any(int D, const KModel& M, FilterArgs P, const Hs
                                   int n_levels, hipStream_t st);
 hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, TreeArgs* down,
                              int n_levels, hipStream_t st);
+hipError_t launch_filter_logz_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, int n_levels,
+                                  hipStream_t st);
 hipError_t launch_sampler_any(int D, const KModel& M, SampArgs S, TreeArgs* up, TreeArgs* down,
                               int n_levels, hipStream_t st);
 hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStream_t st);

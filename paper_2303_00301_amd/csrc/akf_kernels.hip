@@ -559,9 +559,15 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
   double* vw = vmu + D;                    // omega - mu  (GH: y - H mu)
   double* vs = vw + D;                     // S^{-1} w
   double* vom = vs + D;                    // diagonal Omega_t
+  double* red = vom + D;
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * P.B, s1 = min(M.N, s0 + P.B);
   constexpr bool first = FIRST;
+  // lc: log of the normaliser, the sum over the block's steps of the
+  // x_prev-independent part of log N(omega_t; T x_prev + mu, S),
+  // -(dobs log 2 pi + log det S + w' S^{-1} w) / 2; log det S and this thread's
+  // share of w' S^{-1} w are accumulated, the team sum is taken once at the end
+  double ld_sum = 0.0, q_part = 0.0;
   const int dobs = GH ? P.dyo : d;
   if (!P.Ft) lds_load_mat<D>(sF, M.F, d);
   if (GH) lds_load_rect<D>(sH, P.Ho, P.dyo, d);
@@ -626,6 +632,8 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       gemm<D, false, false, false>(Cc, B2, B1);  // S^{-1} Pp
       AKF_RM_FOR(D, q, r, i, j) Cc.t[q][r] *= vom[i];
       matvec<D, false>(vs, B2, vw);  // S^{-1} w
+      ld_sum += logdet;
+      if (tid < D) q_part += vw[tid] * vs[tid];
       if (!first) {
         gemm<D, false, false, false>(R1, B2, B3);  // S^{-1} T
         rm_stage<D>(R1, B1);
@@ -667,6 +675,8 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
     team_sync();
     gemm<D, false, false, false>(R1, B3, B1);  // S^{-1} Mo
     matvec<D, false>(vs, B3, vw);              // S^{-1} w
+    ld_sum += logdet;
+    if (tid < D) q_part += vw[tid] * vs[tid];
     team_sync();
     rm_stage<D>(R1, B2);
     team_sync();
@@ -710,6 +720,8 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
     out[ElemLayout<D>::b + tid] = vb[tid];
     out[ElemLayout<D>::eta + tid] = veta[tid];
   }
+  const double q = team_sum<D>(q_part, red);
+  if (tid == 0) out[ElemLayout<D>::lc] = -0.5 * ((s1 - s0) * dobs * LOG2PI + ld_sum + q);
 }
 
 template <int D, int OBS>
@@ -735,8 +747,10 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 //   eta = A_i' (c - J_j M c) + eta_i
 //   J   = A_i' J_j A_i - (J_j A_i)' M (J_j A_i) + J_i = Z' J_j A_i + J_i,
 //         Z = A_i - M J_j A_i
+//   lc  = lc_i + lc_j - log det W / 2 + b_i' (eta_j + c) / 2 + c' M c / 2
 // (the filtering-element combine of App. A, "Prefix-sums and the parallel
-// Kalman filter").
+// Kalman filter"; lc is the constant of the Gaussian integral over the shared
+// state, with log det W = log det (I + C_i J_j)).
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ void filter_combine(const KModel& M, const double* __restrict__ ei,
@@ -754,6 +768,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   double* vc = vbi + D;
   double* vw = vc + D;
   double* vk = vw + D;
+  double* red = vk + D;
   const int tid = threadIdx.x, d = M.d;
   bool ok = true;
   double ld;
@@ -777,6 +792,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   gemm<D, true, false, false>(R2, S0, S2);  // L' J_j L
   AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
   ok = spd_inv<D>(R2, d, S3, &ld) && ok;  // W^{-1}
+  const double ldW = ld;
   rm_stage<D>(R2, S2);
   team_sync();
   gemm<D, false, false, false>(R3, S0, S2);  // L W^{-1}
@@ -789,6 +805,11 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   if (tid < D) vc[tid] = ej[EL::eta + tid] - vc[tid];
   team_sync();
   matvec<D, false>(vw, S2, vc);     // w = M c
+  const double lc = ei[EL::lc] + ej[EL::lc] - 0.5 * ldW +
+                    0.5 * team_sum<D>(tid < D ? vbi[tid] * (ej[EL::eta + tid] + vc[tid]) +
+                                                    vc[tid] * vw[tid]
+                                              : 0.0,
+                                      red);
   rm_stage<D>(Ai, S0);  // S0 = A_i
   team_sync();
   matvec<D, false>(vk, S1, vw);              // J_j w
@@ -819,6 +840,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   gemm<D, false, true, false>(R3, S3, S0);  // A_j M A_j'
   rm_axpy<D>(R3, 1.0, Cj);
   if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
+  if (tid == 0) out[EL::lc] = lc;
   rm_symmetrise<D>(R3, S1);
   rm_store<D>(R3, out + EL::C, D, D);
   if (!ok && tid == 0) flag_status(status, fail_bit);
@@ -851,12 +873,14 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) 
 // ---------------------------------------------------------------------------
 // Moment pair (m, P) (x) element el -> (m', P'), written to mout / Pout:
 // with P = L L', W = I + L' J L and M = L W^{-1} L' = (P^{-1} + J)^{-1},
-//   m' = A (m + M (eta - J m)) + b,   P' = A M A' + C.
+//   m' = A (m + M (eta - J m)) + b,   P' = A M A' + C,
+// and, when lcout is given, the normaliser as in filter_combine with b_i = m.
 template <int D>
 __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pin,
                                                const double* min_, const double* el,
                                                double* Pout, double* mout, int* status,
-                                               int fail_bit) {
+                                               int fail_bit, const double* lcin = nullptr,
+                                               double* lcout = nullptr) {
   using C = Cfg<D>;
   using EL = ElemLayout<D>;
   extern __shared__ double lds[];
@@ -868,6 +892,7 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
   double* vc = vm + D;
   double* vz = vc + D;
   double* vw = vz + D;
+  double* red = vw + D;
   const int tid = threadIdx.x, d = M.d;
   bool ok = true;
   double ld;
@@ -886,6 +911,7 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
   gemm<D, true, false, false>(R2, S0, S2);  // L' J L
   AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
   ok = spd_inv<D>(R2, d, S3, &ld) && ok;  // W^{-1}
+  const double ldW = ld;
   rm_stage<D>(R2, S2);
   team_sync();
   gemm<D, false, false, false>(R1, S0, S2);  // L W^{-1}
@@ -899,6 +925,11 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
   rm_stage<D>(Ae, S3);  // S3 = A
   team_sync();
   matvec<D, false>(vw, S2, vc);              // M (eta - J m)
+  if (lcout) {
+    const double q = team_sum<D>(
+        tid < D ? vm[tid] * (el[EL::eta + tid] + vc[tid]) + vc[tid] * vw[tid] : 0.0, red);
+    if (tid == 0) *lcout = *lcin + el[EL::lc] - 0.5 * ldW + 0.5 * q;
+  }
   gemm<D, false, false, false>(R1, S3, S2);  // A M
   rm_stage<D>(R1, S0);
   team_sync();
@@ -956,7 +987,7 @@ __device__ __forceinline__ void filter_hs_body(const KModel& M, const HsArgs& H,
   const double* ei = H.src + (int64_t)(k - H.s) * EL::SIZE;
   if (k < 2 * H.s) {
     moment_combine<D>(M, ei + EL::C, ei + EL::b, ej, out + EL::C, out + EL::b, H.status,
-                      H.fail_bit);
+                      H.fail_bit, ei + EL::lc, out + EL::lc);
     for (int e = tid; e < D * D; e += Cfg<D>::NT) {
       out[EL::A + e] = 0.0;
       out[EL::J + e] = 0.0;
@@ -1354,7 +1385,7 @@ __device__ __forceinline__ void mh_finalize_body(const KModel& M, const StepArgs
   __shared__ double red[4];
   const int n_ell = F.n_ell > 0 ? F.n_ell : M.N;
   const double lzf = block_sum(A.ell, n_ell, red);
-  const double lzr = block_sum(A.ell2, n_ell, red);
+  const double lzr = F.lz_rev ? *F.lz_rev : block_sum(A.ell2, n_ell, red);
   const double terms = block_sum(A.part_terms, F.n_part_rev, red);
   const double lhx = block_sum(A.part_lh_x, F.n_part_fwd, red);
   const double lhs = block_sum(A.part_lh_xs, F.n_part_rev, red);
@@ -1451,6 +1482,24 @@ hipError_t launch_filter_scan(const KModel& M, FilterArgs P, const HsArgs* lv, i
   timing_mark(FAM_FILTER_FINAL, 1, st);
   hipLaunchKernelGGL((k_filter_final<D, OBS>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FINAL, 0, st);
+  return hipGetLastError();
+}
+
+// log Z only: fold, then the up-sweep reduction of the block elements; the
+// root's normaliser is log p(omega_{0:N-1}).
+template <int D, int OBS>
+hipError_t launch_filter_logz(const KModel& M, FilterArgs P, const TreeArgs* up, int n_levels,
+                              hipStream_t st) {
+  const size_t lds = lds_bytes_filter<D>(OBS == OBS_GH);
+  const int nb = (M.N + P.B - 1) / P.B;
+  timing_mark(FAM_FILTER_FOLD, 1, st);
+  hipLaunchKernelGGL((k_filter_fold<D, OBS>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
+  timing_mark(FAM_FILTER_FOLD, 0, st);
+  for (int l = 0; l < n_levels; ++l) {
+    timing_mark(FAM_FILTER_UP, 1, st);
+    hipLaunchKernelGGL(k_filter_up<D>, dim3(up[l].n_dst), dim3(Cfg<D>::NT), lds, st, M, up[l]);
+    timing_mark(FAM_FILTER_UP, 0, st);
+  }
   return hipGetLastError();
 }
 
@@ -1578,6 +1627,31 @@ hipError_t launch_filter_any(int D, const KModel& M, FilterArgs P, TreeArgs* up,
     case 16: return launch_filter<16, OBS_DIAG>(M, P, up, down, nl, st);
     case 32: return launch_filter<32, OBS_DIAG>(M, P, up, down, nl, st);
     case 64: return launch_filter<64, OBS_DIAG>(M, P, up, down, nl, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_filter_logz_any(int D, const KModel& M, FilterArgs P, TreeArgs* up, int nl,
+                                  hipStream_t st) {
+  if (P.Ho) {
+    switch (D) {
+      case 16: return launch_filter_logz<16, OBS_GH>(M, P, up, nl, st);
+      case 32: return launch_filter_logz<32, OBS_GH>(M, P, up, nl, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (P.Omd) {
+    switch (D) {
+      case 16: return launch_filter_logz<16, OBS_DENSE>(M, P, up, nl, st);
+      case 32: return launch_filter_logz<32, OBS_DENSE>(M, P, up, nl, st);
+      case 64: return launch_filter_logz<64, OBS_DENSE>(M, P, up, nl, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  switch (D) {
+    case 16: return launch_filter_logz<16, OBS_DIAG>(M, P, up, nl, st);
+    case 32: return launch_filter_logz<32, OBS_DIAG>(M, P, up, nl, st);
+    case 64: return launch_filter_logz<64, OBS_DIAG>(M, P, up, nl, st);
   }
   return hipErrorInvalidValue;
 }

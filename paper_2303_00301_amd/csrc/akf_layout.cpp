@@ -57,7 +57,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
   }
   const size_t dbl = sizeof(double);
   const size_t vn = (size_t)N * d * dbl;
-  const size_t ES = (size_t)(3 * D * D + 2 * D) * dbl;
+  const size_t ES = (size_t)(3 * D * D + 2 * D + 2) * dbl;  // ElemLayout<D>::SIZE
   const size_t PS = (size_t)(D * D + D + 2) * dbl;
   const size_t SS = (size_t)(D * D + D) * dbl;
   size_t off = 0;
@@ -343,6 +343,30 @@ akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double*
   }
   P.pre_elem = buf[Lo.L_hs & 1];
   return hip_check(launch_filter_scan_any(Lo.D, M, P, lv, Lo.L_hs, st), "filter launch");
+}
+
+// log Z of the auxiliary model only: block fold, then the up-sweep reduction
+// of the block elements; *lz points at the root element's normaliser.
+akf_status run_filter_logz(const Layout& Lo, const KModel& M, void* ws, const double* om,
+                           const double* Om, const double* Omd, int* status, int fail_bit,
+                           hipStream_t st, const double* Ft, const double* bt,
+                           const double** lz) {
+  FilterArgs P{};
+  P.B = Lo.B;
+  P.om = om;
+  P.Om = Om;
+  P.Omd = Omd;
+  P.elem = at<double>(ws, Lo.elem[0]);
+  P.ldm = Lo.D;
+  P.status = status;
+  P.fail_bit = fail_bit;
+  P.Ft = Ft;
+  P.bt = bt;
+  TreeArgs up[kMaxLevels], down[kMaxLevels];
+  fill_tree(Lo, ws, 0, Lo.elem, Lo.pre, status, fail_bit, up, down);
+  const int D = Lo.D;
+  *lz = at<double>(ws, Lo.elem[Lo.L]) + (3 * D * D + 2 * D);  // ElemLayout<D>::lc
+  return hip_check(launch_filter_logz_any(D, M, P, up, Lo.L, st), "log-likelihood launch");
 }
 
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,

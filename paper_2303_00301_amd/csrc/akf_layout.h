@@ -70,6 +70,10 @@ akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double*
                       const double* yo = nullptr, const double* Ho = nullptr,
                       const double* Ro = nullptr, int dyo = 0, const double* Ft = nullptr,
                       const double* bt = nullptr);
+akf_status run_filter_logz(const Layout& Lo, const KModel& M, void* ws, const double* om,
+                           const double* Om, const double* Omd, int* status, int fail_bit,
+                           hipStream_t st, const double* Ft, const double* bt,
+                           const double** lz);
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
                        const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
                        hipStream_t st, const double* Ft = nullptr, const double* bt = nullptr);

@@ -90,6 +90,43 @@ def test_kf_sampler_time_varying_dynamics_vs_dense(seed, N, dx):
     np.testing.assert_allclose(Lmap @ Lmap.T, pc, atol=1e-10)
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_element_normalisers_give_log_likelihood(seed):
+    """Elements carrying log c (the normaliser of p(y | x_prev)): under any
+    bracketing the prefix's log c equals the sequential filter's
+    sum_{s <= t} ell_s, and a single element's log c is a plain Gaussian log
+    density."""
+    rng = np.random.default_rng(300 + seed)
+    N, dx, dy = 9, 3, 2
+    m0, P0, F, b, Q, H, R, y = _random_lgssm(rng, N, dx, dy)
+    out = oracle.kf(m0, P0, F, Q, H, R, y, b=b)
+    cum = np.cumsum(out["ell"])
+    el = scan_ops.filter_elements(m0, P0, F, b, Q, H, R, y)
+    lc = scan_ops.filter_log_norms(m0, P0, F, b, Q, H, R, y)
+    assert abs(lc[0] - out["ell"][0]) < 1e-12
+    from tests.oracle_util import mvn_logpdf
+    assert abs(lc[3] - mvn_logpdf(y[3], H @ b, H @ Q @ H.T + R)) < 1e-12
+    pairs = list(zip(el, lc))
+
+    def op(a, c):
+        return (scan_ops.filter_combine(a[0], c[0]),
+                scan_ops.filter_combine_log_norm(a[0], a[1], c[0], c[1]))
+
+    for pref in (scan_ops.scan_fold(pairs, op), scan_ops.scan_random_tree(pairs, op, rng),
+                 scan_ops.scan_random_tree(pairs, op, rng)):
+        np.testing.assert_allclose([p[1] for p in pref], cum, rtol=1e-11, atol=1e-11)
+    # a sign error in the quadratic term is detected
+    def bad(a, c):
+        _, bi, Ci, _, _ = a[0]
+        _, _, _, ej_, Jj = c[0]
+        v = ej_ - Jj @ bi
+        Z = np.eye(dx) + Ci @ Jj
+        good = scan_ops.filter_combine_log_norm(a[0], a[1], c[0], c[1])
+        return (scan_ops.filter_combine(a[0], c[0]), good - v @ np.linalg.solve(Z, Ci @ v))
+    wrong = scan_ops.scan_fold(pairs, bad)
+    assert np.abs(np.array([p[1] for p in wrong]) - cum).max() > 1e-3
+
+
 @pytest.mark.parametrize("seed,N,dx,tv", [(31, 1, 2, False), (32, 2, 2, True), (33, 3, 1, False),
                                           (34, 6, 3, True), (35, 9, 2, False), (36, 12, 2, True)])
 def test_dnc_sampler_law_vs_dense(seed, N, dx, tv):
