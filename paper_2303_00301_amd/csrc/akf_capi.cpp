@@ -15,8 +15,9 @@ using namespace akf;
 
 namespace {
 
+// Step `step` of a run uses status word step & 1 (see k_step_init).
 StepArgs make_step_args(const Layout& Lo, void* ws, const double* y, const double* x_in,
-                        double delta, int order, const double* xi) {
+                        double delta, int order, const double* xi, int step) {
   StepArgs A{};
   A.y = y;
   A.x = x_in;
@@ -39,21 +40,24 @@ StepArgs make_step_args(const Layout& Lo, void* ws, const double* y, const doubl
   A.g_Omd = at<double>(ws, Lo.gOmd);
   A.g_Omd_inv = at<double>(ws, Lo.gOmdinv);
   A.g_scal = at<double>(ws, Lo.gscal);
-  A.status = at<int>(ws, Lo.status);
+  A.status = at<int>(ws, Lo.status) + (step & 1);
   A.accept_flag = at<int>(ws, Lo.accept);
   return A;
 }
 
+// Step `step` (0 = the first of a call) of a run on one workspace.
 akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
                         double delta, int order, const double* xi, const double* unif,
                         double* x_out, double* log_ratio, int32_t* accepted, double* logZ_fwd,
-                        double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st) {
+                        double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st,
+                        int step) {
   const size_t vn = (size_t)M.N * M.d;
-  int* status = at<int>(ws, Lo.status);
-  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, order, xi);
+  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, order, xi, step);
+  int* status = A.status;
   akf_status s;
-  if ((s = hip_check(launch_step_init(status, root_flag(Lo, ws), at<double>(ws, Lo.xin[Lo.L]),
-                                      Lo.D, st),
+  if (step == 0 &&
+      (s = hip_check(launch_step_init(at<int>(ws, Lo.status), root_flag(Lo, ws),
+                                      at<double>(ws, Lo.xin[Lo.L]), Lo.D, st),
                      "init launch")) != AKF_OK)
     return s;
   int n_part_fwd = 0, n_part_rev = 0, n_part_dyn = 0;
@@ -94,6 +98,7 @@ akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, cons
                            &lz_rev)) != AKF_OK)
     return s;
   FinalArgs F{};
+  F.status_next = at<int>(ws, Lo.status) + ((step + 1) & 1);
   F.lz_rev = lz_rev;
   F.part_dyn = Dy.part;
   F.n_part_dyn = n_part_dyn;
@@ -114,12 +119,14 @@ akf_status mh_step_impl(const Layout& Lo, const KModel& M, const double* y, cons
 akf_status fact_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
                           double delta, int order, const double* xi, const double* unif,
                           double* x_out, double* log_ratio, int32_t* accepted, double* logZ_fwd,
-                          double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st) {
+                          double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st,
+                          int step) {
   const size_t vn = (size_t)M.N * M.d;
-  int* status = at<int>(ws, Lo.status);
-  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, order, xi);
+  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, order, xi, step);
+  int* status = A.status;
   akf_status s;
-  if ((s = hip_check(launch_step_init(status, nullptr, nullptr, 0, st), "init launch")) != AKF_OK)
+  if (step == 0 && (s = hip_check(launch_step_init(at<int>(ws, Lo.status), nullptr, nullptr, 0, st),
+                                  "init launch")) != AKF_OK)
     return s;
   int n_part_fwd = 0, n_part_rev = 0;
   if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
@@ -143,6 +150,7 @@ akf_status fact_step_impl(const Layout& Lo, const KModel& M, const double* y, co
   R.fail_bit = ST_REV_NOT_PD;
   if ((s = hip_check(launch_fact_scan(M, R, st), "factorised scan launch")) != AKF_OK) return s;
   FinalArgs F{};
+  F.status_next = at<int>(ws, Lo.status) + ((step + 1) & 1);
   F.n_ell = M.d;
   F.unif = unif;
   F.log_ratio = log_ratio;
@@ -483,7 +491,7 @@ akf_status akf_mh_step(const akf_model* model, const double* y, const double* x_
           AKF_OK)
     return s;
   return mh_step_impl(Lo, M, y, x_in, delta, order, xi, unif, x_out, log_ratio, accepted, logZ_fwd,
-                      logZ_rev, status, ws, (hipStream_t)stream);
+                      logZ_rev, status, ws, (hipStream_t)stream, 0);
 }
 
 akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double delta,
@@ -511,7 +519,7 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
     s = mh_step_impl(Lo, M, y, x, delta, order, xi + (size_t)k * 2 * vn, unif + k, x,
                      log_ratio ? log_ratio + k : nullptr, accepted ? accepted + k : nullptr,
                      logZ_fwd ? logZ_fwd + k : nullptr, logZ_rev ? logZ_rev + k : nullptr,
-                     status ? status + k : nullptr, ws, (hipStream_t)stream);
+                     status ? status + k : nullptr, ws, (hipStream_t)stream, k);
     if (s != AKF_OK) return s;
   }
   return AKF_OK;
@@ -538,7 +546,7 @@ akf_status akf_mh_step_factorised(const akf_model* model, const double* y, const
   make_layout(Lo, model->N, model->dx, model->dy, 0, LAYOUT_FACT);
   if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
   return fact_step_impl(Lo, to_kmodel(model), y, x_in, delta, order, xi, unif, x_out, log_ratio,
-                        accepted, logZ_fwd, logZ_rev, status, ws, (hipStream_t)stream);
+                        accepted, logZ_fwd, logZ_rev, status, ws, (hipStream_t)stream, 0);
 }
 
 akf_status akf_mh_run_factorised(const akf_model* model, const double* y, double* x, double delta,
@@ -560,7 +568,7 @@ akf_status akf_mh_run_factorised(const akf_model* model, const double* y, double
     s = fact_step_impl(Lo, M, y, x, delta, order, xi + (size_t)k * 2 * vn, unif + k, x,
                        log_ratio ? log_ratio + k : nullptr, accepted ? accepted + k : nullptr,
                        logZ_fwd ? logZ_fwd + k : nullptr, logZ_rev ? logZ_rev + k : nullptr,
-                       status ? status + k : nullptr, ws, (hipStream_t)stream);
+                       status ? status + k : nullptr, ws, (hipStream_t)stream, k);
     if (s != AKF_OK) return s;
   }
   return AKF_OK;

@@ -128,12 +128,12 @@ __global__ void __launch_bounds__(FT) k_fact_scan(KModel M, FactArgs P) {
       if (s < cnt) {
         SE e;
         if (t0 + s == 0) {
-          const double Sv = P0 + Om[s];
-          e = SE{0.0, m0 + P0 * (om[s] - m0) / Sv, P0 * Om[s] / Sv, 0.0, 0.0};
+          const double iS = 1.0 / (P0 + Om[s]);
+          e = SE{0.0, m0 + P0 * (om[s] - m0) * iS, P0 * Om[s] * iS, 0.0, 0.0};
         } else {
-          const double Sv = Q + Om[s];
-          e = SE{F * Om[s] / Sv, (Om[s] * bb + Q * om[s]) / Sv, Q * Om[s] / Sv,
-                 F * (om[s] - bb) / Sv, F * F / Sv};
+          const double iS = 1.0 / (Q + Om[s]);
+          e = SE{F * Om[s] * iS, (Om[s] * bb + Q * om[s]) * iS, Q * Om[s] * iS,
+                 F * (om[s] - bb) * iS, F * F * iS};
         }
         acc = se_combine(acc, e);
       }
@@ -153,8 +153,10 @@ __global__ void __launch_bounds__(FT) k_fact_scan(KModel M, FactArgs P) {
     SE pre = (c == 0) ? SE{1.0, 0.0, 0.0, 0.0, 0.0} : SE{0.0, cm, cP, 0.0, 0.0};
     for (int k = 0; k < w; ++k) pre = se_combine(pre, swave[k]);
     pre = se_combine(pre, ex);
-    // final: sequential Kalman update from the prefix moments (b, C)
-    double m = pre.b, Pv = pre.C, ell = 0.0;
+    // final: sequential Kalman update from the prefix moments (b, C); the
+    // log det terms are accumulated as one product (frexp keeps it in range)
+    double m = pre.b, Pv = pre.C, ell = 0.0, sprod = 1.0;
+    int sexp = 0;
 #pragma unroll
     for (int s = 0; s < FS_MAX; ++s) {
       if (s < cnt) {
@@ -163,16 +165,21 @@ __global__ void __launch_bounds__(FT) k_fact_scan(KModel M, FactArgs P) {
         const double Pp = (t == 0) ? P0 : F * F * Pv + Q;
         const double Sv = Pp + Om[s];
         if (!(Sv > 0.0) || !(Pp >= 0.0)) bad = true;
+        const double iS = 1.0 / Sv;
         const double r = om[s] - mp;
-        ell += -0.5 * (LOG2PI_F + log(Sv) + r * r / Sv);
-        m = mp + Pp / Sv * r;
-        Pv = Pp * Om[s] / Sv;
+        int e2;
+        sprod = frexp(sprod * Sv, &e2);
+        sexp += e2;
+        ell += -0.5 * (LOG2PI_F + r * r * iS);
+        m = mp + Pp * iS * r;
+        Pv = Pp * Om[s] * iS;
         if (mfc) {
           mfc[t] = m;
           Pfc[t] = Pv;
         }
       }
     }
+    ell += -0.5 * (log(sprod) + sexp * 0.69314718055994530942);  // log det terms
     lz += block_reduce(ell, red);
     // moments at the chunk's last step for the next chunk
     if (c + 1 < n_chunks && tid == FT - 1) {
@@ -209,8 +216,9 @@ __global__ void __launch_bounds__(FT) k_fact_scan(KModel M, FactArgs P) {
           st[s] = AM{0.0, mf + sqrt(Pf) * xi};
         } else {
           const double Pp1 = F * F * Pf + Q;
-          const double G = Pf * F / Pp1;
-          const double Sig = Pf * Q / Pp1;
+          const double iP = 1.0 / Pp1;
+          const double G = Pf * F * iP;
+          const double Sig = Pf * Q * iP;
           if (!(Pp1 > 0.0) || !(Sig > 0.0)) sbad = true;
           st[s] = AM{G, mf - G * (F * mf + bb) + sqrt(Sig) * xi};
         }

@@ -172,6 +172,7 @@ struct FinalArgs {
   double* logZ_fwd;
   double* logZ_rev;
   int* status_out;
+  int* status_next;  // the other status word, cleared for the next step (one chain)
   int n_part_fwd, n_part_rev;
 };
 

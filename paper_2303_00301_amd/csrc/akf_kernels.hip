@@ -42,12 +42,12 @@ __device__ __forceinline__ void flag_status(int* st, int bit) { atomicOr(st, bit
 // Also marks the root of the filter prefix tree as the identity and sets the
 // state entering the sampler's last block from the right to zero (it is
 // multiplied by E = 0 of the terminal step, but must be finite).
+// status points at the workspace's two status words (steps alternate between
+// them; the decision kernel of one step clears the next step's word).
 __global__ void k_step_init(int* status, double* root_flag, double* root_xin, int D) {
   const int tid = threadIdx.x;
-  if (tid == 0) {
-    *status = 0;
-    if (root_flag) *root_flag = 1.0;
-  }
+  if (tid < 2) status[tid] = 0;
+  if (tid == 0 && root_flag) *root_flag = 1.0;
   if (root_xin && tid < D) root_xin[tid] = 0.0;
 }
 
@@ -207,14 +207,15 @@ constexpr int MVT_WAVES = kMvtWaves;
 
 __device__ __forceinline__ void lin_mvt_body(const KModel& M, const StepArgs& A, int rev,
                                              int item) {
-  __shared__ double sRt[64 * 64];
+  constexpr int LR = 65;  // odd row stride: the transposing store is conflict-free too
+  __shared__ double sRt[64 * LR];
   __shared__ double sr[MVT_WAVES * 64];
   __shared__ double sRr[MVT_WAVES * 64];
   __shared__ int ssite[64];
   __shared__ double red[2 * MVT_WAVES];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int p = M.dy, d = M.d;
-  for (int e = tid; e < p * p; e += blockDim.x) sRt[(e % p) * 64 + e / p] = M.R[e];
+  for (int e = tid; e < p * p; e += blockDim.x) sRt[(e % p) * LR + e / p] = M.R[e];
   if (tid < p) ssite[tid] = M.site[tid];
   const int t = item * MVT_WAVES + w;
   const bool active = t < M.N;
@@ -225,8 +226,16 @@ __device__ __forceinline__ void lin_mvt_body(const KModel& M, const StepArgs& A,
   sr[w * 64 + lane] = r;
   __syncthreads();
   double Rr = 0.0;
-  if (active && lane < p)
-    for (int l = 0; l < p; ++l) Rr += sRt[l * 64 + lane] * sr[w * 64 + l];
+  if (active && lane < p) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    int l = 0;
+    for (; l + 4 <= p; l += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] = fma(sRt[(l + u) * LR + lane], sr[w * 64 + l + u], acc[u]);
+    }
+    for (; l < p; ++l) acc[0] = fma(sRt[l * LR + lane], sr[w * 64 + l], acc[0]);
+    Rr = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
   double q = r * Rr;
   for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
   sRr[w * 64 + lane] = Rr;
@@ -237,8 +246,8 @@ __device__ __forceinline__ void lin_mvt_body(const KModel& M, const StepArgs& A,
     lh = -0.5 * a * log1p(q / M.nu);
     if (lane < d) {
       double sv = 0.0;
-      for (int k = 0; k < p; ++k)
-        if (ssite[k] == lane) sv += sRr[w * 64 + k];
+#pragma unroll 8
+      for (int k = 0; k < p; ++k) sv += (ssite[k] == lane) ? sRr[w * 64 + k] : 0.0;
       const double v = a / (M.nu + q) * sv;
       if (rev)
         term = lin_rev_point(A, base + lane, xt[lane], v, 0.0);
@@ -1413,6 +1422,47 @@ __global__ void __launch_bounds__(256) k_mh_finalize(KModel M, StepArgs A, Final
   mh_finalize_body(M, A, F);
 }
 
+// One chain: the decision fused with the select.  Every workgroup forms the
+// same sums in the same order, hence the same decision; workgroup 0 writes the
+// outputs and clears the next step's status word; each workgroup writes its
+// slice of x_out = accept ? x* : x.
+__global__ void __launch_bounds__(256) k_mh_decide(KModel M, StepArgs A, FinalArgs F,
+                                                   const double* __restrict__ x,
+                                                   double* __restrict__ x_out, int64_t n,
+                                                   int64_t per_block) {
+  __shared__ double red[4];
+  __shared__ int sacc;
+  const int n_ell = F.n_ell > 0 ? F.n_ell : M.N;
+  const double lzf = block_sum(A.ell, n_ell, red);
+  const double lzr = F.lz_rev ? *F.lz_rev : block_sum(A.ell2, n_ell, red);
+  const double terms = block_sum(A.part_terms, F.n_part_rev, red);
+  const double lhx = block_sum(A.part_lh_x, F.n_part_fwd, red);
+  const double lhs = block_sum(A.part_lh_xs, F.n_part_rev, red);
+  const double dyn = F.part_dyn ? block_sum(F.part_dyn, F.n_part_dyn, red) : 0.0;
+  if (threadIdx.x == 0) {
+    int st = *A.status;
+    if (st & ST_FWD_NOT_PD) st = ST_FWD_NOT_PD;
+    double lr = terms + (lhs - lhx) + (lzf - lzr) + dyn;
+    if (st == 0 && !isfinite(lr)) st |= ST_NONFINITE;
+    if (st != 0) lr = -INFINITY;
+    const int acc = (st == 0) && (log(F.unif[0]) < lr);
+    sacc = acc;
+    if (blockIdx.x == 0) {
+      if (F.log_ratio) *F.log_ratio = lr;
+      if (F.accepted) *F.accepted = acc;
+      if (F.logZ_fwd) *F.logZ_fwd = lzf;
+      if (F.logZ_rev) *F.logZ_rev = lzr;
+      if (F.status_out) *F.status_out = st;
+      if (F.status_next) *F.status_next = 0;
+    }
+  }
+  __syncthreads();
+  const bool acc = sacc != 0;
+  const int64_t i0 = (int64_t)blockIdx.x * per_block;
+  const int64_t i1 = i0 + per_block < n ? i0 + per_block : n;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) x_out[i] = acc ? A.xs[i] : x[i];
+}
+
 __device__ __forceinline__ void mh_select_body(int64_t n, const double* __restrict__ x,
                                                const double* __restrict__ xs,
                                                double* __restrict__ x_out,
@@ -1705,10 +1755,10 @@ hipError_t launch_step_init(int* status, double* root_flag, double* root_xin, in
 
 hipError_t launch_finalize(const KModel& M, StepArgs A, FinalArgs F, const double* x,
                            double* x_out, hipStream_t st) {
-  hipLaunchKernelGGL(k_mh_finalize, dim3(1), dim3(256), 0, st, M, A, F);
   const int64_t n = (int64_t)M.N * M.d;
-  hipLaunchKernelGGL(k_mh_select, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, x, A.xs,
-                     x_out, A.accept_flag);
+  const int64_t per_block = 2048;
+  const unsigned grid = (unsigned)((n + per_block - 1) / per_block);
+  hipLaunchKernelGGL(k_mh_decide, dim3(grid), dim3(256), 0, st, M, A, F, x, x_out, n, per_block);
   return hipGetLastError();
 }
 

@@ -112,7 +112,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     Lo.plhxs = take((size_t)Lo.n_part * dbl);
     Lo.pterms = take((size_t)Lo.n_part * dbl);
     Lo.accept = take(sizeof(int));
-    Lo.status = take(sizeof(int));
+    Lo.status = take(2 * sizeof(int));  // two words: consecutive steps alternate
     Lo.total = off;
     return;
   }
@@ -128,7 +128,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     Lo.Gam = take(mat);
     Lo.wb = take(vec);
     Lo.Vc = take(mat);
-    Lo.status = take(sizeof(int));
+    Lo.status = take(2 * sizeof(int));  // two words: consecutive steps alternate
     Lo.total = off;
     return;
   }
@@ -169,7 +169,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     Lo.Pbar = take((size_t)N * D * D * dbl);
     Lo.part = take((size_t)Lo.nb * (2 * D * D + 2 * D) * dbl);
   }
-  Lo.status = take(sizeof(int));
+  Lo.status = take(2 * sizeof(int));  // two words: consecutive steps alternate
   Lo.total = off;
 }
 
