@@ -133,3 +133,51 @@ def test_factorised_entry_points_reject_bad_requests():
     assert call(ws_bytes=need - 1) == 3
     assert lib.akf_mh_run_factorised(C.byref(m), p, p, 0.5, 1, -1, p, p, None, None, None, None,
                                      None, ws, 1 << 30, None) == 1
+
+
+def test_nonlinear_dynamics_validation():
+    lib = _lib.load()
+    m = _fake_model(N=64, dx=3, dy=2, emit=5)
+    m.scale = 1.0
+    m.dyn = 1
+    m.F = None
+    m.dyn_par[3] = 2e-4
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) > 0
+    # linear-only entry points refuse nonlinear dynamics
+    assert lib.akf_filter_workspace_bytes(C.byref(m), 0) == 0
+    assert b"linear dynamics" in lib.akf_last_error()
+    assert lib.akf_sampler_workspace_bytes(C.byref(m), 0) == 0
+    assert lib.akf_dnc_workspace_bytes(C.byref(m)) == 0
+    assert lib.akf_mh_factorised_workspace_bytes(C.byref(m), 1) == 0
+    m.dyn_par[3] = 0.0
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) == 0   # dt must be > 0
+    m.dyn_par[3] = 2e-4
+    m.dx = 4
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) == 0   # Lorenz-63 needs dx = 3
+    m.dyn = 2
+    m.dyn_par[1] = 0.01
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) > 0    # Lorenz-96, dx >= 4
+    m.dx = 3
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) == 0
+    m.dyn = 7
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) == 0
+    # linear dynamics still need F
+    m2 = _fake_model()
+    m2.F = None
+    assert lib.akf_mh_workspace_bytes(C.byref(m2), 2, 0) == 0
+
+
+def test_gauss_site_and_dnc_workspace():
+    lib = _lib.load()
+    m = _fake_model(N=100, dx=5, dy=3, emit=5)
+    m.scale = 0.0
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) == 0   # scale must be > 0
+    m.scale = 2.0
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) > 0
+    small = lib.akf_dnc_workspace_bytes(C.byref(_fake_model(N=100, dx=5)))
+    big = lib.akf_dnc_workspace_bytes(C.byref(_fake_model(N=4096, dx=64)))
+    assert 0 < small < big
+    p = C.c_void_p(0x2000)
+    rc = lib.akf_dnc_sample(C.byref(_fake_model(N=100, dx=5)), p, p, p, None, None,
+                            C.c_void_p(0x10000), 1 << 30, None)
+    assert rc == 1  # x is required
