@@ -21,6 +21,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "akf_team.hpp"
 #include "akf_internal.h"
 
@@ -273,8 +275,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_dnc_down(KModel M, DncArgs A, in
 }
 
 template <int D>
-hipError_t launch_dnc(const KModel& M, DncArgs A, int depth, hipStream_t st) {
-  const size_t lds = (size_t)dnc_lds_doubles<D>() * sizeof(double);
+hipError_t set_dnc_lds_limits(size_t lds) {
   hipError_t e;
   if ((e = hipFuncSetAttribute((const void*)k_dnc_leaf<D>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
@@ -285,9 +286,18 @@ hipError_t launch_dnc(const KModel& M, DncArgs A, int depth, hipStream_t st) {
   if ((e = hipFuncSetAttribute((const void*)k_dnc_root<D>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
     return e;
-  if ((e = hipFuncSetAttribute((const void*)k_dnc_down<D>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
-    return e;
+  return hipFuncSetAttribute((const void*)k_dnc_down<D>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)lds);
+}
+
+template <int D>
+hipError_t launch_dnc(const KModel& M, DncArgs A, int depth, hipStream_t st) {
+  const size_t lds = (size_t)dnc_lds_doubles<D>() * sizeof(double);
+  // the LDS limit is a per-kernel attribute: set once per process
+  static std::once_flag once;
+  static hipError_t set_err = hipSuccess;
+  std::call_once(once, [lds] { set_err = set_dnc_lds_limits<D>(lds); });
+  if (set_err != hipSuccess) return set_err;
   const dim3 nt(Cfg<D>::NT);
   timing_mark(FAM_DNC, 1, st);
   if (A.T >= 1) hipLaunchKernelGGL(k_dnc_leaf<D>, dim3(A.T), nt, lds, st, M, A);
