@@ -236,6 +236,38 @@ def bench_stoch_vol(torch, S, W, K: int, dev) -> dict:
     return out
 
 
+def bench_first_order(torch, S, W, K: int, dev) -> dict:
+    """First-order steps on the latent-field workload (d_x = 64, T = 4096): the
+    plain step, which forms the auxiliary model's covariances every step, and
+    the run that forms them once per call (the first step pays for it)."""
+    w = W.latent_field()
+    delta = 0.2 * w.delta
+    M = S.DeviceModel.from_workload(w, device=dev)
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(71)
+    xi = torch.randn((K + 2, 2, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
+    un = torch.rand((K + 2,), dtype=torch.float64, device=dev, generator=gen).clamp_(min=1e-300)
+    out = {"workload": f"latent_field_d{w.dx}_T{w.N}, order-1 proposal, delta {delta:.3g}, "
+                       f"one chain, {K} steps per call"}
+    for key, reuse in (("plain", False), ("matrices_once_per_call", True)):
+        ws = S.Workspace(dev)
+        x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
+        S.mh_run(M, y, x, delta, 1, xi[:2], un[:2], ws=ws, reuse_matrices=reuse)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = S.mh_run(M, y, x, delta, 1, xi[2:], un[2:], ws=ws, reuse_matrices=reuse)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+                    "acceptance": r["accepted"].float().mean().item(),
+                    "rejected_by_status": int((r["status"] != 0).sum().item())}
+    out["speedup"] = out["plain"]["ms_per_step"] / out["matrices_once_per_call"]["ms_per_step"]
+    return out
+
+
 def bench_spatio_temporal(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dict:
     """Second paper workload: the spatio-temporal model (8 x 8 lattice, T = 1024,
     multivariate-t observations with nu = 1), first order, one chain.  The
@@ -393,6 +425,7 @@ def main() -> int:
     ap.add_argument("--no-spatio-temporal", action="store_true")
     ap.add_argument("--no-lorenz", action="store_true")
     ap.add_argument("--no-samplers", action="store_true")
+    ap.add_argument("--no-first-order", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
                          "reference for the HBM byte counters)")
@@ -500,6 +533,8 @@ def main() -> int:
             torch, S, W, _lib, 100, dev, 0 if args.no_cpu_baseline else 100)
     if not args.no_samplers:
         res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev)
+    if not args.no_first_order:
+        res["first_order"] = bench_first_order(torch, S, W, 50, dev)
     if not args.no_lorenz:
         res["nonlinear"] = bench_lorenz(torch, S, W, 20, dev, 0 if args.no_cpu_baseline else 10)
     if not args.no_cpu_baseline and args.cpu_steps > 0:

@@ -152,6 +152,28 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
                       int32_t* status, void* ws, size_t ws_bytes, int32_t block, void* stream);
 
 /*
+ * n_steps first-order MH steps (Sec. "Auxiliary Kalman sampler", eq.
+ * gaussian-FK-proposal, order fixed at 1) on one chain, with the auxiliary
+ * model's matrices formed once per call.  Under order 1, Omega_t = delta/2 I
+ * whatever the path, so the forward and reverse auxiliary models of every
+ * step share their covariances (P^p_t, S_t, P^f_t, E_t, L_t); only the means
+ * depend on the path.  The first step runs the full filter and sampler and
+ * keeps S_t^{-1}, log det S_t, E_t and chol(L_t); every later proposal is
+ * matrix-vector work.  Arguments, outputs, normals and status bits as
+ * akf_mh_run with order = 1; the chain is the same up to rounding.
+ *   - model: linear dynamics (AKF_ERR_UNSUPPORTED otherwise); any emission.
+ *   - workspace: akf_mh_first_order_workspace_bytes (that of akf_mh_run plus
+ *     three [N, D, D] matrices, D the padded width 16, 32 or 64); its
+ *     contents do not carry over between calls.
+ */
+size_t akf_mh_first_order_workspace_bytes(const akf_model* model, int32_t block);
+akf_status akf_mh_run_first_order(const akf_model* model, const double* y, double* x,
+                                  double delta, int32_t n_steps, const double* xi,
+                                  const double* unif, double* log_ratio, int32_t* accepted,
+                                  double* logZ_fwd, double* logZ_rev, int32_t* status, void* ws,
+                                  size_t ws_bytes, int32_t block, void* stream);
+
+/*
  * Factorised step (Sec. "Spatio-temporal model").  When P0, F and Q are
  * diagonal the prior is a product over coordinates; with a diagonal Omega_t
  * (first order, or second order with the POISSON_LOG, STUDENT_T or STOCH_VOL

@@ -163,6 +163,128 @@ akf_status fact_step_impl(const Layout& Lo, const KModel& M, const double* y, co
   return hip_check(launch_finalize(M, A, F, x_in, x_out, st), "finalize launch");
 }
 
+// First-order steps with the auxiliary model's matrices formed once per call.
+// Under order 1, Omega_t = delta/2 I whatever the path, so the forward and
+// reverse auxiliary models of every step share P^p_t, S_t, P^f_t and the
+// sampler's E_t and L_t.  Step 0 runs the full filter and sampler, keeping
+// S_t^{-1}, log det S_t, chol(L_t) (E_t stays in the sampler's buffer), and
+// forms Phi_t = Omega S_t^{-1} F; every proposal after that is matrix-vector
+// work: the filtering means by an affine suffix scan over reversed time, the
+// log-likelihood terms from the kept S_t, the sampler elements from the kept
+// E_t and chol(L_t), then the sampler's suffix scan.  Set-up failures go to a
+// third status word that each step folds into its own.
+akf_status fixed_mean_scan(const Layout& Lo, const KModel& M, void* ws, int* status,
+                           hipStream_t st) {
+  SampArgs S{};
+  S.B = Lo.B;
+  S.E = at<double>(ws, Lo.Ephi);
+  S.U = at<double>(ws, Lo.U);
+  S.agg = at<double>(ws, Lo.sagg[0]);
+  S.xin = at<double>(ws, Lo.xin[0]);
+  S.xs = at<double>(ws, Lo.mf);  // means in reversed time, stride D
+  S.status = status;
+  TreeArgs up[kMaxLevels], down[kMaxLevels];
+  fill_tree(Lo, ws, 0, Lo.sagg, Lo.xin, status, ST_FWD_NOT_PD, up, down);
+  KModel Mv = M;
+  Mv.d = Lo.D;
+  return hip_check(launch_samp_scan_any(Lo.D, Mv, S, up, down, Lo.L, st), "mean scan launch");
+}
+
+akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
+                           double delta, const double* xi, const double* unif, double* x_out,
+                           double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                           double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st,
+                           int step) {
+  const size_t vn = (size_t)M.N * M.d;
+  const int D = Lo.D;
+  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, 1, xi, step);
+  int* status = A.status;
+  int* setup_status = at<int>(ws, Lo.status) + 2;
+  akf_status s;
+  if (step == 0) {
+    if ((s = hip_check(launch_step_init(at<int>(ws, Lo.status), root_flag(Lo, ws),
+                                        at<double>(ws, Lo.xin[Lo.L]), D, st),
+                       "init launch")) != AKF_OK)
+      return s;
+    if ((s = hip_check(launch_step_init(setup_status, nullptr, nullptr, 0, st), "init launch")) !=
+        AKF_OK)
+      return s;
+  }
+  int n_part_fwd = 0, n_part_rev = 0;
+  if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
+  double* Sinv = at<double>(ws, Lo.Sinv);
+  double* ldS = at<double>(ws, Lo.ldS);
+  double* Ec = at<double>(ws, Lo.E);
+  double* Lc = at<double>(ws, Lo.Lc);
+  FixedArgs X{};
+  // the linearisation's Omega, bit for bit
+  X.ovar = M.emit == EMIT_GAUSSIAN ? 0.5 * delta : 1.0 / (2.0 / delta);
+  X.Sinv = Sinv;
+  X.ldS = ldS;
+  X.Ec = Ec;
+  X.Lc = Lc;
+  X.Ephi = at<double>(ws, Lo.Ephi);
+  X.U = at<double>(ws, Lo.U);
+  X.mfr = at<double>(ws, Lo.mf);
+  X.setup_status = setup_status;
+  X.status = status;
+  X.fail_bit = ST_FWD_NOT_PD;
+  if (step == 0) {
+    double* mf = at<double>(ws, Lo.mf);
+    double* Pf = at<double>(ws, Lo.Pf);
+    if ((s = run_filter(Lo, M, ws, A.om, A.Om, nullptr, mf, Pf, D, A.ell, setup_status,
+                        ST_FWD_NOT_PD, st, nullptr, nullptr, nullptr, 0, nullptr, nullptr, Sinv,
+                        ldS)) != AKF_OK)
+      return s;
+    if ((s = run_sampler(Lo, M, ws, mf, Pf, D, xi + vn, A.xs, setup_status, st, nullptr, nullptr,
+                         Lc)) != AKF_OK)
+      return s;
+    if ((s = hip_check(launch_fixed_phi_any(D, M, X, st), "Phi launch")) != AKF_OK) return s;
+  } else {
+    X.om = A.om;
+    if ((s = hip_check(launch_fixed_cmean_any(D, M, X, st), "mean element launch")) != AKF_OK)
+      return s;
+    if ((s = fixed_mean_scan(Lo, M, ws, status, st)) != AKF_OK) return s;
+    X.xi_x = xi + vn;
+    X.ell = A.ell;
+    if ((s = hip_check(launch_fixed_ell_any(D, M, X, st), "log-likelihood launch")) != AKF_OK)
+      return s;
+    SampArgs S{};
+    S.B = Lo.B;
+    S.E = Ec;
+    S.U = X.U;
+    S.agg = at<double>(ws, Lo.sagg[0]);
+    S.xin = at<double>(ws, Lo.xin[0]);
+    S.xs = A.xs;
+    S.status = status;
+    TreeArgs up[kMaxLevels], down[kMaxLevels];
+    fill_tree(Lo, ws, 0, Lo.sagg, Lo.xin, status, ST_FWD_NOT_PD, up, down);
+    if ((s = hip_check(launch_samp_scan_any(D, M, S, up, down, Lo.L, st), "sampler launch")) !=
+        AKF_OK)
+      return s;
+  }
+  if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
+  X.om = A.om2;
+  X.xi_x = nullptr;
+  X.ell = A.ell2;
+  if ((s = hip_check(launch_fixed_cmean_any(D, M, X, st), "mean element launch")) != AKF_OK)
+    return s;
+  if ((s = fixed_mean_scan(Lo, M, ws, status, st)) != AKF_OK) return s;
+  if ((s = hip_check(launch_fixed_ell_any(D, M, X, st), "log-likelihood launch")) != AKF_OK)
+    return s;
+  FinalArgs F{};
+  F.status_next = at<int>(ws, Lo.status) + ((step + 1) & 1);
+  F.unif = unif;
+  F.log_ratio = log_ratio;
+  F.accepted = accepted;
+  F.logZ_fwd = logZ_fwd;
+  F.logZ_rev = logZ_rev;
+  F.status_out = status_out;
+  F.n_part_fwd = n_part_fwd;
+  F.n_part_rev = n_part_rev;
+  return hip_check(launch_finalize(M, A, F, x_in, x_out, st), "finalize launch");
+}
+
 akf_status check_fact_model(const akf_model* model, int order) {
   akf_status s;
   if ((s = check_model(model, true)) != AKF_OK) return s;
@@ -569,6 +691,44 @@ akf_status akf_mh_run_factorised(const akf_model* model, const double* y, double
                        log_ratio ? log_ratio + k : nullptr, accepted ? accepted + k : nullptr,
                        logZ_fwd ? logZ_fwd + k : nullptr, logZ_rev ? logZ_rev + k : nullptr,
                        status ? status + k : nullptr, ws, (hipStream_t)stream, k);
+    if (s != AKF_OK) return s;
+  }
+  return AKF_OK;
+}
+
+size_t akf_mh_first_order_workspace_bytes(const akf_model* model, int32_t block) {
+  if (check_model(model, true) != AKF_OK || check_order(model, 1) != AKF_OK ||
+      check_linear(model, "akf_mh_run_first_order") != AKF_OK || block < 0)
+    return 0;
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP, false, true);
+  return Lo.total;
+}
+
+akf_status akf_mh_run_first_order(const akf_model* model, const double* y, double* x,
+                                  double delta, int32_t n_steps, const double* xi,
+                                  const double* unif, double* log_ratio, int32_t* accepted,
+                                  double* logZ_fwd, double* logZ_rev, int32_t* status, void* ws,
+                                  size_t ws_bytes, int32_t block, void* stream) {
+  akf_status s;
+  if ((s = check_model(model, true)) != AKF_OK) return s;
+  if ((s = check_linear(model, "akf_mh_run_first_order")) != AKF_OK) return s;
+  if ((s = check_order(model, 1)) != AKF_OK) return s;
+  if (!y || !x || !xi || !unif) return fail(AKF_ERR_INVALID, "y, x, xi and unif must be non-NULL");
+  if (n_steps < 0) return fail(AKF_ERR_INVALID, "n_steps must be >= 0");
+  if (!(delta > 0.0)) return fail(AKF_ERR_INVALID, "delta must be > 0");
+  if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP, false, true);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  if ((s = prepare_device()) != AKF_OK) return s;
+  const KModel M = to_kmodel(model);
+  const size_t vn = (size_t)M.N * M.d;
+  for (int k = 0; k < n_steps; ++k) {
+    s = fixed_step_impl(Lo, M, y, x, delta, xi + (size_t)k * 2 * vn, unif + k, x,
+                        log_ratio ? log_ratio + k : nullptr, accepted ? accepted + k : nullptr,
+                        logZ_fwd ? logZ_fwd + k : nullptr, logZ_rev ? logZ_rev + k : nullptr,
+                        status ? status + k : nullptr, ws, (hipStream_t)stream, k);
     if (s != AKF_OK) return s;
   }
   return AKF_OK;

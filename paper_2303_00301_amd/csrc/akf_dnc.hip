@@ -21,8 +21,6 @@
 #include <math.h>
 #include <stdint.h>
 
-#include <mutex>
-
 #include "akf_team.hpp"
 #include "akf_internal.h"
 
@@ -294,9 +292,7 @@ template <int D>
 hipError_t launch_dnc(const KModel& M, DncArgs A, int depth, hipStream_t st) {
   const size_t lds = (size_t)dnc_lds_doubles<D>() * sizeof(double);
   // the LDS limit is a per-kernel attribute: set once per process
-  static std::once_flag once;
-  static hipError_t set_err = hipSuccess;
-  std::call_once(once, [lds] { set_err = set_dnc_lds_limits<D>(lds); });
+  static const hipError_t set_err = set_dnc_lds_limits<D>(lds);
   if (set_err != hipSuccess) return set_err;
   const dim3 nt(Cfg<D>::NT);
   timing_mark(FAM_DNC, 1, st);

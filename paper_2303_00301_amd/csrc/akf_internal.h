@@ -89,6 +89,9 @@ struct FilterArgs {
   // per-step dynamics F_t [N*d*d], b_t [N*d] (transition into step t), or
   // nullptr for the model's F, b
   const double *Ft, *bt;
+  // re-scan outputs kept for steps that reuse the covariances (diagonal Omega
+  // path; nullptr = not kept): S_t^{-1} [N*D*D], log det S_t [N]
+  double *Sinv, *ldS;
 };
 
 struct TreeArgs {
@@ -121,6 +124,25 @@ struct SampArgs {
   double* xs;        // [N*d]
   int* status;
   const double *Ft, *bt;  // per-step dynamics as in FilterArgs, or nullptr
+  double* Lc;             // chol(L_t) [N*D*D] kept for reuse, or nullptr
+};
+
+// Steps whose auxiliary model has the same covariances every time (first
+// order: Omega_t = delta/2 I), with the matrices formed once per call:
+// S_t^{-1}, log det S_t, the filtering-mean maps Phi_t = Omega S_t^{-1} F (in
+// reversed time), the sampler's E_t and chol(L_t).
+struct FixedArgs {
+  const double* om;        // [N*d] pseudo-observations of this proposal
+  double ovar;             // Omega = ovar I
+  const double *Sinv, *ldS, *Ec, *Lc;
+  double* Ephi;            // [N*D*D] Phi_{N-1-s} at s (written once)
+  double* U;               // [N*D] scan input
+  const double* mfr;       // [N*D] filtering means in reversed time (scan output)
+  const double* xi_x;      // [N*d] path normals, or nullptr (log-likelihood only)
+  double* ell;             // [N]
+  const int* setup_status; // failures of the one-off matrices, copied into status
+  int* status;
+  int fail_bit;
 };
 
 // Extended linearisation of nonlinear dynamics (one wave per time step):
@@ -287,6 +309,9 @@ hipError_t launch_adj_finish_any(int D, const KModel& M, LgArgs G, int nblk, con
                                  hipStream_t st);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 hipError_t launch_fact_scan(const KModel& M, FactArgs P, hipStream_t st);
+hipError_t launch_fixed_phi_any(int D, const KModel& M, FixedArgs A, hipStream_t st);
+hipError_t launch_fixed_cmean_any(int D, const KModel& M, FixedArgs A, hipStream_t st);
+hipError_t launch_fixed_ell_any(int D, const KModel& M, FixedArgs A, hipStream_t st);
 hipError_t launch_qinv(const KModel& M, double* Qinv, hipStream_t st);
 hipError_t launch_dnc_any(int D, const KModel& M, DncArgs A, hipStream_t st);
 int dnc_depth(int T);

@@ -1095,6 +1095,10 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       }
       double logdet;
       ok = spd_inv<D>(R2, d, B2, &logdet) && ok;
+      if (P.Sinv) {
+        rm_store<D>(R2, P.Sinv + (int64_t)t * D * D, D, D);
+        if (tid == 0) P.ldS[t] = logdet;
+      }
       rm_stage<D>(R2, B3);
       rm_stage<D>(Pp, B1);
       team_sync();
@@ -1190,6 +1194,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   double ld;
   if (t == M.N - 1) {
     ok = chol_reg<D>(Pf, d, B3, &ld);
+    if (S.Lc) rm_store<D>(Pf, S.Lc + (int64_t)t * D * D, D, D);
     rm_stage<D>(Pf, B2);
     team_sync();
     if (tid < D) {
@@ -1231,6 +1236,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     if (tid < D) vg[tid] = vm[tid] - vg[tid];  // g = m^f - E m^p
     rm_symmetrise<D>(R2, B2);
     ok = chol_reg<D>(R2, d, B3, &ld) && ok;
+    if (S.Lc) rm_store<D>(R2, S.Lc + (int64_t)t * D * D, D, D);
     rm_stage<D>(R2, B2);
     team_sync();
     if (tid < D) {

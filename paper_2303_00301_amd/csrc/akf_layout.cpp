@@ -39,7 +39,7 @@ int auto_block(int N, int D) {
   return B;
 }
 
-void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn) {
+void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn, bool fixed) {
   Lo.N = N;
   Lo.d = d;
   Lo.dy = dy;
@@ -94,6 +94,12 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
       Lo.Qinv = take((size_t)d * d * dbl);
       Lo.n_part_dyn = (N + 3) / 4;
       Lo.pdyn = take((size_t)Lo.n_part_dyn * dbl);
+    }
+    if (fixed) {
+      Lo.Sinv = take((size_t)N * D * D * dbl);
+      Lo.ldS = take((size_t)N * dbl);
+      Lo.Ephi = take((size_t)N * D * D * dbl);
+      Lo.Lc = take((size_t)N * D * D * dbl);
     }
   }
   if (kind == LAYOUT_FACT) {
@@ -169,7 +175,9 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     Lo.Pbar = take((size_t)N * D * D * dbl);
     Lo.part = take((size_t)Lo.nb * (2 * D * D + 2 * D) * dbl);
   }
-  Lo.status = take(2 * sizeof(int));  // two words: consecutive steps alternate
+  // two words: consecutive steps alternate; first-order runs add two for the
+  // set-up of the shared matrices
+  Lo.status = take((fixed ? 4 : 2) * sizeof(int));
   Lo.total = off;
 }
 
@@ -309,10 +317,12 @@ akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double*
                       const double* Om, const double* Omd, double* mf, double* Pf, int ldm,
                       double* ell, int* status, int fail_bit, hipStream_t st,
                       const double* yo, const double* Ho, const double* Ro, int dyo,
-                      const double* Ft, const double* bt) {
+                      const double* Ft, const double* bt, double* Sinv, double* ldS) {
   FilterArgs P{};
   P.Ft = Ft;
   P.bt = bt;
+  P.Sinv = Sinv;
+  P.ldS = ldS;
   P.yo = yo;
   P.Ho = Ho;
   P.Ro = Ro;
@@ -371,10 +381,11 @@ akf_status run_filter_logz(const Layout& Lo, const KModel& M, void* ws, const do
 
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
                        const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
-                       hipStream_t st, const double* Ft, const double* bt) {
+                       hipStream_t st, const double* Ft, const double* bt, double* Lc) {
   SampArgs S{};
   S.Ft = Ft;
   S.bt = bt;
+  S.Lc = Lc;
   S.B = Lo.B;
   S.mf = mf;
   S.Pf = Pf;

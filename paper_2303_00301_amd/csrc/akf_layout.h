@@ -33,6 +33,9 @@ struct Layout {
   // nonlinear dynamics: per-step F_t, b_t, Q^{-1}, mismatch partial sums
   size_t Ft = 0, bt = 0, Qinv = 0, pdyn = 0;
   int n_part_dyn = 0;
+  // first-order runs: matrices formed once per call (S^{-1}, log det S, the
+  // filtering-mean maps Phi in reversed time, chol(L)); the sampler's E stays in E
+  size_t Sinv = 0, ldS = 0, Ephi = 0, Lc = 0;
   // divide-and-conquer sampler tree
   size_t Elf = 0, glf = 0, Llf = 0, Eno = 0, gno = 0, Lno = 0, Gb = 0, Gam = 0, wb = 0, Vc = 0;
   // (E, g, L) scan, smoother and adjoint
@@ -54,7 +57,8 @@ T* at(void* ws, size_t off) {
 akf_status fail(akf_status s, const char* fmt, ...);
 int pick_D(int d);
 int auto_block(int N, int D);
-void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn = false);
+void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn = false,
+                 bool fixed = false);
 akf_status check_model(const akf_model* m, bool need_emission);
 akf_status check_order(const akf_model* m, int order);
 akf_status check_linear(const akf_model* m, const char* what);
@@ -69,14 +73,16 @@ akf_status run_filter(const Layout& Lo, const KModel& M, void* ws, const double*
                       double* ell, int* status, int fail_bit, hipStream_t st,
                       const double* yo = nullptr, const double* Ho = nullptr,
                       const double* Ro = nullptr, int dyo = 0, const double* Ft = nullptr,
-                      const double* bt = nullptr);
+                      const double* bt = nullptr, double* Sinv = nullptr,
+                      double* ldS = nullptr);
 akf_status run_filter_logz(const Layout& Lo, const KModel& M, void* ws, const double* om,
                            const double* Om, const double* Omd, int* status, int fail_bit,
                            hipStream_t st, const double* Ft, const double* bt,
                            const double** lz);
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
                        const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
-                       hipStream_t st, const double* Ft = nullptr, const double* bt = nullptr);
+                       hipStream_t st, const double* Ft = nullptr, const double* bt = nullptr,
+                       double* Lc = nullptr);
 void fill_egl_tree(const Layout& Lo, void* ws, EglTree* up, EglTree* down);
 akf_status run_egl(const Layout& Lo, void* ws, const double* g, double* outL, double* outg,
                    int ldo, int dout, hipStream_t st);

@@ -224,11 +224,16 @@ def mh_step(model: DeviceModel, y, x, delta: float, order: int, xi, unif, x_out=
 
 
 def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: int = 0,
-           ws: Optional[Workspace] = None, outputs: bool = True, factorised: bool = False) -> dict:
+           ws: Optional[Workspace] = None, outputs: bool = True, factorised: bool = False,
+           reuse_matrices: bool = False) -> dict:
     """n_steps MH steps, x updated in place.  xi [n_steps,2,N,dx], unif [n_steps].
-    factorised as in mh_step."""
+    factorised as in mh_step.  reuse_matrices (order 1, dense prior): the
+    auxiliary model's covariances are formed once for the whole call
+    (akf_mh_run_first_order); the chain is the same up to rounding."""
     lib = _lib.load()
     _check_form(model, factorised)
+    if reuse_matrices and (factorised or order != 1):
+        raise ValueError("reuse_matrices needs order 1 and the dense prior")
     dev = model.device
     N, dx = model.N, model.dx
     n = int(xi.shape[0])
@@ -252,6 +257,13 @@ def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: 
         rc = lib.akf_mh_run_factorised(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), n,
                                        _ptr(xi), _ptr(unif), *outs, wsp, wsb, _stream(dev))
         _lib.check(rc, "akf_mh_run_factorised")
+    elif reuse_matrices:
+        need = _need(lib.akf_mh_first_order_workspace_bytes(C.byref(ms), block),
+                     "akf_mh_first_order_workspace_bytes")
+        wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+        rc = lib.akf_mh_run_first_order(C.byref(ms), _ptr(y), _ptr(x), float(delta), n, _ptr(xi),
+                                        _ptr(unif), *outs, wsp, wsb, int(block), _stream(dev))
+        _lib.check(rc, "akf_mh_run_first_order")
     else:
         need = _need(lib.akf_mh_workspace_bytes(C.byref(ms), order, block),
                      "akf_mh_workspace_bytes")

@@ -181,3 +181,30 @@ def test_gauss_site_and_dnc_workspace():
     rc = lib.akf_dnc_sample(C.byref(_fake_model(N=100, dx=5)), p, p, p, None, None,
                             C.c_void_p(0x10000), 1 << 30, None)
     assert rc == 1  # x is required
+
+
+def test_first_order_run_validation():
+    lib = _lib.load()
+    m = _fake_model(N=128, dx=10)
+    base = lib.akf_mh_workspace_bytes(C.byref(m), 1, 0)
+    need = lib.akf_mh_first_order_workspace_bytes(C.byref(m), 0)
+    # three more [N, D, D] matrices (D = 16 here) and log det S
+    assert need >= base + 3 * 128 * 16 * 16 * 8 + 128 * 8
+    assert lib.akf_mh_first_order_workspace_bytes(C.byref(m), -1) == 0
+    p = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x100000)
+    call = lambda model, n=1, delta=0.5, wsb=need, block=0: lib.akf_mh_run_first_order(
+        C.byref(model), p, p, delta, n, p, p, None, None, None, None, None, ws, wsb, block, None)
+    assert call(m, n=-1) == 1
+    assert call(m, delta=0.0) == 1
+    assert call(m, block=-2) == 1
+    assert call(m, wsb=need - 1) == 3  # workspace too small
+    # nonlinear dynamics: the auxiliary model's matrices change with the path
+    nl = _fake_model(N=64, dx=3, dy=2, emit=5)
+    nl.scale = 1.0
+    nl.dyn = 1
+    nl.F = None
+    nl.dyn_par[3] = 2e-4
+    assert lib.akf_mh_first_order_workspace_bytes(C.byref(nl), 0) == 0
+    assert b"linear dynamics" in lib.akf_last_error()
+    assert call(nl) == 5
