@@ -354,7 +354,8 @@ void akf_batch_plan_destroy(akf_batch_plan* plan);
  * 4 sampler element build, 5 sampler fold, 6 sampler up-sweep, 7 sampler
  * down-sweep, 8 sampler final, 9 factorised scalar filter/sampler,
  * 10 emission and dynamics linearisation, 11 the whole divide-and-conquer
- * sampler), every launch of that kernel on any stream is
+ * sampler, 12 and 13 the block folds of akf_mh_run_first_order's filtering
+ * means and sampled path), every launch of that kernel on any stream is
  * bracketed by a pair of hipEvents recorded on the launch stream; at most
  * `capacity` launches are kept.  akf_timing_collect waits for the recorded
  * events and returns the number of launches and their summed duration in

@@ -95,7 +95,7 @@ SIGNATURES = {
 # kernel families of akf_timing_enable
 FAMILIES = {"filter_fold": 0, "filter_up": 1, "filter_down": 2, "filter_final": 3,
             "samp_build": 4, "samp_fold": 5, "samp_up": 6, "samp_down": 7, "samp_final": 8,
-            "fact_scan": 9, "lin": 10, "dnc": 11}
+            "fact_scan": 9, "lin": 10, "dnc": 11, "fixed_mean_fold": 12, "fixed_samp_fold": 13}
 
 _lib = None
 

@@ -167,27 +167,26 @@ akf_status fact_step_impl(const Layout& Lo, const KModel& M, const double* y, co
 // Under order 1, Omega_t = delta/2 I whatever the path, so the forward and
 // reverse auxiliary models of every step share P^p_t, S_t, P^f_t and the
 // sampler's E_t and L_t.  Step 0 runs the full filter and sampler, keeping
-// S_t^{-1}, log det S_t, chol(L_t) (E_t stays in the sampler's buffer), and
-// forms Phi_t = Omega S_t^{-1} F; every proposal after that is matrix-vector
-// work: the filtering means by an affine suffix scan over reversed time, the
-// log-likelihood terms from the kept S_t, the sampler elements from the kept
-// E_t and chol(L_t), then the sampler's suffix scan.  Set-up failures go to a
-// third status word that each step folds into its own.
-akf_status fixed_mean_scan(const Layout& Lo, const KModel& M, void* ws, int* status,
-                           hipStream_t st) {
-  SampArgs S{};
-  S.B = Lo.B;
-  S.E = at<double>(ws, Lo.Ephi);
-  S.U = at<double>(ws, Lo.U);
-  S.agg = at<double>(ws, Lo.sagg[0]);
-  S.xin = at<double>(ws, Lo.xin[0]);
-  S.xs = at<double>(ws, Lo.mf);  // means in reversed time, stride D
-  S.status = status;
-  TreeArgs up[kMaxLevels], down[kMaxLevels];
-  fill_tree(Lo, ws, 0, Lo.sagg, Lo.xin, status, ST_FWD_NOT_PD, up, down);
-  KModel Mv = M;
-  Mv.d = Lo.D;
-  return hip_check(launch_samp_scan_any(Lo.D, Mv, S, up, down, Lo.L, st), "mean scan launch");
+// S_t^{-1}, log det S_t, E_t and chol(L_t), and forms the node products of two
+// affine scans (the filtering means in reversed time with Phi_t =
+// Omega S_t^{-1} F, the sampled path with E_t).  Every proposal after that is
+// matrix-vector work: the means and log-likelihood terms in one kept scan,
+// the path in another.  Set-up failures go to a third status word that each
+// proposal folds into its step's own.
+struct KeptTree {
+  double* Tm[kMaxLevels + 1];
+  double* Uagg[kMaxLevels + 1];
+  double* xin[kMaxLevels + 1];
+};
+
+KeptTree kept_tree(const Layout& Lo, void* ws, const size_t* tm) {
+  KeptTree K{};
+  for (int l = 0; l <= Lo.L; ++l) {
+    K.Tm[l] = at<double>(ws, tm[l]);
+    K.Uagg[l] = at<double>(ws, Lo.vagg[l]);
+    K.xin[l] = at<double>(ws, Lo.xin[l]);
+  }
+  return K;
 }
 
 akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
@@ -198,7 +197,6 @@ akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, c
   const size_t vn = (size_t)M.N * M.d;
   const int D = Lo.D;
   const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, 1, xi, step);
-  int* status = A.status;
   int* setup_status = at<int>(ws, Lo.status) + 2;
   akf_status s;
   if (step == 0) {
@@ -214,63 +212,63 @@ akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, c
   if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
   double* Sinv = at<double>(ws, Lo.Sinv);
   double* ldS = at<double>(ws, Lo.ldS);
-  double* Ec = at<double>(ws, Lo.E);
+  double* Et = at<double>(ws, Lo.Et);
   double* Lc = at<double>(ws, Lo.Lc);
+  double* Phi = at<double>(ws, Lo.Phi);
+  double* mf = at<double>(ws, Lo.mf);
   FixedArgs X{};
+  X.B = Lo.B;
   // the linearisation's Omega, bit for bit
   X.ovar = M.emit == EMIT_GAUSSIAN ? 0.5 * delta : 1.0 / (2.0 / delta);
   X.Sinv = Sinv;
   X.ldS = ldS;
-  X.Ec = Ec;
+  X.Et = Et;
   X.Lc = Lc;
-  X.Ephi = at<double>(ws, Lo.Ephi);
-  X.U = at<double>(ws, Lo.U);
-  X.mfr = at<double>(ws, Lo.mf);
+  X.Phi = Phi;
+  X.Fp = at<double>(ws, Lo.Fp);
+  X.mf = mf;
+  X.W = at<double>(ws, Lo.U);
+  X.G = at<double>(ws, Lo.Gs);
+  X.xs = A.xs;
+  X.xi_x = xi + vn;
   X.setup_status = setup_status;
-  X.status = status;
-  X.fail_bit = ST_FWD_NOT_PD;
+  X.status = A.status;
+  const KeptTree Kphi = kept_tree(Lo, ws, Lo.tphi), Ke = kept_tree(Lo, ws, Lo.te);
   if (step == 0) {
-    double* mf = at<double>(ws, Lo.mf);
     double* Pf = at<double>(ws, Lo.Pf);
     if ((s = run_filter(Lo, M, ws, A.om, A.Om, nullptr, mf, Pf, D, A.ell, setup_status,
                         ST_FWD_NOT_PD, st, nullptr, nullptr, nullptr, 0, nullptr, nullptr, Sinv,
                         ldS)) != AKF_OK)
       return s;
     if ((s = run_sampler(Lo, M, ws, mf, Pf, D, xi + vn, A.xs, setup_status, st, nullptr, nullptr,
-                         Lc)) != AKF_OK)
+                         Lc, Et)) != AKF_OK)
       return s;
     if ((s = hip_check(launch_fixed_phi_any(D, M, X, st), "Phi launch")) != AKF_OK) return s;
+    const VScanArgs Vphi{M.N, Lo.B, Phi}, Ve{M.N, Lo.B, Et};
+    if ((s = hip_check(launch_vtree_mats_any(D, Vphi, Kphi.Tm, Lo.n_lvl, Lo.L, st),
+                       "scan products launch")) != AKF_OK)
+      return s;
+    if ((s = hip_check(launch_vtree_mats_any(D, Ve, Ke.Tm, Lo.n_lvl, Lo.L, st),
+                       "scan products launch")) != AKF_OK)
+      return s;
   } else {
     X.om = A.om;
-    if ((s = hip_check(launch_fixed_cmean_any(D, M, X, st), "mean element launch")) != AKF_OK)
-      return s;
-    if ((s = fixed_mean_scan(Lo, M, ws, status, st)) != AKF_OK) return s;
-    X.xi_x = xi + vn;
     X.ell = A.ell;
-    if ((s = hip_check(launch_fixed_ell_any(D, M, X, st), "log-likelihood launch")) != AKF_OK)
+    if ((s = hip_check(launch_fixed_scan_any(D, 0, M, X, Kphi.Tm, Kphi.Uagg, Kphi.xin, Lo.n_lvl,
+                                             Lo.L, st),
+                       "mean scan launch")) != AKF_OK)
       return s;
-    SampArgs S{};
-    S.B = Lo.B;
-    S.E = Ec;
-    S.U = X.U;
-    S.agg = at<double>(ws, Lo.sagg[0]);
-    S.xin = at<double>(ws, Lo.xin[0]);
-    S.xs = A.xs;
-    S.status = status;
-    TreeArgs up[kMaxLevels], down[kMaxLevels];
-    fill_tree(Lo, ws, 0, Lo.sagg, Lo.xin, status, ST_FWD_NOT_PD, up, down);
-    if ((s = hip_check(launch_samp_scan_any(D, M, S, up, down, Lo.L, st), "sampler launch")) !=
-        AKF_OK)
+    if ((s = hip_check(launch_fixed_scan_any(D, 1, M, X, Ke.Tm, Ke.Uagg, Ke.xin, Lo.n_lvl, Lo.L,
+                                             st),
+                       "sampler scan launch")) != AKF_OK)
       return s;
   }
   if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
   X.om = A.om2;
-  X.xi_x = nullptr;
   X.ell = A.ell2;
-  if ((s = hip_check(launch_fixed_cmean_any(D, M, X, st), "mean element launch")) != AKF_OK)
-    return s;
-  if ((s = fixed_mean_scan(Lo, M, ws, status, st)) != AKF_OK) return s;
-  if ((s = hip_check(launch_fixed_ell_any(D, M, X, st), "log-likelihood launch")) != AKF_OK)
+  if ((s = hip_check(launch_fixed_scan_any(D, 0, M, X, Kphi.Tm, Kphi.Uagg, Kphi.xin, Lo.n_lvl,
+                                           Lo.L, st),
+                     "mean scan launch")) != AKF_OK)
     return s;
   FinalArgs F{};
   F.status_next = at<int>(ws, Lo.status) + ((step + 1) & 1);

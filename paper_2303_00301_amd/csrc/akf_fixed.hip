@@ -1,21 +1,32 @@
 // akf_fixed.hip -- MH steps whose auxiliary model keeps the same covariances
-// from step to step.
+// from step to step, with every matrix formed once per call.
 //
 // Under first-order proposals Omega_t = delta/2 I for every t and every path
 // (eq. gaussian-FK-proposal with Sigma_t = I), so every covariance of the
-// auxiliary LGSSM -- P^p_t, P^f_t, S_t, the sampler's E_t and L_t -- is the same
-// at every step and for the forward and reverse proposals alike: they depend on
-// the path only through Omega_t.  A run forms them once (the full filter and
-// sampler element build, keeping S_t^{-1}, log det S_t, E_t and chol(L_t)); each
-// proposal then needs matrix-vector work only:
-//   cmean : c_t = omega_t - Omega S_t^{-1} (omega_t - b) (t = 0: with m0), so
-//           that m^f_t = Phi_t m^f_{t-1} + c_t with Phi_t = Omega S_t^{-1} F;
-//   scan  : that affine recursion, run in reversed time through the pathwise
-//           sampler's suffix scan (Phi_0 = 0 is its terminal element);
-//   ell   : ell_t = log N(omega_t; F m^f_{t-1} + b, S_t) from S_t^{-1} and
-//           log det S_t, and for the forward proposal the sampler elements
-//           U_t = m^f_t - E_t (F m^f_t + b) + chol(L_t) xi_t.
-// One team per time step.
+// auxiliary LGSSM -- P^p_t, P^f_t, S_t, the sampler's E_t and L_t -- is the
+// same at every step and for the forward and reverse proposals alike: they
+// depend on the path only through Omega_t.  What changes from proposal to
+// proposal is linear in the pseudo-observations:
+//   filtering means  m^f_t = omega_t - Omega S_t^{-1} r_t with the innovation
+//                    r_t = omega_t - (F m^f_{t-1} + b) (t = 0: omega_0 - m0),
+//                    an affine recursion whose map is Phi_t = Omega S_t^{-1} F;
+//   log-likelihood   ell_t = -1/2 (d log 2 pi + log det S_t + r_t' S_t^{-1} r_t);
+//   sampled path     x_t = E_t (x_{t+1} - g_t) + w_t with g_t = F m^f_t + b and
+//                    w_t = m^f_t + chol(L_t) xi_t (App. A, eq. sampling-op-app).
+// Both recursions are affine suffix scans with fixed matrices (the means run in
+// reversed time, s = N - 1 - t), so the scan's matrix parts -- the products
+// over each block and each tree node -- are fixed too.  A run keeps them all
+// (set-up: k_fixed_phi, k_vtree_fold_mat, k_vtree_up_mat); each proposal then
+// runs a block fold, the tree's vector parts (k_vup_span, k_vdown_span) and a
+// block final per scan, where one step of a block is one product with the
+// kept S_t^{-1} (means, with F held in LDS) or E_t (path): matrix-vector work
+// throughout, bound by reading the kept matrices from HBM.
+//
+// Every kept matrix is stored transposed (At[j*D + i] = A_ij): in a product
+// y = A x, thread i % D of group g = i / D accumulates row i over the columns
+// [g*D/G, (g+1)*D/G), so each of its loads is one coalesced column of D
+// doubles; the G group partials are summed by lane shuffles (one wave, D < 64)
+// or through LDS (D = 64, one group per wave).
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -30,35 +41,72 @@ namespace {
 constexpr double LOG2PI_X = 1.8378770664093454835606594728112;
 
 template <int D>
+struct GMV {
+  static constexpr int NT = Cfg<D>::NT;
+  static constexpr int G = NT / D;   // column groups
+  static constexpr int JG = D / G;   // columns per group
+};
+
+// this thread's JG entries of row threadIdx.x % D of A (At transposed, stride D)
+template <int D>
+__device__ __forceinline__ void gmv_load(double (&a)[GMV<D>::JG], const double* __restrict__ At) {
+  const int i = threadIdx.x % D, g = threadIdx.x / D;
+#pragma unroll
+  for (int jj = 0; jj < GMV<D>::JG; ++jj) a[jj] = At[(g * GMV<D>::JG + jj) * D + i];
+}
+
+template <int D>
+__device__ __forceinline__ double gmv_dot(const double (&a)[GMV<D>::JG], const double* x) {
+  const int g = threadIdx.x / D;
+  double s = 0.0;
+#pragma unroll
+  for (int jj = 0; jj < GMV<D>::JG; ++jj) s = fma(a[jj], x[g * GMV<D>::JG + jj], s);
+  return s;
+}
+
+// Sum of the group partials of row threadIdx.x % D, valid in threads
+// threadIdx.x < D.  Begins with a barrier when D = 64 (red: NT doubles).
+template <int D>
+__device__ __forceinline__ double gmv_combine(double s, double* red) {
+  if constexpr (GMV<D>::NT > 64) {
+    red[threadIdx.x] = s;
+    team_sync();
+    double t = 0.0;
+    if (threadIdx.x < D) {
+#pragma unroll
+      for (int g = 0; g < GMV<D>::G; ++g) t += red[g * D + threadIdx.x];
+    }
+    return t;
+  } else {
+#pragma unroll
+    for (int m = D; m < 64; m <<= 1) s += __shfl_xor(s, m);
+    return s;
+  }
+}
+
+// y[i] = add[i] + (A x)_i, i < D; x in LDS, add (LDS or global) may be null
+// and may alias y.  Team-wide; ends with a barrier after which y is visible.
+template <int D>
+__device__ __forceinline__ void gmv(double* y, const double* __restrict__ At, const double* x,
+                                    const double* add, double* red) {
+  double a[GMV<D>::JG];
+  gmv_load<D>(a, At);
+  const double s = gmv_combine<D>(gmv_dot<D>(a, x), red);
+  if (threadIdx.x < D) y[threadIdx.x] = s + (add ? add[threadIdx.x] : 0.0);
+  team_sync();
+}
+
+template <int D>
 __device__ __forceinline__ void xload_pad(double* s, const double* __restrict__ g) {
   for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) s[(e / D) * Cfg<D>::LD + (e % D)] = g[e];
 }
 
-template <int D>
-__device__ __forceinline__ void xload_user(double* s, const double* __restrict__ g, int d) {
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
-    const int i = e / D, j = e % D;
-    s[i * Cfg<D>::LD + j] = (i < d && j < d) ? g[i * d + j] : 0.0;
-  }
-}
+// ---------------------------------------------------------------------------
+// Set-up
+// ---------------------------------------------------------------------------
 
-// LDS doubles of each kernel: phi two matrices; cmean one matrix and two
-// vectors; ell two matrices and its vectors, two more matrices with the
-// sampler elements
-template <int D>
-constexpr int lds_phi() {
-  return 2 * Cfg<D>::MAT;
-}
-template <int D>
-constexpr int lds_cmean() {
-  return Cfg<D>::MAT + 2 * D;
-}
-template <int D>
-constexpr int lds_ell(bool samp) {
-  return (samp ? 4 : 2) * Cfg<D>::MAT + 8 * D + 16;
-}
-
-// Phi_t = Omega S_t^{-1} F, stored at reversed index N - 1 - t; Phi_0 = 0.
+// Phi_t^T = Omega F^T S_t^{-T} at reversed index N - 1 - t; Phi_0 = 0.  Team 0
+// also keeps F (padded, transposed) for the per-step products.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_phi(KModel M, FixedArgs A) {
   using C = Cfg<D>;
@@ -66,145 +114,522 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_phi(KModel M, FixedArgs A)
   double* B1 = lds;
   double* B2 = B1 + C::MAT;
   const int t = blockIdx.x, d = M.d;
-  double* out = A.Ephi + (int64_t)(M.N - 1 - t) * D * D;
+  double* out = A.Phi + (int64_t)(M.N - 1 - t) * D * D;
   RM<D> R;
   if (t == 0) {
     rm_zero<D>(R);
     rm_store<D>(R, out, D, D);
+    for (int e = threadIdx.x; e < D * D; e += C::NT) {
+      const int j = e / D, i = e % D;
+      A.Fp[e] = (i < d && j < d) ? M.F[i * d + j] : 0.0;
+    }
     return;
   }
-  xload_pad<D>(B1, A.Sinv + (int64_t)t * D * D);
-  xload_user<D>(B2, M.F, d);
+  for (int e = threadIdx.x; e < D * D; e += C::NT) {
+    const int i = e / D, j = e % D;
+    B1[i * C::LD + j] = (i < d && j < d) ? M.F[j * d + i] : 0.0;  // F^T
+  }
+  xload_pad<D>(B2, A.Sinv + (int64_t)t * D * D);  // the kept S^{-1} reads as S^{-T}
   team_sync();
-  gemm<D, false, false, false>(R, B1, B2);  // S^{-1} F
+  gemm<D, false, false, false>(R, B1, B2);
 #pragma unroll
   for (int q = 0; q < Cfg<D>::TPW; ++q) R.t[q] *= A.ovar;
   rm_store<D>(R, out, D, D);
 }
 
-// c_t (reversed index) from this proposal's pseudo-observations.
+// Block products of a kept scan: node k maps the state after its steps to its
+// first state, M_{s0} M_{s0+1} ... M_{s1-1}; in transposed form the product
+// accumulates on the right from the last step back.
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_cmean(KModel M, FixedArgs A) {
+__global__ void __launch_bounds__(Cfg<D>::NT) k_vtree_fold_mat(VScanArgs V, double* Tm0) {
   using C = Cfg<D>;
   extern __shared__ double lds[];
   double* B1 = lds;
-  double* vw = B1 + C::MAT;
-  double* vv = vw + D;
-  const int t = blockIdx.x, tid = threadIdx.x, d = M.d;
-  if (t == 0 && tid == 0 && *A.setup_status) atomicOr(A.status, *A.setup_status);
-  xload_pad<D>(B1, A.Sinv + (int64_t)t * D * D);
-  const double* om = A.om + (int64_t)t * d;
-  if (tid < D) {
-    const double mu = (tid < d) ? (t == 0 ? M.m0[tid] : (M.b ? M.b[tid] : 0.0)) : 0.0;
-    vw[tid] = (tid < d) ? om[tid] - mu : 0.0;
+  double* B2 = B1 + C::MAT;
+  const int k = blockIdx.x;
+  const int s0 = k * V.B, s1 = min(V.N, s0 + V.B);
+  RM<D> acc;
+  rm_load<D>(acc, V.Mt + (int64_t)(s1 - 1) * D * D, D, D);
+  for (int s = s1 - 2; s >= s0; --s) {
+    rm_stage<D>(acc, B1);
+    xload_pad<D>(B2, V.Mt + (int64_t)s * D * D);
+    team_sync();
+    gemm<D, false, false, false>(acc, B1, B2);
+    team_sync();
   }
-  team_sync();
-  matvec<D, false>(vv, B1, vw);  // S^{-1} (omega - mu)
-  if (tid < D) A.U[(int64_t)(M.N - 1 - t) * D + tid] = (tid < d) ? om[tid] - A.ovar * vv[tid] : 0.0;
+  rm_store<D>(acc, Tm0 + (int64_t)k * D * D, D, D);
 }
 
-// ell_t, and (with xi_x) the sampler elements U_t.
+// Tree node k of the next level: left (earlier) o right, (M_l M_r)^T = M_r^T M_l^T.
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_ell(KModel M, FixedArgs A) {
+__global__ void __launch_bounds__(Cfg<D>::NT) k_vtree_up_mat(const double* src, double* dst,
+                                                             int n_src) {
   using C = Cfg<D>;
   extern __shared__ double lds[];
-  double* sF = lds;
-  double* B1 = sF + C::MAT;
-  double* vm = B1 + C::MAT;  // m^f_t
-  double* vq = vm + D;       // m^f_{t-1}
-  double* vp = vq + D;       // m^p_t, then F m^f_t + b
-  double* vr = vp + D;       // residual
-  double* vs = vr + D;       // S^{-1} r
-  double* vx = vs + D;       // xi_t
-  double* vu = vx + D;
-  double* vb = vu + D;       // b, zero-padded
-  double* red = vb + D;
-  double* B2 = red + 16;     // E_t and chol(L_t): sampler elements only
-  double* B3 = B2 + C::MAT;
-  const int t = blockIdx.x, tid = threadIdx.x, d = M.d, N = M.N;
-  const bool samp = A.xi_x != nullptr;
-  xload_user<D>(sF, M.F, d);
-  xload_pad<D>(B1, A.Sinv + (int64_t)t * D * D);
-  if (samp) {
-    if (t < N - 1) xload_pad<D>(B2, A.Ec + (int64_t)t * D * D);
-    xload_pad<D>(B3, A.Lc + (int64_t)t * D * D);
+  double* B1 = lds;
+  double* B2 = B1 + C::MAT;
+  const int k = blockIdx.x;
+  const double* l = src + (int64_t)(2 * k) * D * D;
+  double* out = dst + (int64_t)k * D * D;
+  if (2 * k + 1 >= n_src) {
+    for (int e = threadIdx.x; e < D * D; e += C::NT) out[e] = l[e];
+    return;
   }
+  xload_pad<D>(B1, l + D * D);
+  xload_pad<D>(B2, l);
+  team_sync();
+  RM<D> R;
+  gemm<D, false, false, false>(R, B1, B2);
+  rm_store<D>(R, out, D, D);
+}
+
+// ---------------------------------------------------------------------------
+// Per proposal: filtering means and log-likelihood terms
+// ---------------------------------------------------------------------------
+
+// What a mean step reads from HBM: its row group of the kept S_t^{-1}, omega_t
+// and log det S_t.
+template <int D>
+struct MeanStep {
+  double a[GMV<D>::JG];
+  double om, lds;
+};
+
+template <int D>
+__device__ __forceinline__ void mean_fetch(MeanStep<D>& m, const KModel& M, const FixedArgs& A,
+                                           int t) {
+  gmv_load<D>(m.a, A.Sinv + (int64_t)t * D * D);
+  m.om = (threadIdx.x < M.d) ? A.om[(int64_t)t * M.d + threadIdx.x] : 0.0;
+  m.lds = A.ldS[t];
+}
+
+template <int D>
+struct MeanLds {
+  double Ft[D * D];  // F, transposed and padded
+  double b[D], m0[D];
+  double xv[2][D];
+  double rv[D];
+  double red[GMV<D>::NT];
+};
+
+template <int D>
+__device__ __forceinline__ void mean_lds_init(MeanLds<D>& L, const KModel& M) {
+  const int d = M.d;
+  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
+    const int j = e / D, i = e % D;
+    L.Ft[e] = (i < d && j < d) ? M.F[i * d + j] : 0.0;
+  }
+  if (threadIdx.x < D) {
+    L.b[threadIdx.x] = (M.b && threadIdx.x < d) ? M.b[threadIdx.x] : 0.0;
+    L.m0[threadIdx.x] = (threadIdx.x < d) ? M.m0[threadIdx.x] : 0.0;
+  }
+}
+
+// The mean recursion over reversed steps s_hi down to s_lo (t = N - 1 - s
+// ascending) from the state in L.xv[0]; the next two steps' reads are in
+// flight while one is applied.  FINAL also writes m^f_t and ell_t.  Returns
+// the buffer that holds the last state.
+template <int D, bool FINAL>
+__device__ double* mean_chain(const KModel& M, const FixedArgs& A, int s_hi, int s_lo,
+                              MeanLds<D>& L) {
+  using V = GMV<D>;
+  const int tid = threadIdx.x, i = tid % D, g = tid / D, d = M.d, N = M.N;
+  MeanStep<D> m0, m1, m2;
+  if (s_hi >= s_lo) mean_fetch<D>(m0, M, A, N - 1 - s_hi);
+  if (s_hi - 1 >= s_lo) mean_fetch<D>(m1, M, A, N - s_hi);
+  int cur = 0;
+  for (int s = s_hi; s >= s_lo; --s) {
+    const int t = N - 1 - s;
+    if (s - 2 >= s_lo) mean_fetch<D>(m2, M, A, t + 2);
+    double mp;
+    if (t > 0) {
+      double pf = 0.0;
+#pragma unroll
+      for (int jj = 0; jj < V::JG; ++jj) {
+        const int j = g * V::JG + jj;
+        pf = fma(L.Ft[j * D + i], L.xv[cur][j], pf);
+      }
+      mp = gmv_combine<D>(pf, L.red) + L.b[i];
+    } else {
+      mp = L.m0[i];
+    }
+    if (tid < D) L.rv[tid] = (tid < d) ? m0.om - mp : 0.0;
+    team_sync();
+    const double y = gmv_combine<D>(gmv_dot<D>(m0.a, L.rv), L.red);  // S^{-1} r
+    if (tid < D) {
+      const double xn = (tid < d) ? m0.om - A.ovar * y : 0.0;
+      L.xv[cur ^ 1][tid] = xn;
+      if (FINAL) A.mf[(int64_t)t * D + tid] = xn;
+    }
+    if (FINAL && tid < 64) {
+      double q = (tid < D) ? L.rv[tid] * y : 0.0;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) q += __shfl_xor(q, o);
+      if (tid == 0) A.ell[t] = -0.5 * (d * LOG2PI_X + m0.lds + q);
+    }
+    team_sync();
+    cur ^= 1;
+    m0 = m1;
+    m1 = m2;
+  }
+  return L.xv[cur];
+}
+
+// Block fold of the means: the vector part of the block's map (zero state
+// entering from the right).  Team 0 folds the set-up failures into this
+// step's status.
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_mfold(KModel M, FixedArgs A, double* Uagg0) {
+  __shared__ MeanLds<D> L;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  if (k == 0 && tid == 0 && *A.setup_status) atomicOr(A.status, *A.setup_status);
+  const int s0 = k * A.B, s1 = min(M.N, s0 + A.B);
+  mean_lds_init<D>(L, M);
+  if (tid < D) L.xv[0][tid] = 0.0;
+  team_sync();
+  const double* x = mean_chain<D, false>(M, A, s1 - 1, s0, L);
+  if (tid < D) Uagg0[(int64_t)k * D + tid] = x[tid];
+}
+
+// Block final of the means: m^f_t and ell_t of every step of the block.
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_mfinal(KModel M, FixedArgs A, const double* xin0) {
+  __shared__ MeanLds<D> L;
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int s0 = k * A.B, s1 = min(M.N, s0 + A.B);
+  mean_lds_init<D>(L, M);
+  if (tid < D) L.xv[0][tid] = xin0[(int64_t)k * D + tid];
+  team_sync();
+  mean_chain<D, true>(M, A, s1 - 1, s0, L);
+}
+
+// ---------------------------------------------------------------------------
+// Per proposal: the sampled path
+// ---------------------------------------------------------------------------
+
+// w_t = m^f_t + chol(L_t) xi_t and g_t = F m^f_t + b (g_{N-1} = 0), one team
+// per step.
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_sw(KModel M, FixedArgs A) {
+  __shared__ double vx[D], vm[D], vb[D], red[GMV<D>::NT];
+  const int t = blockIdx.x, tid = threadIdx.x, d = M.d;
   if (tid < D) {
-    vm[tid] = A.mfr[(int64_t)(N - 1 - t) * D + tid];
-    vq[tid] = (t > 0) ? A.mfr[(int64_t)(N - t) * D + tid] : 0.0;
-    vx[tid] = (samp && tid < d) ? A.xi_x[(int64_t)t * d + tid] : 0.0;
+    vx[tid] = (tid < d) ? A.xi_x[(int64_t)t * d + tid] : 0.0;
+    vm[tid] = A.mf[(int64_t)t * D + tid];
     vb[tid] = (M.b && tid < d) ? M.b[tid] : 0.0;
   }
   team_sync();
-  if (t > 0) {
-    matvec<D, false>(vp, sF, vq, vb);  // F m^f_{t-1} + b
+  gmv<D>(A.W + (int64_t)t * D, A.Lc + (int64_t)t * D * D, vx, vm, red);
+  if (t < M.N - 1) {
+    gmv<D>(A.G + (int64_t)t * D, A.Fp, vm, vb, red);
   } else if (tid < D) {
-    vp[tid] = (tid < d) ? M.m0[tid] : 0.0;
+    A.G[(int64_t)t * D + tid] = 0.0;
+  }
+}
+
+template <int D>
+struct SampStep {
+  double a[GMV<D>::JG], gj[GMV<D>::JG];
+  double w;
+};
+
+template <int D>
+__device__ __forceinline__ void samp_fetch(SampStep<D>& m, const FixedArgs& A, int s) {
+  gmv_load<D>(m.a, A.Et + (int64_t)s * D * D);
+  const int g = threadIdx.x / D;
+#pragma unroll
+  for (int jj = 0; jj < GMV<D>::JG; ++jj) m.gj[jj] = A.G[(int64_t)s * D + g * GMV<D>::JG + jj];
+  m.w = (threadIdx.x < D) ? A.W[(int64_t)s * D + threadIdx.x] : 0.0;
+}
+
+// x_s = E_s (x_{s+1} - g_s) + w_s for s from s_hi down to s_lo, from the state
+// in xv[0]; FINAL writes the path.  Returns the buffer with the last state.
+template <int D, bool FINAL>
+__device__ double* samp_chain(const KModel& M, const FixedArgs& A, int s_hi, int s_lo,
+                              double (*xv)[D], double* red) {
+  using V = GMV<D>;
+  const int tid = threadIdx.x, g = tid / D;
+  SampStep<D> m0, m1, m2;
+  if (s_hi >= s_lo) samp_fetch<D>(m0, A, s_hi);
+  if (s_hi - 1 >= s_lo) samp_fetch<D>(m1, A, s_hi - 1);
+  int cur = 0;
+  for (int s = s_hi; s >= s_lo; --s) {
+    if (s - 2 >= s_lo) samp_fetch<D>(m2, A, s - 2);
+    double p = 0.0;
+#pragma unroll
+    for (int jj = 0; jj < V::JG; ++jj) p = fma(m0.a[jj], xv[cur][g * V::JG + jj] - m0.gj[jj], p);
+    const double xn = gmv_combine<D>(p, red) + m0.w;
+    if (tid < D) {
+      xv[cur ^ 1][tid] = xn;
+      if (FINAL && tid < M.d) A.xs[(int64_t)s * M.d + tid] = xn;
+    }
+    team_sync();
+    cur ^= 1;
+    m0 = m1;
+    m1 = m2;
+  }
+  return xv[cur];
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_sfold(KModel M, FixedArgs A, double* Uagg0) {
+  __shared__ double xv[2][D];
+  __shared__ double red[GMV<D>::NT];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int s0 = k * A.B, s1 = min(M.N, s0 + A.B);
+  if (tid < D) xv[0][tid] = 0.0;
+  team_sync();
+  const double* x = samp_chain<D, false>(M, A, s1 - 1, s0, xv, red);
+  if (tid < D) Uagg0[(int64_t)k * D + tid] = x[tid];
+}
+
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_sfinal(KModel M, FixedArgs A, const double* xin0) {
+  __shared__ double xv[2][D];
+  __shared__ double red[GMV<D>::NT];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  const int s0 = k * A.B, s1 = min(M.N, s0 + A.B);
+  if (tid < D) xv[0][tid] = xin0[(int64_t)k * D + tid];
+  team_sync();
+  samp_chain<D, true>(M, A, s1 - 1, s0, xv, red);
+}
+
+// ---------------------------------------------------------------------------
+// The kept tree's vector parts
+// ---------------------------------------------------------------------------
+
+// Up-sweep over levels lo .. lo + R: the node k of level lo + R and the nodes
+// of its subtree, level by level; node j of level lo + r is
+// u_j = M_{2j} u_{2j+1} + u_{2j} over its children at level lo + r - 1 (the
+// left child alone is copied).  A level's matrices are loaded together, then
+// applied one node at a time by the whole team.
+template <int D, int R>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_vup_span(VTreeSpan T) {
+  using V = GMV<D>;
+  constexpr int PMAX = 1 << (R - 1);
+  __shared__ double ph[2][1 << R][64];
+  __shared__ double red[V::NT];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  constexpr int C0 = 1 << R;
+  for (int e = tid; e < C0 * D; e += V::NT) {
+    const int c = e / D, j = k * C0 + c;
+    ph[0][c][e % D] = (j < T.n[0]) ? T.U[0][(int64_t)j * D + e % D] : 0.0;
   }
   team_sync();
-  if (tid < D) vr[tid] = (tid < d) ? A.om[(int64_t)t * d + tid] - vp[tid] : 0.0;
-  team_sync();
-  matvec<D, false>(vs, B1, vr);
-  const double q = team_sum<D>(tid < D ? vr[tid] * vs[tid] : 0.0, red);
-  if (tid == 0) A.ell[t] = -0.5 * (d * LOG2PI_X + A.ldS[t] + q);
-  if (!samp) return;
-  matvec<D, false>(vu, B3, vx, vm);  // m^f + chol(L) xi
-  if (t < N - 1) {
-    matvec<D, false>(vp, sF, vm, vb);  // F m^f_t + b
-    matvec<D, false>(vr, B2, vp);       // E_t (F m^f_t + b)
-    if (tid < D) vu[tid] -= vr[tid];
+  int cur = 0;
+#pragma unroll
+  for (int r = 1; r <= R; ++r) {
+    const int P = 1 << (R - r);
+    double a[PMAX][V::JG];
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      const int j = k * P + q;
+      if (q < P && 2 * j + 1 < T.n[r - 1]) gmv_load<D>(a[q], T.Tm[r - 1] + (int64_t)(2 * j) * D * D);
+    }
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      const int j = k * P + q;
+      if (q < P && j < T.n[r]) {
+        double y = 0.0;
+        if (2 * j + 1 < T.n[r - 1]) y = gmv_combine<D>(gmv_dot<D>(a[q], ph[cur][2 * q + 1]), red);
+        if (tid < D) {
+          y += ph[cur][2 * q][tid];
+          ph[cur ^ 1][q][tid] = y;
+          T.U[r][(int64_t)j * D + tid] = y;
+        }
+        team_sync();
+      }
+    }
+    cur ^= 1;
   }
-  if (tid < D) A.U[(int64_t)t * D + tid] = (tid < d) ? vu[tid] : 0.0;
+}
+
+// Down-sweep over levels lo + R down to lo: from the state entering node k of
+// level lo + R, each node j hands it to its right child 2j + 1 and gives its
+// left child M_{2j+1} x + u_{2j+1} (or the state itself when alone).
+template <int D, int R>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_vdown_span(VTreeSpan T) {
+  using V = GMV<D>;
+  constexpr int PMAX = 1 << (R - 1);
+  __shared__ double ph[2][1 << R][64];
+  __shared__ double red[V::NT];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  if (tid < D) ph[0][0][tid] = T.X[R][(int64_t)k * D + tid];
+  team_sync();
+  int cur = 0;
+#pragma unroll
+  for (int r = R; r >= 1; --r) {
+    const int P = 1 << (R - r);  // parents of this level in the subtree
+    double a[PMAX][V::JG], ur[PMAX];
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      const int j = k * P + q;
+      ur[q] = 0.0;
+      if (q < P && 2 * j + 1 < T.n[r - 1]) {
+        gmv_load<D>(a[q], T.Tm[r - 1] + (int64_t)(2 * j + 1) * D * D);
+        if (tid < D) ur[q] = T.U[r - 1][(int64_t)(2 * j + 1) * D + tid];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PMAX; ++q) {
+      const int j = k * P + q;
+      if (q < P && j < T.n[r]) {
+        const double* xp = ph[cur][q];
+        double* xl = T.X[r - 1] + (int64_t)(2 * j) * D;
+        if (2 * j + 1 < T.n[r - 1]) {
+          const double y = gmv_combine<D>(gmv_dot<D>(a[q], xp), red);
+          if (tid < D) {
+            const double yl = y + ur[q];
+            ph[cur ^ 1][2 * q][tid] = yl;
+            ph[cur ^ 1][2 * q + 1][tid] = xp[tid];
+            xl[tid] = yl;
+            xl[D + tid] = xp[tid];
+          }
+        } else if (tid < D) {
+          ph[cur ^ 1][2 * q][tid] = xp[tid];
+          xl[tid] = xp[tid];
+        }
+        team_sync();
+      }
+    }
+    cur ^= 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <int D>
+constexpr size_t lds_two_mats() {
+  return (size_t)2 * Cfg<D>::MAT * sizeof(double);
 }
 
 template <int D>
 hipError_t set_limits() {
-  hipError_t e;
-  if ((e = hipFuncSetAttribute((const void*)k_fixed_phi<D>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds_phi<D>() * (int)sizeof(double))) != hipSuccess)
-    return e;
-  if ((e = hipFuncSetAttribute((const void*)k_fixed_cmean<D>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize,
-                               lds_cmean<D>() * (int)sizeof(double))) != hipSuccess)
-    return e;
-  return hipFuncSetAttribute((const void*)k_fixed_ell<D>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize,
-                             lds_ell<D>(true) * (int)sizeof(double));
+  const void* k[3] = {(const void*)k_fixed_phi<D>, (const void*)k_vtree_fold_mat<D>,
+                      (const void*)k_vtree_up_mat<D>};
+  for (const void* f : k) {
+    const hipError_t e =
+        hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_two_mats<D>());
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 template <int D>
-hipError_t launch_k(int which, const KModel& M, FixedArgs A, hipStream_t st) {
-  static const hipError_t lim = set_limits<D>();  // once per process
-  if (lim != hipSuccess) return lim;
-  const dim3 g(M.N), b(Cfg<D>::NT);
-  const size_t dbl = sizeof(double);
-  if (which == 0) hipLaunchKernelGGL(k_fixed_phi<D>, g, b, lds_phi<D>() * dbl, st, M, A);
-  if (which == 1) hipLaunchKernelGGL(k_fixed_cmean<D>, g, b, lds_cmean<D>() * dbl, st, M, A);
-  if (which == 2)
-    hipLaunchKernelGGL(k_fixed_ell<D>, g, b, lds_ell<D>(A.xi_x != nullptr) * dbl, st, M, A);
+hipError_t limits() {
+  static const hipError_t e = set_limits<D>();  // once per process
+  return e;
+}
+
+template <int D>
+hipError_t fixed_phi(const KModel& M, FixedArgs A, hipStream_t st) {
+  const hipError_t e = limits<D>();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fixed_phi<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_two_mats<D>(), st, M, A);
   return hipGetLastError();
 }
 
-hipError_t launch_any(int which, int D, const KModel& M, FixedArgs A, hipStream_t st) {
-  switch (D) {
-    case 16: return launch_k<16>(which, M, A, st);
-    case 32: return launch_k<32>(which, M, A, st);
-    case 64: return launch_k<64>(which, M, A, st);
+template <int D>
+hipError_t vtree_mats(const VScanArgs& V, double* const* Tm, const int* n_lvl, int L,
+                      hipStream_t st) {
+  const hipError_t e = limits<D>();
+  if (e != hipSuccess) return e;
+  const dim3 b(Cfg<D>::NT);
+  hipLaunchKernelGGL(k_vtree_fold_mat<D>, dim3(n_lvl[0]), b, lds_two_mats<D>(), st, V, Tm[0]);
+  for (int l = 0; l < L; ++l)
+    hipLaunchKernelGGL(k_vtree_up_mat<D>, dim3(n_lvl[l + 1]), b, lds_two_mats<D>(), st,
+                       (const double*)Tm[l], Tm[l + 1], n_lvl[l]);
+  return hipGetLastError();
+}
+
+// the vector parts of the kept tree: up spans from the leaves, down spans
+// from the root
+template <int D>
+void tree_spans(double* const* Tm, double* const* Uagg, double* const* xin, const int* n_lvl,
+                int L, hipStream_t st) {
+  const dim3 b(Cfg<D>::NT);
+  auto span = [&](int lo, int R) {
+    VTreeSpan T{};
+    T.R = R;
+    for (int r = 0; r <= R; ++r) {
+      if (r < R) T.Tm[r] = Tm[lo + r];
+      T.U[r] = Uagg[lo + r];
+      T.X[r] = xin[lo + r];
+      T.n[r] = n_lvl[lo + r];
+    }
+    return T;
+  };
+  static_assert(kVTreeSpan == 3, "span kernels are instantiated for 1, 2 and 3 levels");
+  for (int lo = 0; lo < L; lo += kVTreeSpan) {
+    const int R = min(kVTreeSpan, L - lo);
+    const dim3 g(n_lvl[lo + R]);
+    if (R == 3) hipLaunchKernelGGL((k_vup_span<D, 3>), g, b, 0, st, span(lo, R));
+    if (R == 2) hipLaunchKernelGGL((k_vup_span<D, 2>), g, b, 0, st, span(lo, R));
+    if (R == 1) hipLaunchKernelGGL((k_vup_span<D, 1>), g, b, 0, st, span(lo, R));
   }
-  return hipErrorInvalidValue;
+  for (int top = L; top > 0; top -= kVTreeSpan) {
+    const int R = min(kVTreeSpan, top);
+    const dim3 g(n_lvl[top]);
+    if (R == 3) hipLaunchKernelGGL((k_vdown_span<D, 3>), g, b, 0, st, span(top - R, R));
+    if (R == 2) hipLaunchKernelGGL((k_vdown_span<D, 2>), g, b, 0, st, span(top - R, R));
+    if (R == 1) hipLaunchKernelGGL((k_vdown_span<D, 1>), g, b, 0, st, span(top - R, R));
+  }
+}
+
+template <int D>
+hipError_t fixed_scan(int which, const KModel& M, FixedArgs A, double* const* Tm,
+                      double* const* Uagg, double* const* xin, const int* n_lvl, int L,
+                      hipStream_t st) {
+  const dim3 b(Cfg<D>::NT), gb(n_lvl[0]);
+  if (which == 0) {
+    timing_mark(FAM_FIXED_MEAN_FOLD, 1, st);
+    hipLaunchKernelGGL(k_mfold<D>, gb, b, 0, st, M, A, Uagg[0]);
+    timing_mark(FAM_FIXED_MEAN_FOLD, 0, st);
+    tree_spans<D>(Tm, Uagg, xin, n_lvl, L, st);
+    hipLaunchKernelGGL(k_mfinal<D>, gb, b, 0, st, M, A, (const double*)xin[0]);
+  } else {
+    hipLaunchKernelGGL(k_sw<D>, dim3(M.N), b, 0, st, M, A);
+    timing_mark(FAM_FIXED_SAMP_FOLD, 1, st);
+    hipLaunchKernelGGL(k_sfold<D>, gb, b, 0, st, M, A, Uagg[0]);
+    timing_mark(FAM_FIXED_SAMP_FOLD, 0, st);
+    tree_spans<D>(Tm, Uagg, xin, n_lvl, L, st);
+    hipLaunchKernelGGL(k_sfinal<D>, gb, b, 0, st, M, A, (const double*)xin[0]);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_fixed_phi_any(int D, const KModel& M, FixedArgs A, hipStream_t st) {
-  return launch_any(0, D, M, A, st);
+  switch (D) {
+    case 16: return fixed_phi<16>(M, A, st);
+    case 32: return fixed_phi<32>(M, A, st);
+    case 64: return fixed_phi<64>(M, A, st);
+  }
+  return hipErrorInvalidValue;
 }
-hipError_t launch_fixed_cmean_any(int D, const KModel& M, FixedArgs A, hipStream_t st) {
-  return launch_any(1, D, M, A, st);
+
+hipError_t launch_vtree_mats_any(int D, const VScanArgs& V, double* const* Tm, const int* n_lvl,
+                                 int L, hipStream_t st) {
+  switch (D) {
+    case 16: return vtree_mats<16>(V, Tm, n_lvl, L, st);
+    case 32: return vtree_mats<32>(V, Tm, n_lvl, L, st);
+    case 64: return vtree_mats<64>(V, Tm, n_lvl, L, st);
+  }
+  return hipErrorInvalidValue;
 }
-hipError_t launch_fixed_ell_any(int D, const KModel& M, FixedArgs A, hipStream_t st) {
-  return launch_any(2, D, M, A, st);
+
+hipError_t launch_fixed_scan_any(int D, int which, const KModel& M, FixedArgs A,
+                                 double* const* Tm, double* const* Uagg, double* const* xin,
+                                 const int* n_lvl, int L, hipStream_t st) {
+  switch (D) {
+    case 16: return fixed_scan<16>(which, M, A, Tm, Uagg, xin, n_lvl, L, st);
+    case 32: return fixed_scan<32>(which, M, A, Tm, Uagg, xin, n_lvl, L, st);
+    case 64: return fixed_scan<64>(which, M, A, Tm, Uagg, xin, n_lvl, L, st);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace akf

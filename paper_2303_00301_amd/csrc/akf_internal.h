@@ -90,7 +90,7 @@ struct FilterArgs {
   // nullptr for the model's F, b
   const double *Ft, *bt;
   // re-scan outputs kept for steps that reuse the covariances (diagonal Omega
-  // path; nullptr = not kept): S_t^{-1} [N*D*D], log det S_t [N]
+  // path; nullptr = not kept): S_t^{-1} [N*D*D] transposed, log det S_t [N]
   double *Sinv, *ldS;
 };
 
@@ -124,25 +124,49 @@ struct SampArgs {
   double* xs;        // [N*d]
   int* status;
   const double *Ft, *bt;  // per-step dynamics as in FilterArgs, or nullptr
-  double* Lc;             // chol(L_t) [N*D*D] kept for reuse, or nullptr
+  // kept for reuse (transposed, [N*D*D]), or nullptr: chol(L_t) and E_t
+  double *Lc, *Et;
 };
 
 // Steps whose auxiliary model has the same covariances every time (first
-// order: Omega_t = delta/2 I), with the matrices formed once per call:
-// S_t^{-1}, log det S_t, the filtering-mean maps Phi_t = Omega S_t^{-1} F (in
-// reversed time), the sampler's E_t and chol(L_t).
+// order: Omega_t = delta/2 I), with the matrices formed once per call.  Every
+// kept matrix is stored transposed (At[j*D + i] = A_ij), so that a
+// matrix-vector product reads it in coalesced columns.
 struct FixedArgs {
+  int B;                   // scan block (steps)
   const double* om;        // [N*d] pseudo-observations of this proposal
   double ovar;             // Omega = ovar I
-  const double *Sinv, *ldS, *Ec, *Lc;
-  double* Ephi;            // [N*D*D] Phi_{N-1-s} at s (written once)
-  double* U;               // [N*D] scan input
-  const double* mfr;       // [N*D] filtering means in reversed time (scan output)
-  const double* xi_x;      // [N*d] path normals, or nullptr (log-likelihood only)
-  double* ell;             // [N]
+  const double *Sinv, *ldS;  // S_t^{-1} [N*D*D], log det S_t [N]
+  const double *Et, *Lc;   // sampler E_t, chol(L_t) [N*D*D]
+  double* Phi;             // [N*D*D] Phi_{N-1-s} at s (set-up, for the tree products)
+  double* Fp;              // [D*D] F, padded (set-up)
+  double* mf;              // [N*D] filtering means (time order)
+  double* ell;             // [N] log-likelihood terms
+  const double* xi_x;      // [N*d] path normals
+  double *W, *G;           // [N*D] sampler scan: w_t = m^f_t + chol(L_t) xi_t, g_t = F m^f_t + b
+  double* xs;              // [N*d] sampled path
   const int* setup_status; // failures of the one-off matrices, copied into status
   int* status;
-  int fail_bit;
+};
+
+// Node products of a kept scan (set-up): elements Mt [N*D*D] in blocks of B
+// steps, then per tree level l the products of node pairs, Tm[l]
+// [n_lvl[l]*D*D]; a node maps the state after its range to its first state;
+// all transposed.
+struct VScanArgs {
+  int N, B;
+  const double* Mt;
+};
+
+// Up to kVTreeSpan consecutive tree levels lo .. lo + R in one launch; one
+// workgroup per node of level lo + R.
+constexpr int kVTreeSpan = 3;
+struct VTreeSpan {
+  const double* Tm[kVTreeSpan];  // node matrices of levels lo .. lo+R-1 (transposed)
+  double* U[kVTreeSpan + 1];     // vector parts of levels lo .. lo+R
+  double* X[kVTreeSpan + 1];     // states entering the nodes of levels lo .. lo+R
+  int n[kVTreeSpan + 1];         // node counts of levels lo .. lo+R
+  int R;
 };
 
 // Extended linearisation of nonlinear dynamics (one wave per time step):
@@ -277,7 +301,8 @@ struct BatchLaunch {
 enum {
   FAM_FILTER_FOLD = 0, FAM_FILTER_UP = 1, FAM_FILTER_DOWN = 2, FAM_FILTER_FINAL = 3,
   FAM_SAMP_BUILD = 4, FAM_SAMP_FOLD = 5, FAM_SAMP_UP = 6, FAM_SAMP_DOWN = 7, FAM_SAMP_FINAL = 8,
-  FAM_FACT = 9, FAM_LIN = 10, FAM_DNC = 11, FAM_COUNT = 12
+  FAM_FACT = 9, FAM_LIN = 10, FAM_DNC = 11, FAM_FIXED_MEAN_FOLD = 12, FAM_FIXED_SAMP_FOLD = 13,
+  FAM_COUNT = 14
 };
 // Called by the launchers before (begin = 1) and after (begin = 0) each launch.
 void timing_mark(int family, int begin, hipStream_t st);
@@ -310,8 +335,15 @@ hipError_t launch_adj_finish_any(int D, const KModel& M, LgArgs G, int nblk, con
 hipError_t launch_zero(double* p, int64_t n, hipStream_t st);
 hipError_t launch_fact_scan(const KModel& M, FactArgs P, hipStream_t st);
 hipError_t launch_fixed_phi_any(int D, const KModel& M, FixedArgs A, hipStream_t st);
-hipError_t launch_fixed_cmean_any(int D, const KModel& M, FixedArgs A, hipStream_t st);
-hipError_t launch_fixed_ell_any(int D, const KModel& M, FixedArgs A, hipStream_t st);
+// matrix parts of a kept scan (set-up): level 0 from the elements, then L levels
+hipError_t launch_vtree_mats_any(int D, const VScanArgs& V, double* const* Tm, const int* n_lvl,
+                                 int L, hipStream_t st);
+// One proposal's filtering means and log-likelihood terms (which = 0), or its
+// sampled path from the kept sampler matrices (which = 1): block fold, the
+// kept tree's vector parts, block final.  Tm: that scan's node products.
+hipError_t launch_fixed_scan_any(int D, int which, const KModel& M, FixedArgs A,
+                                 double* const* Tm, double* const* Uagg, double* const* xin,
+                                 const int* n_lvl, int L, hipStream_t st);
 hipError_t launch_qinv(const KModel& M, double* Qinv, hipStream_t st);
 hipError_t launch_dnc_any(int D, const KModel& M, DncArgs A, hipStream_t st);
 int dnc_depth(int T);

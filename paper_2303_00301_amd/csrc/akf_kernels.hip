@@ -64,33 +64,52 @@ struct EmitOut {
   double lh, v, lam;
 };
 
+// One site's contribution to log h and its derivatives at x_i = xi.
+__device__ __forceinline__ void emit_site(const KModel& M, double yk, double xi, EmitOut& o) {
+  if (M.emit == EMIT_POISSON_LOG) {
+    const double e = exp(xi);
+    o.lh += yk * xi - e;
+    o.v += yk - e;
+    o.lam -= e;
+  } else if (M.emit == EMIT_GAUSS_SITE) {
+    const double s2 = M.scale * M.scale, r = yk - xi;
+    o.lh += -0.5 * r * r / s2;
+    o.v += r / s2;
+    o.lam -= 1.0 / s2;
+  } else if (M.emit == EMIT_STOCH_VOL) {
+    const double q = yk * yk * exp(-xi);  // y ~ N(0, exp(x))
+    o.lh += -0.5 * xi - 0.5 * q;
+    o.v += -0.5 + 0.5 * q;
+    o.lam -= 0.5 * q;
+  } else {
+    const double a = M.nu * M.scale * M.scale;
+    const double r = yk - xi, den = a + r * r;
+    o.lh += -0.5 * (M.nu + 1.0) * log1p(r * r / a);
+    o.v += (M.nu + 1.0) * r / den;
+    o.lam += (M.nu + 1.0) * (r * r - a) / (den * den);
+  }
+}
+
+// Sum over the sites observing latent i.  A site matches one lane of a wave
+// (its latent), so evaluating the sites one by one would run each site's
+// arithmetic with a single active lane.  Instead each pass sweeps the site
+// list uniformly (scalar loads, per-lane selects) for every lane's next
+// matching site, then all matched lanes load and evaluate together: one pass
+// per site of the most-observed latent, plus one.
 __device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __restrict__ yt,
                                              double xi, int i) {
   EmitOut o{0.0, 0.0, 0.0};
-  for (int k = 0; k < M.dy; ++k) {
-    if (M.site[k] != i || isnan(yt[k])) continue;  // NaN: site not observed at t
-    if (M.emit == EMIT_POISSON_LOG) {
-      const double e = exp(xi);
-      o.lh += yt[k] * xi - e;
-      o.v += yt[k] - e;
-      o.lam -= e;
-    } else if (M.emit == EMIT_GAUSS_SITE) {
-      const double s2 = M.scale * M.scale, r = yt[k] - xi;
-      o.lh += -0.5 * r * r / s2;
-      o.v += r / s2;
-      o.lam -= 1.0 / s2;
-    } else if (M.emit == EMIT_STOCH_VOL) {
-      const double q = yt[k] * yt[k] * exp(-xi);  // y ~ N(0, exp(x))
-      o.lh += -0.5 * xi - 0.5 * q;
-      o.v += -0.5 + 0.5 * q;
-      o.lam -= 0.5 * q;
-    } else {
-      const double a = M.nu * M.scale * M.scale;
-      const double r = yt[k] - xi, den = a + r * r;
-      o.lh += -0.5 * (M.nu + 1.0) * log1p(r * r / a);
-      o.v += (M.nu + 1.0) * r / den;
-      o.lam += (M.nu + 1.0) * (r * r - a) / (den * den);
+  int start = 0;
+  for (int pass = 0; pass < M.dy; ++pass) {
+    int kk = -1;
+    for (int k = 0; k < M.dy; ++k) {
+      const int sk = M.site[k];
+      kk = (kk < 0 && k >= start && sk == i) ? k : kk;
     }
+    if (kk < 0) break;
+    const double yk = yt[kk];
+    start = kk + 1;
+    if (!isnan(yk)) emit_site(M, yk, xi, o);  // NaN: site not observed at t
   }
   return o;
 }
@@ -1096,7 +1115,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       double logdet;
       ok = spd_inv<D>(R2, d, B2, &logdet) && ok;
       if (P.Sinv) {
-        rm_store<D>(R2, P.Sinv + (int64_t)t * D * D, D, D);
+        rm_store_t<D>(R2, P.Sinv + (int64_t)t * D * D, D);
         if (tid == 0) P.ldS[t] = logdet;
       }
       rm_stage<D>(R2, B3);
@@ -1194,7 +1213,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   double ld;
   if (t == M.N - 1) {
     ok = chol_reg<D>(Pf, d, B3, &ld);
-    if (S.Lc) rm_store<D>(Pf, S.Lc + (int64_t)t * D * D, D, D);
+    if (S.Lc) rm_store_t<D>(Pf, S.Lc + (int64_t)t * D * D, D);
     rm_stage<D>(Pf, B2);
     team_sync();
     if (tid < D) {
@@ -1205,6 +1224,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     RM<D> Z;
     rm_zero<D>(Z);
     rm_store<D>(Z, S.E + (int64_t)t * D * D, D, D);
+    if (S.Et) rm_store<D>(Z, S.Et + (int64_t)t * D * D, D, D);
   } else {
     rm_load<D>(R2, M.Q, d, d);  // issued early: its latency overlaps G = F P^f
     // the transition into step t + 1
@@ -1228,6 +1248,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     team_sync();
     gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
     rm_store<D>(R1, S.E + (int64_t)t * D * D, D, D);
+    if (S.Et) rm_store_t<D>(R1, S.Et + (int64_t)t * D * D, D);
     rm_stage<D>(R1, B3);  // B3 = E
     team_sync();
     gemm<D, false, false, false>(R2, B3, B1);  // E G
@@ -1236,7 +1257,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     if (tid < D) vg[tid] = vm[tid] - vg[tid];  // g = m^f - E m^p
     rm_symmetrise<D>(R2, B2);
     ok = chol_reg<D>(R2, d, B3, &ld) && ok;
-    if (S.Lc) rm_store<D>(R2, S.Lc + (int64_t)t * D * D, D, D);
+    if (S.Lc) rm_store_t<D>(R2, S.Lc + (int64_t)t * D * D, D);
     rm_stage<D>(R2, B2);
     team_sync();
     if (tid < D) {
@@ -1384,8 +1405,16 @@ __global__ void __launch_bounds__(64) k_samp_final(KModel M, SampArgs S) {
 // accept iff log U < log r and no status bit is set.  One team of 256.
 // ---------------------------------------------------------------------------
 __device__ double block_sum(const double* a, int n, double* red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) s += a[i];
+  // four independent accumulators keep four loads in flight per thread
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  const int stride = blockDim.x;
+  int i = threadIdx.x;
+  for (; i + 3 * stride < n; i += 4 * stride) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s4[q] += a[i + q * stride];
+  }
+  for (; i < n; i += stride) s4[0] += a[i];
+  double s = (s4[0] + s4[1]) + (s4[2] + s4[3]);
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();

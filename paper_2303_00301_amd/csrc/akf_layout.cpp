@@ -96,10 +96,19 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
       Lo.pdyn = take((size_t)Lo.n_part_dyn * dbl);
     }
     if (fixed) {
-      Lo.Sinv = take((size_t)N * D * D * dbl);
+      const size_t mat = (size_t)D * D * dbl;
+      Lo.Sinv = take((size_t)N * mat);
       Lo.ldS = take((size_t)N * dbl);
-      Lo.Ephi = take((size_t)N * D * D * dbl);
-      Lo.Lc = take((size_t)N * D * D * dbl);
+      Lo.Phi = take((size_t)N * mat);
+      Lo.Lc = take((size_t)N * mat);
+      Lo.Et = take((size_t)N * mat);
+      Lo.Fp = take(mat);
+      Lo.Gs = take((size_t)N * D * dbl);
+      for (int l = 0; l <= Lo.L; ++l) {
+        Lo.tphi[l] = take((size_t)Lo.n_lvl[l] * mat);
+        Lo.te[l] = take((size_t)Lo.n_lvl[l] * mat);
+        Lo.vagg[l] = take((size_t)Lo.n_lvl[l] * D * dbl);
+      }
     }
   }
   if (kind == LAYOUT_FACT) {
@@ -381,11 +390,13 @@ akf_status run_filter_logz(const Layout& Lo, const KModel& M, void* ws, const do
 
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
                        const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
-                       hipStream_t st, const double* Ft, const double* bt, double* Lc) {
+                       hipStream_t st, const double* Ft, const double* bt, double* Lc,
+                       double* Et) {
   SampArgs S{};
   S.Ft = Ft;
   S.bt = bt;
   S.Lc = Lc;
+  S.Et = Et;
   S.B = Lo.B;
   S.mf = mf;
   S.Pf = Pf;

@@ -33,9 +33,14 @@ struct Layout {
   // nonlinear dynamics: per-step F_t, b_t, Q^{-1}, mismatch partial sums
   size_t Ft = 0, bt = 0, Qinv = 0, pdyn = 0;
   int n_part_dyn = 0;
-  // first-order runs: matrices formed once per call (S^{-1}, log det S, the
-  // filtering-mean maps Phi in reversed time, chol(L)); the sampler's E stays in E
-  size_t Sinv = 0, ldS = 0, Ephi = 0, Lc = 0;
+  // first-order runs: matrices formed once per call, transposed (S^{-1}, log
+  // det S, the filtering-mean maps Phi in reversed time, chol(L), the
+  // sampler's E, F padded), the node products of the two kept scans, and the
+  // vector parts of those scans' tree nodes
+  size_t Sinv = 0, ldS = 0, Phi = 0, Lc = 0, Et = 0, Fp = 0, Gs = 0;
+  size_t tphi[kMaxLevels + 1] = {0};
+  size_t te[kMaxLevels + 1] = {0};
+  size_t vagg[kMaxLevels + 1] = {0};
   // divide-and-conquer sampler tree
   size_t Elf = 0, glf = 0, Llf = 0, Eno = 0, gno = 0, Lno = 0, Gb = 0, Gam = 0, wb = 0, Vc = 0;
   // (E, g, L) scan, smoother and adjoint
@@ -82,7 +87,7 @@ akf_status run_filter_logz(const Layout& Lo, const KModel& M, void* ws, const do
 akf_status run_sampler(const Layout& Lo, const KModel& M, void* ws, const double* mf,
                        const double* Pf, int ldm, const double* xi_x, double* xs, int* status,
                        hipStream_t st, const double* Ft = nullptr, const double* bt = nullptr,
-                       double* Lc = nullptr);
+                       double* Lc = nullptr, double* Et = nullptr);
 void fill_egl_tree(const Layout& Lo, void* ws, EglTree* up, EglTree* down);
 akf_status run_egl(const Layout& Lo, void* ws, const double* g, double* outL, double* outg,
                    int ldo, int dout, hipStream_t st);

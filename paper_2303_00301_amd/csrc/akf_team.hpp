@@ -116,6 +116,12 @@ __device__ __forceinline__ void rm_store(const RM<D>& a, double* __restrict__ g,
   AKF_RM_FOR(D, q, r, i, j) if (i < d && j < d) g[(size_t)i * ld + j] = a.t[q][r];
 }
 
+// transposed store of the whole D x D tile: G[j*ld + i] = a_ij
+template <int D>
+__device__ __forceinline__ void rm_store_t(const RM<D>& a, double* __restrict__ g, int ld) {
+  AKF_RM_FOR(D, q, r, i, j) g[(size_t)j * ld + i] = a.t[q][r];
+}
+
 template <int D>
 __device__ __forceinline__ void rm_stage(const RM<D>& a, double* s) {
   AKF_RM_FOR(D, q, r, i, j) s[i * Cfg<D>::LD + j] = a.t[q][r];
