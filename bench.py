@@ -236,10 +236,15 @@ def bench_stoch_vol(torch, S, W, K: int, dev) -> dict:
     return out
 
 
-def bench_first_order(torch, S, W, K: int, dev) -> dict:
+def bench_first_order(torch, S, W, _lib, K: int, dev) -> dict:
     """First-order steps on the latent-field workload (d_x = 64, T = 4096): the
     plain step, which forms the auxiliary model's covariances every step, and
-    the run that forms them once per call (the first step pays for it)."""
+    the run that forms them once per call (the first step pays for it).  The
+    roofline is that of the filtering-mean block fold (k_mfold<64>): per
+    launch it reads every kept S_t^{-1} (T d^2 doubles), omega and log det S
+    and writes one vector per block."""
+    import ctypes as C
+    lib = _lib.load()
     w = W.latent_field()
     delta = 0.2 * w.delta
     M = S.DeviceModel.from_workload(w, device=dev)
@@ -255,6 +260,9 @@ def bench_first_order(torch, S, W, K: int, dev) -> dict:
         x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
         S.mh_run(M, y, x, delta, 1, xi[:2], un[:2], ws=ws, reuse_matrices=reuse)
         torch.cuda.synchronize()
+        if reuse:
+            _lib.check(lib.akf_timing_enable(_lib.FAMILIES["fixed_mean_fold"], 2 * K + 8),
+                       "akf_timing_enable")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         r = S.mh_run(M, y, x, delta, 1, xi[2:], un[2:], ws=ws, reuse_matrices=reuse)
@@ -264,6 +272,21 @@ def bench_first_order(torch, S, W, K: int, dev) -> dict:
         out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
                     "acceptance": r["accepted"].float().mean().item(),
                     "rejected_by_status": int((r["status"] != 0).sum().item())}
+        if reuse:
+            n_l, k_ms = C.c_int32(), C.c_double()
+            _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
+            lib.akf_timing_enable(-1, 0)
+            if n_l.value > 0:
+                N, d, D = w.N, w.dx, 64
+                nb = -(-N // auto_block(N, d))
+                nbytes = 8.0 * (N * D * D + N * d + N + nb * D)
+                avg_ms = k_ms.value / n_l.value
+                gbs = nbytes / (avg_ms * 1e-3) / 1e9
+                out[key]["roofline"] = {"bound": "hbm", "kernel": "k_mfold<64>",
+                                        "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                        "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                                        "avg_launch_ms": avg_ms, "launches": n_l.value,
+                                        "bytes_per_launch": nbytes}
     out["speedup"] = out["plain"]["ms_per_step"] / out["matrices_once_per_call"]["ms_per_step"]
     return out
 
@@ -534,7 +557,7 @@ def main() -> int:
     if not args.no_samplers:
         res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev)
     if not args.no_first_order:
-        res["first_order"] = bench_first_order(torch, S, W, 50, dev)
+        res["first_order"] = bench_first_order(torch, S, W, _lib, 50, dev)
     if not args.no_lorenz:
         res["nonlinear"] = bench_lorenz(torch, S, W, 20, dev, 0 if args.no_cpu_baseline else 10)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
