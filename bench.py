@@ -291,6 +291,39 @@ def bench_first_order(torch, S, W, _lib, K: int, dev) -> dict:
     return out
 
 
+def bench_reuse(torch, S, W, K: int, dev) -> dict:
+    """The headline workload (latent field, d_x = 64, T = 4096, order 2) run
+    plainly and with the matrices of a forward proposal reused by the next one
+    after a rejection (akf_mh_run_reuse; one host synchronisation per step).
+    Both runs take the same normals and uniforms from the same state, so they
+    make the same decisions."""
+    w = W.latent_field()
+    M = S.DeviceModel.from_workload(w, device=dev)
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(97)
+    xi = torch.randn((K + 2, 2, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
+    un = torch.rand((K + 2,), dtype=torch.float64, device=dev, generator=gen).clamp_(min=1e-300)
+    out = {"workload": f"latent_field_d{w.dx}_T{w.N}, order-2 proposal, delta {w.delta}, "
+                       f"one chain, {K} steps per call"}
+    for key, reuse in (("plain", False), ("reuse_after_reject", True)):
+        ws = S.Workspace(dev)
+        x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
+        S.mh_run(M, y, x, w.delta, 2, xi[:2], un[:2], ws=ws, reuse_matrices=reuse)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        r = S.mh_run(M, y, x, w.delta, 2, xi[2:], un[2:], ws=ws, reuse_matrices=reuse)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+                    "acceptance": r["accepted"].float().mean().item(),
+                    "rejected_by_status": int((r["status"] != 0).sum().item())}
+    out["speedup"] = out["plain"]["ms_per_step"] / out["reuse_after_reject"]["ms_per_step"]
+    return out
+
+
 def bench_spatio_temporal(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dict:
     """Second paper workload: the spatio-temporal model (8 x 8 lattice, T = 1024,
     multivariate-t observations with nu = 1), first order, one chain.  The
@@ -449,6 +482,7 @@ def main() -> int:
     ap.add_argument("--no-lorenz", action="store_true")
     ap.add_argument("--no-samplers", action="store_true")
     ap.add_argument("--no-first-order", action="store_true")
+    ap.add_argument("--no-reuse", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
                          "reference for the HBM byte counters)")
@@ -558,6 +592,8 @@ def main() -> int:
         res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev)
     if not args.no_first_order:
         res["first_order"] = bench_first_order(torch, S, W, _lib, 50, dev)
+    if not args.no_reuse:
+        res["reuse_order2"] = bench_reuse(torch, S, W, 30, dev)
     if not args.no_lorenz:
         res["nonlinear"] = bench_lorenz(torch, S, W, 20, dev, 0 if args.no_cpu_baseline else 10)
     if not args.no_cpu_baseline and args.cpu_steps > 0:

@@ -174,6 +174,33 @@ akf_status akf_mh_run_first_order(const akf_model* model, const double* y, doubl
                                   size_t ws_bytes, int32_t block, void* stream);
 
 /*
+ * n_steps MH steps of order 1 or 2 on one chain reusing the auxiliary model's
+ * matrices wherever they are unchanged (the matrix parts A, C, J of the filter
+ * elements, and everything built from them, depend on x only through
+ * Omega_t, never on u).  Order 1: as akf_mh_run_first_order.  Order 2:
+ * Omega_t depends on x, so a forward proposal after a rejected step (same x,
+ * new u) reuses the covariances of the forward proposal before it and is
+ * matrix-vector work; after an accepted or failed step, and at step 0, the
+ * forward proposal runs in full and keeps its matrices; the reverse proposal
+ * (a new x* every step) always runs in full.  The host reads each step's
+ * accept flag back before launching the next (one stream synchronisation per
+ * step), so this call blocks and is not graph-capturable.  Arguments,
+ * outputs, normals and status bits as akf_mh_run; the chain equals
+ * akf_mh_run's up to rounding.
+ *   - model: linear dynamics; order 2 takes the diagonal-Omega families
+ *     (POISSON_LOG, STUDENT_T, STOCH_VOL, GAUSS_SITE), AKF_ERR_UNSUPPORTED
+ *     for GAUSSIAN; MVT needs order 1 as everywhere.
+ *   - workspace: akf_mh_reuse_workspace_bytes (that of
+ *     akf_mh_run_first_order).
+ */
+size_t akf_mh_reuse_workspace_bytes(const akf_model* model, int32_t order, int32_t block);
+akf_status akf_mh_run_reuse(const akf_model* model, const double* y, double* x, double delta,
+                            int32_t order, int32_t n_steps, const double* xi, const double* unif,
+                            double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                            double* logZ_rev, int32_t* status, void* ws, size_t ws_bytes,
+                            int32_t block, void* stream);
+
+/*
  * Factorised step (Sec. "Spatio-temporal model").  When P0, F and Q are
  * diagonal the prior is a product over coordinates; with a diagonal Omega_t
  * (first order, or second order with the POISSON_LOG, STUDENT_T or STOCH_VOL

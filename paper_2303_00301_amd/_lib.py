@@ -64,6 +64,9 @@ SIGNATURES = {
     "akf_mh_first_order_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_mh_run_first_order": (C.c_int, [_MP, _vp, _vp, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp, _vp, _sz, _i32, _vp]),
+    "akf_mh_reuse_workspace_bytes": (_sz, [_MP, _i32, _i32]),
+    "akf_mh_run_reuse": (C.c_int, [_MP, _vp, _vp, _d, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                   _vp, _vp, _sz, _i32, _vp]),
     "akf_mh_factorised_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_mh_step_factorised": (C.c_int, [_MP, _vp, _vp, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp, _vp, _vp, _sz, _vp]),

@@ -189,89 +189,93 @@ KeptTree kept_tree(const Layout& Lo, void* ws, const size_t* tm) {
   return K;
 }
 
-akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
-                           double delta, const double* xi, const double* unif, double* x_out,
-                           double* log_ratio, int32_t* accepted, double* logZ_fwd,
-                           double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st,
-                           int step) {
-  const size_t vn = (size_t)M.N * M.d;
-  const int D = Lo.D;
-  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, 1, xi, step);
-  int* setup_status = at<int>(ws, Lo.status) + 2;
+// Kept-matrix state of a run: the workspace pointers of the kept matrices and
+// trees.
+struct Kept {
+  FixedArgs X;
+  KeptTree phi, e;
+  double *Pf;
+};
+
+Kept kept_state(const Layout& Lo, void* ws, const StepArgs& A, const double* xi_x,
+                int* setup_status) {
+  Kept K{};
+  K.X.B = Lo.B;
+  K.X.Sinv = at<double>(ws, Lo.Sinv);
+  K.X.ldS = at<double>(ws, Lo.ldS);
+  K.X.Et = at<double>(ws, Lo.Et);
+  K.X.Lc = at<double>(ws, Lo.Lc);
+  K.X.Phi = at<double>(ws, Lo.Phi);
+  K.X.Fp = at<double>(ws, Lo.Fp);
+  K.X.mf = at<double>(ws, Lo.mf);
+  K.X.W = at<double>(ws, Lo.U);
+  K.X.G = at<double>(ws, Lo.Gs);
+  K.X.xs = A.xs;
+  K.X.xi_x = xi_x;
+  K.X.setup_status = setup_status;
+  K.X.status = A.status;
+  K.phi = kept_tree(Lo, ws, Lo.tphi);
+  K.e = kept_tree(Lo, ws, Lo.te);
+  K.Pf = at<double>(ws, Lo.Pf);
+  return K;
+}
+
+// The plain forward filter and sampler at omega/Omega, keeping S^{-1}, log det
+// S, E and chol(L); failures go to `status`.
+akf_status forward_keep(const Layout& Lo, const KModel& M, void* ws, const StepArgs& A,
+                        const Kept& K, int* status, hipStream_t st) {
   akf_status s;
-  if (step == 0) {
-    if ((s = hip_check(launch_step_init(at<int>(ws, Lo.status), root_flag(Lo, ws),
-                                        at<double>(ws, Lo.xin[Lo.L]), D, st),
-                       "init launch")) != AKF_OK)
-      return s;
-    if ((s = hip_check(launch_step_init(setup_status, nullptr, nullptr, 0, st), "init launch")) !=
-        AKF_OK)
-      return s;
-  }
-  int n_part_fwd = 0, n_part_rev = 0;
-  if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
-  double* Sinv = at<double>(ws, Lo.Sinv);
-  double* ldS = at<double>(ws, Lo.ldS);
-  double* Et = at<double>(ws, Lo.Et);
-  double* Lc = at<double>(ws, Lo.Lc);
-  double* Phi = at<double>(ws, Lo.Phi);
-  double* mf = at<double>(ws, Lo.mf);
-  FixedArgs X{};
-  X.B = Lo.B;
-  // the linearisation's Omega, bit for bit
-  X.ovar = M.emit == EMIT_GAUSSIAN ? 0.5 * delta : 1.0 / (2.0 / delta);
-  X.Sinv = Sinv;
-  X.ldS = ldS;
-  X.Et = Et;
-  X.Lc = Lc;
-  X.Phi = Phi;
-  X.Fp = at<double>(ws, Lo.Fp);
-  X.mf = mf;
-  X.W = at<double>(ws, Lo.U);
-  X.G = at<double>(ws, Lo.Gs);
-  X.xs = A.xs;
-  X.xi_x = xi + vn;
-  X.setup_status = setup_status;
-  X.status = A.status;
-  const KeptTree Kphi = kept_tree(Lo, ws, Lo.tphi), Ke = kept_tree(Lo, ws, Lo.te);
-  if (step == 0) {
-    double* Pf = at<double>(ws, Lo.Pf);
-    if ((s = run_filter(Lo, M, ws, A.om, A.Om, nullptr, mf, Pf, D, A.ell, setup_status,
-                        ST_FWD_NOT_PD, st, nullptr, nullptr, nullptr, 0, nullptr, nullptr, Sinv,
-                        ldS)) != AKF_OK)
-      return s;
-    if ((s = run_sampler(Lo, M, ws, mf, Pf, D, xi + vn, A.xs, setup_status, st, nullptr, nullptr,
-                         Lc, Et)) != AKF_OK)
-      return s;
-    if ((s = hip_check(launch_fixed_phi_any(D, M, X, st), "Phi launch")) != AKF_OK) return s;
-    const VScanArgs Vphi{M.N, Lo.B, Phi}, Ve{M.N, Lo.B, Et};
-    if ((s = hip_check(launch_vtree_mats_any(D, Vphi, Kphi.Tm, Lo.n_lvl, Lo.L, st),
-                       "scan products launch")) != AKF_OK)
-      return s;
-    if ((s = hip_check(launch_vtree_mats_any(D, Ve, Ke.Tm, Lo.n_lvl, Lo.L, st),
-                       "scan products launch")) != AKF_OK)
-      return s;
-  } else {
-    X.om = A.om;
-    X.ell = A.ell;
-    if ((s = hip_check(launch_fixed_scan_any(D, 0, M, X, Kphi.Tm, Kphi.Uagg, Kphi.xin, Lo.n_lvl,
-                                             Lo.L, st),
-                       "mean scan launch")) != AKF_OK)
-      return s;
-    if ((s = hip_check(launch_fixed_scan_any(D, 1, M, X, Ke.Tm, Ke.Uagg, Ke.xin, Lo.n_lvl, Lo.L,
-                                             st),
-                       "sampler scan launch")) != AKF_OK)
-      return s;
-  }
-  if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
-  X.om = A.om2;
-  X.ell = A.ell2;
-  if ((s = hip_check(launch_fixed_scan_any(D, 0, M, X, Kphi.Tm, Kphi.Uagg, Kphi.xin, Lo.n_lvl,
-                                           Lo.L, st),
+  const double* xi_x = K.X.xi_x;
+  if ((s = run_filter(Lo, M, ws, A.om, A.Om, nullptr, K.X.mf, K.Pf, Lo.D, A.ell, status,
+                      ST_FWD_NOT_PD, st, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
+                      const_cast<double*>(K.X.Sinv), const_cast<double*>(K.X.ldS))) != AKF_OK)
+    return s;
+  return run_sampler(Lo, M, ws, K.X.mf, K.Pf, Lo.D, xi_x, A.xs, status, st, nullptr, nullptr,
+                     const_cast<double*>(K.X.Lc), const_cast<double*>(K.X.Et));
+}
+
+// Phi_t = Omega_t S_t^{-1} F and the node products of both kept scans.
+akf_status form_trees(const Layout& Lo, const KModel& M, const Kept& K, const double* Om,
+                      hipStream_t st) {
+  akf_status s;
+  FixedArgs X = K.X;
+  X.Om = Om;
+  if ((s = hip_check(launch_fixed_phi_any(Lo.D, M, X, st), "Phi launch")) != AKF_OK) return s;
+  const VScanArgs Vphi{M.N, Lo.B, X.Phi}, Ve{M.N, Lo.B, X.Et};
+  if ((s = hip_check(launch_vtree_mats_any(Lo.D, Vphi, K.phi.Tm, Lo.n_lvl, Lo.L, st),
+                     "scan products launch")) != AKF_OK)
+    return s;
+  return hip_check(launch_vtree_mats_any(Lo.D, Ve, K.e.Tm, Lo.n_lvl, Lo.L, st),
+                   "scan products launch");
+}
+
+// A proposal's means and log-likelihood terms (and with `path` its sampled
+// path) from the kept matrices.
+akf_status kept_proposal(const Layout& Lo, const KModel& M, const Kept& K, const double* om,
+                         const double* Om, double* ell, bool path, hipStream_t st) {
+  akf_status s;
+  FixedArgs X = K.X;
+  X.om = om;
+  X.Om = Om;
+  X.ell = ell;
+  if ((s = hip_check(launch_fixed_scan_any(Lo.D, 0, M, X, K.phi.Tm, K.phi.Uagg, K.phi.xin,
+                                           Lo.n_lvl, Lo.L, st),
                      "mean scan launch")) != AKF_OK)
     return s;
+  if (!path) return AKF_OK;
+  return hip_check(launch_fixed_scan_any(Lo.D, 1, M, X, K.e.Tm, K.e.Uagg, K.e.xin, Lo.n_lvl, Lo.L,
+                                         st),
+                   "sampler scan launch");
+}
+
+akf_status kept_finalize(const Layout& Lo, const KModel& M, void* ws, const StepArgs& A,
+                         int step, const double* lz_rev, int n_part_fwd, int n_part_rev,
+                         const double* x_in, double* x_out, const double* unif,
+                         double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                         double* logZ_rev, int32_t* status_out, hipStream_t st) {
   FinalArgs F{};
   F.status_next = at<int>(ws, Lo.status) + ((step + 1) & 1);
+  F.lz_rev = lz_rev;
   F.unif = unif;
   F.log_ratio = log_ratio;
   F.accepted = accepted;
@@ -281,6 +285,80 @@ akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, c
   F.n_part_fwd = n_part_fwd;
   F.n_part_rev = n_part_rev;
   return hip_check(launch_finalize(M, A, F, x_in, x_out, st), "finalize launch");
+}
+
+akf_status init_kept_status(const Layout& Lo, void* ws, hipStream_t st) {
+  akf_status s;
+  if ((s = hip_check(launch_step_init(at<int>(ws, Lo.status), root_flag(Lo, ws),
+                                      at<double>(ws, Lo.xin[Lo.L]), Lo.D, st),
+                     "init launch")) != AKF_OK)
+    return s;
+  return hip_check(launch_step_init(at<int>(ws, Lo.status) + 2, nullptr, nullptr, 0, st),
+                   "init launch");
+}
+
+// First order: step 0 is the plain step keeping its matrices (then the trees);
+// every later proposal, forward and reverse, uses them.
+akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
+                           double delta, const double* xi, const double* unif, double* x_out,
+                           double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                           double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st,
+                           int step) {
+  const size_t vn = (size_t)M.N * M.d;
+  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, 1, xi, step);
+  int* setup_status = at<int>(ws, Lo.status) + 2;
+  akf_status s;
+  if (step == 0 && (s = init_kept_status(Lo, ws, st)) != AKF_OK) return s;
+  int n_part_fwd = 0, n_part_rev = 0;
+  if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
+  const Kept K = kept_state(Lo, ws, A, xi + vn, setup_status);
+  if (step == 0) {
+    if ((s = forward_keep(Lo, M, ws, A, K, setup_status, st)) != AKF_OK) return s;
+    if ((s = form_trees(Lo, M, K, A.Om, st)) != AKF_OK) return s;
+  } else if ((s = kept_proposal(Lo, M, K, A.om, A.Om, A.ell, true, st)) != AKF_OK) {
+    return s;
+  }
+  if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
+  if ((s = kept_proposal(Lo, M, K, A.om2, A.Om2, A.ell2, false, st)) != AKF_OK) return s;
+  return kept_finalize(Lo, M, ws, A, step, nullptr, n_part_fwd, n_part_rev, x_in, x_out, unif,
+                       log_ratio, accepted, logZ_fwd, logZ_rev, status_out, st);
+}
+
+// Second order: Omega_t depends on x only, so after a rejected step the next
+// forward proposal (same x, new u) has the covariances of the one before.
+// `fresh`: x changed since the kept matrices were formed (step 0, or the step
+// before accepted or failed); `trees`: the kept scans' products are current.
+// The reverse proposal is at a new x* every step and runs in full.
+akf_status reuse_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
+                           double delta, const double* xi, const double* unif, double* x_out,
+                           double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                           double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st,
+                           int step, bool fresh, bool* trees) {
+  const size_t vn = (size_t)M.N * M.d;
+  const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, 2, xi, step);
+  akf_status s;
+  if (step == 0 && (s = init_kept_status(Lo, ws, st)) != AKF_OK) return s;
+  int n_part_fwd = 0, n_part_rev = 0;
+  if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
+  // set-up failures of a kept forward pass are this step's own failures
+  const Kept K = kept_state(Lo, ws, A, xi + vn, A.status);
+  if (fresh) {
+    if ((s = forward_keep(Lo, M, ws, A, K, A.status, st)) != AKF_OK) return s;
+    *trees = false;
+  } else {
+    if (!*trees) {
+      if ((s = form_trees(Lo, M, K, A.Om, st)) != AKF_OK) return s;
+      *trees = true;
+    }
+    if ((s = kept_proposal(Lo, M, K, A.om, A.Om, A.ell, true, st)) != AKF_OK) return s;
+  }
+  if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
+  const double* lz_rev = nullptr;
+  if ((s = run_filter_logz(Lo, M, ws, A.om2, A.Om2, nullptr, A.status, ST_REV_NOT_PD, st, nullptr,
+                           nullptr, &lz_rev)) != AKF_OK)
+    return s;
+  return kept_finalize(Lo, M, ws, A, step, lz_rev, n_part_fwd, n_part_rev, x_in, x_out, unif,
+                       log_ratio, accepted, logZ_fwd, logZ_rev, status_out, st);
 }
 
 akf_status check_fact_model(const akf_model* model, int order) {
@@ -728,6 +806,74 @@ akf_status akf_mh_run_first_order(const akf_model* model, const double* y, doubl
                         logZ_fwd ? logZ_fwd + k : nullptr, logZ_rev ? logZ_rev + k : nullptr,
                         status ? status + k : nullptr, ws, (hipStream_t)stream, k);
     if (s != AKF_OK) return s;
+  }
+  return AKF_OK;
+}
+
+akf_status check_reuse_model(const akf_model* model, int order) {
+  akf_status s;
+  if ((s = check_model(model, true)) != AKF_OK) return s;
+  if ((s = check_linear(model, "akf_mh_run_reuse")) != AKF_OK) return s;
+  if ((s = check_order(model, order)) != AKF_OK) return s;
+  if (order == 2 && model->emit == AKF_EMIT_GAUSSIAN)
+    return fail(AKF_ERR_UNSUPPORTED, "akf_mh_run_reuse keeps diagonal-Omega matrices; the "
+                                     "GAUSSIAN emission has a dense Omega under order 2");
+  return AKF_OK;
+}
+
+size_t akf_mh_reuse_workspace_bytes(const akf_model* model, int32_t order, int32_t block) {
+  if (check_reuse_model(model, order) != AKF_OK || block < 0) return 0;
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP, false, true);
+  return Lo.total;
+}
+
+akf_status akf_mh_run_reuse(const akf_model* model, const double* y, double* x, double delta,
+                            int32_t order, int32_t n_steps, const double* xi, const double* unif,
+                            double* log_ratio, int32_t* accepted, double* logZ_fwd,
+                            double* logZ_rev, int32_t* status, void* ws, size_t ws_bytes,
+                            int32_t block, void* stream) {
+  akf_status s;
+  if ((s = check_reuse_model(model, order)) != AKF_OK) return s;
+  if (!y || !x || !xi || !unif) return fail(AKF_ERR_INVALID, "y, x, xi and unif must be non-NULL");
+  if (n_steps < 0) return fail(AKF_ERR_INVALID, "n_steps must be >= 0");
+  if (!(delta > 0.0)) return fail(AKF_ERR_INVALID, "delta must be > 0");
+  if (block < 0) return fail(AKF_ERR_INVALID, "block must be >= 0");
+  Layout Lo;
+  make_layout(Lo, model->N, model->dx, model->dy, block, LAYOUT_STEP, false, true);
+  if ((s = check_ws(Lo, ws, ws_bytes)) != AKF_OK) return s;
+  if ((s = prepare_device()) != AKF_OK) return s;
+  const KModel M = to_kmodel(model);
+  const size_t vn = (size_t)M.N * M.d;
+  hipStream_t st = (hipStream_t)stream;
+  bool fresh = true, trees = false;
+  for (int k = 0; k < n_steps; ++k) {
+    double* lr = log_ratio ? log_ratio + k : nullptr;
+    int32_t* acc = accepted ? accepted + k : nullptr;
+    double* zf = logZ_fwd ? logZ_fwd + k : nullptr;
+    double* zr = logZ_rev ? logZ_rev + k : nullptr;
+    int32_t* so = status ? status + k : nullptr;
+    const double* xik = xi + (size_t)k * 2 * vn;
+    if (order == 1) {
+      s = fixed_step_impl(Lo, M, y, x, delta, xik, unif + k, x, lr, acc, zf, zr, so, ws, st, k);
+      if (s != AKF_OK) return s;
+      continue;
+    }
+    s = reuse_step_impl(Lo, M, y, x, delta, xik, unif + k, x, lr, acc, zf, zr, so, ws, st, k,
+                        fresh, &trees);
+    if (s != AKF_OK) return s;
+    if (k + 1 == n_steps) break;
+    // the next forward proposal reuses this one's matrices iff x is unchanged
+    int32_t flags[2] = {0, 0};
+    if ((s = hip_check(hipMemcpyAsync(&flags[0], at<int>(ws, Lo.accept), sizeof(int),
+                                      hipMemcpyDeviceToHost, st),
+                       "accept flag copy")) != AKF_OK ||
+        (s = hip_check(hipMemcpyAsync(&flags[1], at<int>(ws, Lo.status) + (k & 1), sizeof(int),
+                                      hipMemcpyDeviceToHost, st),
+                       "status copy")) != AKF_OK ||
+        (s = hip_check(hipStreamSynchronize(st), "stream synchronize")) != AKF_OK)
+      return s;
+    fresh = flags[0] != 0 || flags[1] != 0;
   }
   return AKF_OK;
 }

@@ -105,8 +105,8 @@ __device__ __forceinline__ void xload_pad(double* s, const double* __restrict__ 
 // Set-up
 // ---------------------------------------------------------------------------
 
-// Phi_t^T = Omega F^T S_t^{-T} at reversed index N - 1 - t; Phi_0 = 0.  Team 0
-// also keeps F (padded, transposed) for the per-step products.
+// Phi_t^T = F^T S_t^{-T} Omega_t at reversed index N - 1 - t; Phi_0 = 0.
+// Team 0 also keeps F (padded, transposed) for the per-step products.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_phi(KModel M, FixedArgs A) {
   using C = Cfg<D>;
@@ -131,9 +131,9 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_phi(KModel M, FixedArgs A)
   }
   xload_pad<D>(B2, A.Sinv + (int64_t)t * D * D);  // the kept S^{-1} reads as S^{-T}
   team_sync();
-  gemm<D, false, false, false>(R, B1, B2);
-#pragma unroll
-  for (int q = 0; q < Cfg<D>::TPW; ++q) R.t[q] *= A.ovar;
+  gemm<D, false, false, false>(R, B1, B2);  // (S^{-1} F)^T
+  const double* Om = A.Om + (int64_t)t * d;
+  AKF_RM_FOR(D, q, r, i, j) R.t[q][r] *= (j < d) ? Om[j] : 0.0;  // Phi^T = (S^{-1} F)^T Omega
   rm_store<D>(R, out, D, D);
 }
 
@@ -187,19 +187,21 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_vtree_up_mat(const double* src, 
 // Per proposal: filtering means and log-likelihood terms
 // ---------------------------------------------------------------------------
 
-// What a mean step reads from HBM: its row group of the kept S_t^{-1}, omega_t
-// and log det S_t.
+// What a mean step reads from HBM: its row group of the kept S_t^{-1}, omega_t,
+// Omega_t and log det S_t.
 template <int D>
 struct MeanStep {
   double a[GMV<D>::JG];
-  double om, lds;
+  double om, Om, lds;
 };
 
 template <int D>
 __device__ __forceinline__ void mean_fetch(MeanStep<D>& m, const KModel& M, const FixedArgs& A,
                                            int t) {
   gmv_load<D>(m.a, A.Sinv + (int64_t)t * D * D);
-  m.om = (threadIdx.x < M.d) ? A.om[(int64_t)t * M.d + threadIdx.x] : 0.0;
+  const bool in = threadIdx.x < M.d;
+  m.om = in ? A.om[(int64_t)t * M.d + threadIdx.x] : 0.0;
+  m.Om = in ? A.Om[(int64_t)t * M.d + threadIdx.x] : 0.0;
   m.lds = A.ldS[t];
 }
 
@@ -257,7 +259,7 @@ __device__ double* mean_chain(const KModel& M, const FixedArgs& A, int s_hi, int
     team_sync();
     const double y = gmv_combine<D>(gmv_dot<D>(m0.a, L.rv), L.red);  // S^{-1} r
     if (tid < D) {
-      const double xn = (tid < d) ? m0.om - A.ovar * y : 0.0;
+      const double xn = (tid < d) ? m0.om - m0.Om * y : 0.0;
       L.xv[cur ^ 1][tid] = xn;
       if (FINAL) A.mf[(int64_t)t * D + tid] = xn;
     }

@@ -128,14 +128,15 @@ struct SampArgs {
   double *Lc, *Et;
 };
 
-// Steps whose auxiliary model has the same covariances every time (first
-// order: Omega_t = delta/2 I), with the matrices formed once per call.  Every
-// kept matrix is stored transposed (At[j*D + i] = A_ij), so that a
-// matrix-vector product reads it in coalesced columns.
+// Proposals whose auxiliary model has covariances formed earlier (first
+// order: Omega_t = delta/2 I for every path; second order: the same x as the
+// proposal that formed them), with the matrices kept.  Every kept matrix is
+// stored transposed (At[j*D + i] = A_ij), so that a matrix-vector product
+// reads it in coalesced columns.
 struct FixedArgs {
   int B;                   // scan block (steps)
   const double* om;        // [N*d] pseudo-observations of this proposal
-  double ovar;             // Omega = ovar I
+  const double* Om;        // [N*d] diagonal Omega_t the matrices were formed with
   const double *Sinv, *ldS;  // S_t^{-1} [N*D*D], log det S_t [N]
   const double *Et, *Lc;   // sampler E_t, chol(L_t) [N*D*D]
   double* Phi;             // [N*D*D] Phi_{N-1-s} at s (set-up, for the tree products)

@@ -1483,6 +1483,7 @@ __global__ void __launch_bounds__(256) k_mh_decide(KModel M, StepArgs A, FinalAr
     const int acc = (st == 0) && (log(F.unif[0]) < lr);
     sacc = acc;
     if (blockIdx.x == 0) {
+      *A.accept_flag = acc;  // for callers that read the decision back
       if (F.log_ratio) *F.log_ratio = lr;
       if (F.accepted) *F.accepted = acc;
       if (F.logZ_fwd) *F.logZ_fwd = lzf;

@@ -227,13 +227,15 @@ def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: 
            ws: Optional[Workspace] = None, outputs: bool = True, factorised: bool = False,
            reuse_matrices: bool = False) -> dict:
     """n_steps MH steps, x updated in place.  xi [n_steps,2,N,dx], unif [n_steps].
-    factorised as in mh_step.  reuse_matrices (order 1, dense prior): the
-    auxiliary model's covariances are formed once for the whole call
-    (akf_mh_run_first_order); the chain is the same up to rounding."""
+    factorised as in mh_step.  reuse_matrices (dense prior): the auxiliary
+    model's matrices are reused wherever unchanged -- order 1: formed once for
+    the whole call (akf_mh_run_first_order); order 2: kept from a forward
+    proposal for the next one after a rejection (akf_mh_run_reuse, one host
+    synchronisation per step).  The chain is the same up to rounding."""
     lib = _lib.load()
     _check_form(model, factorised)
-    if reuse_matrices and (factorised or order != 1):
-        raise ValueError("reuse_matrices needs order 1 and the dense prior")
+    if reuse_matrices and factorised:
+        raise ValueError("reuse_matrices takes the dense prior")
     dev = model.device
     N, dx = model.N, model.dx
     n = int(xi.shape[0])
@@ -257,13 +259,20 @@ def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: 
         rc = lib.akf_mh_run_factorised(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), n,
                                        _ptr(xi), _ptr(unif), *outs, wsp, wsb, _stream(dev))
         _lib.check(rc, "akf_mh_run_factorised")
-    elif reuse_matrices:
+    elif reuse_matrices and order == 1:
         need = _need(lib.akf_mh_first_order_workspace_bytes(C.byref(ms), block),
                      "akf_mh_first_order_workspace_bytes")
         wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
         rc = lib.akf_mh_run_first_order(C.byref(ms), _ptr(y), _ptr(x), float(delta), n, _ptr(xi),
                                         _ptr(unif), *outs, wsp, wsb, int(block), _stream(dev))
         _lib.check(rc, "akf_mh_run_first_order")
+    elif reuse_matrices:
+        need = _need(lib.akf_mh_reuse_workspace_bytes(C.byref(ms), int(order), block),
+                     "akf_mh_reuse_workspace_bytes")
+        wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+        rc = lib.akf_mh_run_reuse(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order), n,
+                                  _ptr(xi), _ptr(unif), *outs, wsp, wsb, int(block), _stream(dev))
+        _lib.check(rc, "akf_mh_run_reuse")
     else:
         need = _need(lib.akf_mh_workspace_bytes(C.byref(ms), order, block),
                      "akf_mh_workspace_bytes")

@@ -208,3 +208,32 @@ def test_first_order_run_validation():
     assert lib.akf_mh_first_order_workspace_bytes(C.byref(nl), 0) == 0
     assert b"linear dynamics" in lib.akf_last_error()
     assert call(nl) == 5
+
+
+def test_reuse_run_validation():
+    lib = _lib.load()
+    m = _fake_model(N=128, dx=10, emit=1)
+    need2 = lib.akf_mh_reuse_workspace_bytes(C.byref(m), 2, 0)
+    assert need2 == lib.akf_mh_first_order_workspace_bytes(C.byref(m), 0) > 0
+    assert lib.akf_mh_reuse_workspace_bytes(C.byref(m), 1, 0) == need2
+    assert lib.akf_mh_reuse_workspace_bytes(C.byref(m), 3, 0) == 0
+    # GAUSSIAN has a dense Omega under order 2
+    g = _fake_model(N=128, dx=10, dy=4, emit=0)
+    assert lib.akf_mh_reuse_workspace_bytes(C.byref(g), 2, 0) == 0
+    assert b"dense Omega" in lib.akf_last_error()
+    assert lib.akf_mh_reuse_workspace_bytes(C.byref(g), 1, 0) > 0
+    p = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x100000)
+    call = lambda model, order=2, n=1, delta=0.5, wsb=need2: lib.akf_mh_run_reuse(
+        C.byref(model), p, p, delta, order, n, p, p, None, None, None, None, None, ws, wsb, 0, None)
+    assert call(g) == 5
+    assert call(m, n=-1) == 1
+    assert call(m, delta=-1.0) == 1
+    assert call(m, wsb=need2 - 1) == 3
+    nl = _fake_model(N=64, dx=3, dy=2, emit=5)
+    nl.scale = 1.0
+    nl.dyn = 1
+    nl.F = None
+    nl.dyn_par[3] = 2e-4
+    assert lib.akf_mh_reuse_workspace_bytes(C.byref(nl), 2, 0) == 0
+    assert call(nl) == 5

@@ -162,12 +162,12 @@ def test_matches_plain_run(S):
     np.testing.assert_allclose(N_(xb), N_(xa), rtol=1e-9, atol=1e-10)
 
 
-def test_rejects_second_order(S):
+def test_rejects_factorised(S):
     w = W.poisson_ar1(N=16)
-    M_dev = S.DeviceModel.from_workload(w, device=dev())
+    M_dev = S.DeviceModel.from_workload(w, device=dev()).diagonal()
     with pytest.raises(ValueError):
-        S.mh_run(M_dev, T(w.y), T(np.zeros((16, 8))), w.delta, 2, T(w.normals(1)),
-                 T(w.uniforms(1)), reuse_matrices=True)
+        S.mh_run(M_dev, T(w.y), T(np.zeros((16, 8))), w.delta, 1, T(w.normals(1)),
+                 T(w.uniforms(1)), factorised=True, reuse_matrices=True)
 
 
 def test_latent_field_full_size(S):
