@@ -54,31 +54,55 @@ KERNEL_SOURCES = ("paper_2303_00301_amd/csrc/akf_team.hpp",
                   "paper_2303_00301_amd/csrc/akf_kernels.hip")
 
 
-def kernel_source_digest() -> str:
+FIXED_TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                  "first_order_mfold_latent_field_traffic.txt")
+FIXED_SOURCES = ("paper_2303_00301_amd/csrc/akf_team.hpp",
+                 "paper_2303_00301_amd/csrc/akf_internal.h",
+                 "paper_2303_00301_amd/csrc/akf_fixed.hip")
+
+
+def _digest(sources) -> str:
     import hashlib
     h = hashlib.sha256()
     root = os.path.dirname(os.path.abspath(__file__))
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(root, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def kernel_source_digest() -> str:
+    return _digest(KERNEL_SOURCES)
+
+
+def fixed_source_digest() -> str:
+    return _digest(FIXED_SOURCES)
+
+
+def _traffic(path: str, digest: str, block: int):
+    try:
+        with open(path) as f:
+            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
+    except OSError:
+        return None
+    kv = {k.strip(): v.strip() for k, v in kv.items()}
+    if kv.get("kernel_source_sha256") != digest:
+        return None
+    if int(kv.get("scan_block", "-1")) != block:
+        return None
+    return float(kv["traffic_bytes_per_launch"])
 
 
 def measured_traffic(block: int):
     """HBM bytes per fold launch from the committed FETCH_SIZE / WRITE_SIZE
     counter summary, or None when there is none, it was taken at another scan
     block size, or the kernel sources changed since it was taken."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            kv = dict(line.split(":", 1) for line in f if ":" in line and not line.startswith("#"))
-    except OSError:
-        return None
-    kv = {k.strip(): v.strip() for k, v in kv.items()}
-    if kv.get("kernel_source_sha256") != kernel_source_digest():
-        return None
-    if int(kv.get("scan_block", "-1")) != block:
-        return None
-    return float(kv["traffic_bytes_per_launch"])
+    return _traffic(TRAFFIC_FILE, kernel_source_digest(), block)
+
+
+def measured_fixed_traffic(block: int):
+    """The same for k_mfold<64> of the first-order run."""
+    return _traffic(FIXED_TRAFFIC_FILE, fixed_source_digest(), block)
 
 
 def auto_block(N: int, d: int) -> int:
@@ -284,7 +308,8 @@ def bench_first_order(torch, S, W, _lib, K: int, dev) -> dict:
                 gbs = nbytes / (avg_ms * 1e-3) / 1e9
                 out[key]["roofline"] = {"bound": "hbm", "kernel": "k_mfold<64>",
                                         "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                                        "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                                        "frac": gbs / PEAK_HBM_GBS,
+                                        "traffic": measured_fixed_traffic(auto_block(N, d)),
                                         "avg_launch_ms": avg_ms, "launches": n_l.value,
                                         "bytes_per_launch": nbytes}
     out["speedup"] = out["plain"]["ms_per_step"] / out["matrices_once_per_call"]["ms_per_step"]

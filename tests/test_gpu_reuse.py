@@ -163,3 +163,17 @@ def test_latent_field_full_size(S):
     acc = _follow(S, M_or, M_dev, w.y, w.x_true.copy(), 3.0 * w.delta, w.normals(4),
                   w.uniforms(4))
     assert _rejected_before_last(acc)
+
+
+def test_single_coordinate(S):
+    """d = 1 (one active coordinate of a 16-wide team), Student-t, N = 50; the
+    oracle's chain rejects six steps, then accepts one."""
+    rng = np.random.default_rng(56)
+    N = 50
+    kw = dict(m0=np.zeros(1), P0=np.eye(1), F=np.array([[0.7]]), Q=np.array([[0.4]]), emit=2,
+              site=np.array([0], np.int32), nu=3.0, scale=0.5)
+    M_or = oracle.Model(**kw)
+    M_dev = S.DeviceModel.from_arrays(N, device=dev(), **kw)
+    y = rng.standard_normal((N, 1))
+    _follow(S, M_or, M_dev, y, 0.3 * rng.standard_normal((N, 1)), 0.1,
+            rng.standard_normal((8, 2, N, 1)), rng.random(8))
