@@ -1192,13 +1192,13 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArg
 // ---------------------------------------------------------------------------
 template <int D>
 __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs& S, int item) {
+  // two LDS matrices (X, Y), so that two teams share a CU: both buffers serve
+  // the inverse as scratch, and G = F P^f is formed again after it
   using C = Cfg<D>;
   extern __shared__ double lds[];
-  double* sF = lds;
-  double* B1 = sF + C::MAT;
-  double* B2 = B1 + C::MAT;
-  double* B3 = B2 + C::MAT;
-  double* vm = B3 + C::MAT;
+  double* X = lds;
+  double* Y = X + C::MAT;
+  double* vm = Y + C::MAT;
   double* vmp = vm + D;
   double* vg = vmp + D;
   double* vxi = vg + D;
@@ -1212,13 +1212,13 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   bool ok = true;
   double ld;
   if (t == M.N - 1) {
-    ok = chol_reg<D>(Pf, d, B3, &ld);
+    ok = chol_reg<D>(Pf, d, X, &ld);
     if (S.Lc) rm_store_t<D>(Pf, S.Lc + (int64_t)t * D * D, D);
-    rm_stage<D>(Pf, B2);
+    rm_stage<D>(Pf, Y);
     team_sync();
     if (tid < D) {
       double s = vm[tid];
-      for (int j = 0; j <= tid; ++j) s = fma(B2[tid * C::LD + j], vxi[j], s);
+      for (int j = 0; j <= tid; ++j) s = fma(Y[tid * C::LD + j], vxi[j], s);
       S.U[(int64_t)t * D + tid] = s;
     }
     RM<D> Z;
@@ -1228,41 +1228,49 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
   } else {
     rm_load<D>(R2, M.Q, d, d);  // issued early: its latency overlaps G = F P^f
     // the transition into step t + 1
-    lds_load_mat<D>(sF, S.Ft ? S.Ft + (int64_t)(t + 1) * d * d : M.F, d);
+    lds_load_mat<D>(X, S.Ft ? S.Ft + (int64_t)(t + 1) * d * d : M.F, d);  // X = F
     const double* bt = S.Ft ? S.bt + (int64_t)(t + 1) * d : M.b;
-    rm_stage<D>(Pf, B1);
+    rm_stage<D>(Pf, Y);
     team_sync();
-    gemm<D, false, false, false>(R1, sF, B1);  // G = F P^f
+    gemm<D, false, false, false>(R1, X, Y);  // G = F P^f
     team_sync();
-    rm_stage<D>(R1, B1);  // B1 = G
+    rm_stage<D>(R1, Y);  // Y = G
     team_sync();
-    gemm<D, false, true, true>(R2, B1, sF);  // Q + G F'
-    matvec<D, false>(vmp, sF, vm);
+    gemm<D, false, true, true>(R2, Y, X);  // Q + G F'
+    matvec<D, false>(vmp, X, vm);
     if (tid < d && bt) vmp[tid] += bt[tid];
     {
       const RM<D> Pp = R2;
-      ok = spd_inv<D>(R2, d, B3, &ld) && ok;  // (P^p)^{-1}
-      inv_refine<D>(R2, Pp, d, B2, B3);       // P^p inherits the conditioning of Q
+      ok = spd_inv<D>(R2, d, X, &ld) && ok;  // (P^p)^{-1}
+      inv_refine<D>(R2, Pp, d, X, Y);        // P^p inherits the conditioning of Q
     }
-    rm_stage<D>(R2, B2);
+    // G again (cheaper than holding it in registers through the inverse)
+    lds_load_mat<D>(X, S.Ft ? S.Ft + (int64_t)(t + 1) * d * d : M.F, d);  // X = F
+    rm_stage<D>(Pf, Y);
     team_sync();
-    gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
+    gemm<D, false, false, false>(R1, X, Y);  // G = F P^f
+    team_sync();
+    rm_stage<D>(R2, X);  // X = (P^p)^{-1}
+    rm_stage<D>(R1, Y);  // Y = G
+    team_sync();
+    gemm<D, true, false, false>(R1, Y, X);  // E = G' (P^p)^{-1}
     rm_store<D>(R1, S.E + (int64_t)t * D * D, D, D);
     if (S.Et) rm_store_t<D>(R1, S.Et + (int64_t)t * D * D, D);
-    rm_stage<D>(R1, B3);  // B3 = E
     team_sync();
-    gemm<D, false, false, false>(R2, B3, B1);  // E G
-    rm_rsub<D>(R2, Pf);                        // L_t = P^f - E G
-    matvec<D, false>(vg, B3, vmp);
+    rm_stage<D>(R1, X);  // X = E
+    team_sync();
+    gemm<D, false, false, false>(R2, X, Y);  // E G
+    rm_rsub<D>(R2, Pf);                      // L_t = P^f - E G
+    matvec<D, false>(vg, X, vmp);
     if (tid < D) vg[tid] = vm[tid] - vg[tid];  // g = m^f - E m^p
-    rm_symmetrise<D>(R2, B2);
-    ok = chol_reg<D>(R2, d, B3, &ld) && ok;
+    rm_symmetrise<D>(R2, Y);
+    ok = chol_reg<D>(R2, d, X, &ld) && ok;
     if (S.Lc) rm_store_t<D>(R2, S.Lc + (int64_t)t * D * D, D);
-    rm_stage<D>(R2, B2);
+    rm_stage<D>(R2, Y);
     team_sync();
     if (tid < D) {
       double s = vg[tid];
-      for (int j = 0; j <= tid; ++j) s = fma(B2[tid * C::LD + j], vxi[j], s);
+      for (int j = 0; j <= tid; ++j) s = fma(Y[tid * C::LD + j], vxi[j], s);
       S.U[(int64_t)t * D + tid] = s;
     }
   }
@@ -1270,7 +1278,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
 }
 
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) k_samp_build(KModel M, SampArgs S) {
+__global__ void __launch_bounds__(Cfg<D>::NT, 2) k_samp_build(KModel M, SampArgs S) {
   samp_build_body<D>(M, S, blockIdx.x);
 }
 
@@ -1521,6 +1529,11 @@ template <int D>
 size_t lds_bytes_filter(bool gh = false) {
   return (size_t)((gh ? 5 : 4) * Cfg<D>::MAT + 12 * D + 16) * sizeof(double);
 }
+// the sampler element build: two matrices and four vectors (two teams per CU)
+template <int D>
+size_t lds_bytes_samp_build() {
+  return (size_t)(2 * Cfg<D>::MAT + 4 * D) * sizeof(double);
+}
 template <int D>
 size_t lds_bytes_samp2() {
   return (size_t)(2 * Cfg<D>::MAT + 2 * D) * sizeof(double);
@@ -1617,7 +1630,8 @@ template <int D>
 hipError_t launch_sampler(const KModel& M, SampArgs S, TreeArgs* lv_up, TreeArgs* lv_down,
                           int n_levels, hipStream_t st) {
   timing_mark(FAM_SAMP_BUILD, 1, st);
-  hipLaunchKernelGGL(k_samp_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_filter<D>(), st, M, S);
+  hipLaunchKernelGGL(k_samp_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_samp_build<D>(), st,
+                     M, S);
   timing_mark(FAM_SAMP_BUILD, 0, st);
   return launch_samp_scan<D>(M, S, lv_up, lv_down, n_levels, st);
 }
