@@ -195,6 +195,7 @@ struct Kept {
   FixedArgs X;
   KeptTree phi, e;
   double *Pf;
+  double *Sinv, *ldS, *Et, *Lc;  // written by the plain forward pass that keeps them
 };
 
 Kept kept_state(const Layout& Lo, void* ws, const StepArgs& A, const double* xi_x,
@@ -217,6 +218,10 @@ Kept kept_state(const Layout& Lo, void* ws, const StepArgs& A, const double* xi_
   K.phi = kept_tree(Lo, ws, Lo.tphi);
   K.e = kept_tree(Lo, ws, Lo.te);
   K.Pf = at<double>(ws, Lo.Pf);
+  K.Sinv = at<double>(ws, Lo.Sinv);
+  K.ldS = at<double>(ws, Lo.ldS);
+  K.Et = at<double>(ws, Lo.Et);
+  K.Lc = at<double>(ws, Lo.Lc);
   return K;
 }
 
@@ -227,11 +232,11 @@ akf_status forward_keep(const Layout& Lo, const KModel& M, void* ws, const StepA
   akf_status s;
   const double* xi_x = K.X.xi_x;
   if ((s = run_filter(Lo, M, ws, A.om, A.Om, nullptr, K.X.mf, K.Pf, Lo.D, A.ell, status,
-                      ST_FWD_NOT_PD, st, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
-                      const_cast<double*>(K.X.Sinv), const_cast<double*>(K.X.ldS))) != AKF_OK)
+                      ST_FWD_NOT_PD, st, nullptr, nullptr, nullptr, 0, nullptr, nullptr, K.Sinv,
+                      K.ldS)) != AKF_OK)
     return s;
   return run_sampler(Lo, M, ws, K.X.mf, K.Pf, Lo.D, xi_x, A.xs, status, st, nullptr, nullptr,
-                     const_cast<double*>(K.X.Lc), const_cast<double*>(K.X.Et));
+                     K.Lc, K.Et);
 }
 
 // Phi_t = Omega_t S_t^{-1} F and the node products of both kept scans.
