@@ -91,7 +91,10 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
     }
   }, 8192);
   tab(cp.fold, [&] { for (int c : cp.chains) for (int k = 0; k < lay[c].nb; ++k) b.items.push_back({c, k}); }, team_cap);
-  tab(cp.sbuild, [&] { for (int c : cp.chains) for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t}); }, team_cap);
+  // the sampler element build runs two one-wave teams per SIMD at D = 32
+  // (D = 16 teams already do; D = 64 teams take a whole CU)
+  const int sbuild_cap = (cp.D == 32 ? 2 : 1) * team_cap;
+  tab(cp.sbuild, [&] { for (int c : cp.chains) for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t}); }, sbuild_cap);
   tab(cp.fin, [&] { for (int c : cp.chains) b.items.push_back({c, 0}); }, 1024);
   for (int l = 1; l <= cp.Lmax; ++l) {
     tab(cp.up[l], [&] {

@@ -1893,8 +1893,10 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_down(BatchLaunch L, int level, 
   }
 }
 
+// two teams per SIMD where the persistent loop's registers still fit (D <= 32)
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) kb_sbuild(BatchLaunch L, const int* step) {
+__global__ void __launch_bounds__(Cfg<D>::NT, D == 64 ? 1 : 2) kb_sbuild(BatchLaunch L,
+                                                                     const int* step) {
   const int s = *step;
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
@@ -1979,14 +1981,20 @@ hipError_t launch_step_advance(int* step, int reset, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <int D>
+size_t batch_lds_bytes_t(int phase) {
+  if (phase == BP_FOLD || phase == BP_UP || phase == BP_DOWN || phase == BP_FINAL)
+    return lds_bytes_filter<D>();
+  if (phase == BP_SBUILD) return lds_bytes_samp_build<D>();
+  if (phase == BP_SFOLD || phase == BP_SUP) return lds_bytes_samp2<D>();
+  return 0;
+}
+
 size_t batch_lds_bytes(int D, int phase) {
-  const bool team = phase == BP_FOLD || phase == BP_UP || phase == BP_DOWN || phase == BP_FINAL ||
-                    phase == BP_SBUILD;
-  const bool two = phase == BP_SFOLD || phase == BP_SUP;
   switch (D) {
-    case 16: return team ? lds_bytes_filter<16>() : (two ? lds_bytes_samp2<16>() : 0);
-    case 32: return team ? lds_bytes_filter<32>() : (two ? lds_bytes_samp2<32>() : 0);
-    case 64: return team ? lds_bytes_filter<64>() : (two ? lds_bytes_samp2<64>() : 0);
+    case 16: return batch_lds_bytes_t<16>(phase);
+    case 32: return batch_lds_bytes_t<32>(phase);
+    case 64: return batch_lds_bytes_t<64>(phase);
   }
   return 0;
 }

@@ -125,3 +125,35 @@ def test_autotuner_cache(S, tmp_path):
     assert len(open(cache).read().strip().splitlines()) == len(lines)
     p1.close()
     p2.close()
+
+
+def test_batch_with_every_team_width(S):
+    """Chains of d = 8, 20 and 64 in one batch (all three team widths): every
+    chain equals its own akf_mh_run, and the first step of the d = 64 chain
+    equals the oracle's."""
+    ws = W.ragged_poisson_batch(n_chains=6, n_min=40, n_max=120, dims=(8, 20, 64), seed=13)
+    assert {w.dx for w in ws} == {8, 20, 64}
+    n_steps = 2
+    chains = _chains(S, ws, n_steps)
+    plan = S.BatchPlan(chains, n_steps, block=8)
+    assert {c["D"] for c in plan.info()["classes"]} == {16, 32, 64}
+    plan.run(use_graph=True)
+    torch.cuda.synchronize()
+    for c in chains:
+        x = T(c["x0"])
+        ref = S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"], block=8)
+        torch.cuda.synchronize()
+        assert torch.equal(c["status"], ref["status"])
+        assert torch.equal(c["accepted"], ref["accepted"])
+        torch.testing.assert_close(c["x"], x, rtol=1e-9, atol=1e-11)
+        for k in ("log_ratio", "logZ_fwd", "logZ_rev"):
+            torch.testing.assert_close(c[k], ref[k], rtol=1e-9, atol=1e-9, msg=k)
+    plan.close()
+    k64 = next(k for k, w in enumerate(ws) if w.dx == 64)
+    w = ws[k64]
+    xi = w.normals(n_steps)
+    r = oracle.mh_step(oracle.Model(**w.oracle_kwargs()), w.y, np.log(w.y + 0.5), w.delta, 2,
+                       xi[0][0], xi[0][1], float(w.uniforms(n_steps)[0]))
+    assert int(chains[k64]["status"].cpu()[0]) == r["status"]
+    lr = float(chains[k64]["log_ratio"].cpu()[0])
+    assert abs(lr - r["log_ratio"]) <= 1e-9 * w.N * w.dx + 1e-9 * max(1.0, abs(r["log_ratio"]))
