@@ -113,23 +113,26 @@ def auto_block(N: int, d: int) -> int:
     return min(B, N)
 
 
-def cpu_baseline(w, n_steps: int) -> dict:
+def cpu_baseline(w, n_steps: int, order=None, delta=None) -> dict:
     """The FP64 oracle (sequential C, one thread) on a bounded sample: n_steps
     full MH steps of the same workload, from the same state and normals."""
     import numpy as np
     import oracle
+    order = w.order if order is None else order
+    delta = w.delta if delta is None else delta
     M = oracle.Model(**w.oracle_kwargs())
     xi = w.normals(n_steps)
     un = w.uniforms(n_steps)
     x = w.x_true.copy()
     t0 = time.perf_counter()
     for k in range(n_steps):
-        r = oracle.mh_step(M, w.y, x, w.delta, w.order, xi[k, 0], xi[k, 1], un[k])
+        r = oracle.mh_step(M, w.y, x, delta, order, xi[k, 0], xi[k, 1], un[k])
         x = r["x_out"]
     dt = time.perf_counter() - t0
     return {"value": n_steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_steps} full MH steps of the same workload (d_x=64, T=4096) by the "
-                      f"sequential FP64 C oracle on one host thread, {dt:.1f} s",
+            "sample": f"{n_steps} full MH steps of order {order} on the same workload "
+                      f"(d_x={w.dx}, T={w.N}) by the sequential FP64 C oracle on one host "
+                      f"thread, {dt:.1f} s",
             "seconds": dt}
 
 
@@ -260,7 +263,7 @@ def bench_stoch_vol(torch, S, W, K: int, dev) -> dict:
     return out
 
 
-def bench_first_order(torch, S, W, _lib, K: int, dev) -> dict:
+def bench_first_order(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
     """First-order steps on the latent-field workload (d_x = 64, T = 4096): the
     plain step, which forms the auxiliary model's covariances every step, and
     the run that forms them once per call (the first step pays for it).  The
@@ -313,15 +316,20 @@ def bench_first_order(torch, S, W, _lib, K: int, dev) -> dict:
                                         "avg_launch_ms": avg_ms, "launches": n_l.value,
                                         "bytes_per_launch": nbytes}
     out["speedup"] = out["plain"]["ms_per_step"] / out["matrices_once_per_call"]["ms_per_step"]
+    if cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline(w, cpu_steps, order=1, delta=delta)
     return out
 
 
-def bench_reuse(torch, S, W, K: int, dev) -> dict:
+def bench_reuse(torch, S, W, _lib, K: int, dev) -> dict:
     """The headline workload (latent field, d_x = 64, T = 4096, order 2) run
     plainly and with the matrices of a forward proposal reused by the next one
     after a rejection (akf_mh_run_reuse; one host synchronisation per step).
     Both runs take the same normals and uniforms from the same state, so they
-    make the same decisions."""
+    make the same decisions.  The roofline is that of the filter fold, which
+    every step's reverse proposal (and every full forward one) runs."""
+    import ctypes as C
+    lib = _lib.load()
     w = W.latent_field()
     M = S.DeviceModel.from_workload(w, device=dev)
     y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
@@ -336,6 +344,9 @@ def bench_reuse(torch, S, W, K: int, dev) -> dict:
         x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
         S.mh_run(M, y, x, w.delta, 2, xi[:2], un[:2], ws=ws, reuse_matrices=reuse)
         torch.cuda.synchronize()
+        if reuse:
+            _lib.check(lib.akf_timing_enable(_lib.FAMILIES["filter_fold"], 4 * K + 8),
+                       "akf_timing_enable")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
         r = S.mh_run(M, y, x, w.delta, 2, xi[2:], un[2:], ws=ws, reuse_matrices=reuse)
@@ -345,6 +356,19 @@ def bench_reuse(torch, S, W, K: int, dev) -> dict:
         out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
                     "acceptance": r["accepted"].float().mean().item(),
                     "rejected_by_status": int((r["status"] != 0).sum().item())}
+        if reuse:
+            n_l, k_ms = C.c_int32(), C.c_double()
+            _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
+            lib.akf_timing_enable(-1, 0)
+            if n_l.value > 0:
+                B = auto_block(w.N, w.dx)
+                avg_ms = k_ms.value / n_l.value
+                achieved = fold_flops_per_launch(w.N, w.dx, B) / (avg_ms * 1e-3) / 1e12
+                out[key]["roofline"] = {"bound": "mfma", "kernel": "k_filter_fold<64>",
+                                        "achieved": achieved, "peak": PEAK_FP64_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": achieved / PEAK_FP64_TFLOPS,
+                                        "traffic": measured_traffic(B),
+                                        "avg_launch_ms": avg_ms, "launches": n_l.value}
     out["speedup"] = out["plain"]["ms_per_step"] / out["reuse_after_reject"]["ms_per_step"]
     return out
 
@@ -616,13 +640,17 @@ def main() -> int:
     if not args.no_samplers:
         res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev)
     if not args.no_first_order:
-        res["first_order"] = bench_first_order(torch, S, W, _lib, 50, dev)
+        res["first_order"] = bench_first_order(torch, S, W, _lib, 50, dev,
+                                               0 if args.no_cpu_baseline else 1)
     if not args.no_reuse:
-        res["reuse_order2"] = bench_reuse(torch, S, W, 30, dev)
+        res["reuse_order2"] = bench_reuse(torch, S, W, _lib, 30, dev)
     if not args.no_lorenz:
         res["nonlinear"] = bench_lorenz(torch, S, W, 20, dev, 0 if args.no_cpu_baseline else 10)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+        if "reuse_order2" in res:
+            # the oracle's plain order-2 step is the same computation on the same workload
+            res["reuse_order2"]["cpu_baseline"] = dict(res["cpu_baseline"])
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
