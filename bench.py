@@ -61,6 +61,29 @@ FIXED_SOURCES = ("paper_2303_00301_amd/csrc/akf_team.hpp",
                  "paper_2303_00301_amd/csrc/akf_fixed.hip")
 
 
+def timed_launches(lib, _lib, family: str, capacity: int, fn):
+    """Run fn() with HIP-event timing on every launch of one kernel family;
+    returns (average launch ms, launches) or (None, 0)."""
+    import ctypes as C
+    _lib.check(lib.akf_timing_enable(_lib.FAMILIES[family], capacity), "akf_timing_enable")
+    fn()
+    n_l, k_ms = C.c_int32(), C.c_double()
+    _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
+    lib.akf_timing_enable(-1, 0)
+    return (k_ms.value / n_l.value, n_l.value) if n_l.value else (None, 0)
+
+
+def roofline_obj(bound: str, kernel: str, work: float, avg_ms, peak: float, unit: str,
+                 scale: float, traffic=None) -> dict:
+    """work per launch (flops or bytes) / average launch time, against peak."""
+    if avg_ms is None:
+        return None
+    achieved = work / (avg_ms * 1e-3) / scale
+    return {"bound": bound, "kernel": kernel, "achieved": achieved, "peak": peak, "unit": unit,
+            "frac": achieved / peak, "traffic": traffic, "avg_launch_ms": avg_ms,
+            "work_per_launch": work}
+
+
 def _digest(sources) -> str:
     import hashlib
     h = hashlib.sha256()
@@ -235,9 +258,11 @@ def bench_adjoint(torch, S, W, reps: int, dev) -> dict:
             "adjoint_over_forward": mb / mf}
 
 
-def bench_stoch_vol(torch, S, W, K: int, dev) -> dict:
+def bench_stoch_vol(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
     """Second paper workload on the same path: multivariate stochastic volatility
-    (d_x = 30, T = 250), one chain, both linearisation orders."""
+    (d_x = 30, T = 250), one chain, both linearisation orders; roofline of the
+    filter fold (32-wide teams), the oracle timed beside it."""
+    lib = _lib.load()
     out = {"workload": "stoch_vol_d30_T250: F = 0.9 I, equicorrelated Q (tau 2, rho 0.25), "
                        "y ~ N(0, exp(x)) per coordinate, one chain"}
     for order in (1, 2):
@@ -253,13 +278,26 @@ def bench_stoch_vol(torch, S, W, K: int, dev) -> dict:
         S.mh_run(M, y, x, w.delta, order, xi[:2], un[:2], ws=ws)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        r = S.mh_run(M, y, x, w.delta, order, xi[2:], un[2:], ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
+        box = {}
+
+        def run():
+            e0.record()
+            box["r"] = S.mh_run(M, y, x, w.delta, order, xi[2:], un[2:], ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+
+        avg, _ = timed_launches(lib, _lib, "filter_fold", 4 * K + 8, run)
+        r = box["r"]
         ms = e0.elapsed_time(e1) / K
-        out[f"order{order}"] = {"delta": w.delta, "ms_per_step": ms, "steps_per_s": 1000.0 / ms,
-                                "acceptance": r["accepted"].float().mean().item()}
+        B = auto_block(w.N, w.dx)
+        res = {"delta": w.delta, "ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+               "acceptance": r["accepted"].float().mean().item(),
+               "roofline": roofline_obj("mfma", "k_filter_fold<32>",
+                                        fold_flops_per_launch(w.N, w.dx, B), avg,
+                                        PEAK_FP64_TFLOPS, "TFLOP/s", 1e12)}
+        if cpu_steps > 0:
+            res["cpu_baseline"] = cpu_baseline(w, cpu_steps, order=order)
+        out[f"order{order}"] = res
     return out
 
 
@@ -413,7 +451,12 @@ def bench_spatio_temporal(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dic
             _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
             lib.akf_timing_enable(-1, 0)
             if n_l.value:
-                res["k_fact_scan_avg_us"] = 1000.0 * k_ms.value / n_l.value
+                avg = k_ms.value / n_l.value
+                res["k_fact_scan_avg_us"] = 1000.0 * avg
+                # about 60 scalar FP64 operations per (time step, coordinate) for the
+                # filter and the sampler together, a division or square root as one
+                res["roofline"] = roofline_obj("alu", "k_fact_scan", 60.0 * w.N * w.dx, avg,
+                                               PEAK_FP64_TFLOPS, "TFLOP/s", 1e12)
         out[name] = res
     out["paper_reference"] = ("0.52 ms per iteration for the parallel-in-time auxiliary Kalman "
                               "sampler on an RTX 3090 (another machine: context only)")
@@ -436,11 +479,12 @@ def bench_spatio_temporal(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dic
     return out
 
 
-def bench_lorenz(torch, S, W, K: int, dev, cpu_steps: int) -> dict:
+def bench_lorenz(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dict:
     """Nonlinear dynamics: the Lorenz-63 SDE of the paper's diffusion-smoothing
     experiment (N = 10001 fine steps, d = 3, sparse Gaussian observations) and a
     Lorenz-96 ring (d = 40, N = 2048, Student-t observations), one chain each,
     second order, extended linearisation at x and x* every step."""
+    lib = _lib.load()
     out = {}
     for name, w in (("lorenz63", W.lorenz63()), ("lorenz96", W.lorenz96())):
         M = S.DeviceModel.from_workload(w, device=dev)
@@ -454,13 +498,23 @@ def bench_lorenz(torch, S, W, K: int, dev, cpu_steps: int) -> dict:
         S.mh_run(M, y, x, w.delta, w.order, xi[:2], un[:2], ws=ws)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        r = S.mh_run(M, y, x, w.delta, w.order, xi[2:], un[2:], ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
+        box = {}
+
+        def run():
+            e0.record()
+            box["r"] = S.mh_run(M, y, x, w.delta, w.order, xi[2:], un[2:], ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+
+        avg, _ = timed_launches(lib, _lib, "filter_fold", 4 * K + 8, run)
+        r = box["r"]
         ms = e0.elapsed_time(e1) / K
+        D = 16 if w.dx <= 16 else (32 if w.dx <= 32 else 64)
         res = {"workload": w.name, "d_x": w.dx, "T": w.N, "delta": w.delta, "ms_per_step": ms,
-               "steps_per_s": 1000.0 / ms, "acceptance": r["accepted"].float().mean().item()}
+               "steps_per_s": 1000.0 / ms, "acceptance": r["accepted"].float().mean().item(),
+               "roofline": roofline_obj("mfma", f"k_filter_fold<{D}>",
+                                        fold_flops_per_launch(w.N, w.dx, auto_block(w.N, w.dx)),
+                                        avg, PEAK_FP64_TFLOPS, "TFLOP/s", 1e12)}
         if cpu_steps > 0:
             import oracle
             Mo = oracle.Model(**w.oracle_kwargs())
@@ -484,11 +538,14 @@ def bench_lorenz(torch, S, W, K: int, dev, cpu_steps: int) -> dict:
     return out
 
 
-def bench_samplers(torch, S, W, _lib, K: int, dev) -> dict:
+def bench_samplers(torch, S, W, _lib, K: int, dev, cpu: bool = False) -> dict:
     """The two pathwise samplers on the same filtering moments (latent field,
     d = 64, T = 4096, pseudo-observations x + N(0, delta/2)): the prefix-sum
     sampler of the MH step (element build + suffix scan) and the
-    divide-and-conquer sampler (bisection tree of bridges)."""
+    divide-and-conquer sampler (bisection tree of bridges).  Rooflines: the
+    prefix-sum sampler's element build (8 d^3 per step) and the whole
+    divide-and-conquer sampler (8 d^3 per leaf step, 14 d^3 per midpoint)."""
+    lib = _lib.load()
     w = W.latent_field()
     M = S.DeviceModel.from_workload(w, device=dev)
     gen = torch.Generator(device=dev)
@@ -500,18 +557,63 @@ def bench_samplers(torch, S, W, _lib, K: int, dev) -> dict:
     mf, Pf, _, _ = S.aux_filter(M, om, Om)
     xi = torch.randn((K + 1, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
     out = {"workload": f"filtering moments of latent_field_d{w.dx}_T{w.N}"}
+    d, N = w.dx, w.N
+    work = {"prefix_sum": ("samp_build", "k_samp_build<64>", 8.0 * d ** 3 * N),
+            "divide_and_conquer": ("dnc", "the divide-and-conquer sampler (all its launches)",
+                                   8.0 * d ** 3 * N + 14.0 * d ** 3 * (N - 2))}
     for name, fn in (("prefix_sum", S.rts_sample), ("divide_and_conquer", S.dnc_sample)):
         ws = S.Workspace(dev)
         fn(M, mf, Pf, xi[0], ws=ws)
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for k in range(K):
-            fn(M, mf, Pf, xi[k + 1], ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
+
+        def run():
+            e0.record()
+            for k in range(K):
+                fn(M, mf, Pf, xi[k + 1], ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+
+        fam, kname, flops = work[name]
+        avg, _ = timed_launches(lib, _lib, fam, 2 * K + 8, run)
         out[name + "_ms"] = e0.elapsed_time(e1) / K
+        out[name + "_roofline"] = roofline_obj("mfma", kname, flops, avg, PEAK_FP64_TFLOPS,
+                                               "TFLOP/s", 1e12)
+    if cpu:
+        out["cpu_baseline"] = sampler_cpu_baseline(w, mf, Pf)
     return out
+
+
+def sampler_cpu_baseline(w, mf_dev, Pf_dev, dnc_steps: int = 512) -> dict:
+    """The oracle's two samplers on the same filtering moments: the prefix-sum
+    (RTS) sampler over the full series, the divide-and-conquer sampler over the
+    first dnc_steps steps scaled to the full length (its work is linear in T)."""
+    import numpy as np
+    import oracle
+    kw = w.oracle_kwargs()
+    F, Q, b = kw["F"], kw["Q"], kw.get("b")
+    mf = mf_dev.cpu().numpy()
+    Pf = Pf_dev.cpu().numpy()
+    mp = np.empty_like(mf)
+    Pp = np.empty_like(Pf)
+    mp[0], Pp[0] = kw["m0"], kw["P0"]
+    mp[1:] = mf[:-1] @ F.T + (0.0 if b is None else b)
+    Pp[1:] = F @ Pf[:-1] @ F.T + Q
+    xi = np.random.default_rng(5).standard_normal(mf.shape)
+    t0 = time.perf_counter()
+    oracle.rts_sample(F, mf, Pf, mp, Pp, xi)
+    t_rts = time.perf_counter() - t0
+    n = min(dnc_steps, w.N)
+    t0 = time.perf_counter()
+    oracle.dnc_sample(F, Q, mf[:n], Pf[:n], xi[:n], b=b)
+    t_dnc = (time.perf_counter() - t0) * w.N / n
+    return {"prefix_sum": {"value": 1.0 / t_rts, "unit": "samples/s", "cores": 1,
+                           "kind": "oracle",
+                           "sample": f"one full RTS sample (T = {w.N}), {t_rts:.1f} s"},
+            "divide_and_conquer": {"value": 1.0 / t_dnc, "unit": "samples/s", "cores": 1,
+                                   "kind": "oracle",
+                                   "sample": f"the first {n} steps of one sample, scaled by "
+                                             f"{w.N}/{n}: {t_dnc:.1f} s per full sample"}}
 
 
 def main() -> int:
@@ -633,19 +735,21 @@ def main() -> int:
     if not args.no_adjoint:
         res["adjoint"] = bench_adjoint(torch, S, W, 5, dev)
     if not args.no_stoch_vol:
-        res["stoch_vol"] = bench_stoch_vol(torch, S, W, 20, dev)
+        res["stoch_vol"] = bench_stoch_vol(torch, S, W, _lib, 20, dev,
+                                           0 if args.no_cpu_baseline else 20)
     if not args.no_spatio_temporal:
         res["spatio_temporal"] = bench_spatio_temporal(
             torch, S, W, _lib, 100, dev, 0 if args.no_cpu_baseline else 100)
     if not args.no_samplers:
-        res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev)
+        res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev, not args.no_cpu_baseline)
     if not args.no_first_order:
         res["first_order"] = bench_first_order(torch, S, W, _lib, 50, dev,
                                                0 if args.no_cpu_baseline else 1)
     if not args.no_reuse:
         res["reuse_order2"] = bench_reuse(torch, S, W, _lib, 30, dev)
     if not args.no_lorenz:
-        res["nonlinear"] = bench_lorenz(torch, S, W, 20, dev, 0 if args.no_cpu_baseline else 10)
+        res["nonlinear"] = bench_lorenz(torch, S, W, _lib, 20, dev,
+                                        0 if args.no_cpu_baseline else 10)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
         if "reuse_order2" in res:
