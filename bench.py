@@ -159,7 +159,7 @@ def cpu_baseline(w, n_steps: int, order=None, delta=None) -> dict:
             "seconds": dt}
 
 
-def bench_batched(torch, S, W, K: int, dev) -> dict:
+def bench_batched(torch, S, W, K: int, dev, cpu: bool = False) -> dict:
     """512 ragged chains (N ~ U{128..8192}, d ~ U{4,16,32}, Poisson log link):
     K steps as one batched plan (hipGraph replay) vs 512 sequential plain runs
     of the same K steps, same normals, same scan blocks."""
@@ -215,19 +215,38 @@ def bench_batched(torch, S, W, K: int, dev) -> dict:
     ms_plain = e0.elapsed_time(e1)
     n_ch = len(chains)
     plan.close()
-    return {"workload": "512 chains, N ~ U{128..8192}, d_x ~ U{4,16,32}, random stable F, "
-                        "Q = 0.1 I, Poisson log link, order 2",
-            "steps": K, "chains": n_ch, "time_steps": int(sum(w.N for w in ws)),
-            "batched_ms_per_step": ms_batched / K, "plain_ms_per_step": ms_plain / K,
-            "batched_chain_steps_per_s": n_ch * K / (ms_batched * 1e-3),
-            "plain_chain_steps_per_s": n_ch * K / (ms_plain * 1e-3),
-            "speedup_vs_plain": ms_plain / ms_batched,
-            "batched_time_steps_per_s": sum(w.N for w in ws) * K / (ms_batched * 1e-3),
-            "acceptance": acc, "classes": info["classes"], "plan_s": t_plan,
-            "setup_s": t_setup}
+    out = {"workload": "512 chains, N ~ U{128..8192}, d_x ~ U{4,16,32}, random stable F, "
+                       "Q = 0.1 I, Poisson log link, order 2",
+           "steps": K, "chains": n_ch, "time_steps": int(sum(w.N for w in ws)),
+           "batched_ms_per_step": ms_batched / K, "plain_ms_per_step": ms_plain / K,
+           "batched_chain_steps_per_s": n_ch * K / (ms_batched * 1e-3),
+           "plain_chain_steps_per_s": n_ch * K / (ms_plain * 1e-3),
+           "speedup_vs_plain": ms_plain / ms_batched,
+           "batched_time_steps_per_s": sum(w.N for w in ws) * K / (ms_batched * 1e-3),
+           "acceptance": acc, "classes": info["classes"], "plan_s": t_plan,
+           "setup_s": t_setup}
+    if cpu:
+        # the oracle steps a sample of the chains once each; its rate in time
+        # steps per second is comparable with batched_time_steps_per_s
+        import numpy as np
+        import oracle
+        sample = ws[:8]
+        t0 = time.perf_counter()
+        for w in sample:
+            xi = w.normals(1)[0]
+            oracle.mh_step(oracle.Model(**w.oracle_kwargs()), w.y, np.log(w.y + 0.5), w.delta, 2,
+                           xi[0], xi[1], float(w.uniforms(1)[0]))
+        dt = time.perf_counter() - t0
+        n_ts = sum(w.N for w in sample)
+        out["cpu_baseline"] = {"value": n_ts / dt, "unit": "time steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one MH step of each of the first {len(sample)} chains "
+                                         f"({n_ts} time steps) by the sequential FP64 C oracle "
+                                         f"on one host thread, {dt:.1f} s"}
+    return out
 
 
-def bench_adjoint(torch, S, W, reps: int, dev) -> dict:
+def bench_adjoint(torch, S, W, reps: int, dev, cpu: bool = False) -> dict:
     """log p(y | theta) and its reverse-mode adjoint, d_x = 32, d_y = 16, T = 16384."""
     pw = W.lgssm_params()
     model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev)
@@ -251,11 +270,26 @@ def bench_adjoint(torch, S, W, reps: int, dev) -> dict:
     tf.sort()
     tb.sort()
     mf, mb = tf[len(tf) // 2], tb[len(tb) // 2]
-    return {"workload": "LGSSM d_x=32, d_y=16, T=16384, theta = (F, log diag Q, H, log diag R), "
-                        "1584 parameters",
-            "forward_ms": mf, "adjoint_ms": mb,
-            "adjoint_time_steps_per_s": pw.N / ((mf + mb) * 1e-3),
-            "adjoint_over_forward": mb / mf}
+    out = {"workload": "LGSSM d_x=32, d_y=16, T=16384, theta = (F, log diag Q, H, log diag R), "
+                       "1584 parameters",
+           "forward_ms": mf, "adjoint_ms": mb,
+           "adjoint_time_steps_per_s": pw.N / ((mf + mb) * 1e-3),
+           "adjoint_over_forward": mb / mf}
+    if cpu:
+        # the oracle's log-likelihood and its gradient (the Fisher score, from the
+        # smoother) on the same series
+        import oracle
+        t = pw.theta0
+        t0 = time.perf_counter()
+        oracle.lgssm_loglik(pw.m0, pw.P0, t.F, t.logq, t.H, t.logr, pw.y)
+        oracle.fisher_score(pw.m0, pw.P0, t.F, t.logq, t.H, t.logr, pw.y)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": pw.N / dt, "unit": "time steps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"log-likelihood and gradient over the same {pw.N} "
+                                         f"steps by the sequential FP64 C oracle on one host "
+                                         f"thread, {dt:.1f} s"}
+    return out
 
 
 def bench_stoch_vol(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
@@ -731,9 +765,10 @@ def main() -> int:
         "roofline": roof,
     }
     if not args.no_batched:
-        res["batched"] = bench_batched(torch, S, W, args.batched_steps, dev)
+        res["batched"] = bench_batched(torch, S, W, args.batched_steps, dev,
+                                       not args.no_cpu_baseline)
     if not args.no_adjoint:
-        res["adjoint"] = bench_adjoint(torch, S, W, 5, dev)
+        res["adjoint"] = bench_adjoint(torch, S, W, 5, dev, not args.no_cpu_baseline)
     if not args.no_stoch_vol:
         res["stoch_vol"] = bench_stoch_vol(torch, S, W, _lib, 20, dev,
                                            0 if args.no_cpu_baseline else 20)
