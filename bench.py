@@ -180,8 +180,8 @@ def bench_batched(torch, S, W, K: int, dev, cpu: bool = False) -> dict:
                                            generator=gen).clamp_(min=1e-300),
                            accepted=torch.empty(K, dtype=torch.int32, device=dev)))
     t_setup = time.perf_counter() - t0
-    cache = os.path.join(os.path.dirname(os.path.abspath(__file__)), "gpurun_out",
-                         "batch_tune.jsonl")
+    import tempfile
+    cache = os.path.join(tempfile.gettempdir(), "auxkf_batch_tune.jsonl")
     os.makedirs(os.path.dirname(cache), exist_ok=True)
     t0 = time.perf_counter()
     plan = S.BatchPlan(chains, K, block=0, tune_cache=cache, device=dev)

@@ -45,7 +45,7 @@ typedef enum {
   AKF_ERR_SHAPE = 2,       /* sizes outside the supported range */
   AKF_ERR_WORKSPACE = 3,   /* ws_bytes smaller than required, or misaligned */
   AKF_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
-  AKF_ERR_UNSUPPORTED = 5  /* valid request this build does not implement */
+  AKF_ERR_UNSUPPORTED = 5  /* valid request the library does not implement */
 } akf_status;
 
 typedef enum {
