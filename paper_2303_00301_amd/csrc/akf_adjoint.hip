@@ -431,11 +431,12 @@ template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
   using C = Cfg<D>;
   extern __shared__ double lds[];
+  // six matrices and ten vectors (53 KB at D = 32), so that three one-wave
+  // teams share a CU
   double* sF = lds;
   double* sH = sF + C::MAT;
   double* B_HP = sH + C::MAT;
-  double* B_Li = B_HP + C::MAT;
-  double* B_Si = B_Li + C::MAT;
+  double* B_Si = B_HP + C::MAT;
   double* Bt = B_Si + C::MAT;
   double* Bu = Bt + C::MAT;
   double* vmp = Bu + C::MAT;
@@ -462,7 +463,8 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
   rm_zero<D>(gH);
   bool ok = true;
   for (int t = s0; t < s1; ++t) {
-    adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, B_Li, ok);
+    // Bt is free while S is inverted: it serves as the inverse's scratch
+    adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, Bt, ok);
     const bool last = (t == N - 1);
     rm_load<D>(Pf, G.Pf + (int64_t)t * D * D, D, D);
     if (tid < D) {
@@ -519,9 +521,9 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
       gemm<D, true, false, false>(R1, Bt, Bu);  // K' Fbar
       team_sync();
       rm_stage<D>(R1, Bu);
-      rm_stage<D>(Pf, B_Li);  // L^{-1} no longer needed
+      rm_stage<D>(Pf, B_HP);  // H Pp is no longer read in this step
       team_sync();
-      gemm<D, false, false, false>(R2, Bu, B_Li);  // K' Fbar P^f
+      gemm<D, false, false, false>(R2, Bu, B_HP);  // K' Fbar P^f
       rm_axpy<D>(gH, -2.0, R2);
       // (K' Fbar K)_jj = sum_i (K' Fbar)_ji K_ij
       if (tid < p) {
@@ -546,15 +548,19 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
 // scaled by the upstream gradient ll_bar.
 template <int D>
 __global__ void __launch_bounds__(256) k_adj_reduce(LgArgs G, int nblk, const double* ll_bar) {
-  const int tid = threadIdx.x + blockIdx.x * blockDim.x;
+  // 32 parameters per workgroup; thread row r (of 8) adds blocks r, r + 8, ...
+  // and the rows are added in row order, so the result does not depend on timing
+  __shared__ double acc[8][33];
+  const int px = threadIdx.x & 31, gy = threadIdx.x >> 5;
+  const int tid = blockIdx.x * 32 + px;
   const int d = G.dx, p = G.dy;
   const int tot = d * d + d + p * d + p;
-  if (tid >= tot) return;
-  const double sc = ll_bar ? *ll_bar : 1.0;
-  int off;
-  double* dst;
+  const bool valid = tid < tot;
+  int off = 0;
+  double* dst = nullptr;
   double mul = 1.0;
-  if (tid < d * d) {
+  if (!valid) {
+  } else if (tid < d * d) {
     const int i = tid / d, j = tid % d;
     off = i * D + j;
     dst = G.dF + tid;
@@ -574,8 +580,17 @@ __global__ void __launch_bounds__(256) k_adj_reduce(LgArgs G, int nblk, const do
     mul = exp(G.logr[k]);
   }
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += G.part[(int64_t)b * (2 * D * D + 2 * D) + off];
-  *dst = sc * mul * s;
+  if (valid)
+    for (int b = gy; b < nblk; b += 8) s += G.part[(int64_t)b * (2 * D * D + 2 * D) + off];
+  acc[gy][px] = s;
+  __syncthreads();
+  if (gy == 0 && valid) {
+    double t = acc[0][px];
+#pragma unroll
+    for (int r = 1; r < 8; ++r) t += acc[r][px];
+    const double sc = ll_bar ? *ll_bar : 1.0;
+    *dst = sc * mul * t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -648,10 +663,10 @@ template <int D>
 hipError_t launch_adj_finish_t(const KModel& M, LgArgs G, int nblk, const double* ll_bar,
                                hipStream_t st) {
   const int64_t n = (int64_t)M.N * D * D;
-  hipLaunchKernelGGL(k_adj_grad<D>, dim3(nblk), dim3(Cfg<D>::NT), lds_bytes_mats<D>(7, 15), st, M,
+  hipLaunchKernelGGL(k_adj_grad<D>, dim3(nblk), dim3(Cfg<D>::NT), lds_bytes_mats<D>(6, 10), st, M,
                      G);
   const int tot = G.dx * G.dx + G.dx + G.dy * G.dx + G.dy;
-  hipLaunchKernelGGL(k_adj_reduce<D>, dim3((tot + 255) / 256), dim3(256), 0, st, G, nblk, ll_bar);
+  hipLaunchKernelGGL(k_adj_reduce<D>, dim3((tot + 31) / 32), dim3(256), 0, st, G, nblk, ll_bar);
   (void)n;
   return hipGetLastError();
 }

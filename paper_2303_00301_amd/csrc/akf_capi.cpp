@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 
 #include "../../include/akf.h"
@@ -612,7 +613,23 @@ akf_status akf_lgssm_loglik_grad(const akf_lgssm* m, const double* ll_bar, doubl
   // G_t in place of Cm, then Pbar: (E, L) scan
   if ((s = hip_check(launch_adj_G_any(D, G, m->N, st), "adjoint G")) != AKF_OK) return s;
   if ((s = run_egl(Lo, ws, nullptr, G.Pbar, nullptr, D, D, st)) != AKF_OK) return s;
-  if ((s = hip_check(launch_adj_finish_any(D, M, G, Lo.nb, ll_bar, st), "adjoint gradient")) !=
+  // Gradient blocks: at width 32 a one-wave team of k_adj_grad fits three to a
+  // CU, so blocks of at least Lo.B steps are made long enough that all of them
+  // run at once (there are then no more of them than the layout's partial
+  // sums hold)
+  int nblk = Lo.nb;
+  if (D == 32) {
+    int dev = 0, ncu = 0;
+    if ((s = hip_check(hipGetDevice(&dev), "device query")) != AKF_OK) return s;
+    if ((s = hip_check(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev),
+                       "CU count query")) != AKF_OK)
+      return s;
+    const int slots = 3 * (ncu > 0 ? ncu : 1);
+    const int Bg = std::max(Lo.B, (m->N + slots - 1) / slots);
+    G.B = Bg;
+    nblk = (m->N + Bg - 1) / Bg;
+  }
+  if ((s = hip_check(launch_adj_finish_any(D, M, G, nblk, ll_bar, st), "adjoint gradient")) !=
       AKF_OK)
     return s;
   if (status)
