@@ -357,15 +357,17 @@ __device__ void adj_step_quantities(const KModel& M, const LgArgs& G, int t, con
 // Cm_t = -1/2 H' (S^{-1} - w w') H.  One team per t, D <= 32.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
+  // four LDS matrices (F, H and two work buffers X, Y; 35 KB at D = 32), so
+  // that four one-wave teams share a CU.  Y serves in turn as staging, as the
+  // inverse's scratch and as S^{-1}; K is formed into registers first, which
+  // frees both work buffers for the rest.
   using C = Cfg<D>;
   extern __shared__ double lds[];
   double* sF = lds;
   double* sH = sF + C::MAT;
-  double* B_HP = sH + C::MAT;
-  double* B_Li = B_HP + C::MAT;
-  double* B_Si = B_Li + C::MAT;
-  double* Bt = B_Si + C::MAT;
-  double* vmp = Bt + C::MAT;
+  double* X = sH + C::MAT;
+  double* Y = X + C::MAT;
+  double* vmp = Y + C::MAT;
   double* vv = vmp + D;
   double* vw = vv + D;
   const int t = blockIdx.x, tid = threadIdx.x, d = G.dx, p = G.dy;
@@ -373,37 +375,35 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
   lds_load_user<D>(sH, G.H, p, d);
   team_sync();
   bool ok = true;
-  RM<D> Pp, R1, R2;
-  adj_step_quantities<D>(M, G, t, sF, sH, B_HP, B_Si, Bt, Pp, vmp, vv, vw, B_Li, ok);
+  RM<D> Pp, R1, R2, K;
+  adj_step_quantities<D>(M, G, t, sF, sH, X, Y, Y, Pp, vmp, vv, vw, Y, ok);  // X = H Pp, Y = S^{-1}
   // h = H' w
   matvec<D, true>(G.U + (int64_t)t * D, sH, vw);
-  // Cm = -1/2 H' (S^{-1} - w w') H
-  rm_unstage<D>(R1, B_Si);
+  // K = (H Pp)' S^{-1};  Sig = S^{-1} - w w'
+  gemm<D, true, false, false>(K, X, Y);
+  rm_unstage<D>(R1, Y);
   AKF_RM_FOR(D, q, r, i, j) R1.t[q][r] -= vw[i] * vw[j];
   team_sync();
-  rm_stage<D>(R1, Bt);
+  // Cm = -1/2 H' Sig H
+  rm_stage<D>(R1, X);
   team_sync();
-  gemm<D, false, false, false>(R2, Bt, sH);  // Sig H
+  gemm<D, false, false, false>(R2, X, sH);  // Sig H
+  rm_stage<D>(R2, Y);
   team_sync();
-  rm_stage<D>(R2, Bt);
-  team_sync();
-  gemm<D, true, false, false>(R1, sH, Bt);  // H' Sig H
-  rm_axpy<D>(R1, -1.5, R1);                 // -1/2 H' Sig H
+  gemm<D, true, false, false>(R1, sH, Y);  // H' Sig H
+  rm_axpy<D>(R1, -1.5, R1);                // -1/2 H' Sig H
   rm_store<D>(R1, G.Cm + (int64_t)t * D * D, D, D);
   if (t == M.N - 1) {
     rm_zero<D>(R1);
     rm_store<D>(R1, G.E + (int64_t)t * D * D, D, D);
   } else {
-    // K = (H Pp)' S^{-1};  Phi = F - (F K) H;  E = Phi'
-    gemm<D, true, false, false>(R1, B_HP, B_Si);  // K
+    // Phi = F - (F K) H;  E = Phi'
+    rm_stage<D>(K, X);
     team_sync();
-    rm_stage<D>(R1, Bt);
+    gemm<D, false, false, false>(R2, sF, X);  // F K
+    rm_stage<D>(R2, Y);
     team_sync();
-    gemm<D, false, false, false>(R2, sF, Bt);  // F K
-    team_sync();
-    rm_stage<D>(R2, Bt);
-    team_sync();
-    gemm<D, false, false, false>(R1, Bt, sH);  // F K H
+    gemm<D, false, false, false>(R1, Y, sH);  // F K H
     RM<D> Fm;
     rm_load<D>(Fm, M.F, d, d);
     rm_rsub<D>(R1, Fm);  // Phi = F - F K H
@@ -656,7 +656,7 @@ hipError_t launch_sum(const double* a, int n, double* out, hipStream_t st) {
 
 template <int D>
 hipError_t launch_adj_build_t(const KModel& M, LgArgs G, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_mats<D>(6, 7), st, M, G);
+  hipLaunchKernelGGL(k_adj_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_mats<D>(4, 3), st, M, G);
   return hipGetLastError();
 }
 template <int D>
