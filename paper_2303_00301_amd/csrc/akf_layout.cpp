@@ -27,11 +27,13 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 int pick_D(int d) { return d <= 16 ? 16 : (d <= 32 ? 32 : (d <= 64 ? 64 : 0)); }
 
 // Default scan block: enough blocks to give every CU (256) its resident teams
-// (LDS-limited: 1 team of 4 waves at D = 64, several single-wave teams below),
-// and at least 4 steps per block so that small problems do not pay for a deep
-// tree of tiny launches.
-int auto_block(int N, int D) {
-  const int teams_per_cu = D == 64 ? 1 : (D == 32 ? 4 : 8);
+// and no more, so that the fold runs in one round (LDS-limited: 1 team of 4
+// waves at D = 64; at D = 32 four single-wave teams, three with a general
+// observation matrix, whose fold holds a fifth matrix; eight at D = 16), and at
+// least 4 steps per block so that small problems do not pay for a deep tree of
+// tiny launches.
+int auto_block(int N, int D, bool general_obs) {
+  const int teams_per_cu = D == 64 ? 1 : (D == 32 ? (general_obs ? 3 : 4) : 8);
   const int target = 256 * teams_per_cu;
   int B = (N + target - 1) / target;
   if (B < 4) B = 4;
@@ -45,7 +47,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
   Lo.dy = dy;
   Lo.D = pick_D(d);
   const int D = Lo.D;
-  Lo.B = block > 0 ? (block > N ? N : block) : auto_block(N, D);
+  Lo.B = block > 0 ? (block > N ? N : block) : auto_block(N, D, kind == LAYOUT_LGSSM);
   Lo.nb = (N + Lo.B - 1) / Lo.B;
   Lo.n_lvl[0] = Lo.nb;
   Lo.L_hs = 0;

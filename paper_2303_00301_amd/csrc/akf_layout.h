@@ -61,7 +61,7 @@ T* at(void* ws, size_t off) {
 
 akf_status fail(akf_status s, const char* fmt, ...);
 int pick_D(int d);
-int auto_block(int N, int D);
+int auto_block(int N, int D, bool general_obs);
 void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn = false,
                  bool fixed = false);
 akf_status check_model(const akf_model* m, bool need_emission);
