@@ -75,8 +75,10 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("N,dx,dy,block", [(1, 3, 2, 0), (5, 2, 1, 2), (64, 4, 3, 0),
                                            (300, 6, 2, 7), (257, 16, 8, 0), (500, 20, 32, 0),
-                                           (1024, 32, 16, 0)])
+                                           (1024, 32, 16, 0), (5000, 24, 10, 4)])
 def test_lgssm_loglik_and_adjoint_match_oracle(S, N, dx, dy, block):
+    """The last case has a short scan block at width 32, where the gradient's
+    per-block sums take longer blocks than the scans (a ragged last one)."""
     pw = W.lgssm_params(N=N, dx=dx, dy=dy, seed=10 + N)
     t0 = pw.theta0
     ll_ref, dF, dq, dH, dr = oracle.fisher_score(pw.m0, pw.P0, t0.F, t0.logq, t0.H, t0.logr, pw.y)
