@@ -70,6 +70,17 @@ typedef enum {
                             dt = p1 */
 } akf_dyn;
 
+/* Arithmetic and storage type of the path's internals (the boundary arrays
+ * are float64 whatever the selection).  FP64 is the only one built: on gfx950
+ * plain FP32 vector arithmetic has the FP64 rate and FP32 matrix cores twice
+ * the FP64 rate, and the paper reports its parallel Kalman sampler diverging
+ * in FP32 (Sec. "Multivariate stochastic volatility model"), so every entry
+ * point computes in FP64 and rejects AKF_F32 with AKF_ERR_UNSUPPORTED. */
+typedef enum {
+  AKF_F64 = 0, /* default: a zero-initialised model selects it */
+  AKF_F32 = 1
+} akf_dtype;
+
 /* Per-step device status bits. */
 enum {
   AKF_ST_FWD_NOT_PD = 1, /* forward proposal undefined: 2/delta - Lambda_t not PD,
@@ -99,6 +110,10 @@ enum {
  * x* for the reverse one; Example "gslr-example") and adds the mismatch
  * between the true and the linearised transition densities to log r.
  * Nonlinear dynamics are accepted by akf_mh_step / akf_mh_run only.
+ *
+ * dtype (akf_dtype) selects the internal arithmetic; every entry point taking
+ * a model returns AKF_ERR_UNSUPPORTED for AKF_F32 (and AKF_ERR_INVALID for an
+ * unknown value), the workspace queries return 0.
  */
 typedef struct akf_model {
   int32_t N, dx, dy;
@@ -109,6 +124,7 @@ typedef struct akf_model {
   double nu, scale;
   int32_t dyn;
   double dyn_par[4];
+  int32_t dtype;
 } akf_model;
 
 /* Description of the last synchronous error on this thread (static storage). */
@@ -300,7 +316,8 @@ typedef struct akf_lgssm {
 /*
  * log p(y_{0:T} | theta) by the parallel filter (predictive form of eq.
  * marginal-likelihood): ll [1] device double, ell [N] per-step terms (may be
- * NULL).  The filtering moments stay in `ws` as the checkpoint of the
+ * NULL).  When a matrix that must be positive definite is not (status != 0),
+ * ll is NaN.  The filtering moments stay in `ws` as the checkpoint of the
  * adjoint; akf_lgssm_loglik_grad must be called with the same model, block
  * and workspace, after this call and before any other use of the workspace.
  */
@@ -312,7 +329,9 @@ akf_status akf_lgssm_loglik(const akf_lgssm* m, double* ll, double* ell, int32_t
  * Reverse-mode adjoint of akf_lgssm_loglik: ll_bar [1] (device, NULL = 1)
  * times d log p / d theta, written to dF [dx,dx], dlogq [dx], dH [dy,dx],
  * dlogr [dy].  Two suffix scans over time (mean and covariance adjoints) from
- * the checkpointed filtering moments, then per-step gradient terms.
+ * the checkpointed filtering moments, then per-step gradient terms.  When the
+ * forward pass or the adjoint met a matrix that is not positive definite
+ * (status != 0) every gradient entry is NaN.
  */
 akf_status akf_lgssm_loglik_grad(const akf_lgssm* m, const double* ll_bar, double* dF,
                                  double* dlogq, double* dH, double* dlogr, int32_t* status,

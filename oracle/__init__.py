@@ -33,12 +33,27 @@ ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
 
 def build(force: bool = False) -> str:
-    """Compile akf_oracle.c into liboracle.so with gcc (plain -O2, no fast-math)."""
+    """Compile akf_oracle.c into liboracle.so with gcc (plain -O2, no fast-math).
+    With AKF_ORACLE_LIB set, that prebuilt library is used instead (the
+    sanitizer test points it at build_sanitized()'s output)."""
+    alt = os.environ.get("AKF_ORACLE_LIB")
+    if alt:
+        return alt
     if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
+
+
+def build_sanitized(path: str) -> str:
+    """The oracle built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (any undefined-behaviour report aborts) at `path`, for host-side memory and
+    arithmetic checks of the C code."""
+    subprocess.check_call(["gcc", "-O1", "-g", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                           "-std=c99", "-fPIC", "-shared", _SRC, "-o", path, "-lm"])
+    return path
 
 
 _lib = None

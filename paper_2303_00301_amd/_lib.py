@@ -28,7 +28,12 @@ class AkfModel(C.Structure):
         ("site", C.c_void_p),
         ("nu", C.c_double), ("scale", C.c_double),
         ("dyn", C.c_int32), ("dyn_par", C.c_double * 4),
+        ("dtype", C.c_int32),
     ]
+
+
+# akf_dtype
+AKF_F64, AKF_F32 = 0, 1
 
 
 class AkfLgssm(C.Structure):

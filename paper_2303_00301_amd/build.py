@@ -17,16 +17,24 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every source (in parallel, `jobs` at a time; 0 = one per CPU up
+    to 16) and link libauxkf.so in place."""
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    jobs = jobs or max(1, min(16, os.cpu_count() or 1))
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
-        cmd = [hipcc, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.check_call(cmd)
+        cmds.append([hipcc, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        for rc, cmd in zip(ex.map(lambda c: subprocess.call(c), cmds), cmds):
+            if rc != 0:
+                raise subprocess.CalledProcessError(rc, cmd)
     tmp = LIB + ".tmp"
     cmd = [hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

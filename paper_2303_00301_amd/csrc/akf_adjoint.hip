@@ -296,15 +296,20 @@ __global__ void k_lgssm_prep(LgArgs G) {
   }
 }
 
-// sum of ell (fixed-order tree within one team)
-__global__ void __launch_bounds__(256) k_sum(const double* __restrict__ a, int n, double* out) {
+// sum of ell (fixed-order tree within one team); NaN when the filter that
+// wrote ell set a status bit (status may be null)
+__global__ void __launch_bounds__(256) k_sum(const double* __restrict__ a, int n, double* out,
+                                             const int* status) {
   __shared__ double red[4];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) s += a[i];
   for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+  if (threadIdx.x == 0) {
+    const double t = red[0] + red[1] + red[2] + red[3];
+    *out = (status && *status != 0) ? __builtin_nan("") : t;
+  }
 }
 
 // Recompute the filter quantities of step t from the checkpoint:
@@ -589,7 +594,8 @@ __global__ void __launch_bounds__(256) k_adj_reduce(LgArgs G, int nblk, const do
 #pragma unroll
     for (int r = 1; r < 8; ++r) t += acc[r][px];
     const double sc = ll_bar ? *ll_bar : 1.0;
-    *dst = sc * mul * t;
+    // a failed forward or adjoint pass (any status bit) leaves no gradient
+    *dst = (*G.status != 0) ? __builtin_nan("") : sc * mul * t;
   }
 }
 
@@ -649,8 +655,8 @@ hipError_t launch_lgssm_prep(LgArgs G, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_sum(const double* a, int n, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, a, n, out);
+hipError_t launch_sum(const double* a, int n, double* out, const int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, st, a, n, out, status);
   return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -67,8 +68,20 @@ struct Built {
   size_t ws_total = 0;
 };
 
+// Scratch outputs of an autotuning candidate's first step: paths in place of
+// the chains' x, and per-chain log ratio, decision and status.
+// steps per trial (the device step counter is reset before the checked step
+// and before the timed ones)
+constexpr int kTrialSteps = 2;
+struct TrialOut {
+  std::vector<double*> x;
+  double* lr = nullptr;
+  int* acc = nullptr;
+  int* st = nullptr;
+};
+
 void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, char* ws_base,
-                 const std::vector<double*>* x_override) {
+                 const TrialOut* trial) {
   cp.Lmax = 0;
   std::vector<Layout> lay(chains.size());
   for (int c : cp.chains) {
@@ -122,7 +135,7 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
     ChainDev& d = b.desc[c];
     memset(&d, 0, sizeof d);
     d.M = to_kmodel(&ch.model);
-    double* x = x_override ? (*x_override)[c] : ch.x;
+    double* x = trial ? trial->x[c] : ch.x;
     StepArgs& A = d.A;
     A.y = ch.y;
     A.x = x;
@@ -192,12 +205,17 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
     d.xi_base = ch.xi;
     d.xi_stride = 2 * (int64_t)ch.model.N * ch.model.dx;
     d.unif_base = ch.unif;
-    if (!x_override) {
+    if (!trial) {
       d.lr_base = ch.log_ratio;
       d.acc_base = ch.accepted;
       d.lzf_base = ch.logZ_fwd;
       d.lzr_base = ch.logZ_rev;
       d.st_base = ch.status;
+    } else {
+      // kTrialSteps slots per chain; only the first step of a trial is read back
+      d.lr_base = trial->lr + (size_t)kTrialSteps * c;
+      d.acc_base = trial->acc + (size_t)kTrialSteps * c;
+      d.st_base = trial->st + (size_t)kTrialSteps * c;
     }
     d.x = x;
   }
@@ -258,36 +276,125 @@ hipError_t enqueue_step(const std::vector<ClassPlan>& classes, const ChainDev* d
   return e;
 }
 
-// Time one eager step of class `cp` with block B on scratch state.  Returns ms or -1.
-double time_candidate(const std::vector<akf_chain>& chains, ClassPlan cp, hipStream_t st) {
+// Plain per-chain reference for the autotuner: one akf_mh_step of every chain
+// of the class from its current path with the run's first normals and uniform.
+struct PlainRef {
+  std::vector<std::vector<double>> x;  // by global chain id (class members only)
+  std::vector<double> lr;
+  std::vector<int> acc, st;
+};
+
+akf_status plain_reference(const std::vector<akf_chain>& chains, const ClassPlan& cp,
+                           hipStream_t st, PlainRef& ref) {
+  size_t ws_need = 0, x_need = 0;
+  for (int c : cp.chains) {
+    const akf_chain& ch = chains[c];
+    ws_need = std::max(ws_need, akf_mh_workspace_bytes(&ch.model, ch.order, 0));
+    x_need = std::max(x_need, (size_t)ch.model.N * ch.model.dx);
+  }
+  if (ws_need == 0) return fail(AKF_ERR_INVALID, "autotuning: a chain's workspace query failed");
+  const size_t xb = (x_need * 8 + 255) / 256 * 256;
+  char* mem = nullptr;
+  if (hipMalloc(&mem, xb + 256 + ws_need) != hipSuccess)
+    return fail(AKF_ERR_HIP, "autotuning: hipMalloc of the plain reference's workspace failed");
+  double* xo = reinterpret_cast<double*>(mem);
+  double* lr = reinterpret_cast<double*>(mem + xb);
+  int* ai = reinterpret_cast<int*>(mem + xb + 8);
+  int* si = reinterpret_cast<int*>(mem + xb + 16);
+  void* ws = mem + xb + 256;
+  ref.x.assign(chains.size(), {});
+  ref.lr.assign(chains.size(), 0.0);
+  ref.acc.assign(chains.size(), 0);
+  ref.st.assign(chains.size(), 0);
+  akf_status s = AKF_OK;
+  for (int c : cp.chains) {
+    const akf_chain& ch = chains[c];
+    s = akf_mh_step(&ch.model, ch.y, ch.x, ch.delta, ch.order, ch.xi, ch.unif, xo, lr, ai,
+                    nullptr, nullptr, si, ws, ws_need, 0, st);
+    if (s != AKF_OK) break;
+    ref.x[c].resize((size_t)ch.model.N * ch.model.dx);
+    hipError_t e = hipMemcpyAsync(ref.x[c].data(), xo, ref.x[c].size() * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ref.lr[c], lr, 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ref.acc[c], ai, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&ref.st[c], si, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      s = fail(AKF_ERR_HIP, "autotuning: plain reference step: %s", hipGetErrorString(e));
+      break;
+    }
+  }
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(mem);
+  return s;
+}
+
+// The candidate's first step agrees with the plain step of every chain: the
+// same status; with the same decision, the same log ratio and path up to the
+// rounding of a different association of the scans; a different decision
+// only at a tie of the log ratio with log U.
+bool candidate_agrees(const std::vector<akf_chain>& chains, const ClassPlan& cp,
+                      const PlainRef& ref, const std::vector<std::vector<double>>& x,
+                      const std::vector<double>& lr, const std::vector<int>& acc,
+                      const std::vector<int>& stv) {
+  for (int c : cp.chains) {
+    const akf_chain& ch = chains[c];
+    const double nd = (double)ch.model.N * ch.model.dx;
+    const double tol_lr = 1e-9 * nd + 1e-9 * std::max(1.0, std::fabs(ref.lr[c]));
+    if (stv[c] != ref.st[c]) return false;
+    if (ref.st[c] != 0) continue;  // both rejected by a status bit: x unchanged
+    if (!(std::fabs(lr[c] - ref.lr[c]) <= tol_lr)) return false;
+    if (acc[c] != ref.acc[c]) continue;  // a tie: the log ratios agree
+    double num = 0.0, den = 0.0;
+    for (size_t i = 0; i < x[c].size(); ++i) {
+      const double e = x[c][i] - ref.x[c][i];
+      num += e * e;
+      den += ref.x[c][i] * ref.x[c][i];
+    }
+    if (!(std::sqrt(num) <= 1e-7 * std::max(1.0, std::sqrt(den)))) return false;
+  }
+  return true;
+}
+
+// Time one eager step of class `cp` with block B on scratch state (after an
+// untimed first step whose outputs are checked against `ref`).  Returns ms,
+// -1 on a failure, -2 when the first step disagrees with the plain path.
+double time_candidate(const std::vector<akf_chain>& chains, ClassPlan cp, const PlainRef& ref,
+                      hipStream_t st) {
   Built b;
   b.desc.resize(chains.size());
   b.ws_off.assign(chains.size(), 0);
   build_class(cp, chains, b, nullptr, nullptr);
-  // scratch x copies
+  // scratch x copies and per-chain outputs
   size_t xbytes = 0;
   for (int c : cp.chains) xbytes += ((size_t)chains[c].model.N * chains[c].model.dx * 8 + 255) / 256 * 256;
-  const size_t desc_bytes = (chains.size() * sizeof(ChainDev) + 255) / 256 * 256;
+  const size_t nc = chains.size();
+  const size_t out_bytes = (nc * 16 * kTrialSteps + 255) / 256 * 256;
+  const size_t desc_bytes = (nc * sizeof(ChainDev) + 255) / 256 * 256;
   const size_t item_bytes = (b.items.size() * sizeof(Item) + 255) / 256 * 256;
-  const size_t total = desc_bytes + item_bytes + 256 + xbytes + b.ws_total;
+  const size_t head = desc_bytes + item_bytes + 256 + out_bytes;
+  const size_t total = head + xbytes + b.ws_total;
   char* mem = nullptr;
   if (hipMalloc(&mem, total) != hipSuccess) return -1.0;
-  char* ws = mem + desc_bytes + item_bytes + 256 + xbytes;
-  std::vector<double*> xs(chains.size(), nullptr);
+  char* ws = mem + head + xbytes;
+  TrialOut tr;
+  tr.x.assign(nc, nullptr);
+  tr.lr = reinterpret_cast<double*>(mem + desc_bytes + item_bytes + 256);
+  tr.acc = reinterpret_cast<int*>(tr.lr + kTrialSteps * nc);
+  tr.st = tr.acc + kTrialSteps * nc;
   size_t xo = 0;
   for (int c : cp.chains) {
-    xs[c] = reinterpret_cast<double*>(mem + desc_bytes + item_bytes + 256 + xo);
+    tr.x[c] = reinterpret_cast<double*>(mem + head + xo);
     const size_t nb = (size_t)chains[c].model.N * chains[c].model.dx * 8;
-    (void)hipMemcpyAsync(xs[c], chains[c].x, nb, hipMemcpyDeviceToDevice, st);
+    (void)hipMemcpyAsync(tr.x[c], chains[c].x, nb, hipMemcpyDeviceToDevice, st);
     xo += (nb + 255) / 256 * 256;
   }
   b.items.clear();
   b.ws_total = 0;
-  build_class(cp, chains, b, ws, &xs);
+  build_class(cp, chains, b, ws, &tr);
   ChainDev* d_desc = reinterpret_cast<ChainDev*>(mem);
   Item* d_items = reinterpret_cast<Item*>(mem + desc_bytes);
   int* d_step = reinterpret_cast<int*>(mem + desc_bytes + item_bytes);
-  (void)hipMemcpyAsync(d_desc, b.desc.data(), chains.size() * sizeof(ChainDev), hipMemcpyHostToDevice, st);
+  (void)hipMemcpyAsync(d_desc, b.desc.data(), nc * sizeof(ChainDev), hipMemcpyHostToDevice, st);
   (void)hipMemcpyAsync(d_items, b.items.data(), b.items.size() * sizeof(Item), hipMemcpyHostToDevice, st);
   std::vector<ClassPlan> one{cp};
   hipEvent_t e0, e1;
@@ -295,17 +402,43 @@ double time_candidate(const std::vector<akf_chain>& chains, ClassPlan cp, hipStr
   (void)hipEventCreate(&e1);
   double ms = -1.0;
   hipError_t err = launch_step_advance(d_step, 1, st);
-  if (err == hipSuccess) err = enqueue_step(one, d_desc, d_items, d_step, st);  // warm-up
-  if (err == hipSuccess) err = launch_step_advance(d_step, 1, st);
-  (void)hipEventRecord(e0, st);
-  for (int r = 0; r < 2 && err == hipSuccess; ++r) {
-    err = enqueue_step(one, d_desc, d_items, d_step, st);
-    if (err == hipSuccess) err = launch_step_advance(d_step, 1, st);
+  if (err == hipSuccess) err = enqueue_step(one, d_desc, d_items, d_step, st);  // checked step
+  // read the checked step back before the timed steps overwrite x
+  std::vector<std::vector<double>> xh(nc);
+  std::vector<double> lr(kTrialSteps * nc, 0.0), lr0(nc, 0.0);
+  std::vector<int> acc(kTrialSteps * nc, 0), stv(kTrialSteps * nc, 0), acc0(nc, 0), st0(nc, 0);
+  for (int c : cp.chains) {
+    if (err != hipSuccess) break;
+    xh[c].resize((size_t)chains[c].model.N * chains[c].model.dx);
+    err = hipMemcpyAsync(xh[c].data(), tr.x[c], xh[c].size() * 8, hipMemcpyDeviceToHost, st);
   }
-  (void)hipEventRecord(e1, st);
-  if (err == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
-    float f = 0.f;
-    if (hipEventElapsedTime(&f, e0, e1) == hipSuccess) ms = f / 2.0;
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(lr.data(), tr.lr, lr.size() * 8, hipMemcpyDeviceToHost, st);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(acc.data(), tr.acc, acc.size() * 4, hipMemcpyDeviceToHost, st);
+  if (err == hipSuccess)
+    err = hipMemcpyAsync(stv.data(), tr.st, stv.size() * 4, hipMemcpyDeviceToHost, st);
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  for (int c : cp.chains) {
+    lr0[c] = lr[(size_t)kTrialSteps * c];
+    acc0[c] = acc[(size_t)kTrialSteps * c];
+    st0[c] = stv[(size_t)kTrialSteps * c];
+  }
+  const bool agrees = err == hipSuccess && candidate_agrees(chains, cp, ref, xh, lr0, acc0, st0);
+  if (err == hipSuccess && agrees) {
+    err = launch_step_advance(d_step, 1, st);
+    (void)hipEventRecord(e0, st);
+    for (int r = 0; r < 2 && err == hipSuccess; ++r) {
+      err = enqueue_step(one, d_desc, d_items, d_step, st);
+      if (err == hipSuccess) err = launch_step_advance(d_step, 1, st);
+    }
+    (void)hipEventRecord(e1, st);
+    if (err == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+      float f = 0.f;
+      if (hipEventElapsedTime(&f, e0, e1) == hipSuccess) ms = f / 2.0;
+    }
+  } else if (err == hipSuccess) {
+    ms = -2.0;
   }
   (void)hipStreamSynchronize(st);
   (void)hipEventDestroy(e0);
@@ -314,30 +447,62 @@ double time_candidate(const std::vector<akf_chain>& chains, ClassPlan cp, hipStr
   return ms;
 }
 
+// Cache key of a class: its team size and the shape of its batch (chain
+// count, lengths, the histograms of d_x, order and emission family).  Stored
+// as the leading fields of a cache line, before "block".
 std::string cache_key(const ClassPlan& cp, const std::vector<akf_chain>& chains) {
   long long sumN = 0;
   int maxN = 0;
+  int ndx[65] = {0}, nord[3] = {0}, nemit[8] = {0};
   for (int c : cp.chains) {
-    sumN += chains[c].model.N;
-    maxN = std::max(maxN, (int)chains[c].model.N);
+    const akf_model& m = chains[c].model;
+    sumN += m.N;
+    maxN = std::max(maxN, (int)m.N);
+    ndx[m.dx] += 1;
+    nord[chains[c].order] += 1;
+    nemit[m.emit & 7] += 1;
   }
-  char buf[160];
-  snprintf(buf, sizeof buf, "\"D\": %d, \"chains\": %zu, \"sum_N\": %lld, \"max_N\": %d", cp.D,
-           cp.chains.size(), sumN, maxN);
-  return buf;
+  std::string k;
+  char buf[96];
+  snprintf(buf, sizeof buf, "\"D\": %d, \"chains\": %zu, \"sum_N\": %lld, \"max_N\": %d, \"dx\": \"",
+           cp.D, cp.chains.size(), sumN, maxN);
+  k += buf;
+  bool first = true;
+  for (int d = 1; d <= 64; ++d)
+    if (ndx[d]) {
+      snprintf(buf, sizeof buf, "%s%d:%d", first ? "" : " ", d, ndx[d]);
+      k += buf;
+      first = false;
+    }
+  snprintf(buf, sizeof buf, "\", \"order\": \"1:%d 2:%d\", \"emit\": \"", nord[1], nord[2]);
+  k += buf;
+  first = true;
+  for (int e = 0; e < 8; ++e)
+    if (nemit[e]) {
+      snprintf(buf, sizeof buf, "%s%d:%d", first ? "" : " ", e, nemit[e]);
+      k += buf;
+      first = false;
+    }
+  k += "\"";
+  return k;
 }
 
+// Block of the last verified line whose key fields equal `key` exactly, or 0.
 int cache_lookup(const char* path, const std::string& key) {
   if (!path) return 0;
   FILE* f = fopen(path, "r");
   if (!f) return 0;
-  char line[512];
+  std::string line;
   int B = 0;
-  while (fgets(line, sizeof line, f)) {
-    if (strstr(line, key.c_str())) {
-      const char* p = strstr(line, "\"block\": ");
-      if (p) B = atoi(p + 9);
-    }
+  char buf[1024];
+  while (fgets(buf, sizeof buf, f)) {
+    line = buf;
+    const size_t kb = line.find(", \"block\": ");
+    if (line.size() < 2 || line[0] != '{' || kb == std::string::npos) continue;
+    if (line.compare(1, kb - 1, key) != 0 || kb - 1 != key.size()) continue;
+    if (line.find("\"verified\": true") == std::string::npos) continue;
+    const int b = atoi(line.c_str() + kb + 11);
+    if (b > 0) B = b;
   }
   fclose(f);
   return B;
@@ -347,7 +512,8 @@ void cache_store(const char* path, const std::string& key, int B, double ms) {
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "{%s, \"block\": %d, \"ms_per_step\": %.4f}\n", key.c_str(), B, ms);
+  fprintf(f, "{%s, \"block\": %d, \"ms_per_step\": %.4f, \"verified\": true}\n", key.c_str(), B,
+          ms);
   fclose(f);
 }
 
@@ -391,15 +557,23 @@ akf_status akf_batch_plan_create(akf_batch_plan** out, int32_t n_chains, const a
       const std::string key = cache_key(cp, P->chains);
       B = cache_lookup(tune_cache, key);
       if (B == 0) {
-        // autotune the scan block on this batch (one eager step per candidate)
+        // autotune the scan block on this batch: each candidate's first step is
+        // checked against plain per-chain steps, then two eager steps are timed
+        PlainRef ref;
+        akf_status rs = plain_reference(P->chains, cp, st, ref);
+        if (rs != AKF_OK) {
+          delete P;
+          return rs;
+        }
         double best = 1e300;
-        int maxN = 0;
+        int maxN = 0, n_disagree = 0;
         for (int c : cp.chains) maxN = std::max(maxN, (int)chains[c].model.N);
         for (int cand : {4, 8, 16, 32, 64, 128}) {
           if (cand > maxN && cand != 4) break;
           ClassPlan trial = cp;
           trial.B = cand;
-          const double ms = time_candidate(P->chains, trial, st);
+          const double ms = time_candidate(P->chains, trial, ref, st);
+          if (ms == -2.0) ++n_disagree;
           if (ms > 0 && ms < best) {
             best = ms;
             B = cand;
@@ -407,7 +581,8 @@ akf_status akf_batch_plan_create(akf_batch_plan** out, int32_t n_chains, const a
         }
         if (B == 0) {
           delete P;
-          return fail(AKF_ERR_HIP, "autotuning failed for D = %d", D);
+          return fail(AKF_ERR_HIP, "autotuning failed for D = %d (%d candidates disagreed with "
+                      "the plain per-chain step)", D, n_disagree);
         }
         cache_store(tune_cache, key, B, best);
       }

@@ -563,7 +563,7 @@ akf_status akf_lgssm_loglik(const akf_lgssm* m, double* ll, double* ell, int32_t
                       at<double>(ws, Lo.Pf), Lo.D, ellw, dstat, ST_FWD_NOT_PD, st, m->y, m->H,
                       G.R, m->dy)) != AKF_OK)
     return s;
-  if ((s = hip_check(launch_sum(ellw, m->N, ll, st), "sum launch")) != AKF_OK) return s;
+  if ((s = hip_check(launch_sum(ellw, m->N, ll, dstat, st), "sum launch")) != AKF_OK) return s;
   if (status)
     return hip_check(hipMemcpyAsync(status, dstat, sizeof(int), hipMemcpyDeviceToDevice, st),
                      "status copy");

@@ -328,7 +328,7 @@ hipError_t launch_egl_scan_any(int D, EglArgs A, EglTree* up, EglTree* down, int
                                hipStream_t st);
 hipError_t launch_smooth_build_any(int D, const KModel& M, SmoothArgs S, hipStream_t st);
 hipError_t launch_lgssm_prep(LgArgs G, hipStream_t st);
-hipError_t launch_sum(const double* a, int n, double* out, hipStream_t st);
+hipError_t launch_sum(const double* a, int n, double* out, const int* status, hipStream_t st);
 hipError_t launch_adj_build_any(int D, const KModel& M, LgArgs G, hipStream_t st);
 hipError_t launch_adj_G_any(int D, LgArgs G, int N, hipStream_t st);
 hipError_t launch_adj_finish_any(int D, const KModel& M, LgArgs G, int nblk, const double* ll_bar,

@@ -237,3 +237,42 @@ def test_reuse_run_validation():
     nl.dyn_par[3] = 2e-4
     assert lib.akf_mh_reuse_workspace_bytes(C.byref(nl), 2, 0) == 0
     assert call(nl) == 5
+
+
+def test_dtype_selector():
+    """The model's dtype field: AKF_F64 (0, the zero-initialised default) is the
+    built path; AKF_F32 is a valid request the library does not implement
+    (AKF_ERR_UNSUPPORTED from the calls, 0 from the workspace queries); any
+    other value is invalid."""
+    lib = _lib.load()
+    p = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x10000)
+    m = _fake_model()
+    assert m.dtype == _lib.AKF_F64
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) > 0
+    step = lambda model: lib.akf_mh_step(C.byref(model), p, p, 0.5, 2, p, p, p, None, None, None,
+                                         None, None, ws, 1 << 30, 0, None)
+    m.dtype = _lib.AKF_F32
+    assert step(m) == 5
+    assert b"AKF_F32" in lib.akf_last_error()
+    for q in (lib.akf_mh_workspace_bytes(C.byref(m), 2, 0),
+              lib.akf_filter_workspace_bytes(C.byref(m), 0),
+              lib.akf_sampler_workspace_bytes(C.byref(m), 0),
+              lib.akf_mh_first_order_workspace_bytes(C.byref(m), 0),
+              lib.akf_mh_reuse_workspace_bytes(C.byref(m), 2, 0),
+              lib.akf_dnc_workspace_bytes(C.byref(m)),
+              lib.akf_smoother_workspace_bytes(C.byref(m), 0)):
+        assert q == 0
+    assert lib.akf_mh_run(C.byref(m), p, p, 0.5, 2, 1, p, p, None, None, None, None, None, ws,
+                          1 << 30, 0, None) == 5
+    m.dtype = 7
+    assert step(m) == 1
+    # batched chains validate each chain's model the same way
+    ch = (_lib.AkfChain * 1)()
+    ch[0].model = _fake_model()
+    ch[0].model.dtype = _lib.AKF_F32
+    ch[0].y = ch[0].x = ch[0].xi = ch[0].unif = 0x2000
+    ch[0].delta, ch[0].order = 0.5, 2
+    h = C.c_void_p()
+    assert lib.akf_batch_plan_create(C.byref(h), 1, ch, 1, 8, None, None) == 5
+    assert not h.value
