@@ -23,6 +23,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 METRIC = "aux-Kalman MCMC steps/s at d_x=64,T=4096; batched+adjoint vs plain, same GPU"
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (vector and matrix)
 PEAK_HBM_GBS = 8000.0
@@ -136,6 +138,41 @@ def auto_block(N: int, d: int) -> int:
     return min(B, N)
 
 
+def host_info() -> dict:
+    """The host the oracle runs on: CPU model and the number of logical CPUs."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count()}
+
+
+def oracle_threads() -> int:
+    """Host threads for the oracle's multi-chain baselines: every core of the
+    GPU's share of the host (at most 16)."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def adj_build_flops_per_step(d: int, p: int) -> float:
+    """Algorithmic flops of one step of the adjoint element build (2 per
+    multiply-add): the predicted moments F P^f F' + Q (4 d^3), H P^p and
+    S = H P^p H' + R (2 p d^2 + 2 p^2 d), S^{-1} (p^3), K = (H P^p)' S^{-1},
+    Sig H, H' Sig H, F K and (F K) H."""
+    return 4.0 * d ** 3 + 8.0 * p * d * d + 6.0 * p * p * d + p ** 3
+
+
+def adj_grad_flops_per_step(d: int, p: int) -> float:
+    """Algorithmic flops of one step of the adjoint's gradient contractions:
+    the same recomputed filter quantities as the element build, K, Pbar F,
+    (Pbar F) P^f, F' Pbar F, S^{-1} H P^p, K' Fbar and (K' Fbar) P^f."""
+    return 10.0 * d ** 3 + 6.0 * p * d * d + 6.0 * p * p * d + p ** 3
+
+
 def cpu_baseline(w, n_steps: int, order=None, delta=None) -> dict:
     """The FP64 oracle (sequential C, one thread) on a bounded sample: n_steps
     full MH steps of the same workload, from the same state and normals."""
@@ -155,15 +192,20 @@ def cpu_baseline(w, n_steps: int, order=None, delta=None) -> dict:
     return {"value": n_steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
             "sample": f"{n_steps} full MH steps of order {order} on the same workload "
                       f"(d_x={w.dx}, T={w.N}) by the sequential FP64 C oracle on one host "
-                      f"thread, {dt:.1f} s",
-            "seconds": dt}
+                      f"thread (one chain is a sequential computation), {dt:.1f} s",
+            "seconds": dt, **host_info()}
 
 
-def bench_batched(torch, S, W, K: int, dev, cpu: bool = False) -> dict:
+def bench_batched(torch, S, W, _lib, K: int, dev, cpu: bool = False) -> dict:
     """512 ragged chains (N ~ U{128..8192}, d ~ U{4,16,32}, Poisson log link):
     K steps as one batched plan (hipGraph replay) vs 512 sequential plain runs
-    of the same K steps, same normals, same scan blocks."""
-    import os
+    of the same K steps from the same start, same normals, same scan blocks;
+    their results are compared chain by chain.  Rooflines of the batched
+    filter fold and sampler element build per team width, from an eager run
+    with event timing."""
+    import ctypes as C
+    import tempfile
+    lib = _lib.load()
     t0 = time.perf_counter()
     ws = W.ragged_poisson_batch()
     gen = torch.Generator(device=dev)
@@ -178,17 +220,45 @@ def bench_batched(torch, S, W, K: int, dev, cpu: bool = False) -> dict:
                                           generator=gen),
                            unif=torch.rand((K,), dtype=torch.float64, device=dev,
                                            generator=gen).clamp_(min=1e-300),
-                           accepted=torch.empty(K, dtype=torch.int32, device=dev)))
+                           accepted=torch.empty(K, dtype=torch.int32, device=dev),
+                           log_ratio=torch.empty(K, dtype=torch.float64, device=dev),
+                           status=torch.empty(K, dtype=torch.int32, device=dev)))
     t_setup = time.perf_counter() - t0
-    import tempfile
     cache = os.path.join(tempfile.gettempdir(), "auxkf_batch_tune.jsonl")
-    os.makedirs(os.path.dirname(cache), exist_ok=True)
     t0 = time.perf_counter()
     plan = S.BatchPlan(chains, K, block=0, tune_cache=cache, device=dev)
     torch.cuda.synchronize()
     t_plan = time.perf_counter() - t0
     info = plan.info()
+    blk = {c["D"]: c["block"] for c in info["classes"]}
     plan.run(use_graph=True)  # warm-up: captures the graph
+    torch.cuda.synchronize()
+    # per-class rooflines from an eager run (events around each launch), then
+    # the timed graph replays from the start state
+    roof = {}
+    fams = [(f"kb_fold<{D}>", f"batch_fold{D}", D, "fold") for D in sorted(blk)]
+    fams += [(f"kb_sbuild<{D}>", f"batch_sbuild{D}", D, "sbuild") for D in sorted(blk)]
+    for kname, fam, D, kind in fams:
+        for c in chains:
+            c["x"].copy_(c["x0"])
+        torch.cuda.synchronize()
+        _lib.check(lib.akf_timing_enable(_lib.FAMILIES[fam], 4 * K + 8), "akf_timing_enable")
+        plan.run(use_graph=False)
+        n_l, k_ms = C.c_int32(), C.c_double()
+        _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
+        lib.akf_timing_enable(-1, 0)
+        if not n_l.value:
+            continue
+        mine = [w for w in ws if (16 if w.dx <= 16 else 32 if w.dx <= 32 else 64) == D]
+        if kind == "fold":
+            work = sum(fold_flops_per_launch(w.N, w.dx, blk[D]) for w in mine)
+        else:
+            work = sum(8.0 * w.dx ** 3 * w.N for w in mine)
+        roof[kname] = roofline_obj("mfma", kname, work, k_ms.value / n_l.value,
+                                   PEAK_FP64_TFLOPS, "TFLOP/s", 1e12)
+        roof[kname]["launches"] = n_l.value
+    for c in chains:
+        c["x"].copy_(c["x0"])
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(plan.stream)
@@ -197,22 +267,37 @@ def bench_batched(torch, S, W, K: int, dev, cpu: bool = False) -> dict:
     torch.cuda.synchronize()
     ms_batched = e0.elapsed_time(e1)
     acc = float(torch.stack([c["accepted"].float().mean() for c in chains]).mean().item())
-    # plain per-chain launches, same inputs and blocks
-    blk = {c["D"]: c["block"] for c in info["classes"]}
+    # plain per-chain launches, same inputs, start and blocks
     wsp = S.Workspace(dev)
+    blk_of = lambda c: blk[16 if c["model"].dx <= 16 else 32]
     xs = [c["x0"].clone() for c in chains]
     for c, x in zip(chains, xs):  # warm-up (workspace growth, code load)
         S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"][:1], c["unif"][:1],
-                 block=blk[16 if c["model"].dx <= 16 else 32], ws=wsp, outputs=False)
+                 block=blk_of(c), ws=wsp, outputs=False)
     xs = [c["x0"].clone() for c in chains]
+    outs = []
     torch.cuda.synchronize()
     e0.record()
     for c, x in zip(chains, xs):
-        S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"],
-                 block=blk[16 if c["model"].dx <= 16 else 32], ws=wsp, outputs=False)
+        outs.append(S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"],
+                             block=blk_of(c), ws=wsp))
     e1.record()
     torch.cuda.synchronize()
     ms_plain = e0.elapsed_time(e1)
+    # chain-by-chain agreement of the two runs
+    max_dx, max_dlr, n_dec, n_status = 0.0, 0.0, 0, 0
+    for w, c, x, o in zip(ws, chains, xs, outs):
+        n_status += int((c["status"] != o["status"]).sum().item())
+        same = bool(torch.equal(c["accepted"], o["accepted"]))
+        n_dec += 0 if same else 1
+        ok = (o["status"] == 0)
+        if bool(ok.any()):
+            d_lr = (c["log_ratio"] - o["log_ratio"]).abs()[ok]
+            max_dlr = max(max_dlr, float(d_lr.max().item()))
+        if same:
+            err = float(torch.linalg.norm(c["x"] - x).item()) / max(
+                1.0, float(torch.linalg.norm(x).item()))
+            max_dx = max(max_dx, err)
     n_ch = len(chains)
     plan.close()
     out = {"workload": "512 chains, N ~ U{128..8192}, d_x ~ U{4,16,32}, random stable F, "
@@ -224,30 +309,53 @@ def bench_batched(torch, S, W, K: int, dev, cpu: bool = False) -> dict:
            "speedup_vs_plain": ms_plain / ms_batched,
            "batched_time_steps_per_s": sum(w.N for w in ws) * K / (ms_batched * 1e-3),
            "acceptance": acc, "classes": info["classes"], "plan_s": t_plan,
-           "setup_s": t_setup}
+           "setup_s": t_setup,
+           "equality_vs_plain": {
+               "same_start_and_normals": True,
+               "max_rel_path_diff": max_dx,
+               "max_abs_log_ratio_diff": max_dlr,
+               "chains_with_a_different_decision": n_dec,
+               "status_mismatches": n_status},
+           "roofline": roof}
     if cpu:
-        # the oracle steps a sample of the chains once each; its rate in time
-        # steps per second is comparable with batched_time_steps_per_s
-        import numpy as np
-        import oracle
-        sample = ws[:8]
-        t0 = time.perf_counter()
-        for w in sample:
-            xi = w.normals(1)[0]
-            oracle.mh_step(oracle.Model(**w.oracle_kwargs()), w.y, np.log(w.y + 0.5), w.delta, 2,
-                           xi[0], xi[1], float(w.uniforms(1)[0]))
-        dt = time.perf_counter() - t0
-        n_ts = sum(w.N for w in sample)
-        out["cpu_baseline"] = {"value": n_ts / dt, "unit": "time steps/s", "cores": 1,
-                               "kind": "oracle",
-                               "sample": f"one MH step of each of the first {len(sample)} chains "
-                                         f"({n_ts} time steps) by the sequential FP64 C oracle "
-                                         f"on one host thread, {dt:.1f} s"}
+        out["cpu_baseline"] = batched_cpu_baseline(ws)
     return out
 
 
-def bench_adjoint(torch, S, W, reps: int, dev, cpu: bool = False) -> dict:
-    """log p(y | theta) and its reverse-mode adjoint, d_x = 32, d_y = 16, T = 16384."""
+def batched_cpu_baseline(ws, n_chains: int = 64) -> dict:
+    """The oracle steps the first n_chains chains once each, one chain per host
+    thread (the C oracle releases the interpreter lock), on every core of the
+    GPU's share of the host; its rate in time steps per second is comparable
+    with batched_time_steps_per_s."""
+    import numpy as np
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    sample = ws[:n_chains]
+    oracle.lib()
+
+    def one(w):
+        xi = w.normals(1)[0]
+        oracle.mh_step(oracle.Model(**w.oracle_kwargs()), w.y, np.log(w.y + 0.5), w.delta, 2,
+                       xi[0], xi[1], float(w.uniforms(1)[0]))
+
+    nt = oracle_threads()
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(max_workers=nt) as ex:
+        list(ex.map(one, sample))
+    dt = time.perf_counter() - t0
+    n_ts = sum(w.N for w in sample)
+    return {"value": n_ts / dt, "unit": "time steps/s", "cores": nt, "kind": "oracle",
+            "sample": f"one MH step of each of the first {len(sample)} chains ({n_ts} time "
+                      f"steps) by the sequential FP64 C oracle, one chain per thread on "
+                      f"{nt} host threads, {dt:.1f} s",
+            **host_info()}
+
+
+def bench_adjoint(torch, S, W, _lib, reps: int, dev, cpu: bool = False) -> dict:
+    """log p(y | theta) and its reverse-mode adjoint, d_x = 32, d_y = 16, T = 16384;
+    rooflines of the adjoint's two matrix kernels (per-step gradient
+    contractions, element build)."""
+    lib = _lib.load()
     pw = W.lgssm_params()
     model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev)
     th = [torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
@@ -270,11 +378,28 @@ def bench_adjoint(torch, S, W, reps: int, dev, cpu: bool = False) -> dict:
     tf.sort()
     tb.sort()
     mf, mb = tf[len(tf) // 2], tb[len(tb) // 2]
+    N, d, p = pw.N, pw.m0.shape[0], pw.y.shape[1]
+    roof = {}
+    for fam, kname, per_step in (("adj_grad", "k_adj_grad<32>", adj_grad_flops_per_step(d, p)),
+                                 ("adj_build", "k_adj_build<32>",
+                                  adj_build_flops_per_step(d, p))):
+        def run():
+            for _ in range(reps):
+                S.lgssm_loglik(model, *th, ws=ws)
+                S.lgssm_loglik_grad(model, *th, ws)
+            torch.cuda.synchronize()
+
+        avg, n_l = timed_launches(lib, _lib, fam, 2 * reps + 4, run)
+        roof[kname] = roofline_obj("mfma", kname, per_step * N, avg, PEAK_FP64_TFLOPS,
+                                   "TFLOP/s", 1e12)
+        if roof[kname] is not None:
+            roof[kname]["launches"] = n_l
     out = {"workload": "LGSSM d_x=32, d_y=16, T=16384, theta = (F, log diag Q, H, log diag R), "
                        "1584 parameters",
            "forward_ms": mf, "adjoint_ms": mb,
            "adjoint_time_steps_per_s": pw.N / ((mf + mb) * 1e-3),
-           "adjoint_over_forward": mb / mf}
+           "adjoint_over_forward": mb / mf,
+           "roofline": roof}
     if cpu:
         # the oracle's log-likelihood and its gradient (the Fisher score, from the
         # smoother) on the same series
@@ -288,7 +413,8 @@ def bench_adjoint(torch, S, W, reps: int, dev, cpu: bool = False) -> dict:
                                "kind": "oracle",
                                "sample": f"log-likelihood and gradient over the same {pw.N} "
                                          f"steps by the sequential FP64 C oracle on one host "
-                                         f"thread, {dt:.1f} s"}
+                                         f"thread (a sequential computation), {dt:.1f} s",
+                               **host_info()}
     return out
 
 
@@ -333,6 +459,74 @@ def bench_stoch_vol(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
             res["cpu_baseline"] = cpu_baseline(w, cpu_steps, order=order)
         out[f"order{order}"] = res
     return out
+
+
+def bench_poisson(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
+    """Poisson AR(1) workload (d_x = 8, T = 1024, delta 0.2, order 2, one chain):
+    at this size one step moves well under a megabyte and runs a few dozen
+    dependent launches, so it is bound by launch and scan-level latency.
+    Reported: ms per step, and per kernel family the launches per step and
+    microseconds per step (each family timed with events in a run of its
+    own; the families cover every launch of the step)."""
+    lib = _lib.load()
+    w = W.poisson_ar1()
+    M = S.DeviceModel.from_workload(w, device=dev)
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+    x = torch.log(y + 0.5).contiguous()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(62)
+    xi = torch.randn((K + 2, 2, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
+    un = torch.rand((K + 2,), dtype=torch.float64, device=dev, generator=gen).clamp_(min=1e-300)
+    ws = S.Workspace(dev)
+    S.mh_run(M, y, x, w.delta, 2, xi[:2], un[:2], ws=ws)
+    torch.cuda.synchronize()
+    x0 = x.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r = S.mh_run(M, y, x, w.delta, 2, xi[2:], un[2:], ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / K
+    phases = {}
+    for fam in ("lin", "filter_fold", "filter_up", "filter_final", "samp_build", "samp_fold",
+                "samp_up", "samp_down", "samp_final", "mh"):
+        x.copy_(x0)
+        box = {}
+
+        def run():
+            S.mh_run(M, y, x, w.delta, 2, xi[2:], un[2:], ws=ws)
+            torch.cuda.synchronize()
+
+        avg, n_l = timed_launches(lib, _lib, fam, 64 * K + 8, run)
+        if n_l:
+            phases[fam] = {"launches_per_step": n_l / K, "us_per_step": 1000.0 * avg * n_l / K}
+    out = {"workload": f"poisson_ar1_d{w.dx}_T{w.N}: F = 0.95 I, Q = 0.2 I, Poisson log link "
+                       f"at every coordinate, delta {w.delta}, order 2, one chain",
+           "ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+           "time_steps_per_s": w.N * 1000.0 / ms,
+           "acceptance": r["accepted"].float().mean().item(),
+           "launches_per_step": sum(p["launches_per_step"] for p in phases.values()),
+           "phases": phases}
+    if cpu_steps > 0:
+        out["cpu_baseline"] = cpu_baseline_from(w, np.log(w.y + 0.5), cpu_steps, 2, w.delta)
+    return out
+
+
+def cpu_baseline_from(w, x0, n_steps: int, order: int, delta: float) -> dict:
+    """The oracle's MH steps of one chain from x0 on one host thread."""
+    import oracle
+    M = oracle.Model(**w.oracle_kwargs())
+    xi = w.normals(n_steps)
+    un = w.uniforms(n_steps)
+    x = x0.copy()
+    t0 = time.perf_counter()
+    for k in range(n_steps):
+        x = oracle.mh_step(M, w.y, x, delta, order, xi[k, 0], xi[k, 1], un[k])["x_out"]
+    dt = time.perf_counter() - t0
+    return {"value": n_steps / dt, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_steps} MH steps of order {order} on the same workload by the "
+                      f"sequential FP64 C oracle on one host thread, {dt:.1f} s",
+            **host_info()}
 
 
 def bench_first_order(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
@@ -509,7 +703,7 @@ def bench_spatio_temporal(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dic
                                "kind": "oracle",
                                "sample": f"{cpu_steps} factorised MH steps of the same workload by "
                                          f"the sequential FP64 C oracle on one host thread, "
-                                         f"{dt:.1f} s"}
+                                         f"{dt:.1f} s", **host_info()}
     return out
 
 
@@ -564,7 +758,7 @@ def bench_lorenz(torch, S, W, _lib, K: int, dev, cpu_steps: int) -> dict:
                                    "kind": "oracle",
                                    "sample": f"{cpu_steps} MH steps of the same workload by the "
                                              f"sequential FP64 C oracle on one host thread, "
-                                             f"{dt:.1f} s"}
+                                             f"{dt:.1f} s", **host_info()}
         out[name] = res
     out["paper_reference"] = ("Lorenz-63 run of 2,500 adaptation + 1e5 steps (with a parameter "
                               "Gibbs step) in 3,149 s on an RTX 3090, about 31 ms per iteration "
@@ -643,11 +837,13 @@ def sampler_cpu_baseline(w, mf_dev, Pf_dev, dnc_steps: int = 512) -> dict:
     t_dnc = (time.perf_counter() - t0) * w.N / n
     return {"prefix_sum": {"value": 1.0 / t_rts, "unit": "samples/s", "cores": 1,
                            "kind": "oracle",
-                           "sample": f"one full RTS sample (T = {w.N}), {t_rts:.1f} s"},
+                           "sample": f"one full RTS sample (T = {w.N}), {t_rts:.1f} s",
+                           **host_info()},
             "divide_and_conquer": {"value": 1.0 / t_dnc, "unit": "samples/s", "cores": 1,
                                    "kind": "oracle",
                                    "sample": f"the first {n} steps of one sample, scaled by "
-                                             f"{w.N}/{n}: {t_dnc:.1f} s per full sample"}}
+                                             f"{w.N}/{n}: {t_dnc:.1f} s per full sample",
+                                   **host_info()}}
 
 
 def main() -> int:
@@ -655,6 +851,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats of --steps steps; the headline is their median")
     ap.add_argument("--block", type=int, default=0, help="scan block size (0 = automatic)")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -667,6 +865,7 @@ def main() -> int:
     ap.add_argument("--no-lorenz", action="store_true")
     ap.add_argument("--no-samplers", action="store_true")
     ap.add_argument("--no-first-order", action="store_true")
+    ap.add_argument("--no-poisson", action="store_true")
     ap.add_argument("--no-reuse", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
@@ -693,11 +892,12 @@ def main() -> int:
     M = S.DeviceModel.from_workload(w, device=dev)
     y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
     x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
-    K, Wm = args.steps, args.warmup
+    K, Wm, R = args.steps, args.warmup, args.repeats
     gen = torch.Generator(device=dev)
     gen.manual_seed(103)
-    xi = torch.randn((K + Wm, 2, N, d), dtype=torch.float64, device=dev, generator=gen)
-    un = torch.rand((K + Wm,), dtype=torch.float64, device=dev, generator=gen).clamp_(min=1e-300)
+    xi = torch.randn((R * K + Wm, 2, N, d), dtype=torch.float64, device=dev, generator=gen)
+    un = torch.rand((R * K + Wm,), dtype=torch.float64, device=dev,
+                    generator=gen).clamp_(min=1e-300)
     ws = S.Workspace(dev)
 
     # warm-up
@@ -705,25 +905,33 @@ def main() -> int:
         S.mh_run(M, y, x, w.delta, w.order, xi[:Wm], un[:Wm], block=B, ws=ws)
     torch.cuda.synchronize()
 
+    # R timed repeats of K steps each (the chain continues across repeats, with
+    # fresh normals); the headline is the median repeat
     lib = _lib.load()
     fam = _lib.FAMILIES[args.roofline_kernel]
-    _lib.check(lib.akf_timing_enable(fam, 8 * K + 16), "akf_timing_enable")
+    _lib.check(lib.akf_timing_enable(fam, 8 * K * R + 16), "akf_timing_enable")
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    ev0.record()
-    out = S.mh_run(M, y, x, w.delta, w.order, xi[Wm:], un[Wm:], block=B, ws=ws)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
+    rep_ms, accs, n_bad = [], [], 0
+    for r in range(R):
+        sl = slice(Wm + r * K, Wm + (r + 1) * K)
+        ev0.record()
+        out = S.mh_run(M, y, x, w.delta, w.order, xi[sl], un[sl], block=B, ws=ws)
+        ev1.record()
+        torch.cuda.synchronize()
+        rep_ms.append(ev0.elapsed_time(ev1))
+        accs.append(out["accepted"].float().mean().item())
+        n_bad += int((out["status"] != 0).sum().item())
     import ctypes as C
     n_l = C.c_int32()
     k_ms = C.c_double()
     _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
     lib.akf_timing_enable(-1, 0)
 
-    acc = out["accepted"].float().mean().item()
-    status_bad = int((out["status"] != 0).sum().item())
+    acc = sum(accs) / len(accs)
+    status_bad = n_bad
+    ms_total = sorted(rep_ms)[len(rep_ms) // 2]
     ms_step = ms_total / K
     steps_s = 1000.0 / ms_step
 
@@ -760,15 +968,17 @@ def main() -> int:
                    "d_x": d, "T": N, "chains": 1, "order": w.order, "delta": w.delta,
                    "scan_block": B},
         "time_steps_per_s": steps_s * N,
+        "repeats": R,
+        "repeat_ms_per_step": [m / K for m in rep_ms],
         "acceptance": acc,
         "rejected_by_status": status_bad,
         "roofline": roof,
     }
     if not args.no_batched:
-        res["batched"] = bench_batched(torch, S, W, args.batched_steps, dev,
+        res["batched"] = bench_batched(torch, S, W, _lib, args.batched_steps, dev,
                                        not args.no_cpu_baseline)
     if not args.no_adjoint:
-        res["adjoint"] = bench_adjoint(torch, S, W, 5, dev, not args.no_cpu_baseline)
+        res["adjoint"] = bench_adjoint(torch, S, W, _lib, 5, dev, not args.no_cpu_baseline)
     if not args.no_stoch_vol:
         res["stoch_vol"] = bench_stoch_vol(torch, S, W, _lib, 20, dev,
                                            0 if args.no_cpu_baseline else 20)
@@ -777,6 +987,9 @@ def main() -> int:
             torch, S, W, _lib, 100, dev, 0 if args.no_cpu_baseline else 100)
     if not args.no_samplers:
         res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev, not args.no_cpu_baseline)
+    if not args.no_poisson:
+        res["poisson"] = bench_poisson(torch, S, W, _lib, 50, dev,
+                                       0 if args.no_cpu_baseline else 20)
     if not args.no_first_order:
         res["first_order"] = bench_first_order(torch, S, W, _lib, 50, dev,
                                                0 if args.no_cpu_baseline else 1)

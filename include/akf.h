@@ -401,12 +401,19 @@ void akf_batch_plan_destroy(akf_batch_plan* plan);
  * down-sweep, 8 sampler final, 9 factorised scalar filter/sampler,
  * 10 emission and dynamics linearisation, 11 the whole divide-and-conquer
  * sampler, 12 and 13 the block folds of akf_mh_run_first_order's filtering
- * means and sampled path), every launch of that kernel on any stream is
+ * means and sampled path, 14 the adjoint's per-step gradient contractions,
+ * 15 the adjoint's element build, 16 / 17 / 18 the batched filter folds of
+ * team width 16 / 32 / 64, 19 / 20 / 21 the batched sampler element builds of
+ * those widths, 22 the MH bookkeeping kernels (step initialisation and the
+ * accept decision); every launch of akf_mh_step / akf_mh_run on a model with
+ * linear dynamics belongs to one family), every
+ * launch of that kernel on any stream is
  * bracketed by a pair of hipEvents recorded on the launch stream; at most
  * `capacity` launches are kept.  akf_timing_collect waits for the recorded
  * events and returns the number of launches and their summed duration in
  * milliseconds, then clears the record.  family < 0 disables timing.  The
- * events are created by akf_timing_enable (not under graph capture).
+ * events are created by akf_timing_enable (not under graph capture); launches
+ * enqueued while their stream is being captured are not timed.
  */
 akf_status akf_timing_enable(int32_t family, int32_t capacity);
 akf_status akf_timing_collect(int32_t* n_launches, double* total_ms);

@@ -103,7 +103,10 @@ SIGNATURES = {
 # kernel families of akf_timing_enable
 FAMILIES = {"filter_fold": 0, "filter_up": 1, "filter_down": 2, "filter_final": 3,
             "samp_build": 4, "samp_fold": 5, "samp_up": 6, "samp_down": 7, "samp_final": 8,
-            "fact_scan": 9, "lin": 10, "dnc": 11, "fixed_mean_fold": 12, "fixed_samp_fold": 13}
+            "fact_scan": 9, "lin": 10, "dnc": 11, "fixed_mean_fold": 12, "fixed_samp_fold": 13,
+            "adj_grad": 14, "adj_build": 15, "batch_fold16": 16, "batch_fold32": 17,
+            "batch_fold64": 18, "batch_sbuild16": 19, "batch_sbuild32": 20,
+            "batch_sbuild64": 21, "mh": 22}
 
 _lib = None
 

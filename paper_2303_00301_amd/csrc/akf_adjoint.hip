@@ -662,15 +662,19 @@ hipError_t launch_sum(const double* a, int n, double* out, const int* status, hi
 
 template <int D>
 hipError_t launch_adj_build_t(const KModel& M, LgArgs G, hipStream_t st) {
+  timing_mark(FAM_ADJ_BUILD, 1, st);
   hipLaunchKernelGGL(k_adj_build<D>, dim3(M.N), dim3(Cfg<D>::NT), lds_bytes_mats<D>(4, 3), st, M, G);
+  timing_mark(FAM_ADJ_BUILD, 0, st);
   return hipGetLastError();
 }
 template <int D>
 hipError_t launch_adj_finish_t(const KModel& M, LgArgs G, int nblk, const double* ll_bar,
                                hipStream_t st) {
   const int64_t n = (int64_t)M.N * D * D;
+  timing_mark(FAM_ADJ_GRAD, 1, st);
   hipLaunchKernelGGL(k_adj_grad<D>, dim3(nblk), dim3(Cfg<D>::NT), lds_bytes_mats<D>(6, 10), st, M,
                      G);
+  timing_mark(FAM_ADJ_GRAD, 0, st);
   const int tot = G.dx * G.dx + G.dx + G.dy * G.dx + G.dy;
   hipLaunchKernelGGL(k_adj_reduce<D>, dim3((tot + 31) / 32), dim3(256), 0, st, G, nblk, ll_bar);
   (void)n;

@@ -413,6 +413,10 @@ void timing_mark(int family, int begin, hipStream_t st) {
   if (g_timing.family != family) return;
   std::lock_guard<std::mutex> lk(g_timing.mu);
   if (g_timing.family != family || !g_timing.ev) return;
+  // launches recorded into a graph are not timed (the events would become
+  // graph nodes)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
   if (begin) {
     if (g_timing.used >= g_timing.capacity) return;
     (void)hipEventRecord(g_timing.ev[2 * g_timing.used], st);

@@ -303,7 +303,11 @@ enum {
   FAM_FILTER_FOLD = 0, FAM_FILTER_UP = 1, FAM_FILTER_DOWN = 2, FAM_FILTER_FINAL = 3,
   FAM_SAMP_BUILD = 4, FAM_SAMP_FOLD = 5, FAM_SAMP_UP = 6, FAM_SAMP_DOWN = 7, FAM_SAMP_FINAL = 8,
   FAM_FACT = 9, FAM_LIN = 10, FAM_DNC = 11, FAM_FIXED_MEAN_FOLD = 12, FAM_FIXED_SAMP_FOLD = 13,
-  FAM_COUNT = 14
+  FAM_ADJ_GRAD = 14, FAM_ADJ_BUILD = 15,
+  FAM_BATCH_FOLD16 = 16, FAM_BATCH_FOLD32 = 17, FAM_BATCH_FOLD64 = 18,
+  FAM_BATCH_SBUILD16 = 19, FAM_BATCH_SBUILD32 = 20, FAM_BATCH_SBUILD64 = 21,
+  FAM_MH = 22,
+  FAM_COUNT = 23
 };
 // Called by the launchers before (begin = 1) and after (begin = 0) each launch.
 void timing_mark(int family, int begin, hipStream_t st);

@@ -1799,7 +1799,9 @@ hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStre
 
 hipError_t launch_step_init(int* status, double* root_flag, double* root_xin, int D,
                             hipStream_t st) {
+  timing_mark(FAM_MH, 1, st);
   hipLaunchKernelGGL(k_step_init, dim3(1), dim3(64), 0, st, status, root_flag, root_xin, D);
+  timing_mark(FAM_MH, 0, st);
   return hipGetLastError();
 }
 
@@ -1808,7 +1810,9 @@ hipError_t launch_finalize(const KModel& M, StepArgs A, FinalArgs F, const doubl
   const int64_t n = (int64_t)M.N * M.d;
   const int64_t per_block = 2048;
   const unsigned grid = (unsigned)((n + per_block - 1) / per_block);
+  timing_mark(FAM_MH, 1, st);
   hipLaunchKernelGGL(k_mh_decide, dim3(grid), dim3(256), 0, st, M, A, F, x, x_out, n, per_block);
+  timing_mark(FAM_MH, 0, st);
   return hipGetLastError();
 }
 
@@ -2009,11 +2013,19 @@ hipError_t launch_batch_phase_t(int phase, BatchLaunch L, int level, int rev, co
     case BP_INIT: hipLaunchKernelGGL(kb_init, g, b64, 0, st, L, D); break;
     case BP_LIN_FWD: hipLaunchKernelGGL(kb_lin, g, b256, 0, st, L, 0, step); break;
     case BP_LIN_REV: hipLaunchKernelGGL(kb_lin, g, b256, 0, st, L, 1, step); break;
-    case BP_FOLD: hipLaunchKernelGGL(kb_fold<D>, g, bt, lds, st, L, rev); break;
+    case BP_FOLD:
+      timing_mark(FAM_BATCH_FOLD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 1, st);
+      hipLaunchKernelGGL(kb_fold<D>, g, bt, lds, st, L, rev);
+      timing_mark(FAM_BATCH_FOLD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 0, st);
+      break;
     case BP_UP: hipLaunchKernelGGL(kb_up<D>, g, bt, lds, st, L, level, rev); break;
     case BP_DOWN: hipLaunchKernelGGL(kb_down<D>, g, bt, lds, st, L, level, rev); break;
     case BP_FINAL: hipLaunchKernelGGL(kb_final<D>, g, bt, lds, st, L, rev); break;
-    case BP_SBUILD: hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step); break;
+    case BP_SBUILD:
+      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 1, st);
+      hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step);
+      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 0, st);
+      break;
     case BP_SFOLD: hipLaunchKernelGGL(kb_sfold<D>, g, bt, lds, st, L); break;
     case BP_SUP: hipLaunchKernelGGL(kb_sup<D>, g, bt, lds, st, L, level); break;
     case BP_SDOWN: hipLaunchKernelGGL(kb_sdown<D>, g, b64, 0, st, L, level); break;

@@ -36,6 +36,10 @@ def T(a, dtype=torch.float64):
     return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=dev())
 
 
+def N_(t):
+    return t.detach().cpu().numpy()
+
+
 def _chains(S, ws, n_steps):
     out = []
     for k, w in enumerate(ws):
@@ -157,3 +161,81 @@ def test_batch_with_every_team_width(S):
     assert int(chains[k64]["status"].cpu()[0]) == r["status"]
     lr = float(chains[k64]["log_ratio"].cpu()[0])
     assert abs(lr - r["log_ratio"]) <= 1e-9 * w.N * w.dx + 1e-9 * max(1.0, abs(r["log_ratio"]))
+
+
+def _lr_tol(N, d, lr_ref):
+    return 1e-9 * N * d + 1e-9 * max(1.0, abs(lr_ref))
+
+
+def test_batched_benchmark_shape_autotuned(S, tmp_path):
+    """The benchmark's ragged batch (its first 48 chains: N up to 8192, d_x in
+    {4, 16, 32}, Poisson log link, order 2), planned with block = 0 so the
+    autotuner picks each class's scan block (its candidates are checked
+    against plain per-chain steps before one is kept), two graph-replayed
+    steps.  Every chain equals its own akf_mh_run with the same block, normals
+    and uniforms; the shortest and longest chain of each width equal the
+    oracle's first step."""
+    ws = W.ragged_poisson_batch(n_chains=48)
+    assert {w.dx for w in ws} == {4, 16, 32}
+    assert max(w.N for w in ws) > 7000 and min(w.N for w in ws) < 1000
+    n_steps = 2
+    chains = _chains(S, ws, n_steps)
+    print(f"planning {len(chains)} chains, {sum(w.N for w in ws)} time steps", flush=True)
+    plan = S.BatchPlan(chains, n_steps, block=0, tune_cache=str(tmp_path / "tune.jsonl"))
+    info = plan.info()
+    blk = {c["D"]: c["block"] for c in info["classes"]}
+    assert set(blk) == {16, 32} and all(b > 0 for b in blk.values())
+    lines = open(tmp_path / "tune.jsonl").read().strip().splitlines()
+    assert len(lines) == 2 and all('"verified": true' in ln for ln in lines)
+    plan.run(use_graph=True)
+    torch.cuda.synchronize()
+    n_tie = 0
+    for w, c in zip(ws, chains):
+        x = T(c["x0"])
+        ref = S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"],
+                       block=blk[16 if w.dx <= 16 else 32])
+        torch.cuda.synchronize()
+        un = N_(c["unif"])
+        same_path = True
+        for k in range(n_steps):
+            assert int(N_(c["status"])[k]) == int(N_(ref["status"])[k]), (w.name, k)
+            if int(N_(ref["status"])[k]) != 0:
+                continue
+            lr, lr_ref = float(N_(c["log_ratio"])[k]), float(N_(ref["log_ratio"])[k])
+            tol = _lr_tol(w.N, w.dx, lr_ref)
+            assert abs(lr - lr_ref) <= tol, (w.name, k, lr, lr_ref)
+            for key in ("logZ_fwd", "logZ_rev"):
+                g, r = float(N_(c[key])[k]), float(N_(ref[key])[k])
+                assert abs(g - r) <= 1e-8 * max(1.0, abs(r)) + 1e-9 * w.N, (w.name, key, g, r)
+            if int(N_(c["accepted"])[k]) != int(N_(ref["accepted"])[k]):
+                assert abs(np.log(un[k]) - lr_ref) <= tol  # a tie: both decisions are right
+                n_tie += 1
+                same_path = False
+                break
+        if same_path:
+            err = torch.linalg.norm(c["x"] - x) / max(1.0, float(torch.linalg.norm(x)))
+            assert float(err) <= 1e-9, (w.name, float(err))
+    plan.close()
+    assert n_tie <= 2
+    # the oracle's first step for the extreme chains of each width
+    picks = []
+    for d in (4, 16, 32):
+        same = [k for k, w in enumerate(ws) if w.dx == d]
+        picks += [min(same, key=lambda k: ws[k].N), max(same, key=lambda k: ws[k].N)]
+    for k in picks:
+        w, c = ws[k], chains[k]
+        print(f"oracle step of chain {k}: d={w.dx} N={w.N}", flush=True)
+        xi = w.normals(n_steps)
+        r = oracle.mh_step(oracle.Model(**w.oracle_kwargs()), w.y, c["x0"], w.delta, 2,
+                           xi[0][0], xi[0][1], float(w.uniforms(n_steps)[0]))
+        assert int(N_(c["status"])[0]) == r["status"]
+        if r["status"] != 0:
+            continue
+        lr = float(N_(c["log_ratio"])[0])
+        tol = _lr_tol(w.N, w.dx, r["log_ratio"])
+        assert abs(lr - r["log_ratio"]) <= tol, (k, lr, r["log_ratio"])
+        for key in ("logZ_fwd", "logZ_rev"):
+            g = float(N_(c[key])[0])
+            assert abs(g - r[key]) <= 1e-8 * max(1.0, abs(r[key])) + 1e-9 * w.N, (k, key)
+        if abs(np.log(w.uniforms(n_steps)[0]) - r["log_ratio"]) > tol:
+            assert int(N_(c["accepted"])[0]) == r["accepted"]

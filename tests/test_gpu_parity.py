@@ -231,6 +231,32 @@ def test_latent_field_full_size_one_step(S):
     _compare_step(S, M_or, M_dev, w.y, x, w.delta, 2, xi[0], un[0])
 
 
+def test_latent_field_full_size_accepted_path(S):
+    """d = 64, N = 4096 in the benchmark's launch configuration, with a uniform
+    small enough that the step accepts (log U = log 1e-12 < log r), so the
+    returned path is the proposal x* itself and is compared element by element
+    with the oracle's x*, scaled by the smoothing standard deviations of the
+    forward auxiliary model."""
+    w = W.latent_field()
+    M_or = oracle.Model(**w.oracle_kwargs())
+    M_dev = S.DeviceModel.from_workload(w, device=dev())
+    xi = w.normals(2)[1]
+    x = w.x_true.copy()
+    r = _compare_step(S, M_or, M_dev, w.y, x, w.delta, 2, xi, 1e-12)
+    assert r["status"] == 0 and r["accepted"] == 1
+    assert np.log(1e-12) < r["log_ratio"] - 1.0
+    # per-coordinate scale of x*: the auxiliary model's smoothing sd at x
+    u = x + np.sqrt(w.delta / 2) * xi[0]
+    om, Om, _, rc = oracle.linearise(M_or, w.y, x, u, w.delta, 2)
+    assert rc == 0
+    kf = oracle.kf(w.m0, w.P0, w.F, w.Q, np.eye(w.dx), Om, om, b=w.b, R_per_t=True)
+    _, Ps, _, _ = oracle.rts_smooth(w.F, kf["mf"], kf["Pf"], kf["mp"], kf["Pp"])
+    out = S.mh_step(M_dev, T(w.y), T(x), w.delta, 2, T(xi), T([1e-12]))
+    torch.cuda.synchronize()
+    err = np.abs(N_(out["x_out"]) - r["xstar"]) / np.sqrt(np.einsum("tii->ti", Ps))
+    assert err.max() < MEAN_TOL, err.max()
+
+
 def test_single_step_single_dim(S):
     rng = np.random.default_rng(5)
     kw = dict(m0=np.zeros(1), P0=np.eye(1), F=np.array([[0.5]]), Q=np.array([[0.3]]), emit=2,
