@@ -28,6 +28,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
 EMIT_GAUSS_SITE = 5
+EMIT_GAUSS_QUAD = 6
 DYN_LINEAR, DYN_LORENZ63, DYN_LORENZ96 = 0, 1, 2
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
@@ -80,6 +81,7 @@ class _Model(C.Structure):
         ("site", _ip),
         ("nu", C.c_double), ("scale", C.c_double),
         ("dyn", C.c_int), ("dyn_par", C.c_double * 4),
+        ("obs_beta", C.c_double), ("slr_var", C.c_double),
     ]
 
 
@@ -96,6 +98,8 @@ def _declare(L):
     L.or_rts_smooth.argtypes = [C.c_int, C.c_int, _dp, C.c_long, _dp, _dp, _dp, _dp, _dp, _dp, _dp]
     L.or_emission.restype = C.c_double
     L.or_emission.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, _dp]
+    L.or_obs_linearise.restype = C.c_int
+    L.or_obs_linearise.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, _dp]
     L.or_linearise.restype = C.c_int
     L.or_linearise.argtypes = [C.POINTER(_Model), _dp, _dp, _dp, C.c_double, C.c_int, _dp, _dp, _dp]
     L.or_dyn.restype = None
@@ -139,7 +143,10 @@ class Model:
     emit: EMIT_GAUSSIAN (H [dy,dx], R [dy,dy]); EMIT_POISSON_LOG,
     EMIT_STUDENT_T, EMIT_STOCH_VOL or EMIT_GAUSS_SITE (site [dy]: y_k observes
     x[site[k]]; nu, scale for Student-t; scale for Gaussian at sites; NaN = not
-    observed); EMIT_MVT (site [dy], precision R [dy,dy], nu).  dyn != DYN_LINEAR
+    observed); EMIT_MVT (site [dy], precision R [dy,dy], nu); EMIT_GAUSS_QUAD
+    (site [dy]: y_k = x + obs_beta x^2 + N(0, scale^2) at x = x[site[k]]).
+    slr_var is the reference variance of the observation-model linearisation
+    used by order 3 (0 = Taylor).  dyn != DYN_LINEAR
     replaces F, b by x_t = f(x_{t-1}) + N(0, Q) with parameters dyn_par.
     """
     m0: np.ndarray
@@ -155,6 +162,8 @@ class Model:
     scale: float = 0.0
     dyn: int = DYN_LINEAR
     dyn_par: tuple = (0.0, 0.0, 0.0, 0.0)
+    obs_beta: float = 0.0
+    slr_var: float = 0.0
 
     @property
     def dx(self) -> int:
@@ -194,6 +203,7 @@ class _Bound:
         par = list(M.dyn_par) + [0.0] * (4 - len(M.dyn_par))
         for i in range(4):
             s.dyn_par[i] = float(par[i])
+        s.obs_beta, s.slr_var = float(M.obs_beta), float(M.slr_var)
         self.s = s
 
     def ref(self):
@@ -262,6 +272,18 @@ def emission(M: Model, yt, xt):
     Lam = np.zeros((M.dx, M.dx))
     lh = lib().or_emission(B.ref(), _p(yt), _p(xt), _p(v), _p(Lam))
     return lh, v, Lam
+
+
+def obs_linearise(M: Model, yt, xt):
+    """(v, Lambda, rc) of the observation model's linear-Gaussian
+    approximation at one time step (statistical linear regression with
+    reference variance M.slr_var; Taylor at 0)."""
+    B = _Bound(M, 1)
+    yt, xt = _f64(yt), _f64(xt)
+    v = np.zeros(M.dx)
+    Lam = np.zeros((M.dx, M.dx))
+    rc = lib().or_obs_linearise(B.ref(), _p(yt), _p(xt), _p(v), _p(Lam))
+    return v, Lam, rc
 
 
 def dyn(M: Model, x):

@@ -24,9 +24,14 @@
  *                    linearised-log-potential-second).
  *   or_dyn, or_dyn_linearise  Euler steps of the Lorenz-63 / Lorenz-96 SDEs and
  *                    their extended linearisation (Example "gslr-example").
+ *   or_obs_linearise the observation model's Gaussian approximation
+ *                    N(H z + c, R) around x_t by statistical linear regression
+ *                    (eq. observation-approx, eq. coeffs; Taylor limit at a zero
+ *                    reference variance).
  *   or_linearise     pseudo-observations (omega_t, Omega_t) of the auxiliary
- *                    LGSSM: first order (eq. gaussian-FK-proposal) or second
- *                    order (eq. second-order), with Sigma_t = I.
+ *                    LGSSM: first order (eq. gaussian-FK-proposal), second
+ *                    order (eq. second-order), or the linearised observation
+ *                    model (order 3: eq. two-lin-prop), with Sigma_t = I.
  *   or_mh_step       one step of the general auxiliary Kalman sampler
  *                    (Alg. "General Auxiliary Kalman sampler"), Hastings-within-
  *                    Gibbs on x | u.
@@ -554,7 +559,7 @@ int or_rts_smooth(int N, int dx, const double* F, long F_stride, const double* m
 /* ------------------------------------------------------------------ */
 
 enum { OR_EMIT_GAUSSIAN = 0, OR_EMIT_POISSON_LOG = 1, OR_EMIT_STUDENT_T = 2, OR_EMIT_STOCH_VOL = 3,
-       OR_EMIT_MVT = 4, OR_EMIT_GAUSS_SITE = 5 };
+       OR_EMIT_MVT = 4, OR_EMIT_GAUSS_SITE = 5, OR_EMIT_GAUSS_QUAD = 6 };
 enum { OR_DYN_LINEAR = 0, OR_DYN_LORENZ63 = 1, OR_DYN_LORENZ96 = 2 };
 
 typedef struct {
@@ -566,6 +571,8 @@ typedef struct {
   double nu, scale;     /* Student-t (nu, scale); multivariate t (nu); Gaussian at sites (scale) */
   int dyn;              /* OR_DYN_*: linear (F, b) or x_t = f(x_{t-1}) + N(0, Q) */
   double dyn_par[4];    /* Lorenz-63: theta1, theta2, theta3, dt; Lorenz-96: forcing, dt */
+  double obs_beta;      /* quadratic observation mean x + beta x^2 (Gaussian, quadratic mean) */
+  double slr_var;       /* reference variance gamma^2 of the observation-model linearisation */
 } or_model;
 
 /*
@@ -663,6 +670,18 @@ double or_emission(const or_model* M, const double* yt, const double* xt, double
       lh += -0.5 * xt[i] - 0.5 * q;
       if (v) v[i] += -0.5 + 0.5 * q;
       if (Lam) Lam[i * n + i] -= 0.5 * q;
+    }
+  } else if (M->emit == OR_EMIT_GAUSS_QUAD) {
+    /* y_k = x_i + beta x_i^2 + N(0, s^2): log h = -(y_k - m)^2 / (2 s^2),
+       m = x_i + beta x_i^2, dm/dx = 1 + 2 beta x_i, d2m/dx2 = 2 beta */
+    const double s2 = M->scale * M->scale, be = M->obs_beta;
+    for (int k = 0; k < p; ++k) {
+      if (isnan(yt[k])) continue;
+      int i = M->site[k];
+      double m = xt[i] + be * xt[i] * xt[i], g = 1.0 + 2.0 * be * xt[i], r = yt[k] - m;
+      lh += -0.5 * r * r / s2;
+      if (v) v[i] += g * r / s2;
+      if (Lam) Lam[i * n + i] += (2.0 * be * r - g * g) / s2;
     }
   } else if (M->emit == OR_EMIT_GAUSS_SITE) {
     /* y_k = x_i + N(0, s^2): log h = -(y_k - x_i)^2 / (2 s^2) */
@@ -791,6 +810,95 @@ static double dyn_mismatch(const or_model* M, const double* z, const double* F, 
  * Omega: [N,dx,dx] dense.  loghsum receives sum_t log h_t(y_t|x_t).
  * Returns 0, or 1 + t when 2/delta I - Lambda_t is not positive definite.
  */
+/*
+ * Linearisation of the observation model (eq. observation-approx):
+ * h_t(y_t | z) ~ N(y_t; H_t z + c_t, R_t) around x_t, by the statistical
+ * linear regression of App. "Generalised statistical linear regression"
+ * (eq. coeffs with the moments of eq. general-GSLR-coeffs) for the reference
+ * variable zeta ~ N(x_t, Gamma), Gamma = slr_var I:
+ *   mu = E[m(zeta)], C = Cov[m(zeta), zeta], S = E[V(zeta)] + Var[m(zeta)],
+ *   H = C Gamma^{-1}, c = mu - H x, R = S - H Gamma H^T,
+ * over the observed sites (NaN entries dropped).  slr_var = 0 is the Taylor
+ * (extended) limit: H = dm/dx at x, c = m(x) - H x, R = E[V].  Families with a
+ * Gaussian observation around a mean: Gaussian at sites (m_k = x_i, V = s^2)
+ * and quadratic mean (m_k = x_i + beta x_i^2, V = s^2); the moments of a
+ * quadratic of a Gaussian are exact:
+ *   E[zeta_i^2] = x_i^2 + g2, Cov(zeta_i^2, zeta_i) = 2 x_i g2,
+ *   Var(zeta_i^2) = 4 x_i^2 g2 + 2 g2^2  (g2 = slr_var).
+ * The proposal of eq. two-lin-prop then sees this Gaussian in place of h_t,
+ * whose log density at z = x has gradient and Hessian
+ *   v = H^T R^{-1} (y - c - H x),  Lambda = -H^T R^{-1} H,
+ * written to v [dx], Lam [dx,dx].  Returns 0, or -1 for another family or a
+ * non-positive-definite R.
+ */
+int or_obs_linearise(const or_model* M, const double* yt, const double* xt, double* v,
+                     double* Lam) {
+  const int n = M->dx, p = M->dy;
+  const double s2 = M->scale * M->scale, g2 = M->slr_var;
+  const double be = (M->emit == OR_EMIT_GAUSS_QUAD) ? M->obs_beta : 0.0;
+  memset(v, 0, sizeof(double) * n);
+  memset(Lam, 0, sizeof(double) * n * n);
+  if (M->emit != OR_EMIT_GAUSS_SITE && M->emit != OR_EMIT_GAUSS_QUAD) return -1;
+  int* ks = malloc(sizeof(int) * p);
+  int po = 0;
+  for (int k = 0; k < p; ++k)
+    if (!isnan(yt[k])) ks[po++] = k;
+  if (po == 0) {
+    free(ks);
+    return 0;
+  }
+  double* mu = malloc(sizeof(double) * po);
+  double* H = calloc((size_t)po * n, sizeof(double));
+  double* R = malloc(sizeof(double) * po * po);
+  double* L = malloc(sizeof(double) * po * po);
+  double* r = malloc(sizeof(double) * po);
+  double* RiH = malloc(sizeof(double) * po * n);
+  double* col = malloc(sizeof(double) * po);
+  /* moments over zeta (coordinates independent under Gamma = g2 I) */
+  for (int a = 0; a < po; ++a) {
+    const int i = M->site[ks[a]];
+    const double x = xt[i];
+    const double Ez2 = x * x + g2;
+    mu[a] = x + be * Ez2;
+    /* C_a,i = Cov(zeta + beta zeta^2, zeta) = g2 + 2 beta x g2; H = C / g2, or
+       dm/dx in the Taylor limit (the same value) */
+    H[a * n + i] = 1.0 + 2.0 * be * x;
+  }
+  for (int a = 0; a < po; ++a)
+    for (int b = 0; b < po; ++b) {
+      const int i = M->site[ks[a]], j = M->site[ks[b]];
+      double S = (a == b) ? s2 : 0.0;
+      if (g2 > 0.0 && i == j) {
+        const double x = xt[i];
+        /* Var(zeta + beta zeta^2) = g2 + 4 beta x g2 + beta^2 (4 x^2 g2 + 2 g2^2) */
+        S += g2 + 4.0 * be * x * g2 + be * be * (4.0 * x * x * g2 + 2.0 * g2 * g2);
+      }
+      /* R = S - H Gamma H^T */
+      double hgh = 0.0;
+      for (int q = 0; q < n; ++q) hgh += H[a * n + q] * g2 * H[b * n + q];
+      R[a * po + b] = S - hgh;
+    }
+  int rc = chol(po, R, L);
+  if (!rc) {
+    /* residual y - c - H x = y - mu */
+    for (int a = 0; a < po; ++a) r[a] = yt[ks[a]] - mu[a];
+    fwd_sub(po, L, r);
+    bwd_sub(po, L, r);
+    for (int q = 0; q < n; ++q) {
+      double sq = 0.0;
+      for (int a = 0; a < po; ++a) sq += H[a * n + q] * r[a];
+      v[q] = sq;
+    }
+    memcpy(RiH, H, sizeof(double) * po * n);
+    chol_solve(po, n, L, RiH, col);
+    mm_tn(n, n, po, H, RiH, Lam);
+    for (int q = 0; q < n * n; ++q) Lam[q] = -Lam[q];
+    symmetrise(n, Lam);
+  }
+  free(ks); free(mu); free(H); free(R); free(L); free(r); free(RiH); free(col);
+  return rc ? -1 : 0;
+}
+
 int or_linearise(const or_model* M, const double* y, const double* x, const double* u, double delta,
                  int order, double* omega, double* Omega, double* loghsum) {
   const int n = M->dx, p = M->dy;
@@ -805,7 +913,18 @@ int or_linearise(const or_model* M, const double* y, const double* x, const doub
   int rc = 0;
   for (long t = 0; t < M->N; ++t) {
     const double* xt = x + t * n;
-    lhs += or_emission(M, y + t * p, xt, v, Lam);
+    if (order == 3) {
+      /* the linearised observation model in place of log h's own derivatives */
+      lhs += or_emission(M, y + t * p, xt, NULL, NULL);
+      if (or_obs_linearise(M, y + t * p, xt, v, Lam)) {
+        if (rc == 0) rc = 1 + (int)t;
+        memset(omega + t * n, 0, sizeof(double) * n);
+        memset(Omega + t * n * n, 0, sizeof(double) * n * n);
+        continue;
+      }
+    } else {
+      lhs += or_emission(M, y + t * p, xt, v, Lam);
+    }
     if (order == 1) memset(Lam, 0, sizeof(double) * n * n);
     for (int i = 0; i < n * n; ++i) Prec[i] = -Lam[i];
     for (int i = 0; i < n; ++i) Prec[i * n + i] += 2.0 / delta;
@@ -1088,7 +1207,7 @@ int or_mh_step_factorised(const or_model* M, const double* y, const double* x, d
                           double* x_out, double* log_ratio, int* accepted, double* logZ_fwd,
                           double* logZ_rev, double* xstar_out) {
   const int N = M->N, n = M->dx;
-  if (M->dyn != OR_DYN_LINEAR) return -1;
+  if (M->dyn != OR_DYN_LINEAR || order == 3) return -1;
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j)
       if (i != j && (M->F[i * n + j] != 0.0 || M->Q[i * n + j] != 0.0 || M->P0[i * n + j] != 0.0))
