@@ -418,6 +418,99 @@ def bench_adjoint(torch, S, W, _lib, reps: int, dev, cpu: bool = False) -> dict:
     return out
 
 
+def bench_gibbs(torch, S, W, _lib, n_sweeps: int, dev, cpu: bool = False) -> dict:
+    """Gibbs sweeps over (theta, x) at the differentiation workload's shape
+    (d_x = 32, d_y = 16, T = 16384, 1584 parameters): MALA on theta with the
+    log-likelihood and adjoint at each proposal, an exact refresh of x and one
+    auxiliary Kalman path step per sweep, all on the device.  The normals are
+    drawn on the device beforehand (a seeded torch generator), outside the
+    timed region.  The adjoint's share is the time of one log-likelihood +
+    gradient evaluation (timed alone on the same theta) over the sweep time."""
+    pw = W.lgssm_params()
+    N, dx, dy = pw.N, pw.m0.shape[0], pw.y.shape[1]
+    p = S.n_theta(dx, dy)
+    sd, eps, k = 10.0, 2e-4, 1
+    model = S.LGSSM(pw.m0, pw.P0, pw.y, device=dev)
+    theta0 = torch.as_tensor(pw.theta0.flat(), dtype=torch.float64, device=dev)
+    x0 = torch.zeros((N, dx), dtype=torch.float64, device=dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(105)
+
+    def draws(n):
+        return (torch.randn((n, p), generator=gen, dtype=torch.float64, device=dev),
+                torch.rand((n, 1), generator=gen, dtype=torch.float64, device=dev),
+                torch.randn((n, N, dx), generator=gen, dtype=torch.float64, device=dev),
+                torch.randn((n, k, 2, N, dx), generator=gen, dtype=torch.float64, device=dev),
+                torch.rand((n, k), generator=gen, dtype=torch.float64, device=dev))
+
+    G = S.gibbs_init(model, theta0, x0, prior_sd=sd)
+    warm = draws(3)
+    for i in range(3):
+        S.gibbs_sweep(G, eps, warm[0][i], warm[1][i], warm[2][i], 0.5, warm[3][i], warm[4][i],
+                      outputs=False)
+    dr = draws(n_sweeps)
+    acc_t = torch.zeros(n_sweeps, dtype=torch.int32, device=dev)
+    acc_p = torch.zeros(n_sweeps, dtype=torch.int32, device=dev)
+    outs = []
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(n_sweeps):
+        outs.append(S.gibbs_sweep(G, eps, dr[0][i], dr[1][i], dr[2][i], 0.5, dr[3][i], dr[4][i]))
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n_sweeps
+    for i, o in enumerate(outs):
+        acc_t[i] = o["accepted_theta"][0]
+        acc_p[i] = o["path_accepted"][0]
+    # one log-likelihood + gradient evaluation on the same shape
+    F, lq, H, lr = (t.contiguous() for t in (G.theta[:dx * dx].view(dx, dx),
+                                              G.theta[dx * dx:dx * dx + dx],
+                                              G.theta[dx * dx + dx:dx * dx + dx + dy * dx]
+                                              .view(dy, dx),
+                                              G.theta[dx * dx + dx + dy * dx:]))
+    ws = S.Workspace(dev)
+    S.lgssm_loglik(model, F, lq, H, lr, ws=ws)
+    S.lgssm_loglik_grad(model, F, lq, H, lr, ws)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(5):
+        S.lgssm_loglik(model, F, lq, H, lr, ws=ws)
+        S.lgssm_loglik_grad(model, F, lq, H, lr, ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ll_ms = e0.elapsed_time(e1) / 5
+    out = {"workload": f"Gibbs sweeps over (theta, x), LGSSM d_x={dx}, d_y={dy}, T={N}, "
+                       f"{p} parameters, prior N(0, {sd:g}^2), MALA step {eps:g}, {k} path step "
+                       f"per sweep",
+           "sweeps": n_sweeps, "ms_per_sweep": ms, "sweeps_per_s": 1e3 / ms,
+           "time_steps_per_s": N * 1e3 / ms,
+           "theta_acceptance": float(acc_t.float().mean().item()),
+           "path_acceptance": float(acc_p.float().mean().item()),
+           "loglik_and_adjoint_ms": ll_ms, "adjoint_share": ll_ms / ms,
+           "final_status": [int(v) for v in G.status.cpu().tolist()]}
+    if cpu:
+        import numpy as np
+        from oracle import gibbs as OG
+        rng = np.random.default_rng(105)
+        th = pw.theta0.flat()
+        t0 = time.perf_counter()
+        lp, g = OG.gibbs_init(pw.m0, pw.P0, pw.y, th, sd)
+        t1 = time.perf_counter()
+        OG.gibbs_sweep(pw.m0, pw.P0, pw.y, th, lp, g, np.zeros((N, dx)), sd, eps,
+                       rng.standard_normal(p), 0.5, rng.standard_normal((N, dx)), 0.5,
+                       rng.standard_normal((k, 2, N, dx)), np.array([0.5]))
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "sweeps/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one sweep of the same shape by the oracle (FP64 C "
+                                         f"Kalman filter, Fisher-identity score, RTS sampler "
+                                         f"and MH step on one host thread), {dt:.1f} s "
+                                         f"(plus {t1 - t0:.1f} s for its starting gradient)",
+                               **host_info()}
+    return out
+
+
 def bench_stoch_vol(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
     """Second paper workload on the same path: multivariate stochastic volatility
     (d_x = 30, T = 250), one chain, both linearisation orders; roofline of the
@@ -860,6 +953,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-gibbs", action="store_true")
+    ap.add_argument("--gibbs-sweeps", type=int, default=200)
     ap.add_argument("--no-stoch-vol", action="store_true")
     ap.add_argument("--no-spatio-temporal", action="store_true")
     ap.add_argument("--no-lorenz", action="store_true")
@@ -979,6 +1074,9 @@ def main() -> int:
                                        not args.no_cpu_baseline)
     if not args.no_adjoint:
         res["adjoint"] = bench_adjoint(torch, S, W, _lib, 5, dev, not args.no_cpu_baseline)
+    if not args.no_gibbs:
+        res["gibbs"] = bench_gibbs(torch, S, W, _lib, args.gibbs_sweeps, dev,
+                                   not args.no_cpu_baseline)
     if not args.no_stoch_vol:
         res["stoch_vol"] = bench_stoch_vol(torch, S, W, _lib, 20, dev,
                                            0 if args.no_cpu_baseline else 20)

@@ -338,6 +338,59 @@ akf_status akf_lgssm_loglik_grad(const akf_lgssm* m, const double* ll_bar, doubl
                                  void* ws, size_t ws_bytes, int32_t block, void* stream);
 
 /*
+ * Gibbs sampler over (theta, x) of the linear-Gaussian model above (the
+ * parametric model of eq. parametric-ssm; parameters and path updated in
+ * turn as in Sec. "Parameter estimation in a continuous-discrete diffusion
+ * smoothing problem").  theta is one flat device array of
+ * p = dx*dx + dx + dy*dx + dy doubles: F (row-major), logq, H (row-major),
+ * logr.  The prior is N(0, prior_sd^2) on every coordinate.  The fields
+ * F, logq, H and logr of `m` are ignored (theta replaces them); N, dx, dy, m0,
+ * P0 and y are used.  1 <= dx, dy <= 32.
+ *
+ * One sweep, all on the device (no host synchronisation):
+ *   1. MALA on log pi(theta) = log p(theta) + log p(y | theta):
+ *      theta' = theta + (eps^2/2) grad(theta) + eps xi_theta, with
+ *      log p(y | theta') and its gradient from the parallel filter and the
+ *      adjoint; log alpha = log pi(theta') - log pi(theta)
+ *      + log q(theta | theta') - log q(theta' | theta),
+ *      q(a | b) = N(a; b + (eps^2/2) grad(b), eps^2 I); accept iff the
+ *      proposal's filter succeeded, log alpha is finite and
+ *      log u_theta < log alpha.  theta, logpost and grad are replaced on
+ *      acceptance.
+ *   2. x ~ p(x | theta, y) exactly (parallel filter + RTS sampler, normals
+ *      xi_x [N,dx]), overwriting x: the theta move targets the theta-marginal,
+ *      so x is re-drawn from its full conditional;
+ *   3. n_path auxiliary Kalman MH steps (order 2; the emission is Gaussian,
+ *      so every step accepts) on x at theta, with xi_path [n_path,2,N,dx] and
+ *      u_path [n_path] as in akf_mh_run.
+ * Arguments: theta [p], logpost [1], grad [p] (log posterior and its gradient
+ * at theta, kept by the caller between sweeps), x [N,dx] (all in/out);
+ * state: `akf_gibbs_state_bytes` bytes (256-aligned) holding the filtering
+ * moments and dense Q, R of theta between sweeps; eps > 0; u_theta [1] in
+ * (0,1).  Outputs (device, each may be NULL): accepted_theta [1],
+ * log_alpha [1], path_log_ratio / path_accepted / path_status [n_path],
+ * status [2]: [0] the proposal's filter/adjoint status (non-zero = the
+ * proposal was rejected as undefined), [1] the refresh sampler's status.
+ * akf_gibbs_init fills logpost, grad and the state for a starting theta
+ * (status [1]; logpost NaN if its filter fails).  Workspace:
+ * akf_gibbs_workspace_bytes (contents not kept between calls).
+ */
+size_t akf_gibbs_state_bytes(const akf_lgssm* m);
+size_t akf_gibbs_workspace_bytes(const akf_lgssm* m, int32_t block);
+akf_status akf_gibbs_init(const akf_lgssm* m, const double* theta, double prior_sd,
+                          double* logpost, double* grad, void* state, size_t state_bytes,
+                          int32_t* status, void* ws, size_t ws_bytes, int32_t block,
+                          void* stream);
+akf_status akf_gibbs_sweep(const akf_lgssm* m, double* theta, double* logpost, double* grad,
+                           double* x, void* state, size_t state_bytes, double prior_sd, double eps,
+                           const double* xi_theta, const double* u_theta, const double* xi_x,
+                           double delta, int32_t n_path, const double* xi_path,
+                           const double* u_path, int32_t* accepted_theta, double* log_alpha,
+                           double* path_log_ratio, int32_t* path_accepted, int32_t* path_status,
+                           int32_t* status, void* ws, size_t ws_bytes, int32_t block,
+                           void* stream);
+
+/*
  * Batched chains: many independent chains (each its own model, length N and
  * dimension dx) advanced together.  All chains are grouped by team size
  * (dx <= 16, <= 32, <= 64); every phase of a step is one persistent launch per

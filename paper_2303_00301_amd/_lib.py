@@ -89,6 +89,13 @@ SIGNATURES = {
     "akf_lgssm_loglik": (C.c_int, [C.c_void_p, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
     "akf_lgssm_loglik_grad": (C.c_int, [C.c_void_p, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32,
                                         _vp]),
+    "akf_gibbs_state_bytes": (_sz, [C.c_void_p]),
+    "akf_gibbs_workspace_bytes": (_sz, [C.c_void_p, _i32]),
+    "akf_gibbs_init": (C.c_int, [C.c_void_p, _vp, _d, _vp, _vp, _vp, _sz, _vp, _vp, _sz, _i32,
+                                 _vp]),
+    "akf_gibbs_sweep": (C.c_int, [C.c_void_p, _vp, _vp, _vp, _vp, _vp, _sz, _d, _d, _vp, _vp,
+                                  _vp, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
+                                  _i32, _vp]),
     "akf_batch_plan_create": (C.c_int, [C.POINTER(C.c_void_p), _i32, C.POINTER(AkfChain), _i32,
                                         _i32, C.c_char_p, _vp]),
     "akf_batch_mh_run": (C.c_int, [_vp, _i32, _vp]),

@@ -491,12 +491,6 @@ int lgssm_D(const akf_lgssm* m) {
   return d <= 16 ? 16 : 32;
 }
 
-void lgssm_layout(Layout& Lo, const akf_lgssm* m, int block) {
-  // team size follows max(dx, dy): the observation block is padded to the same D
-  make_layout(Lo, m->N, m->dx > m->dy ? m->dx : m->dy, m->dy, block, LAYOUT_LGSSM);
-  Lo.d = m->dx;
-}
-
 KModel lgssm_kmodel(const akf_lgssm* m, void* ws, const Layout& Lo) {
   KModel M{};
   M.N = m->N;
@@ -594,8 +588,10 @@ akf_status akf_lgssm_loglik_grad(const akf_lgssm* m, const double* ll_bar, doubl
   G.dH = dH;
   G.dlogr = dlogr;
   KModel M = lgssm_kmodel(m, ws, Lo);
-  // adjoint elements: E = Phi', U = H'w, Cm = -1/2 H' Sig H
-  if ((s = hip_check(launch_step_init(G.status, nullptr, at<double>(ws, Lo.xin[Lo.L]), D, st),
+  // adjoint elements: E = Phi', U = H'w, Cm = -1/2 H' Sig H.  The status word
+  // keeps the forward pass's bits (the adjoint adds its own), so a failed
+  // forward pass also leaves NaN gradients.
+  if ((s = hip_check(launch_step_init(nullptr, nullptr, at<double>(ws, Lo.xin[Lo.L]), D, st),
                      "init launch")) != AKF_OK)
     return s;
   if ((s = hip_check(launch_adj_build_any(D, M, G, st), "adjoint build")) != AKF_OK) return s;

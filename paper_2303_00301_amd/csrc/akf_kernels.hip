@@ -43,10 +43,11 @@ __device__ __forceinline__ void flag_status(int* st, int bit) { atomicOr(st, bit
 // state entering the sampler's last block from the right to zero (it is
 // multiplied by E = 0 of the terminal step, but must be finite).
 // status points at the workspace's two status words (steps alternate between
-// them; the decision kernel of one step clears the next step's word).
+// them; the decision kernel of one step clears the next step's word), or is
+// null to leave them as they are.
 __global__ void k_step_init(int* status, double* root_flag, double* root_xin, int D) {
   const int tid = threadIdx.x;
-  if (tid < 2) status[tid] = 0;
+  if (status && tid < 2) status[tid] = 0;
   if (tid == 0 && root_flag) *root_flag = 1.0;
   if (root_xin && tid < D) root_xin[tid] = 0.0;
 }

@@ -284,6 +284,12 @@ KModel to_kmodel(const akf_model* m) {
   return M;
 }
 
+void lgssm_layout(Layout& Lo, const akf_lgssm* m, int block) {
+  // team size follows max(dx, dy): the observation block is padded to the same D
+  make_layout(Lo, m->N, m->dx > m->dy ? m->dx : m->dy, m->dy, block, LAYOUT_LGSSM);
+  Lo.d = m->dx;
+}
+
 akf_status prepare_device() {
   static std::once_flag once;
   static hipError_t err = hipSuccess;

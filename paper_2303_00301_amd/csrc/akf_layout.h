@@ -64,6 +64,9 @@ int pick_D(int d);
 int auto_block(int N, int D, bool general_obs);
 void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn = false,
                  bool fixed = false);
+// workspace layout of akf_lgssm_loglik / akf_lgssm_loglik_grad (filtering
+// moments at Lo.mf, Lo.Pf with leading dimension Lo.D)
+void lgssm_layout(Layout& Lo, const akf_lgssm* m, int block);
 akf_status check_model(const akf_model* m, bool need_emission);
 akf_status check_order(const akf_model* m, int order);
 akf_status check_linear(const akf_model* m, const char* what);

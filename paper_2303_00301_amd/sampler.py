@@ -453,6 +453,97 @@ class KalmanLogLik(torch.autograd.Function):
         return dF, dq, dH, dr, None, None
 
 
+class GibbsState:
+    """State of a Gibbs sampler over (theta, x) of an LGSSM (akf_gibbs_*):
+    theta [p] (flat F, logq, H, logr), its log posterior and gradient, the
+    path x [N,dx] and the library's per-theta state buffer.  All device
+    tensors, updated in place by gibbs_sweep."""
+
+    def __init__(self, model: "LGSSM", theta, logpost, grad, x, state, ws, prior_sd, block):
+        self.model, self.theta, self.logpost, self.grad, self.x = model, theta, logpost, grad, x
+        self.state, self.ws, self.prior_sd, self.block = state, ws, float(prior_sd), int(block)
+        self.status = torch.zeros(2, dtype=torch.int32, device=model.device)
+
+
+def n_theta(dx: int, dy: int) -> int:
+    return dx * dx + dx + dy * dx + dy
+
+
+def _lgssm_shape(model: "LGSSM") -> _lib.AkfLgssm:
+    s = _lib.AkfLgssm()
+    s.N, s.dx, s.dy = model.N, model.dx, model.dy
+    s.m0, s.P0, s.y = model.m0.data_ptr(), model.P0.data_ptr(), model.y.data_ptr()
+    return s
+
+
+def gibbs_init(model: "LGSSM", theta, x, prior_sd: float = 10.0, block: int = 0) -> GibbsState:
+    """Starts a Gibbs sampler at theta [p] (copied) and path x [N,dx] (copied):
+    log posterior, gradient and the per-theta state (akf_gibbs_init)."""
+    lib = _lib.load()
+    dev = model.device
+    p = n_theta(model.dx, model.dy)
+    _check_f64("theta", theta, (p,))
+    _check_f64("x", x, (model.N, model.dx))
+    s = _lgssm_shape(model)
+    nst = _need(lib.akf_gibbs_state_bytes(C.byref(s)), "akf_gibbs_state_bytes")
+    nws = _need(lib.akf_gibbs_workspace_bytes(C.byref(s), int(block)), "akf_gibbs_workspace_bytes")
+    state, ws = Workspace(dev), Workspace(dev)
+    stp, stb = state.ptr_bytes(nst)
+    wsp, wsb = ws.ptr_bytes(nws)
+    G = GibbsState(model, theta.clone(), torch.empty(1, dtype=torch.float64, device=dev),
+                   torch.empty(p, dtype=torch.float64, device=dev), x.clone(), state, ws,
+                   prior_sd, block)
+    rc = lib.akf_gibbs_init(C.byref(s), _ptr(G.theta), float(prior_sd), _ptr(G.logpost),
+                            _ptr(G.grad), stp, stb, _ptr(G.status), wsp, wsb, int(block),
+                            _stream(dev))
+    _lib.check(rc, "akf_gibbs_init")
+    return G
+
+
+def gibbs_sweep(G: GibbsState, eps: float, xi_theta, u_theta, xi_x, delta: float = 1.0,
+                xi_path=None, u_path=None, outputs: bool = True) -> dict:
+    """One sweep (akf_gibbs_sweep): MALA on theta, exact refresh of x, then
+    len(u_path) auxiliary Kalman path steps.  xi_theta [p], u_theta [1],
+    xi_x [N,dx], xi_path [k,2,N,dx], u_path [k] (device tensors; k may be 0).
+    Updates G in place; returns device tensors accepted_theta, log_alpha,
+    path_log_ratio, path_accepted, path_status and status [2]."""
+    lib = _lib.load()
+    model = G.model
+    dev = model.device
+    N, dx = model.N, model.dx
+    p = G.theta.numel()
+    _check_f64("xi_theta", xi_theta, (p,))
+    _check_f64("u_theta", u_theta, (1,))
+    _check_f64("xi_x", xi_x, (N, dx))
+    k = 0 if u_path is None else int(u_path.shape[0])
+    if k:
+        _check_f64("xi_path", xi_path, (k, 2, N, dx))
+        _check_f64("u_path", u_path, (k,))
+    out = {}
+    if outputs:
+        out = dict(accepted_theta=torch.empty(1, dtype=torch.int32, device=dev),
+                   log_alpha=torch.empty(1, dtype=torch.float64, device=dev),
+                   path_log_ratio=torch.empty(k, dtype=torch.float64, device=dev),
+                   path_accepted=torch.empty(k, dtype=torch.int32, device=dev),
+                   path_status=torch.empty(k, dtype=torch.int32, device=dev))
+    s = _lgssm_shape(model)
+    nst = _need(lib.akf_gibbs_state_bytes(C.byref(s)), "akf_gibbs_state_bytes")
+    nws = _need(lib.akf_gibbs_workspace_bytes(C.byref(s), G.block), "akf_gibbs_workspace_bytes")
+    stp, stb = G.state.ptr_bytes(nst)
+    wsp, wsb = G.ws.ptr_bytes(nws)
+    o = [_ptr(out.get(n)) if k or not n.startswith("path") else None
+         for n in ("accepted_theta", "log_alpha", "path_log_ratio", "path_accepted",
+                   "path_status")]
+    rc = lib.akf_gibbs_sweep(C.byref(s), _ptr(G.theta), _ptr(G.logpost), _ptr(G.grad),
+                             _ptr(G.x), stp, stb, G.prior_sd, float(eps), _ptr(xi_theta),
+                             _ptr(u_theta), _ptr(xi_x), float(delta), k,
+                             _ptr(xi_path) if k else None, _ptr(u_path) if k else None, *o,
+                             _ptr(G.status), wsp, wsb, G.block, _stream(dev))
+    _lib.check(rc, "akf_gibbs_sweep")
+    out["status"] = G.status
+    return out
+
+
 class BatchPlan:
     """Many independent chains advanced together by batched persistent kernels
     (include/akf.h, akf_batch_*).  `chains` is a list of dicts with keys model

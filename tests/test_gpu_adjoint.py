@@ -147,3 +147,24 @@ def test_autograd_function(S):
     assert abs(ll.item() - ll_ref) < 1e-9 * abs(ll_ref)
     for p, ref in zip(params, (dF, dq, dH, dr)):
         assert _rel(N_(p.grad), 2.5 * ref) < GRAD_TOL
+
+
+def test_failed_forward_pass_gives_nan_loglik_and_gradient(S):
+    """P0 = -I with R = 1e-6 I: the first innovation covariance H P0 H' + R is
+    negative definite, the forward filter flags it, the log-likelihood is NaN
+    and the adjoint, which keeps the forward's status bits, returns NaN for
+    every gradient entry (the oracle fails too)."""
+    pw = W.lgssm_params(N=40, dx=3, dy=2, seed=12)
+    t0 = pw.theta0
+    t0 = type(t0)(t0.F, t0.logq, t0.H, np.full(2, np.log(1e-6)))
+    P0 = -np.eye(3)
+    assert np.isnan(oracle.lgssm_loglik(pw.m0, P0, t0.F, t0.logq, t0.H, t0.logr, pw.y))
+    model = S.LGSSM(pw.m0, P0, pw.y, device=dev())
+    th = _theta_dev(t0)
+    ll, _, st, ws = S.lgssm_loglik(model, *th)
+    g = S.lgssm_loglik_grad(model, *th, ws)
+    torch.cuda.synchronize()
+    assert int(N_(st)[0]) != 0 and int(N_(g[4])[0]) != 0
+    assert np.isnan(float(N_(ll)[0]))
+    for got in g[:4]:
+        assert np.all(np.isnan(N_(got)))
