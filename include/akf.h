@@ -168,6 +168,29 @@ akf_status akf_mh_run(const akf_model* model, const double* y, double* x, double
                       int32_t* status, void* ws, size_t ws_bytes, int32_t block, void* stream);
 
 /*
+ * akf_mh_step without a workspace, for callers that cannot allocate device
+ * memory (work under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Arguments and outputs are akf_mh_step's; the scratch memory is a
+ * fixed array of AKF_NOALLOC_SCRATCH_BYTES bytes inside the library, one per
+ * device (each device holds it until the process ends).  The call allocates
+ * and frees nothing.
+ *   - Limit: a problem whose akf_mh_workspace_bytes(model, order, block)
+ *     exceeds AKF_NOALLOC_SCRATCH_BYTES returns AKF_ERR_SHAPE (64 MiB covers,
+ *     e.g., dx = 8 at N = 1024, dx = 30 at N = 250, dx = 64 at N = 96).
+ *   - Every call on one device shares that device's array: calls that may
+ *     overlap on one device (other streams, other host threads) race; order
+ *     them on one stream.  The array keeps the last call's contents; the step
+ *     initialises everything it reads, so no clearing is needed between calls.
+ *   - `stream` must belong to the current device (AKF_ERR_INVALID otherwise).
+ */
+#define AKF_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+akf_status akf_mh_step_noalloc(const akf_model* model, const double* y, const double* x_in,
+                               double delta, int32_t order, const double* xi, const double* unif,
+                               double* x_out, double* log_ratio, int32_t* accepted,
+                               double* logZ_fwd, double* logZ_rev, int32_t* status, int32_t block,
+                               void* stream);
+
+/*
  * n_steps first-order MH steps (Sec. "Auxiliary Kalman sampler", eq.
  * gaussian-FK-proposal, order fixed at 1) on one chain, with the auxiliary
  * model's matrices formed once per call.  Under order 1, Omega_t = delta/2 I

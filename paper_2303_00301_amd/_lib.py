@@ -11,6 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libauxkf.so")
 
 AKF_OK = 0
+NOALLOC_SCRATCH_BYTES = 64 << 20  # AKF_NOALLOC_SCRATCH_BYTES
 ERR_NAMES = {1: "AKF_ERR_INVALID", 2: "AKF_ERR_SHAPE", 3: "AKF_ERR_WORKSPACE", 4: "AKF_ERR_HIP",
              5: "AKF_ERR_UNSUPPORTED"}
 
@@ -66,6 +67,8 @@ SIGNATURES = {
                               _vp, _sz, _i32, _vp]),
     "akf_mh_run": (C.c_int, [_MP, _vp, _vp, _d, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                              _vp, _sz, _i32, _vp]),
+    "akf_mh_step_noalloc": (C.c_int, [_MP, _vp, _vp, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
+                                      _vp, _vp, _i32, _vp]),
     "akf_mh_first_order_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_mh_run_first_order": (C.c_int, [_MP, _vp, _vp, _d, _i32, _vp, _vp, _vp, _vp, _vp, _vp,
                                          _vp, _vp, _sz, _i32, _vp]),

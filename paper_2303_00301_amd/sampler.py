@@ -223,6 +223,33 @@ def mh_step(model: DeviceModel, y, x, delta: float, order: int, xi, unif, x_out=
     return dict(x_out=x_out, log_ratio=lr, accepted=acc, logZ_fwd=lzf, logZ_rev=lzr, status=st)
 
 
+def mh_step_noalloc(model: DeviceModel, y, x, delta: float, order: int, xi, unif, x_out,
+                    log_ratio, accepted, logZ_fwd, logZ_rev, status, block: int = 0) -> None:
+    """akf_mh_step_noalloc: mh_step with the library's fixed scratch array in
+    place of a workspace.  Every output is a caller tensor (x_out [N,dx]
+    float64; log_ratio, logZ_fwd, logZ_rev [1] float64; accepted, status [1]
+    int32), so this call allocates nothing on the device."""
+    lib = _lib.load()
+    _check_form(model, False)
+    N, dx = model.N, model.dx
+    _check_f64("y", y, (N, model.dy))
+    _check_f64("x", x, (N, dx))
+    _check_f64("xi", xi, (2, N, dx))
+    _check_f64("unif", unif, (1,))
+    _check_f64("x_out", x_out, (N, dx))
+    for name, t in (("log_ratio", log_ratio), ("logZ_fwd", logZ_fwd), ("logZ_rev", logZ_rev)):
+        _check_f64(name, t, (1,))
+    for name, t in (("accepted", accepted), ("status", status)):
+        if t.dtype != torch.int32 or tuple(t.shape) != (1,) or t.device != model.device:
+            raise _lib.AkfError(f"{name} must be an int32 tensor of shape (1,) on {model.device}")
+    ms = model.cstruct()
+    rc = lib.akf_mh_step_noalloc(C.byref(ms), _ptr(y), _ptr(x), float(delta), int(order),
+                                 _ptr(xi), _ptr(unif), _ptr(x_out), _ptr(log_ratio),
+                                 _ptr(accepted), _ptr(logZ_fwd), _ptr(logZ_rev), _ptr(status),
+                                 int(block), _stream(model.device))
+    _lib.check(rc, "akf_mh_step_noalloc")
+
+
 def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: int = 0,
            ws: Optional[Workspace] = None, outputs: bool = True, factorised: bool = False,
            reuse_matrices: bool = False) -> dict:

@@ -65,6 +65,24 @@ def test_mh_step_rejects_bad_model(field, value, code):
     assert lib.akf_last_error()
 
 
+def test_mh_step_noalloc_rejects_problems_beyond_its_array():
+    """The no-allocation step refuses, before any device call, a problem whose
+    workspace exceeds the library's fixed scratch array."""
+    lib = _lib.load()
+    hdr = open(os.path.join(ROOT, "include", "akf.h")).read()
+    mib = re.search(r"#define AKF_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << 20\)", hdr)
+    assert mib and int(mib.group(1)) << 20 == _lib.NOALLOC_SCRATCH_BYTES
+    m = _fake_model(N=4096, dx=64, dy=32)
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) > _lib.NOALLOC_SCRATCH_BYTES
+    p = C.c_void_p(0x2000)
+    rc = lib.akf_mh_step_noalloc(C.byref(m), p, p, 0.5, 2, p, p, p, None, None, None, None,
+                                 None, 0, None)
+    assert rc == 2
+    assert b"scratch" in lib.akf_last_error()
+    small = _fake_model(N=1024, dx=8, dy=8)
+    assert 0 < lib.akf_mh_workspace_bytes(C.byref(small), 2, 0) <= _lib.NOALLOC_SCRATCH_BYTES
+
+
 def test_mh_step_rejects_bad_arguments():
     lib = _lib.load()
     m = _fake_model()
