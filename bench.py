@@ -549,6 +549,7 @@ def bench_stoch_vol(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
                                         fold_flops_per_launch(w.N, w.dx, B), avg,
                                         PEAK_FP64_TFLOPS, "TFLOP/s", 1e12)}
         if cpu_steps > 0:
+            progress("cpu_baseline ...")
             res["cpu_baseline"] = cpu_baseline(w, cpu_steps, order=order)
         out[f"order{order}"] = res
     return out
@@ -939,6 +940,11 @@ def sampler_cpu_baseline(w, mf_dev, Pf_dev, dnc_steps: int = 512) -> dict:
                                    **host_info()}}
 
 
+def progress(msg: str) -> None:
+    """One line on stderr as each bench object starts, so a long run shows it is alive."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -1045,6 +1051,7 @@ def main() -> int:
                 "avg_launch_ms": avg_ms, "launches": n_l.value,
                 "flops_per_launch": flops}
 
+    progress(f"headline: {steps_s:.1f} steps/s")
     res = {
         "metric": METRIC,
         "value": steps_s,
@@ -1070,33 +1077,44 @@ def main() -> int:
         "roofline": roof,
     }
     if not args.no_batched:
+        progress("batched ...")
         res["batched"] = bench_batched(torch, S, W, _lib, args.batched_steps, dev,
                                        not args.no_cpu_baseline)
     if not args.no_adjoint:
+        progress("adjoint ...")
         res["adjoint"] = bench_adjoint(torch, S, W, _lib, 5, dev, not args.no_cpu_baseline)
     if not args.no_gibbs:
+        progress("gibbs ...")
         res["gibbs"] = bench_gibbs(torch, S, W, _lib, args.gibbs_sweeps, dev,
                                    not args.no_cpu_baseline)
     if not args.no_stoch_vol:
+        progress("stoch_vol ...")
         res["stoch_vol"] = bench_stoch_vol(torch, S, W, _lib, 20, dev,
                                            0 if args.no_cpu_baseline else 20)
     if not args.no_spatio_temporal:
+        progress("spatio_temporal ...")
         res["spatio_temporal"] = bench_spatio_temporal(
             torch, S, W, _lib, 100, dev, 0 if args.no_cpu_baseline else 100)
     if not args.no_samplers:
+        progress("samplers ...")
         res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev, not args.no_cpu_baseline)
     if not args.no_poisson:
+        progress("poisson ...")
         res["poisson"] = bench_poisson(torch, S, W, _lib, 50, dev,
                                        0 if args.no_cpu_baseline else 20)
     if not args.no_first_order:
+        progress("first_order ...")
         res["first_order"] = bench_first_order(torch, S, W, _lib, 50, dev,
                                                0 if args.no_cpu_baseline else 1)
     if not args.no_reuse:
+        progress("reuse_order2 ...")
         res["reuse_order2"] = bench_reuse(torch, S, W, _lib, 30, dev)
     if not args.no_lorenz:
+        progress("nonlinear ...")
         res["nonlinear"] = bench_lorenz(torch, S, W, _lib, 20, dev,
                                         0 if args.no_cpu_baseline else 10)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
+        progress("cpu_baseline ...")
         res["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
         if "reuse_order2" in res:
             # the oracle's plain order-2 step is the same computation on the same workload
