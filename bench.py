@@ -555,6 +555,54 @@ def bench_stoch_vol(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
     return out
 
 
+def bench_obs_linearisation(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
+    """Order 3 on the quadratic-observation field (d_x = 64, T = 4096, 32 sites,
+    y = z + 0.2 z^2 + N(0, 0.25)): the proposal takes the Gaussian fitted to the
+    observation model around the path in place of log h's own derivatives.
+    One chain; the linearisation changes only the elementwise kernels, so the
+    step costs what the Student-t field's order-2 step costs.  Roofline of the
+    filter fold; the oracle's order-3 step timed beside it."""
+    lib = _lib.load()
+    w = W.quadratic_obs_field()
+    M = S.DeviceModel.from_workload(w, device=dev)
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+    x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(109)
+    xi = torch.randn((K + 2, 2, w.N, w.dx), dtype=torch.float64, device=dev, generator=gen)
+    un = torch.rand((K + 2,), dtype=torch.float64, device=dev, generator=gen).clamp_(min=1e-300)
+    ws = S.Workspace(dev)
+    S.mh_run(M, y, x, w.delta, 3, xi[:2], un[:2], ws=ws)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    box = {}
+
+    def run():
+        e0.record()
+        box["r"] = S.mh_run(M, y, x, w.delta, 3, xi[2:], un[2:], ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+
+    avg, _ = timed_launches(lib, _lib, "filter_fold", 4 * K + 8, run)
+    r = box["r"]
+    ms = e0.elapsed_time(e1) / K
+    B = auto_block(w.N, w.dx)
+    res = {"workload": f"quadratic_obs_field_d{w.dx}_T{w.N}: latent-field dynamics, "
+                       f"y = z + {w.obs_beta} z^2 + N(0, {w.scale}^2) at 32 sites, order 3 "
+                       f"(reference variance {w.slr_var}), one chain",
+           "delta": w.delta, "steps": K, "ms_per_step": ms, "steps_per_s": 1000.0 / ms,
+           "time_steps_per_s": 1000.0 / ms * w.N,
+           "acceptance": r["accepted"].float().mean().item(),
+           "rejected_by_status": int((r["status"] != 0).sum().item()),
+           "roofline": roofline_obj("mfma", "k_filter_fold<64>",
+                                    fold_flops_per_launch(w.N, w.dx, B), avg,
+                                    PEAK_FP64_TFLOPS, "TFLOP/s", 1e12)}
+    if cpu_steps > 0:
+        progress("cpu_baseline ...")
+        res["cpu_baseline"] = cpu_baseline(w, cpu_steps, order=3)
+    return res
+
+
 def bench_poisson(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dict:
     """Poisson AR(1) workload (d_x = 8, T = 1024, delta 0.2, order 2, one chain):
     at this size one step moves well under a megabyte and runs a few dozen
@@ -967,6 +1015,7 @@ def main() -> int:
     ap.add_argument("--no-samplers", action="store_true")
     ap.add_argument("--no-first-order", action="store_true")
     ap.add_argument("--no-poisson", action="store_true")
+    ap.add_argument("--no-obs-lin", action="store_true")
     ap.add_argument("--no-reuse", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
@@ -1098,6 +1147,10 @@ def main() -> int:
     if not args.no_samplers:
         progress("samplers ...")
         res["samplers"] = bench_samplers(torch, S, W, _lib, 5, dev, not args.no_cpu_baseline)
+    if not args.no_obs_lin:
+        progress("obs_linearisation ...")
+        res["obs_linearisation"] = bench_obs_linearisation(
+            torch, S, W, _lib, 20, dev, 0 if args.no_cpu_baseline else 1)
     if not args.no_poisson:
         progress("poisson ...")
         res["poisson"] = bench_poisson(torch, S, W, _lib, 50, dev,

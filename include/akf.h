@@ -56,7 +56,9 @@ typedef enum {
   AKF_EMIT_MVT = 4,         /* y_t = x_t[site] + V_t, V_t multivariate t with nu degrees of
                                freedom and precision R [dy,dy] (Sec. "Spatio-temporal model");
                                first-order proposals only */
-  AKF_EMIT_GAUSS_SITE = 5   /* y_{t,k} = x_{t,site[k]} + N(0, scale^2) */
+  AKF_EMIT_GAUSS_SITE = 5,  /* y_{t,k} = x_{t,site[k]} + N(0, scale^2) */
+  AKF_EMIT_GAUSS_QUAD = 6   /* y_{t,k} = z + obs_beta z^2 + N(0, scale^2), z = x_{t,site[k]}
+                               (a nonlinear observation mean, for order 3) */
 } akf_emit;
 
 /* Dynamics families: x_t = F x_{t-1} + b + N(0, Q), or x_t = f(x_{t-1}) + N(0, Q)
@@ -94,11 +96,12 @@ enum {
 /*
  * Model description (eq. ssm with Gaussian dynamics).  m0 [dx], P0 [dx,dx],
  * F [dx,dx], b [dx] or NULL (zero), Q [dx,dx].  Emission per `emit`:
- * GAUSSIAN uses H, R; POISSON_LOG, STUDENT_T, STOCH_VOL, MVT and GAUSS_SITE use
- * site [dy] (int32, each in [0, dx); several sites may observe the same
- * coordinate); STUDENT_T also nu > 0 and scale > 0; GAUSS_SITE scale > 0; MVT
- * also the precision R [dy,dy] (symmetric positive definite) and nu > 0.  In
- * the site-wise families (POISSON_LOG, STUDENT_T, STOCH_VOL, GAUSS_SITE) a NaN
+ * GAUSSIAN uses H, R; POISSON_LOG, STUDENT_T, STOCH_VOL, MVT, GAUSS_SITE and
+ * GAUSS_QUAD use site [dy] (int32, each in [0, dx); several sites may observe
+ * the same coordinate); STUDENT_T also nu > 0 and scale > 0; GAUSS_SITE and
+ * GAUSS_QUAD scale > 0 (GAUSS_QUAD also obs_beta); MVT also the precision
+ * R [dy,dy] (symmetric positive definite) and nu > 0.  In the site-wise
+ * families (POISSON_LOG, STUDENT_T, STOCH_VOL, GAUSS_SITE, GAUSS_QUAD) a NaN
  * y_{t,k} marks an unobserved site.  All pointers are device pointers.
  * MVT with order 2 is rejected with AKF_ERR_UNSUPPORTED (its Hessian would
  * make Omega_t dense and time-varying).
@@ -125,6 +128,9 @@ typedef struct akf_model {
   int32_t dyn;
   double dyn_par[4];
   int32_t dtype;
+  double obs_beta; /* GAUSS_QUAD: coefficient of the quadratic term of the observation mean */
+  double slr_var;  /* order 3: reference variance gamma^2 >= 0 of the observation-model
+                      linearisation (0 = the Taylor limit) */
 } akf_model;
 
 /* Description of the last synchronous error on this thread (static storage). */
@@ -142,7 +148,16 @@ size_t akf_mh_workspace_bytes(const akf_model* model, int32_t order, int32_t blo
  *   y      [N,dy]     observations
  *   x_in   [N,dx]     current path
  *   delta  > 0        auxiliary step size (u_t ~ N(x_t, delta/2 I))
- *   order  1 or 2     linearisation order of log h_t
+ *   order  1, 2 or 3  linearisation of log h_t: 1 and 2 take log h_t's own
+ *                     gradient (and Hessian) at the path (eq. gaussian-FK-proposal,
+ *                     eq. second-order); 3 replaces h_t by a Gaussian
+ *                     N(H_t z + c_t, R_t) fitted around the path by statistical
+ *                     linear regression with reference variable N(x_t, slr_var I)
+ *                     (eq. observation-approx, eq. coeffs, eq. general-GSLR-coeffs)
+ *                     and takes that Gaussian's gradient and Hessian
+ *                     (eq. two-lin-prop); order 3 needs GAUSS_SITE or GAUSS_QUAD
+ *                     (AKF_ERR_UNSUPPORTED otherwise) and slr_var >= 0.  The
+ *                     target keeps the true h_t in every order.
  *   xi     [2,N,dx]   standard normals: xi[0] for u, xi[1] for the path sample
  *   unif   [1]        uniform in (0,1) for the accept test (accept iff log unif < log r)
  *   x_out  [N,dx]     new path (x* if accepted, else x_in); may alias x_in

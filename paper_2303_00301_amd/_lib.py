@@ -30,6 +30,7 @@ class AkfModel(C.Structure):
         ("nu", C.c_double), ("scale", C.c_double),
         ("dyn", C.c_int32), ("dyn_par", C.c_double * 4),
         ("dtype", C.c_int32),
+        ("obs_beta", C.c_double), ("slr_var", C.c_double),
     ]
 
 

@@ -372,6 +372,8 @@ akf_status check_fact_model(const akf_model* model, int order) {
   if ((s = check_model(model, true)) != AKF_OK) return s;
   if ((s = check_linear(model, "the factorised step")) != AKF_OK) return s;
   if ((s = check_order(model, order)) != AKF_OK) return s;
+  if (order == 3)
+    return fail(AKF_ERR_UNSUPPORTED, "the factorised step takes orders 1 and 2");
   if (model->emit == AKF_EMIT_GAUSSIAN)
     return fail(AKF_ERR_UNSUPPORTED, "the factorised step needs a site-based emission family "
                                      "(its Gaussian emission has a dense H)");
@@ -837,6 +839,7 @@ akf_status check_reuse_model(const akf_model* model, int order) {
   if ((s = check_model(model, true)) != AKF_OK) return s;
   if ((s = check_linear(model, "akf_mh_run_reuse")) != AKF_OK) return s;
   if ((s = check_order(model, order)) != AKF_OK) return s;
+  if (order == 3) return fail(AKF_ERR_UNSUPPORTED, "akf_mh_run_reuse takes orders 1 and 2");
   if (order == 2 && model->emit == AKF_EMIT_GAUSSIAN)
     return fail(AKF_ERR_UNSUPPORTED, "akf_mh_run_reuse keeps diagonal-Omega matrices; the "
                                      "GAUSSIAN emission has a dense Omega under order 2");

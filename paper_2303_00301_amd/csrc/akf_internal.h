@@ -6,7 +6,7 @@
 namespace akf {
 
 enum { EMIT_GAUSSIAN = 0, EMIT_POISSON_LOG = 1, EMIT_STUDENT_T = 2, EMIT_STOCH_VOL = 3,
-       EMIT_MVT = 4, EMIT_GAUSS_SITE = 5 };
+       EMIT_MVT = 4, EMIT_GAUSS_SITE = 5, EMIT_GAUSS_QUAD = 6 };
 enum { DYN_LINEAR = 0, DYN_LORENZ63 = 1, DYN_LORENZ96 = 2 };
 enum { ST_FWD_NOT_PD = 1, ST_REV_NOT_PD = 2, ST_NONFINITE = 4 };
 
@@ -22,6 +22,7 @@ struct KModel {
   double nu, scale;
   int dyn;
   double dyn_par[4];
+  double obs_beta, slr_var;  // quadratic observation mean; order-3 reference variance
 };
 
 // Filter element (A, b, C, eta, J), padded to D, and lc = log c, the

@@ -63,6 +63,8 @@ __global__ void k_step_init(int* status, double* root_flag, double* root_xin, in
 // ---------------------------------------------------------------------------
 struct EmitOut {
   double lh, v, lam;
+  double ysum;  // sum of the latent's observed y_k (order 3)
+  int cnt;      // number of the latent's observed sites (order 3)
 };
 
 // One site's contribution to log h and its derivatives at x_i = xi.
@@ -77,6 +79,12 @@ __device__ __forceinline__ void emit_site(const KModel& M, double yk, double xi,
     o.lh += -0.5 * r * r / s2;
     o.v += r / s2;
     o.lam -= 1.0 / s2;
+  } else if (M.emit == EMIT_GAUSS_QUAD) {
+    const double s2 = M.scale * M.scale, dm = 1.0 + 2.0 * M.obs_beta * xi;
+    const double r = yk - xi - M.obs_beta * xi * xi;
+    o.lh += -0.5 * r * r / s2;
+    o.v += r * dm / s2;
+    o.lam += (2.0 * M.obs_beta * r - dm * dm) / s2;
   } else if (M.emit == EMIT_STOCH_VOL) {
     const double q = yk * yk * exp(-xi);  // y ~ N(0, exp(x))
     o.lh += -0.5 * xi - 0.5 * q;
@@ -99,7 +107,7 @@ __device__ __forceinline__ void emit_site(const KModel& M, double yk, double xi,
 // per site of the most-observed latent, plus one.
 __device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __restrict__ yt,
                                              double xi, int i) {
-  EmitOut o{0.0, 0.0, 0.0};
+  EmitOut o{0.0, 0.0, 0.0, 0.0, 0};
   int start = 0;
   for (int pass = 0; pass < M.dy; ++pass) {
     int kk = -1;
@@ -110,9 +118,33 @@ __device__ __forceinline__ EmitOut emit_diag(const KModel& M, const double* __re
     if (kk < 0) break;
     const double yk = yt[kk];
     start = kk + 1;
-    if (!isnan(yk)) emit_site(M, yk, xi, o);  // NaN: site not observed at t
+    if (!isnan(yk)) {  // NaN: site not observed at t
+      emit_site(M, yk, xi, o);
+      o.ysum += yk;
+      ++o.cnt;
+    }
   }
   return o;
+}
+
+// Order 3 (eq. two-lin-prop): v and Lambda become the gradient and Hessian at
+// z = x of log N(y; H z + c, R), the Gaussian fitted to h around x by
+// statistical linear regression with reference variable N(x, g2 I) (eq. coeffs
+// with the moments of eq. general-GSLR-coeffs).  For a latent x_i observed by
+// k sites with mean m(z) = z + beta z^2 and noise scale^2: each of those sites'
+// rows of H is h e_i with h = 1 + 2 beta x_i, the regression mean is
+// mu = x_i + beta (x_i^2 + g2), and R over those sites is scale^2 I + c 1 1'
+// with c = Var m(zeta) - h^2 g2 = 2 beta^2 g2^2 (moments of a quadratic of a
+// Gaussian), uncorrelated with other latents' sites.  So 1' R^{-1} =
+// 1' / (scale^2 + k c), and
+//   v_i = h (sum_k y_k - k mu) / (scale^2 + k c),  Lambda_ii = -h^2 k / (scale^2 + k c).
+// g2 = 0 is the Taylor limit (Gauss-Newton curvature).  log h stays the true one.
+__device__ __forceinline__ void slr_override(const KModel& M, double x, EmitOut& o) {
+  const double be = (M.emit == EMIT_GAUSS_QUAD) ? M.obs_beta : 0.0, g2 = M.slr_var;
+  const double h = 1.0 + 2.0 * be * x, mu = x + be * (x * x + g2);
+  const double den = M.scale * M.scale + o.cnt * (2.0 * be * be * g2 * g2);
+  o.v = h * (o.ysum - o.cnt * mu) / den;
+  o.lam = -h * h * o.cnt / den;
 }
 
 // Per-(t, i) tail of the forward linearisation: draws u and writes the
@@ -142,7 +174,8 @@ __device__ __forceinline__ void lin_fwd_diag_body(const KModel& M, const StepArg
   if (gid < n) {
     const int t = (int)(gid / M.d), i = (int)(gid % M.d);
     const double x = A.x[gid];
-    const EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, x, i);
+    EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, x, i);
+    if (A.order == 3) slr_override(M, x, e);
     lin_fwd_point(A, gid, x, e.v, (A.order == 1) ? 0.0 : e.lam);
     lh = e.lh;
   }
@@ -191,7 +224,8 @@ __device__ __forceinline__ void lin_rev_diag_body(const KModel& M, const StepArg
   if (gid < n) {
     const int t = (int)(gid / M.d), i = (int)(gid % M.d);
     const double xs = A.xs[gid];
-    const EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, xs, i);
+    EmitOut e = emit_diag(M, A.y + (int64_t)t * M.dy, xs, i);
+    if (A.order == 3) slr_override(M, xs, e);
     term = lin_rev_point(A, gid, xs, e.v, (A.order == 1) ? 0.0 : e.lam);
     lhs = e.lh;
   }

@@ -1,6 +1,7 @@
 // akf_layout.cpp -- host-side helpers shared by the C ABI translation units
 // (see akf_layout.h).
 #include <hip/hip_runtime.h>
+#include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -237,6 +238,12 @@ akf_status check_model(const akf_model* m, bool need_emission) {
       if (!m->site) return fail(AKF_ERR_INVALID, "Gaussian-at-sites emission needs site");
       if (!(m->scale > 0.0)) return fail(AKF_ERR_INVALID, "Gaussian-at-sites emission needs scale > 0");
       break;
+    case AKF_EMIT_GAUSS_QUAD:
+      if (!m->site) return fail(AKF_ERR_INVALID, "quadratic-mean Gaussian emission needs site");
+      if (!(m->scale > 0.0) || !isfinite(m->obs_beta))
+        return fail(AKF_ERR_INVALID,
+                    "quadratic-mean Gaussian emission needs scale > 0 and a finite obs_beta");
+      break;
     case AKF_EMIT_MVT:
       if (!m->site || !m->R) return fail(AKF_ERR_INVALID, "multivariate-t emission needs site and R");
       if (!(m->nu > 0.0)) return fail(AKF_ERR_INVALID, "multivariate-t emission needs nu > 0");
@@ -248,7 +255,14 @@ akf_status check_model(const akf_model* m, bool need_emission) {
 }
 
 akf_status check_order(const akf_model* m, int order) {
-  if (order != 1 && order != 2) return fail(AKF_ERR_INVALID, "order must be 1 or 2");
+  if (order < 1 || order > 3) return fail(AKF_ERR_INVALID, "order must be 1, 2 or 3");
+  if (order == 3) {
+    if (m->emit != AKF_EMIT_GAUSS_SITE && m->emit != AKF_EMIT_GAUSS_QUAD)
+      return fail(AKF_ERR_UNSUPPORTED, "order 3 (the observation model's linearisation) needs a "
+                                       "Gaussian-around-a-mean family: GAUSS_SITE or GAUSS_QUAD");
+    if (!(m->slr_var >= 0.0) || !isfinite(m->slr_var))
+      return fail(AKF_ERR_INVALID, "order 3 needs a finite reference variance slr_var >= 0");
+  }
   if (order == 2 && m->emit == AKF_EMIT_MVT)
     return fail(AKF_ERR_UNSUPPORTED,
                 "the multivariate-t emission supports first-order proposals only (its Hessian "
@@ -281,6 +295,8 @@ KModel to_kmodel(const akf_model* m) {
   M.scale = m->scale;
   M.dyn = m->dyn;
   for (int i = 0; i < 4; ++i) M.dyn_par[i] = m->dyn_par[i];
+  M.obs_beta = m->obs_beta;
+  M.slr_var = m->slr_var;
   return M;
 }
 

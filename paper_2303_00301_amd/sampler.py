@@ -15,7 +15,7 @@ import torch
 from . import _lib
 
 EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
-EMIT_GAUSS_SITE = 5
+EMIT_GAUSS_SITE, EMIT_GAUSS_QUAD = 5, 6
 DYN_LINEAR, DYN_LORENZ63, DYN_LORENZ96 = 0, 1, 2
 ST_FWD_NOT_PD, ST_REV_NOT_PD, ST_NONFINITE = 1, 2, 4
 
@@ -69,21 +69,26 @@ class DeviceModel:
     scale: float = 0.0
     dyn: int = DYN_LINEAR
     dyn_par: tuple = (0.0, 0.0, 0.0, 0.0)
+    obs_beta: float = 0.0
+    slr_var: float = 0.0
 
     @classmethod
     def from_arrays(cls, N, m0, P0, F, Q, emit, b=None, H=None, R=None, site=None, nu=0.0,
-                    scale=0.0, dyn=DYN_LINEAR, dyn_par=(0.0, 0.0, 0.0, 0.0), device=None):
+                    scale=0.0, dyn=DYN_LINEAR, dyn_par=(0.0, 0.0, 0.0, 0.0), obs_beta=0.0,
+                    slr_var=0.0, device=None):
         dev = _dev(device)
         return cls(N=int(N), m0=_t(m0, dev), P0=_t(P0, dev), F=_t(F, dev), Q=_t(Q, dev),
                    emit=int(emit), b=_t(b, dev), H=_t(H, dev), R=_t(R, dev),
                    site=_t(site, dev, torch.int32), nu=float(nu), scale=float(scale),
-                   dyn=int(dyn), dyn_par=tuple(float(v) for v in dyn_par))
+                   dyn=int(dyn), dyn_par=tuple(float(v) for v in dyn_par),
+                   obs_beta=float(obs_beta), slr_var=float(slr_var))
 
     @classmethod
     def from_workload(cls, w, device=None):
         return cls.from_arrays(w.N, w.m0, w.P0, w.F, w.Q, w.emit, b=w.b, H=w.H, R=w.R,
                                site=w.site, nu=w.nu, scale=w.scale, dyn=w.dyn,
-                               dyn_par=w.dyn_par, device=device)
+                               dyn_par=w.dyn_par, obs_beta=getattr(w, "obs_beta", 0.0),
+                               slr_var=getattr(w, "slr_var", 0.0), device=device)
 
     @property
     def dx(self) -> int:
@@ -116,7 +121,8 @@ class DeviceModel:
             out[k] = dg
         return DeviceModel(N=self.N, m0=self.m0, P0=out["P0"], F=out["F"], Q=out["Q"],
                            emit=self.emit, b=self.b, H=self.H, R=self.R, site=self.site,
-                           nu=self.nu, scale=self.scale)
+                           nu=self.nu, scale=self.scale, obs_beta=self.obs_beta,
+                           slr_var=self.slr_var)
 
     def cstruct(self) -> _lib.AkfModel:
         s = _lib.AkfModel()
@@ -133,6 +139,7 @@ class DeviceModel:
         par = list(self.dyn_par) + [0.0] * (4 - len(self.dyn_par))
         for i in range(4):
             s.dyn_par[i] = par[i]
+        s.obs_beta, s.slr_var = self.obs_beta, self.slr_var
         return s
 
 

@@ -12,7 +12,7 @@ Seeds: model/data from ``default_rng(data_seed)``, step normals from
 Emission codes match the C-ABI: 0 Gaussian (H, R), 1 Poisson with log link,
 2 Student-t at observation sites, 3 stochastic volatility (y ~ N(0, exp(x))),
 4 multivariate t with a precision matrix, 5 Gaussian at observation sites (NaN =
-not observed).  Dynamics: 0 linear (F, b), 1 Lorenz-63 and 2 Lorenz-96 Euler
+not observed), 6 Gaussian around a quadratic mean at observation sites.  Dynamics: 0 linear (F, b), 1 Lorenz-63 and 2 Lorenz-96 Euler
 steps.
 """
 from __future__ import annotations
@@ -23,7 +23,7 @@ from typing import List, Optional
 import numpy as np
 
 EMIT_GAUSSIAN, EMIT_POISSON_LOG, EMIT_STUDENT_T, EMIT_STOCH_VOL, EMIT_MVT = 0, 1, 2, 3, 4
-EMIT_GAUSS_SITE = 5
+EMIT_GAUSS_SITE, EMIT_GAUSS_QUAD = 5, 6
 DYN_LINEAR, DYN_LORENZ63, DYN_LORENZ96 = 0, 1, 2
 
 
@@ -52,6 +52,8 @@ class Workload:
     extra: dict = field(default_factory=dict)
     dyn: int = DYN_LINEAR
     dyn_par: tuple = (0.0, 0.0, 0.0, 0.0)
+    obs_beta: float = 0.0
+    slr_var: float = 0.0
 
     @property
     def dx(self) -> int:
@@ -79,7 +81,8 @@ class Workload:
     def oracle_kwargs(self) -> dict:
         return dict(m0=self.m0, P0=self.P0, F=self.F, Q=self.Q, emit=self.emit, b=self.b,
                     H=self.H, R=self.R, site=self.site, nu=self.nu, scale=self.scale,
-                    dyn=self.dyn, dyn_par=tuple(self.dyn_par))
+                    dyn=self.dyn, dyn_par=tuple(self.dyn_par), obs_beta=self.obs_beta,
+                    slr_var=self.slr_var)
 
 
 def _simulate(rng, N, m0, P0, F, Q, b=None):
@@ -164,6 +167,33 @@ def latent_field(N: int = 4096, d: int = 64, n_sites: int = 32, nu: float = 3.0,
     return Workload(f"latent_field_d{d}_N{N}", N, m0, P0, F, Q, EMIT_STUDENT_T, y, site=site,
                     nu=nu, scale=scale, delta=LATENT_FIELD_DELTA if delta is None else delta,
                     order=2, seed=seed, x_true=x)
+
+
+# Step size of the quadratic-observation field under order 3 (the latent field's
+# order-2 value; the proposal's curvature here comes from the fitted Gaussian).
+QUAD_FIELD_DELTA = 0.057
+
+
+def quadratic_obs_field(N: int = 4096, d: int = 64, n_sites: int = 32, beta: float = 0.2,
+                        scale: float = 0.5, slr_var: float = 0.05, seed: int = 9,
+                        delta: Optional[float] = None, repeat_sites: int = 0) -> Workload:
+    """The latent field's dynamics (periodic_grid_F_Q) observed through a
+    nonlinear mean: y_{t,k} = z + beta z^2 + N(0, scale^2), z = x_t[site[k]], at
+    n_sites evenly spaced sites, the first `repeat_sites` of them observed by a
+    second site as well.  Sampled with order 3: the observation model is
+    replaced, around the path, by the Gaussian of the statistical linear
+    regression with reference variance slr_var."""
+    rng = np.random.default_rng(seed)
+    m0, P0 = np.zeros(d), np.eye(d)
+    F, Q = periodic_grid_F_Q(d)
+    x = _simulate(rng, N, m0, P0, F, Q)
+    base = (np.arange(n_sites) * (d // n_sites)).astype(np.int32)
+    site = np.concatenate([base, base[:repeat_sites]]).astype(np.int32)
+    z = x[:, site]
+    y = z + beta * z * z + scale * rng.standard_normal(z.shape)
+    return Workload(f"quadratic_obs_field_d{d}_N{N}", N, m0, P0, F, Q, EMIT_GAUSS_QUAD, y,
+                    site=site, scale=scale, delta=QUAD_FIELD_DELTA if delta is None else delta,
+                    order=3, seed=seed, x_true=x, obs_beta=beta, slr_var=slr_var)
 
 
 # Step sizes of the stochastic-volatility workload (d = 30, T = 250, seed 6) toward

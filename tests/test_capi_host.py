@@ -65,6 +65,37 @@ def test_mh_step_rejects_bad_model(field, value, code):
     assert lib.akf_last_error()
 
 
+def test_order3_validation():
+    """Order 3 (the observation model's linearisation) is accepted for the
+    Gaussian-around-a-mean families only, with a finite reference variance >= 0,
+    and only by the plain step and run; the quadratic family needs a finite
+    obs_beta and scale > 0."""
+    lib = _lib.load()
+    q = _fake_model(emit=6)
+    q.scale, q.obs_beta, q.slr_var = 0.5, 0.3, 0.1
+    assert lib.akf_mh_workspace_bytes(C.byref(q), 3, 0) > 0
+    assert lib.akf_mh_workspace_bytes(C.byref(q), 2, 0) > 0
+    g = _fake_model(emit=5)
+    assert lib.akf_mh_workspace_bytes(C.byref(g), 3, 0) > 0
+    for emit in (0, 1, 2, 3, 4):
+        assert lib.akf_mh_workspace_bytes(C.byref(_fake_model(emit=emit)), 3, 0) == 0
+    p = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x10000)
+    step = lambda m, order=3: lib.akf_mh_step(C.byref(m), p, p, 0.5, order, p, p, p, None, None,
+                                              None, None, None, ws, 1 << 30, 0, None)
+    q.slr_var = -0.1
+    assert step(q) == 1
+    q.slr_var = float("inf")
+    assert step(q) == 1
+    q.slr_var, q.obs_beta = 0.1, float("nan")
+    assert step(q) == 1
+    q.obs_beta, q.scale = 0.3, 0.0
+    assert step(q) == 1
+    q.scale = 0.5
+    assert lib.akf_mh_reuse_workspace_bytes(C.byref(q), 3, 0) == 0
+    assert lib.akf_mh_factorised_workspace_bytes(C.byref(q), 3) == 0
+
+
 def test_mh_step_noalloc_rejects_problems_beyond_its_array():
     """The no-allocation step refuses, before any device call, a problem whose
     workspace exceeds the library's fixed scratch array."""
@@ -94,7 +125,8 @@ def test_mh_step_rejects_bad_arguments():
         None)
     assert call(delta=0.0) == 1
     assert call(delta=float("nan")) == 1
-    assert call(order=3) == 1
+    assert call(order=4) == 1
+    assert call(order=3) == 5    # order 3 needs GAUSS_SITE or GAUSS_QUAD (this model is Poisson)
     assert call(y=None) == 1
     assert call(block=-1) == 1
     assert call(ws=C.c_void_p(0x10001)) == 3   # misaligned
