@@ -151,6 +151,122 @@ def path_combine(ei, ej):
     return (Ei @ Ej, Ei @ Uj + Ui)
 
 
+# ---------------------------------------------------------------------------
+# Square-root form (the filter the paper points to for FP32 robustness in its
+# stochastic-volatility section).  Covariances are carried as factors: the
+# filtering element holds U with C = U U^T and Z with J = Z Z^T, and every
+# covariance update is a triangularisation.  All functions take a dtype so that
+# tests can run them in float32; the default is float64.
+#
+# tria(M), M [r, c] with c >= r: the lower-triangular L [r, r] with
+# non-negative diagonal and L L^T = M M^T (from a QR factorisation of M^T).
+#
+# Element of step t >= 1 for the pseudo-observation omega_t = x_t + N(0, Om_t)
+# (H = I, diagonal Om_t), from the block triangularisation
+#     tria([[Om^{1/2}, L_Q], [0, L_Q]]) = [[P11, 0], [P21, P22]]:
+# P11 P11^T = S = Q + Om, P21 = Q P11^{-T}, P22 P22^T = Q - Q S^{-1} Q = C, so
+#     K = P21 P11^{-1},  A = F - K F,  b = b_dyn + K w,  U = P22,
+#     Z = F^T P11^{-T},  eta = Z P11^{-1} w,  w = omega_t - b_dyn,
+#     log c = -1/2 (d log 2 pi + 2 sum log diag P11 + |P11^{-1} w|^2);
+# step 0 uses the prior factor L_0 in place of L_Q, m0 in place of b_dyn, and
+# has A = 0, Z = 0, eta = 0.
+#
+# Combine (i earlier, j later), from
+#     tria([[U_i^T Z_j, I], [Z_j, 0]]) = [[X11, 0], [X21, X22]]:
+# X11 X11^T = W = I + U_i^T J_j U_i, X21 = J_j U_i X11^{-T},
+# X22 X22^T = J_j (I + C_i J_j)^{-1}.  With G = U_i X11^{-T} and
+# M = I - G X21^T = (I + C_i J_j)^{-1} (Woodbury):
+#     A = A_j M A_i,  b = A_j M (b_i + C_i eta_j) + b_j,
+#     U = tria([A_j G, U_j])           (C_i - C_i J_j M C_i = G G^T),
+#     eta = A_i^T M^T c + eta_i,  c = eta_j - J_j b_i,
+#     Z = tria([A_i^T X22, Z_i]),
+#     log c = log c_i + log c_j - sum log diag X11 + 1/2 b_i^T (eta_j + c)
+#             + 1/2 |X11^{-1} U_i^T c|^2.
+#
+# Sampling element from tria([[L_Q, F U^f_t], [0, U^f_t]]) = [[P11, 0],
+# [P21, P22]]: P11 P11^T = P^p_{t+1}, E_t = P21 P11^{-1}, chol(L_t) = P22,
+# g_t = m^f_t - E_t (F m^f_t + b_dyn).
+# ---------------------------------------------------------------------------
+def tria(M, dtype=np.float64):
+    M = np.asarray(M, dtype)
+    R = np.linalg.qr(M.T, mode="r")
+    L = R.T[:, :M.shape[0]]
+    s = np.where(np.diag(L) < 0, -1, 1).astype(dtype)
+    return L * s
+
+
+def _lower_solve(L, B):
+    """L^{-1} B for lower-triangular L (B a vector or matrix)."""
+    return np.linalg.solve(L, B)
+
+
+def _right_solve(B, L):
+    """B L^{-1} for lower-triangular L."""
+    return np.linalg.solve(L.T, B.T).T
+
+
+def sqrt_filter_elements(m0, P0, F, b, Q, om, Om, dtype=np.float64):
+    """Square-root elements (A, b, U, eta, Z, log c) for t = 0..N-1; Om [N, d] holds
+    the diagonal pseudo-observation variances."""
+    N, d = om.shape
+    F = np.asarray(F, dtype)
+    b = np.zeros(d, dtype) if b is None else np.asarray(b, dtype)
+    LQ = np.linalg.cholesky(np.asarray(Q, np.float64)).astype(dtype)
+    L0 = np.linalg.cholesky(np.asarray(P0, np.float64)).astype(dtype)
+    Zd = np.zeros((d, d), dtype)
+    out = []
+    for t in range(N):
+        Ls, mu = (L0, np.asarray(m0, dtype)) if t == 0 else (LQ, b)
+        Psi = tria(np.block([[np.diag(np.sqrt(Om[t])).astype(dtype), Ls], [Zd, Ls]]), dtype)
+        P11, P21, P22 = Psi[:d, :d], Psi[d:, :d], Psi[d:, d:]
+        K = _right_solve(P21, P11)
+        w = np.asarray(om[t], dtype) - mu
+        s = _lower_solve(P11, w)
+        lc = -0.5 * (d * np.log(2 * np.pi) + 2 * np.sum(np.log(np.diag(P11).astype(np.float64)))
+                     + float(s @ s))
+        if t == 0:
+            el = (Zd.copy(), mu + K @ w, P22, np.zeros(d, dtype), Zd.copy())
+        else:
+            Z = _lower_solve(P11, F).T
+            el = (F - K @ F, mu + K @ w, P22, Z @ s, Z)
+        out.append(el + (lc,))
+    return out
+
+
+def sqrt_filter_combine(ei, ej, dtype=np.float64):
+    Ai, bi, Ui, eti, Zi, lci = ei
+    Aj, bj, Uj, etj, Zj, lcj = ej
+    d = Ai.shape[0]
+    I = np.eye(d, dtype=dtype)
+    X = tria(np.block([[Ui.T @ Zj, I], [Zj, np.zeros((d, d), dtype)]]), dtype)
+    X11, X21, X22 = X[:d, :d], X[d:, :d], X[d:, d:]
+    G = _lower_solve(X11, Ui.T).T
+    Mm = I - G @ X21.T
+    c = etj - Zj @ (Zj.T @ bi)
+    h = _lower_solve(X11, Ui.T @ c)
+    lc = (lci + lcj - np.sum(np.log(np.diag(X11).astype(np.float64)))
+          + 0.5 * float(bi @ (etj + c)) + 0.5 * float(h @ h))
+    return (Aj @ Mm @ Ai, Aj @ (Mm @ (bi + Ui @ (Ui.T @ etj))) + bj,
+            tria(np.hstack([Aj @ G, Uj]), dtype), Ai.T @ (Mm.T @ c) + eti,
+            tria(np.hstack([Ai.T @ X22, Zi]), dtype), lc)
+
+
+def sqrt_sampling_elements(F, b, Q, mf, Uf, dtype=np.float64):
+    """(E, g, chol L) for t = 0..N-1 from filtering means and factors U^f_t."""
+    N, d = mf.shape
+    F = np.asarray(F, dtype)
+    b = np.zeros(d, dtype) if b is None else np.asarray(b, dtype)
+    LQ = np.linalg.cholesky(np.asarray(Q, np.float64)).astype(dtype)
+    out = []
+    for t in range(N - 1):
+        Psi = tria(np.block([[LQ, F @ Uf[t]], [np.zeros((d, d), dtype), Uf[t]]]), dtype)
+        P11, P21, P22 = Psi[:d, :d], Psi[d:, :d], Psi[d:, d:]
+        E = _right_solve(P21, P11)
+        out.append((E, mf[t] - E @ (F @ mf[t] + b), P22))
+    out.append((np.zeros((d, d), dtype), np.asarray(mf[-1], dtype), np.asarray(Uf[-1], dtype)))
+    return out
+
+
 def scan_fold(elems, op):
     """Inclusive prefix scan by left fold: out[t] = e_0 op ... op e_t."""
     out = [elems[0]]
