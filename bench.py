@@ -954,6 +954,102 @@ def bench_samplers(torch, S, W, _lib, K: int, dev, cpu: bool = False) -> dict:
     return out
 
 
+def bench_sqrt(torch, S, W, _lib, K: int, dev, cpu: bool = False) -> dict:
+    """Square-root filter and sampler (akf_sqrt_filter_sample) in FP32 and FP64
+    beside the covariance-form FP64 filter and sampler (akf_aux_filter +
+    akf_rts_sample) on the same pseudo-observations, with each one's largest
+    error against the oracle: relative on filtering means and covariances,
+    absolute per step on the log-likelihood, in smoothing sd on the path.
+    Workloads: the stochastic-volatility auxiliary model (d = 30, T = 250, the
+    paper's FP32 case) and a d = 32, T = 4096 model with cond(Q) = 1e6 and
+    pseudo-observation variances 0.01-0.05."""
+    import time
+    import numpy as np
+    import oracle
+
+    def errs(res, ref, x_ref, sd):
+        mf, Pf = res["mf"], res["Pf"]
+        sc = np.maximum(np.linalg.norm(ref["mf"], axis=1), np.sqrt(np.einsum("tii->t", ref["Pf"])))
+        return {"mean_rel": float((np.linalg.norm(mf - ref["mf"], axis=1) / sc).max()),
+                "cov_rel": float((np.linalg.norm(Pf - ref["Pf"], axis=(1, 2)) /
+                                  np.linalg.norm(ref["Pf"], axis=(1, 2))).max()),
+                "ell_abs": float(np.abs(res["ell"] - ref["ell"]).max()),
+                "path_sd": float((np.abs(res["x"] - x_ref) / sd).max())}
+
+    cases = {}
+    w = W.stoch_vol(order=2)
+    rng = np.random.default_rng(6)
+    u = w.x_true + np.sqrt(w.delta / 2) * rng.standard_normal(w.x_true.shape)
+    om, Om, _, _ = oracle.linearise(oracle.Model(**w.oracle_kwargs()), w.y, w.x_true, u,
+                                    w.delta, 2)
+    Om = np.stack([np.diag(o) for o in Om]) if Om.ndim == 3 else Om
+    cases["stoch_vol_d30_T250"] = (w.m0, w.P0, w.F, w.b, w.Q, om, Om)
+    rng = np.random.default_rng(32)
+    d, N = 32, 4096
+    G = rng.standard_normal((d, d))
+    F = 0.9 * G / np.max(np.abs(np.linalg.eigvals(G)))
+    Uo, _ = np.linalg.qr(rng.standard_normal((d, d)))
+    Q = (Uo * (np.logspace(0, -6, d) * 0.1)) @ Uo.T
+    Q = 0.5 * (Q + Q.T)
+    cases["cond1e6_d32_T4096"] = (np.zeros(d), np.eye(d), F, None, Q,
+                                  0.5 * rng.standard_normal((N, d)),
+                                  rng.uniform(0.01, 0.05, (N, d)))
+    out = {}
+    for name, (m0, P0, F, b, Q, om, Om) in cases.items():
+        N, d = om.shape
+        xi = np.random.default_rng(7).standard_normal((N, d))
+        t0 = time.perf_counter()
+        ref = oracle.kf(m0, P0, F, Q, np.eye(d), np.stack([np.diag(o) for o in Om]), om, b=b,
+                        R_per_t=True)
+        x_ref, _ = oracle.rts_sample(F, ref["mf"], ref["Pf"], ref["mp"], ref["Pp"], xi)
+        t_or = time.perf_counter() - t0
+        _, Ps, _, _ = oracle.rts_smooth(F, ref["mf"], ref["Pf"], ref["mp"], ref["Pp"])
+        sd = np.sqrt(np.einsum("tii->ti", Ps))
+        M = S.DeviceModel.from_arrays(N, m0, P0, F, Q, W.EMIT_POISSON_LOG, b=b, device=dev)
+        T_ = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+        om_d, Om_d, xi_d = T_(om), T_(Om), T_(xi)
+        res = {"N": N, "d": d}
+
+        def time_it(fn):
+            fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(K):
+                r = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / K, r
+
+        for dt in ("f32", "f64"):
+            ws = S.Workspace(dev)
+            ms, r = time_it(lambda: S.sqrt_filter_sample(M, om_d, Om_d, xi_d, dtype=dt, ws=ws))
+            Uf = r["Uf"].cpu().numpy()
+            got = {"mf": r["mf"].cpu().numpy(), "Pf": Uf @ np.transpose(Uf, (0, 2, 1)),
+                   "ell": r["ell"].cpu().numpy(), "x": r["x"].cpu().numpy()}
+            res[f"sqrt_{dt}"] = {"ms": ms, "status": int(r["status"].item()),
+                                 "error_vs_oracle": errs(got, ref, x_ref, sd)}
+        ws = S.Workspace(dev)
+
+        def cov_form():
+            mf, Pf, ell, st = S.aux_filter(M, om_d, Om_d, ws=ws)
+            x, st2 = S.rts_sample(M, mf, Pf, xi_d, ws=ws)
+            return dict(mf=mf, Pf=Pf, ell=ell, x=x, status=st)
+
+        ms, r = time_it(cov_form)
+        got = {k: r[k].cpu().numpy() for k in ("mf", "Pf", "ell", "x")}
+        res["covariance_f64"] = {"ms": ms, "status": int(r["status"].item()),
+                                 "error_vs_oracle": errs(got, ref, x_ref, sd)}
+        if cpu:
+            res["cpu_baseline"] = {"value": 1.0 / t_or, "unit": "filter+sample calls/s",
+                                   "cores": 1, "kind": "oracle",
+                                   "sample": f"one sequential FP64 Kalman filter and RTS sample "
+                                             f"(d={d}, T={N}) by the C oracle, {t_or:.2f} s",
+                                   **host_info()}
+        out[name] = res
+    return out
+
+
 def sampler_cpu_baseline(w, mf_dev, Pf_dev, dnc_steps: int = 512) -> dict:
     """The oracle's two samplers on the same filtering moments: the prefix-sum
     (RTS) sampler over the full series, the divide-and-conquer sampler over the
@@ -1016,6 +1112,7 @@ def main() -> int:
     ap.add_argument("--no-first-order", action="store_true")
     ap.add_argument("--no-poisson", action="store_true")
     ap.add_argument("--no-obs-lin", action="store_true")
+    ap.add_argument("--no-sqrt", action="store_true")
     ap.add_argument("--no-reuse", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
@@ -1151,6 +1248,9 @@ def main() -> int:
         progress("obs_linearisation ...")
         res["obs_linearisation"] = bench_obs_linearisation(
             torch, S, W, _lib, 20, dev, 0 if args.no_cpu_baseline else 1)
+    if not args.no_sqrt:
+        progress("sqrt ...")
+        res["sqrt_filter"] = bench_sqrt(torch, S, W, _lib, 10, dev, not args.no_cpu_baseline)
     if not args.no_poisson:
         progress("poisson ...")
         res["poisson"] = bench_poisson(torch, S, W, _lib, 50, dev,

@@ -73,11 +73,13 @@ typedef enum {
 } akf_dyn;
 
 /* Arithmetic and storage type of the path's internals (the boundary arrays
- * are float64 whatever the selection).  FP64 is the only one built: on gfx950
- * plain FP32 vector arithmetic has the FP64 rate and FP32 matrix cores twice
- * the FP64 rate, and the paper reports its parallel Kalman sampler diverging
- * in FP32 (Sec. "Multivariate stochastic volatility model"), so every entry
- * point computes in FP64 and rejects AKF_F32 with AKF_ERR_UNSUPPORTED. */
+ * are float64 whatever the selection).  The MH step and every covariance-form
+ * entry point compute in FP64: on gfx950 plain FP32 vector arithmetic has the
+ * FP64 rate and FP32 matrix cores twice the FP64 rate, and the paper reports
+ * its parallel Kalman sampler diverging in FP32 (Sec. "Multivariate stochastic
+ * volatility model"), so they reject AKF_F32 with AKF_ERR_UNSUPPORTED.  The
+ * square-root filter and sampler (akf_sqrt_filter_sample), the form built for
+ * FP32, take either. */
 typedef enum {
   AKF_F64 = 0, /* default: a zero-initialised model selects it */
   AKF_F32 = 1
@@ -115,8 +117,8 @@ enum {
  * Nonlinear dynamics are accepted by akf_mh_step / akf_mh_run only.
  *
  * dtype (akf_dtype) selects the internal arithmetic; every entry point taking
- * a model returns AKF_ERR_UNSUPPORTED for AKF_F32 (and AKF_ERR_INVALID for an
- * unknown value), the workspace queries return 0.
+ * a model but akf_sqrt_filter_sample returns AKF_ERR_UNSUPPORTED for AKF_F32
+ * (and AKF_ERR_INVALID for an unknown value), the workspace queries return 0.
  */
 typedef struct akf_model {
   int32_t N, dx, dy;
@@ -308,6 +310,42 @@ size_t akf_sampler_workspace_bytes(const akf_model* model, int32_t block);
 akf_status akf_rts_sample(const akf_model* model, const double* mf, const double* Pf,
                           const double* xi, double* x, int32_t* status, void* ws,
                           size_t ws_bytes, int32_t block, void* stream);
+
+/*
+ * Square-root form of the parallel filter and of the pathwise sampler, the
+ * form the paper points to for FP32 robustness (Sec. "Multivariate stochastic
+ * volatility model": its parallel Kalman sampler diverged in FP32).  Same
+ * auxiliary model as akf_aux_filter (x_t = F x_{t-1} + b + N(0, Q),
+ * omega_t = x_t + N(0, diag(Omega_t)); emission fields ignored) and the same
+ * results up to rounding, with every covariance carried as a lower-triangular
+ * factor and every covariance update a triangularisation (Householder, in
+ * double): filtering elements (A, b, U, eta, Z) with C = U U^T, J = Z Z^T
+ * (App. A, "Prefix-sums and the parallel Kalman filter", in factor form),
+ * sampling elements E_t and chol(L_t) from one triangularisation per step
+ * (App. A, "Parallel Rauch--Tung--Striebel sampler").
+ *   - model->dtype selects the storage and arithmetic of every matrix and
+ *     vector: AKF_F32 or AKF_F64 (the triangularisations and the likelihood
+ *     sums accumulate in double either way).  1 <= dx <= 32; linear dynamics.
+ *   - omega, Omega [N,dx] (Omega: the diagonal variances, > 0);
+ *     mf [N,dx] filtering means (required); Uf [N,dx,dx] the lower factors of
+ *     the filtering covariances (P^f_t = Uf_t Uf_t^T) or NULL; ell [N] the
+ *     per-step predictive log-likelihood terms or NULL; logZ [1] their sum or
+ *     NULL (NaN when *status != 0).
+ *   - xi [N,dx] standard normals and x_out [N,dx]: the path sample, with
+ *     x_{N-1} = mf + Uf xi_{N-1}, x_t = mf_t + E_t (x_{t+1} - F mf_t - b) +
+ *     chol(L_t) xi_t (the noise map of akf_rts_sample); x_out NULL skips the
+ *     sampler (xi may then be NULL).
+ *   - *status (device int32, may be NULL): AKF_ST_FWD_NOT_PD when Q or P0 is
+ *     not positive definite or a factor has a non-positive pivot, else 0.
+ *   - workspace: akf_sqrt_workspace_bytes(model, block); block = time steps
+ *     per scan block (0 = automatic).
+ */
+size_t akf_sqrt_workspace_bytes(const akf_model* model, int32_t block);
+akf_status akf_sqrt_filter_sample(const akf_model* model, const double* omega,
+                                  const double* Omega, const double* xi, double* x_out,
+                                  double* mf, double* Uf, double* ell, double* logZ,
+                                  int32_t* status, void* ws, size_t ws_bytes, int32_t block,
+                                  void* stream);
 
 /*
  * Divide-and-conquer pathwise sampler (App. A, "Divide-and-conquer

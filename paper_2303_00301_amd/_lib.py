@@ -85,6 +85,9 @@ SIGNATURES = {
     "akf_aux_filter": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
     "akf_sampler_workspace_bytes": (_sz, [_MP, _i32]),
     "akf_rts_sample": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _i32, _vp]),
+    "akf_sqrt_workspace_bytes": (_sz, [_MP, _i32]),
+    "akf_sqrt_filter_sample": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                         _sz, _i32, _vp]),
     "akf_dnc_workspace_bytes": (_sz, [_MP]),
     "akf_dnc_sample": (C.c_int, [_MP, _vp, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "akf_smoother_workspace_bytes": (_sz, [_MP, _i32]),

@@ -194,13 +194,16 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
 }
 
 
-akf_status check_model(const akf_model* m, bool need_emission) {
+akf_status check_model(const akf_model* m, bool need_emission, bool allow_f32) {
   if (!m) return fail(AKF_ERR_INVALID, "model is NULL");
   if (m->N < 1) return fail(AKF_ERR_SHAPE, "N must be >= 1 (got %d)", m->N);
   if (m->dx < 1 || m->dx > 64) return fail(AKF_ERR_SHAPE, "dx must be in [1, 64] (got %d)", m->dx);
-  if (m->dtype == AKF_F32)
-    return fail(AKF_ERR_UNSUPPORTED, "dtype AKF_F32 is not built: the path computes in FP64");
-  if (m->dtype != AKF_F64) return fail(AKF_ERR_INVALID, "unknown dtype %d", m->dtype);
+  if (m->dtype == AKF_F32 && !allow_f32)
+    return fail(AKF_ERR_UNSUPPORTED, "dtype AKF_F32 is built for the square-root filter and "
+                                     "sampler only (akf_sqrt_filter_sample); this entry point "
+                                     "computes in FP64");
+  if (m->dtype != AKF_F64 && m->dtype != AKF_F32)
+    return fail(AKF_ERR_INVALID, "unknown dtype %d", m->dtype);
   switch (m->dyn) {
     case AKF_DYN_LINEAR:
       if (!m->F) return fail(AKF_ERR_INVALID, "linear dynamics need F");

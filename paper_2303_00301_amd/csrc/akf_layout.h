@@ -67,7 +67,8 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
 // workspace layout of akf_lgssm_loglik / akf_lgssm_loglik_grad (filtering
 // moments at Lo.mf, Lo.Pf with leading dimension Lo.D)
 void lgssm_layout(Layout& Lo, const akf_lgssm* m, int block);
-akf_status check_model(const akf_model* m, bool need_emission);
+// allow_f32: the entry point computes in FP32 when the model asks for it
+akf_status check_model(const akf_model* m, bool need_emission, bool allow_f32 = false);
 akf_status check_order(const akf_model* m, int order);
 akf_status check_linear(const akf_model* m, const char* what);
 KModel to_kmodel(const akf_model* m);

@@ -359,6 +359,41 @@ def rts_sample(model: DeviceModel, mf, Pf, xi, block: int = 0, ws: Optional[Work
     return x, st
 
 
+def sqrt_filter_sample(model: DeviceModel, omega, Omega, xi=None, dtype: str = "f32",
+                       block: int = 0, factors: bool = True, ws: Optional[Workspace] = None):
+    """Square-root parallel filter (and, with xi [N,dx], the pathwise sample) of
+    x_t = F x_{t-1} + b + N(0,Q), omega_t = x_t + N(0, diag Omega_t), computed in
+    FP32 (dtype "f32") or FP64 ("f64") with the triangularisations in FP64
+    (akf_sqrt_filter_sample; dx <= 32).  Returns a dict of device tensors: mf
+    [N,dx], Uf [N,dx,dx] (lower factors of P^f; None unless factors), ell [N],
+    logZ [1], x [N,dx] (None without xi), status [1]."""
+    lib = _lib.load()
+    dev = model.device
+    N, dx = model.N, model.dx
+    _check_f64("omega", omega, (N, dx))
+    _check_f64("Omega", Omega, (N, dx))
+    if xi is not None:
+        _check_f64("xi", xi, (N, dx))
+    if dtype not in ("f32", "f64"):
+        raise ValueError("dtype must be 'f32' or 'f64'")
+    f = dict(dtype=torch.float64, device=dev)
+    mf = torch.empty((N, dx), **f)
+    Uf = torch.empty((N, dx, dx), **f) if factors else None
+    ell = torch.empty(N, **f)
+    lz = torch.empty(1, **f)
+    x = torch.empty((N, dx), **f) if xi is not None else None
+    st = torch.empty(1, dtype=torch.int32, device=dev)
+    ms = model.cstruct()
+    ms.dtype = _lib.AKF_F32 if dtype == "f32" else _lib.AKF_F64
+    need = _need(lib.akf_sqrt_workspace_bytes(C.byref(ms), block), "akf_sqrt_workspace_bytes")
+    wsp, wsb = (ws or _ws_for(dev)).ptr_bytes(need)
+    rc = lib.akf_sqrt_filter_sample(C.byref(ms), _ptr(omega), _ptr(Omega), _ptr(xi), _ptr(x),
+                                    _ptr(mf), _ptr(Uf), _ptr(ell), _ptr(lz), _ptr(st), wsp, wsb,
+                                    int(block), _stream(dev))
+    _lib.check(rc, "akf_sqrt_filter_sample")
+    return dict(mf=mf, Uf=Uf, ell=ell, logZ=lz, x=x, status=st)
+
+
 def dnc_sample(model: DeviceModel, mf, Pf, xi, ws: Optional[Workspace] = None):
     """Divide-and-conquer path sample from filtering moments (same law as
     rts_sample, its own noise map).  Returns (x [N,dx], status [1])."""

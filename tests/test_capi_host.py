@@ -96,6 +96,41 @@ def test_order3_validation():
     assert lib.akf_mh_factorised_workspace_bytes(C.byref(q), 3) == 0
 
 
+def test_sqrt_filter_validation():
+    """The square-root filter takes AKF_F32 and AKF_F64 (its FP32 workspace is
+    smaller), dx <= 32 and linear dynamics; the covariance-form entry points
+    still reject AKF_F32."""
+    lib = _lib.load()
+    m = _fake_model(N=250, dx=30, dy=30)
+    m.dtype = _lib.AKF_F64
+    b64 = lib.akf_sqrt_workspace_bytes(C.byref(m), 0)
+    m.dtype = _lib.AKF_F32
+    b32 = lib.akf_sqrt_workspace_bytes(C.byref(m), 0)
+    assert 0 < b32 < b64
+    assert lib.akf_mh_workspace_bytes(C.byref(m), 2, 0) == 0
+    assert lib.akf_filter_workspace_bytes(C.byref(m), 0) == 0
+    m.dtype = 7
+    assert lib.akf_sqrt_workspace_bytes(C.byref(m), 0) == 0
+    m.dtype = _lib.AKF_F32
+    m.dx = 33
+    assert lib.akf_sqrt_workspace_bytes(C.byref(m), 0) == 0
+    m.dx = 8
+    m.dyn = 2
+    m.dyn_par[1] = 0.01
+    assert lib.akf_sqrt_workspace_bytes(C.byref(m), 0) == 0
+    m.dyn = 0
+    p = C.c_void_p(0x2000)
+    ws = C.c_void_p(0x10000)
+    call = lambda **kw: lib.akf_sqrt_filter_sample(
+        C.byref(m), kw.get("om", p), p, kw.get("xi", p), kw.get("x", p), kw.get("mf", p), None,
+        None, None, None, ws, kw.get("ws_bytes", 1 << 30), kw.get("block", 0), None)
+    assert call(om=None) == 1
+    assert call(mf=None) == 1
+    assert call(xi=None) == 1       # a path sample needs normals
+    assert call(block=-1) == 1
+    assert call(ws_bytes=16) == 3
+
+
 def test_mh_step_noalloc_rejects_problems_beyond_its_array():
     """The no-allocation step refuses, before any device call, a problem whose
     workspace exceeds the library's fixed scratch array."""
