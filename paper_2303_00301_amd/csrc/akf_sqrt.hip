@@ -50,7 +50,7 @@ struct Dm {
   static constexpr int MAT = D * LM;        // entries of one LDS matrix
   static constexpr int LW = 2 * D + 1;      // row stride of the triangularisation area
   static constexpr int WSZ = 2 * D * LW;    // 2D rows (doubles)
-  static constexpr int DV = 4 * D + 8;      // double scratch of tria and reductions
+  static constexpr int DV = 8;              // double scratch
 };
 
 // Element in the workspace: A, U, Z (D x D dense, zero padded), b, eta.
@@ -94,7 +94,7 @@ __device__ __forceinline__ double team_sum(double v, double* red) {
 
 // dst (LDS, D x D) <- a d x d array with leading dimension ld, zero padded.
 template <class T, int D, class S>
-__device__ void ld_mat(T* dst, const S* src, int d, int ld) {
+__device__ __forceinline__ void ld_mat(T* dst, const S* src, int d, int ld) {
   for (int e = threadIdx.x; e < D * D; e += NT) {
     const int i = e / D, j = e % D;
     dst[i * Dm<D>::LM + j] = (i < d && j < d) ? (T)src[(int64_t)i * ld + j] : T(0);
@@ -104,12 +104,12 @@ __device__ void ld_mat(T* dst, const S* src, int d, int ld) {
 
 // global dense D x D <- LDS matrix
 template <class T, int D>
-__device__ void st_mat(T* dst, const T* src) {
+__device__ __forceinline__ void st_mat(T* dst, const T* src) {
   for (int e = threadIdx.x; e < D * D; e += NT) dst[e] = src[(e / D) * Dm<D>::LM + e % D];
 }
 
 template <class T, int D>
-__device__ void set_eye(T* dst, int d, T diag) {
+__device__ __forceinline__ void set_eye(T* dst, int d, T diag) {
   for (int e = threadIdx.x; e < D * D; e += NT) {
     const int i = e / D, j = e % D;
     dst[i * Dm<D>::LM + j] = (i == j && i < d) ? diag : T(0);
@@ -118,20 +118,21 @@ __device__ void set_eye(T* dst, int d, T diag) {
 }
 
 template <class T, int D>
-__device__ void cp_mat(T* dst, const T* src) {
+__device__ __forceinline__ void cp_mat(T* dst, const T* src) {
   for (int e = threadIdx.x; e < Dm<D>::MAT; e += NT) dst[e] = src[e];
   __syncthreads();
 }
 
 // C = op(A) op(B) (+ Cadd, which may be C itself); C must not alias A or B.
 template <class T, int D, bool TA, bool TB>
-__device__ void mm(T* __restrict__ C, const T* __restrict__ A, const T* __restrict__ B, int d,
+__device__ __forceinline__ void mm(T* __restrict__ C, const T* __restrict__ A, const T* __restrict__ B, int d,
                    const T* Cadd = nullptr, T sign = T(1)) {
   constexpr int L = Dm<D>::LM;
   for (int e = threadIdx.x; e < D * D; e += NT) {
     const int i = e / D, j = e % D;
     T acc = T(0);
-    for (int k = 0; k < d; ++k) {
+#pragma unroll
+    for (int k = 0; k < D; ++k) {  // the zero padding makes the padded width exact
       const T a = TA ? A[k * L + i] : A[i * L + k];
       const T b = TB ? B[j * L + k] : B[k * L + j];
       acc = fma(a, b, acc);
@@ -143,52 +144,73 @@ __device__ void mm(T* __restrict__ C, const T* __restrict__ A, const T* __restri
 
 // y = op(A) x (+ y0, which may be y); y must not alias x.
 template <class T, int D, bool TA>
-__device__ void mv(T* __restrict__ y, const T* __restrict__ A, const T* __restrict__ x, int d,
+__device__ __forceinline__ void mv(T* __restrict__ y, const T* __restrict__ A, const T* __restrict__ x, int d,
                    const T* y0 = nullptr, T sign = T(1)) {
   constexpr int L = Dm<D>::LM;
   const int i = threadIdx.x;
   if (i < D) {
     T acc = T(0);
-    if (i < d)
-      for (int k = 0; k < d; ++k) acc = fma(TA ? A[k * L + i] : A[i * L + k], x[k], acc);
+#pragma unroll
+    for (int k = 0; k < D; ++k) acc = fma(TA ? A[k * L + i] : A[i * L + k], x[k], acc);
     y[i] = (i < d) ? ((y0 ? y0[i] : T(0)) + sign * acc) : T(0);
   }
   __syncthreads();
 }
 
+// Lanes per column of a triangular solve over ncols columns: a power of two,
+// at most one wave, with all columns' groups fitting in the team.
+__device__ __forceinline__ int solve_group(int ncols) {
+  int g = 64;
+  while (g > 1 && g * ncols > NT) g >>= 1;
+  return g;
+}
+
 // X <- L^{-1} X over ncols columns of X (entry (i, j) at X[i*rs + j*cs]); L lower
-// (LDS, stride LM).  Returns false on a non-positive pivot.
+// (LDS, stride LM).  Forward substitution by columns of L: each column of X has
+// a group of lanes, lane r owning the rows i = r mod group; x_i is formed by its
+// owner, broadcast across the group by a shuffle, and every lane updates its
+// rows below i.  Returns false on a non-positive pivot.
 template <class T, int D>
-__device__ bool solve_l(T* X, int rs, int cs, const T* L, int ncols, int d) {
+__device__ __forceinline__ bool solve_l(T* X, int rs, int cs, const T* L, int ncols, int d) {
   constexpr int LM = Dm<D>::LM;
+  const int gs = solve_group(ncols), tid = threadIdx.x, j = tid / gs, r = tid % gs;
   bool ok = true;
-  const int j = threadIdx.x;
   if (j < ncols) {
     for (int i = 0; i < d; ++i) {
-      T acc = X[i * rs + j * cs];
-      for (int k = 0; k < i; ++k) acc = fma(-L[i * LM + k], X[k * rs + j * cs], acc);
-      const T p = L[i * LM + i];
-      ok = ok && (p > T(0));
-      X[i * rs + j * cs] = acc / p;
+      T xi = T(0);
+      if (r == i % gs) {
+        const T p = L[i * LM + i];
+        ok = ok && (p > T(0));
+        xi = X[i * rs + j * cs] / p;
+        X[i * rs + j * cs] = xi;
+      }
+      xi = __shfl(xi, i % gs, gs);
+      for (int k = i + 1 + ((r - i - 1) % gs + gs) % gs; k < d; k += gs)
+        X[k * rs + j * cs] = fma(-L[k * LM + i], xi, X[k * rs + j * cs]);
     }
   }
   __syncthreads();
   return __syncthreads_and(ok);
 }
 
-// X <- L^{-T} X over ncols columns (backward substitution with the upper L^T).
+// X <- L^{-T} X over ncols columns (backward substitution with the upper L^T),
+// laid out as solve_l.
 template <class T, int D>
-__device__ bool solve_lt(T* X, int rs, int cs, const T* L, int ncols, int d) {
+__device__ __forceinline__ bool solve_lt(T* X, int rs, int cs, const T* L, int ncols, int d) {
   constexpr int LM = Dm<D>::LM;
+  const int gs = solve_group(ncols), tid = threadIdx.x, j = tid / gs, r = tid % gs;
   bool ok = true;
-  const int j = threadIdx.x;
   if (j < ncols) {
     for (int i = d - 1; i >= 0; --i) {
-      T acc = X[i * rs + j * cs];
-      for (int k = i + 1; k < d; ++k) acc = fma(-L[k * LM + i], X[k * rs + j * cs], acc);
-      const T p = L[i * LM + i];
-      ok = ok && (p > T(0));
-      X[i * rs + j * cs] = acc / p;
+      T xi = T(0);
+      if (r == i % gs) {
+        const T p = L[i * LM + i];
+        ok = ok && (p > T(0));
+        xi = X[i * rs + j * cs] / p;
+        X[i * rs + j * cs] = xi;
+      }
+      xi = __shfl(xi, i % gs, gs);
+      for (int k = r; k < i; k += gs) X[k * rs + j * cs] = fma(-L[i * LM + k], xi, X[k * rs + j * cs]);
     }
   }
   __syncthreads();
@@ -197,95 +219,105 @@ __device__ bool solve_lt(T* X, int rs, int cs, const T* L, int ncols, int d) {
 
 // Rows of X (D x D in LDS): X <- X L^{-T} and X <- X L^{-1}.
 template <class T, int D>
-__device__ bool rows_times_linvT(T* X, const T* L, int nrows, int d) {
+__device__ __forceinline__ bool rows_times_linvT(T* X, const T* L, int nrows, int d) {
   return solve_l<T, D>(X, 1, Dm<D>::LM, L, nrows, d);
 }
 template <class T, int D>
-__device__ bool rows_times_linv(T* X, const T* L, int nrows, int d) {
+__device__ __forceinline__ bool rows_times_linv(T* X, const T* L, int nrows, int d) {
   return solve_lt<T, D>(X, 1, Dm<D>::LM, L, nrows, d);
 }
 
 // sum of log of the first d diagonal entries of an LDS factor, in double
 template <class T, int D>
-__device__ double logdiag(const T* L, int d, double* red) {
+__device__ __forceinline__ double logdiag(const T* L, int d, double* red) {
   double v = 0.0;
   for (int i = threadIdx.x; i < d; i += NT) v += log((double)L[i * Dm<D>::LM + i]);
   return team_sum(v, red);
 }
 
 template <class T, int D>
-__device__ double dot(const T* x, const T* y, int d, double* red) {
+__device__ __forceinline__ double dot(const T* x, const T* y, int d, double* red) {
   double v = 0.0;
   for (int i = threadIdx.x; i < d; i += NT) v += (double)x[i] * (double)y[i];
   return team_sum(v, red);
 }
 
 // ---------------------------------------------------------------------------
-// tria: in-place triangularisation of the r x c block (c >= r) at the top left
-// of W (double, row stride LW).  On return W[0:r][0:r] is the lower-triangular
-// L with non-negative diagonal and L L^T = M M^T for the block M given.  Row k
-// in turn: a Householder reflection from the right maps its tail W[k][k:c] to
-// (alpha, 0, ..., 0) and is applied to the rows below; column k is negated when
-// alpha < 0 (which leaves L L^T unchanged).
-// dv: double scratch of Dm<D>::DV entries.
+// tria: in-place triangularisation of the r x c block M (c >= r) at the top
+// left of W (double, row stride LW).  On return W[0:r][0:r] is the lower-
+// triangular L with non-negative diagonal and L L^T = M M^T.  L is computed in
+// double as the Cholesky factor of the Gram matrix M M^T, itself formed in
+// double: for matrices held in FP32 this is as accurate as a Householder
+// reduction (the squared condition number of M, at most ~1e8 on these models,
+// stays far below 1/eps of double), and it replaces a chain of r dependent
+// reflections by one product and a Cholesky with two barriers per column.
+// The factorisation is for a positive semi-definite matrix: a pivot <= 0 (an
+// exactly singular direction, e.g. a zero block, or its rounding) gives a zero
+// column.  Each thread keeps its 4 x 4 share of the Gram matrix in registers
+// until every thread has read M, then writes it over M.
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ void tria(double* W, int r, int c, double* dv) {
-  constexpr int LW = Dm<D>::LW;
-  double* v = dv;           // reflection vector, entries for columns k..c-1
-  double* wv = dv + 2 * D;  // beta * (row . v) for rows below k
-  double* sc = dv + 4 * D;  // [0] beta, [1] alpha
-  const int tid = threadIdx.x;
+__device__ __forceinline__ void tria(double* W, int r, int c, double* dv) {
+  constexpr int LW = Dm<D>::LW, R = 2 * D, NB = R / 16;
+  const int tid = threadIdx.x, ti = tid >> 4, tj = tid & 15;
+  // Gram matrix: thread (ti, tj) accumulates rows ti + 16 u and columns
+  // tj + 16 v (consecutive threads read consecutive rows: no bank conflicts)
+  double gv[NB][NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+#pragma unroll
+    for (int v = 0; v < NB; ++v) gv[u][v] = 0.0;
+#pragma unroll 2
+  for (int k = 0; k < c; ++k) {
+    double a[NB], b[NB];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      a[u] = (ti + 16 * u < r) ? W[(ti + 16 * u) * LW + k] : 0.0;
+      b[u] = (tj + 16 * u < r) ? W[(tj + 16 * u) * LW + k] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u)
+#pragma unroll
+      for (int v = 0; v < NB; ++v) gv[u][v] = fma(a[u], b[v], gv[u][v]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < NB; ++u)
+#pragma unroll
+    for (int v = 0; v < NB; ++v) {
+      const int i = ti + 16 * u, j = tj + 16 * v;
+      if (i < r && j < r) W[i * LW + j] = (j <= i) ? gv[u][v] : 0.0;
+    }
+  __syncthreads();
+  // right-looking Cholesky; thread (ti, tj) updates rows ti + 16 a and
+  // columns tj + 16 b of the trailing block
   for (int k = 0; k < r; ++k) {
-    const int n = c - k;
-    if (tid < 64) {
-      double s2 = 0.0;
-      for (int j = tid; j < n; j += 64) {
-        const double x = W[k * LW + k + j];
-        s2 += x * x;
-      }
-      for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o);
-      const double x0 = W[k * LW + k];
-      const double sg = sqrt(s2);
-      const double alpha = (x0 >= 0.0) ? -sg : sg;
-      const double v0 = x0 - alpha;
-      const double vtv = s2 - x0 * x0 + v0 * v0;
-      for (int j = tid; j < n; j += 64) v[j] = (j == 0) ? v0 : W[k * LW + k + j];
-      if (tid == 0) {
-        sc[0] = (s2 > 0.0 && vtv > 0.0) ? 2.0 / vtv : 0.0;
-        sc[1] = (s2 > 0.0) ? alpha : 0.0;
+    const double p = W[k * LW + k];
+    const double dk = (p > 0.0) ? sqrt(p) : 0.0;
+    const double inv = (dk > 0.0) ? 1.0 / dk : 0.0;
+    for (int i = k + 1 + tid; i < r; i += NT) W[i * LW + k] *= inv;
+    __syncthreads();
+    if (tid == 0) W[k * LW + k] = dk;
+#pragma unroll
+    for (int a = 0; a < R / 16; ++a) {
+      const int i = k + 1 + ti + 16 * a;
+      if (i < r) {
+        const double lik = W[i * LW + k];
+#pragma unroll
+        for (int b = 0; b < R / 16; ++b) {
+          const int j = k + 1 + tj + 16 * b;
+          if (j <= i) W[i * LW + j] = fma(-lik, W[j * LW + k], W[i * LW + j]);
+        }
       }
     }
-    __syncthreads();
-    const double beta = sc[0];
-    const int rows = r - k - 1;
-    if (beta != 0.0 && rows > 0) {
-      // rows below k: four lanes per row, columns split by j mod 4
-      const int ii = tid >> 2, q = tid & 3;
-      double acc = 0.0;
-      if (ii < rows)
-        for (int j = q; j < n; j += 4) acc += W[(k + 1 + ii) * LW + k + j] * v[j];
-      acc += __shfl_xor(acc, 1);
-      acc += __shfl_xor(acc, 2);
-      if (ii < rows && q == 0) wv[ii] = beta * acc;
-      __syncthreads();
-      for (int e = tid; e < rows * n; e += NT) {
-        const int i = e / n, j = e % n;
-        W[(k + 1 + i) * LW + k + j] -= wv[i] * v[j];
-      }
-    }
-    __syncthreads();
-    const double alpha = sc[1];
-    for (int j = tid; j < n; j += NT) W[k * LW + k + j] = (j == 0) ? fabs(alpha) : 0.0;
-    if (alpha < 0.0)
-      for (int i = k + 1 + tid; i < r; i += NT) W[i * LW + k] = -W[i * LW + k];
     __syncthreads();
   }
+  (void)dv;
 }
 
 // W block (roff, coff) of size d x d <- an LDS matrix (optionally transposed)
 template <class T, int D, bool TR>
-__device__ void to_w(double* W, int roff, int coff, const T* M, int d) {
+__device__ __forceinline__ void to_w(double* W, int roff, int coff, const T* M, int d) {
   constexpr int LW = Dm<D>::LW, LM = Dm<D>::LM;
   for (int e = threadIdx.x; e < d * d; e += NT) {
     const int i = e / d, j = e % d;
@@ -294,7 +326,7 @@ __device__ void to_w(double* W, int roff, int coff, const T* M, int d) {
 }
 
 template <int D>
-__device__ void w_fill(double* W, int roff, int coff, int d, double diag) {
+__device__ __forceinline__ void w_fill(double* W, int roff, int coff, int d, double diag) {
   constexpr int LW = Dm<D>::LW;
   for (int e = threadIdx.x; e < d * d; e += NT) {
     const int i = e / d, j = e % d;
@@ -304,7 +336,7 @@ __device__ void w_fill(double* W, int roff, int coff, int d, double diag) {
 
 // LDS matrix (zero padded) <- W block (roff, coff), d x d
 template <class T, int D>
-__device__ void from_w(T* M, const double* W, int roff, int coff, int d) {
+__device__ __forceinline__ void from_w(T* M, const double* W, int roff, int coff, int d) {
   constexpr int LW = Dm<D>::LW, LM = Dm<D>::LM;
   for (int e = threadIdx.x; e < D * D; e += NT) {
     const int i = e / D, j = e % D;
@@ -317,7 +349,7 @@ __device__ void from_w(T* M, const double* W, int roff, int coff, int d) {
 // factor, written to Uo).  s = P11^{-1} (omega - m_p).  Returns the predictive
 // log density of omega, in double, through *lpred.
 template <class T, int D>
-__device__ bool sqrt_update(double* W, double* dv, const T* Up, const double* Om_t, int d, T* P11,
+__device__ __forceinline__ bool sqrt_update(double* W, double* dv, const T* Up, const double* Om_t, int d, T* P11,
                             T* P21, T* Uo, T* vs, const T* vmp, const double* om_t, double* red,
                             double* lpred) {
   for (int e = threadIdx.x; e < d * d; e += NT) {
@@ -343,7 +375,7 @@ __device__ bool sqrt_update(double* W, double* dv, const T* Up, const double* Om
 
 // Prediction factor U_p = tria([F U, L_Q]) into Up (FU: scratch matrix).
 template <class T, int D>
-__device__ void sqrt_predict(double* W, double* dv, const T* sF, const T* U, const T* sLQ, int d,
+__device__ __forceinline__ void sqrt_predict(double* W, double* dv, const T* sF, const T* U, const T* sLQ, int d,
                              T* FU, T* Up) {
   mm<T, D, false, false>(FU, sF, U, d);
   to_w<T, D, false>(W, 0, 0, FU, d);
@@ -358,7 +390,7 @@ __device__ void sqrt_predict(double* W, double* dv, const T* sF, const T* U, con
 // set-up: L_Q = chol(Q), L_0 = chol(P0) (double), F in T
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ bool chol_lds(double* A, int d) {
+__device__ __forceinline__ bool chol_lds(double* A, int d) {
   constexpr int LM = Dm<D>::LM;
   __shared__ int okf;
   if (threadIdx.x == 0) okf = 1;
@@ -413,21 +445,22 @@ struct Carve {
   T* m[14];
   T* v[10];
   double *W, *dv, *red;
-  __device__ Carve(unsigned char* base, int nm, int nv) {
+  __device__ __forceinline__ Carve(unsigned char* base, int nm, int nv) {
     T* p = reinterpret_cast<T*>(base);
     for (int i = 0; i < nm; ++i) m[i] = p + i * Dm<D>::MAT;
     p += nm * Dm<D>::MAT;
     for (int i = 0; i < nv; ++i) v[i] = p + i * D;
-    p += nv * D;
-    uintptr_t a = reinterpret_cast<uintptr_t>(p);
-    a = (a + 15) & ~uintptr_t(15);
-    W = reinterpret_cast<double*>(a);
+    // the double areas start at a 16-byte multiple; plain pointer arithmetic on
+    // the LDS base (no integer round trip) lets the compiler keep LDS accesses
+    W = reinterpret_cast<double*>(base + tbytes(nm, nv));
     dv = W + Dm<D>::WSZ;
     red = dv + Dm<D>::DV;
   }
+  static constexpr size_t tbytes(int nm, int nv) {
+    return (((size_t)(nm * Dm<D>::MAT + nv * D) * sizeof(T)) + 15) & ~size_t(15);
+  }
   static constexpr size_t bytes(int nm, int nv) {
-    return (size_t)(nm * Dm<D>::MAT + nv * D) * sizeof(T) + 16 +
-           (size_t)(Dm<D>::WSZ + Dm<D>::DV + NT / 64) * sizeof(double);
+    return tbytes(nm, nv) + (size_t)(Dm<D>::WSZ + Dm<D>::DV + NT / 64) * sizeof(double);
   }
 };
 
