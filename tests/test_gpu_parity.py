@@ -310,3 +310,44 @@ def test_mh_run_matches_repeated_steps(S):
     torch.cuda.synchronize()
     assert torch.equal(x, x_run)
     np.testing.assert_array_equal(N_(out["log_ratio"]), np.array(lrs))
+
+
+def test_mh_run_graph_replay_matches_eager(S):
+    """A K-step run captured as a graph and replayed several times, with fresh
+    normals written into the captured buffers and eager runs (and host
+    synchronisations) between replays: every replay equals the eager run from
+    the same start and normals (same kernels, so bit for bit)."""
+    w = W.latent_field(N=96)
+    M = S.DeviceModel.from_workload(w, device=dev())
+    y = T(w.y)
+    K = 3
+    gen = torch.Generator(device=dev())
+    gen.manual_seed(5)
+    xi = torch.empty((K, 2, w.N, w.dx), dtype=torch.float64, device=dev())
+    un = torch.empty((K,), dtype=torch.float64, device=dev())
+    ws = S.Workspace(dev())
+    x_cap = T(w.x_true)
+    xi.normal_(generator=gen)
+    un.uniform_(generator=gen)
+    S.mh_run(M, y, x_cap, w.delta, 2, xi, un, ws=ws)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = S.mh_run(M, y, x_cap, w.delta, 2, xi, un, ws=ws)
+    torch.cuda.synchronize()
+    x = T(w.x_true)
+    for rep in range(4):
+        xi.normal_(generator=gen)
+        un.uniform_(generator=gen)
+        un.clamp_(min=1e-300)
+        if rep == 2:
+            un.fill_(1e-300)  # a replay whose steps accept unless a proposal fails
+        start = x.clone()
+        x_cap.copy_(start)
+        g.replay()
+        torch.cuda.synchronize()
+        eager = S.mh_run(M, y, x, w.delta, 2, xi, un, ws=ws)
+        torch.cuda.synchronize()
+        assert torch.equal(x_cap, x), rep
+        for k in ("log_ratio", "accepted", "logZ_fwd", "logZ_rev", "status"):
+            assert torch.equal(out[k], eager[k]), (rep, k)
