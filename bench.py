@@ -1113,6 +1113,8 @@ def main() -> int:
     ap.add_argument("--no-poisson", action="store_true")
     ap.add_argument("--no-obs-lin", action="store_true")
     ap.add_argument("--no-sqrt", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the eager launches only (no graph capture; for profiler runs)")
     ap.add_argument("--no-reuse", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the bench, run 3 plain device copies of MIB MiB (a known-size "
@@ -1192,33 +1194,37 @@ def main() -> int:
 
     refill()
     x_cap = x.clone()
+    if args.eager:
+        rep_g, graph_ok, acc = rep_ms, None, acc_eager
+        status_bad = n_bad
     S.mh_run(M, y, x_cap, w.delta, w.order, xi_g, un_g, block=B, ws=ws)  # warm the graph's shapes
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        g_out = S.mh_run(M, y, x_cap, w.delta, w.order, xi_g, un_g, block=B, ws=ws)
-    torch.cuda.synchronize()
-    x_cap.copy_(x)
-    graph.replay()
-    x_eager = x.clone()
-    e_out = S.mh_run(M, y, x_eager, w.delta, w.order, xi_g, un_g, block=B, ws=ws)
-    torch.cuda.synchronize()
-    graph_ok = bool(torch.equal(x_cap, x_eager) and
-                    torch.equal(g_out["log_ratio"], e_out["log_ratio"]) and
-                    torch.equal(g_out["accepted"], e_out["accepted"]))
-    rep_g, accs, n_bad = [], [], 0
-    for r in range(R):
-        refill()
+    if not args.eager:
         torch.cuda.synchronize()
-        ev0.record()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            g_out = S.mh_run(M, y, x_cap, w.delta, w.order, xi_g, un_g, block=B, ws=ws)
+        torch.cuda.synchronize()
+        x_cap.copy_(x)
         graph.replay()
-        ev1.record()
+        x_eager = x.clone()
+        e_out = S.mh_run(M, y, x_eager, w.delta, w.order, xi_g, un_g, block=B, ws=ws)
         torch.cuda.synchronize()
-        rep_g.append(ev0.elapsed_time(ev1))
-        accs.append(g_out["accepted"].float().mean().item())
-        n_bad += int((g_out["status"] != 0).sum().item())
-    acc = sum(accs) / len(accs)
-    status_bad = n_bad
+        graph_ok = bool(torch.equal(x_cap, x_eager) and
+                        torch.equal(g_out["log_ratio"], e_out["log_ratio"]) and
+                        torch.equal(g_out["accepted"], e_out["accepted"]))
+        rep_g, accs, n_bad = [], [], 0
+        for r in range(R):
+            refill()
+            torch.cuda.synchronize()
+            ev0.record()
+            graph.replay()
+            ev1.record()
+            torch.cuda.synchronize()
+            rep_g.append(ev0.elapsed_time(ev1))
+            accs.append(g_out["accepted"].float().mean().item())
+            n_bad += int((g_out["status"] != 0).sum().item())
+        acc = sum(accs) / len(accs)
+        status_bad = n_bad
     ms_total = sorted(rep_g)[len(rep_g) // 2]
     ms_step = ms_total / K
     steps_s = 1000.0 / ms_step
@@ -1258,8 +1264,9 @@ def main() -> int:
                    "scan_block": B},
         "time_steps_per_s": steps_s * N,
         "repeats": R,
-        "timing": "median of the repeats of one captured K-step graph replayed with fresh "
-                  "normals (HIP events); eager launches of the same run beside it",
+        "timing": ("median of the eager repeats (HIP events; --eager)" if args.eager else
+                   "median of the repeats of one captured K-step graph replayed with fresh "
+                   "normals (HIP events); eager launches of the same run beside it"),
         "repeat_ms_per_step": [m / K for m in rep_g],
         "graph_replay_equals_eager": graph_ok,
         "eager_ms_per_step": eager_ms_step,
