@@ -565,7 +565,7 @@ def bench_obs_linearisation(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) 
     lib = _lib.load()
     w = W.quadratic_obs_field()
     M = S.DeviceModel.from_workload(w, device=dev)
-    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev)
+    y = torch.as_tensor(w.y, dtype=torch.float64, device=dev).contiguous()
     x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
     gen = torch.Generator(device=dev)
     gen.manual_seed(109)

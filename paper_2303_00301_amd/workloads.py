@@ -190,7 +190,7 @@ def quadratic_obs_field(N: int = 4096, d: int = 64, n_sites: int = 32, beta: flo
     base = (np.arange(n_sites) * (d // n_sites)).astype(np.int32)
     site = np.concatenate([base, base[:repeat_sites]]).astype(np.int32)
     z = x[:, site]
-    y = z + beta * z * z + scale * rng.standard_normal(z.shape)
+    y = np.ascontiguousarray(z + beta * z * z + scale * rng.standard_normal(z.shape))
     return Workload(f"quadratic_obs_field_d{d}_N{N}", N, m0, P0, F, Q, EMIT_GAUSS_QUAD, y,
                     site=site, scale=scale, delta=QUAD_FIELD_DELTA if delta is None else delta,
                     order=3, seed=seed, x_true=x, obs_beta=beta, slr_var=slr_var)
