@@ -815,7 +815,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 // Kalman filter"; lc is the constant of the Gaussian integral over the shared
 // state, with log det W = log det (I + C_i J_j)).
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int U = 4>
 __device__ __forceinline__ void filter_combine(const KModel& M, const double* __restrict__ ei,
                                                const double* __restrict__ ej,
                                                double* __restrict__ out, int* status,
@@ -849,19 +849,19 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   ok = chol_reg<D>(R1, d, S3, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);                        // S0 = L
   team_sync();
-  gemm<D, false, false, false>(R2, S1, S0);  // J_j L
+  gemm<D, false, false, false, U>(R2, S1, S0);  // J_j L
   rm_stage<D>(R2, S2);
   team_sync();
-  gemm<D, true, false, false>(R2, S0, S2);  // L' J_j L
+  gemm<D, true, false, false, U>(R2, S0, S2);  // L' J_j L
   AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
   ok = spd_inv<D>(R2, d, S3, &ld) && ok;  // W^{-1}
   const double ldW = ld;
   rm_stage<D>(R2, S2);
   team_sync();
-  gemm<D, false, false, false>(R3, S0, S2);  // L W^{-1}
+  gemm<D, false, false, false, U>(R3, S0, S2);  // L W^{-1}
   rm_stage<D>(R3, S3);
   team_sync();
-  gemm<D, false, true, false>(R2, S3, S0);  // M = L W^{-1} L'
+  gemm<D, false, true, false, U>(R2, S3, S0);  // M = L W^{-1} L'
   matvec<D, false>(vc, S1, vbi);            // J_j b_i
   team_sync();
   rm_stage<D>(R2, S2);  // S2 = M
@@ -876,31 +876,31 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   rm_stage<D>(Ai, S0);  // S0 = A_i
   team_sync();
   matvec<D, false>(vk, S1, vw);              // J_j w
-  gemm<D, false, false, false>(R1, S1, S0);  // P = J_j A_i
+  gemm<D, false, false, false, U>(R1, S1, S0);  // P = J_j A_i
   rm_stage<D>(R1, S3);                       // S3 = P
   team_sync();
   if (tid < D) vk[tid] = vc[tid] - vk[tid];  // c - J_j M c
-  gemm<D, false, false, false>(R2, S2, S3);  // M P
+  gemm<D, false, false, false, U>(R2, S2, S3);  // M P
   R3 = Ai;
   rm_axpy<D>(R3, -1.0, R2);  // Z1 = A_i - M P
   team_sync();
   matvec<D, true>(out + EL::eta, S0, vk, ei + EL::eta);  // eta = A_i' (c - J_j M c) + eta_i
   rm_stage<D>(R3, S1);  // S1 = Z1
   team_sync();
-  gemm<D, true, false, false>(R1, S1, S3);  // J = Z1' P + J_i = A_i'P - P'MP + J_i
+  gemm<D, true, false, false, U>(R1, S1, S3);  // J = Z1' P + J_i = A_i'P - P'MP + J_i
   rm_axpy<D>(R1, 1.0, Ji);
   rm_symmetrise<D>(R1, S3);  // ends synchronised
   rm_store<D>(R1, out + EL::J, D, D);
   rm_stage<D>(Aj, S0);  // S0 = A_j
   if (tid < D) vw[tid] += vbi[tid];
   team_sync();
-  gemm<D, false, false, false>(R3, S0, S1);  // A = A_j Z1
+  gemm<D, false, false, false, U>(R3, S0, S1);  // A = A_j Z1
   rm_store<D>(R3, out + EL::A, D, D);
-  gemm<D, false, false, false>(R2, S0, S2);  // A_j M
+  gemm<D, false, false, false, U>(R2, S0, S2);  // A_j M
   matvec<D, false>(vc, S0, vw);              // A_j (b_i + M c)
   rm_stage<D>(R2, S3);
   team_sync();
-  gemm<D, false, true, false>(R3, S3, S0);  // A_j M A_j'
+  gemm<D, false, true, false, U>(R3, S3, S0);  // A_j M A_j'
   rm_axpy<D>(R3, 1.0, Cj);
   if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
   if (tid == 0) out[EL::lc] = lc;
@@ -909,7 +909,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   if (!ok && tid == 0) flag_status(status, fail_bit);
 }
 
-template <int D>
+template <int D, int U = 4>
 __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& T, int item) {
   using EL = ElemLayout<D>;
   const int k = item, tid = threadIdx.x;
@@ -919,12 +919,12 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
     for (int e = tid; e < EL::SIZE; e += Cfg<D>::NT) out[e] = ei[e];
     return;
   }
-  filter_combine<D>(M, ei, ei + EL::SIZE, out, T.status, T.fail_bit);
+  filter_combine<D, U>(M, ei, ei + EL::SIZE, out, T.status, T.fail_bit);
 }
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) {
-  filter_up_body<D>(M, T, blockIdx.x);
+  filter_up_body<D, D / 4>(M, T, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -938,7 +938,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up(KModel M, TreeArgs T) 
 // with P = L L', W = I + L' J L and M = L W^{-1} L' = (P^{-1} + J)^{-1},
 //   m' = A (m + M (eta - J m)) + b,   P' = A M A' + C,
 // and, when lcout is given, the normaliser as in filter_combine with b_i = m.
-template <int D>
+template <int D, int U = 4>
 __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pin,
                                                const double* min_, const double* el,
                                                double* Pout, double* mout, int* status,
@@ -968,19 +968,19 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
   ok = chol_reg<D>(R1, d, S3, &ld) && ok;  // R1 = L
   rm_stage<D>(R1, S0);
   team_sync();
-  gemm<D, false, false, false>(R2, S1, S0);  // J L
+  gemm<D, false, false, false, U>(R2, S1, S0);  // J L
   rm_stage<D>(R2, S2);
   team_sync();
-  gemm<D, true, false, false>(R2, S0, S2);  // L' J L
+  gemm<D, true, false, false, U>(R2, S0, S2);  // L' J L
   AKF_RM_FOR(D, q, r, i, j) if (i == j && i < d) R2.t[q][r] += 1.0;
   ok = spd_inv<D>(R2, d, S3, &ld) && ok;  // W^{-1}
   const double ldW = ld;
   rm_stage<D>(R2, S2);
   team_sync();
-  gemm<D, false, false, false>(R1, S0, S2);  // L W^{-1}
+  gemm<D, false, false, false, U>(R1, S0, S2);  // L W^{-1}
   rm_stage<D>(R1, S3);
   team_sync();
-  gemm<D, false, true, false>(R2, S3, S0);  // M
+  gemm<D, false, true, false, U>(R2, S3, S0);  // M
   matvec<D, false>(vc, S1, vm);             // J m
   team_sync();
   rm_stage<D>(R2, S2);  // S2 = M
@@ -993,11 +993,11 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
         tid < D ? vm[tid] * (el[EL::eta + tid] + vc[tid]) + vc[tid] * vw[tid] : 0.0, red);
     if (tid == 0) *lcout = *lcin + el[EL::lc] - 0.5 * ldW + 0.5 * q;
   }
-  gemm<D, false, false, false>(R1, S3, S2);  // A M
+  gemm<D, false, false, false, U>(R1, S3, S2);  // A M
   rm_stage<D>(R1, S0);
   team_sync();
   if (tid < D) vw[tid] += vm[tid];
-  gemm<D, false, true, false>(R2, S0, S3);  // A M A'
+  gemm<D, false, true, false, U>(R2, S0, S3);  // A M A'
   rm_axpy<D>(R2, 1.0, Ce);
   team_sync();
   matvec<D, false>(vz, S3, vw);
@@ -1008,7 +1008,7 @@ __device__ __forceinline__ void moment_combine(const KModel& M, const double* Pi
 }
 
 
-template <int D>
+template <int D, int U = 4>
 __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs& T, int item) {
   using C = Cfg<D>;
   using EL = ElemLayout<D>;
@@ -1028,7 +1028,7 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
     if (tid == 0) pr[PL::flag] = 0.0;
     return;
   }
-  moment_combine<D>(M, pin + PL::P, pin + PL::m, el, pr + PL::P, pr + PL::m, T.status,
+  moment_combine<D, U>(M, pin + PL::P, pin + PL::m, el, pr + PL::P, pr + PL::m, T.status,
                     T.fail_bit);
   if (tid == 0) pr[PL::flag] = 0.0;
 }
@@ -1037,7 +1037,7 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
 // k < 2s the left operand covers block 0, so it is a filtering moment pair
 // (A = 0, J = 0): the combine reduces to the moment update and the result is
 // again a moment pair.
-template <int D>
+template <int D, int U = 4>
 __device__ __forceinline__ void filter_hs_body(const KModel& M, const HsArgs& H, int k) {
   using EL = ElemLayout<D>;
   const int tid = threadIdx.x;
@@ -1049,7 +1049,7 @@ __device__ __forceinline__ void filter_hs_body(const KModel& M, const HsArgs& H,
   }
   const double* ei = H.src + (int64_t)(k - H.s) * EL::SIZE;
   if (k < 2 * H.s) {
-    moment_combine<D>(M, ei + EL::C, ei + EL::b, ej, out + EL::C, out + EL::b, H.status,
+    moment_combine<D, U>(M, ei + EL::C, ei + EL::b, ej, out + EL::C, out + EL::b, H.status,
                       H.fail_bit, ei + EL::lc, out + EL::lc);
     for (int e = tid; e < D * D; e += Cfg<D>::NT) {
       out[EL::A + e] = 0.0;
@@ -1057,18 +1057,18 @@ __device__ __forceinline__ void filter_hs_body(const KModel& M, const HsArgs& H,
     }
     if (tid < D) out[EL::eta + tid] = 0.0;
   } else {
-    filter_combine<D>(M, ei, ej, out, H.status, H.fail_bit);
+    filter_combine<D, U>(M, ei, ej, out, H.status, H.fail_bit);
   }
 }
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_hs(KModel M, HsArgs H) {
-  filter_hs_body<D>(M, H, blockIdx.x);
+  filter_hs_body<D, D / 4>(M, H, blockIdx.x);
 }
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T) {
-  filter_down_body<D>(M, T, blockIdx.x);
+  filter_down_body<D, D / 4>(M, T, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1077,7 +1077,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_down(KModel M, TreeArgs T
 // form likelihood term ell_t = log N(omega_t; m^p_t, P^p_t + Omega_t).
 // Writes m^f_t, P^f_t (when requested) and ell_t.
 // ---------------------------------------------------------------------------
-template <int D, int OBS>
+template <int D, int OBS, int U = 4>
 __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterArgs& P, int item) {
   using C = Cfg<D>;
   using PL = PrefLayout<D>;
@@ -1128,11 +1128,11 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       rm_load<D>(Pp, M.Q, d, d);  // issued early: its latency overlaps F P
       rm_stage<D>(Pm, B1);
       team_sync();
-      gemm<D, false, false, false>(T, sF, B1);
+      gemm<D, false, false, false, U>(T, sF, B1);
       team_sync();
       rm_stage<D>(T, B1);
       team_sync();
-      gemm<D, false, true, true>(Pp, B1, sF);  // Q + (F P) F'
+      gemm<D, false, true, true, U>(Pp, B1, sF);  // Q + (F P) F'
       matvec<D, false>(vmp, sF, vm);
       team_sync();
       if (tid < d && bt) vmp[tid] += bt[tid];
@@ -1156,7 +1156,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
       rm_stage<D>(R2, B3);
       rm_stage<D>(Pp, B1);
       team_sync();
-      gemm<D, false, false, false>(Pm, B3, B1);  // S^{-1} Pp
+      gemm<D, false, false, false, U>(Pm, B3, B1);  // S^{-1} Pp
       matvec<D, false>(vs, B3, vw);
       AKF_RM_FOR(D, q, r, i, j) Pm.t[q][r] *= vom[i];
       const double rr = team_sum<D>(tid < D ? vw[tid] * vs[tid] : 0.0, red);
@@ -1172,11 +1172,11 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
     rm_stage<D>(Pp, B1);
     if constexpr (GH) {
       team_sync();
-      gemm<D, false, false, false>(T, sH, B1);  // H Pp
+      gemm<D, false, false, false, U>(T, sH, B1);  // H Pp
       team_sync();
       rm_stage<D>(T, B1);
       team_sync();
-      gemm<D, false, true, false>(R2, B1, sH);
+      gemm<D, false, true, false, U>(R2, B1, sH);
       rm_add_load<D>(R2, P.Ro, P.dyo, P.dyo);
       matvec<D, false>(vw, sH, vmp);
       team_sync();
@@ -1195,12 +1195,12 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
     ok = spd_inv<D>(R2, dobs, B2, &logdet) && ok;
     rm_stage<D>(R2, B3);
     team_sync();
-    gemm<D, false, false, false>(T, B3, B1);  // S^{-1} Mo
+    gemm<D, false, false, false, U>(T, B3, B1);  // S^{-1} Mo
     matvec<D, false>(vs, B3, vw);
     team_sync();
     rm_stage<D>(T, B2);
     const double rr = team_sum<D>(tid < D ? vw[tid] * vs[tid] : 0.0, red);
-    gemm<D, true, false, false>(Pm, B1, B2);  // Mo' S^{-1} Mo
+    gemm<D, true, false, false, U>(Pm, B1, B2);  // Mo' S^{-1} Mo
     rm_rsub<D>(Pm, Pp);  // P^f = Pp - Mo' S^{-1} Mo
     matvec<D, true>(vm, B1, vs, vmp);  // m^f = m^p + Mo' S^{-1} w
     if (tid == 0) P.ell[t] = -0.5 * (dobs * LOG2PI + logdet + rr);
@@ -1215,7 +1215,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
 
 template <int D, int OBS>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArgs P) {
-  filter_final_body<D, OBS>(M, P, blockIdx.x);
+  filter_final_body<D, OBS, D / 4>(M, P, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1319,7 +1319,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT, 2) k_samp_build(KModel M, SampArgs
 
 // Sampler, block fold: suffix aggregate (E~, U~) of a block, folding from its
 // last step backwards: (E~, U~) <- (E_t E~, E_t U~ + U_t).
-template <int D>
+template <int D, int U = 4>
 __device__ __forceinline__ void samp_fold_body(const KModel& M, const SampArgs& S, int item) {
   using C = Cfg<D>;
   extern __shared__ double lds[];
@@ -1336,7 +1336,7 @@ __device__ __forceinline__ void samp_fold_body(const KModel& M, const SampArgs& 
     lds_load_pad<D>(B1, S.E + (int64_t)t * D * D);
     rm_stage<D>(Et, B2);
     team_sync();
-    gemm<D, false, false, false>(Et, B1, B2);
+    gemm<D, false, false, false, U>(Et, B1, B2);
     matvec<D, false>(vn, B1, vu);
     team_sync();
     if (tid < D) vu[tid] = vn[tid] + S.U[(int64_t)t * D + tid];
@@ -1349,7 +1349,7 @@ __device__ __forceinline__ void samp_fold_body(const KModel& M, const SampArgs& 
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_fold(KModel M, SampArgs S) {
-  samp_fold_body<D>(M, S, blockIdx.x);
+  samp_fold_body<D, D / 4>(M, S, blockIdx.x);
 }
 
 // Sampler tree up-sweep: node k = left (earlier) o right = (E_l E_r, E_l U_r + U_l).

@@ -162,15 +162,19 @@ __device__ __forceinline__ void rm_symmetrise(RM<D>& a, double* s) {
   team_sync();
 }
 
-// c = op(A) op(B) (+ c when ACC), A and B D x D in LDS.
-template <int D, bool TA, bool TB, bool ACC>
+// c = op(A) op(B) (+ c when ACC), A and B D x D in LDS.  U k-steps per
+// unrolled iteration: the full D / 4 lets every operand load issue ahead of
+// the products that need it (one team at D = 64: 4.4k cycles, against 6.5k
+// with U = 4), at the price of registers, so kernels near the register limit
+// keep U = 4.
+template <int D, bool TA, bool TB, bool ACC, int U = 4>
 __device__ __forceinline__ void gemm(RM<D>& c, const double* sA, const double* sB) {
   using C = Cfg<D>;
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int r0 = (D == 64) ? 32 * (w >> 1) : 0, c0 = (D == 64) ? 32 * (w & 1) : 0;
   const int li = l & 15, lk = l >> 4;
   if (!ACC) rm_zero<D>(c);
-#pragma unroll 4
+#pragma unroll U
   for (int kb = 0; kb < D / 4; ++kb) {
     const int k = 4 * kb + lk;
     double a[C::TS], b[C::TS];
