@@ -605,7 +605,7 @@ __device__ __forceinline__ void lds_load_rect(double* s, const double* __restric
 // FIRST: the block contains t = 0 (its element has A = 0 and J = 0).  The
 // two cases are compiled separately so that A and T hold no registers across
 // the inverse.
-template <int D, int OBS, bool FIRST>
+template <int D, int OBS, bool FIRST, int U = 4>
 __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterArgs& P, int item) {
   using C = Cfg<D>;
   constexpr bool GH = (OBS == OBS_GH);
@@ -659,18 +659,18 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       rm_load<D>(Pp, M.Q, d, d);  // issued early: its latency overlaps F C
       rm_stage<D>(Cc, B1);
       team_sync();
-      gemm<D, false, false, false>(T, sF, B1);  // F C
+      gemm<D, false, false, false, U>(T, sF, B1);  // F C
       team_sync();
       rm_stage<D>(T, B1);
       team_sync();
-      gemm<D, false, true, true>(Pp, B1, sF);  // Q + (F C) F'
+      gemm<D, false, true, true, U>(Pp, B1, sF);  // Q + (F C) F'
       matvec<D, false>(vmu, sF, vb);
       team_sync();
       if (tid < d && bt) vmu[tid] += bt[tid];
       if (!first) {
         rm_stage<D>(A, B1);
         team_sync();
-        gemm<D, false, false, false>(T, sF, B1);  // T = F A
+        gemm<D, false, false, false, U>(T, sF, B1);  // T = F A
       }
       team_sync();
     }
@@ -692,16 +692,16 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       ok = spd_inv<D>(R2, d, B2, &logdet) && ok;  // R2 = S^{-1}
       rm_stage<D>(R2, B2);
       team_sync();
-      gemm<D, false, false, false>(Cc, B2, B1);  // S^{-1} Pp
+      gemm<D, false, false, false, U>(Cc, B2, B1);  // S^{-1} Pp
       AKF_RM_FOR(D, q, r, i, j) Cc.t[q][r] *= vom[i];
       matvec<D, false>(vs, B2, vw);  // S^{-1} w
       ld_sum += logdet;
       if (tid < D) q_part += vw[tid] * vs[tid];
       if (!first) {
-        gemm<D, false, false, false>(R1, B2, B3);  // S^{-1} T
+        gemm<D, false, false, false, U>(R1, B2, B3);  // S^{-1} T
         rm_stage<D>(R1, B1);
         team_sync();
-        gemm<D, true, false, true>(J, B3, B1);  // J += T' S^{-1} T
+        gemm<D, true, false, true, U>(J, B3, B1);  // J += T' S^{-1} T
         AKF_RM_FOR(D, q, r, i, j) A.t[q][r] = vom[i] * R1.t[q][r];
         matvec<D, true>(veta, B3, vs, veta);  // eta += T' S^{-1} w
       }
@@ -713,11 +713,11 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
     rm_stage<D>(Pp, B1);
     if constexpr (GH) {
       team_sync();
-      gemm<D, false, false, false>(R1, sH, B1);  // H Pp
+      gemm<D, false, false, false, U>(R1, sH, B1);  // H Pp
       team_sync();
       rm_stage<D>(R1, B1);
       team_sync();
-      gemm<D, false, true, false>(R2, B1, sH);  // H Pp H'
+      gemm<D, false, true, false, U>(R2, B1, sH);  // H Pp H'
       rm_add_load<D>(R2, P.Ro, P.dyo, P.dyo);
       matvec<D, false>(vw, sH, vmu);
       team_sync();
@@ -736,14 +736,14 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
     ok = spd_inv<D>(R2, dobs, B2, &logdet) && ok;  // R2 = S^{-1}
     rm_stage<D>(R2, B3);
     team_sync();
-    gemm<D, false, false, false>(R1, B3, B1);  // S^{-1} Mo
+    gemm<D, false, false, false, U>(R1, B3, B1);  // S^{-1} Mo
     matvec<D, false>(vs, B3, vw);              // S^{-1} w
     ld_sum += logdet;
     if (tid < D) q_part += vw[tid] * vs[tid];
     team_sync();
     rm_stage<D>(R1, B2);
     team_sync();
-    gemm<D, true, false, false>(Cc, B1, B2);  // Mo' S^{-1} Mo
+    gemm<D, true, false, false, U>(Cc, B1, B2);  // Mo' S^{-1} Mo
     rm_rsub<D>(Cc, Pp);  // C = Pp - Mo' S^{-1} Mo
     matvec<D, true>(vb, B1, vs, vmu);  // b = mu + Mo' S^{-1} w
     if (!first) {
@@ -751,17 +751,17 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       rm_stage<D>(T, B2);  // B2 <- Mt (T, or H T)
       if constexpr (GH) {
         team_sync();
-        gemm<D, false, false, false>(R1, sH, B2);  // H T
+        gemm<D, false, false, false, U>(R1, sH, B2);  // H T
         team_sync();
         rm_stage<D>(R1, B2);
       }
       team_sync();
-      gemm<D, false, false, false>(R1, B3, B2);  // S^{-1} Mt
+      gemm<D, false, false, false, U>(R1, B3, B2);  // S^{-1} Mt
       team_sync();
       rm_stage<D>(R1, B3);
       team_sync();
-      gemm<D, true, false, true>(J, B2, B3);   // J += Mt' S^{-1} Mt
-      gemm<D, true, false, false>(A, B1, B3);  // Mo' S^{-1} Mt
+      gemm<D, true, false, true, U>(J, B2, B3);   // J += Mt' S^{-1} Mt
+      gemm<D, true, false, false, U>(A, B1, B3);  // Mo' S^{-1} Mt
       rm_rsub<D>(A, T);  // A = T - Mo' S^{-1} Mt
       matvec<D, true>(veta, B2, vs, veta);  // eta += Mt' S^{-1} w
     } else if (first) {
@@ -787,17 +787,20 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
   if (tid == 0) out[ElemLayout<D>::lc] = -0.5 * ((s1 - s0) * dobs * LOG2PI + ld_sum + q);
 }
 
-template <int D, int OBS>
+template <int D, int OBS, int U = 4>
 __device__ __forceinline__ void filter_fold_body(const KModel& M, const FilterArgs& P, int item) {
   if (item == 0)
-    filter_fold_impl<D, OBS, true>(M, P, item);
+    filter_fold_impl<D, OBS, true, U>(M, P, item);
   else
-    filter_fold_impl<D, OBS, false>(M, P, item);
+    filter_fold_impl<D, OBS, false, U>(M, P, item);
 }
 
 template <int D, int OBS>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs P) {
-  filter_fold_body<D, OBS>(M, P, blockIdx.x);
+  // k-steps per unrolled GEMM iteration: the most that fits the register budget
+  // without spills (the D = 64 diagonal fold holds 512 registers per lane)
+  constexpr int U = (D < 64) ? D / 4 : (OBS == OBS_DIAG ? 8 : 4);
+  filter_fold_body<D, OBS, U>(M, P, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1225,7 +1228,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArg
 //   g_t = m^f - E_t (F m^f + bias),            U_t = g_t + chol(L_t) xi_t.
 // Terminal step: E = 0, U = m^f + chol(P^f) xi.
 // ---------------------------------------------------------------------------
-template <int D>
+template <int D, int U = 4>
 __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs& S, int item) {
   // two LDS matrices (X, Y), so that two teams share a CU: both buffers serve
   // the inverse as scratch, and G = F P^f is formed again after it
@@ -1267,11 +1270,11 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     const double* bt = S.Ft ? S.bt + (int64_t)(t + 1) * d : M.b;
     rm_stage<D>(Pf, Y);
     team_sync();
-    gemm<D, false, false, false>(R1, X, Y);  // G = F P^f
+    gemm<D, false, false, false, U>(R1, X, Y);  // G = F P^f
     team_sync();
     rm_stage<D>(R1, Y);  // Y = G
     team_sync();
-    gemm<D, false, true, true>(R2, Y, X);  // Q + G F'
+    gemm<D, false, true, true, U>(R2, Y, X);  // Q + G F'
     matvec<D, false>(vmp, X, vm);
     if (tid < d && bt) vmp[tid] += bt[tid];
     {
@@ -1283,18 +1286,18 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     lds_load_mat<D>(X, S.Ft ? S.Ft + (int64_t)(t + 1) * d * d : M.F, d);  // X = F
     rm_stage<D>(Pf, Y);
     team_sync();
-    gemm<D, false, false, false>(R1, X, Y);  // G = F P^f
+    gemm<D, false, false, false, U>(R1, X, Y);  // G = F P^f
     team_sync();
     rm_stage<D>(R2, X);  // X = (P^p)^{-1}
     rm_stage<D>(R1, Y);  // Y = G
     team_sync();
-    gemm<D, true, false, false>(R1, Y, X);  // E = G' (P^p)^{-1}
+    gemm<D, true, false, false, U>(R1, Y, X);  // E = G' (P^p)^{-1}
     rm_store<D>(R1, S.E + (int64_t)t * D * D, D, D);
     if (S.Et) rm_store_t<D>(R1, S.Et + (int64_t)t * D * D, D);
     team_sync();
     rm_stage<D>(R1, X);  // X = E
     team_sync();
-    gemm<D, false, false, false>(R2, X, Y);  // E G
+    gemm<D, false, false, false, U>(R2, X, Y);  // E G
     rm_rsub<D>(R2, Pf);                      // L_t = P^f - E G
     matvec<D, false>(vg, X, vmp);
     if (tid < D) vg[tid] = vm[tid] - vg[tid];  // g = m^f - E m^p
@@ -1314,7 +1317,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT, 2) k_samp_build(KModel M, SampArgs S) {
-  samp_build_body<D>(M, S, blockIdx.x);
+  samp_build_body<D, (D == 64 ? 8 : D / 4)>(M, S, blockIdx.x);  // no more spills than U = 4
 }
 
 // Sampler, block fold: suffix aggregate (E~, U~) of a block, folding from its
@@ -1903,7 +1906,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_final(BatchLaunch L, int rev) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
-    filter_final_body<D, OBS_DIAG>(c.M, rev ? c.Fr : c.Ff, I.i);
+    filter_final_body<D, OBS_DIAG, D / 4>(c.M, rev ? c.Fr : c.Ff, I.i);
     __syncthreads();
   }
 }
@@ -1927,7 +1930,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_down(BatchLaunch L, int level, 
     const ChainDev& c = L.cd[I.c];
     TreeArgs T = c.fdown[level - 1];
     T.fail_bit = rev ? ST_REV_NOT_PD : ST_FWD_NOT_PD;
-    filter_down_body<D>(c.M, T, I.i);
+    filter_down_body<D, (D < 64 ? D / 4 : 4)>(c.M, T, I.i);
     __syncthreads();
   }
 }
@@ -1942,7 +1945,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT, D == 64 ? 1 : 2) kb_sbuild(BatchLa
     const ChainDev& c = L.cd[I.c];
     SampArgs S = c.S;
     S.xi_x = c.xi_base + (int64_t)s * c.xi_stride + (int64_t)c.M.N * c.M.d;
-    samp_build_body<D>(c.M, S, I.i);
+    samp_build_body<D>(c.M, S, I.i);  // two teams per SIMD: the register budget keeps U = 4
     __syncthreads();
   }
 }
@@ -1952,7 +1955,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_sfold(BatchLaunch L) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
-    samp_fold_body<D>(c.M, c.S, I.i);
+    samp_fold_body<D, D / 4>(c.M, c.S, I.i);
     __syncthreads();
   }
 }
