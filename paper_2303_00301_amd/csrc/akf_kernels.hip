@@ -1335,10 +1335,24 @@ __device__ __forceinline__ void samp_fold_body(const KModel& M, const SampArgs& 
   RM<D> Et;
   rm_load<D>(Et, S.E + (int64_t)(s1 - 1) * D * D, D, D);
   if (tid < D) vu[tid] = S.U[(int64_t)(s1 - 1) * D + tid];
+  // E of the next step is fetched into registers while this step's products
+  // run, so the loop does not wait on HBM (each thread holds PER entries)
+  constexpr int PER = D * D / C::NT;
+  double pre[PER];
+  auto fetch = [&](int t) {
+#pragma unroll
+    for (int m = 0; m < PER; ++m) pre[m] = S.E[(int64_t)t * D * D + tid + m * C::NT];
+  };
+  if (s1 - 2 >= s0) fetch(s1 - 2);
   for (int t = s1 - 2; t >= s0; --t) {
-    lds_load_pad<D>(B1, S.E + (int64_t)t * D * D);
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int e = tid + m * C::NT;
+      B1[(e / D) * C::LD + e % D] = pre[m];
+    }
     rm_stage<D>(Et, B2);
     team_sync();
+    if (t - 1 >= s0) fetch(t - 1);
     gemm<D, false, false, false, U>(Et, B1, B2);
     matvec<D, false>(vn, B1, vu);
     team_sync();
