@@ -70,6 +70,10 @@ struct EglState {  // suffix state entering a node from the right
   static constexpr int SIZE = D * D + D;
 };
 
+// The GEMMs of the scan kernels, the smoother's and the adjoint's element
+// builds are fully unrolled (U = D / 4); the gradient kernel, at its register
+// limit, keeps the default.
+//
 // acc <- e_t o acc for t = s1-2 .. s0, starting from acc = e_{s1-1}.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_egl_fold(EglArgs A) {
@@ -92,14 +96,14 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_egl_fold(EglArgs A) {
     rm_stage<D>(Et, B2);
     rm_stage<D>(Lt, B3);
     team_sync();
-    gemm<D, false, false, false>(Et, B1, B2);  // E_t E~
-    gemm<D, false, false, false>(T, B1, B3);   // E_t L~
+    gemm<D, false, false, false, D / 4>(Et, B1, B2);  // E_t E~
+    gemm<D, false, false, false, D / 4>(T, B1, B3);   // E_t L~
     matvec<D, false>(vn, B1, vg);
     team_sync();
     rm_stage<D>(T, B3);
     if (tid < D) vg[tid] = vn[tid] + (A.g ? A.g[(int64_t)t * D + tid] : 0.0);
     team_sync();
-    gemm<D, false, true, false>(Lt, B3, B1);  // (E_t L~) E_t'
+    gemm<D, false, true, false, D / 4>(Lt, B3, B1);  // (E_t L~) E_t'
     rm_add_load<D>(Lt, A.L + (int64_t)t * D * D, D, D);
     rm_symmetrise<D>(Lt, B2);
   }
@@ -133,15 +137,15 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_egl_up(EglTree T) {
   if (tid < D) vg[tid] = er[EL::g + tid];
   team_sync();
   RM<D> R1, R2;
-  gemm<D, false, false, false>(R1, B1, B2);  // E_l E_r
-  gemm<D, false, false, false>(R2, B1, B3);  // E_l L_r
+  gemm<D, false, false, false, D / 4>(R1, B1, B2);  // E_l E_r
+  gemm<D, false, false, false, D / 4>(R2, B1, B3);  // E_l L_r
   matvec<D, false>(vn, B1, vg);
   rm_store<D>(R1, out + EL::E, D, D);
   team_sync();
   rm_stage<D>(R2, B3);
   if (tid < D) out[EL::g + tid] = vn[tid] + el[EL::g + tid];
   team_sync();
-  gemm<D, false, true, false>(R1, B3, B1);  // E_l L_r E_l'
+  gemm<D, false, true, false, D / 4>(R1, B3, B1);  // E_l L_r E_l'
   rm_add_load<D>(R1, el + EL::L, D, D);
   rm_symmetrise<D>(R1, B2);
   rm_store<D>(R1, out + EL::L, D, D);
@@ -175,13 +179,13 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_egl_down(EglTree T) {
   if (tid < D) vg[tid] = sin[ES::g + tid];
   team_sync();
   RM<D> R1;
-  gemm<D, false, false, false>(R1, B1, B2);  // E_r L
+  gemm<D, false, false, false, D / 4>(R1, B1, B2);  // E_r L
   matvec<D, false>(vn, B1, vg);
   team_sync();
   rm_stage<D>(R1, B2);
   if (tid < D) sl[ES::g + tid] = vn[tid] + er[EL::g + tid];
   team_sync();
-  gemm<D, false, true, false>(R1, B2, B1);  // E_r L E_r'
+  gemm<D, false, true, false, D / 4>(R1, B2, B1);  // E_r L E_r'
   rm_add_load<D>(R1, er + EL::L, D, D);
   rm_symmetrise<D>(R1, B2);
   rm_store<D>(R1, sl + ES::L, D, D);
@@ -207,13 +211,13 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_egl_final(EglArgs A) {
     lds_load_pad2<D>(B1, A.E + (int64_t)t * D * D);
     rm_stage<D>(Lm, B2);
     team_sync();
-    gemm<D, false, false, false>(T, B1, B2);
+    gemm<D, false, false, false, D / 4>(T, B1, B2);
     matvec<D, false>(vn, B1, vg);
     team_sync();
     rm_stage<D>(T, B2);
     if (tid < D) vg[tid] = vn[tid] + (A.g ? A.g[(int64_t)t * D + tid] : 0.0);
     team_sync();
-    gemm<D, false, true, false>(Lm, B2, B1);
+    gemm<D, false, true, false, D / 4>(Lm, B2, B1);
     rm_add_load<D>(Lm, A.L + (int64_t)t * D * D, D, D);
     rm_symmetrise<D>(Lm, B2);
     rm_store<D>(Lm, A.outL + (int64_t)t * A.ldo * A.ldo, A.ldo, A.dout);
@@ -253,11 +257,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   lds_load_user<D>(sF, M.F, d, d);
   rm_stage<D>(Pf, B1);
   team_sync();
-  gemm<D, false, false, false>(R1, sF, B1);  // G = F P^f
+  gemm<D, false, false, false, D / 4>(R1, sF, B1);  // G = F P^f
   team_sync();
   rm_stage<D>(R1, B1);
   team_sync();
-  gemm<D, false, true, true>(R2, B1, sF);  // Q + G F'
+  gemm<D, false, true, true, D / 4>(R2, B1, sF);  // Q + G F'
   matvec<D, false>(vmp, sF, vm);
   if (tid < d && M.b) vmp[tid] += M.b[tid];
   {
@@ -267,11 +271,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_smooth_build(KModel M, SmoothArg
   }
   rm_stage<D>(R2, B2);
   team_sync();
-  gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
+  gemm<D, true, false, false, D / 4>(R1, B1, B2);  // E = G' (P^p)^{-1}
   rm_store<D>(R1, S.E + (int64_t)t * D * D, D, D);
   rm_stage<D>(R1, B3);
   team_sync();
-  gemm<D, false, false, false>(R2, B3, B1);  // E G
+  gemm<D, false, false, false, D / 4>(R2, B3, B1);  // E G
   rm_rsub<D>(R2, Pf);                        // L = P^f - E G
   matvec<D, false>(vg, B3, vmp);
   if (tid < D) S.g[(int64_t)t * D + tid] = vm[tid] - vg[tid];
@@ -385,17 +389,17 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
   // h = H' w
   matvec<D, true>(G.U + (int64_t)t * D, sH, vw);
   // K = (H Pp)' S^{-1};  Sig = S^{-1} - w w'
-  gemm<D, true, false, false>(K, X, Y);
+  gemm<D, true, false, false, D / 4>(K, X, Y);
   rm_unstage<D>(R1, Y);
   AKF_RM_FOR(D, q, r, i, j) R1.t[q][r] -= vw[i] * vw[j];
   team_sync();
   // Cm = -1/2 H' Sig H
   rm_stage<D>(R1, X);
   team_sync();
-  gemm<D, false, false, false>(R2, X, sH);  // Sig H
+  gemm<D, false, false, false, D / 4>(R2, X, sH);  // Sig H
   rm_stage<D>(R2, Y);
   team_sync();
-  gemm<D, true, false, false>(R1, sH, Y);  // H' Sig H
+  gemm<D, true, false, false, D / 4>(R1, sH, Y);  // H' Sig H
   rm_axpy<D>(R1, -1.5, R1);                // -1/2 H' Sig H
   rm_store<D>(R1, G.Cm + (int64_t)t * D * D, D, D);
   if (t == M.N - 1) {
@@ -405,10 +409,10 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_build(KModel M, LgArgs G) {
     // Phi = F - (F K) H;  E = Phi'
     rm_stage<D>(K, X);
     team_sync();
-    gemm<D, false, false, false>(R2, sF, X);  // F K
+    gemm<D, false, false, false, D / 4>(R2, sF, X);  // F K
     rm_stage<D>(R2, Y);
     team_sync();
-    gemm<D, false, false, false>(R1, Y, sH);  // F K H
+    gemm<D, false, false, false, D / 4>(R1, Y, sH);  // F K H
     RM<D> Fm;
     rm_load<D>(Fm, M.F, d, d);
     rm_rsub<D>(R1, Fm);  // Phi = F - F K H
