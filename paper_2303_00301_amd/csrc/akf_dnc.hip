@@ -90,11 +90,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_dnc_leaf(KModel M, DncArgs A) {
   if (tid < D) vm[tid] = (tid < d) ? A.mf[(int64_t)t * A.ldm + tid] : 0.0;
   rm_stage<D>(Pf, B1);
   team_sync();
-  gemm<D, false, false, false>(R1, sF, B1);  // G = F P^f
+  gemm<D, false, false, false, D / 4>(R1, sF, B1);  // G = F P^f
   team_sync();
   rm_stage<D>(R1, B1);  // B1 = G
   team_sync();
-  gemm<D, false, true, true>(R2, B1, sF);  // P^p = Q + G F'
+  gemm<D, false, true, true, D / 4>(R2, B1, sF);  // P^p = Q + G F'
   matvec<D, false>(vmp, sF, vm);
   if (tid < d && bt) vmp[tid] += bt[tid];
   bool ok;
@@ -106,11 +106,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_dnc_leaf(KModel M, DncArgs A) {
   }
   rm_stage<D>(R2, B2);
   team_sync();
-  gemm<D, true, false, false>(R1, B1, B2);  // E = G' (P^p)^{-1}
+  gemm<D, true, false, false, D / 4>(R1, B1, B2);  // E = G' (P^p)^{-1}
   rm_store<D>(R1, A.Elf + (int64_t)t * D * D, D, D);
   rm_stage<D>(R1, B3);
   team_sync();
-  gemm<D, false, false, false>(R2, B3, B1);  // E G
+  gemm<D, false, false, false, D / 4>(R2, B3, B1);  // E G
   rm_rsub<D>(R2, Pf);                        // L = P^f - E G
   rm_symmetrise<D>(R2, B2);
   rm_store<D>(R2, A.Llf + (int64_t)t * D * D, D, D);
@@ -161,12 +161,12 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_dnc_up(KModel M, DncArgs A, int 
   rm_stage<D>(L2, B3);
   team_sync();
   RM<D> E;
-  gemm<D, false, false, false>(E, B1, B2);   // E = E1 E2
-  gemm<D, false, false, false>(T1, B1, B3);  // T1 = E1 L2
+  gemm<D, false, false, false, D / 4>(E, B1, B2);   // E = E1 E2
+  gemm<D, false, false, false, D / 4>(T1, B1, B3);  // T1 = E1 L2
   matvec<D, false>(vg, B1, vg2, vg1);        // g = E1 g2 + g1
   rm_stage<D>(T1, B4);
   team_sync();
-  gemm<D, false, true, true>(L, B4, B1);  // L = L1 + T1 E1'
+  gemm<D, false, true, true, D / 4>(L, B4, B1);  // L = L1 + T1 E1'
   rm_symmetrise<D>(L, B2);
   rm_store<D>(E, A.Eno + (int64_t)l * D * D, D, D);
   rm_store<D>(L, A.Lno + (int64_t)l * D * D, D, D);
@@ -182,18 +182,18 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_dnc_up(KModel M, DncArgs A, int 
   rm_stage<D>(R, B3);
   team_sync();
   RM<D> G;
-  gemm<D, true, false, false>(G, B4, B3);  // G = T1' L^{-1}
+  gemm<D, true, false, false, D / 4>(G, B4, B3);  // G = T1' L^{-1}
   team_sync();
   rm_stage<D>(G, B3);
   rm_stage<D>(E, B1);
   team_sync();
-  gemm<D, false, false, false>(R, B3, B1);  // G E
+  gemm<D, false, false, false, D / 4>(R, B3, B1);  // G E
   rm_rsub<D>(R, E2);                        // Gamma = E2 - G E
   rm_store<D>(G, A.Gb + (int64_t)l * D * D, D, D);
   rm_store<D>(R, A.Gam + (int64_t)l * D * D, D, D);
   matvec<D, false>(vw, B3, vg);  // G g
   if (tid < D) A.wb[(int64_t)l * D + tid] = vg2[tid] - vw[tid];
-  gemm<D, false, false, false>(R, B3, B4);  // G T1
+  gemm<D, false, false, false, D / 4>(R, B3, B4);  // G T1
   rm_rsub<D>(R, L2);                        // V = L2 - G E1 L2
   rm_symmetrise<D>(R, B2);
   ok = chol_reg<D>(R, d, scr, &ld) && ok;
