@@ -39,16 +39,13 @@ __device__ __forceinline__ void flag_status2(int* st, int bit) { atomicOr(st, bi
 
 template <int D>
 __device__ __forceinline__ void lds_load_pad2(double* s, const double* __restrict__ g) {
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) s[(e / D) * Cfg<D>::LD + (e % D)] = g[e];
+  lds_fill<D>(s, [=](int i, int j) { return g[i * D + j]; });
 }
 
 template <int D>
 __device__ __forceinline__ void lds_load_user(double* s, const double* __restrict__ g, int rows,
                                               int cols) {
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
-    const int i = e / D, j = e % D;
-    s[i * Cfg<D>::LD + j] = (i < rows && j < cols) ? g[i * cols + j] : 0.0;
-  }
+  lds_fill<D>(s, [=](int i, int j) { return (i < rows && j < cols) ? g[i * cols + j] : 0.0; });
 }
 
 template <int D>
@@ -127,7 +124,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_egl_up(EglTree T) {
   const double* el = T.src + (int64_t)(2 * k) * EL::SIZE;
   double* out = T.dst + (int64_t)k * EL::SIZE;
   if (2 * k + 1 >= T.n_src) {
-    for (int e = tid; e < EL::SIZE; e += C::NT) out[e] = el[e];
+    team_copy<C::NT>(out, el, EL::SIZE);
     return;
   }
   const double* er = el + EL::SIZE;
@@ -168,11 +165,11 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_egl_down(EglTree T) {
   const bool has_right = (2 * k + 1 < T.n_dst);
   double* sl = T.pre_dst + (int64_t)(2 * k) * ES::SIZE;
   if (!has_right) {
-    for (int e = tid; e < ES::SIZE; e += C::NT) sl[e] = sin[e];
+    team_copy<C::NT>(sl, sin, ES::SIZE);
     return;
   }
   double* sr = T.pre_dst + (int64_t)(2 * k + 1) * ES::SIZE;
-  for (int e = tid; e < ES::SIZE; e += C::NT) sr[e] = sin[e];
+  team_copy<C::NT>(sr, sin, ES::SIZE);
   const double* er = T.src + (int64_t)(2 * k + 1) * EL::SIZE;
   lds_load_pad2<D>(B1, er + EL::E);
   lds_load_pad2<D>(B2, sin + ES::L);

@@ -30,15 +30,12 @@ namespace {
 
 template <int D>
 __device__ __forceinline__ void load_pad(double* s, const double* __restrict__ g) {
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) s[(e / D) * Cfg<D>::LD + (e % D)] = g[e];
+  lds_fill<D>(s, [=](int i, int j) { return g[i * D + j]; });
 }
 
 template <int D>
 __device__ __forceinline__ void load_user(double* s, const double* __restrict__ g, int d) {
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
-    const int i = e / D, j = e % D;
-    s[i * Cfg<D>::LD + j] = (i < d && j < d) ? g[i * d + j] : 0.0;
-  }
+  lds_fill<D>(s, [=](int i, int j) { return (i < d && j < d) ? g[i * d + j] : 0.0; });
 }
 
 // Node slot i at depth j of the bisection tree of [0, T]; false when the slot

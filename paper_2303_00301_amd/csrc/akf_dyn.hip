@@ -14,6 +14,7 @@
 #include <stdint.h>
 
 #include "akf_internal.h"
+#include "akf_team.hpp"
 
 namespace akf {
 
@@ -80,7 +81,9 @@ __global__ void __launch_bounds__(64 * DW) k_dyn_lin(KModel M, DynArgs A) {
   const bool active = t >= 1 && t < M.N;
   const bool mis = A.z != nullptr;
   if (mis)
-    for (int e = tid; e < d * d; e += blockDim.x) sQ[(e / d) * 64 + e % d] = A.Qinv[e];
+    team_move<64 * DW, 64 * 64>(
+        d * d, [&](int e) { return A.Qinv[e]; },
+        [&](int e, double v) { sQ[(e / d) * 64 + e % d] = v; });
   if (lane < 64) {
     sa[w][lane] = (active && lane < d) ? A.a[(int64_t)(t - 1) * d + lane] : 0.0;
     sz[w][lane] = (active && mis && lane < d) ? A.z[(int64_t)(t - 1) * d + lane] : 0.0;

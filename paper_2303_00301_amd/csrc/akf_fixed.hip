@@ -98,7 +98,7 @@ __device__ __forceinline__ void gmv(double* y, const double* __restrict__ At, co
 
 template <int D>
 __device__ __forceinline__ void xload_pad(double* s, const double* __restrict__ g) {
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) s[(e / D) * Cfg<D>::LD + (e % D)] = g[e];
+  lds_fill<D>(s, [=](int i, int j) { return g[i * D + j]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -119,16 +119,16 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_phi(KModel M, FixedArgs A)
   if (t == 0) {
     rm_zero<D>(R);
     rm_store<D>(R, out, D, D);
-    for (int e = threadIdx.x; e < D * D; e += C::NT) {
-      const int j = e / D, i = e % D;
-      A.Fp[e] = (i < d && j < d) ? M.F[i * d + j] : 0.0;
-    }
+    team_move<C::NT, D * D>(
+        D * D,
+        [&](int e) {
+          const int j = e / D, i = e % D;
+          return (i < d && j < d) ? M.F[i * d + j] : 0.0;
+        },
+        [&](int e, double v) { A.Fp[e] = v; });
     return;
   }
-  for (int e = threadIdx.x; e < D * D; e += C::NT) {
-    const int i = e / D, j = e % D;
-    B1[i * C::LD + j] = (i < d && j < d) ? M.F[j * d + i] : 0.0;  // F^T
-  }
+  lds_fill<D>(B1, [&](int i, int j) { return (i < d && j < d) ? M.F[j * d + i] : 0.0; });  // F^T
   xload_pad<D>(B2, A.Sinv + (int64_t)t * D * D);  // the kept S^{-1} reads as S^{-T}
   team_sync();
   gemm<D, false, false, false>(R, B1, B2);  // (S^{-1} F)^T
@@ -172,7 +172,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_vtree_up_mat(const double* src, 
   const double* l = src + (int64_t)(2 * k) * D * D;
   double* out = dst + (int64_t)k * D * D;
   if (2 * k + 1 >= n_src) {
-    for (int e = threadIdx.x; e < D * D; e += C::NT) out[e] = l[e];
+    team_copy<C::NT>(out, l, D * D);
     return;
   }
   xload_pad<D>(B1, l + D * D);
@@ -217,10 +217,13 @@ struct MeanLds {
 template <int D>
 __device__ __forceinline__ void mean_lds_init(MeanLds<D>& L, const KModel& M) {
   const int d = M.d;
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
-    const int j = e / D, i = e % D;
-    L.Ft[e] = (i < d && j < d) ? M.F[i * d + j] : 0.0;
-  }
+  team_move<Cfg<D>::NT, D * D>(
+      D * D,
+      [&](int e) {
+        const int j = e / D, i = e % D;
+        return (i < d && j < d) ? M.F[i * d + j] : 0.0;
+      },
+      [&](int e, double v) { L.Ft[e] = v; });
   if (threadIdx.x < D) {
     L.b[threadIdx.x] = (M.b && threadIdx.x < d) ? M.b[threadIdx.x] : 0.0;
     L.m0[threadIdx.x] = (threadIdx.x < d) ? M.m0[threadIdx.x] : 0.0;
@@ -413,10 +416,13 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_vup_span(VTreeSpan T) {
   __shared__ double red[V::NT];
   const int k = blockIdx.x, tid = threadIdx.x;
   constexpr int C0 = 1 << R;
-  for (int e = tid; e < C0 * D; e += V::NT) {
-    const int c = e / D, j = k * C0 + c;
-    ph[0][c][e % D] = (j < T.n[0]) ? T.U[0][(int64_t)j * D + e % D] : 0.0;
-  }
+  team_move<V::NT, C0 * D>(
+      C0 * D,
+      [&](int e) {
+        const int j = k * C0 + e / D;
+        return (j < T.n[0]) ? T.U[0][(int64_t)j * D + e % D] : 0.0;
+      },
+      [&](int e, double v) { ph[0][e / D][e % D] = v; });
   team_sync();
   int cur = 0;
 #pragma unroll

@@ -548,7 +548,9 @@ __device__ __forceinline__ void build_S(double* s, const RM<D>& P, const double*
   team_sync();
   const int tid = threadIdx.x;
   if (dense) {
-    for (int e = tid; e < d * d; e += Cfg<D>::NT) s[(e / d) * Cfg<D>::LD + (e % d)] += dense[e];
+    team_move<Cfg<D>::NT, D * D, 4>(
+        d * d, [&](int e) { return dense[e]; },
+        [&](int e, double v) { s[(e / d) * Cfg<D>::LD + (e % d)] += v; });
   } else if (tid < d) {
     s[tid * Cfg<D>::LD + tid] += Om_t[tid];
   }
@@ -556,6 +558,9 @@ __device__ __forceinline__ void build_S(double* s, const RM<D>& P, const double*
 }
 
 // Load a d x d user matrix into an LDS buffer, zero padded.
+// (A rolled loop: its callers sit in per-step loops that hold most of the
+// register file, where the unrolled form of lds_fill keeps its addresses live
+// across the loop and spills.)
 template <int D>
 __device__ __forceinline__ void lds_load_mat(double* s, const double* __restrict__ g, int d) {
   for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) {
@@ -565,9 +570,15 @@ __device__ __forceinline__ void lds_load_mat(double* s, const double* __restrict
 }
 
 // Load a padded D x D workspace matrix into an LDS buffer.
-template <int D>
+// G = 0: a rolled loop, for persistent kernels, whose outer loop would keep
+// the unrolled form's addresses live (and spill).
+template <int D, int G = D * D / Cfg<D>::NT>
 __device__ __forceinline__ void lds_load_pad(double* s, const double* __restrict__ g) {
-  for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) s[(e / D) * Cfg<D>::LD + (e % D)] = g[e];
+  if constexpr (G == 0) {
+    for (int e = threadIdx.x; e < D * D; e += Cfg<D>::NT) s[(e / D) * Cfg<D>::LD + (e % D)] = g[e];
+  } else {
+    lds_fill<D, G>(s, [=](int i, int j) { return g[i * D + j]; });
+  }
 }
 
 template <int D>
@@ -818,7 +829,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 // Kalman filter"; lc is the constant of the Gaussian integral over the shared
 // state, with log det W = log det (I + C_i J_j)).
 // ---------------------------------------------------------------------------
-template <int D, int U = 4>
+template <int D, int U = 4, int G = D * D / Cfg<D>::NT>
 __device__ __forceinline__ void filter_combine(const KModel& M, const double* __restrict__ ei,
                                                const double* __restrict__ ej,
                                                double* __restrict__ out, int* status,
@@ -840,7 +851,7 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   double ld;
   RM<D> R1, R2, R3;
   rm_load<D>(R1, ei + EL::C, D, d);
-  lds_load_pad<D>(S1, ej + EL::J);
+  lds_load_pad<D, G>(S1, ej + EL::J);
   if (tid < D) vbi[tid] = ei[EL::b + tid];
   // the operands needed later are fetched now, so their HBM latency overlaps
   // the factorisations (no global stores precede the barriers until then)
@@ -912,17 +923,21 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   if (!ok && tid == 0) flag_status(status, fail_bit);
 }
 
-template <int D, int U = 4>
+template <int D, int U = 4, int G = D * D / Cfg<D>::NT>
 __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& T, int item) {
   using EL = ElemLayout<D>;
   const int k = item, tid = threadIdx.x;
   const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
   double* out = T.dst + (int64_t)k * EL::SIZE;
   if (2 * k + 1 >= T.n_src) {
-    for (int e = tid; e < EL::SIZE; e += Cfg<D>::NT) out[e] = ei[e];
+    if constexpr (G > 0) {
+      team_copy<Cfg<D>::NT>(out, ei, EL::SIZE);
+    } else {
+      for (int e = tid; e < EL::SIZE; e += Cfg<D>::NT) out[e] = ei[e];
+    }
     return;
   }
-  filter_combine<D, U>(M, ei, ei + EL::SIZE, out, T.status, T.fail_bit);
+  filter_combine<D, U, G>(M, ei, ei + EL::SIZE, out, T.status, T.fail_bit);
 }
 
 template <int D>
@@ -1021,12 +1036,12 @@ __device__ __forceinline__ void filter_down_body(const KModel& M, const TreeArgs
   const bool ident = pin[PL::flag] != 0.0;
   // left child: same prefix
   double* pl = T.pre_dst + (int64_t)(2 * k) * PL::SIZE;
-  for (int e = tid; e < PL::SIZE; e += C::NT) pl[e] = pin[e];
+  team_copy<C::NT>(pl, pin, PL::SIZE);
   if (2 * k + 1 >= T.n_dst) return;
   double* pr = T.pre_dst + (int64_t)(2 * k + 1) * PL::SIZE;
   const double* el = T.src + (int64_t)(2 * k) * EL::SIZE;  // left child's element
   if (ident) {
-    for (int e = tid; e < D * D; e += C::NT) pr[PL::P + e] = el[EL::C + e];
+    team_copy<C::NT>(pr + PL::P, el + EL::C, D * D);
     if (tid < D) pr[PL::m + tid] = el[EL::b + tid];
     if (tid == 0) pr[PL::flag] = 0.0;
     return;
@@ -1047,7 +1062,7 @@ __device__ __forceinline__ void filter_hs_body(const KModel& M, const HsArgs& H,
   const double* ej = H.src + (int64_t)k * EL::SIZE;
   double* out = H.dst + (int64_t)k * EL::SIZE;
   if (k < H.s) {
-    for (int e = tid; e < EL::SIZE; e += Cfg<D>::NT) out[e] = ej[e];
+    team_copy<Cfg<D>::NT>(out, ej, EL::SIZE);
     return;
   }
   const double* ei = H.src + (int64_t)(k - H.s) * EL::SIZE;
@@ -1383,7 +1398,7 @@ __device__ __forceinline__ void samp_up_body(const KModel& M, const TreeArgs& T,
   const double* el = T.src + (int64_t)(2 * k) * SL::SIZE;
   double* out = T.dst + (int64_t)k * SL::SIZE;
   if (2 * k + 1 >= T.n_src) {
-    for (int e = tid; e < SL::SIZE; e += C::NT) out[e] = el[e];
+    team_copy<C::NT>(out, el, SL::SIZE);
     return;
   }
   const double* er = el + SL::SIZE;
@@ -1392,7 +1407,7 @@ __device__ __forceinline__ void samp_up_body(const KModel& M, const TreeArgs& T,
   if (tid < D) vu[tid] = er[SL::U + tid];
   team_sync();
   RM<D> R;
-  gemm<D, false, false, false>(R, B1, B2);
+  gemm<D, false, false, false, D / 4>(R, B1, B2);
   matvec<D, false>(vn, B1, vu);
   rm_store<D>(R, out + SL::E, D, D);
   team_sync();
@@ -1932,7 +1947,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_up(BatchLaunch L, int level, in
     const ChainDev& c = L.cd[I.c];
     TreeArgs T = c.fup[level - 1];
     T.fail_bit = rev ? ST_REV_NOT_PD : ST_FWD_NOT_PD;
-    filter_up_body<D>(c.M, T, I.i);
+    filter_up_body<D, 4, 0>(c.M, T, I.i);
     __syncthreads();
   }
 }

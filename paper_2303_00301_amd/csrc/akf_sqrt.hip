@@ -93,13 +93,24 @@ __device__ __forceinline__ double team_sum(double v, double* red) {
 }
 
 // dst (LDS, D x D) <- a d x d array with leading dimension ld, zero padded.
-template <class T, int D, class S>
+// Every lane issues all of its loads before its first LDS write (a
+// lane-strided loop stays rolled and waits out each load in turn); with
+// SYNC = false the caller batches several loads under one barrier.
+template <class T, int D, bool SYNC = true, class S>
 __device__ __forceinline__ void ld_mat(T* dst, const S* src, int d, int ld) {
-  for (int e = threadIdx.x; e < D * D; e += NT) {
-    const int i = e / D, j = e % D;
-    dst[i * Dm<D>::LM + j] = (i < d && j < d) ? (T)src[(int64_t)i * ld + j] : T(0);
+  constexpr int PER = (D * D + NT - 1) / NT;
+  T v[PER];
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * NT, i = e / D, j = e % D;
+    v[k] = (e < D * D && i < d && j < d) ? (T)src[(int64_t)i * ld + j] : T(0);
   }
-  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < PER; ++k) {
+    const int e = threadIdx.x + k * NT;
+    if (e < D * D) dst[(e / D) * Dm<D>::LM + e % D] = v[k];
+  }
+  if constexpr (SYNC) __syncthreads();
 }
 
 // global dense D x D <- LDS matrix
@@ -490,7 +501,7 @@ __global__ void __launch_bounds__(NT) k_sq_fold(SqArgs<T> P) {
   T *vb = c.v[0], *veta = c.v[1], *vmu = c.v[2], *vw = c.v[3], *vs = c.v[4], *vt = c.v[5];
   const int d = P.d, blk = blockIdx.x, tid = threadIdx.x;
   const int s0 = blk * P.B, s1 = min(P.N, s0 + P.B);
-  ld_mat<T, D>(sF, P.Fs, D, D);
+  ld_mat<T, D, false>(sF, P.Fs, D, D);
   ld_mat<T, D>(sLQ, P.LQ, D, D);
   set_eye<T, D>(sA, d, blk == 0 ? T(0) : T(1));
   set_eye<T, D>(sU, d, T(0));
@@ -563,7 +574,19 @@ __global__ void __launch_bounds__(NT) k_sq_hs(SqArgs<T> P) {
   const T* ej = P.el_in + (int64_t)k * El<D>::SIZE;
   T* out = P.el_out + (int64_t)k * El<D>::SIZE;
   if (k < s) {
-    for (int e = tid; e < El<D>::SIZE; e += NT) out[e] = ej[e];
+    for (int base = 0; base < El<D>::SIZE; base += 8 * NT) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * NT + tid;
+        v[u] = e < El<D>::SIZE ? ej[e] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = base + u * NT + tid;
+        if (e < El<D>::SIZE) out[e] = v[u];
+      }
+    }
     if (tid == 0) P.lc_out[k] = P.lc_in[k];
     return;
   }
@@ -573,11 +596,11 @@ __global__ void __launch_bounds__(NT) k_sq_hs(SqArgs<T> P) {
     *X11 = c.m[6], *X21 = c.m[7], *X22 = c.m[8], *G = c.m[9], *Mm = c.m[10], *Tm = c.m[11];
   T *bi = c.v[0], *eti = c.v[1], *bj = c.v[2], *etj = c.v[3], *vc = c.v[4], *v1 = c.v[5],
     *v2 = c.v[6], *v3 = c.v[7];
-  ld_mat<T, D>(Ui, ei + El<D>::U, D, D);
-  ld_mat<T, D>(Zj, ej + El<D>::Z, D, D);
-  ld_mat<T, D>(Ai, ei + El<D>::A, D, D);
-  ld_mat<T, D>(Aj, ej + El<D>::A, D, D);
-  ld_mat<T, D>(Uj, ej + El<D>::U, D, D);
+  ld_mat<T, D, false>(Ui, ei + El<D>::U, D, D);
+  ld_mat<T, D, false>(Zj, ej + El<D>::Z, D, D);
+  ld_mat<T, D, false>(Ai, ei + El<D>::A, D, D);
+  ld_mat<T, D, false>(Aj, ej + El<D>::A, D, D);
+  ld_mat<T, D, false>(Uj, ej + El<D>::U, D, D);
   ld_mat<T, D>(Zi, ei + El<D>::Z, D, D);
   if (tid < D) {
     bi[tid] = ei[El<D>::b + tid];
@@ -670,7 +693,7 @@ __global__ void __launch_bounds__(NT) k_sq_final(SqArgs<T> P) {
   T *vm = c.v[0], *vmp = c.v[1], *vs = c.v[2];
   const int d = P.d, blk = blockIdx.x, tid = threadIdx.x;
   const int s0 = blk * P.B, s1 = min(P.N, s0 + P.B);
-  ld_mat<T, D>(sF, P.Fs, D, D);
+  ld_mat<T, D, false>(sF, P.Fs, D, D);
   ld_mat<T, D>(sLQ, P.LQ, D, D);
   if (blk > 0) {
     const T* pre = P.el_in + (int64_t)(blk - 1) * El<D>::SIZE;  // prefix through block blk-1
@@ -737,7 +760,7 @@ __global__ void __launch_bounds__(NT) k_sq_sbuild(SqArgs<T> P) {
     if (tid < D) P.Ut[(int64_t)t * D + tid] = vo[tid];
     return;
   }
-  ld_mat<T, D>(sF, P.Fs, D, D);
+  ld_mat<T, D, false>(sF, P.Fs, D, D);
   ld_mat<T, D>(sLQ, P.LQ, D, D);
   mm<T, D, false, false>(sX, sF, sU, d);
   to_w<T, D, false>(c.W, 0, 0, sLQ, d);

@@ -137,6 +137,65 @@ __device__ __forceinline__ void rm_unstage(RM<D>& a, const double* s) {
   AKF_RM_FOR(D, q, r, i, j) a.t[q][r] = s[i * Cfg<D>::LD + j];
 }
 
+// store(e, load(e)) for every e < n (n <= CAP) by a team of NT threads, each
+// lane issuing G loads before their stores (all of them by default).  A
+// lane-strided loop (e = tid; e < n; e += NT) has no trip count the compiler
+// can see, stays rolled and waits out one memory latency per iteration (16
+// round trips for a 64 x 64 matrix over 256 lanes, about 20k cycles).  Code
+// that holds most of the register file passes a small G: each group of G
+// loads costs one round trip and 2 G registers.
+template <int NT, int CAP, int G = (CAP + NT - 1) / NT, typename L, typename S>
+__device__ __forceinline__ void team_move(int n, L load, S store) {
+  constexpr int PER = (CAP + NT - 1) / NT;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int k0 = 0; k0 < PER; k0 += G) {
+    double v[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int e = tid + (k0 + k) * NT;
+      v[k] = (k0 + k < PER && e < n) ? load(e) : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+      const int e = tid + (k0 + k) * NT;
+      if (k0 + k < PER && e < n) store(e, v[k]);
+    }
+  }
+}
+
+// LDS matrix s (leading dimension LD) from element (i, j) = at(i, j) of the
+// D x D block, read from global memory by the whole team, G loads per lane
+// in flight (see team_move).
+template <int D, int G = D * D / Cfg<D>::NT, typename F>
+__device__ __forceinline__ void lds_fill(double* s, F at) {
+  using C = Cfg<D>;
+  team_move<C::NT, D * D, G>(
+      D * D, [&](int e) { return at(e / D, e % D); },
+      [&](int e, double v) { s[(e / D) * C::LD + (e % D)] = v; });
+}
+
+// dst[e] = src[e] for e < n by NT threads, eight loads per lane in flight
+// before their stores (same reason as lds_fill).
+template <int NT>
+__device__ __forceinline__ void team_copy(double* __restrict__ dst,
+                                          const double* __restrict__ src, int n) {
+  const int tid = threadIdx.x;
+  for (int base = 0; base < n; base += 8 * NT) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = base + k * NT + tid;
+      v[k] = e < n ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const int e = base + k * NT + tid;
+      if (e < n) dst[e] = v[k];
+    }
+  }
+}
+
 // y += alpha * x
 template <int D>
 __device__ __forceinline__ void rm_axpy(RM<D>& y, double alpha, const RM<D>& x) {
