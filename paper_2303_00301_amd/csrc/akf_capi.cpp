@@ -37,6 +37,7 @@ StepArgs make_step_args(const Layout& Lo, void* ws, const double* y, const doubl
   A.part_lh_xs = at<double>(ws, Lo.plhxs);
   A.part_terms = at<double>(ws, Lo.pterms);
   A.g_G = at<double>(ws, Lo.gG);
+  A.g_Ht = at<double>(ws, Lo.gHt);
   A.g_Rinv = at<double>(ws, Lo.gRinv);
   A.g_Omd = at<double>(ws, Lo.gOmd);
   A.g_Omd_inv = at<double>(ws, Lo.gOmdinv);

@@ -12,6 +12,9 @@ enum { ST_FWD_NOT_PD = 1, ST_REV_NOT_PD = 2, ST_NONFINITE = 4 };
 
 // time steps (one wave each) per workgroup of the multivariate-t linearisation
 constexpr int kMvtWaves = 4;
+// time steps per workgroup of the Gaussian-emission linearisation (four waves,
+// each taking every fourth of them)
+constexpr int kGaussStepsPerBlock = 16;
 
 // Model as the kernels see it (all arrays are device pointers, d-sized).
 struct KModel {
@@ -59,7 +62,7 @@ struct StepArgs {
   double* xs;                       // [N*d]
   double *ell, *ell2;               // [N]
   double *part_lh_x, *part_lh_xs, *part_terms;
-  double *g_G, *g_Rinv, *g_Omd, *g_Omd_inv, *g_scal;
+  double *g_G, *g_Ht, *g_Rinv, *g_Omd, *g_Omd_inv, *g_scal;
   int* status;
   int* accept_flag;
 };

@@ -336,195 +336,213 @@ __global__ void __launch_bounds__(64 * MVT_WAVES) k_lin_mvt(KModel M, StepArgs A
 
 // ---------------------------------------------------------------------------
 // Gaussian emissions y = H x + N(0, R): v = G (y - H x), Lambda = -G H with
-// G = H^T R^{-1}; constant dense Omega under order 2.  One thread per t.
-// gprep: G [d, dy], Rinv [dy, dy], Omd [d, d] (order 2), Omd_inv [d, d],
-// logdet(Omd) in gscal[0].
+// G = H^T R^{-1}; constant dense Omega under order 2.
+// gprep (workspace, written once per step by k_gauss_prep):
+//   g_G = G^T = R^{-1} H [dy, d] (row k holds column k of G),
+//   g_Ht = H^T [d, dy], g_Rinv = R^{-1} [dy, dy],
+//   g_Omd_inv = 2/delta I + G H [d, d] (order 2; 2/delta I under order 1),
+//   g_Omd = its inverse, g_scal[0] = log det g_Omd.
+// The symmetric matrices and the transposed copies let a wave read column
+// i of a product as lane i of one coalesced row.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_gauss_prep(KModel M, StepArgs A) {
-  // single team of 64 threads; dims <= 64.  Gauss-Jordan on SPD matrices
-  // (no pivoting needed) in LDS.
-  __shared__ double sM[64 * 65];
-  __shared__ double sI[64 * 65];
+constexpr int GP_LD = 65;
+
+// In-place Gauss-Jordan inverse of the n x n SPD matrix in sM (LDS, leading
+// dimension GP_LD) into sI, which holds the identity on entry; no pivoting.
+// Thread j < n owns column j of both, so an elimination step is one pass over
+// rows with independent iterations.  Returns sum log(pivot) (every thread).
+__device__ double gp_invert(double* sM, double* sI, double* colk, int n) {
+  const int j = threadIdx.x;
+  double logdet = 0.0;
+  for (int k = 0; k < n; ++k) {
+    if (j < n) colk[j] = sM[j * GP_LD + k];
+    __syncthreads();
+    const double piv = colk[k];
+    logdet += log(piv);
+    if (j < n) {
+      const double inv = 1.0 / piv;
+      const double mk = sM[k * GP_LD + j] * inv, ik = sI[k * GP_LD + j] * inv;
+      for (int i = 0; i < n; ++i) {
+        if (i == k) continue;
+        const double f = colk[i];
+        sM[i * GP_LD + j] -= f * mk;
+        sI[i * GP_LD + j] -= f * ik;
+      }
+      sM[k * GP_LD + j] = mk;
+      sI[k * GP_LD + j] = ik;
+    }
+    __syncthreads();
+  }
+  return logdet;
+}
+
+__global__ void __launch_bounds__(256) k_gauss_prep(KModel M, StepArgs A) {
+  __shared__ double sM[64 * GP_LD], sI[64 * GP_LD], sH[64 * GP_LD], sG[64 * GP_LD];
+  __shared__ double colk[64];
   const int tid = threadIdx.x, d = M.d, p = M.dy;
-  const int LDm = 65;
-  // R^{-1}
-  for (int e = tid; e < p * p; e += 64) {
+  team_move<256, 64 * 64>(
+      p * d, [&](int e) { return M.H[e]; },
+      [&](int e, double v) { sH[(e / d) * GP_LD + e % d] = v; });
+  team_move<256, 64 * 64>(
+      p * p, [&](int e) { return M.R[e]; },
+      [&](int e, double v) { sM[(e / p) * GP_LD + e % p] = v; });
+  for (int e = tid; e < 64 * GP_LD; e += 256) sI[e] = (e % GP_LD == e / GP_LD) ? 1.0 : 0.0;
+  __syncthreads();
+  gp_invert(sM, sI, colk, p);  // sI = R^{-1}
+  for (int e = tid; e < p * p; e += 256) {
     const int i = e / p, j = e % p;
-    sM[i * LDm + j] = M.R[e];
-    sI[i * LDm + j] = (i == j) ? 1.0 : 0.0;
+    A.g_Rinv[e] = 0.5 * (sI[i * GP_LD + j] + sI[j * GP_LD + i]);
+  }
+  // G^T = R^{-1} H and H^T
+  for (int e = tid; e < p * d; e += 256) {
+    const int k = e / d, i = e % d;
+    double acc = 0.0;
+    for (int l = 0; l < p; ++l) acc = fma(0.5 * (sI[k * GP_LD + l] + sI[l * GP_LD + k]),
+                                          sH[l * GP_LD + i], acc);
+    sG[k * GP_LD + i] = acc;
+    A.g_G[e] = acc;
+    A.g_Ht[i * p + k] = sH[k * GP_LD + i];
   }
   __syncthreads();
-  for (int k = 0; k < p; ++k) {
-    const double piv = sM[k * LDm + k];
-    __syncthreads();
-    if (tid < p) {
-      sM[k * LDm + tid] /= piv;
-      sI[k * LDm + tid] /= piv;
+  // precision 2/delta I - Lambda = 2/delta I + G H; Omd = its inverse
+  const double two_d = 2.0 / A.delta;
+  for (int e = tid; e < 64 * GP_LD; e += 256) {
+    const int i = e / GP_LD, j = e % GP_LD;
+    double v = 0.0;
+    if (i < d && j < d) {
+      if (A.order != 1)
+        for (int k = 0; k < p; ++k) v = fma(sG[k * GP_LD + i], sH[k * GP_LD + j], v);
+      if (i == j) v += two_d;
+      A.g_Omd_inv[i * d + j] = v;
     }
-    __syncthreads();
-    for (int e = tid; e < p * p; e += 64) {
-      const int i = e / p, j = e % p;
-      if (i != k) {
-        const double f = sM[i * LDm + k];
-        sI[i * LDm + j] -= f * sI[k * LDm + j];
-        if (j != k) sM[i * LDm + j] -= f * sM[k * LDm + j];
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < p; i += 64)
-      if (i != k) sM[i * LDm + k] = 0.0;
-    __syncthreads();
-  }
-  for (int e = tid; e < p * p; e += 64) A.g_Rinv[e] = sI[(e / p) * LDm + e % p];
-  // G = H^T R^{-1}  [d, p]
-  for (int e = tid; e < d * p; e += 64) {
-    const int i = e / p, j = e % p;
-    double s = 0.0;
-    for (int k = 0; k < p; ++k) s += M.H[k * d + i] * sI[k * LDm + j];
-    A.g_G[e] = s;
+    sM[e] = v;
+    sI[e] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // precision 2/delta I - Lambda = 2/delta I + G H  -> Omd_inv ; Omd = inverse
-  for (int e = tid; e < d * d; e += 64) {
+  const double logdet_prec = gp_invert(sM, sI, colk, d);
+  for (int e = tid; e < d * d; e += 256) {
     const int i = e / d, j = e % d;
-    double s = 0.0;
-    if (A.order != 1)
-      for (int k = 0; k < p; ++k) s += A.g_G[i * p + k] * M.H[k * d + j];
-    s += (i == j) ? 2.0 / A.delta : 0.0;
-    A.g_Omd_inv[e] = s;
-    sM[i * LDm + j] = s;
-    sI[i * LDm + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  double logdet_prec = 0.0;
-  for (int k = 0; k < d; ++k) {
-    const double piv = sM[k * LDm + k];
-    logdet_prec += log(piv);
-    __syncthreads();
-    if (tid < d) {
-      sM[k * LDm + tid] /= piv;
-      sI[k * LDm + tid] /= piv;
-    }
-    __syncthreads();
-    for (int e = tid; e < d * d; e += 64) {
-      const int i = e / d, j = e % d;
-      if (i != k) {
-        const double f = sM[i * LDm + k];
-        sI[i * LDm + j] -= f * sI[k * LDm + j];
-        if (j != k) sM[i * LDm + j] -= f * sM[k * LDm + j];
-      }
-    }
-    __syncthreads();
-    for (int i = tid; i < d; i += 64)
-      if (i != k) sM[i * LDm + k] = 0.0;
-    __syncthreads();
-  }
-  for (int e = tid; e < d * d; e += 64) {
-    const int i = e / d, j = e % d;
-    A.g_Omd[e] = 0.5 * (sI[i * LDm + j] + sI[j * LDm + i]);
+    A.g_Omd[e] = 0.5 * (sI[i * GP_LD + j] + sI[j * GP_LD + i]);
   }
   if (tid == 0) A.g_scal[0] = -logdet_prec;  // log det Omega
 }
 
-// log h(y_t | x) = -1/2 (y - H x)^T R^{-1} (y - H x) (constants dropped)
-__device__ double gauss_loglik_t(const KModel& M, const StepArgs& A, const double* yt,
-                                 const double* xt, double* res /*[dy] scratch*/) {
-  for (int k = 0; k < M.dy; ++k) {
-    double s = yt[k];
-    for (int j = 0; j < M.d; ++j) s -= M.H[k * M.d + j] * xt[j];
-    res[k] = s;
-  }
-  double q = 0.0;
-  for (int k = 0; k < M.dy; ++k) {
-    double s = 0.0;
-    for (int l = 0; l < M.dy; ++l) s += A.g_Rinv[k * M.dy + l] * res[l];
-    q += res[k] * s;
-  }
-  return -0.5 * q;
+// One wave per time step (grid-stride over t, GL_WAVES waves per workgroup),
+// lane i for coordinate i (or observation k).  rev = 0: forward (draw u,
+// linearise at x); rev = 1: reverse (linearise at x*, same u) plus the MH
+// terms.  Order 2 gives a constant dense Omega (omega = Omega (2/delta u +
+// G y)); order 1 gives the diagonal Omega = delta/2 with omega = u + delta/2 v.
+// log h(y_t | x) = -1/2 (y - H x)^T R^{-1} (y - H x) (constants dropped).
+constexpr int GL_WAVES = 4;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
 }
 
-// One thread per t.  rev = 0: forward (draw u, linearise at x); rev = 1:
-// reverse (linearise at x*, same u) plus the MH terms.  Order 2 gives a
-// constant dense Omega (omega = Omega (2/delta u + G y)); order 1 gives the
-// diagonal Omega = delta/2 with omega = u + delta/2 v.
-__global__ void __launch_bounds__(64) k_lin_gauss(KModel M, StepArgs A, int rev) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  double lh = 0.0, term = 0.0;
-  if (t < M.N) {
-    const int d = M.d, p = M.dy;
-    const double* yt = A.y + (int64_t)t * p;
-    const double* xt = A.x + (int64_t)t * d;
-    const double* xst = A.xs + (int64_t)t * d;
-    double* ut = A.u + (int64_t)t * d;
-    double res[64], rhs[64], v[64];
-    if (!rev)
-      for (int i = 0; i < d; ++i) ut[i] = xt[i] + sqrt(0.5 * A.delta) * A.xi_u[(int64_t)t * d + i];
-    const double* lin = rev ? xst : xt;
-    lh = gauss_loglik_t(M, A, yt, lin, res);
-    double* om = (rev ? A.om2 : A.om) + (int64_t)t * d;
-    double* Om = (rev ? A.Om2 : A.Om) + (int64_t)t * d;
-    if (A.order == 1) {
-      // v = G (y - H x)
-      for (int i = 0; i < d; ++i) {
-        double s = 0.0;
-        for (int k = 0; k < p; ++k) s += A.g_G[i * p + k] * res[k];
-        v[i] = s;
-      }
-      for (int i = 0; i < d; ++i) {
-        Om[i] = 0.5 * A.delta;
-        om[i] = ut[i] + 0.5 * A.delta * v[i];
-      }
+// lane i: sum_j Mt[j * ld + i] v[j] for j < n (Mt row j is column j of the
+// product's matrix; v in LDS, read as a broadcast), two accumulators.
+__device__ __forceinline__ double gl_col_dot(const double* __restrict__ Mt, int ld, int i,
+                                              const double* v, int n) {
+  double a0 = 0.0, a1 = 0.0;
+  int j = 0;
+  for (; j + 1 < n; j += 2) {
+    a0 = fma(Mt[j * ld + i], v[j], a0);
+    a1 = fma(Mt[(j + 1) * ld + i], v[j + 1], a1);
+  }
+  if (j < n) a0 = fma(Mt[j * ld + i], v[j], a0);
+  return a0 + a1;
+}
+
+__global__ void __launch_bounds__(64 * GL_WAVES) k_lin_gauss(KModel M, StepArgs A, int rev) {
+  __shared__ double sv[GL_WAVES][3][64];
+  __shared__ double red[GL_WAVES][2];
+  const int tid = threadIdx.x, l = tid & 63, w = tid >> 6;
+  const int d = M.d, p = M.dy;
+  const double half_d = 0.5 * A.delta, sq = sqrt(0.5 * A.delta);
+  double lh_acc = 0.0, term_acc = 0.0;
+  double* s0 = sv[w][0];
+  double* s1 = sv[w][1];
+  double* s2 = sv[w][2];
+  for (int t0 = blockIdx.x * GL_WAVES; t0 < M.N; t0 += gridDim.x * GL_WAVES) {
+    const int t = t0 + w;
+    const bool act = t < M.N;
+    const int64_t bd = (int64_t)t * d, bp = (int64_t)t * p;
+    const bool li = act && l < d, lk = act && l < p;
+    const double xl = li ? A.x[bd + l] : 0.0;
+    const double xsl = (li && rev) ? A.xs[bd + l] : 0.0;
+    double ul;
+    if (!rev) {
+      ul = li ? xl + sq * A.xi_u[bd + l] : 0.0;
+      if (li) A.u[bd + l] = ul;
     } else {
-      for (int i = 0; i < d; ++i) {
-        double s = 2.0 / A.delta * ut[i];
-        for (int k = 0; k < p; ++k) s += A.g_G[i * p + k] * yt[k];
-        rhs[i] = s;
-      }
-      for (int i = 0; i < d; ++i) {
-        double s = 0.0;
-        for (int j = 0; j < d; ++j) s += A.g_Omd[i * d + j] * rhs[j];
-        om[i] = s;
-        Om[i] = A.g_Omd[i * d + i];
-      }
+      ul = li ? A.u[bd + l] : 0.0;
     }
+    const double yk = lk ? A.y[bp + l] : 0.0;
+    s0[l] = rev ? xsl : xl;  // linearisation point
+    s2[l] = yk;
+    __syncthreads();
+    // residual r = y - H x (lane k)
+    const double rk = lk ? yk - gl_col_dot(A.g_Ht, p, l, s0, d) : 0.0;
+    s1[l] = rk;
+    __syncthreads();
+    const double Rr = lk ? gl_col_dot(A.g_Rinv, p, l, s1, p) : 0.0;
+    const double lh = -0.5 * wave_sum(rk * Rr);
+    double oml, Oml;
+    if (A.order == 1) {
+      const double v = li ? gl_col_dot(A.g_G, d, l, s1, p) : 0.0;
+      Oml = half_d;
+      oml = ul + half_d * v;
+    } else {
+      const double rhs = li ? 2.0 / A.delta * ul + gl_col_dot(A.g_G, d, l, s2, p) : 0.0;
+      __syncthreads();
+      s0[l] = rhs;
+      __syncthreads();
+      oml = li ? gl_col_dot(A.g_Omd, d, l, s0, d) : 0.0;
+      Oml = li ? A.g_Omd[l * d + l] : 0.0;
+    }
+    double* om = rev ? A.om2 : A.om;
+    double* Om = rev ? A.Om2 : A.Om;
+    if (li) {
+      om[bd + l] = oml;
+      Om[bd + l] = Oml;
+    }
+    if (act) lh_acc += lh;
     if (rev) {
       // MH terms (log h difference is added from the partial sums)
-      double aux = 0.0;
-      for (int i = 0; i < d; ++i) {
-        const double a = ut[i] - xt[i], c = ut[i] - xst[i];
-        aux += a * a - c * c;
-      }
-      term = aux / A.delta;
-      const double* omf = A.om + (int64_t)t * d;
+      const double a = ul - xl, c = ul - xsl;
+      double term = li ? (a * a - c * c) / A.delta : 0.0;
+      const double omf = li ? A.om[bd + l] : 0.0;
+      const double rq = li ? oml - xl : 0.0, fq = li ? omf - xsl : 0.0;
       if (A.order == 1) {
-        const double s2 = 0.5 * A.delta;
-        double q = 0.0;
-        for (int i = 0; i < d; ++i) {
-          const double rq = om[i] - xt[i], fq = omf[i] - xst[i];
-          q += -0.5 * rq * rq / s2 + 0.5 * fq * fq / s2;
-        }
-        term += q;
+        term += li ? (-0.5 * rq * rq + 0.5 * fq * fq) / half_d : 0.0;
       } else {
         // same dense Omega both ways: log-determinants cancel
-        double q = 0.0;
-        for (int i = 0; i < d; ++i) {
-          double sr = 0.0, sf = 0.0;
-          for (int j = 0; j < d; ++j) {
-            sr += A.g_Omd_inv[i * d + j] * (om[j] - xt[j]);
-            sf += A.g_Omd_inv[i * d + j] * (omf[j] - xst[j]);
-          }
-          q += -0.5 * (om[i] - xt[i]) * sr + 0.5 * (omf[i] - xst[i]) * sf;
-        }
-        term += q;
+        __syncthreads();
+        s0[l] = rq;
+        s1[l] = fq;
+        __syncthreads();
+        const double sr = li ? gl_col_dot(A.g_Omd_inv, d, l, s0, d) : 0.0;
+        const double sf = li ? gl_col_dot(A.g_Omd_inv, d, l, s1, d) : 0.0;
+        term += -0.5 * rq * sr + 0.5 * fq * sf;
       }
+      term = wave_sum(term);
+      if (act) term_acc += term;
     }
+    __syncthreads();
   }
-  __shared__ double red[2];
-  for (int o = 32; o > 0; o >>= 1) {
-    lh += __shfl_xor(lh, o);
-    term += __shfl_xor(term, o);
+  if (l == 0) {
+    red[w][0] = lh_acc;
+    red[w][1] = term_acc;
   }
-  if (threadIdx.x == 0) {
+  __syncthreads();
+  if (tid == 0) {
+    double lh = 0.0, term = 0.0;
+    for (int i = 0; i < GL_WAVES; ++i) {
+      lh += red[i][0];
+      term += red[i][1];
+    }
     if (rev) {
       A.part_terms[blockIdx.x] = term;
       A.part_lh_xs[blockIdx.x] = lh;
@@ -532,7 +550,6 @@ __global__ void __launch_bounds__(64) k_lin_gauss(KModel M, StepArgs A, int rev)
       A.part_lh_x[blockIdx.x] = lh;
     }
   }
-  (void)red;
 }
 
 // ---------------------------------------------------------------------------
@@ -1843,10 +1860,10 @@ hipError_t set_lds_limits_all() {
 hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStream_t st) {
   timing_mark(FAM_LIN, 1, st);
   if (M.emit == EMIT_GAUSSIAN) {
-    const int nblk = (M.N + 63) / 64;
+    const int nblk = (M.N + kGaussStepsPerBlock - 1) / kGaussStepsPerBlock;
     *n_part = nblk;
-    if (!rev) hipLaunchKernelGGL(k_gauss_prep, dim3(1), dim3(64), 0, st, M, A);
-    hipLaunchKernelGGL(k_lin_gauss, dim3(nblk), dim3(64), 0, st, M, A, rev);
+    if (!rev) hipLaunchKernelGGL(k_gauss_prep, dim3(1), dim3(256), 0, st, M, A);
+    hipLaunchKernelGGL(k_lin_gauss, dim3(nblk), dim3(64 * GL_WAVES), 0, st, M, A, rev);
   } else if (M.emit == EMIT_MVT) {
     const int nblk = (M.N + MVT_WAVES - 1) / MVT_WAVES;
     *n_part = nblk;

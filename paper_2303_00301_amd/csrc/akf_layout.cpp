@@ -70,7 +70,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     return o;
   };
   const int nparts_diag = (int)(((int64_t)N * d + 255) / 256);
-  const int nparts_gauss = (N + 63) / 64;
+  const int nparts_gauss = (N + kGaussStepsPerBlock - 1) / kGaussStepsPerBlock;
   const int nparts_mvt = (N + kMvtWaves - 1) / kMvtWaves;
   Lo.n_part = nparts_diag > nparts_gauss ? nparts_diag : nparts_gauss;
   if (nparts_mvt > Lo.n_part) Lo.n_part = nparts_mvt;
@@ -86,6 +86,7 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     Lo.plhxs = take((size_t)Lo.n_part * dbl);
     Lo.pterms = take((size_t)Lo.n_part * dbl);
     Lo.gG = take((size_t)d * (dy > 0 ? dy : 1) * dbl);
+    Lo.gHt = take((size_t)d * (dy > 0 ? dy : 1) * dbl);
     Lo.gRinv = take((size_t)(dy > 0 ? dy * dy : 1) * dbl);
     Lo.gOmd = take((size_t)d * d * dbl);
     Lo.gOmdinv = take((size_t)d * d * dbl);

@@ -21,7 +21,7 @@ struct Layout {
   // byte offsets
   size_t u = 0, om = 0, Om = 0, om2 = 0, Om2 = 0, xs = 0, ell = 0, ell2 = 0;
   size_t plhx = 0, plhxs = 0, pterms = 0;
-  size_t gG = 0, gRinv = 0, gOmd = 0, gOmdinv = 0, gscal = 0;
+  size_t gG = 0, gHt = 0, gRinv = 0, gOmd = 0, gOmdinv = 0, gscal = 0;
   size_t elem[kMaxLevels + 1] = {0};
   size_t hs = 0;  // second buffer of the scan over block elements
   int L_hs = 0;   // levels of that scan: smallest L with 2^L >= nb

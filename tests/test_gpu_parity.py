@@ -159,9 +159,11 @@ def test_linear_gaussian_tiny_acceptance_one(S):
 
 
 @pytest.mark.parametrize("order", [1, 2])
-def test_gaussian_general_H(S, order):
-    rng = np.random.default_rng(31 + order)
-    N, dx, dy = 50, 6, 3
+@pytest.mark.parametrize("N,dx,dy", [(50, 6, 3), (333, 40, 20), (97, 64, 64)])
+def test_gaussian_general_H(S, order, N, dx, dy):
+    """Gaussian emissions with a general H (the wave-per-step linearisation:
+    observation and state lanes, a ragged last workgroup of time steps)."""
+    rng = np.random.default_rng(31 + order + dx)
     m0, P0, F, b, Q = _stable_model(rng, dx)
     H = rng.standard_normal((dy, dx))
     C = rng.standard_normal((dy, dy))
