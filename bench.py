@@ -732,10 +732,13 @@ def bench_first_order(torch, S, W, _lib, K: int, dev, cpu_steps: int = 0) -> dic
 def bench_reuse(torch, S, W, _lib, K: int, dev) -> dict:
     """The headline workload (latent field, d_x = 64, T = 4096, order 2) run
     plainly and with the matrices of a forward proposal reused by the next one
-    after a rejection (akf_mh_run_reuse; one host synchronisation per step).
-    Both runs take the same normals and uniforms from the same state, so they
-    make the same decisions.  The roofline is that of the filter fold, which
-    every step's reverse proposal (and every full forward one) runs."""
+    after a rejection (akf_mh_run_reuse, which decides each step's branch on
+    the device and issues the launches of both, gated).  Both runs take the
+    same normals and uniforms from the same state, so they make the same
+    decisions.  The roofline is that of the filter fold, which every step's
+    reverse proposal (and every full forward one) runs; its launches are timed
+    in the plain run, since the reuse run's gated-off fold launches (which exit
+    at once) would enter the same average."""
     import ctypes as C
     lib = _lib.load()
     w = W.latent_field()
@@ -752,7 +755,7 @@ def bench_reuse(torch, S, W, _lib, K: int, dev) -> dict:
         x = torch.as_tensor(w.x_true, dtype=torch.float64, device=dev).contiguous()
         S.mh_run(M, y, x, w.delta, 2, xi[:2], un[:2], ws=ws, reuse_matrices=reuse)
         torch.cuda.synchronize()
-        if reuse:
+        if not reuse:
             _lib.check(lib.akf_timing_enable(_lib.FAMILIES["filter_fold"], 4 * K + 8),
                        "akf_timing_enable")
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -764,7 +767,7 @@ def bench_reuse(torch, S, W, _lib, K: int, dev) -> dict:
         out[key] = {"ms_per_step": ms, "steps_per_s": 1000.0 / ms,
                     "acceptance": r["accepted"].float().mean().item(),
                     "rejected_by_status": int((r["status"] != 0).sum().item())}
-        if reuse:
+        if not reuse:
             n_l, k_ms = C.c_int32(), C.c_double()
             _lib.check(lib.akf_timing_collect(C.byref(n_l), C.byref(k_ms)), "akf_timing_collect")
             lib.akf_timing_enable(-1, 0)

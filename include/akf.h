@@ -238,11 +238,13 @@ akf_status akf_mh_run_first_order(const akf_model* model, const double* y, doubl
  * new u) reuses the covariances of the forward proposal before it and is
  * matrix-vector work; after an accepted or failed step, and at step 0, the
  * forward proposal runs in full and keeps its matrices; the reverse proposal
- * (a new x* every step) always runs in full.  The host reads each step's
- * accept flag back before launching the next (one stream synchronisation per
- * step), so this call blocks and is not graph-capturable.  Arguments,
- * outputs, normals and status bits as akf_mh_run; the chain equals
- * akf_mh_run's up to rounding.
+ * (a new x* every step) always runs in full.  The branch is decided on the
+ * device: each step issues the launches of both forward branches, gated on a
+ * workspace word that the step's decision updates, so the call never
+ * synchronises with the host, returns once the steps are enqueued, and can be
+ * captured in a graph (the first step initialises the word; a replay must
+ * start from step 0 of its own capture).  Arguments, outputs, normals and
+ * status bits as akf_mh_run; the chain equals akf_mh_run's up to rounding.
  *   - model: linear dynamics; order 2 takes the diagonal-Omega families
  *     (POISSON_LOG, STUDENT_T, STOCH_VOL, GAUSS_SITE), AKF_ERR_UNSUPPORTED
  *     for GAUSSIAN; MVT needs order 1 as everywhere.

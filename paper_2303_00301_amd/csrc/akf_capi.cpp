@@ -248,7 +248,7 @@ akf_status form_trees(const Layout& Lo, const KModel& M, const Kept& K, const do
   FixedArgs X = K.X;
   X.Om = Om;
   if ((s = hip_check(launch_fixed_phi_any(Lo.D, M, X, st), "Phi launch")) != AKF_OK) return s;
-  const VScanArgs Vphi{M.N, Lo.B, X.Phi}, Ve{M.N, Lo.B, X.Et};
+  const VScanArgs Vphi{M.N, Lo.B, X.Phi, M.gate}, Ve{M.N, Lo.B, X.Et, M.gate};
   if ((s = hip_check(launch_vtree_mats_any(Lo.D, Vphi, K.phi.Tm, Lo.n_lvl, Lo.L, st),
                      "scan products launch")) != AKF_OK)
     return s;
@@ -294,13 +294,19 @@ akf_status kept_finalize(const Layout& Lo, const KModel& M, void* ws, const Step
   return hip_check(launch_finalize(M, A, F, x_in, x_out, st), "finalize launch");
 }
 
+// the reuse gate (see k_reuse_gate), zero (a fresh pass) at the first step
+int* reuse_gate_word(const Layout& Lo, void* ws) { return at<int>(ws, Lo.status) + 4; }
+
 akf_status init_kept_status(const Layout& Lo, void* ws, hipStream_t st) {
   akf_status s;
   if ((s = hip_check(launch_step_init(at<int>(ws, Lo.status), root_flag(Lo, ws),
                                       at<double>(ws, Lo.xin[Lo.L]), Lo.D, st),
                      "init launch")) != AKF_OK)
     return s;
-  return hip_check(launch_step_init(at<int>(ws, Lo.status) + 2, nullptr, nullptr, 0, st),
+  if ((s = hip_check(launch_step_init(at<int>(ws, Lo.status) + 2, nullptr, nullptr, 0, st),
+                     "init launch")) != AKF_OK)
+    return s;
+  return hip_check(launch_step_init(reuse_gate_word(Lo, ws), nullptr, nullptr, 0, st),
                    "init launch");
 }
 
@@ -336,11 +342,16 @@ akf_status fixed_step_impl(const Layout& Lo, const KModel& M, const double* y, c
 // `fresh`: x changed since the kept matrices were formed (step 0, or the step
 // before accepted or failed); `trees`: the kept scans' products are current.
 // The reverse proposal is at a new x* every step and runs in full.
+// Order 2 with matrix reuse: the forward proposal keeps the plain pass's
+// matrices, and after a rejection (x unchanged) the next forward proposal is
+// formed from them.  The branch is decided on the device: every launch of the
+// three branches is issued each step and gated on the reuse word, so a run
+// needs no host synchronisation and can be captured in a graph.
 akf_status reuse_step_impl(const Layout& Lo, const KModel& M, const double* y, const double* x_in,
                            double delta, const double* xi, const double* unif, double* x_out,
                            double* log_ratio, int32_t* accepted, double* logZ_fwd,
                            double* logZ_rev, int32_t* status_out, void* ws, hipStream_t st,
-                           int step, bool fresh, bool* trees) {
+                           int step) {
   const size_t vn = (size_t)M.N * M.d;
   const StepArgs A = make_step_args(Lo, ws, y, x_in, delta, 2, xi, step);
   akf_status s;
@@ -349,23 +360,24 @@ akf_status reuse_step_impl(const Layout& Lo, const KModel& M, const double* y, c
   if ((s = hip_check(launch_lin(M, A, 0, &n_part_fwd, st), "linearise launch")) != AKF_OK) return s;
   // set-up failures of a kept forward pass are this step's own failures
   const Kept K = kept_state(Lo, ws, A, xi + vn, A.status);
-  if (fresh) {
-    if ((s = forward_keep(Lo, M, ws, A, K, A.status, st)) != AKF_OK) return s;
-    *trees = false;
-  } else {
-    if (!*trees) {
-      if ((s = form_trees(Lo, M, K, A.Om, st)) != AKF_OK) return s;
-      *trees = true;
-    }
-    if ((s = kept_proposal(Lo, M, K, A.om, A.Om, A.ell, true, st)) != AKF_OK) return s;
-  }
+  int* gate = reuse_gate_word(Lo, ws);
+  KModel Mfresh = M, Mtrees = M, Mkept = M;
+  Mfresh.gate = Gate{gate, 0, 0};
+  Mtrees.gate = Gate{gate, 1, 1};
+  Mkept.gate = Gate{gate, 1, 2};
+  if ((s = forward_keep(Lo, Mfresh, ws, A, K, A.status, st)) != AKF_OK) return s;
+  if ((s = form_trees(Lo, Mtrees, K, A.Om, st)) != AKF_OK) return s;
+  if ((s = kept_proposal(Lo, Mkept, K, A.om, A.Om, A.ell, true, st)) != AKF_OK) return s;
   if ((s = hip_check(launch_lin(M, A, 1, &n_part_rev, st), "linearise launch")) != AKF_OK) return s;
   const double* lz_rev = nullptr;
   if ((s = run_filter_logz(Lo, M, ws, A.om2, A.Om2, nullptr, A.status, ST_REV_NOT_PD, st, nullptr,
                            nullptr, &lz_rev)) != AKF_OK)
     return s;
-  return kept_finalize(Lo, M, ws, A, step, lz_rev, n_part_fwd, n_part_rev, x_in, x_out, unif,
-                       log_ratio, accepted, logZ_fwd, logZ_rev, status_out, st);
+  if ((s = kept_finalize(Lo, M, ws, A, step, lz_rev, n_part_fwd, n_part_rev, x_in, x_out, unif,
+                         log_ratio, accepted, logZ_fwd, logZ_rev, status_out, st)) != AKF_OK)
+    return s;
+  // the next forward proposal reuses this one's matrices iff x is unchanged
+  return hip_check(launch_reuse_gate(A.accept_flag, A.status, gate, st), "reuse gate launch");
 }
 
 akf_status check_fact_model(const akf_model* model, int order) {
@@ -872,7 +884,6 @@ akf_status akf_mh_run_reuse(const akf_model* model, const double* y, double* x, 
   const KModel M = to_kmodel(model);
   const size_t vn = (size_t)M.N * M.d;
   hipStream_t st = (hipStream_t)stream;
-  bool fresh = true, trees = false;
   for (int k = 0; k < n_steps; ++k) {
     double* lr = log_ratio ? log_ratio + k : nullptr;
     int32_t* acc = accepted ? accepted + k : nullptr;
@@ -880,26 +891,11 @@ akf_status akf_mh_run_reuse(const akf_model* model, const double* y, double* x, 
     double* zr = logZ_rev ? logZ_rev + k : nullptr;
     int32_t* so = status ? status + k : nullptr;
     const double* xik = xi + (size_t)k * 2 * vn;
-    if (order == 1) {
+    if (order == 1)
       s = fixed_step_impl(Lo, M, y, x, delta, xik, unif + k, x, lr, acc, zf, zr, so, ws, st, k);
-      if (s != AKF_OK) return s;
-      continue;
-    }
-    s = reuse_step_impl(Lo, M, y, x, delta, xik, unif + k, x, lr, acc, zf, zr, so, ws, st, k,
-                        fresh, &trees);
+    else
+      s = reuse_step_impl(Lo, M, y, x, delta, xik, unif + k, x, lr, acc, zf, zr, so, ws, st, k);
     if (s != AKF_OK) return s;
-    if (k + 1 == n_steps) break;
-    // the next forward proposal reuses this one's matrices iff x is unchanged
-    int32_t flags[2] = {0, 0};
-    if ((s = hip_check(hipMemcpyAsync(&flags[0], at<int>(ws, Lo.accept), sizeof(int),
-                                      hipMemcpyDeviceToHost, st),
-                       "accept flag copy")) != AKF_OK ||
-        (s = hip_check(hipMemcpyAsync(&flags[1], at<int>(ws, Lo.status) + (k & 1), sizeof(int),
-                                      hipMemcpyDeviceToHost, st),
-                       "status copy")) != AKF_OK ||
-        (s = hip_check(hipStreamSynchronize(st), "stream synchronize")) != AKF_OK)
-      return s;
-    fresh = flags[0] != 0 || flags[1] != 0;
   }
   return AKF_OK;
 }

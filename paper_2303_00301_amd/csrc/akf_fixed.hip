@@ -109,6 +109,7 @@ __device__ __forceinline__ void xload_pad(double* s, const double* __restrict__ 
 // Team 0 also keeps F (padded, transposed) for the per-step products.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_phi(KModel M, FixedArgs A) {
+  if (gate_shut(M.gate)) return;
   using C = Cfg<D>;
   extern __shared__ double lds[];
   double* B1 = lds;
@@ -142,6 +143,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_fixed_phi(KModel M, FixedArgs A)
 // accumulates on the right from the last step back.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_vtree_fold_mat(VScanArgs V, double* Tm0) {
+  if (gate_shut(V.gate)) return;
   using C = Cfg<D>;
   extern __shared__ double lds[];
   double* B1 = lds;
@@ -163,7 +165,8 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_vtree_fold_mat(VScanArgs V, doub
 // Tree node k of the next level: left (earlier) o right, (M_l M_r)^T = M_r^T M_l^T.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_vtree_up_mat(const double* src, double* dst,
-                                                             int n_src) {
+                                                             int n_src, Gate g) {
+  if (gate_shut(g)) return;
   using C = Cfg<D>;
   extern __shared__ double lds[];
   double* B1 = lds;
@@ -285,6 +288,7 @@ __device__ double* mean_chain(const KModel& M, const FixedArgs& A, int s_hi, int
 // step's status.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_mfold(KModel M, FixedArgs A, double* Uagg0) {
+  if (gate_shut(M.gate)) return;
   __shared__ MeanLds<D> L;
   const int k = blockIdx.x, tid = threadIdx.x;
   if (k == 0 && tid == 0 && *A.setup_status) atomicOr(A.status, *A.setup_status);
@@ -299,6 +303,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_mfold(KModel M, FixedArgs A, dou
 // Block final of the means: m^f_t and ell_t of every step of the block.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_mfinal(KModel M, FixedArgs A, const double* xin0) {
+  if (gate_shut(M.gate)) return;
   __shared__ MeanLds<D> L;
   const int k = blockIdx.x, tid = threadIdx.x;
   const int s0 = k * A.B, s1 = min(M.N, s0 + A.B);
@@ -316,6 +321,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_mfinal(KModel M, FixedArgs A, co
 // per step.
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_sw(KModel M, FixedArgs A) {
+  if (gate_shut(M.gate)) return;
   __shared__ double vx[D], vm[D], vb[D], red[GMV<D>::NT];
   const int t = blockIdx.x, tid = threadIdx.x, d = M.d;
   if (tid < D) {
@@ -378,6 +384,7 @@ __device__ double* samp_chain(const KModel& M, const FixedArgs& A, int s_hi, int
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_sfold(KModel M, FixedArgs A, double* Uagg0) {
+  if (gate_shut(M.gate)) return;
   __shared__ double xv[2][D];
   __shared__ double red[GMV<D>::NT];
   const int k = blockIdx.x, tid = threadIdx.x;
@@ -390,6 +397,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_sfold(KModel M, FixedArgs A, dou
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_sfinal(KModel M, FixedArgs A, const double* xin0) {
+  if (gate_shut(M.gate)) return;
   __shared__ double xv[2][D];
   __shared__ double red[GMV<D>::NT];
   const int k = blockIdx.x, tid = threadIdx.x;
@@ -410,6 +418,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_sfinal(KModel M, FixedArgs A, co
 // applied one node at a time by the whole team.
 template <int D, int R>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_vup_span(VTreeSpan T) {
+  if (gate_shut(T.gate)) return;
   using V = GMV<D>;
   constexpr int PMAX = 1 << (R - 1);
   __shared__ double ph[2][1 << R][64];
@@ -457,6 +466,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_vup_span(VTreeSpan T) {
 // left child M_{2j+1} x + u_{2j+1} (or the state itself when alone).
 template <int D, int R>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_vdown_span(VTreeSpan T) {
+  if (gate_shut(T.gate)) return;
   using V = GMV<D>;
   constexpr int PMAX = 1 << (R - 1);
   __shared__ double ph[2][1 << R][64];
@@ -548,7 +558,7 @@ hipError_t vtree_mats(const VScanArgs& V, double* const* Tm, const int* n_lvl, i
   hipLaunchKernelGGL(k_vtree_fold_mat<D>, dim3(n_lvl[0]), b, lds_two_mats<D>(), st, V, Tm[0]);
   for (int l = 0; l < L; ++l)
     hipLaunchKernelGGL(k_vtree_up_mat<D>, dim3(n_lvl[l + 1]), b, lds_two_mats<D>(), st,
-                       (const double*)Tm[l], Tm[l + 1], n_lvl[l]);
+                       (const double*)Tm[l], Tm[l + 1], n_lvl[l], V.gate);
   return hipGetLastError();
 }
 
@@ -556,11 +566,12 @@ hipError_t vtree_mats(const VScanArgs& V, double* const* Tm, const int* n_lvl, i
 // from the root
 template <int D>
 void tree_spans(double* const* Tm, double* const* Uagg, double* const* xin, const int* n_lvl,
-                int L, hipStream_t st) {
+                int L, Gate gate, hipStream_t st) {
   const dim3 b(Cfg<D>::NT);
   auto span = [&](int lo, int R) {
     VTreeSpan T{};
     T.R = R;
+    T.gate = gate;
     for (int r = 0; r <= R; ++r) {
       if (r < R) T.Tm[r] = Tm[lo + r];
       T.U[r] = Uagg[lo + r];
@@ -595,14 +606,14 @@ hipError_t fixed_scan(int which, const KModel& M, FixedArgs A, double* const* Tm
     timing_mark(FAM_FIXED_MEAN_FOLD, 1, st);
     hipLaunchKernelGGL(k_mfold<D>, gb, b, 0, st, M, A, Uagg[0]);
     timing_mark(FAM_FIXED_MEAN_FOLD, 0, st);
-    tree_spans<D>(Tm, Uagg, xin, n_lvl, L, st);
+    tree_spans<D>(Tm, Uagg, xin, n_lvl, L, M.gate, st);
     hipLaunchKernelGGL(k_mfinal<D>, gb, b, 0, st, M, A, (const double*)xin[0]);
   } else {
     hipLaunchKernelGGL(k_sw<D>, dim3(M.N), b, 0, st, M, A);
     timing_mark(FAM_FIXED_SAMP_FOLD, 1, st);
     hipLaunchKernelGGL(k_sfold<D>, gb, b, 0, st, M, A, Uagg[0]);
     timing_mark(FAM_FIXED_SAMP_FOLD, 0, st);
-    tree_spans<D>(Tm, Uagg, xin, n_lvl, L, st);
+    tree_spans<D>(Tm, Uagg, xin, n_lvl, L, M.gate, st);
     hipLaunchKernelGGL(k_sfinal<D>, gb, b, 0, st, M, A, (const double*)xin[0]);
   }
   return hipGetLastError();

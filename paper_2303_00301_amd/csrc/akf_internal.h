@@ -16,6 +16,21 @@ constexpr int kMvtWaves = 4;
 // each taking every fourth of them)
 constexpr int kGaussStepsPerBlock = 16;
 
+// Device-side gate of a launch: the kernel runs iff w == nullptr or
+// lo <= *w <= hi; every workgroup reads the word at entry and leaves at once
+// when the gate is shut, so one launch sequence can serve branches that are
+// decided on the device (and be captured in a graph).
+struct Gate {
+  const int* w;
+  int lo, hi;
+};
+
+__device__ __forceinline__ bool gate_shut(const Gate& g) {
+  if (!g.w) return false;
+  const int v = *g.w;
+  return v < g.lo || v > g.hi;
+}
+
 // Model as the kernels see it (all arrays are device pointers, d-sized).
 struct KModel {
   int N, d, dy, emit;
@@ -26,6 +41,7 @@ struct KModel {
   int dyn;
   double dyn_par[4];
   double obs_beta, slr_var;  // quadratic observation mean; order-3 reference variance
+  Gate gate;                 // launches of the reuse path's branches (closed = skip)
 };
 
 // Filter element (A, b, C, eta, J), padded to D, and lc = log c, the
@@ -161,6 +177,7 @@ struct FixedArgs {
 struct VScanArgs {
   int N, B;
   const double* Mt;
+  Gate gate;
 };
 
 // Up to kVTreeSpan consecutive tree levels lo .. lo + R in one launch; one
@@ -172,6 +189,7 @@ struct VTreeSpan {
   double* X[kVTreeSpan + 1];     // states entering the nodes of levels lo .. lo+R
   int n[kVTreeSpan + 1];         // node counts of levels lo .. lo+R
   int R;
+  Gate gate;
 };
 
 // Extended linearisation of nonlinear dynamics (one wave per time step):
@@ -325,6 +343,7 @@ hipError_t launch_filter_logz_any(int D, const KModel& M, FilterArgs P, TreeArgs
 hipError_t launch_sampler_any(int D, const KModel& M, SampArgs S, TreeArgs* up, TreeArgs* down,
                               int n_levels, hipStream_t st);
 hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStream_t st);
+hipError_t launch_reuse_gate(const int* accept, const int* status, int* gate, hipStream_t st);
 hipError_t launch_step_init(int* status, double* root_flag, double* root_xin, int D,
                             hipStream_t st);
 hipError_t launch_finalize(const KModel& M, StepArgs A, FinalArgs F, const double* x,

@@ -269,7 +269,9 @@ __device__ __forceinline__ void lin_mvt_body(const KModel& M, const StepArgs& A,
   __shared__ double red[2 * MVT_WAVES];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int p = M.dy, d = M.d;
-  for (int e = tid; e < p * p; e += blockDim.x) sRt[(e % p) * LR + e / p] = M.R[e];
+  team_move<64 * MVT_WAVES, 64 * 64>(
+      p * p, [&](int e) { return M.R[e]; },
+      [&](int e, double v) { sRt[(e % p) * LR + e / p] = v; });
   if (tid < p) ssite[tid] = M.site[tid];
   const int t = item * MVT_WAVES + w;
   const bool active = t < M.N;
@@ -828,6 +830,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
   // k-steps per unrolled GEMM iteration: the most that fits the register budget
   // without spills (the D = 64 diagonal fold holds 512 registers per lane)
   constexpr int U = (D < 64) ? D / 4 : (OBS == OBS_DIAG ? 8 : 4);
+  if (gate_shut(M.gate)) return;
   filter_fold_body<D, OBS, U>(M, P, blockIdx.x);
 }
 
@@ -1098,6 +1101,7 @@ __device__ __forceinline__ void filter_hs_body(const KModel& M, const HsArgs& H,
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_hs(KModel M, HsArgs H) {
+  if (gate_shut(M.gate)) return;
   filter_hs_body<D, D / 4>(M, H, blockIdx.x);
 }
 
@@ -1250,6 +1254,7 @@ __device__ __forceinline__ void filter_final_body(const KModel& M, const FilterA
 
 template <int D, int OBS>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_final(KModel M, FilterArgs P) {
+  if (gate_shut(M.gate)) return;
   filter_final_body<D, OBS, D / 4>(M, P, blockIdx.x);
 }
 
@@ -1349,6 +1354,7 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT, 2) k_samp_build(KModel M, SampArgs S) {
+  if (gate_shut(M.gate)) return;
   samp_build_body<D, (D == 64 ? 8 : D / 4)>(M, S, blockIdx.x);  // no more spills than U = 4
 }
 
@@ -1398,6 +1404,7 @@ __device__ __forceinline__ void samp_fold_body(const KModel& M, const SampArgs& 
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_fold(KModel M, SampArgs S) {
+  if (gate_shut(M.gate)) return;
   samp_fold_body<D, D / 4>(M, S, blockIdx.x);
 }
 
@@ -1433,6 +1440,7 @@ __device__ __forceinline__ void samp_up_body(const KModel& M, const TreeArgs& T,
 
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) k_samp_up(KModel M, TreeArgs T) {
+  if (gate_shut(M.gate)) return;
   samp_up_body<D>(M, T, blockIdx.x);
 }
 
@@ -1461,6 +1469,7 @@ __device__ __forceinline__ void samp_down_body(const KModel& M, const TreeArgs& 
 
 template <int D>
 __global__ void __launch_bounds__(64) k_samp_down(KModel M, TreeArgs T) {
+  if (gate_shut(M.gate)) return;
   samp_down_body<D>(M, T, blockIdx.x);
 }
 
@@ -1489,6 +1498,7 @@ __device__ __forceinline__ void samp_final_body(const KModel& M, const SampArgs&
 
 template <int D>
 __global__ void __launch_bounds__(64) k_samp_final(KModel M, SampArgs S) {
+  if (gate_shut(M.gate)) return;
   samp_final_body<D>(M, S, blockIdx.x);
 }
 
@@ -1878,6 +1888,22 @@ hipError_t launch_lin(const KModel& M, StepArgs A, int rev, int* n_part, hipStre
       hipLaunchKernelGGL(k_lin_rev_diag, dim3(nblk), dim3(256), 0, st, M, A);
   }
   timing_mark(FAM_LIN, 0, st);
+  return hipGetLastError();
+}
+
+// The branch of the next step of a run that reuses a rejected proposal's
+// matrices: 0 = a fresh forward pass (after an acceptance or a failure),
+// 1 = reuse whose trees are still to be formed (after a fresh pass), 2 = reuse
+// with the trees formed.
+__global__ void k_reuse_gate(const int* accept, const int* status, int* gate) {
+  if (threadIdx.x == 0) {
+    const int g = *gate;
+    *gate = (*accept != 0 || *status != 0) ? 0 : (g == 0 ? 1 : 2);
+  }
+}
+
+hipError_t launch_reuse_gate(const int* accept, const int* status, int* gate, hipStream_t st) {
+  hipLaunchKernelGGL(k_reuse_gate, dim3(1), dim3(64), 0, st, accept, status, gate);
   return hipGetLastError();
 }
 

@@ -188,9 +188,10 @@ void make_layout(Layout& Lo, int N, int d, int dy, int block, int kind, bool dyn
     Lo.Pbar = take((size_t)N * D * D * dbl);
     Lo.part = take((size_t)Lo.nb * (2 * D * D + 2 * D) * dbl);
   }
-  // two words: consecutive steps alternate; first-order runs add two for the
-  // set-up of the shared matrices
-  Lo.status = take((fixed ? 4 : 2) * sizeof(int));
+  // two words: consecutive steps alternate; runs that keep matrices add two
+  // for the set-up of the shared matrices and two for the reuse gate (the
+  // branch of the next step, decided on the device)
+  Lo.status = take((fixed ? 6 : 2) * sizeof(int));
   Lo.total = off;
 }
 
@@ -282,7 +283,7 @@ akf_status check_linear(const akf_model* m, const char* what) {
 }
 
 KModel to_kmodel(const akf_model* m) {
-  KModel M;
+  KModel M{};
   M.N = m->N;
   M.d = m->dx;
   M.dy = m->dy;

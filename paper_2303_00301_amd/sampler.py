@@ -264,8 +264,9 @@ def mh_run(model: DeviceModel, y, x, delta: float, order: int, xi, unif, block: 
     factorised as in mh_step.  reuse_matrices (dense prior): the auxiliary
     model's matrices are reused wherever unchanged -- order 1: formed once for
     the whole call (akf_mh_run_first_order); order 2: kept from a forward
-    proposal for the next one after a rejection (akf_mh_run_reuse, one host
-    synchronisation per step).  The chain is the same up to rounding."""
+    proposal for the next one after a rejection (akf_mh_run_reuse, the branch
+    decided on the device, so the call can be captured in a graph).  The chain
+    is the same up to rounding."""
     lib = _lib.load()
     _check_form(model, factorised)
     if reuse_matrices and factorised:

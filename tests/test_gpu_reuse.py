@@ -177,3 +177,51 @@ def test_single_coordinate(S):
     y = rng.standard_normal((N, 1))
     _follow(S, M_or, M_dev, y, 0.3 * rng.standard_normal((N, 1)), 0.1,
             rng.standard_normal((8, 2, N, 1)), rng.random(8))
+
+
+def test_reuse_run_graph_replay_matches_eager(S):
+    """The reuse run decides its branch on the device, so a K-step call can be
+    captured in a graph: replays with fresh normals (one of them accepting
+    every step, one rejecting every step) equal eager calls from the same start,
+    bit for bit, with eager work and host synchronisations between replays."""
+    w = W.latent_field(N=96)
+    M = S.DeviceModel.from_workload(w, device=dev())
+    y = T(w.y)
+    K = 4
+    gen = torch.Generator(device=dev())
+    gen.manual_seed(17)
+    xi = torch.empty((K, 2, w.N, w.dx), dtype=torch.float64, device=dev())
+    un = torch.empty((K,), dtype=torch.float64, device=dev())
+    ws = S.Workspace(dev())
+    x_cap = T(w.x_true)
+    xi.normal_(generator=gen)
+    un.uniform_(generator=gen)
+    delta = 2.0 * w.delta
+    S.mh_run(M, y, x_cap, delta, 2, xi, un, ws=ws, reuse_matrices=True)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = S.mh_run(M, y, x_cap, delta, 2, xi, un, ws=ws, reuse_matrices=True)
+    torch.cuda.synchronize()
+    x = T(w.x_true)
+    rejected = False
+    for rep in range(5):
+        xi.normal_(generator=gen)
+        un.uniform_(generator=gen)
+        un.clamp_(min=1e-300)
+        if rep == 2:
+            un.fill_(1e-300)  # accepts unless a proposal fails
+        if rep == 3:
+            un.fill_(1.0)  # log U = 0: rejects unless log r > 0
+        start = x.clone()
+        x_cap.copy_(start)
+        g.replay()
+        torch.cuda.synchronize()
+        eager = S.mh_run(M, y, x, delta, 2, xi, un, ws=ws, reuse_matrices=True)
+        torch.cuda.synchronize()
+        assert torch.equal(x_cap, x), rep
+        for k in ("log_ratio", "accepted", "logZ_fwd", "logZ_rev", "status"):
+            assert torch.equal(out[k], eager[k]), (rep, k)
+        acc = N_(eager["accepted"])
+        rejected = rejected or bool(np.any(acc[:-1] == 0))
+    assert rejected
