@@ -364,7 +364,7 @@ __device__ __forceinline__ double rsqrt_nr(double q) {
 // on the way (L_ik = c_i / sqrt(q), i >= k).  Indices >= nv are padding: they
 // get a unit diagonal.  A non-positive pivot clears ok (the results are then
 // unspecified).
-template <bool CHOL>
+template <bool CHOL, bool PART = false>
 __device__ __forceinline__ void tile_sweep16(double p[4], int nv, double Lk[4], LogDet& ld,
                                              bool& ok) {
   const int l = threadIdx.x & 63, lg = l >> 4, lc = l & 15;
@@ -411,7 +411,28 @@ __device__ __forceinline__ void tile_sweep16(double p[4], int nv, double Lk[4], 
       }
     }
   };
-  static_for<0, 16>(step);
+  if (!PART || nv >= 16) {
+    static_for<0, 16>(step);
+  } else {
+    // PART, a tile with padding (a team wider than d): the steps of padded
+    // pivots change no valid entry (their column is zero there), so they are
+    // skipped and the padded part is set to what they would have left (unit
+    // diagonal).  Only the 16-wide teams take this path: in wider teams the
+    // second code path costs registers that the big kernels do not have.
+    auto some = [&](auto kc) {
+      if (decltype(kc)::value < nv) step(kc);
+    };
+    static_for<0, 16>(some);
+    ld.mul(prod);  // pivots of an unfinished group of four
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 4 * r + lg;
+      if (i >= nv || lc >= nv) {
+        p[r] = (i == lc) ? -1.0 : 0.0;  // negated below
+        if constexpr (CHOL) Lk[r] = (i == lc) ? 1.0 : 0.0;
+      }
+    }
+  }
 #pragma unroll
   for (int r = 0; r < 4; ++r) p[r] = -p[r];
 }
@@ -489,7 +510,7 @@ __device__ bool spd_inv(RM<D>& A, int d, double* scr, double* logdet) {
   if constexpr (D == 16) {
     double p[4], dummy[4];
     tile_regs(A.t[0], p);
-    tile_sweep16<false>(p, d, dummy, ld, ok);
+    tile_sweep16<false, D == 16>(p, d, dummy, ld, ok);
 #pragma unroll
     for (int r = 0; r < 4; ++r) A.t[0][r] = p[r];
   } else {
@@ -513,7 +534,7 @@ __device__ bool spd_inv(RM<D>& A, int d, double* scr, double* logdet) {
       };
       double pv[4], dummy[4];
       brow(kb, pv);
-      tile_sweep16<false>(pv, d - 16 * kb, dummy, ld, ok);  // pv = P^{-1}
+      tile_sweep16<false, D == 16>(pv, d - 16 * kb, dummy, ld, ok);  // pv = P^{-1}
       const dbl4 z = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ti = 0; ti < C::TS; ++ti) {
@@ -574,7 +595,7 @@ __device__ bool chol_reg(RM<D>& A, int d, double* scr, double* logdet) {
   if constexpr (D == 16) {
     double p[4], Lk[4];
     tile_regs(A.t[0], p);
-    tile_sweep16<true>(p, d, Lk, ld, ok);
+    tile_sweep16<true, D == 16>(p, d, Lk, ld, ok);
 #pragma unroll
     for (int r = 0; r < 4; ++r) A.t[0][r] = Lk[r];
   } else {
@@ -601,7 +622,7 @@ __device__ bool chol_reg(RM<D>& A, int d, double* scr, double* logdet) {
       double pv[4], Lk[4], G[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) pv[r] = BC[(16 * kb + 4 * r + lg) * LDC + lc];
-      tile_sweep16<true>(pv, d - 16 * kb, Lk, ld, ok);  // pv = A_KK^{-1}, Lk = L_KK
+      tile_sweep16<true, D == 16>(pv, d - 16 * kb, Lk, ld, ok);  // pv = A_KK^{-1}, Lk = L_KK
       const dbl4 z = {0.0, 0.0, 0.0, 0.0};
       chol_tile_rinv(pv, Lk, G);  // G = L_KK^{-T}
       double LTr[C::TS][4], LTc[C::TS][4];  // (L_TK)' for the wave's row / column tiles
