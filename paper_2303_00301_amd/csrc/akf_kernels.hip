@@ -849,7 +849,12 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_filter_fold(KModel M, FilterArgs
 // Kalman filter"; lc is the constant of the Gaussian integral over the shared
 // state, with log det W = log det (I + C_i J_j)).
 // ---------------------------------------------------------------------------
-template <int D, int U = 4, int G = D * D / Cfg<D>::NT>
+// SIDE 0 writes the whole element.  A node of a level that fits on the chip
+// twice is combined by two workgroups, each forming M (the factorisations and
+// their products) and then one side of the outputs: SIDE 1 the J side (J,
+// eta, A: four products after M), SIDE 2 the C side (C, b and lc: two), so a
+// level waits for the prefix and four products instead of eight.
+template <int D, int U = 4, int G = D * D / Cfg<D>::NT, int SIDE = 0>
 __device__ __forceinline__ void filter_combine(const KModel& M, const double* __restrict__ ei,
                                                const double* __restrict__ ej,
                                                double* __restrict__ out, int* status,
@@ -907,39 +912,45 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
                                                     vc[tid] * vw[tid]
                                               : 0.0,
                                       red);
-  rm_stage<D>(Ai, S0);  // S0 = A_i
-  team_sync();
-  matvec<D, false>(vk, S1, vw);              // J_j w
-  gemm<D, false, false, false, U>(R1, S1, S0);  // P = J_j A_i
-  rm_stage<D>(R1, S3);                       // S3 = P
-  team_sync();
-  if (tid < D) vk[tid] = vc[tid] - vk[tid];  // c - J_j M c
-  gemm<D, false, false, false, U>(R2, S2, S3);  // M P
-  R3 = Ai;
-  rm_axpy<D>(R3, -1.0, R2);  // Z1 = A_i - M P
-  team_sync();
-  matvec<D, true>(out + EL::eta, S0, vk, ei + EL::eta);  // eta = A_i' (c - J_j M c) + eta_i
-  rm_stage<D>(R3, S1);  // S1 = Z1
-  team_sync();
-  gemm<D, true, false, false, U>(R1, S1, S3);  // J = Z1' P + J_i = A_i'P - P'MP + J_i
-  rm_axpy<D>(R1, 1.0, Ji);
-  rm_symmetrise<D>(R1, S3);  // ends synchronised
-  rm_store<D>(R1, out + EL::J, D, D);
+  if constexpr (SIDE != 2) {
+    rm_stage<D>(Ai, S0);  // S0 = A_i
+    team_sync();
+    matvec<D, false>(vk, S1, vw);              // J_j w
+    gemm<D, false, false, false, U>(R1, S1, S0);  // P = J_j A_i
+    rm_stage<D>(R1, S3);                       // S3 = P
+    team_sync();
+    if (tid < D) vk[tid] = vc[tid] - vk[tid];  // c - J_j M c
+    gemm<D, false, false, false, U>(R2, S2, S3);  // M P
+    R3 = Ai;
+    rm_axpy<D>(R3, -1.0, R2);  // Z1 = A_i - M P
+    team_sync();
+    matvec<D, true>(out + EL::eta, S0, vk, ei + EL::eta);  // eta = A_i' (c - J_j M c) + eta_i
+    rm_stage<D>(R3, S1);  // S1 = Z1
+    team_sync();
+    gemm<D, true, false, false, U>(R1, S1, S3);  // J = Z1' P + J_i = A_i'P - P'MP + J_i
+    rm_axpy<D>(R1, 1.0, Ji);
+    rm_symmetrise<D>(R1, S3);  // ends synchronised
+    rm_store<D>(R1, out + EL::J, D, D);
+  }
   rm_stage<D>(Aj, S0);  // S0 = A_j
   if (tid < D) vw[tid] += vbi[tid];
   team_sync();
-  gemm<D, false, false, false, U>(R3, S0, S1);  // A = A_j Z1
-  rm_store<D>(R3, out + EL::A, D, D);
-  gemm<D, false, false, false, U>(R2, S0, S2);  // A_j M
-  matvec<D, false>(vc, S0, vw);              // A_j (b_i + M c)
-  rm_stage<D>(R2, S3);
-  team_sync();
-  gemm<D, false, true, false, U>(R3, S3, S0);  // A_j M A_j'
-  rm_axpy<D>(R3, 1.0, Cj);
-  if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
-  if (tid == 0) out[EL::lc] = lc;
-  rm_symmetrise<D>(R3, S1);
-  rm_store<D>(R3, out + EL::C, D, D);
+  if constexpr (SIDE != 2) {
+    gemm<D, false, false, false, U>(R3, S0, S1);  // A = A_j Z1
+    rm_store<D>(R3, out + EL::A, D, D);
+  }
+  if constexpr (SIDE != 1) {
+    gemm<D, false, false, false, U>(R2, S0, S2);  // A_j M
+    matvec<D, false>(vc, S0, vw);              // A_j (b_i + M c)
+    rm_stage<D>(R2, S3);
+    team_sync();
+    gemm<D, false, true, false, U>(R3, S3, S0);  // A_j M A_j'
+    rm_axpy<D>(R3, 1.0, Cj);
+    if (tid < D) out[EL::b + tid] = vc[tid] + ej[EL::b + tid];
+    if (tid == 0) out[EL::lc] = lc;
+    rm_symmetrise<D>(R3, S1);
+    rm_store<D>(R3, out + EL::C, D, D);
+  }
   if (!ok && tid == 0) flag_status(status, fail_bit);
 }
 
@@ -958,6 +969,27 @@ __device__ __forceinline__ void filter_up_body(const KModel& M, const TreeArgs& 
     return;
   }
   filter_combine<D, U, G>(M, ei, ei + EL::SIZE, out, T.status, T.fail_bit);
+}
+
+// One node per two workgroups (see filter_combine's SIDE); a left child
+// without a partner is copied by the first of them.
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT) k_filter_up_split(KModel M, TreeArgs T) {
+  if (gate_shut(M.gate)) return;
+  using EL = ElemLayout<D>;
+  const int k = blockIdx.x >> 1, side = blockIdx.x & 1;
+  const double* ei = T.src + (int64_t)(2 * k) * EL::SIZE;
+  double* out = T.dst + (int64_t)k * EL::SIZE;
+  if (2 * k + 1 >= T.n_src) {
+    if (side == 0) team_copy<Cfg<D>::NT>(out, ei, EL::SIZE);
+    return;
+  }
+  if (side == 0)
+    filter_combine<D, D / 4, D * D / Cfg<D>::NT, 1>(M, ei, ei + EL::SIZE, out, T.status,
+                                                      T.fail_bit);
+  else
+    filter_combine<D, D / 4, D * D / Cfg<D>::NT, 2>(M, ei, ei + EL::SIZE, out, T.status,
+                                                      T.fail_bit);
 }
 
 template <int D>
@@ -1680,6 +1712,18 @@ hipError_t launch_filter_scan(const KModel& M, FilterArgs P, const HsArgs* lv, i
 
 // log Z only: fold, then the up-sweep reduction of the block elements; the
 // root's normaliser is log p(omega_{0:N-1}).
+// compute units of the current device (queried once per process)
+static int compute_units() {
+  static const int n = [] {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    return v;
+  }();
+  return n;
+}
+
 template <int D, int OBS>
 hipError_t launch_filter_logz(const KModel& M, FilterArgs P, const TreeArgs* up, int n_levels,
                               hipStream_t st) {
@@ -1688,9 +1732,16 @@ hipError_t launch_filter_logz(const KModel& M, FilterArgs P, const TreeArgs* up,
   timing_mark(FAM_FILTER_FOLD, 1, st);
   hipLaunchKernelGGL((k_filter_fold<D, OBS>), dim3(nb), dim3(Cfg<D>::NT), lds, st, M, P);
   timing_mark(FAM_FILTER_FOLD, 0, st);
+  // a level whose nodes fit on the chip twice runs each node on two workgroups
+  const int n_cu = compute_units();
   for (int l = 0; l < n_levels; ++l) {
     timing_mark(FAM_FILTER_UP, 1, st);
-    hipLaunchKernelGGL(k_filter_up<D>, dim3(up[l].n_dst), dim3(Cfg<D>::NT), lds, st, M, up[l]);
+    if (2 * up[l].n_dst <= n_cu)
+      hipLaunchKernelGGL(k_filter_up_split<D>, dim3(2 * up[l].n_dst), dim3(Cfg<D>::NT), lds, st,
+                         M, up[l]);
+    else
+      hipLaunchKernelGGL(k_filter_up<D>, dim3(up[l].n_dst), dim3(Cfg<D>::NT), lds, st, M,
+                         up[l]);
     timing_mark(FAM_FILTER_UP, 0, st);
   }
   return hipGetLastError();
@@ -1764,6 +1815,9 @@ hipError_t set_lds_limits() {
     if ((e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
       return e;
   if ((e = hipFuncSetAttribute((const void*)k_filter_up<D>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
+    return e;
+  if ((e = hipFuncSetAttribute((const void*)k_filter_up_split<D>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, lf)) != hipSuccess)
     return e;
   if ((e = hipFuncSetAttribute((const void*)k_filter_down<D>,
