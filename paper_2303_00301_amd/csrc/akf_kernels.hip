@@ -731,7 +731,8 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
         gemm<D, false, false, false, U>(R1, B2, B3);  // S^{-1} T
         rm_stage<D>(R1, B1);
         team_sync();
-        gemm<D, true, false, true, U>(J, B3, B1);  // J += T' S^{-1} T
+        // fully unrolled where the register budget still allows it
+        gemm<D, true, false, true, (OBS == OBS_DIAG && D == 64) ? D / 4 : U>(J, B3, B1);  // J += T' S^{-1} T
         AKF_RM_FOR(D, q, r, i, j) A.t[q][r] = vom[i] * R1.t[q][r];
         matvec<D, true>(veta, B3, vs, veta);  // eta += T' S^{-1} w
       }

@@ -13,10 +13,12 @@
 //  * Runtime size d <= D: padded rows/columns are zero in every matrix
 //    (factors and inverses included).
 //
-// GEMMs run on the f64 matrix cores.  Inverses of SPD matrices (Gauss-Jordan)
-// and Cholesky factors are computed in registers, one pivot per sweep, with
-// the pivot row/column broadcast through a small double-buffered LDS vector
-// (one barrier per sweep).
+// GEMMs run on the f64 matrix cores.  Inverses of SPD matrices (block
+// Gauss-Jordan) and Cholesky factors (blocked, right-looking) are computed in
+// registers: each 16 x 16 pivot tile is swept inside one wave (lane
+// broadcasts, no LDS), the pivot block row or column is staged through a
+// double-buffered LDS panel (one barrier per panel), and every other product
+// is an MFMA chain.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
