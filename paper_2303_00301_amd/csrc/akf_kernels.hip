@@ -1340,11 +1340,13 @@ __device__ __forceinline__ void samp_build_body(const KModel& M, const SampArgs&
     const double* bt = S.Ft ? S.bt + (int64_t)(t + 1) * d : M.b;
     rm_stage<D>(Pf, Y);
     team_sync();
-    gemm<D, false, false, false, U>(R1, X, Y);  // G = F P^f
+    // at D = 64 the first two products fully unrolled: the register budget
+    // allows it here (and the allocator then spills less than with U)
+    gemm<D, false, false, false, (D == 64 ? D / 4 : U)>(R1, X, Y);  // G = F P^f
     team_sync();
     rm_stage<D>(R1, Y);  // Y = G
     team_sync();
-    gemm<D, false, true, true, U>(R2, Y, X);  // Q + G F'
+    gemm<D, false, true, true, (D == 64 ? D / 4 : U)>(R2, Y, X);  // Q + G F'
     matvec<D, false>(vmp, X, vm);
     if (tid < d && bt) vmp[tid] += bt[tid];
     {
@@ -2023,7 +2025,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_fold(BatchLaunch L, int rev) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
-    filter_fold_body<D, OBS_DIAG>(c.M, rev ? c.Fr : c.Ff, I.i);
+    filter_fold_body<D, OBS_DIAG, (D < 64 ? D / 4 : 4)>(c.M, rev ? c.Fr : c.Ff, I.i);
     __syncthreads();
   }
 }
@@ -2045,7 +2047,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_up(BatchLaunch L, int level, in
     const ChainDev& c = L.cd[I.c];
     TreeArgs T = c.fup[level - 1];
     T.fail_bit = rev ? ST_REV_NOT_PD : ST_FWD_NOT_PD;
-    filter_up_body<D, 4, 0>(c.M, T, I.i);
+    filter_up_body<D, (D < 64 ? D / 4 : 4), 0>(c.M, T, I.i);
     __syncthreads();
   }
 }
