@@ -68,8 +68,8 @@ struct EglState {  // suffix state entering a node from the right
 };
 
 // The GEMMs of the scan kernels, the smoother's and the adjoint's element
-// builds are fully unrolled (U = D / 4); the gradient kernel, at its register
-// limit, keeps the default.
+// builds are fully unrolled (U = D / 4); in the gradient kernel every product
+// but one (K, the last to fit, would spill) is.
 //
 // acc <- e_t o acc for t = s1-2 .. s0, starting from acc = e_{s1-1}.
 template <int D>
@@ -332,22 +332,22 @@ __device__ void adj_step_quantities(const KModel& M, const LgArgs& G, int t, con
     rm_stage<D>(R1, Btmp);
     if (tid < D) vv[tid] = G.mf[(int64_t)(t - 1) * D + tid];
     team_sync();
-    gemm<D, false, false, false>(R1, sF, Btmp);  // F P^f
+    gemm<D, false, false, false, D / 4>(R1, sF, Btmp);  // F P^f
     matvec<D, false>(vmp, sF, vv);
     team_sync();
     rm_stage<D>(R1, Btmp);
     team_sync();
-    gemm<D, false, true, false>(Pp, Btmp, sF);
+    gemm<D, false, true, false, D / 4>(Pp, Btmp, sF);
     rm_add_load<D>(Pp, G.Q, d, d);
   }
   team_sync();
   rm_stage<D>(Pp, Btmp);
   team_sync();
-  gemm<D, false, false, false>(R1, sH, Btmp);  // H Pp
+  gemm<D, false, false, false, D / 4>(R1, sH, Btmp);  // H Pp
   team_sync();
   rm_stage<D>(R1, B_HP);
   team_sync();
-  gemm<D, false, true, false>(R1, B_HP, sH);  // S = H Pp H' + R
+  gemm<D, false, true, false, D / 4>(R1, B_HP, sH);  // S = H Pp H' + R
   rm_add_load<D>(R1, G.R, p, p);
   matvec<D, false>(vv, sH, vmp);
   if (tid < D) vv[tid] = (tid < p) ? G.y[(int64_t)t * p + tid] - vv[tid] : 0.0;
@@ -491,14 +491,14 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
     if (!last) {
       lds_load_pad2<D>(Bu, G.Pbar + (int64_t)(t + 1) * D * D);
       team_sync();
-      gemm<D, false, false, false>(R1, Bu, sF);  // Pbar F
+      gemm<D, false, false, false, D / 4>(R1, Bu, sF);  // Pbar F
       team_sync();
       rm_stage<D>(R1, Bt);
       rm_stage<D>(Pf, Bu);
       team_sync();
-      gemm<D, false, false, false>(R2, Bt, Bu);  // Pbar F P^f
+      gemm<D, false, false, false, D / 4>(R2, Bt, Bu);  // Pbar F P^f
       rm_axpy<D>(gF, 2.0, R2);
-      gemm<D, true, false, false>(Fb, sF, Bt);  // F' Pbar F
+      gemm<D, true, false, false, D / 4>(Fb, sF, Bt);  // F' Pbar F
       team_sync();
       // dF += mbar_{t+1} m^f_t'
       AKF_RM_FOR(D, q, r, i, j) gF.t[q][r] += vmb[i] * vmf[j];
@@ -512,7 +512,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
     team_sync();
     // H-gradient:  w mp' - Sig H Pp + w (P^f fbar)' - (K' fbar) m^f' - 2 K' Fbar P^f
     // Sig H Pp = S^{-1} (H Pp) - w (w' H Pp)
-    gemm<D, false, false, false>(R1, B_Si, B_HP);  // S^{-1} H Pp
+    gemm<D, false, false, false, D / 4>(R1, B_Si, B_HP);  // S^{-1} H Pp
     rm_axpy<D>(gH, -1.0, R1);
     // w' H Pp  (row vector) into vv
     matvec<D, true>(vv, B_HP, vw);
@@ -524,12 +524,12 @@ __global__ void __launch_bounds__(Cfg<D>::NT) k_adj_grad(KModel M, LgArgs G) {
       // K' Fbar -> R1 (Bt holds K)
       rm_stage<D>(Fb, Bu);
       team_sync();
-      gemm<D, true, false, false>(R1, Bt, Bu);  // K' Fbar
+      gemm<D, true, false, false, D / 4>(R1, Bt, Bu);  // K' Fbar
       team_sync();
       rm_stage<D>(R1, Bu);
       rm_stage<D>(Pf, B_HP);  // H Pp is no longer read in this step
       team_sync();
-      gemm<D, false, false, false>(R2, Bu, B_HP);  // K' Fbar P^f
+      gemm<D, false, false, false, D / 4>(R2, Bu, B_HP);  // K' Fbar P^f
       rm_axpy<D>(gH, -2.0, R2);
       // (K' Fbar K)_jj = sum_i (K' Fbar)_ji K_ij
       if (tid < p) {
