@@ -518,10 +518,14 @@ akf_status akf_batch_plan_create(akf_batch_plan** plan, int32_t n_chains, const 
 akf_status akf_batch_mh_run(akf_batch_plan* plan, int32_t use_graph, void* stream);
 
 /* Plan diagnostics: number of groups and, per group (up to max_classes), its
- * team size D, scan block and chain count; total device bytes. */
+ * team size D, scan block, chain count and, at D = 32, the sampler build's
+ * one-wave teams per SIMD (2, or 1 with the whole register file; 0 at the
+ * widths with a single layout); total device bytes.  Any output pointer
+ * except n_classes may be NULL. */
 akf_status akf_batch_plan_info(const akf_batch_plan* plan, int32_t max_classes,
                                int32_t* n_classes, int32_t* D, int32_t* block,
-                               int32_t* n_chains_in_class, size_t* device_bytes);
+                               int32_t* n_chains_in_class, int32_t* sbuild_teams_per_simd,
+                               size_t* device_bytes);
 void akf_batch_plan_destroy(akf_batch_plan* plan);
 
 /*

@@ -108,7 +108,7 @@ SIGNATURES = {
     "akf_batch_mh_run": (C.c_int, [_vp, _i32, _vp]),
     "akf_batch_plan_info": (C.c_int, [_vp, _i32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32), C.POINTER(C.c_int32),
-                                      C.POINTER(C.c_size_t)]),
+                                      C.POINTER(C.c_int32), C.POINTER(C.c_size_t)]),
     "akf_batch_plan_destroy": (None, [_vp]),
     "akf_timing_enable": (C.c_int, [_i32, _i32]),
     "akf_timing_collect": (C.c_int, [C.POINTER(C.c_int32), C.POINTER(C.c_double)]),

@@ -19,6 +19,7 @@ using namespace akf;
 
 struct ClassPlan {
   int D = 0, B = 0, Lmax = 0;
+  int sb_teams = 2;  // sampler-build teams per SIMD (1 or 2; D = 64 teams take a CU)
   std::vector<int> chains;
   struct Tab {
     size_t off = 0;  // index into the item table
@@ -104,9 +105,10 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
     }
   }, 8192);
   tab(cp.fold, [&] { for (int c : cp.chains) for (int k = 0; k < lay[c].nb; ++k) b.items.push_back({c, k}); }, team_cap);
-  // the sampler element build runs two one-wave teams per SIMD at D = 32
-  // (D = 16 teams already do; D = 64 teams take a whole CU)
-  const int sbuild_cap = (cp.D == 32 ? 2 : 1) * team_cap;
+  // the sampler element build runs one or two one-wave teams per SIMD at
+  // D = 32 (the autotuner's choice; D = 16 teams already fill the CU, D = 64
+  // teams take a whole CU)
+  const int sbuild_cap = (cp.D == 32 && cp.sb_teams == 2 ? 2 : 1) * team_cap;
   tab(cp.sbuild, [&] { for (int c : cp.chains) for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t}); }, sbuild_cap);
   tab(cp.fin, [&] { for (int c : cp.chains) b.items.push_back({c, 0}); }, 1024);
   for (int l = 1; l <= cp.Lmax; ++l) {
@@ -248,7 +250,7 @@ hipError_t enqueue_class_step_part(const ClassPlan& cp, const ChainDev* d_desc, 
       filter(0);
       break;
     case 1:
-      run(BP_SBUILD, cp.sbuild, 0, 0);
+      run(cp.sb_teams == 2 ? BP_SBUILD : BP_SBUILD1, cp.sbuild, 0, 0);
       run(BP_SFOLD, cp.fold, 0, 0);
       for (int l = 1; l <= cp.Lmax; ++l) run(BP_SUP, cp.up[l], l, 0);
       for (int l = cp.Lmax; l >= 1; --l) run(BP_SDOWN, cp.down[l], l, 0);
@@ -487,8 +489,9 @@ std::string cache_key(const ClassPlan& cp, const std::vector<akf_chain>& chains)
   return k;
 }
 
-// Block of the last verified line whose key fields equal `key` exactly, or 0.
-int cache_lookup(const char* path, const std::string& key) {
+// Block and sampler-build layout of the last verified line whose key fields
+// equal `key` exactly; B = 0 when there is none.
+int cache_lookup(const char* path, const std::string& key, int* sb_teams) {
   if (!path) return 0;
   FILE* f = fopen(path, "r");
   if (!f) return 0;
@@ -501,19 +504,28 @@ int cache_lookup(const char* path, const std::string& key) {
     if (line.size() < 2 || line[0] != '{' || kb == std::string::npos) continue;
     if (line.compare(1, kb - 1, key) != 0 || kb - 1 != key.size()) continue;
     if (line.find("\"verified\": true") == std::string::npos) continue;
+    static const char kTeams[] = "\"sbuild_teams_per_simd\": ";
+    const size_t ks = line.find(kTeams);
+    if (ks == std::string::npos) continue;  // a line of an older layout search
     const int b = atoi(line.c_str() + kb + 11);
-    if (b > 0) B = b;
+    const int t = atoi(line.c_str() + ks + sizeof kTeams - 1);
+    if (b > 0 && (t == 1 || t == 2)) {
+      B = b;
+      *sb_teams = t;
+    }
   }
   fclose(f);
   return B;
 }
 
-void cache_store(const char* path, const std::string& key, int B, double ms) {
+void cache_store(const char* path, const std::string& key, int B, int sb_teams, double ms) {
   if (!path) return;
   FILE* f = fopen(path, "a");
   if (!f) return;
-  fprintf(f, "{%s, \"block\": %d, \"ms_per_step\": %.4f, \"verified\": true}\n", key.c_str(), B,
-          ms);
+  fprintf(f,
+          "{%s, \"block\": %d, \"sbuild_teams_per_simd\": %d, \"ms_per_step\": %.4f, "
+          "\"verified\": true}\n",
+          key.c_str(), B, sb_teams, ms);
   fclose(f);
 }
 
@@ -553,9 +565,10 @@ akf_status akf_batch_plan_create(akf_batch_plan** out, int32_t n_chains, const a
       if (pick_D(chains[k].model.dx) == D) cp.chains.push_back(k);
     if (cp.chains.empty()) continue;
     int B = block;
+    int sb_teams = 2;
     if (B == 0) {
       const std::string key = cache_key(cp, P->chains);
-      B = cache_lookup(tune_cache, key);
+      B = cache_lookup(tune_cache, key, &sb_teams);
       if (B == 0) {
         // autotune the scan block on this batch: each candidate's first step is
         // checked against plain per-chain steps, then two eager steps are timed
@@ -568,15 +581,22 @@ akf_status akf_batch_plan_create(akf_batch_plan** out, int32_t n_chains, const a
         double best = 1e300;
         int maxN = 0, n_disagree = 0;
         for (int c : cp.chains) maxN = std::max(maxN, (int)chains[c].model.N);
+        // the search covers the block and, at D = 32, the sampler build's
+        // teams per SIMD
         for (int cand : {4, 8, 16, 32, 64, 128}) {
           if (cand > maxN && cand != 4) break;
-          ClassPlan trial = cp;
-          trial.B = cand;
-          const double ms = time_candidate(P->chains, trial, ref, st);
-          if (ms == -2.0) ++n_disagree;
-          if (ms > 0 && ms < best) {
-            best = ms;
-            B = cand;
+          for (int teams : {2, 1}) {
+            if (teams == 1 && D != 32) continue;
+            ClassPlan trial = cp;
+            trial.B = cand;
+            trial.sb_teams = teams;
+            const double ms = time_candidate(P->chains, trial, ref, st);
+            if (ms == -2.0) ++n_disagree;
+            if (ms > 0 && ms < best) {
+              best = ms;
+              B = cand;
+              sb_teams = teams;
+            }
           }
         }
         if (B == 0) {
@@ -584,10 +604,11 @@ akf_status akf_batch_plan_create(akf_batch_plan** out, int32_t n_chains, const a
           return fail(AKF_ERR_HIP, "autotuning failed for D = %d (%d candidates disagreed with "
                       "the plain per-chain step)", D, n_disagree);
         }
-        cache_store(tune_cache, key, B, best);
+        cache_store(tune_cache, key, B, sb_teams, best);
       }
     }
     cp.B = B;
+    cp.sb_teams = sb_teams;
     P->classes.push_back(cp);
   }
   // final layout: descriptors, items, step counter, workspaces in one allocation
@@ -658,13 +679,15 @@ akf_status akf_batch_mh_run(akf_batch_plan* P, int32_t use_graph, void* stream) 
 
 akf_status akf_batch_plan_info(const akf_batch_plan* P, int32_t max_classes, int32_t* n_classes,
                                int32_t* D, int32_t* block, int32_t* n_chains_in_class,
-                               size_t* device_bytes) {
+                               int32_t* sbuild_teams_per_simd, size_t* device_bytes) {
   if (!P || !n_classes) return fail(AKF_ERR_INVALID, "plan and n_classes must be non-NULL");
   *n_classes = (int32_t)P->classes.size();
   for (int i = 0; i < (int)P->classes.size() && i < max_classes; ++i) {
     if (D) D[i] = P->classes[i].D;
     if (block) block[i] = P->classes[i].B;
     if (n_chains_in_class) n_chains_in_class[i] = (int32_t)P->classes[i].chains.size();
+    if (sbuild_teams_per_simd)
+      sbuild_teams_per_simd[i] = P->classes[i].D == 32 ? P->classes[i].sb_teams : 0;
   }
   if (device_bytes) *device_bytes = P->dbytes;
   return AKF_OK;

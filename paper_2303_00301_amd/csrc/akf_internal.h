@@ -380,7 +380,8 @@ hipError_t launch_dyn_lin(const KModel& M, DynArgs A, int* n_part, hipStream_t s
 // Batched launches for one D class.  `step` is the device step counter.
 enum BatchPhase {
   BP_INIT = 0, BP_LIN_FWD, BP_LIN_REV, BP_FOLD, BP_UP, BP_DOWN, BP_FINAL, BP_SBUILD, BP_SFOLD,
-  BP_SUP, BP_SDOWN, BP_SFINAL, BP_FINALIZE, BP_SELECT
+  BP_SUP, BP_SDOWN, BP_SFINAL, BP_FINALIZE, BP_SELECT,
+  BP_SBUILD1  // the sampler build with one team per SIMD (a layout the autotuner may pick)
 };
 hipError_t launch_batch_phase(int D, int phase, BatchLaunch L, int level, int rev,
                               const int* step, hipStream_t st);

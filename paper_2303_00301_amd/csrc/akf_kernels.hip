@@ -2079,6 +2079,21 @@ __global__ void __launch_bounds__(Cfg<D>::NT, D == 64 ? 1 : 2) kb_sbuild(BatchLa
   }
 }
 
+// the same with one team per SIMD and the whole register file: no spills and
+// fully unrolled products, half the teams (the autotuner times both layouts)
+template <int D>
+__global__ void __launch_bounds__(Cfg<D>::NT, 1) kb_sbuild1(BatchLaunch L, const int* step) {
+  const int s = *step;
+  for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
+    const Item I = L.items[w];
+    const ChainDev& c = L.cd[I.c];
+    SampArgs S = c.S;
+    S.xi_x = c.xi_base + (int64_t)s * c.xi_stride + (int64_t)c.M.N * c.M.d;
+    samp_build_body<D, D / 4>(c.M, S, I.i);
+    __syncthreads();
+  }
+}
+
 template <int D>
 __global__ void __launch_bounds__(Cfg<D>::NT) kb_sfold(BatchLaunch L) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
@@ -2156,7 +2171,7 @@ template <int D>
 size_t batch_lds_bytes_t(int phase) {
   if (phase == BP_FOLD || phase == BP_UP || phase == BP_DOWN || phase == BP_FINAL)
     return lds_bytes_filter<D>();
-  if (phase == BP_SBUILD) return lds_bytes_samp_build<D>();
+  if (phase == BP_SBUILD || phase == BP_SBUILD1) return lds_bytes_samp_build<D>();
   if (phase == BP_SFOLD || phase == BP_SUP) return lds_bytes_samp2<D>();
   return 0;
 }
@@ -2191,6 +2206,14 @@ hipError_t launch_batch_phase_t(int phase, BatchLaunch L, int level, int rev, co
     case BP_SBUILD:
       timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 1, st);
       hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step);
+      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 0, st);
+      break;
+    case BP_SBUILD1:
+      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 1, st);
+      if constexpr (D == 64)
+        hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step);  // one team per CU either way
+      else
+        hipLaunchKernelGGL(kb_sbuild1<D>, g, bt, lds, st, L, step);
       timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 0, st);
       break;
     case BP_SFOLD: hipLaunchKernelGGL(kb_sfold<D>, g, bt, lds, st, L); break;

@@ -670,10 +670,12 @@ class BatchPlan:
         D = (C.c_int32 * 4)()
         B = (C.c_int32 * 4)()
         nc = (C.c_int32 * 4)()
+        sb = (C.c_int32 * 4)()
         nbytes = C.c_size_t()
-        _lib.check(lib.akf_batch_plan_info(self.handle, 4, C.byref(n), D, B, nc, C.byref(nbytes)),
-                   "akf_batch_plan_info")
-        return dict(classes=[dict(D=D[i], block=B[i], chains=nc[i]) for i in range(n.value)],
+        _lib.check(lib.akf_batch_plan_info(self.handle, 4, C.byref(n), D, B, nc, sb,
+                                           C.byref(nbytes)), "akf_batch_plan_info")
+        return dict(classes=[dict(D=D[i], block=B[i], chains=nc[i], sbuild_teams_per_simd=sb[i])
+                             for i in range(n.value)],
                     device_bytes=nbytes.value)
 
     def close(self):

@@ -125,7 +125,10 @@ def test_autotuner_cache(S, tmp_path):
     lines = open(cache).read().strip().splitlines()
     assert len(lines) == len(i1["classes"])
     p2 = S.BatchPlan(chains, 1, block=0, tune_cache=cache)
-    assert [c["block"] for c in p2.info()["classes"]] == [c["block"] for c in i1["classes"]]
+    assert [(c["block"], c["sbuild_teams_per_simd"]) for c in p2.info()["classes"]] == \
+        [(c["block"], c["sbuild_teams_per_simd"]) for c in i1["classes"]]
+    for c in i1["classes"]:
+        assert c["sbuild_teams_per_simd"] in ((1, 2) if c["D"] == 32 else (0,))
     assert len(open(cache).read().strip().splitlines()) == len(lines)
     p1.close()
     p2.close()
@@ -239,3 +242,41 @@ def test_batched_benchmark_shape_autotuned(S, tmp_path):
             assert abs(g - r[key]) <= 1e-8 * max(1.0, abs(r[key])) + 1e-9 * w.N, (k, key)
         if abs(np.log(w.uniforms(n_steps)[0]) - r["log_ratio"]) > tol:
             assert int(N_(c["accepted"])[0]) == r["accepted"]
+
+
+def test_sbuild_layouts_from_the_cache(S, tmp_path):
+    """The autotuner also picks the D = 32 sampler build's teams per SIMD (two,
+    or one with the whole register file).  Each layout, forced through a cache
+    line of this batch's key, gives the same chains as plain per-chain runs."""
+    ws = [w for w in W.ragged_poisson_batch(n_chains=24, n_min=40, n_max=600, seed=12)
+          if w.dx > 16][:6]
+    assert len(ws) >= 3
+    n_steps = 2
+    cache = tmp_path / "tune.jsonl"
+    plan = S.BatchPlan(_chains(S, ws, n_steps), n_steps, block=0, tune_cache=str(cache))
+    plan.close()
+    (line,) = open(cache).read().strip().splitlines()
+    assert '"sbuild_teams_per_simd": ' in line and '"verified": true' in line
+    head, tail = line.split(', "sbuild_teams_per_simd": ')
+    for teams in (1, 2):
+        cache.write_text(f'{head}, "sbuild_teams_per_simd": {teams}{tail[1:]}\n')
+        chains = _chains(S, ws, n_steps)
+        plan = S.BatchPlan(chains, n_steps, block=0, tune_cache=str(cache))
+        (cls,) = plan.info()["classes"]
+        assert cls["D"] == 32 and cls["sbuild_teams_per_simd"] == teams
+        assert len(open(cache).read().strip().splitlines()) == 1  # read, not re-tuned
+        plan.run(use_graph=True)
+        torch.cuda.synchronize()
+        for w, c in zip(ws, chains):
+            x = T(c["x0"])
+            ref = S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"],
+                           block=cls["block"])
+            torch.cuda.synchronize()
+            assert torch.equal(c["status"], ref["status"]), (teams, w.name)
+            for k in range(n_steps):
+                lr, lr_ref = float(N_(c["log_ratio"])[k]), float(N_(ref["log_ratio"])[k])
+                assert abs(lr - lr_ref) <= _lr_tol(w.N, w.dx, lr_ref), (teams, w.name, k)
+            if torch.equal(c["accepted"], ref["accepted"]):
+                err = torch.linalg.norm(c["x"] - x) / max(1.0, float(torch.linalg.norm(x)))
+                assert float(err) <= 1e-9, (teams, w.name, float(err))
+        plan.close()
