@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -42,8 +43,6 @@ struct akf_batch_plan {
 };
 
 namespace {
-
-int teams_per_cu(int D) { return D == 64 ? 1 : (D == 32 ? 4 : 8); }
 
 int grid_for(int n, int cap) { return std::max(1, std::min(n, cap)); }
 
@@ -96,7 +95,9 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
     t.n = (int)(b.items.size() - t.off);
     t.grid = grid_for(t.n, cap);
   };
-  const int team_cap = 256 * teams_per_cu(cp.D);
+  // team phases: one workgroup per item here; each launch then caps its grid
+  // at what its kernel keeps resident on the chip (launch_batch_phase)
+  const int team_cap = INT_MAX;
   tab(cp.init, [&] { for (int c : cp.chains) b.items.push_back({c, 0}); }, 1024);
   tab(cp.lin, [&] {
     for (int c : cp.chains) {
@@ -105,11 +106,7 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
     }
   }, 8192);
   tab(cp.fold, [&] { for (int c : cp.chains) for (int k = 0; k < lay[c].nb; ++k) b.items.push_back({c, k}); }, team_cap);
-  // the sampler element build runs one or two one-wave teams per SIMD at
-  // D = 32 (the autotuner's choice; D = 16 teams already fill the CU, D = 64
-  // teams take a whole CU)
-  const int sbuild_cap = (cp.D == 32 && cp.sb_teams == 2 ? 2 : 1) * team_cap;
-  tab(cp.sbuild, [&] { for (int c : cp.chains) for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t}); }, sbuild_cap);
+  tab(cp.sbuild, [&] { for (int c : cp.chains) for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t}); }, team_cap);
   tab(cp.fin, [&] { for (int c : cp.chains) b.items.push_back({c, 0}); }, 1024);
   for (int l = 1; l <= cp.Lmax; ++l) {
     tab(cp.up[l], [&] {
@@ -552,6 +549,7 @@ akf_status akf_batch_plan_create(akf_batch_plan** out, int32_t n_chains, const a
   }
   akf_status s = prepare_device();
   if (s != AKF_OK) return s;
+  for (int D : {16, 32, 64}) batch_caps(D);
   hipStream_t st = (hipStream_t)stream;
   akf_batch_plan* P = new akf_batch_plan();
   P->n_chains = n_chains;

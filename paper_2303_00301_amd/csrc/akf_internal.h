@@ -387,5 +387,7 @@ hipError_t launch_batch_phase(int D, int phase, BatchLaunch L, int level, int re
                               const int* step, hipStream_t st);
 hipError_t launch_step_advance(int* step, int reset, hipStream_t st);
 size_t batch_lds_bytes(int D, int phase);
+// Queries the resident-grid cap of every team phase at width D (kept per kernel).
+void batch_caps(int D);
 
 }  // namespace akf

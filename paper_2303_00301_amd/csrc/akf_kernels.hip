@@ -2021,7 +2021,7 @@ __global__ void __launch_bounds__(256) kb_lin(BatchLaunch L, int rev, const int*
 }
 
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) kb_fold(BatchLaunch L, int rev) {
+__global__ void __launch_bounds__(Cfg<D>::NT, D == 16 ? 3 : 1) kb_fold(BatchLaunch L, int rev) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
@@ -2031,7 +2031,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_fold(BatchLaunch L, int rev) {
 }
 
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) kb_final(BatchLaunch L, int rev) {
+__global__ void __launch_bounds__(Cfg<D>::NT, D == 16 ? 3 : D == 32 ? 2 : 1) kb_final(BatchLaunch L, int rev) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
@@ -2053,7 +2053,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_up(BatchLaunch L, int level, in
 }
 
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT) kb_down(BatchLaunch L, int level, int rev) {
+__global__ void __launch_bounds__(Cfg<D>::NT, D == 16 ? 3 : 1) kb_down(BatchLaunch L, int level, int rev) {
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
     const Item I = L.items[w];
     const ChainDev& c = L.cd[I.c];
@@ -2066,7 +2066,7 @@ __global__ void __launch_bounds__(Cfg<D>::NT) kb_down(BatchLaunch L, int level, 
 
 // two teams per SIMD where the persistent loop's registers still fit (D <= 32)
 template <int D>
-__global__ void __launch_bounds__(Cfg<D>::NT, D == 64 ? 1 : 2) kb_sbuild(BatchLaunch L,
+__global__ void __launch_bounds__(Cfg<D>::NT, D == 64 ? 1 : D == 16 ? 3 : 2) kb_sbuild(BatchLaunch L,
                                                                      const int* step) {
   const int s = *step;
   for (int w = blockIdx.x; w < L.n_items; w += gridDim.x) {
@@ -2185,10 +2185,58 @@ size_t batch_lds_bytes(int D, int phase) {
   return 0;
 }
 
+// Workgroups of `kernel` that the chip holds at once: its occupancy per CU
+// (registers and LDS) times the CU count.  A persistent phase launches no more
+// than that, so every workgroup starts at once and none waits for a slot.
+template <typename K>
+int resident_grid(K kernel, int threads, size_t lds) {
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  return per_cu * std::max(1, compute_units());
+}
+
+// The cap of each team phase, queried once per kernel (batch_caps() queries
+// them all when a plan is made, outside any graph capture).
+template <int D>
+int batch_cap(int phase) {
+  constexpr int NT = Cfg<D>::NT;
+  switch (phase) {
+    case BP_FOLD: { static const int c = resident_grid(kb_fold<D>, NT, batch_lds_bytes(D, phase)); return c; }
+    case BP_UP: { static const int c = resident_grid(kb_up<D>, NT, batch_lds_bytes(D, phase)); return c; }
+    case BP_DOWN: { static const int c = resident_grid(kb_down<D>, NT, batch_lds_bytes(D, phase)); return c; }
+    case BP_FINAL: { static const int c = resident_grid(kb_final<D>, NT, batch_lds_bytes(D, phase)); return c; }
+    case BP_SBUILD: { static const int c = resident_grid(kb_sbuild<D>, NT, batch_lds_bytes(D, phase)); return c; }
+    case BP_SBUILD1: {
+      static const int c = D == 64 ? batch_cap<D>(BP_SBUILD)
+                                   : resident_grid(kb_sbuild1<D>, NT, batch_lds_bytes(D, phase));
+      return c;
+    }
+    case BP_SFOLD: { static const int c = resident_grid(kb_sfold<D>, NT, batch_lds_bytes(D, phase)); return c; }
+    case BP_SUP: { static const int c = resident_grid(kb_sup<D>, NT, batch_lds_bytes(D, phase)); return c; }
+    case BP_SDOWN: { static const int c = resident_grid(kb_sdown<D>, 64, 0); return c; }
+    case BP_SFINAL: { static const int c = resident_grid(kb_sfinal<D>, 64, 0); return c; }
+  }
+  return 0;  // the other phases keep the plan's grid
+}
+
+void batch_caps(int D) {
+  for (int ph = 0; ph <= BP_SBUILD1; ++ph) {
+    switch (D) {
+      case 16: batch_cap<16>(ph); break;
+      case 32: batch_cap<32>(ph); break;
+      case 64: batch_cap<64>(ph); break;
+    }
+  }
+}
+
 template <int D>
 hipError_t launch_batch_phase_t(int phase, BatchLaunch L, int level, int rev, const int* step,
                                 hipStream_t st) {
   if (L.n_items <= 0) return hipSuccess;
+  const int cap = batch_cap<D>(phase);
+  if (cap > 0) L.grid = std::min(L.n_items, cap);
   const dim3 g(L.grid), bt(Cfg<D>::NT), b64(64), b256(256);
   const size_t lds = batch_lds_bytes(D, phase);
   switch (phase) {
