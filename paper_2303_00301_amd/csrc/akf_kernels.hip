@@ -688,16 +688,24 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       }
       rm_load<D>(Pp, M.Q, d, d);  // issued early: its latency overlaps F C
       rm_stage<D>(Cc, B1);
+      // below D = 64 F C and T = F A are formed together; at D = 64 the
+      // register file cannot hold both through the next product
+      constexpr bool PAIR = (D < 64);
+      if (first || !PAIR) {
+        team_sync();
+        gemm<D, false, false, false, U>(R1, sF, B1);  // F C
+      } else {
+        rm_stage<D>(A, B3);
+        team_sync();
+        gemm2<D, false, false, U>(R1, T, sF, B1, B3);  // F C and T = F A
+      }
       team_sync();
-      gemm<D, false, false, false, U>(T, sF, B1);  // F C
-      team_sync();
-      rm_stage<D>(T, B1);
+      rm_stage<D>(R1, B1);
       team_sync();
       gemm<D, false, true, true, U>(Pp, B1, sF);  // Q + (F C) F'
       matvec<D, false>(vmu, sF, vb);
-      team_sync();
       if (tid < d && bt) vmu[tid] += bt[tid];
-      if (!first) {
+      if (!first && !PAIR) {
         rm_stage<D>(A, B1);
         team_sync();
         gemm<D, false, false, false, U>(T, sF, B1);  // T = F A
@@ -722,13 +730,19 @@ __device__ __forceinline__ void filter_fold_impl(const KModel& M, const FilterAr
       ok = spd_inv<D>(R2, d, B2, &logdet) && ok;  // R2 = S^{-1}
       rm_stage<D>(R2, B2);
       team_sync();
-      gemm<D, false, false, false, U>(Cc, B2, B1);  // S^{-1} Pp
+      // S^{-1} Pp and S^{-1} T formed together (not in the batched D = 64
+      // fold, U = 4, whose register allocation spills more with the pair)
+      constexpr bool PAIR2 = !(D == 64 && U < 8);
+      if (first || !PAIR2)
+        gemm<D, false, false, false, U>(Cc, B2, B1);  // S^{-1} Pp
+      else
+        gemm2<D, false, false, U>(Cc, R1, B2, B1, B3);  // S^{-1} Pp, S^{-1} T
       AKF_RM_FOR(D, q, r, i, j) Cc.t[q][r] *= vom[i];
-      matvec<D, false>(vs, B2, vw);  // S^{-1} w
+      matvec<D, false>(vs, B2, vw);  // S^{-1} w (ends synchronised: B1 is free)
       ld_sum += logdet;
       if (tid < D) q_part += vw[tid] * vs[tid];
       if (!first) {
-        gemm<D, false, false, false, U>(R1, B2, B3);  // S^{-1} T
+        if (!PAIR2) gemm<D, false, false, false, U>(R1, B2, B3);  // S^{-1} T
         rm_stage<D>(R1, B1);
         team_sync();
         // fully unrolled where the register budget still allows it
@@ -936,12 +950,18 @@ __device__ __forceinline__ void filter_combine(const KModel& M, const double* __
   rm_stage<D>(Aj, S0);  // S0 = A_j
   if (tid < D) vw[tid] += vbi[tid];
   team_sync();
-  if constexpr (SIDE != 2) {
+  // both sides: A_j Z1 and A_j M formed together (not in the batched D = 64
+  // up-sweep, U = 4, whose register allocation spills more with the pair)
+  constexpr bool PAIR = (SIDE == 0) && !(D == 64 && U < 8);
+  if constexpr (PAIR) {
+    gemm2<D, false, false, U>(R3, R2, S0, S1, S2);  // A = A_j Z1, A_j M
+    rm_store<D>(R3, out + EL::A, D, D);
+  } else if constexpr (SIDE != 2) {
     gemm<D, false, false, false, U>(R3, S0, S1);  // A = A_j Z1
     rm_store<D>(R3, out + EL::A, D, D);
   }
   if constexpr (SIDE != 1) {
-    gemm<D, false, false, false, U>(R2, S0, S2);  // A_j M
+    if constexpr (!PAIR) gemm<D, false, false, false, U>(R2, S0, S2);  // A_j M
     matvec<D, false>(vc, S0, vw);              // A_j (b_i + M c)
     rm_stage<D>(R2, S3);
     team_sync();

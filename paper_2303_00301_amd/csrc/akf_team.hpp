@@ -258,6 +258,47 @@ __device__ __forceinline__ void gemm(RM<D>& c, const double* sA, const double* s
   }
 }
 
+// c1 = op(A) B1, c2 = op(A) B2 (+ c when ACC): two products that share their
+// left operand, interleaved so that each k-step loads A's fragments once and
+// issues twice as many independent MFMA chains behind its loads.
+template <int D, bool TA, bool ACC, int U = 4>
+__device__ __forceinline__ void gemm2(RM<D>& c1, RM<D>& c2, const double* sA, const double* sB1,
+                                      const double* sB2) {
+  using C = Cfg<D>;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int r0 = (D == 64) ? 32 * (w >> 1) : 0, c0 = (D == 64) ? 32 * (w & 1) : 0;
+  const int li = l & 15, lk = l >> 4;
+  if (!ACC) {
+    rm_zero<D>(c1);
+    rm_zero<D>(c2);
+  }
+#pragma unroll U
+  for (int kb = 0; kb < D / 4; ++kb) {
+    const int k = 4 * kb + lk;
+    double a[C::TS], b1[C::TS], b2[C::TS];
+#pragma unroll
+    for (int ti = 0; ti < C::TS; ++ti) {
+      const int i = r0 + 16 * ti + li;
+      a[ti] = TA ? sA[k * C::LD + i] : sA[i * C::LD + k];
+    }
+#pragma unroll
+    for (int tj = 0; tj < C::TS; ++tj) {
+      const int j = c0 + 16 * tj + li;
+      b1[tj] = sB1[k * C::LD + j];
+      b2[tj] = sB2[k * C::LD + j];
+    }
+#pragma unroll
+    for (int ti = 0; ti < C::TS; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < C::TS; ++tj) {
+        c1.t[ti * C::TS + tj] =
+            __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b1[tj], c1.t[ti * C::TS + tj], 0, 0, 0);
+        c2.t[ti * C::TS + tj] =
+            __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b2[tj], c2.t[ti * C::TS + tj], 0, 0, 0);
+      }
+  }
+}
+
 // element (ti, tj, r) of a register matrix with a runtime tile index ti or tj
 // (TS <= 2).  Both candidates are read as values before the select: a select
 // between two element lvalues would index the register array at run time and
