@@ -10,7 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libauxkf.so")
 ARCH = os.environ.get("AKF_OFFLOAD_ARCH", "gfx950")
 SOURCES = ["akf_kernels.hip", "akf_adjoint.hip", "akf_fact.hip", "akf_dyn.hip", "akf_dnc.hip",
-           "akf_fixed.hip", "akf_gibbs.hip", "akf_noalloc.hip", "akf_sqrt.hip",
+           "akf_fixed.hip", "akf_gibbs.hip", "akf_noalloc.hip", "akf_sqrt.hip", "akf_lane.hip",
            "akf_layout.cpp", "akf_capi.cpp", "akf_batch.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -26,7 +26,12 @@ struct ClassPlan {
     size_t off = 0;  // index into the item table
     int n = 0, grid = 0;
   };
-  Tab init, lin, fold, sbuild, fin, up[kMaxLv + 1], down[kMaxLv + 1];
+  // fold: every chain's blocks (the sampler fold and final); fold_team /
+  // fold_lane and sbuild / sbuild_lane: the filter fold, re-scan and sampler
+  // build items of the chains on teams and of those on one lane per item
+  // (d <= 4 in the 16-wide class)
+  Tab init, lin, fold, fold_team, fold_lane, sbuild, sbuild_lane, fin, up[kMaxLv + 1],
+      down[kMaxLv + 1];
 };
 
 struct akf_batch_plan {
@@ -106,7 +111,27 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
     }
   }, 8192);
   tab(cp.fold, [&] { for (int c : cp.chains) for (int k = 0; k < lay[c].nb; ++k) b.items.push_back({c, k}); }, team_cap);
-  tab(cp.sbuild, [&] { for (int c : cp.chains) for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t}); }, team_cap);
+  auto on_lane = [&](int c) { return cp.D == 16 && chains[c].model.dx <= kLaneMaxD; };
+  tab(cp.fold_team, [&] {
+    for (int c : cp.chains)
+      if (!on_lane(c))
+        for (int k = 0; k < lay[c].nb; ++k) b.items.push_back({c, k});
+  }, team_cap);
+  tab(cp.fold_lane, [&] {
+    for (int c : cp.chains)
+      if (on_lane(c))
+        for (int k = 0; k < lay[c].nb; ++k) b.items.push_back({c, k});
+  }, team_cap);
+  tab(cp.sbuild, [&] {
+    for (int c : cp.chains)
+      if (!on_lane(c))
+        for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t});
+  }, team_cap);
+  tab(cp.sbuild_lane, [&] {
+    for (int c : cp.chains)
+      if (on_lane(c))
+        for (int t = 0; t < chains[c].model.N; ++t) b.items.push_back({c, t});
+  }, team_cap);
   tab(cp.fin, [&] { for (int c : cp.chains) b.items.push_back({c, 0}); }, 1024);
   for (int l = 1; l <= cp.Lmax; ++l) {
     tab(cp.up[l], [&] {
@@ -234,11 +259,17 @@ hipError_t enqueue_class_step_part(const ClassPlan& cp, const ChainDev* d_desc, 
   auto run = [&](int phase, const ClassPlan::Tab& t, int level, int rev) {
     if (e == hipSuccess) e = launch_batch_phase(cp.D, phase, L(t), level, rev, d_step, st);
   };
+  // the timing hook brackets a phase's team and lane launches together
+  const int fam_off = cp.D == 16 ? 0 : cp.D == 32 ? 1 : 2;
   auto filter = [&](int rev) {
-    run(BP_FOLD, cp.fold, 0, rev);
+    timing_mark(FAM_BATCH_FOLD16 + fam_off, 1, st);
+    run(BP_FOLD_LANE, cp.fold_lane, 0, rev);
+    run(BP_FOLD, cp.fold_team, 0, rev);
+    timing_mark(FAM_BATCH_FOLD16 + fam_off, 0, st);
     for (int l = 1; l <= cp.Lmax; ++l) run(BP_UP, cp.up[l], l, rev);
     for (int l = cp.Lmax; l >= 1; --l) run(BP_DOWN, cp.down[l], l, rev);
-    run(BP_FINAL, cp.fold, 0, rev);
+    run(BP_FINAL_LANE, cp.fold_lane, 0, rev);
+    run(BP_FINAL, cp.fold_team, 0, rev);
   };
   switch (part) {
     case 0:
@@ -247,7 +278,10 @@ hipError_t enqueue_class_step_part(const ClassPlan& cp, const ChainDev* d_desc, 
       filter(0);
       break;
     case 1:
+      timing_mark(FAM_BATCH_SBUILD16 + fam_off, 1, st);
+      run(BP_SBUILD_LANE, cp.sbuild_lane, 0, 0);
       run(cp.sb_teams == 2 ? BP_SBUILD : BP_SBUILD1, cp.sbuild, 0, 0);
+      timing_mark(FAM_BATCH_SBUILD16 + fam_off, 0, st);
       run(BP_SFOLD, cp.fold, 0, 0);
       for (int l = 1; l <= cp.Lmax; ++l) run(BP_SUP, cp.up[l], l, 0);
       for (int l = cp.Lmax; l >= 1; --l) run(BP_SDOWN, cp.down[l], l, 0);
@@ -390,6 +424,7 @@ double time_candidate(const std::vector<akf_chain>& chains, ClassPlan cp, const 
   b.items.clear();
   b.ws_total = 0;
   build_class(cp, chains, b, ws, &tr);
+  (void)launch_zero(reinterpret_cast<double*>(ws), (int64_t)(b.ws_total / 8), st);  // as the plan's
   ChainDev* d_desc = reinterpret_cast<ChainDev*>(mem);
   Item* d_items = reinterpret_cast<Item*>(mem + desc_bytes);
   int* d_step = reinterpret_cast<int*>(mem + desc_bytes + item_bytes);
@@ -625,6 +660,12 @@ akf_status akf_batch_plan_create(akf_batch_plan** out, int32_t n_chains, const a
   b.items.clear();
   b.ws_total = 0;
   for (ClassPlan& cp : P->classes) build_class(cp, P->chains, b, ws, nullptr);
+  // zero once: the padding of arrays that only the lane kernels write
+  // (akf_lane.hip stores the 4 x 4 corners) stays zero from here on
+  if (launch_zero(reinterpret_cast<double*>(ws), (int64_t)(b.ws_total / 8), st) != hipSuccess) {
+    akf_batch_plan_destroy(P);
+    return fail(AKF_ERR_HIP, "zeroing the batch plan's workspace failed");
+  }
   P->d_desc = reinterpret_cast<ChainDev*>(P->dmem);
   P->d_items = reinterpret_cast<Item*>(P->dmem + desc_bytes);
   P->d_step = reinterpret_cast<int*>(P->dmem + desc_bytes + item_bytes);

@@ -289,6 +289,9 @@ struct LgArgs {
 // tables of (chain, item) pairs walked by persistent kernels.
 // ---------------------------------------------------------------------------
 constexpr int kMaxLv = 24;
+// batched chains with d <= kLaneMaxD run their fold, re-scan and sampler build
+// one lane per item (akf_lane.hip)
+constexpr int kLaneMaxD = 4;
 
 struct ChainDev {
   KModel M;
@@ -381,7 +384,9 @@ hipError_t launch_dyn_lin(const KModel& M, DynArgs A, int* n_part, hipStream_t s
 enum BatchPhase {
   BP_INIT = 0, BP_LIN_FWD, BP_LIN_REV, BP_FOLD, BP_UP, BP_DOWN, BP_FINAL, BP_SBUILD, BP_SFOLD,
   BP_SUP, BP_SDOWN, BP_SFINAL, BP_FINALIZE, BP_SELECT,
-  BP_SBUILD1  // the sampler build with one team per SIMD (a layout the autotuner may pick)
+  BP_SBUILD1,  // the sampler build with one team per SIMD (a layout the autotuner may pick)
+  // one lane per item for chains with d <= 4 in the 16-wide class (akf_lane.hip)
+  BP_FOLD_LANE, BP_FINAL_LANE, BP_SBUILD_LANE
 };
 hipError_t launch_batch_phase(int D, int phase, BatchLaunch L, int level, int rev,
                               const int* step, hipStream_t st);
@@ -389,5 +394,6 @@ hipError_t launch_step_advance(int* step, int reset, hipStream_t st);
 size_t batch_lds_bytes(int D, int phase);
 // Queries the resident-grid cap of every team phase at width D (kept per kernel).
 void batch_caps(int D);
+hipError_t launch_lane_phase(int phase, BatchLaunch L, int rev, const int* step, hipStream_t st);
 
 }  // namespace akf

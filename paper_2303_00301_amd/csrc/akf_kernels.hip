@@ -2255,6 +2255,8 @@ template <int D>
 hipError_t launch_batch_phase_t(int phase, BatchLaunch L, int level, int rev, const int* step,
                                 hipStream_t st) {
   if (L.n_items <= 0) return hipSuccess;
+  if (phase == BP_FOLD_LANE || phase == BP_FINAL_LANE || phase == BP_SBUILD_LANE)
+    return launch_lane_phase(phase, L, rev, step, st);
   const int cap = batch_cap<D>(phase);
   if (cap > 0) L.grid = std::min(L.n_items, cap);
   const dim3 g(L.grid), bt(Cfg<D>::NT), b64(64), b256(256);
@@ -2263,26 +2265,16 @@ hipError_t launch_batch_phase_t(int phase, BatchLaunch L, int level, int rev, co
     case BP_INIT: hipLaunchKernelGGL(kb_init, g, b64, 0, st, L, D); break;
     case BP_LIN_FWD: hipLaunchKernelGGL(kb_lin, g, b256, 0, st, L, 0, step); break;
     case BP_LIN_REV: hipLaunchKernelGGL(kb_lin, g, b256, 0, st, L, 1, step); break;
-    case BP_FOLD:
-      timing_mark(FAM_BATCH_FOLD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 1, st);
-      hipLaunchKernelGGL(kb_fold<D>, g, bt, lds, st, L, rev);
-      timing_mark(FAM_BATCH_FOLD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 0, st);
-      break;
+    case BP_FOLD: hipLaunchKernelGGL(kb_fold<D>, g, bt, lds, st, L, rev); break;
     case BP_UP: hipLaunchKernelGGL(kb_up<D>, g, bt, lds, st, L, level, rev); break;
     case BP_DOWN: hipLaunchKernelGGL(kb_down<D>, g, bt, lds, st, L, level, rev); break;
     case BP_FINAL: hipLaunchKernelGGL(kb_final<D>, g, bt, lds, st, L, rev); break;
-    case BP_SBUILD:
-      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 1, st);
-      hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step);
-      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 0, st);
-      break;
+    case BP_SBUILD: hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step); break;
     case BP_SBUILD1:
-      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 1, st);
       if constexpr (D == 64)
         hipLaunchKernelGGL(kb_sbuild<D>, g, bt, lds, st, L, step);  // one team per CU either way
       else
         hipLaunchKernelGGL(kb_sbuild1<D>, g, bt, lds, st, L, step);
-      timing_mark(FAM_BATCH_SBUILD16 + (D == 16 ? 0 : D == 32 ? 1 : 2), 0, st);
       break;
     case BP_SFOLD: hipLaunchKernelGGL(kb_sfold<D>, g, bt, lds, st, L); break;
     case BP_SUP: hipLaunchKernelGGL(kb_sup<D>, g, bt, lds, st, L, level); break;
