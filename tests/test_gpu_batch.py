@@ -280,3 +280,47 @@ def test_sbuild_layouts_from_the_cache(S, tmp_path):
                 err = torch.linalg.norm(c["x"] - x) / max(1.0, float(torch.linalg.norm(x)))
                 assert float(err) <= 1e-9, (teams, w.name, float(err))
         plan.close()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_small_state_chains_on_lanes(S, use_graph):
+    """Chains with d <= 4 run their filter fold, re-scan and sampler build one
+    lane per item (4 x 4 register algebra) inside the 16-wide group: every d
+    from 1 to 4, N from 1 up to several blocks with a ragged tail, beside
+    16-wide team chains of the same group, equal to plain per-chain runs; the
+    first step of each small chain equals the oracle's."""
+    ws = W.ragged_poisson_batch(n_chains=12, n_min=1, n_max=200, dims=(1, 2, 3, 4), seed=21)
+    ws += W.ragged_poisson_batch(n_chains=2, n_min=30, n_max=90, dims=(16,), seed=22)
+    ws[0] = W.ragged_poisson_batch(n_chains=1, n_min=1, n_max=1, dims=(3,), seed=23)[0]
+    assert {w.dx for w in ws} >= {1, 2, 3, 4, 16} and min(w.N for w in ws) == 1
+    n_steps = 3
+    chains = _chains(S, ws, n_steps)
+    plan = S.BatchPlan(chains, n_steps, block=8)
+    assert [c["D"] for c in plan.info()["classes"]] == [16]
+    plan.run(use_graph=use_graph)
+    torch.cuda.synchronize()
+    for w, c in zip(ws, chains):
+        x = T(c["x0"])
+        ref = S.mh_run(c["model"], c["y"], x, c["delta"], 2, c["xi"], c["unif"], block=8)
+        torch.cuda.synchronize()
+        assert torch.equal(c["status"], ref["status"]), w.name
+        assert torch.equal(c["accepted"], ref["accepted"]), w.name
+        torch.testing.assert_close(c["x"], x, rtol=1e-9, atol=1e-11, msg=w.name)
+        for k in ("log_ratio", "logZ_fwd", "logZ_rev"):
+            torch.testing.assert_close(c[k], ref[k], rtol=1e-9, atol=1e-9, msg=f"{w.name} {k}")
+    plan.close()
+    # the first step of each small chain against the oracle
+    one = _chains(S, ws, 1)
+    plan = S.BatchPlan(one, 1, block=8)
+    plan.run(use_graph=use_graph)
+    torch.cuda.synchronize()
+    for w, c in zip(ws, one):
+        if w.dx > 4:
+            continue
+        M = oracle.Model(**w.oracle_kwargs())
+        xi = w.normals(1)[0]
+        r = oracle.mh_step(M, w.y, c["x0"], w.delta, 2, xi[0], xi[1], w.uniforms(1)[0])
+        assert int(c["status"].item()) == r["status"], w.name
+        assert abs(c["log_ratio"].item() - r["log_ratio"]) < 1e-7 * max(1, abs(r["log_ratio"]))
+        np.testing.assert_allclose(c["x"].cpu().numpy(), r["x_out"], rtol=1e-7, atol=1e-8)
+    plan.close()
