@@ -258,9 +258,8 @@ def bench_batched(torch, S, W, _lib, K: int, dev, cpu: bool = False) -> dict:
                                    PEAK_FP64_TFLOPS, "TFLOP/s", 1e12)
         roof[kname]["launches"] = n_l.value
         if D == 16:  # the timed phase also runs the d <= 4 chains, one lane per item
-            roof[kname]["includes"] = ("kl_phase<0> (fold)" if kind == "fold"
-                                       else "kl_phase<2> (sampler build)") + \
-                " for the d <= 4 chains, one lane per item
+            lane = "kl_phase<0> (fold)" if kind == "fold" else "kl_phase<2> (sampler build)"
+            roof[kname]["includes"] = lane + " for the d <= 4 chains, one lane per item"
     for c in chains:
         c["x"].copy_(c["x0"])
     torch.cuda.synchronize()
