@@ -26,11 +26,10 @@ struct ClassPlan {
     size_t off = 0;  // index into the item table
     int n = 0, grid = 0;
   };
-  // fold: every chain's blocks (the sampler fold and final); fold_team /
-  // fold_lane and sbuild / sbuild_lane: the filter fold, re-scan and sampler
-  // build items of the chains on teams and of those on one lane per item
+  // fold_team / fold_lane and sbuild / sbuild_lane: the per-block and
+  // per-step items of the chains on teams and of those on one lane per item
   // (d <= 4 in the 16-wide class)
-  Tab init, lin, fold, fold_team, fold_lane, sbuild, sbuild_lane, fin, up[kMaxLv + 1],
+  Tab init, lin, fold_team, fold_lane, sbuild, sbuild_lane, fin, up[kMaxLv + 1],
       down[kMaxLv + 1];
 };
 
@@ -110,7 +109,6 @@ void build_class(ClassPlan& cp, const std::vector<akf_chain>& chains, Built& b, 
       for (int k = 0; k < nchunk; ++k) b.items.push_back({c, k});
     }
   }, 8192);
-  tab(cp.fold, [&] { for (int c : cp.chains) for (int k = 0; k < lay[c].nb; ++k) b.items.push_back({c, k}); }, team_cap);
   auto on_lane = [&](int c) { return cp.D == 16 && chains[c].model.dx <= kLaneMaxD; };
   tab(cp.fold_team, [&] {
     for (int c : cp.chains)
@@ -282,10 +280,12 @@ hipError_t enqueue_class_step_part(const ClassPlan& cp, const ChainDev* d_desc, 
       run(BP_SBUILD_LANE, cp.sbuild_lane, 0, 0);
       run(cp.sb_teams == 2 ? BP_SBUILD : BP_SBUILD1, cp.sbuild, 0, 0);
       timing_mark(FAM_BATCH_SBUILD16 + fam_off, 0, st);
-      run(BP_SFOLD, cp.fold, 0, 0);
+      run(BP_SFOLD_LANE, cp.fold_lane, 0, 0);
+      run(BP_SFOLD, cp.fold_team, 0, 0);
       for (int l = 1; l <= cp.Lmax; ++l) run(BP_SUP, cp.up[l], l, 0);
       for (int l = cp.Lmax; l >= 1; --l) run(BP_SDOWN, cp.down[l], l, 0);
-      run(BP_SFINAL, cp.fold, 0, 0);
+      run(BP_SFINAL_LANE, cp.fold_lane, 0, 0);
+      run(BP_SFINAL, cp.fold_team, 0, 0);
       break;
     case 2:
       run(BP_LIN_REV, cp.lin, 0, 1);

@@ -289,8 +289,9 @@ struct LgArgs {
 // tables of (chain, item) pairs walked by persistent kernels.
 // ---------------------------------------------------------------------------
 constexpr int kMaxLv = 24;
-// batched chains with d <= kLaneMaxD run their fold, re-scan and sampler build
-// one lane per item (akf_lane.hip)
+// batched chains with d <= kLaneMaxD run their filter fold and re-scan and the
+// sampler's element build, block fold and final pass one lane per item
+// (akf_lane.hip)
 constexpr int kLaneMaxD = 4;
 
 struct ChainDev {
@@ -386,7 +387,7 @@ enum BatchPhase {
   BP_SUP, BP_SDOWN, BP_SFINAL, BP_FINALIZE, BP_SELECT,
   BP_SBUILD1,  // the sampler build with one team per SIMD (a layout the autotuner may pick)
   // one lane per item for chains with d <= 4 in the 16-wide class (akf_lane.hip)
-  BP_FOLD_LANE, BP_FINAL_LANE, BP_SBUILD_LANE
+  BP_FOLD_LANE, BP_FINAL_LANE, BP_SBUILD_LANE, BP_SFOLD_LANE, BP_SFINAL_LANE
 };
 hipError_t launch_batch_phase(int D, int phase, BatchLaunch L, int level, int rev,
                               const int* step, hipStream_t st);

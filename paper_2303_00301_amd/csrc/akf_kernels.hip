@@ -2255,7 +2255,7 @@ template <int D>
 hipError_t launch_batch_phase_t(int phase, BatchLaunch L, int level, int rev, const int* step,
                                 hipStream_t st) {
   if (L.n_items <= 0) return hipSuccess;
-  if (phase == BP_FOLD_LANE || phase == BP_FINAL_LANE || phase == BP_SBUILD_LANE)
+  if (phase >= BP_FOLD_LANE)
     return launch_lane_phase(phase, L, rev, step, st);
   const int cap = batch_cap<D>(phase);
   if (cap > 0) L.grid = std::min(L.n_items, cap);

@@ -1,6 +1,7 @@
 // akf_lane.hip -- batched chains with a state of at most four coordinates:
-// one lane per item (a block of the filter fold or re-scan, a time step of the
-// sampler element build), its matrices 4 x 4 in registers.
+// one lane per item (a block of the filter fold, the re-scan, the sampler's
+// block fold and final pass; a time step of the sampler element build), its
+// matrices 4 x 4 in registers.
 //
 // Such chains belong to the 16-wide class (their element, moment and sampler
 // arrays are padded to 16, and every other phase runs on 16-wide teams), but a
@@ -491,7 +492,56 @@ __device__ void lane_sbuild(const KModel& M, const SampArgs& S, int t) {
   if (!ok) flag(S.status, ST_FWD_NOT_PD);
 }
 
-// one lane per item; PH: 0 fold, 1 re-scan, 2 sampler element build
+// ---------------------------------------------------------------------------
+// Sampler, block fold: the suffix aggregate of block `blk`, folding from its
+// last step backwards, (E~, U~) <- (E_t E~, E_t U~ + U_t).
+// ---------------------------------------------------------------------------
+__device__ void lane_sfold(const KModel& M, const SampArgs& S, int blk) {
+  const int d = M.d;
+  const int s0 = blk * S.B, s1 = min(M.N, s0 + S.B);
+  M4 Ea;
+  double ua[K];
+  m_load(Ea, S.E + (int64_t)(s1 - 1) * DP * DP, DP, d);
+#pragma unroll
+  for (int i = 0; i < K; ++i) ua[i] = (i < d) ? S.U[(int64_t)(s1 - 1) * DP + i] : 0.0;
+  for (int t = s1 - 2; t >= s0; --t) {
+    M4 Et, P;
+    m_load(Et, S.E + (int64_t)t * DP * DP, DP, d);
+    m_mul(P, Et, Ea);
+    Ea = P;
+    double nu[K];
+    m_vec(nu, Et, ua);
+#pragma unroll
+    for (int i = 0; i < K; ++i) ua[i] = nu[i] + ((i < d) ? S.U[(int64_t)t * DP + i] : 0.0);
+  }
+  double* out = S.agg + (int64_t)blk * SampLayout<DP>::SIZE;
+  m_store_corner(Ea, out + SampLayout<DP>::E);
+  v_store_pad(ua, d, out + SampLayout<DP>::U);
+}
+
+// Sampler, block final pass: x*_t = E_t x*_{t+1} + U_t from the state entering
+// the block on the right.
+__device__ void lane_sfinal(const KModel& M, const SampArgs& S, int blk) {
+  const int d = M.d;
+  const int s0 = blk * S.B, s1 = min(M.N, s0 + S.B);
+  double x[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) x[i] = (i < d) ? S.xin[(int64_t)blk * DP + i] : 0.0;
+  for (int t = s1 - 1; t >= s0; --t) {
+    M4 Et;
+    m_load(Et, S.E + (int64_t)t * DP * DP, DP, d);
+    double nx[K];
+    m_vec(nx, Et, x);
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      x[i] = nx[i] + ((i < d) ? S.U[(int64_t)t * DP + i] : 0.0);
+      if (i < d) S.xs[(int64_t)t * d + i] = x[i];
+    }
+  }
+}
+
+// one lane per item; PH: 0 fold, 1 re-scan, 2 sampler element build,
+// 3 sampler block fold, 4 sampler block final pass
 template <int PH>
 __global__ void __launch_bounds__(64) kl_phase(BatchLaunch L, int rev, const int* step) {
   const int w = blockIdx.x * 64 + threadIdx.x;
@@ -502,10 +552,14 @@ __global__ void __launch_bounds__(64) kl_phase(BatchLaunch L, int rev, const int
     lane_fold(c.M, rev ? c.Fr : c.Ff, I.i);
   } else if constexpr (PH == 1) {
     lane_final(c.M, rev ? c.Fr : c.Ff, I.i);
-  } else {
+  } else if constexpr (PH == 2) {
     SampArgs S = c.S;
     S.xi_x = c.xi_base + (int64_t)(*step) * c.xi_stride + (int64_t)c.M.N * c.M.d;
     lane_sbuild(c.M, S, I.i);
+  } else if constexpr (PH == 3) {
+    lane_sfold(c.M, c.S, I.i);
+  } else {
+    lane_sfinal(c.M, c.S, I.i);
   }
 }
 
@@ -519,6 +573,8 @@ hipError_t launch_lane_phase(int phase, BatchLaunch L, int rev, const int* step,
     case BP_FOLD_LANE: hipLaunchKernelGGL(kl_phase<0>, g, b, 0, st, L, rev, step); break;
     case BP_FINAL_LANE: hipLaunchKernelGGL(kl_phase<1>, g, b, 0, st, L, rev, step); break;
     case BP_SBUILD_LANE: hipLaunchKernelGGL(kl_phase<2>, g, b, 0, st, L, rev, step); break;
+    case BP_SFOLD_LANE: hipLaunchKernelGGL(kl_phase<3>, g, b, 0, st, L, rev, step); break;
+    case BP_SFINAL_LANE: hipLaunchKernelGGL(kl_phase<4>, g, b, 0, st, L, rev, step); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
