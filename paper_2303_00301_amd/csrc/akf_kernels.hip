@@ -1529,44 +1529,25 @@ __global__ void __launch_bounds__(64) k_samp_down(KModel M, TreeArgs T) {
 }
 
 // Sampler, block final: x*_t = E_t x*_{t+1} + U_t inside each block.
-// Thread i < D keeps row i of E_t and U_t in registers and loads the next
-// step's while this one's product runs (two register sets, alternating), so a
-// step waits on the state, not on HBM.
 template <int D>
 __device__ __forceinline__ void samp_final_body(const KModel& M, const SampArgs& S, int item) {
   __shared__ double vx[64];
+  __shared__ double vn[64];
   const int blk = item, tid = threadIdx.x, d = M.d;
   const int s0 = blk * S.B, s1 = min(M.N, s0 + S.B);
-  const bool row = tid < D;
-  if (row) vx[tid] = S.xin[(int64_t)blk * D + tid];
-  double ea[D], eb[D], ua = 0.0, ub = 0.0;
-  auto fetch = [&](int t, double* e, double& u) {
-    if (row && t >= s0) {
-      const double* r = S.E + (int64_t)t * D * D + (int64_t)tid * D;
-#pragma unroll
-      for (int j = 0; j < D; ++j) e[j] = r[j];
-      u = S.U[(int64_t)t * D + tid];
-    }
-  };
-  auto apply = [&](int t, const double* e, double u) {
-    double v = u;
-    if (row) {
-#pragma unroll
-      for (int j = 0; j < D; ++j) v = fma(e[j], vx[j], v);
-    }
-    __syncthreads();  // every thread has read x_{t+1}
-    if (row) vx[tid] = v;
-    if (tid < d) S.xs[(int64_t)t * d + tid] = v;
-    __syncthreads();
-  };
-  fetch(s1 - 1, ea, ua);
+  if (tid < D) vx[tid] = S.xin[(int64_t)blk * D + tid];
   __syncthreads();
-  for (int t = s1 - 1; t >= s0; t -= 2) {
-    fetch(t - 1, eb, ub);
-    apply(t, ea, ua);
-    if (t - 1 < s0) break;
-    fetch(t - 2, ea, ua);
-    apply(t - 1, eb, ub);
+  for (int t = s1 - 1; t >= s0; --t) {
+    const double* Et = S.E + (int64_t)t * D * D;
+    if (tid < D) {
+      double s = S.U[(int64_t)t * D + tid];
+      for (int j = 0; j < D; ++j) s = fma(Et[tid * D + j], vx[j], s);
+      vn[tid] = s;
+    }
+    __syncthreads();
+    if (tid < D) vx[tid] = vn[tid];
+    if (tid < d) S.xs[(int64_t)t * d + tid] = vn[tid];
+    __syncthreads();
   }
 }
 
